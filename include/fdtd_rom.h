@@ -1,0 +1,187 @@
+/*
+ * fdtd_rom.h - C ABI of the MI355X (gfx950) library for the stable FDTD
+ * method with embedded reduced-order models (Zhang, Bekmambetova, Triverio,
+ * "A Stable FDTD Method with Embedded Reduced-Order Models", IEEE TAP 2017).
+ *
+ * Problem statement (paper Sec. II first paragraph, Sec. IV, Sec. IV-C last
+ * paragraph): a 2D TEz coarse Yee grid with PEC walls and one or more
+ * refined regions; each region is replaced by a reduced model with boundary
+ * ports; at run time the coarse grid is advanced with the conventional
+ * leap-frog updates (eqs. (3), (5)) and every reduced model, together with
+ * the coarse electric field on its interface, with the explicit update of
+ * eq. (23).
+ *
+ * Conventions shared by every entry point
+ *   - coarse cell (i, j), 0 <= i < nx, 0 <= j < ny; host maps are row-major
+ *     [j * nx + i];
+ *   - Hz(i, j) at the cell centre; Ex(i, j), 0 <= j <= ny, on the horizontal
+ *     edge y = j*dy; Ey(i, j), 0 <= i <= nx, on the vertical edge x = i*dx;
+ *     PEC walls: Ex(., 0), Ex(., ny), Ey(0, .), Ey(nx, .) are zero;
+ *   - leap-frog state after k steps: E at time k*dt, Hz at (k - 1/2)*dt;
+ *   - a reduced region covers coarse cells [i0, i0+ni) x [j0, j0+nj); its
+ *     np = 2*(ni+nj) ports are ordered South (Ex(i0+c, j0)), North
+ *     (Ex(i0+c, j0+nj)), West (Ey(i0, j0+c)), East (Ey(i0+ni, j0+c)), c
+ *     increasing along each side (the ordering of eq. (8) at coarse
+ *     resolution);
+ *   - every host pointer argument is borrowed: the library copies what it
+ *     needs before the call returns;
+ *   - functions return FDTD_OK (0) or a negative status; a thread-local
+ *     message describing the last failure is available from
+ *     fdtd_rom_last_error().  No C++ exception crosses this interface.
+ */
+#ifndef FDTD_ROM_H
+#define FDTD_ROM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FDTD_OK = 0,
+  FDTD_EINVAL = -1,       /* invalid argument or geometry */
+  FDTD_ENOMEM = -2,       /* workspace too small / host allocation failed */
+  FDTD_EDEVICE = -3,      /* HIP runtime error */
+  FDTD_ENOTPASSIVE = -4,  /* reduced model violates eq. (26a) at dt */
+  FDTD_EUNSTABLE = -5,    /* non-finite field detected */
+  FDTD_ESTATE = -6        /* call not valid in the current state */
+};
+
+enum { FDTD_F32 = 0, FDTD_F64 = 1 };
+enum { FDTD_HZ = 0, FDTD_EX = 1, FDTD_EY = 2 };
+
+/* Physical constants used by both the library and its validation. */
+#define FDTD_C0 299792458.0
+#define FDTD_MU0 (4.0e-7 * 3.14159265358979323846)
+
+/* Coarse grid (eqs. (1), (3), (5)).  eps_r / sigma: host [ny*nx] relative
+ * permittivity and conductivity (S/m) per cell; NULL means 1 / 0.  Edge
+ * material is the mean over the two cells sharing the edge (eq. (3)).
+ * dtype: FDTD_F32 or FDTD_F64 arithmetic and storage on the device. */
+typedef struct {
+  int32_t nx, ny;
+  double dx, dy, dt;
+  int32_t dtype;
+  const double* eps_r;
+  const double* sigma;
+} fdtd_grid;
+
+/* One embedded reduced model (eqs. (11)-(12)), built on coarse ports.
+ * Rt, Ft: host [q*q] row-major (R~, F~ of eq. (11)); Lt: host [q*np]
+ * row-major (L~ = V^T L); B~ = L~ Sc is implied with
+ * Sc = diag(-dx I, +dx I, +dy I, -dy I) (coarse analog of eq. (25)).
+ * x0: host [q] initial reduced state or NULL for zero; the interface E
+ * starts at L~^T x0.  group >= 0: regions with the same group use one
+ * copy of the matrices on the device (their Rt/Ft/Lt must be identical and
+ * their surroundings must give identical interface half cells). */
+typedef struct {
+  int32_t i0, j0, ni, nj;
+  int32_t q;
+  int32_t group;
+  const double* Rt;
+  const double* Ft;
+  const double* Lt;
+  const double* x0;
+} fdtd_rom;
+
+/* Additive source: at step n (0-based) incr[n] is added to component comp
+ * over positions [i0, i1) x [j0, j1) - to Hz^{n+1/2} right after its update
+ * (centred at t = n*dt) or to E^{n+1} right after its update.  nt >= the
+ * number of steps the simulation will run (max_steps). */
+typedef struct {
+  int32_t comp, i0, i1, j0, j1;
+  int32_t nt;
+  const double* incr;
+} fdtd_source;
+
+/* Point probe: after step n, probe value n is Hz^{n+1/2}(i, j) or E^{n+1}. */
+typedef struct {
+  int32_t comp, i, j;
+} fdtd_probe;
+
+typedef struct {
+  fdtd_grid grid;
+  const fdtd_rom* roms;
+  int32_t nroms;
+  const fdtd_source* sources;
+  int32_t nsources;
+  const fdtd_probe* probes;
+  int32_t nprobes;
+  int32_t max_steps; /* capacity of the probe record and source tables */
+} fdtd_problem;
+
+typedef struct fdtd_rom_sim fdtd_rom_sim; /* opaque, owned by the library */
+
+/* Device workspace (bytes) that fdtd_rom_create needs for this problem. */
+int fdtd_rom_workspace_size(const fdtd_problem* prob, size_t* bytes);
+
+/* Validate the problem, fold the coarse interface half cells into the
+ * closed form of eq. (23) (FP64 on the host), and lay the problem out in
+ * the caller's device workspace.
+ *   dev_workspace: device pointer, >= fdtd_rom_workspace_size bytes, 256-B
+ *     aligned; owned by the caller and must outlive the handle.
+ *   hip_stream: hipStream_t every launch and copy of this handle goes to
+ *     (NULL = the default stream).
+ * Checks: dimensions > 0; dt <= the coarse CFL limit of eq. (1) with
+ * c = c0/sqrt(min eps_r) (FDTD_EINVAL); every region at least one cell from
+ * the walls and its one-cell ring disjoint from other regions (FDTD_EINVAL);
+ * sources and probes on cells/edges updated by the coarse stencil
+ * (FDTD_EINVAL); R~ symmetric to 1e-12 relative and positive definite by
+ * Cholesky (eq. (26a), Theorem 1; FDTD_ENOTPASSIVE). */
+int fdtd_rom_create(const fdtd_problem* prob, void* dev_workspace, size_t ws_bytes,
+                    void* hip_stream, fdtd_rom_sim** out);
+
+/* Advance one leap-frog step / nsteps steps (asynchronous on the stream).
+ * FDTD_ESTATE if the step count would exceed max_steps. */
+int fdtd_rom_step(fdtd_rom_sim* sim);
+int fdtd_rom_run(fdtd_rom_sim* sim, int32_t nsteps);
+
+/* Number of steps taken so far. */
+int fdtd_rom_steps_done(const fdtd_rom_sim* sim, int32_t* n);
+
+/* Probe record rows [first, first+count) into host [count * nprobes]
+ * (row-major, probe index fastest), converted to double.  Synchronises the
+ * stream. */
+int fdtd_rom_read_probes(const fdtd_rom_sim* sim, int32_t first, int32_t count,
+                         double* host_out);
+
+/* Current field comp in the natural layout into host memory:
+ * Hz [ny*nx], Ex [(ny+1)*nx], Ey [ny*(nx+1)] (walls included, zero).
+ * Cells and edges inside reduced regions read as zero.  Synchronises. */
+int fdtd_rom_read_field(const fdtd_rom_sim* sim, int32_t comp, double* host_out);
+
+/* Reduced state x~ of region k into host [q].  Synchronises. */
+int fdtd_rom_read_rom_state(const fdtd_rom_sim* sim, int32_t k, double* host_out);
+
+/* Host-only (no device call): validate prob like fdtd_rom_create and
+ * return, for region k, the FP64 closed-form matrices of eq. (23) that
+ * create folds from eqs. (13)-(22):
+ *   A~  = (R~ + F~ + L~ C+ L~^T)^{-1} (R~ - F~ + L~ C- L~^T)   [q*q]
+ *   B~' = (R~ + F~ + L~ C+ L~^T)^{-1} L~ Sc                     [q*np]
+ *   C~  = L~^T                                                   [np*q]
+ * with C+- = Dl Dl' (eps/dt +- sigma/2) of the coarse half cell outside each
+ * port (eq. (13)).  Row-major host buffers; any may be NULL. */
+int fdtd_rom_coupled_update(const fdtd_problem* prob, int32_t k, double* A, double* B,
+                            double* C);
+
+/* Per-kernel timing with HIP events on the handle's stream: while enabled,
+ * every stencil launch and every coupling launch is bracketed by events;
+ * fdtd_rom_profile_read synchronises and returns the summed durations (ms)
+ * and launch counts since the last reset. */
+int fdtd_rom_profile_enable(fdtd_rom_sim* sim, int32_t enable);
+int fdtd_rom_profile_read(fdtd_rom_sim* sim, double* stencil_ms, int64_t* stencil_launches,
+                          double* coupling_ms, int64_t* coupling_launches);
+
+/* Release the handle (the workspace stays the caller's). */
+void fdtd_rom_destroy(fdtd_rom_sim* sim);
+
+const char* fdtd_rom_strerror(int status);
+const char* fdtd_rom_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDTD_ROM_H */

@@ -1,0 +1,243 @@
+"""ctypes binding of include/fdtd_rom.h: same names, argument marshalling only.
+
+The shared library is built in-tree by ``paper_1609_07114_amd.build``.  If
+it is missing, ``lib()`` raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdtdrom.so")
+
+FDTD_OK, FDTD_EINVAL, FDTD_ENOMEM, FDTD_EDEVICE = 0, -1, -2, -3
+FDTD_ENOTPASSIVE, FDTD_EUNSTABLE, FDTD_ESTATE = -4, -5, -6
+FDTD_F32, FDTD_F64 = 0, 1
+FDTD_HZ, FDTD_EX, FDTD_EY = 0, 1, 2
+
+_dp = C.POINTER(C.c_double)
+
+
+class fdtd_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
+                ("dt", C.c_double), ("dtype", C.c_int32), ("eps_r", _dp), ("sigma", _dp)]
+
+
+class fdtd_rom(C.Structure):
+    _fields_ = [("i0", C.c_int32), ("j0", C.c_int32), ("ni", C.c_int32), ("nj", C.c_int32),
+                ("q", C.c_int32), ("group", C.c_int32), ("Rt", _dp), ("Ft", _dp), ("Lt", _dp),
+                ("x0", _dp)]
+
+
+class fdtd_source(C.Structure):
+    _fields_ = [("comp", C.c_int32), ("i0", C.c_int32), ("i1", C.c_int32), ("j0", C.c_int32),
+                ("j1", C.c_int32), ("nt", C.c_int32), ("incr", _dp)]
+
+
+class fdtd_probe(C.Structure):
+    _fields_ = [("comp", C.c_int32), ("i", C.c_int32), ("j", C.c_int32)]
+
+
+class fdtd_problem(C.Structure):
+    _fields_ = [("grid", fdtd_grid), ("roms", C.POINTER(fdtd_rom)), ("nroms", C.c_int32),
+                ("sources", C.POINTER(fdtd_source)), ("nsources", C.c_int32),
+                ("probes", C.POINTER(fdtd_probe)), ("nprobes", C.c_int32),
+                ("max_steps", C.c_int32)]
+
+
+class FdtdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_LIB = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "fdtd_rom_workspace_size": (C.c_int, [C.POINTER(fdtd_problem), C.POINTER(C.c_size_t)]),
+    "fdtd_rom_create": (C.c_int, [C.POINTER(fdtd_problem), C.c_void_p, C.c_size_t, C.c_void_p,
+                                  C.POINTER(C.c_void_p)]),
+    "fdtd_rom_step": (C.c_int, [C.c_void_p]),
+    "fdtd_rom_run": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_steps_done": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "fdtd_rom_read_probes": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _dp]),
+    "fdtd_rom_read_field": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
+    "fdtd_rom_read_rom_state": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
+    "fdtd_rom_coupled_update": (C.c_int, [C.POINTER(fdtd_problem), C.c_int32, _dp, _dp, _dp]),
+    "fdtd_rom_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_profile_read": (C.c_int, [C.c_void_p, _dp, C.POINTER(C.c_int64), _dp,
+                                        C.POINTER(C.c_int64)]),
+    "fdtd_rom_destroy": (None, [C.c_void_p]),
+    "fdtd_rom_strerror": (C.c_char_p, [C.c_int]),
+    "fdtd_rom_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load the in-tree HIP library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_1609_07114_amd.build.build() "
+                               "(hipcc, gfx950) first; there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc):
+    if rc != FDTD_OK:
+        msg = lib().fdtd_rom_last_error().decode()
+        raise FdtdError(rc, msg)
+    return rc
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+# ---------------------------------------------------------------------------
+# marshalling of a problem description
+# ---------------------------------------------------------------------------
+
+class ProblemStruct:
+    """Owns the C structs and the contiguous float64 arrays they point to."""
+
+    def __init__(self, nx, ny, dx, dy, dt, dtype, eps_r, sigma, roms, sources, probes,
+                 max_steps):
+        self._keep = []
+
+        def arr(x):
+            if x is None:
+                return None
+            a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+            self._keep.append(a)
+            return a
+        g = fdtd_grid(nx, ny, dx, dy, dt, FDTD_F64 if dtype in ("f64", FDTD_F64) else FDTD_F32,
+                      _ptr(arr(eps_r)), _ptr(arr(sigma)))
+        rarr = (fdtd_rom * max(1, len(roms)))()
+        for k, r in enumerate(roms):
+            Rt, Ft, Lt = arr(r["Rt"]), arr(r["Ft"]), arr(r["Lt"])
+            x0 = arr(r.get("x0"))
+            rarr[k] = fdtd_rom(r["i0"], r["j0"], r["ni"], r["nj"], Rt.shape[0], r.get("group", -1),
+                               _ptr(Rt), _ptr(Ft), _ptr(Lt), _ptr(x0))
+        sarr = (fdtd_source * max(1, len(sources)))()
+        for k, s in enumerate(sources):
+            inc = arr(s["incr"])
+            sarr[k] = fdtd_source(s["comp"], s["i0"], s["i1"], s["j0"], s["j1"], inc.size, _ptr(inc))
+        parr = (fdtd_probe * max(1, len(probes)))()
+        for k, p in enumerate(probes):
+            parr[k] = fdtd_probe(p["comp"], p["i"], p["j"])
+        self._keep += [rarr, sarr, parr]
+        self.s = fdtd_problem(g, rarr, len(roms), sarr, len(sources), parr, len(probes), max_steps)
+
+    @classmethod
+    def from_workload(cls, prob, rom_mats, max_steps=None, dtype=None, x0=None):
+        roms = []
+        for k, (spec, m) in enumerate(zip(prob.roms, rom_mats)):
+            roms.append(dict(i0=spec.i0, j0=spec.j0, ni=spec.ni, nj=spec.nj,
+                             group=spec.group, Rt=m["Rt"], Ft=m["Ft"], Lt=m["Lt"],
+                             x0=None if x0 is None else x0[k]))
+        srcs = [dict(comp=s.comp, i0=s.i0, i1=s.i1, j0=s.j0, j1=s.j1, incr=s.incr)
+                for s in prob.sources]
+        prbs = [dict(comp=p.comp, i=p.i, j=p.j) for p in prob.probes]
+        ms = prob.nsteps if max_steps is None else max_steps
+        return cls(prob.nx, prob.ny, prob.dx, prob.dy, prob.dt, dtype or prob.dtype, prob.eps_r,
+                   prob.sigma, roms, srcs, prbs, ms)
+
+
+# ---------------------------------------------------------------------------
+# the C entry points, same names
+# ---------------------------------------------------------------------------
+
+def fdtd_rom_workspace_size(problem: ProblemStruct) -> int:
+    n = C.c_size_t(0)
+    _check(lib().fdtd_rom_workspace_size(C.byref(problem.s), C.byref(n)))
+    return int(n.value)
+
+
+def fdtd_rom_create(problem: ProblemStruct, dev_ptr: int, nbytes: int, stream: int):
+    h = C.c_void_p()
+    _check(lib().fdtd_rom_create(C.byref(problem.s), C.c_void_p(dev_ptr), nbytes,
+                                 C.c_void_p(stream), C.byref(h)))
+    return h
+
+
+def fdtd_rom_step(h):
+    _check(lib().fdtd_rom_step(h))
+
+
+def fdtd_rom_run(h, nsteps: int):
+    _check(lib().fdtd_rom_run(h, int(nsteps)))
+
+
+def fdtd_rom_steps_done(h) -> int:
+    n = C.c_int32(0)
+    _check(lib().fdtd_rom_steps_done(h, C.byref(n)))
+    return int(n.value)
+
+
+def fdtd_rom_read_probes(h, first: int, count: int, nprobes: int) -> np.ndarray:
+    out = np.zeros((count, nprobes), dtype=np.float64)
+    _check(lib().fdtd_rom_read_probes(h, first, count, _ptr(out)))
+    return out
+
+
+def fdtd_rom_read_field(h, comp: int, nx: int, ny: int) -> np.ndarray:
+    shape = {FDTD_HZ: (ny, nx), FDTD_EX: (ny + 1, nx), FDTD_EY: (ny, nx + 1)}[comp]
+    out = np.zeros(shape, dtype=np.float64)
+    _check(lib().fdtd_rom_read_field(h, comp, _ptr(out)))
+    return out
+
+
+def fdtd_rom_read_rom_state(h, k: int, q: int) -> np.ndarray:
+    out = np.zeros(q, dtype=np.float64)
+    _check(lib().fdtd_rom_read_rom_state(h, k, _ptr(out)))
+    return out
+
+
+def fdtd_rom_coupled_update(problem: ProblemStruct, k: int):
+    r = problem.s.roms[k]
+    q, np_ = r.q, 2 * (r.ni + r.nj)
+    A = np.zeros((q, q))
+    B = np.zeros((q, np_))
+    Cm = np.zeros((np_, q))
+    _check(lib().fdtd_rom_coupled_update(C.byref(problem.s), k, _ptr(A), _ptr(B), _ptr(Cm)))
+    return A, B, Cm
+
+
+def fdtd_rom_profile_enable(h, enable: bool):
+    _check(lib().fdtd_rom_profile_enable(h, 1 if enable else 0))
+
+
+def fdtd_rom_profile_read(h):
+    a = C.c_double(0)
+    b = C.c_double(0)
+    na = C.c_int64(0)
+    nb = C.c_int64(0)
+    _check(lib().fdtd_rom_profile_read(h, C.byref(a), C.byref(na), C.byref(b), C.byref(nb)))
+    return float(a.value), int(na.value), float(b.value), int(nb.value)
+
+
+def fdtd_rom_destroy(h):
+    lib().fdtd_rom_destroy(h)
+
+
+def fdtd_rom_strerror(status: int) -> str:
+    return lib().fdtd_rom_strerror(status).decode()
+
+
+def fdtd_rom_last_error() -> str:
+    return lib().fdtd_rom_last_error().decode()

@@ -1,0 +1,804 @@
+// Host runtime of the C ABI declared in include/fdtd_rom.h.
+//
+// create(): validates the problem (eq. (1) CFL, geometry, eq. (26a)
+// passivity by Cholesky), folds the coarse interface half cells of eq. (13)
+// into the closed form of eq. (23) in FP64, and lays everything out in the
+// caller's device workspace.  run(): per step one fused stencil launch and
+// one coupling launch on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/fdtd_rom.h"
+#include "common.hpp"
+#include "linalg.hpp"
+
+using namespace fdtd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+const double kC0 = FDTD_C0;
+const double kMu0 = FDTD_MU0;
+const double kEps0 = 1.0 / (kMu0 * kC0 * kC0);
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  int pitch = 0;
+  size_t tsize = 0;
+  size_t field_elems = 0;
+  size_t off_ctrl = 0, off_fields = 0, off_al = 0, off_be = 0, off_src = 0;
+  size_t off_pbuf = 0, off_poff = 0, off_pcomp = 0, off_roms = 0, off_mats = 0;
+  size_t off_xs = 0, off_idx = 0, total = 0;
+  size_t mats_elems = 0, xs_elems = 0, idx_elems = 0;
+  std::vector<int> slot_of_rom;     // matrix slot per region
+  std::vector<int> slot_rep;        // representative region per slot
+  std::vector<size_t> slot_off;     // element offset of each slot in the pool
+  std::vector<size_t> x_off, i_off; // per region
+};
+
+int ports_of(const fdtd_rom& r) { return 2 * (r.ni + r.nj); }
+
+// Shape-level validation and workspace plan (no numerics).
+int plan(const fdtd_problem* p, Layout& L) {
+  if (!p) return fail(FDTD_EINVAL, "null problem");
+  const fdtd_grid& g = p->grid;
+  if (g.nx < 2 || g.ny < 2) return fail(FDTD_EINVAL, "grid must be at least 2x2 (got %dx%d)", g.nx, g.ny);
+  if (!(g.dx > 0) || !(g.dy > 0) || !(g.dt > 0)) return fail(FDTD_EINVAL, "dx, dy, dt must be positive");
+  if (g.dtype != FDTD_F32 && g.dtype != FDTD_F64) return fail(FDTD_EINVAL, "dtype must be FDTD_F32 or FDTD_F64");
+  if (p->max_steps < 1) return fail(FDTD_EINVAL, "max_steps must be >= 1");
+  if (p->nroms < 0 || (p->nroms > 0 && !p->roms)) return fail(FDTD_EINVAL, "bad region list");
+  if (p->nsources < 0 || p->nsources > kMaxSrc || (p->nsources > 0 && !p->sources))
+    return fail(FDTD_EINVAL, "between 0 and %d sources are supported", kMaxSrc);
+  if (p->nprobes < 0 || (p->nprobes > 0 && !p->probes)) return fail(FDTD_EINVAL, "bad probe list");
+  const size_t ts = g.dtype == FDTD_F32 ? 4 : 8;
+  L.tsize = ts;
+  L.pitch = (int)align_up((size_t)g.nx, kWave);
+  L.field_elems = (size_t)g.ny * L.pitch;
+  // matrix slots (shared by group)
+  L.slot_of_rom.assign(p->nroms, -1);
+  L.slot_rep.clear();
+  std::vector<int> group_slot;
+  std::vector<int> group_id;
+  for (int k = 0; k < p->nroms; ++k) {
+    const fdtd_rom& r = p->roms[k];
+    if (r.ni < 1 || r.nj < 1) return fail(FDTD_EINVAL, "region %d: empty footprint", k);
+    if (r.q < 1 || r.q > kMaxQ) return fail(FDTD_EINVAL, "region %d: order q=%d outside [1, %d]", k, r.q, kMaxQ);
+    if (ports_of(r) > kMaxPorts) return fail(FDTD_EINVAL, "region %d: %d ports exceed %d", k, ports_of(r), kMaxPorts);
+    if (!r.Rt || !r.Ft || !r.Lt) return fail(FDTD_EINVAL, "region %d: missing matrices", k);
+    int slot = -1;
+    if (r.group >= 0) {
+      for (size_t s = 0; s < group_id.size(); ++s)
+        if (group_id[s] == r.group) slot = group_slot[s];
+    }
+    if (slot < 0) {
+      slot = (int)L.slot_rep.size();
+      L.slot_rep.push_back(k);
+      if (r.group >= 0) {
+        group_id.push_back(r.group);
+        group_slot.push_back(slot);
+      }
+    }
+    L.slot_of_rom[k] = slot;
+  }
+  L.slot_off.clear();
+  size_t me = 0;
+  for (int rep : L.slot_rep) {
+    const fdtd_rom& r = p->roms[rep];
+    const int np = ports_of(r);
+    L.slot_off.push_back(me);
+    me += (size_t)r.q * (r.q + np) + (size_t)np * r.q;
+    me = align_up(me, 64);
+  }
+  L.mats_elems = me;
+  L.x_off.clear();
+  L.i_off.clear();
+  size_t xe = 0, ie = 0;
+  for (int k = 0; k < p->nroms; ++k) {
+    L.x_off.push_back(xe);
+    L.i_off.push_back(ie);
+    xe = align_up(xe + p->roms[k].q, 64);
+    ie = align_up(ie + 2 * (size_t)ports_of(p->roms[k]), 64);
+  }
+  L.xs_elems = xe;
+  L.idx_elems = ie;
+  size_t o = 0;
+  L.off_ctrl = o;
+  o = align_up(o + kCtrlInts * sizeof(int), 256);
+  L.off_fields = o;
+  o = align_up(o + 6 * L.field_elems * ts, 256);
+  L.off_al = o;
+  o = align_up(o + L.field_elems * ts, 256);
+  L.off_be = o;
+  o = align_up(o + L.field_elems * ts, 256);
+  L.off_src = o;
+  // at least one (zero) row so unused source slots point at valid memory
+  o = align_up(o + (size_t)std::max(p->nsources, 1) * p->max_steps * ts, 256);
+  L.off_pbuf = o;
+  o = align_up(o + (size_t)p->max_steps * p->nprobes * ts, 256);
+  L.off_poff = o;
+  o = align_up(o + (size_t)p->nprobes * sizeof(int), 256);
+  L.off_pcomp = o;
+  o = align_up(o + (size_t)p->nprobes * sizeof(int), 256);
+  L.off_roms = o;
+  o = align_up(o + (size_t)p->nroms * sizeof(RomDev), 256);
+  L.off_mats = o;
+  o = align_up(o + L.mats_elems * ts, 256);
+  L.off_xs = o;
+  o = align_up(o + L.xs_elems * ts, 256);
+  L.off_idx = o;
+  o = align_up(o + L.idx_elems * sizeof(int), 256);
+  L.total = o;
+  return FDTD_OK;
+}
+
+struct RomHost {
+  int i0, j0, ni, nj, q, np, slot;
+  std::vector<double> A, B, C;  // closed form, row-major
+};
+
+}  // namespace
+
+struct fdtd_rom_sim {
+  int dtype = FDTD_F32;
+  int nx = 0, ny = 0, pitch = 0;
+  double dx = 0, dy = 0, dt = 0;
+  int max_steps = 0, steps = 0, nprobes = 0, nsrc = 0, nroms = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Layout L;
+  int cur = 0;
+  int seg = 16;
+  std::vector<RomHost> roms;
+  StencilParams<float> sp_f[2];
+  StencilParams<double> sp_d[2];
+  CouplingParams<float> cp_f[2];
+  CouplingParams<double> cp_d[2];
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_st, ev_cp;
+  size_t used_st = 0, used_cp = 0;
+  double ms_st = 0, ms_cp = 0;
+  int64_t n_st = 0, n_cp = 0;
+};
+
+namespace {
+
+template <typename T>
+int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsigned char>& inside) {
+  const Layout& L = s->L;
+  const int nx = s->nx, ny = s->ny, P = L.pitch;
+  const size_t fe = L.field_elems;
+  const fdtd_grid& g = p->grid;
+  std::vector<T> host(fe, T(0));
+  char* ws = s->ws;
+  hipStream_t st = s->stream;
+  auto up = [&](size_t off, const void* src, size_t bytes) -> int {
+    if (bytes == 0) return FDTD_OK;
+    if (hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+      return fail(FDTD_EDEVICE, "hipMemcpyAsync failed");
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(FDTD_EDEVICE, "hipStreamSynchronize failed");
+    return FDTD_OK;
+  };
+  int rc;
+  // control block
+  int ctrl[kCtrlInts] = {0, 0, 0, 0};
+  if ((rc = up(L.off_ctrl, ctrl, sizeof(ctrl))) != FDTD_OK) return rc;
+  // fields: Hz zero; E zero except the interface value L~^T x0 of each region
+  std::vector<T> ex(fe, T(0)), ey(fe, T(0));
+  for (int k = 0; k < p->nroms; ++k) {
+    const fdtd_rom& r = p->roms[k];
+    if (!r.x0) continue;
+    const int np = ports_of(r);
+    for (int c = 0; c < np; ++c) {
+      double y = 0;
+      for (int a = 0; a < r.q; ++a) y += r.Lt[(size_t)a * np + c] * r.x0[a];
+      int ei, ej;
+      bool isx;
+      if (c < r.ni) { ei = r.i0 + c; ej = r.j0; isx = true; }
+      else if (c < 2 * r.ni) { ei = r.i0 + c - r.ni; ej = r.j0 + r.nj; isx = true; }
+      else if (c < 2 * r.ni + r.nj) { ei = r.i0; ej = r.j0 + c - 2 * r.ni; isx = false; }
+      else { ei = r.i0 + r.ni; ej = r.j0 + c - 2 * r.ni - r.nj; isx = false; }
+      (isx ? ex : ey)[(size_t)ej * P + ei] = (T)y;
+    }
+  }
+  const size_t fb = fe * sizeof(T);
+  for (int set = 0; set < 2; ++set) {
+    if ((rc = up(L.off_fields + (3 * set + 0) * fb, host.data(), fb)) != FDTD_OK) return rc;
+    if ((rc = up(L.off_fields + (3 * set + 1) * fb, ex.data(), fb)) != FDTD_OK) return rc;
+    if ((rc = up(L.off_fields + (3 * set + 2) * fb, ey.data(), fb)) != FDTD_OK) return rc;
+  }
+  // per-cell material: a = eps0*eps_r/dt (negative inside regions), b = sigma/2
+  std::vector<T> al(fe, T(0)), be(fe, T(0));
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const size_t c = (size_t)j * nx + i;
+      const double er = g.eps_r ? g.eps_r[c] : 1.0;
+      const double sg = g.sigma ? g.sigma[c] : 0.0;
+      al[(size_t)j * P + i] = inside[c] ? T(-1) : (T)(kEps0 * er / g.dt);
+      be[(size_t)j * P + i] = inside[c] ? T(0) : (T)(sg / 2.0);
+    }
+  if ((rc = up(L.off_al, al.data(), fb)) != FDTD_OK) return rc;
+  if ((rc = up(L.off_be, be.data(), fb)) != FDTD_OK) return rc;
+  // sources
+  std::vector<T> sv((size_t)std::max(p->nsources, 1) * p->max_steps, T(0));
+  for (int k = 0; k < p->nsources; ++k)
+    for (int n = 0; n < p->max_steps; ++n)
+      sv[(size_t)k * p->max_steps + n] = (T)p->sources[k].incr[n];
+  if ((rc = up(L.off_src, sv.data(), sv.size() * sizeof(T))) != FDTD_OK) return rc;
+  // probes
+  std::vector<int> poff(p->nprobes), pcomp(p->nprobes);
+  for (int k = 0; k < p->nprobes; ++k) {
+    poff[k] = p->probes[k].j * P + p->probes[k].i;
+    pcomp[k] = p->probes[k].comp;
+  }
+  if ((rc = up(L.off_poff, poff.data(), poff.size() * sizeof(int))) != FDTD_OK) return rc;
+  if ((rc = up(L.off_pcomp, pcomp.data(), pcomp.size() * sizeof(int))) != FDTD_OK) return rc;
+  std::vector<T> zeros_pbuf((size_t)p->max_steps * p->nprobes, T(0));
+  if ((rc = up(L.off_pbuf, zeros_pbuf.data(), zeros_pbuf.size() * sizeof(T))) != FDTD_OK) return rc;
+  // regions
+  std::vector<RomDev> rd(p->nroms);
+  std::vector<T> mats(L.mats_elems, T(0));
+  std::vector<T> xs(L.xs_elems, T(0));
+  std::vector<int> idx(L.idx_elems, 0);
+  for (size_t sl = 0; sl < L.slot_rep.size(); ++sl) {
+    const RomHost& h = s->roms[L.slot_rep[sl]];
+    const int q = h.q, np = h.np;
+    T* m = mats.data() + L.slot_off[sl];
+    for (int c = 0; c < q + np; ++c)
+      for (int a = 0; a < q; ++a)
+        m[(size_t)c * q + a] = (T)(c < q ? h.A[(size_t)a * q + c] : h.B[(size_t)a * np + (c - q)]);
+    T* cm = m + (size_t)q * (q + np);
+    for (int a = 0; a < q; ++a)
+      for (int c = 0; c < np; ++c) cm[(size_t)a * np + c] = (T)h.C[(size_t)c * q + a];
+  }
+  for (int k = 0; k < p->nroms; ++k) {
+    const fdtd_rom& r = p->roms[k];
+    const int np = ports_of(r);
+    rd[k].q = r.q;
+    rd[k].np = np;
+    rd[k].n_ex = 2 * r.ni;
+    rd[k].m_off = (int64_t)L.slot_off[L.slot_of_rom[k]];
+    rd[k].x_off = (int64_t)L.x_off[k];
+    rd[k].i_off = (int64_t)L.i_off[k];
+    if (r.x0)
+      for (int a = 0; a < r.q; ++a) xs[L.x_off[k] + a] = (T)r.x0[a];
+    int* gi = idx.data() + L.i_off[k];
+    int* si = gi + np;
+    for (int c = 0; c < np; ++c) {
+      int ei, ej, oi, oj;
+      if (c < r.ni) { ei = r.i0 + c; ej = r.j0; oi = ei; oj = r.j0 - 1; }
+      else if (c < 2 * r.ni) { ei = r.i0 + c - r.ni; ej = r.j0 + r.nj; oi = ei; oj = ej; }
+      else if (c < 2 * r.ni + r.nj) { ei = r.i0; ej = r.j0 + c - 2 * r.ni; oi = r.i0 - 1; oj = ej; }
+      else { ei = r.i0 + r.ni; ej = r.j0 + c - 2 * r.ni - r.nj; oi = ei; oj = ej; }
+      gi[c] = oj * P + oi;
+      si[c] = ej * P + ei;
+    }
+  }
+  if ((rc = up(L.off_roms, rd.data(), rd.size() * sizeof(RomDev))) != FDTD_OK) return rc;
+  if ((rc = up(L.off_mats, mats.data(), mats.size() * sizeof(T))) != FDTD_OK) return rc;
+  if ((rc = up(L.off_xs, xs.data(), xs.size() * sizeof(T))) != FDTD_OK) return rc;
+  if ((rc = up(L.off_idx, idx.data(), idx.size() * sizeof(int))) != FDTD_OK) return rc;
+
+  // kernel parameter blocks for both ping-pong parities
+  for (int set = 0; set < 2; ++set) {
+    StencilParams<T> sp{};
+    T* f_in = (T*)(ws + L.off_fields + 3 * set * fb);
+    T* f_out = (T*)(ws + L.off_fields + 3 * (set ^ 1) * fb);
+    sp.hz = f_in;
+    sp.ex = f_in + fe;
+    sp.ey = f_in + 2 * fe;
+    sp.hzo = f_out;
+    sp.exo = f_out + fe;
+    sp.eyo = f_out + 2 * fe;
+    sp.al = (const T*)(ws + L.off_al);
+    sp.be = (const T*)(ws + L.off_be);
+    sp.ctrl = (const int*)(ws + L.off_ctrl);
+    sp.nx = nx;
+    sp.ny = ny;
+    sp.pitch = P;
+    sp.tiles_x = (nx + kWave - 1) / kWave;
+    sp.chdy = (T)(g.dt / (kMu0 * g.dy));
+    sp.chdx = (T)(g.dt / (kMu0 * g.dx));
+    sp.k2dy = (T)(2.0 / g.dy);
+    sp.k2dx = (T)(2.0 / g.dx);
+    sp.nsrc = p->nsources;
+    for (int k = 0; k < kMaxSrc; ++k) {
+      sp.src[k].comp = -1;
+      sp.src[k].incr = (const T*)(ws + L.off_src);
+    }
+    for (int k = 0; k < p->nsources; ++k) {
+      const fdtd_source& so = p->sources[k];
+      sp.src[k].comp = so.comp;
+      sp.src[k].i0 = so.i0;
+      sp.src[k].i1 = so.i1;
+      sp.src[k].j0 = so.j0;
+      sp.src[k].j1 = so.j1;
+      sp.src[k].incr = (const T*)(ws + L.off_src) + (size_t)k * p->max_steps;
+    }
+    CouplingParams<T> cp{};
+    cp.roms = (const RomDev*)(ws + L.off_roms);
+    cp.nroms = p->nroms;
+    cp.mats = (const T*)(ws + L.off_mats);
+    cp.xs = (T*)(ws + L.off_xs);
+    cp.idx = (const int*)(ws + L.off_idx);
+    cp.hz = f_out;
+    cp.ex = f_out + fe;
+    cp.ey = f_out + 2 * fe;
+    cp.nprobes = p->nprobes;
+    cp.probe_off = (const int*)(ws + L.off_poff);
+    cp.probe_comp = (const int*)(ws + L.off_pcomp);
+    cp.probe_buf = (T*)(ws + L.off_pbuf);
+    cp.ctrl = (int*)(ws + L.off_ctrl);
+    cp.nblocks = p->nroms + 1;
+    if constexpr (sizeof(T) == 4) {
+      s->sp_f[set] = sp;
+      s->cp_f[set] = cp;
+    } else {
+      s->sp_d[set] = sp;
+      s->cp_d[set] = cp;
+    }
+  }
+  return FDTD_OK;
+}
+
+int coupling_precompute(const fdtd_problem* p, std::vector<RomHost>& out) {
+  const fdtd_grid& g = p->grid;
+  const int nx = g.nx;
+  out.resize(p->nroms);
+  for (int k = 0; k < p->nroms; ++k) {
+    const fdtd_rom& r = p->roms[k];
+    RomHost& h = out[k];
+    h.i0 = r.i0; h.j0 = r.j0; h.ni = r.ni; h.nj = r.nj; h.q = r.q;
+    const int q = r.q, np = ports_of(r);
+    h.np = np;
+    // eq. (26a): R~ symmetric positive definite
+    double rmax = 0, asym = 0;
+    for (int a = 0; a < q; ++a)
+      for (int b = 0; b < q; ++b) {
+        rmax = std::max(rmax, std::fabs(r.Rt[(size_t)a * q + b]));
+        asym = std::max(asym, std::fabs(r.Rt[(size_t)a * q + b] - r.Rt[(size_t)b * q + a]));
+      }
+    if (!(asym <= 1e-12 * rmax))
+      return fail(FDTD_ENOTPASSIVE, "region %d: R~ not symmetric (%.3g relative)", k, asym / rmax);
+    std::vector<double> ch(r.Rt, r.Rt + (size_t)q * q);
+    if (!la::cholesky(q, ch.data()))
+      return fail(FDTD_ENOTPASSIVE, "region %d: R~ is not positive definite at dt (eq. 26a)", k);
+    // coarse half cells of eq. (13): Dl Dl' (eps/dt +- sigma/2), outside material
+    std::vector<double> cp(np), cm(np), sc(np);
+    for (int c = 0; c < np; ++c) {
+      int oi, oj;
+      double dl, dlh, s;
+      if (c < r.ni) { oi = r.i0 + c; oj = r.j0 - 1; dl = g.dx; dlh = g.dy / 2; s = -g.dx; }
+      else if (c < 2 * r.ni) { oi = r.i0 + c - r.ni; oj = r.j0 + r.nj; dl = g.dx; dlh = g.dy / 2; s = g.dx; }
+      else if (c < 2 * r.ni + r.nj) { oi = r.i0 - 1; oj = r.j0 + c - 2 * r.ni; dl = g.dy; dlh = g.dx / 2; s = g.dy; }
+      else { oi = r.i0 + r.ni; oj = r.j0 + c - 2 * r.ni - r.nj; dl = g.dy; dlh = g.dx / 2; s = -g.dy; }
+      const size_t ci = (size_t)oj * nx + oi;
+      const double e = kEps0 * (g.eps_r ? g.eps_r[ci] : 1.0);
+      const double sg = g.sigma ? g.sigma[ci] : 0.0;
+      cp[c] = dl * dlh * (e / g.dt + sg / 2.0);
+      cm[c] = dl * dlh * (e / g.dt - sg / 2.0);
+      sc[c] = s;
+    }
+    // M = R~ + F~ + L~ C+ L~^T ;  RHS = [R~ - F~ + L~ C- L~^T | L~ Sc]
+    std::vector<double> M((size_t)q * q), RHS((size_t)q * (q + np));
+    for (int a = 0; a < q; ++a)
+      for (int b = 0; b < q; ++b) {
+        double sp = 0, sm = 0;
+        for (int c = 0; c < np; ++c) {
+          const double l = r.Lt[(size_t)a * np + c] * r.Lt[(size_t)b * np + c];
+          sp += l * cp[c];
+          sm += l * cm[c];
+        }
+        const double R = r.Rt[(size_t)a * q + b], F = r.Ft[(size_t)a * q + b];
+        M[(size_t)a * q + b] = R + F + sp;
+        RHS[(size_t)a * (q + np) + b] = R - F + sm;
+      }
+    for (int a = 0; a < q; ++a)
+      for (int c = 0; c < np; ++c) RHS[(size_t)a * (q + np) + q + c] = r.Lt[(size_t)a * np + c] * sc[c];
+    std::vector<int> piv;
+    if (!la::lu_factor(q, M.data(), piv))
+      return fail(FDTD_ENOTPASSIVE, "region %d: coupled update matrix is singular", k);
+    la::lu_solve(q, M.data(), piv, RHS.data(), q + np);
+    h.A.assign((size_t)q * q, 0.0);
+    h.B.assign((size_t)q * np, 0.0);
+    h.C.assign((size_t)np * q, 0.0);
+    for (int a = 0; a < q; ++a) {
+      for (int b = 0; b < q; ++b) h.A[(size_t)a * q + b] = RHS[(size_t)a * (q + np) + b];
+      for (int c = 0; c < np; ++c) h.B[(size_t)a * np + c] = RHS[(size_t)a * (q + np) + q + c];
+    }
+    for (int c = 0; c < np; ++c)
+      for (int a = 0; a < q; ++a) h.C[(size_t)c * q + a] = r.Lt[(size_t)a * np + c];
+    (void)cm;
+  }
+  return FDTD_OK;
+}
+
+int validate_numbers(const fdtd_problem* p, const Layout& L, std::vector<unsigned char>& inside) {
+  const fdtd_grid& g = p->grid;
+  const int nx = g.nx, ny = g.ny;
+  double emin = 1e300;
+  for (size_t c = 0; c < (size_t)nx * ny; ++c) {
+    const double e = g.eps_r ? g.eps_r[c] : 1.0;
+    const double s = g.sigma ? g.sigma[c] : 0.0;
+    if (!(e > 0) || !std::isfinite(e)) return fail(FDTD_EINVAL, "eps_r must be positive and finite");
+    if (!(s >= 0) || !std::isfinite(s)) return fail(FDTD_EINVAL, "sigma must be non-negative and finite");
+    emin = std::min(emin, e);
+  }
+  // eq. (1) on the coarse grid, slowest-medium-free bound c = c0/sqrt(min eps_r)
+  const double c = kC0 / std::sqrt(emin);
+  const double lim = 1.0 / (c * std::sqrt(1.0 / (g.dx * g.dx) + 1.0 / (g.dy * g.dy)));
+  if (g.dt > lim) return fail(FDTD_EINVAL, "dt=%.6g exceeds the coarse CFL limit %.6g of eq. (1)", g.dt, lim);
+  inside.assign((size_t)nx * ny, 0);
+  for (int k = 0; k < p->nroms; ++k) {
+    const fdtd_rom& r = p->roms[k];
+    if (r.i0 < 1 || r.j0 < 1 || r.i0 + r.ni > nx - 1 || r.j0 + r.nj > ny - 1)
+      return fail(FDTD_EINVAL, "region %d must keep one coarse cell to every wall", k);
+  }
+  for (int k = 0; k < p->nroms; ++k) {
+    const fdtd_rom& a = p->roms[k];
+    for (int m = 0; m < p->nroms; ++m) {
+      if (m == k) continue;
+      const fdtd_rom& b = p->roms[m];
+      const bool sep = a.i0 + a.ni + 1 <= b.i0 || b.i0 + b.ni <= a.i0 - 1 ||
+                       a.j0 + a.nj + 1 <= b.j0 || b.j0 + b.nj <= a.j0 - 1;
+      if (!sep) return fail(FDTD_EINVAL, "regions %d and %d: one-cell rings overlap", k, m);
+    }
+    for (int j = a.j0; j < a.j0 + a.nj; ++j)
+      for (int i = a.i0; i < a.i0 + a.ni; ++i) inside[(size_t)j * nx + i] = 1;
+  }
+  auto cell_ok = [&](int i, int j) { return i >= 0 && i < nx && j >= 0 && j < ny && !inside[(size_t)j * nx + i]; };
+  auto active = [&](int comp, int i, int j) -> bool {
+    if (comp == FDTD_HZ) return cell_ok(i, j);
+    if (comp == FDTD_EX) return i >= 0 && i < nx && j >= 1 && j <= ny - 1 && cell_ok(i, j) && cell_ok(i, j - 1);
+    if (comp == FDTD_EY) return j >= 0 && j < ny && i >= 1 && i <= nx - 1 && cell_ok(i, j) && cell_ok(i - 1, j);
+    return false;
+  };
+  for (int k = 0; k < p->nsources; ++k) {
+    const fdtd_source& s = p->sources[k];
+    if (s.comp < 0 || s.comp > 2) return fail(FDTD_EINVAL, "source %d: bad component", k);
+    if (!s.incr || s.nt < p->max_steps) return fail(FDTD_EINVAL, "source %d: needs max_steps increments", k);
+    if (s.i0 >= s.i1 || s.j0 >= s.j1) return fail(FDTD_EINVAL, "source %d: empty rectangle", k);
+    for (int j = s.j0; j < s.j1; ++j)
+      for (int i = s.i0; i < s.i1; ++i)
+        if (!active(s.comp, i, j))
+          return fail(FDTD_EINVAL, "source %d: (%d,%d) is not updated by the coarse stencil", k, i, j);
+  }
+  for (int k = 0; k < p->nprobes; ++k) {
+    const fdtd_probe& pr = p->probes[k];
+    if (!active(pr.comp, pr.i, pr.j))
+      return fail(FDTD_EINVAL, "probe %d: (%d,%d) comp %d is not a coarse-stencil sample", k, pr.i, pr.j, pr.comp);
+  }
+  // shared-matrix groups must really be identical
+  for (int k = 0; k < p->nroms; ++k) {
+    const int rep = L.slot_rep[L.slot_of_rom[k]];
+    if (rep == k) continue;
+    const fdtd_rom& a = p->roms[rep];
+    const fdtd_rom& b = p->roms[k];
+    const int q = a.q, np = ports_of(a);
+    if (b.q != q || b.ni != a.ni || b.nj != a.nj)
+      return fail(FDTD_EINVAL, "region %d: group %d members differ in shape", k, b.group);
+    if ((a.Rt != b.Rt && std::memcmp(a.Rt, b.Rt, sizeof(double) * q * q)) ||
+        (a.Ft != b.Ft && std::memcmp(a.Ft, b.Ft, sizeof(double) * q * q)) ||
+        (a.Lt != b.Lt && std::memcmp(a.Lt, b.Lt, sizeof(double) * q * np)))
+      return fail(FDTD_EINVAL, "region %d: group %d members have different matrices", k, b.group);
+    // identical surroundings (interface half cells)
+    auto ring = [&](const fdtd_rom& r, int c, double& e, double& s) {
+      int oi, oj;
+      if (c < r.ni) { oi = r.i0 + c; oj = r.j0 - 1; }
+      else if (c < 2 * r.ni) { oi = r.i0 + c - r.ni; oj = r.j0 + r.nj; }
+      else if (c < 2 * r.ni + r.nj) { oi = r.i0 - 1; oj = r.j0 + c - 2 * r.ni; }
+      else { oi = r.i0 + r.ni; oj = r.j0 + c - 2 * r.ni - r.nj; }
+      const size_t ci = (size_t)oj * nx + oi;
+      e = g.eps_r ? g.eps_r[ci] : 1.0;
+      s = g.sigma ? g.sigma[ci] : 0.0;
+    };
+    for (int c = 0; c < np; ++c) {
+      double e1, s1, e2, s2;
+      ring(a, c, e1, s1);
+      ring(b, c, e2, s2);
+      if (e1 != e2 || s1 != s2)
+        return fail(FDTD_EINVAL, "region %d: group %d members sit in different material", k, b.group);
+    }
+  }
+  return FDTD_OK;
+}
+
+template <typename T>
+StencilParams<T>& stencil_params(fdtd_rom_sim* s, int set) {
+  if constexpr (sizeof(T) == 4) return s->sp_f[set];
+  else return s->sp_d[set];
+}
+
+template <typename T>
+CouplingParams<T>& coupling_params(fdtd_rom_sim* s, int set) {
+  if constexpr (sizeof(T) == 4) return s->cp_f[set];
+  else return s->cp_d[set];
+}
+
+template <typename T>
+int run_steps(fdtd_rom_sim* s, int nsteps) {
+  for (int k = 0; k < nsteps; ++k) {
+    StencilParams<T>& sp = stencil_params<T>(s, s->cur);
+    CouplingParams<T>& cp = coupling_params<T>(s, s->cur);
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+    if (s->prof) {
+      if (s->used_st >= s->ev_st.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+          return fail(FDTD_EDEVICE, "hipEventCreate failed");
+        s->ev_st.emplace_back(a, b);
+      }
+      if (s->used_cp >= s->ev_cp.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+          return fail(FDTD_EDEVICE, "hipEventCreate failed");
+        s->ev_cp.emplace_back(a, b);
+      }
+      e0 = s->ev_st[s->used_st].first;
+      e1 = s->ev_st[s->used_st].second;
+      e2 = s->ev_cp[s->used_cp].first;
+      e3 = s->ev_cp[s->used_cp].second;
+      ++s->used_st;
+      ++s->used_cp;
+      hipEventRecord(e0, s->stream);
+    }
+    if (launch_stencil<T>(sp, s->seg, s->stream) != hipSuccess)
+      return fail(FDTD_EDEVICE, "stencil launch failed");
+    if (s->prof) {
+      hipEventRecord(e1, s->stream);
+      hipEventRecord(e2, s->stream);
+    }
+    if (launch_coupling<T>(cp, s->stream) != hipSuccess)
+      return fail(FDTD_EDEVICE, "coupling launch failed");
+    if (s->prof) hipEventRecord(e3, s->stream);
+    s->cur ^= 1;
+    ++s->steps;
+  }
+  return FDTD_OK;
+}
+
+template <typename T>
+void to_double(const std::vector<char>& raw, size_t n, double* out) {
+  const T* t = (const T*)raw.data();
+  for (size_t k = 0; k < n; ++k) out[k] = (double)t[k];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fdtd_rom_strerror(int status) {
+  switch (status) {
+    case FDTD_OK: return "ok";
+    case FDTD_EINVAL: return "invalid argument";
+    case FDTD_ENOMEM: return "out of memory / workspace too small";
+    case FDTD_EDEVICE: return "HIP device error";
+    case FDTD_ENOTPASSIVE: return "reduced model not passive at this time step";
+    case FDTD_EUNSTABLE: return "non-finite field (instability)";
+    case FDTD_ESTATE: return "invalid state for this call";
+    default: return "unknown status";
+  }
+}
+
+const char* fdtd_rom_last_error(void) { return g_err.c_str(); }
+
+int fdtd_rom_workspace_size(const fdtd_problem* prob, size_t* bytes) {
+  if (!bytes) return fail(FDTD_EINVAL, "null output");
+  try {
+    Layout L;
+    const int rc = plan(prob, L);
+    if (rc != FDTD_OK) return rc;
+    *bytes = L.total;
+    return FDTD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(FDTD_ENOMEM, "host allocation failed");
+  }
+}
+
+int fdtd_rom_create(const fdtd_problem* prob, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                    fdtd_rom_sim** out) {
+  if (!out) return fail(FDTD_EINVAL, "null output handle");
+  *out = nullptr;
+  try {
+    Layout L;
+    int rc = plan(prob, L);
+    if (rc != FDTD_OK) return rc;
+    if (!dev_workspace) return fail(FDTD_EINVAL, "null workspace");
+    if (((uintptr_t)dev_workspace) % 256) return fail(FDTD_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total) return fail(FDTD_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+    std::vector<unsigned char> inside;
+    rc = validate_numbers(prob, L, inside);
+    if (rc != FDTD_OK) return rc;
+    fdtd_rom_sim* s = new fdtd_rom_sim();
+    s->dtype = prob->grid.dtype;
+    s->nx = prob->grid.nx;
+    s->ny = prob->grid.ny;
+    s->pitch = L.pitch;
+    s->dx = prob->grid.dx;
+    s->dy = prob->grid.dy;
+    s->dt = prob->grid.dt;
+    s->max_steps = prob->max_steps;
+    s->nprobes = prob->nprobes;
+    s->nsrc = prob->nsources;
+    s->nroms = prob->nroms;
+    s->stream = (hipStream_t)hip_stream;
+    s->ws = (char*)dev_workspace;
+    s->L = L;
+    rc = coupling_precompute(prob, s->roms);
+    if (rc == FDTD_OK)
+      rc = (s->dtype == FDTD_F32) ? setup_device<float>(s, prob, inside)
+                                  : setup_device<double>(s, prob, inside);
+    if (rc != FDTD_OK) {
+      delete s;
+      return rc;
+    }
+    *out = s;
+    return FDTD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(FDTD_ENOMEM, "host allocation failed");
+  }
+}
+
+int fdtd_rom_step(fdtd_rom_sim* sim) { return fdtd_rom_run(sim, 1); }
+
+int fdtd_rom_run(fdtd_rom_sim* sim, int32_t nsteps) {
+  if (!sim) return fail(FDTD_EINVAL, "null handle");
+  if (nsteps < 0) return fail(FDTD_EINVAL, "negative step count");
+  if ((int64_t)sim->steps + nsteps > sim->max_steps)
+    return fail(FDTD_ESTATE, "%d + %d steps exceed max_steps=%d", sim->steps, nsteps, sim->max_steps);
+  return sim->dtype == FDTD_F32 ? run_steps<float>(sim, nsteps) : run_steps<double>(sim, nsteps);
+}
+
+int fdtd_rom_steps_done(const fdtd_rom_sim* sim, int32_t* n) {
+  if (!sim || !n) return fail(FDTD_EINVAL, "null argument");
+  *n = sim->steps;
+  return FDTD_OK;
+}
+
+int fdtd_rom_read_probes(const fdtd_rom_sim* sim, int32_t first, int32_t count, double* host_out) {
+  if (!sim || (!host_out && count > 0)) return fail(FDTD_EINVAL, "null argument");
+  if (first < 0 || count < 0 || (int64_t)first + count > sim->steps)
+    return fail(FDTD_EINVAL, "probe rows [%d, %d) outside the %d steps taken", first, first + count, sim->steps);
+  const size_t n = (size_t)count * sim->nprobes;
+  if (n == 0) return FDTD_OK;
+  const size_t ts = sim->L.tsize;
+  std::vector<char> raw(n * ts);
+  if (hipMemcpyAsync(raw.data(), sim->ws + sim->L.off_pbuf + (size_t)first * sim->nprobes * ts, n * ts,
+                     hipMemcpyDeviceToHost, sim->stream) != hipSuccess ||
+      hipStreamSynchronize(sim->stream) != hipSuccess)
+    return fail(FDTD_EDEVICE, "probe read failed: %s", hipGetErrorString(hipGetLastError()));
+  if (ts == 4) to_double<float>(raw, n, host_out);
+  else to_double<double>(raw, n, host_out);
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(host_out[k])) return fail(FDTD_EUNSTABLE, "non-finite probe value at row %zu", first + k / sim->nprobes);
+  return FDTD_OK;
+}
+
+int fdtd_rom_read_field(const fdtd_rom_sim* sim, int32_t comp, double* host_out) {
+  if (!sim || !host_out) return fail(FDTD_EINVAL, "null argument");
+  if (comp < 0 || comp > 2) return fail(FDTD_EINVAL, "bad component");
+  const size_t ts = sim->L.tsize, fe = sim->L.field_elems;
+  std::vector<char> raw(fe * ts);
+  const char* src = sim->ws + sim->L.off_fields + (3 * sim->cur + comp) * fe * ts;
+  if (hipMemcpyAsync(raw.data(), src, fe * ts, hipMemcpyDeviceToHost, sim->stream) != hipSuccess ||
+      hipStreamSynchronize(sim->stream) != hipSuccess)
+    return fail(FDTD_EDEVICE, "field read failed");
+  std::vector<double> d(fe);
+  if (ts == 4) to_double<float>(raw, fe, d.data());
+  else to_double<double>(raw, fe, d.data());
+  const int nx = sim->nx, ny = sim->ny, P = sim->pitch;
+  if (comp == FDTD_HZ) {
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) host_out[(size_t)j * nx + i] = d[(size_t)j * P + i];
+  } else if (comp == FDTD_EX) {
+    for (int j = 0; j <= ny; ++j)
+      for (int i = 0; i < nx; ++i) host_out[(size_t)j * nx + i] = j < ny ? d[(size_t)j * P + i] : 0.0;
+  } else {
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i <= nx; ++i) host_out[(size_t)j * (nx + 1) + i] = i < nx ? d[(size_t)j * P + i] : 0.0;
+  }
+  return FDTD_OK;
+}
+
+int fdtd_rom_read_rom_state(const fdtd_rom_sim* sim, int32_t k, double* host_out) {
+  if (!sim || !host_out) return fail(FDTD_EINVAL, "null argument");
+  if (k < 0 || k >= sim->nroms) return fail(FDTD_EINVAL, "region index out of range");
+  const size_t ts = sim->L.tsize;
+  const int q = sim->roms[k].q;
+  std::vector<char> raw((size_t)q * ts);
+  if (hipMemcpyAsync(raw.data(), sim->ws + sim->L.off_xs + sim->L.x_off[k] * ts, q * ts, hipMemcpyDeviceToHost,
+                     sim->stream) != hipSuccess ||
+      hipStreamSynchronize(sim->stream) != hipSuccess)
+    return fail(FDTD_EDEVICE, "state read failed");
+  if (ts == 4) to_double<float>(raw, q, host_out);
+  else to_double<double>(raw, q, host_out);
+  return FDTD_OK;
+}
+
+int fdtd_rom_coupled_update(const fdtd_problem* prob, int32_t k, double* A, double* B, double* C) {
+  try {
+    Layout L;
+    int rc = plan(prob, L);
+    if (rc != FDTD_OK) return rc;
+    if (k < 0 || k >= prob->nroms) return fail(FDTD_EINVAL, "region index out of range");
+    std::vector<unsigned char> inside;
+    rc = validate_numbers(prob, L, inside);
+    if (rc != FDTD_OK) return rc;
+    std::vector<RomHost> roms;
+    rc = coupling_precompute(prob, roms);
+    if (rc != FDTD_OK) return rc;
+    const RomHost& h = roms[k];
+    if (A) std::memcpy(A, h.A.data(), h.A.size() * sizeof(double));
+    if (B) std::memcpy(B, h.B.data(), h.B.size() * sizeof(double));
+    if (C) std::memcpy(C, h.C.data(), h.C.size() * sizeof(double));
+    return FDTD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(FDTD_ENOMEM, "host allocation failed");
+  }
+}
+
+int fdtd_rom_profile_enable(fdtd_rom_sim* sim, int32_t enable) {
+  if (!sim) return fail(FDTD_EINVAL, "null handle");
+  sim->prof = enable != 0;
+  return FDTD_OK;
+}
+
+int fdtd_rom_profile_read(fdtd_rom_sim* sim, double* stencil_ms, int64_t* stencil_launches, double* coupling_ms,
+                          int64_t* coupling_launches) {
+  if (!sim) return fail(FDTD_EINVAL, "null handle");
+  if (hipStreamSynchronize(sim->stream) != hipSuccess) return fail(FDTD_EDEVICE, "synchronize failed");
+  double a = 0, b = 0;
+  for (size_t k = 0; k < sim->used_st; ++k) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, sim->ev_st[k].first, sim->ev_st[k].second) != hipSuccess)
+      return fail(FDTD_EDEVICE, "hipEventElapsedTime failed");
+    a += ms;
+  }
+  for (size_t k = 0; k < sim->used_cp; ++k) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, sim->ev_cp[k].first, sim->ev_cp[k].second) != hipSuccess)
+      return fail(FDTD_EDEVICE, "hipEventElapsedTime failed");
+    b += ms;
+  }
+  if (stencil_ms) *stencil_ms = a;
+  if (stencil_launches) *stencil_launches = (int64_t)sim->used_st;
+  if (coupling_ms) *coupling_ms = b;
+  if (coupling_launches) *coupling_launches = (int64_t)sim->used_cp;
+  sim->used_st = sim->used_cp = 0;
+  return FDTD_OK;
+}
+
+void fdtd_rom_destroy(fdtd_rom_sim* sim) {
+  if (!sim) return;
+  for (auto& e : sim->ev_st) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
+  for (auto& e : sim->ev_cp) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
+  delete sim;
+}
+
+}  // extern "C"

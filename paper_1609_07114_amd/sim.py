@@ -1,0 +1,74 @@
+"""Simulation handle: device workspace from PyTorch, stream from PyTorch,
+every computation in the HIP library (capi)."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import capi
+
+
+class Simulation:
+    def __init__(self, prob, rom_mats, max_steps=None, dtype=None, x0=None, device="cuda:0"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("a ROCm GPU is required (torch.cuda.is_available() is False)")
+        self.torch = torch
+        self.prob = prob
+        self.ps = capi.ProblemStruct.from_workload(prob, rom_mats, max_steps=max_steps,
+                                                   dtype=dtype, x0=x0)
+        self.nbytes = capi.fdtd_rom_workspace_size(self.ps)
+        self.device = torch.device(device)
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = capi.fdtd_rom_create(self.ps, self.ws.data_ptr(), self.nbytes,
+                                      self.stream.cuda_stream)
+        self.nprobes = len(prob.probes)
+        self.q = [m["Rt"].shape[0] for m in rom_mats]
+
+    def run(self, nsteps):
+        capi.fdtd_rom_run(self.h, nsteps)
+
+    def step(self):
+        capi.fdtd_rom_step(self.h)
+
+    @property
+    def steps_done(self):
+        return capi.fdtd_rom_steps_done(self.h)
+
+    def probes(self, first=0, count=None):
+        if count is None:
+            count = self.steps_done - first
+        return capi.fdtd_rom_read_probes(self.h, first, count, self.nprobes)
+
+    def field(self, comp):
+        return capi.fdtd_rom_read_field(self.h, comp, self.prob.nx, self.prob.ny)
+
+    def rom_state(self, k):
+        return capi.fdtd_rom_read_rom_state(self.h, k, self.q[k])
+
+    def coupled_update(self, k):
+        return capi.fdtd_rom_coupled_update(self.ps, k)
+
+    def profile(self, enable=True):
+        capi.fdtd_rom_profile_enable(self.h, enable)
+
+    def profile_read(self):
+        return capi.fdtd_rom_profile_read(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            self.stream.synchronize()
+            capi.fdtd_rom_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

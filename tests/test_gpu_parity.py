@@ -1,0 +1,156 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle
+on identical seeded inputs and identical reduced models (built by the
+oracle).  Bars: FP64 runs <= 1e-12 relative L2, FP32 runs <= 1e-5 relative
+L2 against the oracle evaluated in FP64 with the FP32-rounded coefficients
+and coupling matrices an FP32 run computes with."""
+import copy
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import sim as osim
+from oracle import subgrid as osub
+from paper_1609_07114_amd import capi
+from paper_1609_07114_amd.sim import Simulation
+from tests._util import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _gpu_run(prob, roms, nsteps=None, dtype=None, chunks=None, x0=None):
+    nsteps = prob.nsteps if nsteps is None else nsteps
+    print(f"[gpu] {prob.name} {dtype or prob.dtype} steps={nsteps} roms={len(roms)}", flush=True)
+    with Simulation(prob, roms, max_steps=nsteps, dtype=dtype, x0=x0) as s:
+        if chunks:
+            done = 0
+            for c in chunks:
+                s.run(c)
+                done += c
+            s.run(nsteps - done)
+        else:
+            s.run(nsteps)
+        out = dict(probes=s.probes(), hz=s.field(0), ex=s.field(1), ey=s.field(2),
+                   x=[s.rom_state(k) for k in range(len(roms))])
+    return out
+
+
+def _oracle(prob, roms, nsteps=None, fp32=False, mode="closed", init=None):
+    run = osim.CoupledRun(prob, roms, mode=mode, fp32=fp32, init=init)
+    nsteps = prob.nsteps if nsteps is None else nsteps
+    pr = np.empty((nsteps, len(prob.probes)))
+    for n in range(nsteps):
+        run.step()
+        pr[n] = run.probes()
+    return dict(probes=pr, hz=run.f.hz * run.cell, ex=run.f.ex, ey=run.f.ey, x=run.x)
+
+
+def _compare(g, o, tol, fields=True):
+    assert rel_l2(g["probes"], o["probes"]) <= tol, rel_l2(g["probes"], o["probes"])
+    if fields:
+        for k in ("hz", "ex", "ey"):
+            assert rel_l2(g[k], o[k]) <= tol, (k, rel_l2(g[k], o[k]))
+        for a, b in zip(g["x"], o["x"]):
+            assert rel_l2(a, b) <= tol, rel_l2(a, b)
+
+
+def test_c1_cavity_fp64_literal():
+    """60x60 cavity, one order-40 model, 2000 steps, FP64: against the
+    oracle's literal eq. (19) solve."""
+    p = W.cavity_c1()
+    roms = osim.build_roms(p)
+    g = _gpu_run(p, roms)
+    o = _oracle(p, roms, mode="literal")
+    assert np.max(np.abs(o["probes"])) > 1e-3
+    _compare(g, o, TOL64)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_random_two_models_full_state(dtype, tol):
+    p = W.random_problem(3, 70, 45, 400, nroms=2, block=(5, 4), r=2, q=12)
+    roms = osim.build_roms(p)
+    g = _gpu_run(p, roms, dtype=dtype)
+    o = _oracle(p, roms, fp32=(dtype == "f32"))
+    _compare(g, o, tol)
+
+
+@pytest.mark.parametrize("nx,ny", [(65, 33), (130, 77), (64, 64), (200, 5), (3, 90)])
+@pytest.mark.parametrize("dtype,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_ragged_grids_no_models(nx, ny, dtype, tol):
+    """Tile tails in x (64-wide waves) and y (segments), all source and
+    probe components, no reduced regions."""
+    p = W.random_problem(40 + nx, nx, ny, 150, nroms=0)
+    g = _gpu_run(p, [], dtype=dtype)
+    o = _oracle(p, [], fp32=(dtype == "f32"))
+    _compare(g, o, tol)
+
+
+def test_chunked_runs_equal_one_run():
+    p = W.random_problem(8, 50, 40, 120, nroms=1, block=(5, 5), r=2, q=10)
+    roms = osim.build_roms(p)
+    a = _gpu_run(p, roms, dtype="f64")
+    b = _gpu_run(p, roms, dtype="f64", chunks=[1, 1, 7, 50])
+    assert np.array_equal(a["probes"], b["probes"])
+    assert np.array_equal(a["hz"], b["hz"])
+
+
+def test_identity_basis_r1_is_plain_yee():
+    p = W.random_problem(1, 90, 70, 300, nroms=1, block=(5, 4), r=1, q=0)
+    roms = osim.build_roms(p, basis="identity", clip=False)
+    g = _gpu_run(p, roms, dtype="f64")
+    pp = copy.deepcopy(p)
+    s = p.roms[0]
+    pp.eps_r[s.j0:s.j0 + s.nj, s.i0:s.i0 + s.ni] = s.eps_r
+    pp.sigma[s.j0:s.j0 + s.nj, s.i0:s.i0 + s.ni] = s.sigma
+    pp.roms = []
+    ref = osim.run(pp, [])
+    assert rel_l2(g["probes"], ref) <= TOL64
+
+
+def test_identity_basis_r2_is_subgridding():
+    p = W.random_problem(3, 40, 36, 300, nroms=2, block=(5, 4), r=2, q=0)
+    roms = osim.build_roms(p, basis="identity", clip=False)
+    g = _gpu_run(p, roms, dtype="f64")
+    ref = osub.run(p)
+    assert rel_l2(g["probes"], ref) <= TOL64
+
+
+def test_initial_reduced_state_energy_decay():
+    """Start from a random reduced state (no source): the run must follow
+    the oracle and the oracle's storage function must not increase."""
+    p = W.random_problem(9, 40, 36, 200, nroms=2, block=(5, 4), r=2, q=12)
+    for s in p.sources:
+        s.incr[:] = 0
+    roms = osim.build_roms(p)
+    rng = np.random.default_rng(3)
+    x0 = [rng.standard_normal(m["Rt"].shape[0]) for m in roms]
+    g = _gpu_run(p, roms, dtype="f64", x0=x0)
+    init = dict(hz=np.zeros((p.ny, p.nx)), ex=np.zeros((p.ny + 1, p.nx)),
+                ey=np.zeros((p.ny, p.nx + 1)), x=x0)
+    o = _oracle(p, roms, init=init)
+    _compare(g, o, TOL64)
+
+
+def test_random_media_256_fp32():
+    """Reduced C2 recipe: 256^2 random patch medium, four models of orders
+    16-48, dt = 0.95 coarse CFL, 1500 steps, FP32."""
+    p = W.random_media(n=256, nsteps=1500, spacing=128, offset=48, block=16,
+                       qs=(16, 24, 32, 48), n_probe_side=4)
+    roms = osim.build_roms(p)
+    g = _gpu_run(p, roms)
+    o = _oracle(p, roms, fp32=True)
+    assert np.max(np.abs(o["probes"])) > 0
+    _compare(g, o, TOL32)
+
+
+def test_max_steps_enforced():
+    p = W.random_problem(2, 30, 30, 10, nroms=0)
+    with Simulation(p, [], max_steps=10) as s:
+        s.run(10)
+        with pytest.raises(capi.FdtdError) as e:
+            s.run(1)
+        assert e.value.status == capi.FDTD_ESTATE
