@@ -1,0 +1,189 @@
+"""Benchmark: coarse-grid FDTD with embedded reduced models on one MI355X.
+
+Workload (default): the 2048 x 2048 FP32 random-medium run - eps_r in
+[1, 10], sigma in [0, 0.05] S/m per 32x32 patch (seeded), 16 embedded
+32x32-cell regions refined 4x with orders {32, 48, 64, 96}, dt = 0.95 x the
+coarse vacuum CFL limit, 10,000 steps, 64 probes.  A step is one leap-frog
+step of the whole hot path: fused Hz/E stencil, every model's gather /
+reduced update / scatter, probe record.  Reduced models come from the
+library's host FP64 builder (setup, not timed).
+
+Prints one JSON line (metric, value in Mcell-updates/s, roofline of the
+stencil kernel from HIP events, oracle CPU baseline on a bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mcell-updates/s + % HBM roofline; batched & adjoint vs plain, 1 GPU, 1e-5 err"
+PEAK_HBM_GBS = 8000.0
+# algorithmic bytes of one step launch (FP32): per coarse cell Hz, Ex, Ey read
+# + write (24 B) and the per-cell material pair (a, b) read (8 B); per model
+# the (q+np)^2 update matrix of eq. (23) read once
+BYTES_PER_CELL_F32 = 32
+
+
+def step_bytes(prob):
+    cells = prob.nx * prob.ny
+    mats = sum(4 * (s.q + s.n_ports) ** 2 for s in prob.roms)
+    return BYTES_PER_CELL_F32 * cells + mats
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "stencil_c2_2048_hbm_counters.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("paper_1609_07114_amd/csrc/kernels.hip", "paper_1609_07114_amd/csrc/common.hpp"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per stencil launch from committed rocprofv3 counter runs,
+    if they were taken on the current kernel source (else None)."""
+    try:
+        with open(COUNTERS_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(prob, nsteps):
+    """The oracle (NumPy FP64, closed form of eq. (23)) stepping the same
+    grid for a bounded number of steps.  Model matrices are placeholders of
+    the same orders (building oracle models is setup and is not timed)."""
+    import numpy as np
+    from oracle import sim as osim
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    rng = np.random.default_rng(0)
+    roms = []
+    for s in prob.roms:
+        q, npt = s.q, s.n_ports
+        roms.append(dict(Rt=np.eye(q), Ft=np.zeros((q, q)),
+                         Lt=1e-3 * rng.standard_normal((q, npt))))
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        run = osim.CoupledRun(prob, roms, mode="closed", fp32=True)
+        run.step()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            run.step()
+            run.probes()
+        dt = time.perf_counter() - t0
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    rate = prob.nx * prob.ny * nsteps / dt / 1e6
+    return {"value": rate, "unit": "Mcell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle NumPy FP64 (closed-form eq. (23), FP32-rounded coefficients) on the "
+                      f"same {prob.nx}x{prob.ny} grid with {len(prob.roms)} models of the same "
+                      f"orders, {nsteps} steps after 1 untimed step, single thread; model "
+                      f"matrices are same-shape placeholders",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--n", type=int, default=2048, help="grid size (default: the 2048^2 workload)")
+    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_1609_07114_amd import romgen
+    from paper_1609_07114_amd.sim import Simulation
+
+    if not torch.cuda.is_available():
+        print("bench.py: no ROCm GPU visible", file=sys.stderr)
+        sys.exit(1)
+    total = args.warmup + args.steps
+    prob = W.random_media(n=args.n, nsteps=total)
+    t0 = time.perf_counter()
+    roms = romgen.build_roms(prob)
+    t_build = time.perf_counter() - t0
+    print(f"bench: {len(roms)} reduced models built in {t_build:.1f} s", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy_mib:
+        nb = args.calibrate_copy_mib << 20
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    sim = Simulation(prob, roms, max_steps=total)
+    sim.run(args.warmup)
+    torch.cuda.synchronize()
+    sim.profile(True)
+    sim.profile_read()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st_ms, st_n, tail_ms, tail_n = sim.profile_read()
+    sim.profile(False)
+    probes = sim.probes(0, total)
+    sim.close()
+    import numpy as np
+    finite = bool(np.all(np.isfinite(probes)))
+
+    elapsed = t1 - t0
+    ms_step = elapsed * 1e3 / args.steps
+    cells = prob.nx * prob.ny
+    value = cells * args.steps / elapsed / 1e6
+    st_avg_s = st_ms / st_n / 1e3
+    alg_bytes = step_bytes(prob)
+    achieved = alg_bytes / st_avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
+                "kernel": "step_kernel<float,16>", "bytes_per_launch": alg_bytes,
+                "avg_launch_us": round(st_avg_s * 1e6, 3), "launches": st_n}
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mcell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"C2 random media {prob.nx}x{prob.ny}, 16 embedded 32x32-cell "
+                               f"models (r=4, q in 32/48/64/96), dt=0.95 coarse CFL, "
+                               f"{args.steps} timed steps, 64 probes",
+                   "nx": prob.nx, "ny": prob.ny, "n_models": len(prob.roms),
+                   "orders": sorted({s.q for s in prob.roms}), "parallelism": "single GPU"},
+        "roofline": roofline,
+        "run_tail_us": round(tail_ms / max(tail_n, 1) * 1e3, 3),
+        "model_build_s": round(t_build, 2),
+        "finite": finite,
+    }
+    print(f"bench: GPU {value:.0f} Mcell-updates/s, {ms_step:.4f} ms/step", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -166,13 +166,60 @@ int fdtd_rom_read_rom_state(const fdtd_rom_sim* sim, int32_t k, double* host_out
 int fdtd_rom_coupled_update(const fdtd_problem* prob, int32_t k, double* A, double* B,
                             double* C);
 
-/* Per-kernel timing with HIP events on the handle's stream: while enabled,
- * every stencil launch and every coupling launch is bracketed by events;
- * fdtd_rom_profile_read synchronises and returns the summed durations (ms)
- * and launch counts since the last reset. */
+/* Reduced model of one refined region, built on the host in FP64 (paper
+ * Sec. II eqs. (2)-(8), Sec. III eqs. (9)-(12), Sec. V-E eq. (27)):
+ *   1. the fine TEz model of the region (r*ni x r*nj cells of dx/r x dy/r,
+ *      boundary half cells and hanging variables, eqs. (3)-(8)), with the r
+ *      fine boundary E samples of each coarse interface edge tied together
+ *      (interpolation rule eq. (15) applied before reduction), so that the
+ *      model has np = 2(ni+nj) coarse ports, input matrix Lc Sc;
+ *   2. block Krylov directions of (p0 R + F)^{-1} R from (p0 R + F)^{-1} B
+ *      at p0 = pi * f_max * dt, each block orthogonalised against earlier
+ *      directions in the mass inner product diag(De, Dm)/dt and ordered by
+ *      decreasing mass norm;
+ *   3. SPRIM split (eq. (9)): V1 = the E rows, V2 = the H rows of those
+ *      directions, Gram-Schmidt in order, q1 = ceil(q/2), q2 = floor(q/2);
+ *   4. congruence R~ = V^T R V, F~ = V^T F V, L~ = V^T Lc (eqs. (11)-(12));
+ *   5. if clip != 0 and the largest singular value of
+ *      R11^{-1/2} K~ R22^{-1/2} exceeds theta * 2/dt (eq. (27)), the
+ *      singular values above that bound are lowered to it and K~ is
+ *      replaced in R~ and F~ (theta <= 0 selects 0.99).
+ * eps_r, sigma: host fine-cell maps [(r*nj) * (r*ni)], row-major.
+ * Outputs (caller-allocated, row-major): Rt [q*q], Ft [q*q], Lt [q*np];
+ * state order: q1 E coordinates then q2 H coordinates.  FDTD_EINVAL if the
+ * Krylov space deflates below q.  Thread-safe (no shared state). */
+typedef struct {
+  int32_t ni, nj, r;
+  double dx, dy, dt;
+  const double* eps_r;
+  const double* sigma;
+  int32_t q;
+  double f_max;
+  double theta;
+  int32_t clip;
+} fdtd_rom_build_params;
+
+typedef struct {
+  int32_t q1, q2;
+  double p0;
+  double smax_before, smax_after; /* largest s_k of eq. (27) before/after */
+  int32_t clipped;
+  int32_t n_fine_states;          /* size of the restricted fine model */
+} fdtd_rom_build_info;
+
+int fdtd_rom_build(const fdtd_rom_build_params* params, double* Rt, double* Ft, double* Lt,
+                   fdtd_rom_build_info* info);
+
+/* Per-kernel timing with HIP events on the handle's stream.  One step is
+ * one launch of the step kernel (coarse stencil, every model's eq. (23)
+ * update and the probe record run as concurrent workgroups of that launch);
+ * each run() call ends with a probe-flush and a step-counter launch.  While
+ * enabled, every step launch and every end-of-run pair are bracketed by
+ * events; fdtd_rom_profile_read synchronises and returns the summed
+ * durations (ms) and counts since the last read. */
 int fdtd_rom_profile_enable(fdtd_rom_sim* sim, int32_t enable);
-int fdtd_rom_profile_read(fdtd_rom_sim* sim, double* stencil_ms, int64_t* stencil_launches,
-                          double* coupling_ms, int64_t* coupling_launches);
+int fdtd_rom_profile_read(fdtd_rom_sim* sim, double* step_ms, int64_t* step_launches,
+                          double* tail_ms, int64_t* tail_launches);
 
 /* Release the handle (the workspace stays the caller's). */
 void fdtd_rom_destroy(fdtd_rom_sim* sim);

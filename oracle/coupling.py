@@ -16,7 +16,8 @@ literal system of eq. (19) in z = [y; U; x~] reads
   A1 z^{n+1} = A2 z^n + [Sc H^{n+1/2}; 0; 0]                   (eq. (19))
 with C+- = Dl Dl' (De/dt +- Ds/2).  Eliminating y and U (y = L~^T x~ at
 every step) gives the closed form of eq. (23):
-  x~^{n+1} = A~ x~^n + B~' H^{n+1/2},  y^{n+1} = C~ x~^{n+1},
+  x~^{n+1} = A~ x~^n + B~' H^{n+1/2},  y^{n+1} = C~ x~^{n+1}
+           = C~ A~ x~^n + C~ B~' H^{n+1/2},
   A~ = (R~+F~+L~ C+ L~^T)^{-1} (R~-F~+L~ C- L~^T),
   B~' = (R~+F~+L~ C+ L~^T)^{-1} L~ Sc,  C~ = L~^T.
 
@@ -113,6 +114,13 @@ class RomCoupling:
         B = np.linalg.solve(M, Lt * self.Sc[None, :])
         C = Lt.T.copy()
         return A, B, C
+
+    def update_matrix(self):
+        """Eq. (23) as one map on [x~^n; h^{n+1/2}] -> [x~^{n+1}; y^{n+1}]:
+        G = [[A~, B~'], [C~ A~, C~ B~']] (y^{n+1} taken directly from the
+        step-n quantities, as eq. (23) gives it)."""
+        A, B, C = self.closed_form()
+        return np.block([[A, B], [C @ A, C @ B]])
 
     def gather(self, hz):
         return np.array([hz[oj, oi] for (_, _, _, oi, oj, _, _) in self.ports])

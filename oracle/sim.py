@@ -35,9 +35,10 @@ from .yee import EX, EY, HZ
 class CoupledRun:
     def __init__(self, prob, roms, mode="literal", fp32=False, init=None):
         """``roms``: list of dict(Rt, Ft, Lt) aligned with prob.roms.
-        mode 'literal' solves eq. (19); 'closed' applies eq. (23) (with
-        fp32=True its matrices, like the stencil coefficients, are rounded
-        to float32 first, which is what an FP32 run computes with)."""
+        mode 'literal' solves eq. (19); 'closed' applies eq. (23).  With
+        fp32=True the stencil coefficients and eq. (23)'s update matrix on
+        [x~^n; h] are rounded to float32 first (what an FP32 run computes
+        with) and the run proceeds in FP64 arithmetic."""
         self.prob = prob
         self.mode = mode
         nx, ny = prob.nx, prob.ny
@@ -53,9 +54,10 @@ class CoupledRun:
                             spec.nj, prob.eps_r, prob.sigma, prob.dx, prob.dy,
                             prob.dt)
             A, B, C = c.closed_form()
-            if fp32:
-                A, B, C = (np.asarray(M, np.float32).astype(np.float64) for M in (A, B, C))
             c.Ac, c.Bc, c.Cc = A, B, C
+            # an FP32 run rounds eq. (23)'s update matrix on [x~^n; h]
+            c.G32 = (np.asarray(c.update_matrix(), np.float32).astype(np.float64)
+                     if fp32 else None)
             self.cpl.append(c)
         self.x = [np.zeros(c.q) for c in self.cpl]
         if init is not None:
@@ -81,6 +83,10 @@ class CoupledRun:
                 iy, iu, ix = c.sl
                 self.x[k] = self.z[k][ix].copy()
                 y = self.z[k][iy]
+            elif c.G32 is not None:
+                out = c.G32 @ np.concatenate([self.x[k], h])
+                self.x[k] = out[:c.q]
+                y = out[c.q:]
             else:
                 self.x[k] = c.Ac @ self.x[k] + c.Bc @ h
                 y = c.Cc @ self.x[k]

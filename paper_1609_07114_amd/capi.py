@@ -48,6 +48,19 @@ class fdtd_problem(C.Structure):
                 ("max_steps", C.c_int32)]
 
 
+class fdtd_rom_build_params(C.Structure):
+    _fields_ = [("ni", C.c_int32), ("nj", C.c_int32), ("r", C.c_int32), ("dx", C.c_double),
+                ("dy", C.c_double), ("dt", C.c_double), ("eps_r", _dp), ("sigma", _dp),
+                ("q", C.c_int32), ("f_max", C.c_double), ("theta", C.c_double),
+                ("clip", C.c_int32)]
+
+
+class fdtd_rom_build_info(C.Structure):
+    _fields_ = [("q1", C.c_int32), ("q2", C.c_int32), ("p0", C.c_double),
+                ("smax_before", C.c_double), ("smax_after", C.c_double),
+                ("clipped", C.c_int32), ("n_fine_states", C.c_int32)]
+
+
 class FdtdError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{msg} (status {status})")
@@ -68,6 +81,8 @@ _SIGS = {
     "fdtd_rom_read_field": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
     "fdtd_rom_read_rom_state": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
     "fdtd_rom_coupled_update": (C.c_int, [C.POINTER(fdtd_problem), C.c_int32, _dp, _dp, _dp]),
+    "fdtd_rom_build": (C.c_int, [C.POINTER(fdtd_rom_build_params), _dp, _dp, _dp,
+                                 C.POINTER(fdtd_rom_build_info)]),
     "fdtd_rom_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "fdtd_rom_profile_read": (C.c_int, [C.c_void_p, _dp, C.POINTER(C.c_int64), _dp,
                                         C.POINTER(C.c_int64)]),
@@ -84,6 +99,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: run paper_1609_07114_amd.build.build() "
                                "(hipcc, gfx950) first; there is no CPU fallback")
+        # PyTorch-ROCm carries its own HIP runtime, loaded under the soname
+        # libamdhip64.so.7 that this library links against.  Importing torch
+        # first makes the dynamic loader bind this library to that one
+        # runtime; loading the library first would put a second HIP runtime
+        # in the process, and device pointers from torch would be foreign to it.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
@@ -216,6 +237,24 @@ def fdtd_rom_coupled_update(problem: ProblemStruct, k: int):
     Cm = np.zeros((np_, q))
     _check(lib().fdtd_rom_coupled_update(C.byref(problem.s), k, _ptr(A), _ptr(B), _ptr(Cm)))
     return A, B, Cm
+
+
+def fdtd_rom_build(ni, nj, r, dx, dy, dt, eps_r, sigma, q, f_max, theta=0.99, clip=True):
+    """Reduced model of one refined region (host FP64 in the library)."""
+    er = np.ascontiguousarray(eps_r, dtype=np.float64)
+    sg = np.ascontiguousarray(sigma, dtype=np.float64)
+    assert er.shape == (r * nj, r * ni) and sg.shape == er.shape
+    np_ = 2 * (ni + nj)
+    Rt = np.zeros((q, q))
+    Ft = np.zeros((q, q))
+    Lt = np.zeros((q, np_))
+    prm = fdtd_rom_build_params(ni, nj, r, dx, dy, dt, _ptr(er), _ptr(sg), q, f_max, theta,
+                                1 if clip else 0)
+    info = fdtd_rom_build_info()
+    _check(lib().fdtd_rom_build(C.byref(prm), _ptr(Rt), _ptr(Ft), _ptr(Lt), C.byref(info)))
+    return dict(Rt=Rt, Ft=Ft, Lt=Lt, q1=info.q1, q2=info.q2, p0=info.p0,
+                smax_before=info.smax_before, smax_after=info.smax_after,
+                clipped=bool(info.clipped), n_fine_states=info.n_fine_states)
 
 
 def fdtd_rom_profile_enable(h, enable: bool):

@@ -25,56 +25,70 @@ struct Src {
 //                                zero; Ex(.,ny) is the north wall, implicit)
 //   Ey(i,j) at ey[j*pitch+i]   (i < nx; Ey(0,.) is the west wall, stored
 //                                zero; Ey(nx,.) is the east wall, implicit)
-// so every cell owns its Hz, its south Ex and its west Ey.
+// so every cell owns its Hz, its south Ex and its west Ey.  Two such sets
+// ping-pong: the state after n steps (E^n, Hz^{n-1/2}) lives in set n & 1.
+
+// One embedded model on the device.  Its update is eq. (23) written as one
+// matrix on z = [x~^n; h^{n+1/2}]:
+//   [x~^{n+1}; y^{n+1}] = G z,  G = [[A~, B~'], [C~ A~, C~ B~']],
+// rows padded to a multiple of kRowsPerBlock, row stride ldg (multiple of 64).
+struct RomDev {
+  int q, np, n_ex;   // n_ex: ports [0, n_ex) are Ex (S, N), the rest Ey (W, E)
+  int ldg;           // padded row length of G (>= q + np)
+  int64_t g_off;     // G, row-major
+  int64_t x_off;     // reduced state, two buffers of xstride (step parity)
+  int64_t xstride;
+  int64_t i_off;     // gather offsets [np] (Hz cells) then scatter offsets [np]
+};
+
+constexpr int kRowsPerWave = 4;
+constexpr int kRowsPerBlock = kRowsPerWave * (kBlock / kWave);
+
+struct RowBlock {
+  int rom;
+  int row0;          // first of kRowsPerBlock rows of G
+};
+
+// Everything one leap-frog step needs.  One launch advances every tile of
+// the coarse grid and every embedded model from step n to n+1, where
+// n = ctrl[0] + step_off (ctrl[0] is advanced by a tick launch after each
+// batch of steps, so a captured batch can be replayed).
 template <typename T>
-struct StencilParams {
-  const T* hz;
-  const T* ex;
-  const T* ey;
-  T* hzo;
-  T* exo;
-  T* eyo;
+struct StepParams {
+  T* f[2][3];        // field sets [parity][Hz, Ex, Ey]
   const T* al;       // per cell eps0*eps_r/dt; negative inside reduced regions
   const T* be;       // per cell sigma/2
-  const int* ctrl;
+  int* ctrl;
+  int step_off;
   int nx, ny, pitch;
-  int tiles_x, tiles_y, seg;
+  int tiles_x, nst_blocks;
   T chdy, chdx;      // dt/(mu0 dy), dt/(mu0 dx)
   T k2dy, k2dx;      // 2/dy, 2/dx
   int nsrc;
   Src<T> src[kMaxSrc];
-};
-
-// One embedded model on the device.
-struct RomDev {
-  int q, np, n_ex;   // n_ex: ports [0, n_ex) are Ex (S, N), the rest Ey (W, E)
-  int64_t m_off;     // [A~ | B~'] column-major q x (q+np), then C~ column-major np x q
-  int64_t x_off;     // reduced state
-  int64_t i_off;     // gather offsets [np] (Hz cells) then scatter offsets [np]
-};
-
-template <typename T>
-struct CouplingParams {
+  // embedded models
   const RomDev* roms;
-  int nroms;
+  const RowBlock* blocks;
+  int nrowblocks;    // real row blocks
+  int ncoup_blocks;  // row blocks padded to a multiple of 8 (XCD alignment)
   const T* mats;
   T* xs;
   const int* idx;
-  const T* hz;       // step n+1 buffers
-  T* ex;
-  T* ey;
+  // probes
   int nprobes;
   const int* probe_off;
   const int* probe_comp;
   T* probe_buf;      // [max_steps][nprobes]
-  int* ctrl;
-  int nblocks;
 };
+
+// Record a failure message for fdtd_rom_last_error() and return code.
+int fail(int code, const char* fmt, ...);
 
 // launchers (kernels.hip)
 template <typename T>
-hipError_t launch_stencil(const StencilParams<T>& p, int seg, hipStream_t s);
+hipError_t launch_step(const StepParams<T>& p, int seg, hipStream_t s);
 template <typename T>
-hipError_t launch_coupling(const CouplingParams<T>& p, hipStream_t s);
+hipError_t launch_probe_flush(const StepParams<T>& p, hipStream_t s);
+hipError_t launch_tick(int* ctrl, int k, hipStream_t s);
 
 }  // namespace fdtd

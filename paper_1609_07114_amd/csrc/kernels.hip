@@ -1,29 +1,37 @@
 // gfx950 kernels of the embedded-ROM FDTD time step.
 //
-//  yee_step  : fused coarse-grid leap-frog step (paper eqs. (5) then (3)):
-//              Hz^{n-1/2} -> Hz^{n+1/2}, E^n -> E^{n+1}, with additive
-//              sources; reads the step-n buffers, writes the step-(n+1)
-//              buffers (ping-pong, so tiles can recompute their halo).
-//  coupling  : per embedded model, eq. (23) in closed form: gather the coarse
-//              Hz^{n+1/2} next to its ports, x~ <- A~ x~ + B~' h, y <- C~ x~,
-//              scatter y^{n+1} into the interface edges; plus the probe
-//              record and the device step counter.
+// One launch per leap-frog step n -> n+1 (step_kernel).  Its workgroups are
+// of three kinds, all reading only the step-n buffers (set n & 1) and writing
+// disjoint parts of the step-(n+1) buffers, so they run concurrently:
+//   * coupling row blocks (first, so they start early): eq. (23) for every
+//     embedded model, written as one matrix G on z = [x~^n; h^{n+1/2}]
+//     giving [x~^{n+1}; y^{n+1}].  h (the coarse Hz^{n+1/2} just outside the
+//     ports) is recomputed from the step-n fields with the same arithmetic as
+//     the stencil, so it equals the stencil's value bit for bit; y^{n+1} is
+//     written into the interface edges;
+//   * stencil tiles: coarse leap-frog update (eq. (5) then eq. (3)),
+//     Hz^{n-1/2} -> Hz^{n+1/2}, E^n -> E^{n+1} on every edge that is neither
+//     on a PEC wall nor on or inside a reduced region, plus additive sources;
+//   * one probe block: records probe row n-1 (Hz^{n-1/2}, E^n), i.e. the
+//     values the previous launch produced.
+// A probe-flush launch records the last row of a batch and a one-thread tick
+// launch advances the device step base.
 //
 // Stencil design (HBM-bound, one pass per step):
 //   * a wave owns 64 adjacent columns and marches up a segment of SEG rows,
 //     carrying Ex(i,j), Hz^{n+1/2}(i,j-1) and the material of row j-1 in
-//     registers; the horizontal neighbours (Ey(i+1,j), Hz^{n+1/2}(i-1,j),
-//     material of cell i-1) come from adjacent lanes by cross-lane moves,
-//     lanes 0 and 63 fetch the one column outside the wave;
+//     registers, with the loads of row j+1 issued before row j is computed;
+//     horizontal neighbours (Ey(i+1,j), Hz^{n+1/2}(i-1,j), material of cell
+//     i-1) come from adjacent lanes, lanes 0 and 63 fetch the one column
+//     outside the wave;
 //   * each segment recomputes Hz^{n+1/2} of the row below it (one extra row
-//     per SEG), so the whole step needs a single launch;
+//     per SEG), so the step needs no second pass;
 //   * per-edge coefficients are rebuilt from per-cell (a, b) =
 //     (eps0*eps_r/dt, sigma/2): s = a1+a2, t = b1+b2, Ca = (s-t)/(s+t),
 //     Cb/d = (2/d)/(s+t) - 32 algorithmic bytes per cell update instead of
 //     the 40 a per-edge coefficient table would cost;
-//   * cells inside a reduced region carry a < 0: their Hz stays zero and
-//     the edges on and inside the region keep their value (the interface
-//     edges are then written by the coupling kernel);
+//   * cells inside a reduced region carry a < 0: their Hz stays zero, edges
+//     inside keep their (zero) value and interface edges are not written;
 //   * workgroups are remapped so each of the 8 XCDs (own L2) takes a
 //     contiguous band of tiles, keeping the halo rows within one L2.
 #include "common.hpp"
@@ -39,6 +47,14 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
                      : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
+// eq. (5) divided by the cell area; shared by the stencil and the coupling
+// blocks so both produce identical Hz^{n+1/2}
+template <typename T>
+__device__ __forceinline__ T hz_update(T h, T ex0, T ex1, T ey0, T ey1, T chdy, T chdx) {
+#pragma clang fp contract(off)
+  return h + (chdy * (ex1 - ex0) - chdx * (ey1 - ey0));
+}
+
 template <typename T>
 __device__ __forceinline__ void edge_coef(T s, T t, T k2, T& ca, T& cb) {
 #pragma clang fp contract(off)
@@ -47,9 +63,18 @@ __device__ __forceinline__ void edge_coef(T s, T t, T k2, T& ca, T& cb) {
   cb = k2 * rcp;
 }
 
+// field pointer of set `par`, component c (selects, not dynamic indexing of
+// the kernel-argument array)
 template <typename T>
-__device__ __forceinline__ T src_sum(const StencilParams<T>& p, const T* sinc, int comp,
-                                     int i, int j) {
+__device__ __forceinline__ T* fld(const StepParams<T>& p, int par, int c) {
+  T* a = c == 0 ? p.f[0][0] : (c == 1 ? p.f[0][1] : p.f[0][2]);
+  T* b = c == 0 ? p.f[1][0] : (c == 1 ? p.f[1][1] : p.f[1][2]);
+  return par ? b : a;
+}
+
+template <typename T>
+__device__ __forceinline__ T src_sum(const StepParams<T>& p, const T* sinc, int comp, int i,
+                                     int j) {
   T acc = T(0);
 #pragma unroll
   for (int s = 0; s < kMaxSrc; ++s) {
@@ -61,14 +86,42 @@ __device__ __forceinline__ T src_sum(const StencilParams<T>& p, const T* sinc, i
   return acc;
 }
 
+template <typename T>
+struct RowIn {
+  T h, ex1, ey0, al, be;
+};
+
+template <typename T>
+__device__ __forceinline__ RowIn<T> load_row(const T* hz, const T* ex, const T* ey,
+                                             const StepParams<T>& p, size_t o, bool ok, bool up,
+                                             size_t P) {
+  RowIn<T> r{T(0), T(0), T(0), T(0), T(0)};
+  if (ok) {
+    r.h = hz[o];
+    r.ex1 = up ? ex[o + P] : T(0);
+    r.ey0 = ey[o];
+    r.al = p.al[o];
+    r.be = p.be[o];
+  }
+  return r;
+}
+
 template <typename T, int SEG>
-__global__ void __launch_bounds__(kBlock) yee_step(const StencilParams<T> p) {
+__device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
+  const int par = n & 1;
+  const T* hz = fld(p, par, 0);
+  const T* ex = fld(p, par, 1);
+  const T* ey = fld(p, par, 2);
+  T* hzo = fld(p, par ^ 1, 0);
+  T* exo = fld(p, par ^ 1, 1);
+  T* eyo = fld(p, par ^ 1, 2);
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = xcd_tile(t, p.nst_blocks);
   const int tx = tile % p.tiles_x;
   const int tyb = tile / p.tiles_x;
-  const int i = tx * kWave + lane;
+  const int iw = tx * kWave;
+  const int i = iw + lane;
   const int j0 = (tyb * (kBlock / kWave) + wv) * SEG;
   if (j0 >= p.ny) return;  // uniform over the wave
   const int j1 = min(j0 + SEG, p.ny);
@@ -78,184 +131,233 @@ __global__ void __launch_bounds__(kBlock) yee_step(const StencilParams<T> p) {
   const bool in = i < nx;
   const bool has_left = (lane == 0) && (i >= 1);
   const bool has_right = (lane == kWave - 1) && (i + 1 < nx);
-  const int n = p.ctrl[0];
+  const int js = j0 > 0 ? j0 - 1 : 0;
+  // wave-uniform: does any source touch columns [iw-1, iw+64) x rows [js, j1)?
+  bool any_src = false;
+  for (int s = 0; s < p.nsrc; ++s) {
+    const Src<T>& S = p.src[s];
+    any_src |= S.i0 < iw + kWave && S.i1 > iw - 1 && S.j0 < j1 && S.j1 > js;
+  }
   T sinc[kMaxSrc];
 #pragma unroll
-  for (int s = 0; s < kMaxSrc; ++s) sinc[s] = (s < p.nsrc) ? p.src[s].incr[n] : T(0);
+  for (int s = 0; s < kMaxSrc; ++s) sinc[s] = T(0);
+  if (any_src) {
+#pragma unroll
+    for (int s = 0; s < kMaxSrc; ++s)
+      if (s < p.nsrc) sinc[s] = p.src[s].incr[n];
+  }
 
-  const int js = j0 > 0 ? j0 - 1 : 0;
-  T ex_c = in ? p.ex[(size_t)js * P + i] : T(0);
-  T exl_c = has_left ? p.ex[(size_t)js * P + i - 1] : T(0);
+  T ex_c = in ? ex[(size_t)js * P + i] : T(0);
+  T exl_c = has_left ? ex[(size_t)js * P + i - 1] : T(0);
   T hn_prev = T(0), a_prev = T(0), b_prev = T(0);
+  // software pipeline: row j+1 is requested before row j is computed
+  RowIn<T> nxt = load_row(hz, ex, ey, p, (size_t)js * P + i, in, js + 1 < ny, P);
+  RowIn<T> nxl = load_row(hz, ex, ey, p, (size_t)js * P + i - 1, has_left, js + 1 < ny, P);
+  T ey1_n = has_right ? ey[(size_t)js * P + i + 1] : T(0);
   for (int j = js; j < j1; ++j) {
     const size_t o = (size_t)j * P + i;
-    const bool up = (j + 1) < ny;
-    T h = T(0), ex1 = T(0), ey0 = T(0), al = T(0), be = T(0);
-    if (in) {
-      h = p.hz[o];
-      ex1 = up ? p.ex[o + P] : T(0);
-      ey0 = p.ey[o];
-      al = p.al[o];
-      be = p.be[o];
+    const RowIn<T> cur = nxt;
+    const RowIn<T> cul = nxl;
+    const T ey1_r = ey1_n;
+    if (j + 1 < j1) {
+      const bool up2 = (j + 2) < ny;
+      nxt = load_row(hz, ex, ey, p, o + P, in, up2, P);
+      nxl = load_row(hz, ex, ey, p, o + P - 1, has_left, up2, P);
+      ey1_n = has_right ? ey[o + P + 1] : T(0);
     }
-    T ey1 = __shfl_down(ey0, 1, kWave);
-    if (lane == kWave - 1) ey1 = has_right ? p.ey[o + 1] : T(0);
+    T ey1 = __shfl_down(cur.ey0, 1, kWave);
+    if (lane == kWave - 1) ey1 = ey1_r;
     // eq. (5): Hz^{n+1/2}
-    T hn = h + (p.chdy * (ex1 - ex_c) - p.chdx * (ey1 - ey0));
-    hn += src_sum(p, sinc, 0, i, j);
-    if (!(al > T(0))) hn = T(0);
+    T hn = hz_update(cur.h, ex_c, cur.ex1, cur.ey0, ey1, p.chdy, p.chdx);
+    if (any_src) hn += src_sum(p, sinc, 0, i, j);
+    if (!(cur.al > T(0))) hn = T(0);
     T hnl = __shfl_up(hn, 1, kWave);
-    T all = __shfl_up(al, 1, kWave);
-    T bel = __shfl_up(be, 1, kWave);
+    T all = __shfl_up(cur.al, 1, kWave);
+    T bel = __shfl_up(cur.be, 1, kWave);
     if (lane == 0) {
       hnl = T(0);
-      all = T(0);
-      bel = T(0);
+      all = cul.al;
+      bel = cul.be;
       if (has_left) {
-        const T hl = p.hz[o - 1];
-        const T exl1 = up ? p.ex[o - 1 + P] : T(0);
-        const T eyl0 = p.ey[o - 1];
-        all = p.al[o - 1];
-        bel = p.be[o - 1];
-        hnl = hl + (p.chdy * (exl1 - exl_c) - p.chdx * (ey0 - eyl0));
-        hnl += src_sum(p, sinc, 0, i - 1, j);
+        hnl = hz_update(cul.h, exl_c, cul.ex1, cul.ey0, cur.ey0, p.chdy, p.chdx);
+        if (any_src) hnl += src_sum(p, sinc, 0, i - 1, j);
         if (!(all > T(0))) hnl = T(0);
-        exl_c = exl1;
+        exl_c = cul.ex1;
       }
     }
     if (j >= j0 && in) {
       // eq. (3): Ex^{n+1}(i,j) between cells (i,j-1) and (i,j)
+      const bool ax = cur.al > T(0) && a_prev > T(0);
       T exn = ex_c;
-      if (j >= 1 && al > T(0) && a_prev > T(0)) {
+      if (j >= 1 && ax) {
         T ca, cb;
-        edge_coef(al + a_prev, be + b_prev, p.k2dy, ca, cb);
+        edge_coef(cur.al + a_prev, cur.be + b_prev, p.k2dy, ca, cb);
         exn = ca * ex_c + cb * (hn - hn_prev);
       }
-      exn += src_sum(p, sinc, 1, i, j);
       // Ey^{n+1}(i,j) between cells (i-1,j) and (i,j)
-      T eyn = ey0;
-      if (i >= 1 && al > T(0) && all > T(0)) {
+      const bool ay = cur.al > T(0) && all > T(0);
+      T eyn = cur.ey0;
+      if (i >= 1 && ay) {
         T ca, cb;
-        edge_coef(al + all, be + bel, p.k2dx, ca, cb);
-        eyn = ca * ey0 - cb * (hn - hnl);
+        edge_coef(cur.al + all, cur.be + bel, p.k2dx, ca, cb);
+        eyn = ca * cur.ey0 - cb * (hn - hnl);
       }
-      eyn += src_sum(p, sinc, 2, i, j);
-      p.hzo[o] = hn;
-      p.exo[o] = exn;
-      p.eyo[o] = eyn;
+      if (any_src) {
+        exn += src_sum(p, sinc, 1, i, j);
+        eyn += src_sum(p, sinc, 2, i, j);
+      }
+      hzo[o] = hn;
+      // interface edges (exactly one side inside a region) belong to the
+      // coupling blocks of this launch
+      if (!((cur.al < T(0)) != (a_prev < T(0)))) exo[o] = exn;
+      if (!((cur.al < T(0)) != (all < T(0)))) eyo[o] = eyn;
     }
     hn_prev = hn;
-    a_prev = al;
-    b_prev = be;
-    ex_c = ex1;
-  }
-}
-
-// out = M v for column-major M (rows x cols), v and out in LDS.  Rows are
-// split over threads, columns over `parts` thread groups, partial sums
-// reduced through LDS.  Ends with a barrier.
-template <typename T>
-__device__ void block_matvec(const T* __restrict__ M, int rows, int cols, const T* v, T* out,
-                             T* part) {
-  const int tid = threadIdx.x;
-  for (int r0 = 0; r0 < rows; r0 += kBlock) {
-    const int R = min(rows - r0, kBlock);
-    const int parts = kBlock / R;
-    const int row = tid % R;
-    const int pt = tid / R;
-    T acc = T(0);
-    if (pt < parts) {
-      const int cper = (cols + parts - 1) / parts;
-      const int c0 = pt * cper;
-      const int c1 = min(cols, c0 + cper);
-      const T* col = M + (size_t)c0 * rows + r0 + row;
-      for (int c = c0; c < c1; ++c, col += rows) acc += *col * v[c];
-    }
-    part[tid] = acc;
-    __syncthreads();
-    if (tid < R) {
-      T s = T(0);
-      for (int k = 0; k < parts; ++k) s += part[k * R + tid];
-      out[r0 + tid] = s;
-    }
-    __syncthreads();
+    a_prev = cur.al;
+    b_prev = cur.be;
+    ex_c = cur.ex1;
   }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) coupling(const CouplingParams<T> p) {
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Coarse Hz^{n+1/2} of an active cell from the step-n fields (the value the
+// stencil computes for it).
+template <typename T>
+__device__ T ring_h(const StepParams<T>& p, const T* hz, const T* ex, const T* ey, int off, int n) {
+  const int P = p.pitch;
+  const int j = off / P;
+  const int i = off - j * P;
+  const T ex1 = (j + 1 < p.ny) ? ex[off + P] : T(0);
+  const T ey1 = (i + 1 < p.nx) ? ey[off + 1] : T(0);
+  T h = hz_update(hz[off], ex[off], ex1, ey[off], ey1, p.chdy, p.chdx);
+  T acc = T(0);  // same summation order as the stencil's source term
+  for (int s = 0; s < p.nsrc; ++s) {
+    const Src<T>& S = p.src[s];
+    if (S.comp == 0 && i >= S.i0 && i < S.i1 && j >= S.j0 && j < S.j1) acc += S.incr[n];
+  }
+  return p.nsrc > 0 ? h + acc : h;
+}
+
+// Rows [row0, row0 + kRowsPerBlock) of one model's eq. (23) update matrix.
+template <typename T>
+__device__ void coupling_rows(const StepParams<T>& p, int b, int n) {
   __shared__ T z[kMaxQ + kMaxPorts];
-  __shared__ T xn[kMaxQ];
-  __shared__ T part[kBlock];
+  const int par = n & 1;
   const int tid = threadIdx.x;
-  const int n = p.ctrl[0];
-  const int b = blockIdx.x;
-  if (b < p.nroms) {
-    const RomDev r = p.roms[b];
-    const int q = r.q;
-    const int np = r.np;
-    const int nc = q + np;
-    const T* M = p.mats + r.m_off;
-    const T* C = M + (size_t)q * nc;
-    T* x = p.xs + r.x_off;
-    const int* gi = p.idx + r.i_off;
-    const int* si = gi + np;
-    for (int t = tid; t < nc; t += kBlock) z[t] = (t < q) ? x[t] : p.hz[gi[t - q]];
-    __syncthreads();
-    block_matvec(M, q, nc, z, xn, part);     // x~^{n+1} = A~ x~^n + B~' h
-    for (int t = tid; t < q; t += kBlock) x[t] = xn[t];
-    block_matvec(C, np, q, xn, z, part);     // y^{n+1} = C~ x~^{n+1}
-    for (int t = tid; t < np; t += kBlock) {
-      if (t < r.n_ex)
-        p.ex[si[t]] = z[t];
-      else
-        p.ey[si[t]] = z[t];
-    }
-  } else {
-    for (int t = tid; t < p.nprobes; t += kBlock) {
-      const int c = p.probe_comp[t];
-      const int o = p.probe_off[t];
-      const T v = (c == 0) ? p.hz[o] : ((c == 1) ? p.ex[o] : p.ey[o]);
-      p.probe_buf[(size_t)n * p.nprobes + t] = v;
-    }
-  }
-  // every block has read ctrl[0]; the last one to finish advances the step
+  const RowBlock rb = p.blocks[b];
+  const RomDev r = p.roms[rb.rom];
+  const T* xin = p.xs + r.x_off + par * r.xstride;
+  T* xout = p.xs + r.x_off + (par ^ 1) * r.xstride;
+  const int* gi = p.idx + r.i_off;
+  const int* si = gi + r.np;
+  const T* hz = fld(p, par, 0);
+  const T* ex = fld(p, par, 1);
+  const T* ey = fld(p, par, 2);
+  for (int c = tid; c < r.ldg; c += kBlock)
+    z[c] = c < r.q ? xin[c] : (c < r.q + r.np ? ring_h(p, hz, ex, ey, gi[c - r.q], n) : T(0));
   __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    const int prev = atomicAdd(&p.ctrl[1], 1);
-    if (prev == p.nblocks - 1) {
-      p.ctrl[1] = 0;
-      p.ctrl[0] = n + 1;
-      __threadfence();
+  const int lane = tid & (kWave - 1);
+  const int row0 = rb.row0 + (tid / kWave) * kRowsPerWave;
+  const T* G = p.mats + r.g_off + (size_t)row0 * r.ldg;
+  T acc[kRowsPerWave];
+#pragma unroll
+  for (int k = 0; k < kRowsPerWave; ++k) acc[k] = T(0);
+  for (int c = lane; c < r.ldg; c += kWave) {
+    const T zc = z[c];
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) acc[k] += G[(size_t)k * r.ldg + c] * zc;
+  }
+#pragma unroll
+  for (int k = 0; k < kRowsPerWave; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0) {
+    T* exo = fld(p, par ^ 1, 1);
+    T* eyo = fld(p, par ^ 1, 2);
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) {
+      const int row = row0 + k;
+      if (row < r.q) {
+        xout[row] = acc[k];
+      } else if (row < r.q + r.np) {
+        const int pp = row - r.q;
+        if (pp < r.n_ex)
+          exo[si[pp]] = acc[k];
+        else
+          eyo[si[pp]] = acc[k];
+      }
     }
   }
 }
 
+// Probe row m (m >= 0) from the set holding the state after m+1 steps.
 template <typename T>
-hipError_t launch_stencil(const StencilParams<T>& p, int seg, hipStream_t s) {
-  const int rows = (kBlock / kWave) * seg;
-  const int nblk = p.tiles_x * ((p.ny + rows - 1) / rows);
-  const dim3 g(nblk), b(kBlock);
+__device__ void record_probes(const StepParams<T>& p, int m) {
+  if (m < 0) return;
+  const int par = (m + 1) & 1;
+  for (int t = threadIdx.x; t < p.nprobes; t += kBlock) {
+    const int c = p.probe_comp[t];
+    const int o = p.probe_off[t];
+    p.probe_buf[(size_t)m * p.nprobes + t] = fld(p, par, c)[o];
+  }
+}
+
+template <typename T, int SEG>
+__global__ void __launch_bounds__(kBlock) step_kernel(const StepParams<T> p) {
+  const int n = p.ctrl[0] + p.step_off;
+  const int b = blockIdx.x;
+  if (b < p.ncoup_blocks) {
+    if (b < p.nrowblocks) coupling_rows(p, b, n);
+    return;
+  }
+  const int t = b - p.ncoup_blocks;
+  if (t < p.nst_blocks) {
+    stencil_tile<T, SEG>(p, t, n);
+    return;
+  }
+  record_probes(p, n - 1);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) probe_kernel(const StepParams<T> p) {
+  record_probes(p, p.ctrl[0] + p.step_off - 1);
+}
+
+__global__ void tick_kernel(int* ctrl, int k) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctrl[0] += k;
+}
+
+template <typename T>
+hipError_t launch_step(const StepParams<T>& p, int seg, hipStream_t s) {
+  const dim3 g(p.ncoup_blocks + p.nst_blocks + 1), b(kBlock);
   switch (seg) {
-    case 8: hipLaunchKernelGGL((yee_step<T, 8>), g, b, 0, s, p); break;
-    case 16: hipLaunchKernelGGL((yee_step<T, 16>), g, b, 0, s, p); break;
-    case 32: hipLaunchKernelGGL((yee_step<T, 32>), g, b, 0, s, p); break;
-    case 64: hipLaunchKernelGGL((yee_step<T, 64>), g, b, 0, s, p); break;
+    case 8: hipLaunchKernelGGL((step_kernel<T, 8>), g, b, 0, s, p); break;
+    case 16: hipLaunchKernelGGL((step_kernel<T, 16>), g, b, 0, s, p); break;
+    case 32: hipLaunchKernelGGL((step_kernel<T, 32>), g, b, 0, s, p); break;
+    case 64: hipLaunchKernelGGL((step_kernel<T, 64>), g, b, 0, s, p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_coupling(const CouplingParams<T>& p, hipStream_t s) {
-  hipLaunchKernelGGL((coupling<T>), dim3(p.nblocks), dim3(kBlock), 0, s, p);
+hipError_t launch_probe_flush(const StepParams<T>& p, hipStream_t s) {
+  hipLaunchKernelGGL((probe_kernel<T>), dim3(1), dim3(kBlock), 0, s, p);
   return hipGetLastError();
 }
 
-template hipError_t launch_stencil<float>(const StencilParams<float>&, int, hipStream_t);
-template hipError_t launch_stencil<double>(const StencilParams<double>&, int, hipStream_t);
-template hipError_t launch_coupling<float>(const CouplingParams<float>&, hipStream_t);
-template hipError_t launch_coupling<double>(const CouplingParams<double>&, hipStream_t);
+hipError_t launch_tick(int* ctrl, int k, hipStream_t s) {
+  hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, s, ctrl, k);
+  return hipGetLastError();
+}
+
+template hipError_t launch_step<float>(const StepParams<float>&, int, hipStream_t);
+template hipError_t launch_step<double>(const StepParams<double>&, int, hipStream_t);
+template hipError_t launch_probe_flush<float>(const StepParams<float>&, hipStream_t);
+template hipError_t launch_probe_flush<double>(const StepParams<double>&, hipStream_t);
 
 }  // namespace fdtd

@@ -1,0 +1,530 @@
+// Host FP64 reduced-model builder (paper Secs. II-III and V-E):
+//   fine-region descriptor system on coarse ports -> block Krylov
+//   directions -> SPRIM split V = blkdiag(V1, V2) (eq. (9)) -> congruence
+//   R~, F~, L~ (eqs. (11)-(12)) -> singular-value clip of eq. (27).
+//
+// Fine model (eqs. (3)-(8)), restricted to coarse ports (the r fine boundary
+// E samples on one coarse interface edge are one unknown, eq. (15)):
+//   R = [[De/dt, -K/2], [-K^T/2, Dm/dt]],  F = [[Ds/2, -K/2], [K^T/2, 0]],
+//   B = Lc Sc,  Sc = diag(-dx, +dx, +dy, -dy) per port side (S, N, W, E).
+// Solves with (p0 R + F) = [[D1, -a K], [b K^T, c I]] (D1 = p0 De/dt + Ds/2,
+// a = (1+p0)/2, b = (1-p0)/2, c = p0 Dm/dt) go through the H-block Schur
+// complement S = c I + a b K^T D1^{-1} K, which is symmetric positive
+// definite for 0 < p0 < 1; S is banded in the natural cell order and is
+// factored once by a banded Cholesky.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fdtd_rom.h"
+#include "common.hpp"
+#include "linalg.hpp"
+
+namespace {
+
+const double kC0 = FDTD_C0;
+const double kMu0 = FDTD_MU0;
+const double kEps0 = 1.0 / (kMu0 * kC0 * kC0);
+
+struct Csr {
+  int rows = 0, cols = 0;
+  std::vector<int> ptr, col;
+  std::vector<double> val;
+};
+
+Csr transpose(const Csr& A) {
+  Csr T;
+  T.rows = A.cols;
+  T.cols = A.rows;
+  T.ptr.assign(T.rows + 1, 0);
+  for (int c : A.col) T.ptr[c + 1]++;
+  for (int r = 0; r < T.rows; ++r) T.ptr[r + 1] += T.ptr[r];
+  T.col.resize(A.col.size());
+  T.val.resize(A.val.size());
+  std::vector<int> fill(T.ptr.begin(), T.ptr.end() - 1);
+  for (int r = 0; r < A.rows; ++r)
+    for (int k = A.ptr[r]; k < A.ptr[r + 1]; ++k) {
+      const int d = fill[A.col[k]]++;
+      T.col[d] = r;
+      T.val[d] = A.val[k];
+    }
+  return T;
+}
+
+// out (A.rows) = A x (A.cols), one column
+void spmv(const Csr& A, const double* x, double* out) {
+  for (int r = 0; r < A.rows; ++r) {
+    double s = 0;
+    for (int k = A.ptr[r]; k < A.ptr[r + 1]; ++k) s += A.val[k] * x[A.col[k]];
+    out[r] = s;
+  }
+}
+
+struct FineModel {
+  int Nx, Ny, ni, nj, r, np;
+  int nEx, nEy, nE, nH, n;
+  double dx, dy, dxh, dyh, dt;
+  std::vector<double> De, Ds, Sc;  // E diagonals, port scale
+  double Dm;
+  Csr K, KT;                       // E x H and its transpose
+  std::vector<int> port_row;       // E index of each port
+};
+
+// Restricted fine model.  E order: interior Ex (j = 1..Ny-1, i), interior Ey
+// (j, i = 1..Nx-1), ports S, N, W, E; H order: j * Nx + i.
+void assemble(FineModel& m, int ni, int nj, int r, double dx, double dy, double dt, const double* er,
+              const double* sg) {
+  m.ni = ni;
+  m.nj = nj;
+  m.r = r;
+  m.Nx = r * ni;
+  m.Ny = r * nj;
+  m.dx = dx;
+  m.dy = dy;
+  m.dt = dt;
+  m.dxh = dx / r;
+  m.dyh = dy / r;
+  const int Nx = m.Nx, Ny = m.Ny;
+  m.np = 2 * (ni + nj);
+  m.nEx = Nx * (Ny - 1);
+  m.nEy = (Nx - 1) * Ny;
+  m.nE = m.nEx + m.nEy + m.np;
+  m.nH = Nx * Ny;
+  m.n = m.nE + m.nH;
+  m.De.assign(m.nE, 0.0);
+  m.Ds.assign(m.nE, 0.0);
+  m.Dm = kMu0 * m.dxh * m.dyh;
+  const double A = m.dxh * m.dyh;
+  auto E = [&](int i, int j) { return er[(size_t)j * Nx + i]; };
+  auto S = [&](int i, int j) { return sg[(size_t)j * Nx + i]; };
+  std::vector<std::vector<std::pair<int, double>>> rows(m.nE);
+  for (int j = 1; j < Ny; ++j)
+    for (int i = 0; i < Nx; ++i) {
+      const int e = (j - 1) * Nx + i;
+      m.De[e] = A * kEps0 * 0.5 * (E(i, j - 1) + E(i, j));
+      m.Ds[e] = A * 0.5 * (S(i, j - 1) + S(i, j));
+      rows[e] = {{j * Nx + i, +m.dxh}, {(j - 1) * Nx + i, -m.dxh}};
+    }
+  for (int j = 0; j < Ny; ++j)
+    for (int i = 1; i < Nx; ++i) {
+      const int e = m.nEx + j * (Nx - 1) + (i - 1);
+      m.De[e] = A * kEps0 * 0.5 * (E(i - 1, j) + E(i, j));
+      m.Ds[e] = A * 0.5 * (S(i - 1, j) + S(i, j));
+      rows[e] = {{j * Nx + i, -m.dyh}, {j * Nx + i - 1, +m.dyh}};
+    }
+  const int pb = m.nEx + m.nEy;
+  m.Sc.assign(m.np, 0.0);
+  m.port_row.assign(m.np, 0);
+  for (int c = 0; c < ni; ++c) {
+    const int eS = pb + c, eN = pb + ni + c;
+    m.Sc[c] = -dx;
+    m.Sc[ni + c] = +dx;
+    for (int i = c * r; i < (c + 1) * r; ++i) {
+      // boundary half cells of eq. (4), summed over the r fine edges
+      m.De[eS] += m.dxh * (m.dyh / 2) * kEps0 * E(i, 0);
+      m.Ds[eS] += m.dxh * (m.dyh / 2) * S(i, 0);
+      rows[eS].push_back({i, +m.dxh});
+      m.De[eN] += m.dxh * (m.dyh / 2) * kEps0 * E(i, Ny - 1);
+      m.Ds[eN] += m.dxh * (m.dyh / 2) * S(i, Ny - 1);
+      rows[eN].push_back({(Ny - 1) * Nx + i, -m.dxh});
+    }
+  }
+  for (int c = 0; c < nj; ++c) {
+    const int eW = pb + 2 * ni + c, eE = pb + 2 * ni + nj + c;
+    m.Sc[2 * ni + c] = +dy;
+    m.Sc[2 * ni + nj + c] = -dy;
+    for (int j = c * r; j < (c + 1) * r; ++j) {
+      m.De[eW] += m.dyh * (m.dxh / 2) * kEps0 * E(0, j);
+      m.Ds[eW] += m.dyh * (m.dxh / 2) * S(0, j);
+      rows[eW].push_back({j * Nx, -m.dyh});
+      m.De[eE] += m.dyh * (m.dxh / 2) * kEps0 * E(Nx - 1, j);
+      m.Ds[eE] += m.dyh * (m.dxh / 2) * S(Nx - 1, j);
+      rows[eE].push_back({j * Nx + Nx - 1, +m.dyh});
+    }
+  }
+  for (int p = 0; p < m.np; ++p) m.port_row[p] = pb + p;
+  m.K.rows = m.nE;
+  m.K.cols = m.nH;
+  m.K.ptr.assign(m.nE + 1, 0);
+  for (int e = 0; e < m.nE; ++e) {
+    for (auto& pr : rows[e]) {
+      m.K.col.push_back(pr.first);
+      m.K.val.push_back(pr.second);
+    }
+    m.K.ptr[e + 1] = (int)m.K.col.size();
+  }
+  m.KT = transpose(m.K);
+}
+
+// Banded Cholesky of an SPD matrix with half-bandwidth bw; L(i, i-d) at
+// L[i*(bw+1) + d].
+struct Banded {
+  int n = 0, bw = 0;
+  std::vector<double> L;
+  double& at(int i, int d) { return L[(size_t)i * (bw + 1) + d]; }
+  double get(int i, int j) const { return L[(size_t)i * (bw + 1) + (i - j)]; }
+};
+
+bool band_cholesky(Banded& B) {
+  const int n = B.n, bw = B.bw, w = bw + 1;
+  double* L = B.L.data();
+  for (int i = 0; i < n; ++i) {
+    const int j0 = std::max(0, i - bw);
+    for (int j = j0; j <= i; ++j) {
+      double s = L[(size_t)i * w + (i - j)];
+      const int k0 = std::max(j0, j - bw);
+      const double* li = L + (size_t)i * w;
+      const double* lj = L + (size_t)j * w;
+      for (int k = k0; k < j; ++k) s -= li[i - k] * lj[j - k];
+      if (i == j) {
+        if (!(s > 0.0)) return false;
+        L[(size_t)i * w] = std::sqrt(s);
+      } else {
+        L[(size_t)i * w + (i - j)] = s / lj[0];
+      }
+    }
+  }
+  return true;
+}
+
+void band_solve(const Banded& B, double* x) {
+  const int n = B.n, bw = B.bw, w = bw + 1;
+  const double* L = B.L.data();
+  for (int i = 0; i < n; ++i) {
+    double s = x[i];
+    const double* li = L + (size_t)i * w;
+    const int k0 = std::max(0, i - bw);
+    for (int k = k0; k < i; ++k) s -= li[i - k] * x[k];
+    x[i] = s / li[0];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = x[i];
+    const int k1 = std::min(n - 1, i + bw);
+    for (int k = i + 1; k <= k1; ++k) s -= L[(size_t)k * w + (k - i)] * x[k];
+    x[i] = s / L[(size_t)i * w];
+  }
+}
+
+struct Solver {
+  const FineModel* m;
+  double p0, a, b, c;
+  std::vector<double> D1;
+  Banded S;
+  std::vector<double> t, u, v;
+
+  bool init(const FineModel& fm, double p0_) {
+    m = &fm;
+    p0 = p0_;
+    a = 0.5 * (1.0 + p0);
+    b = 0.5 * (1.0 - p0);
+    c = p0 * fm.Dm / fm.dt;
+    D1.resize(fm.nE);
+    for (int e = 0; e < fm.nE; ++e) D1[e] = p0 * fm.De[e] / fm.dt + 0.5 * fm.Ds[e];
+    // bandwidth of K^T D1^{-1} K
+    int bw = 0;
+    for (int e = 0; e < fm.nE; ++e)
+      for (int k = fm.K.ptr[e]; k < fm.K.ptr[e + 1]; ++k)
+        for (int l = fm.K.ptr[e]; l < fm.K.ptr[e + 1]; ++l)
+          bw = std::max(bw, std::abs(fm.K.col[k] - fm.K.col[l]));
+    S.n = fm.nH;
+    S.bw = bw;
+    S.L.assign((size_t)fm.nH * (bw + 1), 0.0);
+    for (int h = 0; h < fm.nH; ++h) S.at(h, 0) = c;
+    for (int e = 0; e < fm.nE; ++e) {
+      const double wgt = a * b / D1[e];
+      for (int k = fm.K.ptr[e]; k < fm.K.ptr[e + 1]; ++k)
+        for (int l = fm.K.ptr[e]; l < fm.K.ptr[e + 1]; ++l) {
+          const int i = fm.K.col[k], j = fm.K.col[l];
+          if (j > i) continue;
+          S.at(i, i - j) += wgt * fm.K.val[k] * fm.K.val[l];
+        }
+    }
+    t.resize(fm.nE);
+    u.resize(fm.nH);
+    v.resize(fm.nE);
+    return band_cholesky(S);
+  }
+
+  // x = (p0 R + F)^{-1} rhs, one column of length n (E part then H part)
+  void solve(const double* rhs, double* x) {
+    const FineModel& fm = *m;
+    for (int e = 0; e < fm.nE; ++e) t[e] = rhs[e] / D1[e];
+    spmv(fm.KT, t.data(), u.data());
+    double* xh = x + fm.nE;
+    for (int h = 0; h < fm.nH; ++h) xh[h] = rhs[fm.nE + h] - b * u[h];
+    band_solve(S, xh);
+    spmv(fm.K, xh, v.data());
+    for (int e = 0; e < fm.nE; ++e) x[e] = t[e] + a * v[e] / D1[e];
+  }
+
+  // y = R x, one column
+  void apply_R(const double* x, double* y) {
+    const FineModel& fm = *m;
+    spmv(fm.K, x + fm.nE, v.data());
+    spmv(fm.KT, x, u.data());
+    for (int e = 0; e < fm.nE; ++e) y[e] = fm.De[e] / fm.dt * x[e] - 0.5 * v[e];
+    for (int h = 0; h < fm.nH; ++h) y[fm.nE + h] = -0.5 * u[h] + fm.Dm / fm.dt * x[fm.nE + h];
+  }
+};
+
+using Cols = std::vector<std::vector<double>>;  // column vectors
+
+double dot_w(const std::vector<double>& x, const std::vector<double>& y, const std::vector<double>& w) {
+  double s = 0;
+  for (size_t k = 0; k < x.size(); ++k) s += x[k] * w[k] * y[k];
+  return s;
+}
+
+// Krylov directions, ordered as described in rom builder docs.
+bool krylov_dirs(Solver& sol, const FineModel& fm, int ncols, Cols& dirs, std::string& err) {
+  const int n = fm.n;
+  std::vector<double> mass(n);
+  for (int e = 0; e < fm.nE; ++e) mass[e] = fm.De[e] / fm.dt;
+  for (int h = 0; h < fm.nH; ++h) mass[fm.nE + h] = fm.Dm / fm.dt;
+  // X0 = (p0 R + F)^{-1} B, B = Lc Sc
+  Cols X(fm.np, std::vector<double>(n, 0.0));
+  std::vector<double> rhs(n);
+  for (int p = 0; p < fm.np; ++p) {
+    std::fill(rhs.begin(), rhs.end(), 0.0);
+    rhs[fm.port_row[p]] = fm.Sc[p];
+    sol.solve(rhs.data(), X[p].data());
+  }
+  double ref = -1;
+  const double tol = 1e-12;
+  std::vector<double> Mv(n);
+  while ((int)dirs.size() < ncols) {
+    const int m = (int)X.size();
+    // two passes of mass-orthogonalisation against earlier directions
+    for (int pass = 0; pass < 2; ++pass)
+      for (auto& y : X) {
+        for (int k = 0; k < n; ++k) Mv[k] = mass[k] * y[k];
+        for (auto& d : dirs) {
+          double cf = 0;
+          for (int k = 0; k < n; ++k) cf += d[k] * Mv[k];
+          for (int k = 0; k < n; ++k) y[k] -= cf * d[k];
+        }
+      }
+    std::vector<double> G((size_t)m * m), Q((size_t)m * m), w(m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j <= i; ++j) G[(size_t)i * m + j] = G[(size_t)j * m + i] = dot_w(X[i], X[j], mass);
+    fdtd::la::sym_eig(m, G.data(), Q.data(), w.data());
+    std::vector<int> order(m);
+    for (int i = 0; i < m; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return w[x] > w[y]; });
+    if (ref < 0) ref = w[order[0]];
+    Cols W;
+    for (int oi : order) {
+      if (!(w[oi] > tol * tol * ref)) break;
+      std::vector<double> v(n, 0.0);
+      for (int j = 0; j < m; ++j) {
+        const double z = Q[(size_t)j * m + oi];
+        if (z == 0.0) continue;
+        for (int k = 0; k < n; ++k) v[k] += z * X[j][k];
+      }
+      const double s = 1.0 / std::sqrt(w[oi]);
+      for (int k = 0; k < n; ++k) v[k] *= s;
+      W.push_back(std::move(v));
+    }
+    if (W.empty()) break;
+    if (dirs.size() + W.size() >= (size_t)ncols) {
+      for (auto& v : W) dirs.push_back(std::move(v));
+      break;
+    }
+    Cols Xn(W.size(), std::vector<double>(n));
+    std::vector<double> Rw(n);
+    for (size_t c = 0; c < W.size(); ++c) {
+      sol.apply_R(W[c].data(), Rw.data());
+      sol.solve(Rw.data(), Xn[c].data());
+    }
+    for (auto& v : W) dirs.push_back(std::move(v));
+    X.swap(Xn);
+  }
+  (void)err;
+  return true;
+}
+
+// Gram-Schmidt in order over rows [r0, r0+len) of the directions.
+Cols gs_part(const Cols& dirs, int r0, int len, int q) {
+  Cols out;
+  for (const auto& d : dirs) {
+    if ((int)out.size() >= q) break;
+    std::vector<double> v(d.begin() + r0, d.begin() + r0 + len);
+    double nv = 0;
+    for (double x : v) nv += x * x;
+    nv = std::sqrt(nv);
+    if (nv == 0.0) continue;
+    for (int pass = 0; pass < 2; ++pass)
+      for (const auto& u : out) {
+        double cf = 0;
+        for (int k = 0; k < len; ++k) cf += u[k] * v[k];
+        for (int k = 0; k < len; ++k) v[k] -= cf * u[k];
+      }
+    double nr = 0;
+    for (double x : v) nr += x * x;
+    nr = std::sqrt(nr);
+    if (nr <= 1e-10 * nv) continue;
+    for (double& x : v) x /= nr;
+    out.push_back(std::move(v));
+  }
+  return out;
+}
+
+// symmetric matrix function A^p via Jacobi, row-major n x n
+void sym_pow(int n, const double* A, double p, double* out) {
+  std::vector<double> W(A, A + (size_t)n * n), Q((size_t)n * n), w(n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) W[(size_t)i * n + j] = W[(size_t)j * n + i] = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+  fdtd::la::sym_eig(n, W.data(), Q.data(), w.data());
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0;
+      for (int k = 0; k < n; ++k) s += Q[(size_t)i * n + k] * std::pow(w[k], p) * Q[(size_t)j * n + k];
+      out[(size_t)i * n + j] = s;
+    }
+}
+
+}  // namespace
+
+using fdtd::fail;
+
+extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, double* Ft, double* Lt,
+                              fdtd_rom_build_info* info) {
+  if (!prm || !Rt || !Ft || !Lt) return fail(FDTD_EINVAL, "null argument");
+  const fdtd_rom_build_params& P = *prm;
+  if (P.ni < 1 || P.nj < 1 || P.r < 1) return fail(FDTD_EINVAL, "bad region size");
+  if (!(P.dx > 0) || !(P.dy > 0) || !(P.dt > 0)) return fail(FDTD_EINVAL, "dx, dy, dt must be positive");
+  if (!P.eps_r || !P.sigma) return fail(FDTD_EINVAL, "fine material maps required");
+  if (P.q < 2) return fail(FDTD_EINVAL, "order q must be >= 2");
+  const double p0 = 3.14159265358979323846 * P.f_max * P.dt;
+  if (!(p0 > 0.0 && p0 < 1.0)) return fail(FDTD_EINVAL, "expansion point p0 = pi f_max dt = %g outside (0, 1)", p0);
+  const double theta = P.theta > 0 ? P.theta : 0.99;
+  const size_t nf = (size_t)P.r * P.ni * P.r * P.nj;
+  for (size_t k = 0; k < nf; ++k)
+    if (!(P.eps_r[k] > 0) || !(P.sigma[k] >= 0)) return fail(FDTD_EINVAL, "fine material must have eps_r > 0, sigma >= 0");
+  try {
+    FineModel fm;
+    assemble(fm, P.ni, P.nj, P.r, P.dx, P.dy, P.dt, P.eps_r, P.sigma);
+    const int q1 = (P.q + 1) / 2, q2 = P.q / 2;
+    if (q1 > fm.nE || q2 > fm.nH) return fail(FDTD_EINVAL, "order q=%d exceeds the fine model", P.q);
+    Solver sol;
+    if (!sol.init(fm, p0)) return fail(FDTD_EINVAL, "Schur complement not positive definite");
+    Cols dirs;
+    std::string err;
+    const int need = std::max(q1, q2);
+    krylov_dirs(sol, fm, need + 8, dirs, err);
+    Cols V1 = gs_part(dirs, 0, fm.nE, q1);
+    Cols V2 = gs_part(dirs, fm.nE, fm.nH, q2);
+    if ((int)V1.size() < q1 || (int)V2.size() < q2)
+      return fail(FDTD_EINVAL, "Krylov space too small for q=%d (got %zu E, %zu H)", P.q, V1.size(), V2.size());
+    const int q = q1 + q2, np = fm.np;
+    // congruence (eqs. (11)-(12))
+    std::vector<double> R((size_t)q * q, 0.0), F((size_t)q * q, 0.0);
+    for (int a = 0; a < q1; ++a)
+      for (int b2 = 0; b2 <= a; ++b2) {
+        double sr = 0, sf = 0;
+        for (int e = 0; e < fm.nE; ++e) {
+          const double pr = V1[a][e] * V1[b2][e];
+          sr += pr * fm.De[e];
+          sf += pr * fm.Ds[e];
+        }
+        R[(size_t)a * q + b2] = R[(size_t)b2 * q + a] = sr / P.dt;
+        F[(size_t)a * q + b2] = F[(size_t)b2 * q + a] = 0.5 * sf;
+      }
+    std::vector<double> KV(fm.nE);
+    std::vector<double> Kt((size_t)q1 * q2);  // K~ = V1^T K V2
+    for (int c = 0; c < q2; ++c) {
+      spmv(fm.K, V2[c].data(), KV.data());
+      for (int a = 0; a < q1; ++a) {
+        double s = 0;
+        for (int e = 0; e < fm.nE; ++e) s += V1[a][e] * KV[e];
+        Kt[(size_t)a * q2 + c] = s;
+      }
+    }
+    for (int a = 0; a < q2; ++a)
+      for (int b2 = 0; b2 <= a; ++b2) {
+        double s = 0;
+        for (int h = 0; h < fm.nH; ++h) s += V2[a][h] * V2[b2][h];
+        R[(size_t)(q1 + a) * q + q1 + b2] = R[(size_t)(q1 + b2) * q + q1 + a] = fm.Dm / P.dt * s;
+      }
+    // eq. (27): s_k of R11^{-1/2} K~ R22^{-1/2} against 2/dt
+    std::vector<double> R11((size_t)q1 * q1), R22((size_t)q2 * q2);
+    for (int a = 0; a < q1; ++a)
+      for (int b2 = 0; b2 < q1; ++b2) R11[(size_t)a * q1 + b2] = P.dt * R[(size_t)a * q + b2];
+    for (int a = 0; a < q2; ++a)
+      for (int b2 = 0; b2 < q2; ++b2) R22[(size_t)a * q2 + b2] = P.dt * R[(size_t)(q1 + a) * q + q1 + b2];
+    std::vector<double> R11m((size_t)q1 * q1), R22m((size_t)q2 * q2), R11p((size_t)q1 * q1), R22p((size_t)q2 * q2);
+    sym_pow(q1, R11.data(), -0.5, R11m.data());
+    sym_pow(q2, R22.data(), -0.5, R22m.data());
+    std::vector<double> tmp((size_t)q1 * q2), M((size_t)q1 * q2);
+    fdtd::la::gemm(q1, q2, q1, R11m.data(), Kt.data(), tmp.data());
+    fdtd::la::gemm(q1, q2, q2, tmp.data(), R22m.data(), M.data());
+    std::vector<double> MtM((size_t)q2 * q2, 0.0), Wv((size_t)q2 * q2), s2(q2);
+    for (int i = 0; i < q2; ++i)
+      for (int j = 0; j < q2; ++j) {
+        double s = 0;
+        for (int k = 0; k < q1; ++k) s += M[(size_t)k * q2 + i] * M[(size_t)k * q2 + j];
+        MtM[(size_t)i * q2 + j] = s;
+      }
+    fdtd::la::sym_eig(q2, MtM.data(), Wv.data(), s2.data());
+    double smax = 0;
+    for (int k = 0; k < q2; ++k) smax = std::max(smax, std::sqrt(std::max(0.0, s2[k])));
+    const double lim = theta * 2.0 / P.dt;
+    double smax_after = smax;
+    int clipped = 0;
+    if (P.clip && smax > lim) {
+      clipped = 1;
+      smax_after = 0;
+      for (int k = 0; k < q2; ++k) {
+        const double sk = std::sqrt(std::max(0.0, s2[k]));
+        if (sk <= lim) {
+          smax_after = std::max(smax_after, sk);
+          continue;
+        }
+        smax_after = std::max(smax_after, lim);
+        // M -= (s_k - lim) u_k w_k^T with u_k = M w_k / s_k
+        std::vector<double> wk(q2), uk(q1);
+        for (int i = 0; i < q2; ++i) wk[i] = Wv[(size_t)i * q2 + k];
+        for (int a = 0; a < q1; ++a) {
+          double s = 0;
+          for (int i = 0; i < q2; ++i) s += M[(size_t)a * q2 + i] * wk[i];
+          uk[a] = s / sk;
+        }
+        for (int a = 0; a < q1; ++a)
+          for (int i = 0; i < q2; ++i) M[(size_t)a * q2 + i] -= (sk - lim) * uk[a] * wk[i];
+      }
+      sym_pow(q1, R11.data(), 0.5, R11p.data());
+      sym_pow(q2, R22.data(), 0.5, R22p.data());
+      fdtd::la::gemm(q1, q2, q1, R11p.data(), M.data(), tmp.data());
+      fdtd::la::gemm(q1, q2, q2, tmp.data(), R22p.data(), Kt.data());
+    }
+    for (int a = 0; a < q1; ++a)
+      for (int c = 0; c < q2; ++c) {
+        const double k = Kt[(size_t)a * q2 + c];
+        R[(size_t)a * q + q1 + c] = -0.5 * k;
+        R[(size_t)(q1 + c) * q + a] = -0.5 * k;
+        F[(size_t)a * q + q1 + c] = -0.5 * k;
+        F[(size_t)(q1 + c) * q + a] = +0.5 * k;
+      }
+    std::memcpy(Rt, R.data(), R.size() * sizeof(double));
+    std::memcpy(Ft, F.data(), F.size() * sizeof(double));
+    for (int a = 0; a < q; ++a)
+      for (int p = 0; p < np; ++p) Lt[(size_t)a * np + p] = a < q1 ? V1[a][fm.port_row[p]] : 0.0;
+    if (info) {
+      info->q1 = q1;
+      info->q2 = q2;
+      info->p0 = p0;
+      info->smax_before = smax;
+      info->smax_after = smax_after;
+      info->clipped = clipped;
+      info->n_fine_states = fm.n;
+    }
+    return FDTD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(FDTD_ENOMEM, "host allocation failed");
+  }
+}

@@ -24,10 +24,10 @@
 using namespace fdtd;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-int fail(int code, const char* fmt, ...) {
+int fdtd::fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -36,6 +36,8 @@ int fail(int code, const char* fmt, ...) {
   g_err = buf;
   return code;
 }
+
+namespace {
 
 const double kC0 = FDTD_C0;
 const double kMu0 = FDTD_MU0;
@@ -51,6 +53,8 @@ struct Layout {
   size_t off_pbuf = 0, off_poff = 0, off_pcomp = 0, off_roms = 0, off_mats = 0;
   size_t off_xs = 0, off_idx = 0, total = 0;
   size_t mats_elems = 0, xs_elems = 0, idx_elems = 0;
+  int nrowblocks = 0;
+  size_t off_blocks = 0;
   std::vector<int> slot_of_rom;     // matrix slot per region
   std::vector<int> slot_rep;        // representative region per slot
   std::vector<size_t> slot_off;     // element offset of each slot in the pool
@@ -107,18 +111,20 @@ int plan(const fdtd_problem* p, Layout& L) {
     const fdtd_rom& r = p->roms[rep];
     const int np = ports_of(r);
     L.slot_off.push_back(me);
-    me += (size_t)r.q * (r.q + np) + (size_t)np * r.q;
+    me += align_up((size_t)r.q + np, kRowsPerBlock) * align_up((size_t)r.q + np, kWave);
     me = align_up(me, 64);
   }
   L.mats_elems = me;
   L.x_off.clear();
   L.i_off.clear();
   size_t xe = 0, ie = 0;
+  L.nrowblocks = 0;
   for (int k = 0; k < p->nroms; ++k) {
     L.x_off.push_back(xe);
     L.i_off.push_back(ie);
-    xe = align_up(xe + p->roms[k].q, 64);
+    xe = align_up(xe + 2 * align_up((size_t)p->roms[k].q, 64), 64);
     ie = align_up(ie + 2 * (size_t)ports_of(p->roms[k]), 64);
+    L.nrowblocks += (int)(align_up((size_t)p->roms[k].q + ports_of(p->roms[k]), kRowsPerBlock) / kRowsPerBlock);
   }
   L.xs_elems = xe;
   L.idx_elems = ie;
@@ -142,6 +148,8 @@ int plan(const fdtd_problem* p, Layout& L) {
   o = align_up(o + (size_t)p->nprobes * sizeof(int), 256);
   L.off_roms = o;
   o = align_up(o + (size_t)p->nroms * sizeof(RomDev), 256);
+  L.off_blocks = o;
+  o = align_up(o + (size_t)L.nrowblocks * sizeof(RowBlock), 256);
   L.off_mats = o;
   o = align_up(o + L.mats_elems * ts, 256);
   L.off_xs = o;
@@ -167,13 +175,10 @@ struct fdtd_rom_sim {
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   Layout L;
-  int cur = 0;
   int seg = 16;
   std::vector<RomHost> roms;
-  StencilParams<float> sp_f[2];
-  StencilParams<double> sp_d[2];
-  CouplingParams<float> cp_f[2];
-  CouplingParams<double> cp_d[2];
+  StepParams<float> sp_f;
+  StepParams<double> sp_d;
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_st, ev_cp;
   size_t used_st = 0, used_cp = 0;
@@ -260,26 +265,38 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
   std::vector<T> mats(L.mats_elems, T(0));
   std::vector<T> xs(L.xs_elems, T(0));
   std::vector<int> idx(L.idx_elems, 0);
+  // G = [[A~, B~'], [C~ A~, C~ B~']] (eq. (23) on [x~^n; h]), row-major,
+  // rows padded to kRowsPerBlock, row length padded to a multiple of 64
   for (size_t sl = 0; sl < L.slot_rep.size(); ++sl) {
     const RomHost& h = s->roms[L.slot_rep[sl]];
-    const int q = h.q, np = h.np;
-    T* m = mats.data() + L.slot_off[sl];
-    for (int c = 0; c < q + np; ++c)
-      for (int a = 0; a < q; ++a)
-        m[(size_t)c * q + a] = (T)(c < q ? h.A[(size_t)a * q + c] : h.B[(size_t)a * np + (c - q)]);
-    T* cm = m + (size_t)q * (q + np);
-    for (int a = 0; a < q; ++a)
-      for (int c = 0; c < np; ++c) cm[(size_t)a * np + c] = (T)h.C[(size_t)c * q + a];
+    const int q = h.q, np = h.np, nc = q + np;
+    const size_t ldg = align_up((size_t)nc, kWave);
+    T* g = mats.data() + L.slot_off[sl];
+    std::vector<double> CA((size_t)np * q), CB((size_t)np * np);
+    la::gemm(np, q, q, h.C.data(), h.A.data(), CA.data());
+    la::gemm(np, np, q, h.C.data(), h.B.data(), CB.data());
+    for (int a = 0; a < q; ++a) {
+      for (int c = 0; c < q; ++c) g[(size_t)a * ldg + c] = (T)h.A[(size_t)a * q + c];
+      for (int c = 0; c < np; ++c) g[(size_t)a * ldg + q + c] = (T)h.B[(size_t)a * np + c];
+    }
+    for (int k = 0; k < np; ++k) {
+      for (int c = 0; c < q; ++c) g[(size_t)(q + k) * ldg + c] = (T)CA[(size_t)k * q + c];
+      for (int c = 0; c < np; ++c) g[(size_t)(q + k) * ldg + q + c] = (T)CB[(size_t)k * np + c];
+    }
   }
+  std::vector<RowBlock> blocks;
   for (int k = 0; k < p->nroms; ++k) {
     const fdtd_rom& r = p->roms[k];
     const int np = ports_of(r);
     rd[k].q = r.q;
     rd[k].np = np;
     rd[k].n_ex = 2 * r.ni;
-    rd[k].m_off = (int64_t)L.slot_off[L.slot_of_rom[k]];
+    rd[k].ldg = (int)align_up((size_t)r.q + np, kWave);
+    rd[k].g_off = (int64_t)L.slot_off[L.slot_of_rom[k]];
     rd[k].x_off = (int64_t)L.x_off[k];
+    rd[k].xstride = (int64_t)align_up((size_t)r.q, 64);
     rd[k].i_off = (int64_t)L.i_off[k];
+    for (int row0 = 0; row0 < r.q + np; row0 += kRowsPerBlock) blocks.push_back(RowBlock{k, row0});
     if (r.x0)
       for (int a = 0; a < r.q; ++a) xs[L.x_off[k] + a] = (T)r.x0[a];
     int* gi = idx.data() + L.i_off[k];
@@ -294,70 +311,57 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
       si[c] = ej * P + ei;
     }
   }
+  if ((int)blocks.size() != L.nrowblocks) return fail(FDTD_EINVAL, "internal: row-block count mismatch");
+  if ((rc = up(L.off_blocks, blocks.data(), blocks.size() * sizeof(RowBlock))) != FDTD_OK) return rc;
   if ((rc = up(L.off_roms, rd.data(), rd.size() * sizeof(RomDev))) != FDTD_OK) return rc;
   if ((rc = up(L.off_mats, mats.data(), mats.size() * sizeof(T))) != FDTD_OK) return rc;
   if ((rc = up(L.off_xs, xs.data(), xs.size() * sizeof(T))) != FDTD_OK) return rc;
   if ((rc = up(L.off_idx, idx.data(), idx.size() * sizeof(int))) != FDTD_OK) return rc;
 
-  // kernel parameter blocks for both ping-pong parities
-  for (int set = 0; set < 2; ++set) {
-    StencilParams<T> sp{};
-    T* f_in = (T*)(ws + L.off_fields + 3 * set * fb);
-    T* f_out = (T*)(ws + L.off_fields + 3 * (set ^ 1) * fb);
-    sp.hz = f_in;
-    sp.ex = f_in + fe;
-    sp.ey = f_in + 2 * fe;
-    sp.hzo = f_out;
-    sp.exo = f_out + fe;
-    sp.eyo = f_out + 2 * fe;
-    sp.al = (const T*)(ws + L.off_al);
-    sp.be = (const T*)(ws + L.off_be);
-    sp.ctrl = (const int*)(ws + L.off_ctrl);
-    sp.nx = nx;
-    sp.ny = ny;
-    sp.pitch = P;
-    sp.tiles_x = (nx + kWave - 1) / kWave;
-    sp.chdy = (T)(g.dt / (kMu0 * g.dy));
-    sp.chdx = (T)(g.dt / (kMu0 * g.dx));
-    sp.k2dy = (T)(2.0 / g.dy);
-    sp.k2dx = (T)(2.0 / g.dx);
-    sp.nsrc = p->nsources;
-    for (int k = 0; k < kMaxSrc; ++k) {
-      sp.src[k].comp = -1;
-      sp.src[k].incr = (const T*)(ws + L.off_src);
-    }
-    for (int k = 0; k < p->nsources; ++k) {
-      const fdtd_source& so = p->sources[k];
-      sp.src[k].comp = so.comp;
-      sp.src[k].i0 = so.i0;
-      sp.src[k].i1 = so.i1;
-      sp.src[k].j0 = so.j0;
-      sp.src[k].j1 = so.j1;
-      sp.src[k].incr = (const T*)(ws + L.off_src) + (size_t)k * p->max_steps;
-    }
-    CouplingParams<T> cp{};
-    cp.roms = (const RomDev*)(ws + L.off_roms);
-    cp.nroms = p->nroms;
-    cp.mats = (const T*)(ws + L.off_mats);
-    cp.xs = (T*)(ws + L.off_xs);
-    cp.idx = (const int*)(ws + L.off_idx);
-    cp.hz = f_out;
-    cp.ex = f_out + fe;
-    cp.ey = f_out + 2 * fe;
-    cp.nprobes = p->nprobes;
-    cp.probe_off = (const int*)(ws + L.off_poff);
-    cp.probe_comp = (const int*)(ws + L.off_pcomp);
-    cp.probe_buf = (T*)(ws + L.off_pbuf);
-    cp.ctrl = (int*)(ws + L.off_ctrl);
-    cp.nblocks = p->nroms + 1;
-    if constexpr (sizeof(T) == 4) {
-      s->sp_f[set] = sp;
-      s->cp_f[set] = cp;
-    } else {
-      s->sp_d[set] = sp;
-      s->cp_d[set] = cp;
-    }
+  // kernel parameter block
+  StepParams<T> sp{};
+  for (int set = 0; set < 2; ++set)
+    for (int c = 0; c < 3; ++c) sp.f[set][c] = (T*)(ws + L.off_fields + (3 * set + c) * fb);
+  sp.al = (const T*)(ws + L.off_al);
+  sp.be = (const T*)(ws + L.off_be);
+  sp.ctrl = (int*)(ws + L.off_ctrl);
+  sp.step_off = 0;
+  sp.nx = nx;
+  sp.ny = ny;
+  sp.pitch = P;
+  sp.tiles_x = (nx + kWave - 1) / kWave;
+  sp.nst_blocks = 0;  // set per tiling in set_tiling()
+  sp.chdy = (T)(g.dt / (kMu0 * g.dy));
+  sp.chdx = (T)(g.dt / (kMu0 * g.dx));
+  sp.k2dy = (T)(2.0 / g.dy);
+  sp.k2dx = (T)(2.0 / g.dx);
+  sp.nsrc = p->nsources;
+  for (int k = 0; k < kMaxSrc; ++k) {
+    sp.src[k].comp = -1;
+    sp.src[k].incr = (const T*)(ws + L.off_src);
   }
+  for (int k = 0; k < p->nsources; ++k) {
+    const fdtd_source& so = p->sources[k];
+    sp.src[k].comp = so.comp;
+    sp.src[k].i0 = so.i0;
+    sp.src[k].i1 = so.i1;
+    sp.src[k].j0 = so.j0;
+    sp.src[k].j1 = so.j1;
+    sp.src[k].incr = (const T*)(ws + L.off_src) + (size_t)k * p->max_steps;
+  }
+  sp.roms = (const RomDev*)(ws + L.off_roms);
+  sp.blocks = (const RowBlock*)(ws + L.off_blocks);
+  sp.nrowblocks = L.nrowblocks;
+  sp.ncoup_blocks = (L.nrowblocks + 7) / 8 * 8;
+  sp.mats = (const T*)(ws + L.off_mats);
+  sp.xs = (T*)(ws + L.off_xs);
+  sp.idx = (const int*)(ws + L.off_idx);
+  sp.nprobes = p->nprobes;
+  sp.probe_off = (const int*)(ws + L.off_poff);
+  sp.probe_comp = (const int*)(ws + L.off_pcomp);
+  sp.probe_buf = (T*)(ws + L.off_pbuf);
+  if constexpr (sizeof(T) == 4) s->sp_f = sp;
+  else s->sp_d = sp;
   return FDTD_OK;
 }
 
@@ -524,56 +528,63 @@ int validate_numbers(const fdtd_problem* p, const Layout& L, std::vector<unsigne
 }
 
 template <typename T>
-StencilParams<T>& stencil_params(fdtd_rom_sim* s, int set) {
-  if constexpr (sizeof(T) == 4) return s->sp_f[set];
-  else return s->sp_d[set];
+StepParams<T>& step_params(fdtd_rom_sim* s) {
+  if constexpr (sizeof(T) == 4) return s->sp_f;
+  else return s->sp_d;
 }
 
-template <typename T>
-CouplingParams<T>& coupling_params(fdtd_rom_sim* s, int set) {
-  if constexpr (sizeof(T) == 4) return s->cp_f[set];
-  else return s->cp_d[set];
+// rows of the grid one stencil workgroup covers = 4 waves x seg rows
+void set_tiling(fdtd_rom_sim* s, int seg) {
+  s->seg = seg;
+  const int rows = (kBlock / kWave) * seg;
+  const int nst = ((s->nx + kWave - 1) / kWave) * ((s->ny + rows - 1) / rows);
+  s->sp_f.nst_blocks = nst;
+  s->sp_d.nst_blocks = nst;
+}
+
+int ev_pair(fdtd_rom_sim* s, std::vector<std::pair<hipEvent_t, hipEvent_t>>& pool, size_t& used,
+            hipEvent_t& a, hipEvent_t& b) {
+  if (used >= pool.size()) {
+    hipEvent_t x, y;
+    if (hipEventCreate(&x) != hipSuccess || hipEventCreate(&y) != hipSuccess)
+      return fail(FDTD_EDEVICE, "hipEventCreate failed");
+    pool.emplace_back(x, y);
+  }
+  a = pool[used].first;
+  b = pool[used].second;
+  ++used;
+  return FDTD_OK;
 }
 
 template <typename T>
 int run_steps(fdtd_rom_sim* s, int nsteps) {
+  if (nsteps == 0) return FDTD_OK;
+  StepParams<T> sp = step_params<T>(s);
   for (int k = 0; k < nsteps; ++k) {
-    StencilParams<T>& sp = stencil_params<T>(s, s->cur);
-    CouplingParams<T>& cp = coupling_params<T>(s, s->cur);
-    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+    sp.step_off = k;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     if (s->prof) {
-      if (s->used_st >= s->ev_st.size()) {
-        hipEvent_t a, b;
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
-          return fail(FDTD_EDEVICE, "hipEventCreate failed");
-        s->ev_st.emplace_back(a, b);
-      }
-      if (s->used_cp >= s->ev_cp.size()) {
-        hipEvent_t a, b;
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
-          return fail(FDTD_EDEVICE, "hipEventCreate failed");
-        s->ev_cp.emplace_back(a, b);
-      }
-      e0 = s->ev_st[s->used_st].first;
-      e1 = s->ev_st[s->used_st].second;
-      e2 = s->ev_cp[s->used_cp].first;
-      e3 = s->ev_cp[s->used_cp].second;
-      ++s->used_st;
-      ++s->used_cp;
-      hipEventRecord(e0, s->stream);
+      const int rc = ev_pair(s, s->ev_st, s->used_st, e0, e1);
+      if (rc != FDTD_OK) return rc;
+      if (hipEventRecord(e0, s->stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
     }
-    if (launch_stencil<T>(sp, s->seg, s->stream) != hipSuccess)
-      return fail(FDTD_EDEVICE, "stencil launch failed");
-    if (s->prof) {
-      hipEventRecord(e1, s->stream);
-      hipEventRecord(e2, s->stream);
-    }
-    if (launch_coupling<T>(cp, s->stream) != hipSuccess)
-      return fail(FDTD_EDEVICE, "coupling launch failed");
-    if (s->prof) hipEventRecord(e3, s->stream);
-    s->cur ^= 1;
-    ++s->steps;
+    if (launch_step<T>(sp, s->seg, s->stream) != hipSuccess)
+      return fail(FDTD_EDEVICE, "step launch failed: %s", hipGetErrorString(hipGetLastError()));
+    if (s->prof && hipEventRecord(e1, s->stream) != hipSuccess)
+      return fail(FDTD_EDEVICE, "hipEventRecord failed");
   }
+  // record the last probe row of the batch, then advance the device step base
+  hipEvent_t e2 = nullptr, e3 = nullptr;
+  if (s->prof) {
+    const int rc = ev_pair(s, s->ev_cp, s->used_cp, e2, e3);
+    if (rc != FDTD_OK) return rc;
+    if (hipEventRecord(e2, s->stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
+  }
+  sp.step_off = nsteps;
+  if (launch_probe_flush<T>(sp, s->stream) != hipSuccess || launch_tick(sp.ctrl, nsteps, s->stream) != hipSuccess)
+    return fail(FDTD_EDEVICE, "probe/tick launch failed");
+  if (s->prof && hipEventRecord(e3, s->stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
+  s->steps += nsteps;
   return FDTD_OK;
 }
 
@@ -648,6 +659,7 @@ int fdtd_rom_create(const fdtd_problem* prob, void* dev_workspace, size_t ws_byt
     if (rc == FDTD_OK)
       rc = (s->dtype == FDTD_F32) ? setup_device<float>(s, prob, inside)
                                   : setup_device<double>(s, prob, inside);
+    if (rc == FDTD_OK) set_tiling(s, 16);
     if (rc != FDTD_OK) {
       delete s;
       return rc;
@@ -699,7 +711,7 @@ int fdtd_rom_read_field(const fdtd_rom_sim* sim, int32_t comp, double* host_out)
   if (comp < 0 || comp > 2) return fail(FDTD_EINVAL, "bad component");
   const size_t ts = sim->L.tsize, fe = sim->L.field_elems;
   std::vector<char> raw(fe * ts);
-  const char* src = sim->ws + sim->L.off_fields + (3 * sim->cur + comp) * fe * ts;
+  const char* src = sim->ws + sim->L.off_fields + (3 * (sim->steps & 1) + comp) * fe * ts;
   if (hipMemcpyAsync(raw.data(), src, fe * ts, hipMemcpyDeviceToHost, sim->stream) != hipSuccess ||
       hipStreamSynchronize(sim->stream) != hipSuccess)
     return fail(FDTD_EDEVICE, "field read failed");
@@ -726,7 +738,9 @@ int fdtd_rom_read_rom_state(const fdtd_rom_sim* sim, int32_t k, double* host_out
   const size_t ts = sim->L.tsize;
   const int q = sim->roms[k].q;
   std::vector<char> raw((size_t)q * ts);
-  if (hipMemcpyAsync(raw.data(), sim->ws + sim->L.off_xs + sim->L.x_off[k] * ts, q * ts, hipMemcpyDeviceToHost,
+  // x~^n sits in the buffer of parity n (eq. (23) writes the other one)
+  const size_t xo = sim->L.x_off[k] + (size_t)(sim->steps & 1) * (((size_t)q + 63) / 64 * 64);
+  if (hipMemcpyAsync(raw.data(), sim->ws + sim->L.off_xs + xo * ts, q * ts, hipMemcpyDeviceToHost,
                      sim->stream) != hipSuccess ||
       hipStreamSynchronize(sim->stream) != hipSuccess)
     return fail(FDTD_EDEVICE, "state read failed");
@@ -763,8 +777,8 @@ int fdtd_rom_profile_enable(fdtd_rom_sim* sim, int32_t enable) {
   return FDTD_OK;
 }
 
-int fdtd_rom_profile_read(fdtd_rom_sim* sim, double* stencil_ms, int64_t* stencil_launches, double* coupling_ms,
-                          int64_t* coupling_launches) {
+int fdtd_rom_profile_read(fdtd_rom_sim* sim, double* step_ms, int64_t* step_launches, double* tail_ms,
+                          int64_t* tail_launches) {
   if (!sim) return fail(FDTD_EINVAL, "null handle");
   if (hipStreamSynchronize(sim->stream) != hipSuccess) return fail(FDTD_EDEVICE, "synchronize failed");
   double a = 0, b = 0;
@@ -780,10 +794,10 @@ int fdtd_rom_profile_read(fdtd_rom_sim* sim, double* stencil_ms, int64_t* stenci
       return fail(FDTD_EDEVICE, "hipEventElapsedTime failed");
     b += ms;
   }
-  if (stencil_ms) *stencil_ms = a;
-  if (stencil_launches) *stencil_launches = (int64_t)sim->used_st;
-  if (coupling_ms) *coupling_ms = b;
-  if (coupling_launches) *coupling_launches = (int64_t)sim->used_cp;
+  if (step_ms) *step_ms = a;
+  if (step_launches) *step_launches = (int64_t)sim->used_st;
+  if (tail_ms) *tail_ms = b;
+  if (tail_launches) *tail_launches = (int64_t)sim->used_cp;
   sim->used_st = sim->used_cp = 0;
   return FDTD_OK;
 }

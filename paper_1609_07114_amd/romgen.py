@@ -1,0 +1,33 @@
+"""Reduced models for every refined region of a problem, built by the
+library's host FP64 builder (fdtd_rom_build), regions in parallel threads
+(the ctypes call releases the GIL).  Regions sharing a group >= 0 are built
+once."""
+from __future__ import annotations
+
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+from . import capi
+
+
+def build_roms(prob, theta=0.99, clip=True, workers=None):
+    jobs = []
+    slot = {}
+    order = []
+    for k, spec in enumerate(prob.roms):
+        key = ("g", spec.group) if spec.group >= 0 else ("r", k)
+        if key not in slot:
+            slot[key] = len(jobs)
+            jobs.append(spec)
+        order.append(slot[key])
+
+    def one(spec):
+        return capi.fdtd_rom_build(spec.ni, spec.nj, spec.r, prob.dx, prob.dy, prob.dt,
+                                   spec.eps_r, spec.sigma, spec.q, spec.f_max, theta, clip)
+    workers = workers or min(len(jobs), max(1, min(16, os.cpu_count() or 1))) or 1
+    if len(jobs) <= 1:
+        built = [one(s) for s in jobs]
+    else:
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            built = list(ex.map(one, jobs))
+    return [built[i] for i in order]

@@ -5,6 +5,7 @@ L2 against the oracle evaluated in FP64 with the FP32-rounded coefficients
 and coupling matrices an FP32 run computes with."""
 import copy
 import math
+import os
 
 import numpy as np
 import pytest
@@ -154,3 +155,62 @@ def test_max_steps_enforced():
         with pytest.raises(capi.FdtdError) as e:
             s.run(1)
         assert e.value.status == capi.FDTD_ESTATE
+
+
+def test_product_models_end_to_end():
+    """The library's own model builder feeding the GPU run vs the oracle's
+    builder feeding the oracle run (FP64): the two builds differ only by a
+    change of reduced coordinates, so the probes agree to round-off."""
+    from paper_1609_07114_amd import romgen
+    p = W.random_media(n=256, nsteps=800, spacing=128, offset=48, block=16,
+                       qs=(16, 24, 32, 48), n_probe_side=4, dtype="f64")
+    lib_roms = romgen.build_roms(p)
+    ora_roms = osim.build_roms(p)
+    g = _gpu_run(p, lib_roms)
+    o = _oracle(p, ora_roms)
+    assert rel_l2(g["probes"], o["probes"]) <= 1e-9
+    for k in ("hz", "ex", "ey"):
+        assert rel_l2(g[k], o[k]) <= 1e-9
+
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _c2_models(prob):
+    """Oracle-built models of the 2048^2 workload (tests/golden/make_c2_golden.py)."""
+    z = np.load(os.path.join(GOLD, "c2_models.npz"))
+    return [dict(Rt=z[f"R{k}"], Ft=z[f"F{k}"], Lt=z[f"L{k}"]) for k in range(len(prob.roms))]
+
+
+def test_full_size_random_media_2048_fp32_active_models():
+    """The 2048^2 benchmark configuration itself (16 models, FP32), started
+    from random reduced states so every model is active at once; 40 steps
+    compared element by element on all fields, states and probes."""
+    p = W.random_media(n=2048, nsteps=40)
+    roms = _c2_models(p)
+    rng = np.random.default_rng(11)
+    x0 = [rng.standard_normal(m["Rt"].shape[0]) for m in roms]
+    g = _gpu_run(p, roms, x0=x0)
+    init = dict(hz=np.zeros((p.ny, p.nx)), ex=np.zeros((p.ny + 1, p.nx)),
+                ey=np.zeros((p.ny, p.nx + 1)), x=x0)
+    o = _oracle(p, roms, fp32=True, init=init)
+    assert np.max(np.abs(o["hz"])) > 0
+    _compare(g, o, TOL32)
+
+
+def test_full_size_random_media_2048_fp32_10000_steps():
+    """The whole 10,000-step 2048^2 run in the benchmark's launch
+    configuration: all 64 probe series against the oracle's stored run."""
+    path = os.path.join(GOLD, "c2_probes_f32.npz")
+    z = np.load(path)
+    ref = z["probes"].astype(np.float64)
+    n = int(z["steps"])
+    p = W.random_media(n=2048, nsteps=n)
+    roms = _c2_models(p)
+    with Simulation(p, roms, max_steps=n) as s:
+        s.run(n)
+        got = s.probes()
+    assert np.max(np.abs(ref)) > 0
+    err = rel_l2(got, ref)
+    print(f"2048^2 x {n} steps: rel L2 vs oracle = {err:.3e}", flush=True)
+    assert err <= TOL32

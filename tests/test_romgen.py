@@ -1,0 +1,91 @@
+"""The library's host FP64 reduced-model builder (fdtd_rom_build) against the
+oracle's independent builder.  Two valid builds of the same subspace differ
+by a change of reduced coordinates, so they are compared through the
+coordinate-free transfer function H(p) = L^T (pR + F)^{-1} L Sc, plus
+Theorem 1's invariants and the clip bound of eq. (27)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import rom as orom
+from oracle import yee
+from oracle.constants import C0
+from paper_1609_07114_amd import capi, romgen
+
+PVALS = [0.3, 0.05 + 0.4j, 0.9j, 0.02]
+
+
+def _both(spec, prob, **kw):
+    a = capi.fdtd_rom_build(spec.ni, spec.nj, spec.r, prob.dx, prob.dy, prob.dt, spec.eps_r,
+                            spec.sigma, spec.q, spec.f_max, **kw)
+    b = orom.build_rom(spec.eps_r, spec.sigma, spec.r, prob.dx, prob.dy, prob.dt, spec.q,
+                       spec.f_max, clip=kw.get("clip", True))
+    return a, b
+
+
+def _tf_err(a, b, p):
+    Sc = b["Sc"]
+    Ha = orom.transfer(a["Rt"], a["Ft"], a["Lt"], Sc, p)
+    Hb = orom.transfer(b["Rt"], b["Ft"], b["Lt"], Sc, p)
+    return np.max(np.abs(Ha - Hb)) / np.max(np.abs(Hb))
+
+
+@pytest.mark.parametrize("seed,block,r,q", [(20, (5, 4), 2, 14), (21, (3, 4), 3, 11),
+                                           (22, (4, 4), 2, 40)])
+def test_builder_matches_oracle_transfer(seed, block, r, q):
+    p = W.random_problem(seed, 26, 22, 10, nroms=1, block=block, r=r, q=q)
+    a, b = _both(p.roms[0], p)
+    assert (a["q1"], a["q2"]) == (b["q1"], b["q2"])
+    for pv in PVALS + [b["p0"]]:
+        assert _tf_err(a, b, pv) < 1e-10, pv
+
+
+def test_builder_theorem1_invariants():
+    p = W.random_problem(23, 26, 22, 10, nroms=1, block=(5, 5), r=2, q=20)
+    s = p.roms[0]
+    a = capi.fdtd_rom_build(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, s.q, s.f_max)
+    Rt, Ft = a["Rt"], a["Ft"]
+    assert np.array_equal(Rt, Rt.T)
+    np.linalg.cholesky(Rt)
+    assert np.linalg.eigvalsh(Ft + Ft.T).min() >= -1e-12 * np.abs(Ft).max()
+    # only E coordinates see the ports: L~ rows of the H block are zero
+    assert np.all(a["Lt"][a["q1"]:] == 0)
+
+
+def test_builder_clip_active_matches_oracle():
+    """dt = 1.9x the fine CFL, a nearly complete basis: the clip of eq. (27)
+    is active in both builders and leaves the same model."""
+    p = W.random_problem(11, 10, 9, 10, nroms=1, block=(3, 3), r=2, q=0,
+                         dt_frac_coarse=0.95, lossy=True)
+    s = p.roms[0]
+    s.eps_r[:] = 1.0          # vacuum region: its own CFL limit is eq. (1) on the fine cells
+    s.q = 64
+    a, b = _both(s, p)
+    assert a["clipped"] and b["clipped"]
+    assert a["smax_before"] == pytest.approx(b["smax_before"], rel=1e-9)
+    assert a["smax_after"] <= 0.99 * 2 / p.dt * (1 + 1e-12)
+    np.linalg.cholesky(a["Rt"])
+    for pv in PVALS:
+        assert _tf_err(a, b, pv) < 1e-9, pv
+    # without the clip the same model is not passive at this dt
+    c = capi.fdtd_rom_build(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, s.q, s.f_max,
+                            clip=False)
+    with pytest.raises(np.linalg.LinAlgError):
+        np.linalg.cholesky(c["Rt"])
+
+
+def test_builder_rejects_bad_order():
+    p = W.random_problem(24, 26, 22, 10, nroms=1, block=(2, 2), r=1, q=4)
+    s = p.roms[0]
+    with pytest.raises(capi.FdtdError):
+        capi.fdtd_rom_build(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, 500, s.f_max)
+
+
+def test_build_roms_groups_and_threads():
+    p = W.many_copies(n=512, nsteps=10, q=16, spacing=128, block=8)
+    roms = romgen.build_roms(p)
+    assert len(roms) == len(p.roms) == 16
+    assert all(r is roms[0] for r in roms)
+    p2 = W.random_media(n=256, nsteps=10, spacing=128, offset=48, block=16, qs=(16, 24, 32, 48))
+    r2 = romgen.build_roms(p2)
+    assert [m["Rt"].shape[0] for m in r2] == [s.q for s in p2.roms]
