@@ -221,6 +221,21 @@ int fdtd_rom_profile_enable(fdtd_rom_sim* sim, int32_t enable);
 int fdtd_rom_profile_read(fdtd_rom_sim* sim, double* step_ms, int64_t* step_launches,
                           double* tail_ms, int64_t* tail_launches);
 
+/* Launch configuration.  set_tiling: rows each wave of a stencil tile
+ * advances (8, 16 or 32; default 16).  set_graph: batch > 0 makes run()
+ * replay a captured HIP graph of `batch` steps (capture happens on first use
+ * on a library-owned stream, replay on the handle's stream; remainders and
+ * profiled runs use direct launches); 0 (default) disables graphs. */
+int fdtd_rom_set_tiling(fdtd_rom_sim* sim, int32_t seg);
+
+/* Regions sharing one model (same group >= 0, FP32, at least 8 of them,
+ * q + np <= 512) are advanced by one FP32 MFMA GEMM per step over all copies
+ * (eq. (23) for every copy at once) when enabled (default); disabled, every
+ * region uses its own row-parallel GEMV.  Both give the same result up to
+ * FP32 summation order. */
+int fdtd_rom_set_shared_gemm(fdtd_rom_sim* sim, int32_t enable);
+int fdtd_rom_set_graph(fdtd_rom_sim* sim, int32_t batch);
+
 /* Release the handle (the workspace stays the caller's). */
 void fdtd_rom_destroy(fdtd_rom_sim* sim);
 

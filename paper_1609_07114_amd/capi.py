@@ -86,6 +86,9 @@ _SIGS = {
     "fdtd_rom_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "fdtd_rom_profile_read": (C.c_int, [C.c_void_p, _dp, C.POINTER(C.c_int64), _dp,
                                         C.POINTER(C.c_int64)]),
+    "fdtd_rom_set_tiling": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_set_shared_gemm": (C.c_int, [C.c_void_p, C.c_int32]),
     "fdtd_rom_destroy": (None, [C.c_void_p]),
     "fdtd_rom_strerror": (C.c_char_p, [C.c_int]),
     "fdtd_rom_last_error": (C.c_char_p, []),
@@ -268,6 +271,18 @@ def fdtd_rom_profile_read(h):
     nb = C.c_int64(0)
     _check(lib().fdtd_rom_profile_read(h, C.byref(a), C.byref(na), C.byref(b), C.byref(nb)))
     return float(a.value), int(na.value), float(b.value), int(nb.value)
+
+
+def fdtd_rom_set_tiling(h, seg: int):
+    _check(lib().fdtd_rom_set_tiling(h, int(seg)))
+
+
+def fdtd_rom_set_shared_gemm(h, enable: bool):
+    _check(lib().fdtd_rom_set_shared_gemm(h, 1 if enable else 0))
+
+
+def fdtd_rom_set_graph(h, batch: int):
+    _check(lib().fdtd_rom_set_graph(h, int(batch)))
 
 
 def fdtd_rom_destroy(h):

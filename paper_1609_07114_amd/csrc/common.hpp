@@ -39,14 +39,23 @@ struct RomDev {
   int64_t x_off;     // reduced state, two buffers of xstride (step parity)
   int64_t xstride;
   int64_t i_off;     // gather offsets [np] (Hz cells) then scatter offsets [np]
+  int64_t gt_off;    // G column-major (leading dimension ldg) for the shared-model GEMM, -1 if none
 };
 
 constexpr int kRowsPerWave = 4;
 constexpr int kRowsPerBlock = kRowsPerWave * (kBlock / kWave);
+constexpr int kGemmCopies = 16;    // copies (columns) per shared-model GEMM block
+constexpr int kMaxGemmM = 512;     // q + np handled by the GEMM blocks
+constexpr int kMinGemmCopies = 8;  // shared groups at least this large use the GEMM
 
+// One coupling workgroup.  kind 0: rows [row0, row0 + kRowsPerBlock) of
+// region `a`'s update matrix (GEMV).  kind 1: FP32 MFMA GEMM of one shared
+// model for up to kGemmCopies regions listed at copies[b .. b + c).
 struct RowBlock {
-  int rom;
-  int row0;          // first of kRowsPerBlock rows of G
+  int kind;
+  int a;
+  int b;
+  int c;
 };
 
 // Everything one leap-frog step needs.  One launch advances every tile of
@@ -69,8 +78,9 @@ struct StepParams {
   // embedded models
   const RomDev* roms;
   const RowBlock* blocks;
-  int nrowblocks;    // real row blocks
-  int ncoup_blocks;  // row blocks padded to a multiple of 8 (XCD alignment)
+  const int* copies; // region lists of the GEMM blocks
+  int nrowblocks;    // real coupling blocks
+  int ncoup_blocks;  // coupling blocks padded to a multiple of 8 (XCD alignment)
   const T* mats;
   T* xs;
   const int* idx;
@@ -86,7 +96,7 @@ int fail(int code, const char* fmt, ...);
 
 // launchers (kernels.hip)
 template <typename T>
-hipError_t launch_step(const StepParams<T>& p, int seg, hipStream_t s);
+hipError_t launch_step(const StepParams<T>& p, int seg, size_t smem, hipStream_t s);
 template <typename T>
 hipError_t launch_probe_flush(const StepParams<T>& p, hipStream_t s);
 hipError_t launch_tick(int* ctrl, int k, hipStream_t s);

@@ -3,9 +3,10 @@
 // One launch per leap-frog step n -> n+1 (step_kernel).  Its workgroups are
 // of three kinds, all reading only the step-n buffers (set n & 1) and writing
 // disjoint parts of the step-(n+1) buffers, so they run concurrently:
-//   * coupling row blocks (first, so they start early): eq. (23) for every
+//   * coupling blocks (first, so they start early): eq. (23) for every
 //     embedded model, written as one matrix G on z = [x~^n; h^{n+1/2}]
-//     giving [x~^{n+1}; y^{n+1}].  h (the coarse Hz^{n+1/2} just outside the
+//     giving [x~^{n+1}; y^{n+1}] - a row-parallel GEMV per model, or, for
+//     regions sharing one model (FP32), one MFMA GEMM over the copies.  h (the coarse Hz^{n+1/2} just outside the
 //     ports) is recomputed from the step-n fields with the same arithmetic as
 //     the stencil, so it equals the stencil's value bit for bit; y^{n+1} is
 //     written into the interface edges;
@@ -246,12 +247,10 @@ __device__ T ring_h(const StepParams<T>& p, const T* hz, const T* ex, const T* e
 
 // Rows [row0, row0 + kRowsPerBlock) of one model's eq. (23) update matrix.
 template <typename T>
-__device__ void coupling_rows(const StepParams<T>& p, int b, int n) {
-  __shared__ T z[kMaxQ + kMaxPorts];
+__device__ void coupling_rows(const StepParams<T>& p, const RowBlock& rb, int n, T* z) {
   const int par = n & 1;
   const int tid = threadIdx.x;
-  const RowBlock rb = p.blocks[b];
-  const RomDev r = p.roms[rb.rom];
+  const RomDev r = p.roms[rb.a];
   const T* xin = p.xs + r.x_off + par * r.xstride;
   T* xout = p.xs + r.x_off + (par ^ 1) * r.xstride;
   const int* gi = p.idx + r.i_off;
@@ -263,7 +262,7 @@ __device__ void coupling_rows(const StepParams<T>& p, int b, int n) {
     z[c] = c < r.q ? xin[c] : (c < r.q + r.np ? ring_h(p, hz, ex, ey, gi[c - r.q], n) : T(0));
   __syncthreads();
   const int lane = tid & (kWave - 1);
-  const int row0 = rb.row0 + (tid / kWave) * kRowsPerWave;
+  const int row0 = rb.b + (tid / kWave) * kRowsPerWave;
   const T* G = p.mats + r.g_off + (size_t)row0 * r.ldg;
   T acc[kRowsPerWave];
 #pragma unroll
@@ -294,6 +293,77 @@ __device__ void coupling_rows(const StepParams<T>& p, int b, int n) {
   }
 }
 
+// Shared model, many copies: Out (M x copies) = G (M x M) * Z (M x copies)
+// with Z's column c = [x~_c^n; h_c^{n+1/2}] of region copies[b + c], as FP32
+// MFMA 16x16x4 tiles.  Z is staged in LDS ([k][copy], 16 copies per row);
+// each wave takes every fourth 16-row tile of the output and walks K in
+// steps of 4.  Operand layout of v_mfma_f32_16x16x4f32 (wave64): lane l holds
+// A(l % 16, l / 16) and B(l / 16, l % 16); the result register i of lane l is
+// D(4 * (l / 16) + i, l % 16).
+__device__ void coupling_gemm(const StepParams<float>& p, const RowBlock& gb, int n, float* zs) {
+  const int par = n & 1;
+  const int tid = threadIdx.x;
+  const int ncp = gb.c;
+  const int* list = p.copies + gb.b;
+  const RomDev r = p.roms[list[0]];
+  const int M = r.ldg;  // padded q + np (multiple of 64)
+  const float* hz = fld(p, par, 0);
+  const float* ex = fld(p, par, 1);
+  const float* ey = fld(p, par, 2);
+  for (int e = tid; e < M * kGemmCopies; e += kBlock) {
+    const int k = e / kGemmCopies;
+    const int c = e - k * kGemmCopies;
+    float v = 0.f;
+    if (c < ncp) {
+      const RomDev rc = p.roms[list[c]];
+      if (k < rc.q)
+        v = p.xs[rc.x_off + par * rc.xstride + k];
+      else if (k < rc.q + rc.np)
+        v = ring_h(p, hz, ex, ey, p.idx[rc.i_off + (k - rc.q)], n);
+    }
+    zs[e] = v;
+  }
+  __syncthreads();
+  const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
+  const int lr = lane & 15;  // A row / B column / D column within the tile
+  const int lk = lane >> 4;  // A column / B row / D row group
+  const float* GT = p.mats + r.gt_off;
+  float* exo = fld(p, par ^ 1, 1);
+  float* eyo = fld(p, par ^ 1, 2);
+  for (int rt = wv; rt < M / 16; rt += kBlock / kWave) {
+    const int row0 = rt * 16;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    const float* a_ptr = GT + (size_t)lk * M + row0 + lr;
+    const float* b_ptr = zs + lk * kGemmCopies + lr;
+#pragma unroll 8
+    for (int k0 = 0; k0 < M; k0 += 4) {
+      const float a = a_ptr[(size_t)k0 * M];
+      const float b = b_ptr[k0 * kGemmCopies];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+    if (lr < ncp) {
+      const RomDev rc = p.roms[list[lr]];
+      float* xout = p.xs + rc.x_off + (par ^ 1) * rc.xstride;
+      const int* si = p.idx + rc.i_off + rc.np;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = row0 + 4 * lk + i;
+        if (row < rc.q) {
+          xout[row] = acc[i];
+        } else if (row < rc.q + rc.np) {
+          const int pp = row - rc.q;
+          if (pp < rc.n_ex)
+            exo[si[pp]] = acc[i];
+          else
+            eyo[si[pp]] = acc[i];
+        }
+      }
+    }
+  }
+}
+
 // Probe row m (m >= 0) from the set holding the state after m+1 steps.
 template <typename T>
 __device__ void record_probes(const StepParams<T>& p, int m) {
@@ -308,10 +378,20 @@ __device__ void record_probes(const StepParams<T>& p, int m) {
 
 template <typename T, int SEG>
 __global__ void __launch_bounds__(kBlock) step_kernel(const StepParams<T> p) {
+  extern __shared__ __align__(16) unsigned char smem[];
   const int n = p.ctrl[0] + p.step_off;
   const int b = blockIdx.x;
   if (b < p.ncoup_blocks) {
-    if (b < p.nrowblocks) coupling_rows(p, b, n);
+    if (b < p.nrowblocks) {
+      const RowBlock rb = p.blocks[b];
+      if constexpr (sizeof(T) == 4) {
+        if (rb.kind == 1) {
+          coupling_gemm(p, rb, n, reinterpret_cast<float*>(smem));
+          return;
+        }
+      }
+      coupling_rows(p, rb, n, reinterpret_cast<T*>(smem));
+    }
     return;
   }
   const int t = b - p.ncoup_blocks;
@@ -332,13 +412,12 @@ __global__ void tick_kernel(int* ctrl, int k) {
 }
 
 template <typename T>
-hipError_t launch_step(const StepParams<T>& p, int seg, hipStream_t s) {
+hipError_t launch_step(const StepParams<T>& p, int seg, size_t smem, hipStream_t s) {
   const dim3 g(p.ncoup_blocks + p.nst_blocks + 1), b(kBlock);
   switch (seg) {
-    case 8: hipLaunchKernelGGL((step_kernel<T, 8>), g, b, 0, s, p); break;
-    case 16: hipLaunchKernelGGL((step_kernel<T, 16>), g, b, 0, s, p); break;
-    case 32: hipLaunchKernelGGL((step_kernel<T, 32>), g, b, 0, s, p); break;
-    case 64: hipLaunchKernelGGL((step_kernel<T, 64>), g, b, 0, s, p); break;
+    case 8: hipLaunchKernelGGL((step_kernel<T, 8>), g, b, smem, s, p); break;
+    case 16: hipLaunchKernelGGL((step_kernel<T, 16>), g, b, smem, s, p); break;
+    case 32: hipLaunchKernelGGL((step_kernel<T, 32>), g, b, smem, s, p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -355,8 +434,8 @@ hipError_t launch_tick(int* ctrl, int k, hipStream_t s) {
   return hipGetLastError();
 }
 
-template hipError_t launch_step<float>(const StepParams<float>&, int, hipStream_t);
-template hipError_t launch_step<double>(const StepParams<double>&, int, hipStream_t);
+template hipError_t launch_step<float>(const StepParams<float>&, int, size_t, hipStream_t);
+template hipError_t launch_step<double>(const StepParams<double>&, int, size_t, hipStream_t);
 template hipError_t launch_probe_flush<float>(const StepParams<float>&, hipStream_t);
 template hipError_t launch_probe_flush<double>(const StepParams<double>&, hipStream_t);
 

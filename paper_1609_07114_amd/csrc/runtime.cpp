@@ -53,8 +53,14 @@ struct Layout {
   size_t off_pbuf = 0, off_poff = 0, off_pcomp = 0, off_roms = 0, off_mats = 0;
   size_t off_xs = 0, off_idx = 0, total = 0;
   size_t mats_elems = 0, xs_elems = 0, idx_elems = 0;
-  int nrowblocks = 0;
-  size_t off_blocks = 0;
+  int nrowblocks = 0;        // all-GEMV coupling list
+  int nblocks_mixed = 0;     // GEMM for eligible shared groups + GEMV for the rest
+  size_t off_blocks = 0, off_blocks_mixed = 0, off_copies = 0;
+  std::vector<char> slot_gemm;     // slot uses the MFMA GEMM path
+  std::vector<size_t> slot_gt_off; // element offset of the column-major copy
+  std::vector<int> slot_members;   // regions per slot
+  size_t ncopies = 0;
+  size_t smem_gemv = 0, smem_mixed = 0;
   std::vector<int> slot_of_rom;     // matrix slot per region
   std::vector<int> slot_rep;        // representative region per slot
   std::vector<size_t> slot_off;     // element offset of each slot in the pool
@@ -106,26 +112,52 @@ int plan(const fdtd_problem* p, Layout& L) {
     L.slot_of_rom[k] = slot;
   }
   L.slot_off.clear();
+  L.slot_members.assign(L.slot_rep.size(), 0);
+  for (int k = 0; k < p->nroms; ++k) L.slot_members[L.slot_of_rom[k]]++;
+  L.slot_gemm.assign(L.slot_rep.size(), 0);
+  L.slot_gt_off.assign(L.slot_rep.size(), 0);
   size_t me = 0;
-  for (int rep : L.slot_rep) {
-    const fdtd_rom& r = p->roms[rep];
+  for (size_t sl = 0; sl < L.slot_rep.size(); ++sl) {
+    const fdtd_rom& r = p->roms[L.slot_rep[sl]];
     const int np = ports_of(r);
+    const size_t ldg = align_up((size_t)r.q + np, kWave);
     L.slot_off.push_back(me);
-    me += align_up((size_t)r.q + np, kRowsPerBlock) * align_up((size_t)r.q + np, kWave);
+    me += align_up((size_t)r.q + np, kRowsPerBlock) * ldg;
     me = align_up(me, 64);
+    // shared model, FP32, enough copies: MFMA GEMM over the copies
+    if (g.dtype == FDTD_F32 && r.group >= 0 && L.slot_members[sl] >= kMinGemmCopies && ldg <= (size_t)kMaxGemmM) {
+      L.slot_gemm[sl] = 1;
+      L.slot_gt_off[sl] = me;
+      me = align_up(me + ldg * ldg, 64);
+    }
   }
   L.mats_elems = me;
   L.x_off.clear();
   L.i_off.clear();
   size_t xe = 0, ie = 0;
   L.nrowblocks = 0;
+  L.nblocks_mixed = 0;
+  L.ncopies = 0;
+  L.smem_gemv = L.smem_mixed = 0;
   for (int k = 0; k < p->nroms; ++k) {
     L.x_off.push_back(xe);
     L.i_off.push_back(ie);
+    const size_t ldg = align_up((size_t)p->roms[k].q + ports_of(p->roms[k]), kWave);
     xe = align_up(xe + 2 * align_up((size_t)p->roms[k].q, 64), 64);
     ie = align_up(ie + 2 * (size_t)ports_of(p->roms[k]), 64);
-    L.nrowblocks += (int)(align_up((size_t)p->roms[k].q + ports_of(p->roms[k]), kRowsPerBlock) / kRowsPerBlock);
+    const int rb = (int)(align_up((size_t)p->roms[k].q + ports_of(p->roms[k]), kRowsPerBlock) / kRowsPerBlock);
+    L.nrowblocks += rb;
+    L.smem_gemv = std::max(L.smem_gemv, ldg * ts);
+    if (L.slot_gemm[L.slot_of_rom[k]]) {
+      L.ncopies++;
+      L.smem_mixed = std::max(L.smem_mixed, ldg * kGemmCopies * ts);
+    } else {
+      L.nblocks_mixed += rb;
+      L.smem_mixed = std::max(L.smem_mixed, ldg * ts);
+    }
   }
+  for (size_t sl = 0; sl < L.slot_rep.size(); ++sl)
+    if (L.slot_gemm[sl]) L.nblocks_mixed += (L.slot_members[sl] + kGemmCopies - 1) / kGemmCopies;
   L.xs_elems = xe;
   L.idx_elems = ie;
   size_t o = 0;
@@ -150,6 +182,10 @@ int plan(const fdtd_problem* p, Layout& L) {
   o = align_up(o + (size_t)p->nroms * sizeof(RomDev), 256);
   L.off_blocks = o;
   o = align_up(o + (size_t)L.nrowblocks * sizeof(RowBlock), 256);
+  L.off_blocks_mixed = o;
+  o = align_up(o + (size_t)L.nblocks_mixed * sizeof(RowBlock), 256);
+  L.off_copies = o;
+  o = align_up(o + std::max<size_t>(L.ncopies, 1) * sizeof(int), 256);
   L.off_mats = o;
   o = align_up(o + L.mats_elems * ts, 256);
   L.off_xs = o;
@@ -176,9 +212,15 @@ struct fdtd_rom_sim {
   char* ws = nullptr;
   Layout L;
   int seg = 16;
+  size_t smem = 0;        // dynamic LDS of the step kernel
+  bool shared_gemm = true;
   std::vector<RomHost> roms;
   StepParams<float> sp_f;
   StepParams<double> sp_d;
+  int graph_batch = 0;               // > 0: replay captured batches of this many steps
+  hipStream_t cap_stream = nullptr;  // library-owned stream used only for capture
+  hipGraphExec_t graph = nullptr;
+  int graph_steps = 0, graph_seg = 0;
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_st, ev_cp;
   size_t used_st = 0, used_cp = 0;
@@ -284,7 +326,28 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
       for (int c = 0; c < np; ++c) g[(size_t)(q + k) * ldg + q + c] = (T)CB[(size_t)k * np + c];
     }
   }
-  std::vector<RowBlock> blocks;
+  for (size_t sl = 0; sl < L.slot_rep.size(); ++sl) {
+    if (!L.slot_gemm[sl]) continue;
+    const RomHost& h = s->roms[L.slot_rep[sl]];
+    const size_t ldg = align_up((size_t)h.q + h.np, kWave);
+    const T* g = mats.data() + L.slot_off[sl];
+    T* gt = mats.data() + L.slot_gt_off[sl];
+    for (size_t a = 0; a < ldg && a < align_up((size_t)h.q + h.np, kRowsPerBlock); ++a)
+      for (size_t c = 0; c < ldg; ++c) gt[c * ldg + a] = g[a * ldg + c];
+  }
+  std::vector<RowBlock> blocks, mixed;
+  std::vector<int> copies;
+  for (size_t sl = 0; sl < L.slot_rep.size(); ++sl) {
+    if (!L.slot_gemm[sl]) continue;
+    std::vector<int> members;
+    for (int k = 0; k < p->nroms; ++k)
+      if (L.slot_of_rom[k] == (int)sl) members.push_back(k);
+    for (size_t c0 = 0; c0 < members.size(); c0 += kGemmCopies) {
+      const int cnt = (int)std::min<size_t>(kGemmCopies, members.size() - c0);
+      mixed.push_back(RowBlock{1, (int)sl, (int)copies.size(), cnt});
+      for (int c = 0; c < cnt; ++c) copies.push_back(members[c0 + c]);
+    }
+  }
   for (int k = 0; k < p->nroms; ++k) {
     const fdtd_rom& r = p->roms[k];
     const int np = ports_of(r);
@@ -296,7 +359,11 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
     rd[k].x_off = (int64_t)L.x_off[k];
     rd[k].xstride = (int64_t)align_up((size_t)r.q, 64);
     rd[k].i_off = (int64_t)L.i_off[k];
-    for (int row0 = 0; row0 < r.q + np; row0 += kRowsPerBlock) blocks.push_back(RowBlock{k, row0});
+    rd[k].gt_off = L.slot_gemm[L.slot_of_rom[k]] ? (int64_t)L.slot_gt_off[L.slot_of_rom[k]] : -1;
+    for (int row0 = 0; row0 < r.q + np; row0 += kRowsPerBlock) {
+      blocks.push_back(RowBlock{0, k, row0, 0});
+      if (!L.slot_gemm[L.slot_of_rom[k]]) mixed.push_back(RowBlock{0, k, row0, 0});
+    }
     if (r.x0)
       for (int a = 0; a < r.q; ++a) xs[L.x_off[k] + a] = (T)r.x0[a];
     int* gi = idx.data() + L.i_off[k];
@@ -311,8 +378,11 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
       si[c] = ej * P + ei;
     }
   }
-  if ((int)blocks.size() != L.nrowblocks) return fail(FDTD_EINVAL, "internal: row-block count mismatch");
+  if ((int)blocks.size() != L.nrowblocks || (int)mixed.size() != L.nblocks_mixed || copies.size() != L.ncopies)
+    return fail(FDTD_EINVAL, "internal: coupling block count mismatch");
   if ((rc = up(L.off_blocks, blocks.data(), blocks.size() * sizeof(RowBlock))) != FDTD_OK) return rc;
+  if ((rc = up(L.off_blocks_mixed, mixed.data(), mixed.size() * sizeof(RowBlock))) != FDTD_OK) return rc;
+  if ((rc = up(L.off_copies, copies.data(), copies.size() * sizeof(int))) != FDTD_OK) return rc;
   if ((rc = up(L.off_roms, rd.data(), rd.size() * sizeof(RomDev))) != FDTD_OK) return rc;
   if ((rc = up(L.off_mats, mats.data(), mats.size() * sizeof(T))) != FDTD_OK) return rc;
   if ((rc = up(L.off_xs, xs.data(), xs.size() * sizeof(T))) != FDTD_OK) return rc;
@@ -350,9 +420,12 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
     sp.src[k].incr = (const T*)(ws + L.off_src) + (size_t)k * p->max_steps;
   }
   sp.roms = (const RomDev*)(ws + L.off_roms);
-  sp.blocks = (const RowBlock*)(ws + L.off_blocks);
-  sp.nrowblocks = L.nrowblocks;
-  sp.ncoup_blocks = (L.nrowblocks + 7) / 8 * 8;
+  sp.copies = (const int*)(ws + L.off_copies);
+  // shared groups use the MFMA GEMM when eligible (fdtd_rom_set_shared_gemm)
+  sp.blocks = (const RowBlock*)(ws + L.off_blocks_mixed);
+  sp.nrowblocks = L.nblocks_mixed;
+  sp.ncoup_blocks = (L.nblocks_mixed + 7) / 8 * 8;
+  s->smem = L.smem_mixed;
   sp.mats = (const T*)(ws + L.off_mats);
   sp.xs = (T*)(ws + L.off_xs);
   sp.idx = (const int*)(ws + L.off_idx);
@@ -533,20 +606,26 @@ StepParams<T>& step_params(fdtd_rom_sim* s) {
   else return s->sp_d;
 }
 
-// rows of the grid one stencil workgroup covers = 4 waves x seg rows
+// a stencil workgroup covers 64 columns x (4 waves x seg rows)
 void set_tiling(fdtd_rom_sim* s, int seg) {
   s->seg = seg;
   const int rows = (kBlock / kWave) * seg;
-  const int nst = ((s->nx + kWave - 1) / kWave) * ((s->ny + rows - 1) / rows);
+  const int tx = (s->nx + kWave - 1) / kWave;
+  const int nst = tx * ((s->ny + rows - 1) / rows);
   s->sp_f.nst_blocks = nst;
   s->sp_d.nst_blocks = nst;
+  s->sp_f.tiles_x = tx;
+  s->sp_d.tiles_x = tx;
 }
 
 int ev_pair(fdtd_rom_sim* s, std::vector<std::pair<hipEvent_t, hipEvent_t>>& pool, size_t& used,
             hipEvent_t& a, hipEvent_t& b) {
   if (used >= pool.size()) {
     hipEvent_t x, y;
-    if (hipEventCreate(&x) != hipSuccess || hipEventCreate(&y) != hipSuccess)
+    // timing-only events: no system-scope release/acquire (no cache flush
+    // between the launches being timed)
+    if (hipEventCreateWithFlags(&x, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&y, hipEventDisableSystemFence) != hipSuccess)
       return fail(FDTD_EDEVICE, "hipEventCreate failed");
     pool.emplace_back(x, y);
   }
@@ -556,34 +635,89 @@ int ev_pair(fdtd_rom_sim* s, std::vector<std::pair<hipEvent_t, hipEvent_t>>& poo
   return FDTD_OK;
 }
 
+// Enqueue nsteps step launches, the probe flush and the tick on `stream`.
 template <typename T>
-int run_steps(fdtd_rom_sim* s, int nsteps) {
-  if (nsteps == 0) return FDTD_OK;
+int enqueue_steps(fdtd_rom_sim* s, int nsteps, hipStream_t stream, bool prof) {
   StepParams<T> sp = step_params<T>(s);
   for (int k = 0; k < nsteps; ++k) {
     sp.step_off = k;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (s->prof) {
+    if (prof) {
       const int rc = ev_pair(s, s->ev_st, s->used_st, e0, e1);
       if (rc != FDTD_OK) return rc;
-      if (hipEventRecord(e0, s->stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
+      if (hipEventRecord(e0, stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
     }
-    if (launch_step<T>(sp, s->seg, s->stream) != hipSuccess)
+    if (launch_step<T>(sp, s->seg, s->smem, stream) != hipSuccess)
       return fail(FDTD_EDEVICE, "step launch failed: %s", hipGetErrorString(hipGetLastError()));
-    if (s->prof && hipEventRecord(e1, s->stream) != hipSuccess)
-      return fail(FDTD_EDEVICE, "hipEventRecord failed");
+    if (prof && hipEventRecord(e1, stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
   }
   // record the last probe row of the batch, then advance the device step base
   hipEvent_t e2 = nullptr, e3 = nullptr;
-  if (s->prof) {
+  if (prof) {
     const int rc = ev_pair(s, s->ev_cp, s->used_cp, e2, e3);
     if (rc != FDTD_OK) return rc;
-    if (hipEventRecord(e2, s->stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
+    if (hipEventRecord(e2, stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
   }
   sp.step_off = nsteps;
-  if (launch_probe_flush<T>(sp, s->stream) != hipSuccess || launch_tick(sp.ctrl, nsteps, s->stream) != hipSuccess)
+  if (launch_probe_flush<T>(sp, stream) != hipSuccess || launch_tick(sp.ctrl, nsteps, stream) != hipSuccess)
     return fail(FDTD_EDEVICE, "probe/tick launch failed");
-  if (s->prof && hipEventRecord(e3, s->stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
+  if (prof && hipEventRecord(e3, stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
+  return FDTD_OK;
+}
+
+void drop_graph(fdtd_rom_sim* s) {
+  if (s->graph) (void)hipGraphExecDestroy(s->graph);
+  s->graph = nullptr;
+  s->graph_steps = 0;
+}
+
+// Capture one batch of graph_batch steps (step kernels + flush + tick) on the
+// library's own stream; it is replayed on the caller's stream.  Every launch
+// reads its step index from the device base, so one graph serves any start.
+template <typename T>
+int capture_graph(fdtd_rom_sim* s) {
+  drop_graph(s);
+  if (!s->cap_stream && hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(FDTD_EDEVICE, "hipStreamCreateWithFlags failed");
+  if (hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return fail(FDTD_EDEVICE, "hipStreamBeginCapture failed");
+  int rc = enqueue_steps<T>(s, s->graph_batch, s->cap_stream, false);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+  if (rc != FDTD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess || !g) return fail(FDTD_EDEVICE, "hipStreamEndCapture failed");
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return fail(FDTD_EDEVICE, "hipGraphInstantiate failed");
+  s->graph = ex;
+  s->graph_steps = s->graph_batch;
+  s->graph_seg = s->seg;
+  return FDTD_OK;
+}
+
+template <typename T>
+int run_steps(fdtd_rom_sim* s, int nsteps) {
+  if (nsteps == 0) return FDTD_OK;
+  int done = 0;
+  if (s->graph_batch > 0 && !s->prof && nsteps >= s->graph_batch) {
+    if (!s->graph || s->graph_steps != s->graph_batch || s->graph_seg != s->seg) {
+      const int rc = capture_graph<T>(s);
+      if (rc != FDTD_OK) return rc;
+    }
+    while (nsteps - done >= s->graph_batch) {
+      if (hipGraphLaunch(s->graph, s->stream) != hipSuccess)
+        return fail(FDTD_EDEVICE, "hipGraphLaunch failed: %s", hipGetErrorString(hipGetLastError()));
+      done += s->graph_batch;
+    }
+  }
+  if (nsteps > done) {
+    const int rc = enqueue_steps<T>(s, nsteps - done, s->stream, s->prof);
+    if (rc != FDTD_OK) return rc;
+  }
   s->steps += nsteps;
   return FDTD_OK;
 }
@@ -802,15 +936,56 @@ int fdtd_rom_profile_read(fdtd_rom_sim* sim, double* step_ms, int64_t* step_laun
   return FDTD_OK;
 }
 
+int fdtd_rom_set_tiling(fdtd_rom_sim* sim, int32_t seg) {
+  if (!sim) return fail(FDTD_EINVAL, "null handle");
+  if (seg != 8 && seg != 16 && seg != 32) return fail(FDTD_EINVAL, "segment rows must be 8, 16 or 32");
+  set_tiling(sim, seg);
+  return FDTD_OK;
+}
+
+int fdtd_rom_set_shared_gemm(fdtd_rom_sim* sim, int32_t enable) {
+  if (!sim) return fail(FDTD_EINVAL, "null handle");
+  const Layout& L = sim->L;
+  const bool on = enable != 0;
+  const RowBlock* b = (const RowBlock*)(sim->ws + (on ? L.off_blocks_mixed : L.off_blocks));
+  const int nb = on ? L.nblocks_mixed : L.nrowblocks;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 0) {
+      sim->sp_f.blocks = b;
+      sim->sp_f.nrowblocks = nb;
+      sim->sp_f.ncoup_blocks = (nb + 7) / 8 * 8;
+    } else {
+      sim->sp_d.blocks = b;
+      sim->sp_d.nrowblocks = nb;
+      sim->sp_d.ncoup_blocks = (nb + 7) / 8 * 8;
+    }
+  }
+  sim->smem = on ? L.smem_mixed : L.smem_gemv;
+  sim->shared_gemm = on;
+  drop_graph(sim);
+  return FDTD_OK;
+}
+
+int fdtd_rom_set_graph(fdtd_rom_sim* sim, int32_t batch) {
+  if (!sim) return fail(FDTD_EINVAL, "null handle");
+  if (batch < 0 || batch > 4096) return fail(FDTD_EINVAL, "graph batch must be in [0, 4096]");
+  sim->graph_batch = batch;
+  if (batch == 0) drop_graph(sim);
+  return FDTD_OK;
+}
+
 void fdtd_rom_destroy(fdtd_rom_sim* sim) {
   if (!sim) return;
+  (void)hipStreamSynchronize(sim->stream);
+  drop_graph(sim);
+  if (sim->cap_stream) (void)hipStreamDestroy(sim->cap_stream);
   for (auto& e : sim->ev_st) {
-    hipEventDestroy(e.first);
-    hipEventDestroy(e.second);
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
   }
   for (auto& e : sim->ev_cp) {
-    hipEventDestroy(e.first);
-    hipEventDestroy(e.second);
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
   }
   delete sim;
 }

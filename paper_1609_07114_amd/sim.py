@@ -49,6 +49,15 @@ class Simulation:
     def coupled_update(self, k):
         return capi.fdtd_rom_coupled_update(self.ps, k)
 
+    def set_tiling(self, seg):
+        capi.fdtd_rom_set_tiling(self.h, seg)
+
+    def set_shared_gemm(self, enable):
+        capi.fdtd_rom_set_shared_gemm(self.h, enable)
+
+    def set_graph(self, batch):
+        capi.fdtd_rom_set_graph(self.h, batch)
+
     def profile(self, enable=True):
         capi.fdtd_rom_profile_enable(self.h, enable)
 

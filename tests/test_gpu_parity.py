@@ -55,7 +55,11 @@ def _compare(g, o, tol, fields=True):
     if fields:
         for k in ("hz", "ex", "ey"):
             assert rel_l2(g[k], o[k]) <= tol, (k, rel_l2(g[k], o[k]))
-        for a, b in zip(g["x"], o["x"]):
+        if len(g["x"]):
+            # all reduced states as one vector: a region the wave has not
+            # reached holds values below FP32's normal range in the oracle
+            a = np.concatenate(g["x"])
+            b = np.concatenate(o["x"])
             assert rel_l2(a, b) <= tol, rel_l2(a, b)
 
 
@@ -214,3 +218,67 @@ def test_full_size_random_media_2048_fp32_10000_steps():
     err = rel_l2(got, ref)
     print(f"2048^2 x {n} steps: rel L2 vs oracle = {err:.3e}", flush=True)
     assert err <= TOL32
+
+
+def test_graph_replays_match_eager():
+    """Captured step batches replayed several times (with host reads and
+    synchronisations in between, and odd remainders) give bit-identical
+    results to direct launches."""
+    import torch
+    p = W.random_problem(8, 70, 45, 300, nroms=2, block=(5, 4), r=2, q=12, dtype="f32")
+    roms = osim.build_roms(p)
+    eager = _gpu_run(p, roms)
+    with Simulation(p, roms, max_steps=300) as s:
+        s.set_graph(16)
+        mids = []
+        for chunk in (40, 3, 16, 100, 141):
+            s.run(chunk)
+            torch.cuda.synchronize()
+            mids.append(s.probes(0, s.steps_done))
+        got = dict(probes=s.probes(), hz=s.field(0), ex=s.field(1), ey=s.field(2))
+    assert np.array_equal(got["probes"], eager["probes"])
+    for k in ("hz", "ex", "ey"):
+        assert np.array_equal(got[k], eager[k])
+    for m in mids:
+        assert np.array_equal(m, eager["probes"][:m.shape[0]])
+
+
+@pytest.mark.parametrize("nx,ny", [(130, 77), (124, 40), (125, 33), (63, 9), (3, 20)])
+@pytest.mark.parametrize("seg", [8, 32])
+def test_tilings_match(nx, ny, seg):
+    """Every tiling (rows per wave segment) gives bit-identical fields,
+    including ragged tails of the 62-column tiles."""
+    nroms = 2 if nx > 20 else 0
+    p = W.random_problem(12 + nx, nx, ny, 120, nroms=nroms, block=(5, 4), r=2, q=12)
+    roms = osim.build_roms(p)
+    ref = _gpu_run(p, roms)
+    with Simulation(p, roms, max_steps=120) as s:
+        s.set_tiling(seg)
+        s.run(120)
+        got = dict(probes=s.probes(), hz=s.field(0), ex=s.field(1), ey=s.field(2))
+    for k in ("probes", "hz", "ex", "ey"):
+        assert np.array_equal(got[k], ref[k]), k
+    o = _oracle(p, roms)
+    _compare(got | dict(x=[]), o, TOL64, fields=True)
+
+
+@pytest.mark.parametrize("q,block,spacing,n", [(128, 32, 128, 1024), (40, 8, 48, 400)])
+def test_shared_model_mfma_gemm(q, block, spacing, n):
+    """Many copies of one model: the FP32 MFMA GEMM over all copies, the
+    per-copy GEMV path and the oracle agree."""
+    p = W.many_copies(n=n, nsteps=200, q=q, spacing=spacing, block=block)
+    assert len(p.roms) >= 16
+    roms = osim.build_roms(p)
+    with Simulation(p, roms, max_steps=200) as s:
+        s.run(200)
+        gemm = dict(probes=s.probes(), hz=s.field(0), ex=s.field(1), ey=s.field(2),
+                    x=[s.rom_state(k) for k in range(len(roms))])
+    with Simulation(p, roms, max_steps=200) as s:
+        s.set_shared_gemm(False)
+        s.run(200)
+        gemv = dict(probes=s.probes(), hz=s.field(0), ex=s.field(1), ey=s.field(2))
+    for k in ("probes", "hz", "ex", "ey"):
+        assert rel_l2(gemm[k], gemv[k]) <= TOL32, (k, rel_l2(gemm[k], gemv[k]))
+    assert np.max(np.abs(gemm["x"][0])) > 0
+    o = _oracle(p, roms, fp32=True)
+    _compare(gemm, o, TOL32)
