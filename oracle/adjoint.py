@@ -1,0 +1,167 @@
+"""Discrete adjoint of the coupled run: gradient of
+    J = dt * sum_{n=0}^{N-1} (Hz_p^{n+1/2})^2
+with respect to the per-cell relative permittivity and conductivity of the
+coarse grid (paper Sec. II-A eq. (3) coefficients; eq. (23) coupling held
+fixed: the reduced models are inputs).
+
+The forward step (oracle.sim) is linear in the state s^n = (E^n, Hz^{n-1/2},
+x~^n) for fixed coefficients:
+  1. Hz' = M (Hz + curlE(E)) + src            (eq. (5), M = active-cell mask)
+  2. E'  = Ca E + Cb curlH(Hz') + src          on active edges (eq. (3))
+  3. [x~'; y'] = G [x~; gather(Hz')],  E'[interface] = y'   (eq. (23))
+  4. J += dt (Hz'_p)^2
+The reverse sweep applies the transpose of 3, 2, 1 in that order with
+lambda^N = 0, and accumulates dJ/dCa_e = sum lambda_E'_e E_e and
+dJ/dCb_e = sum lambda_E'_e dH_e over active edges.  With a = eps/dt,
+b = sigma/2 on an edge (eps, sigma the mean of its two cells),
+Ca = (a-b)/(a+b) and Cb/d = 1/((a+b) d):
+  dCa/da = 2b/(a+b)^2, dCa/db = -2a/(a+b)^2, d(Cb/d)/da = d(Cb/d)/db = -1/((a+b)^2 d),
+  da/deps_r(cell) = eps0/(2 dt), db/dsigma(cell) = 1/4 for each of the edge's cells.
+Cells inside reduced regions and their one-cell rings (whose half cells
+enter C+- of eq. (13)) get zero gradient: the models are held fixed.
+
+Parity: pinned by central finite differences of the oracle's own forward
+run and by the transpose identity <lambda, delta s> of one step.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .constants import EPS0
+from . import sim as osim
+from . import yee
+
+
+def _edge_ab(prob):
+    """a = eps/dt, b = sigma/2 on interior edges (FP64)."""
+    er, sg, dt = prob.eps_r, prob.sigma, prob.dt
+    ax = EPS0 * 0.5 * (er[1:, :] + er[:-1, :]) / dt
+    bx = 0.25 * (sg[1:, :] + sg[:-1, :])
+    ay = EPS0 * 0.5 * (er[:, 1:] + er[:, :-1]) / dt
+    by = 0.25 * (sg[:, 1:] + sg[:, :-1])
+    return ax, bx, ay, by
+
+
+def gradient_mask(prob):
+    """True for cells whose gradient is reported (outside every region and
+    its one-cell ring)."""
+    m = np.ones((prob.ny, prob.nx), dtype=bool)
+    for s in prob.roms:
+        m[max(s.j0 - 1, 0):s.j0 + s.nj + 1, max(s.i0 - 1, 0):s.i0 + s.ni + 1] = False
+    return m
+
+
+def forward_states(prob, roms, nsteps=None, probe=0):
+    """Forward run keeping (E^n, Hz^{n-1/2}) for n = 0..N and the objective."""
+    run = osim.CoupledRun(prob, roms, mode="closed")
+    nsteps = prob.nsteps if nsteps is None else nsteps
+    states = [(run.f.ex.copy(), run.f.ey.copy(), run.f.hz.copy())]
+    J = 0.0
+    pr = prob.probes[probe]
+    for n in range(nsteps):
+        run.step()
+        states.append((run.f.ex.copy(), run.f.ey.copy(), run.f.hz.copy()))
+        J += prob.dt * run.f.hz[pr.j, pr.i] ** 2
+    return run, states, J
+
+
+def adjoint_gradient(prob, roms, nsteps=None, probe=0):
+    """Return (J, dJ/deps_r [ny,nx], dJ/dsigma [ny,nx])."""
+    nsteps = prob.nsteps if nsteps is None else nsteps
+    run, states, J = forward_states(prob, roms, nsteps, probe)
+    nx, ny = prob.nx, prob.ny
+    cell, exm, eym = run.cell, run.exm, run.eym
+    ca_x, cb_x, ca_y, cb_y, chdy, chdx = run.ca_x, run.cb_x, run.ca_y, run.cb_y, run.chdy, run.chdx
+    pr = prob.probes[probe]
+    if pr.comp != yee.HZ:
+        raise ValueError("objective probe must be an Hz probe")
+    # interface edges of every model
+    Gs = [c.update_matrix() for c in run.cpl]
+    lam_ex = np.zeros((ny + 1, nx))
+    lam_ey = np.zeros((ny, nx + 1))
+    lam_hz = np.zeros((ny, nx))
+    lam_x = [np.zeros(c.q) for c in run.cpl]
+    g_cax = np.zeros((ny + 1, nx))
+    g_cbx = np.zeros((ny + 1, nx))
+    g_cay = np.zeros((ny, nx + 1))
+    g_cby = np.zeros((ny, nx + 1))
+    for n in range(nsteps - 1, -1, -1):
+        ex0, ey0, _ = states[n]          # E^n
+        _, _, hz1 = states[n + 1]        # Hz^{n+1/2}
+        hz1 = hz1 * cell
+        # objective: J += dt (Hz'_p)^2
+        lam_h = lam_hz.copy()
+        lam_h[pr.j, pr.i] += 2.0 * prob.dt * hz1[pr.j, pr.i]
+        lam_ex_in = lam_ex.copy()
+        lam_ey_in = lam_ey.copy()
+        # 3. coupling: [x'; y'] = G [x; gather(Hz')], y' into interface edges
+        new_lam_x = []
+        for c, G, lx in zip(run.cpl, Gs, lam_x):
+            ly = c.read_y(lam_ex_in, lam_ey_in)
+            back = G.T @ np.concatenate([lx, ly])
+            new_lam_x.append(back[:c.q].copy())
+            for k, (_, _, _, oi, oj, _, _) in enumerate(c.ports):
+                lam_h[oj, oi] += back[c.q + k]
+            c.scatter(lam_ex_in, lam_ey_in, np.zeros(c.np_))   # consumed
+        # 2. E' = Ca E + Cb curlH(Hz') on active edges
+        lex = np.where(exm, lam_ex_in, 0.0)
+        ley = np.where(eym, lam_ey_in, 0.0)
+        dhx = np.zeros((ny + 1, nx))
+        dhx[1:ny, :] = hz1[1:, :] - hz1[:-1, :]
+        dhy = np.zeros((ny, nx + 1))
+        dhy[:, 1:nx] = -(hz1[:, 1:] - hz1[:, :-1])
+        g_cax += lex * ex0
+        g_cbx += lex * dhx
+        g_cay += ley * ey0
+        g_cby += ley * dhy
+        # d/dHz' of sum lex*cb_x*(Hz(j)-Hz(j-1)) + ley*cb_y*(-(Hz(i)-Hz(i-1)))
+        wx = lex * cb_x
+        wy = ley * cb_y
+        lam_h += wx[:-1, :] - wx[1:, :]       # edge (i,j) above cell (i,j-1): +, edge (i,j+1): -
+        lam_h += -wy[:, :-1] + wy[:, 1:]
+        # 1. Hz' = M (Hz + chdy (Ex(j+1)-Ex(j)) - chdx (Ey(i+1)-Ey(i)))
+        mu = lam_h * cell
+        new_ex = lex * ca_x
+        new_ey = ley * ca_y
+        new_ex[1:, :] += chdy * mu
+        new_ex[:-1, :] -= chdy * mu
+        new_ey[:, 1:] -= chdx * mu
+        new_ey[:, :-1] += chdx * mu
+        # walls carry no adjoint (E fixed at zero there)
+        new_ex[0, :] = 0.0
+        new_ex[ny, :] = 0.0
+        new_ey[:, 0] = 0.0
+        new_ey[:, nx] = 0.0
+        lam_ex, lam_ey, lam_hz, lam_x = new_ex, new_ey, mu, new_lam_x
+    # chain rule to cell materials
+    ax, bx, ay, by = _edge_ab(prob)
+    d = {}
+    for (gca, gcb, a, b, dd, sl) in ((g_cax, g_cbx, ax, bx, prob.dy, (slice(1, ny), slice(None))),
+                                     (g_cay, g_cby, ay, by, prob.dx, (slice(None), slice(1, nx)))):
+        s2 = (a + b) ** 2
+        dca_da = 2 * b / s2
+        dca_db = -2 * a / s2
+        dcb_dab = -1.0 / (s2 * dd)
+        ga = gca[sl] * dca_da + gcb[sl] * dcb_dab     # dJ/da on each edge
+        gb = gca[sl] * dca_db + gcb[sl] * dcb_dab     # dJ/db
+        d[id(gca)] = (ga, gb)
+    gex_a, gex_b = d[id(g_cax)]   # [ny-1, nx], edge between cells (i,j-1),(i,j)
+    gey_a, gey_b = d[id(g_cay)]   # [ny, nx-1], edge between cells (i-1,j),(i,j)
+    geps = np.zeros((ny, nx))
+    gsig = np.zeros((ny, nx))
+    fa = EPS0 / (2.0 * prob.dt)
+    fb = 0.25
+    geps[:-1, :] += fa * gex_a
+    geps[1:, :] += fa * gex_a
+    geps[:, :-1] += fa * gey_a
+    geps[:, 1:] += fa * gey_a
+    gsig[:-1, :] += fb * gex_b
+    gsig[1:, :] += fb * gex_b
+    gsig[:, :-1] += fb * gey_b
+    gsig[:, 1:] += fb * gey_b
+    m = gradient_mask(prob)
+    return J, np.where(m, geps, 0.0), np.where(m, gsig, 0.0)
+
+
+def objective(prob, roms, nsteps=None, probe=0):
+    return forward_states(prob, roms, nsteps, probe)[2]

@@ -1,0 +1,61 @@
+"""Pins of the oracle's discrete adjoint: central finite differences of the
+oracle's own forward run (lossy and lossless, with embedded models), zero
+gradient on masked cells, and the objective's definition."""
+import copy
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint as oadj
+from oracle import sim as osim
+
+
+@pytest.fixture(scope="module")
+def case():
+    p = W.random_problem(31, 30, 26, 250, nroms=1, block=(5, 4), r=2, q=12,
+                         dt_frac_coarse=0.9, f_bw=3e9)
+    roms = osim.build_roms(p)
+    J, ge, gs = oadj.adjoint_gradient(p, roms)
+    return p, roms, J, ge, gs
+
+
+def _fd(p, roms, arr, i, j, h):
+    pp = copy.deepcopy(p)
+    getattr(pp, arr)[j, i] += h
+    pm = copy.deepcopy(p)
+    getattr(pm, arr)[j, i] -= h
+    return (oadj.objective(pp, roms) - oadj.objective(pm, roms)) / (2 * h)
+
+
+def test_objective_is_time_integrated_probe_energy(case):
+    p, roms, J, _, _ = case
+    pr = osim.run(p, roms, mode="closed")[:, 0]
+    assert J == pytest.approx(p.dt * np.sum(pr ** 2), rel=1e-12)
+
+
+def test_adjoint_matches_central_differences(case):
+    p, roms, J, ge, gs = case
+    m = oadj.gradient_mask(p)
+    rng = np.random.default_rng(0)
+    cells = [(i, j) for j in range(1, p.ny - 1) for i in range(1, p.nx - 1) if m[j, i]]
+    for k in rng.choice(len(cells), 5, replace=False):
+        i, j = cells[k]
+        fd_e = _fd(p, roms, "eps_r", i, j, 1e-4)
+        fd_s = _fd(p, roms, "sigma", i, j, 1e-5)
+        assert ge[j, i] == pytest.approx(fd_e, rel=2e-6, abs=1e-6 * np.abs(ge).max())
+        assert gs[j, i] == pytest.approx(fd_s, rel=2e-6, abs=1e-6 * np.abs(gs).max())
+
+
+def test_adjoint_lossless_two_models():
+    p = W.random_problem(33, 34, 28, 200, nroms=2, block=(4, 4), r=2, q=10,
+                         dt_frac_coarse=0.9, lossy=False, f_bw=3e9)
+    roms = osim.build_roms(p)
+    J, ge, gs = oadj.adjoint_gradient(p, roms)
+    m = oadj.gradient_mask(p)
+    assert np.all(ge[~m] == 0) and np.all(gs[~m] == 0)
+    (i, j) = [(i, j) for j in range(2, p.ny - 2) for i in range(2, p.nx - 2) if m[j, i]][17]
+    assert ge[j, i] == pytest.approx(_fd(p, roms, "eps_r", i, j, 1e-4), rel=2e-6,
+                                     abs=1e-6 * np.abs(ge).max())
+    assert gs[j, i] == pytest.approx(_fd(p, roms, "sigma", i, j, 1e-5), rel=2e-6,
+                                     abs=1e-6 * np.abs(gs).max())
