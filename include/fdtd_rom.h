@@ -236,6 +236,38 @@ int fdtd_rom_set_tiling(fdtd_rom_sim* sim, int32_t seg);
 int fdtd_rom_set_shared_gemm(fdtd_rom_sim* sim, int32_t enable);
 int fdtd_rom_set_graph(fdtd_rom_sim* sim, int32_t batch);
 
+/* Discrete adjoint (reverse-time sweep) of the coupled leap-frog run for the
+ * objective J = dt * sum_{n=0}^{nsteps-1} (Hz_p^{n+1/2})^2 at Hz probe p:
+ * the gradient of J with respect to the relative permittivity and the
+ * conductivity of every coarse cell (Sec. II-A eqs. (3) and (5) transposed,
+ * eq. (23) transposed with the reduced models held fixed).  The two cells
+ * of an edge share its eq. (3) coefficients through the averages
+ * a = eps0 mean(eps_r)/dt and b = mean(sigma)/2 (Ca = (a-b)/(a+b),
+ * Cb = 1/(a+b)); cells inside a region or on its one-cell ring (whose
+ * material is folded into the models' eq. (13) half cells) report zero.
+ *
+ * fdtd_rom_adjoint_workspace_size: device bytes the sweep needs for nsteps
+ * with a checkpoint every ckpt_every steps (0 selects ceil(sqrt(nsteps))):
+ * ceil(nsteps/ckpt_every) checkpoints of the fields and reduced states,
+ * ckpt_every recomputed field sets, two adjoint field sets, the adjoint
+ * reduced states, two FP64 per-cell accumulators and G^T of every model.
+ *
+ * fdtd_rom_adjoint: runs the forward from the handle's initial state (the
+ * handle must have taken no step; FDTD_ESTATE otherwise), keeping
+ * checkpoints, then sweeps back one segment at a time, recomputing each
+ * segment's forward states from its checkpoint.  Afterwards the handle
+ * stands at step nsteps with its probe record filled, as after
+ * fdtd_rom_run(sim, nsteps).
+ *   probe: index of an Hz probe of the problem (FDTD_EINVAL otherwise).
+ *   dev_adj_ws: device pointer, 256-B aligned, >= the size above; caller's.
+ *   J: host double; grad_eps_r, grad_sigma: host [ny*nx] row-major (cell
+ *     (i,j) at j*nx+i), caller-allocated.  Synchronises the stream. */
+int fdtd_rom_adjoint_workspace_size(const fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every,
+                                    size_t* bytes);
+int fdtd_rom_adjoint(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int32_t probe,
+                     void* dev_adj_ws, size_t ws_bytes, double* J, double* grad_eps_r,
+                     double* grad_sigma);
+
 /* Release the handle (the workspace stays the caller's). */
 void fdtd_rom_destroy(fdtd_rom_sim* sim);
 

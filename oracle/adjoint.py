@@ -51,9 +51,11 @@ def gradient_mask(prob):
     return m
 
 
-def forward_states(prob, roms, nsteps=None, probe=0):
-    """Forward run keeping (E^n, Hz^{n-1/2}) for n = 0..N and the objective."""
-    run = osim.CoupledRun(prob, roms, mode="closed")
+def forward_states(prob, roms, nsteps=None, probe=0, fp32=False):
+    """Forward run keeping (E^n, Hz^{n-1/2}) for n = 0..N and the objective.
+    fp32: the eq. (3) coefficients and eq. (23) update matrix rounded to FP32
+    as an FP32 run holds them (arithmetic stays FP64)."""
+    run = osim.CoupledRun(prob, roms, mode="closed", fp32=fp32)
     nsteps = prob.nsteps if nsteps is None else nsteps
     states = [(run.f.ex.copy(), run.f.ey.copy(), run.f.hz.copy())]
     J = 0.0
@@ -65,10 +67,11 @@ def forward_states(prob, roms, nsteps=None, probe=0):
     return run, states, J
 
 
-def adjoint_gradient(prob, roms, nsteps=None, probe=0):
-    """Return (J, dJ/deps_r [ny,nx], dJ/dsigma [ny,nx])."""
+def adjoint_gradient(prob, roms, nsteps=None, probe=0, fp32=False):
+    """Return (J, dJ/deps_r [ny,nx], dJ/dsigma [ny,nx]).  fp32: transpose of
+    the forward with FP32-rounded coefficients (see forward_states)."""
     nsteps = prob.nsteps if nsteps is None else nsteps
-    run, states, J = forward_states(prob, roms, nsteps, probe)
+    run, states, J = forward_states(prob, roms, nsteps, probe, fp32)
     nx, ny = prob.nx, prob.ny
     cell, exm, eym = run.cell, run.exm, run.eym
     ca_x, cb_x, ca_y, cb_y, chdy, chdx = run.ca_x, run.cb_x, run.ca_y, run.cb_y, run.chdy, run.chdx
@@ -76,7 +79,7 @@ def adjoint_gradient(prob, roms, nsteps=None, probe=0):
     if pr.comp != yee.HZ:
         raise ValueError("objective probe must be an Hz probe")
     # interface edges of every model
-    Gs = [c.update_matrix() for c in run.cpl]
+    Gs = [c.G32 if fp32 else c.update_matrix() for c in run.cpl]
     lam_ex = np.zeros((ny + 1, nx))
     lam_ey = np.zeros((ny, nx + 1))
     lam_hz = np.zeros((ny, nx))

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_NAME = "libfdtdrom.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
-SOURCES = ["csrc/kernels.hip", "csrc/runtime.cpp", "csrc/romgen.cpp"]
+SOURCES = ["csrc/kernels.hip", "csrc/adjoint.hip", "csrc/runtime.cpp", "csrc/adjoint_rt.cpp",
+           "csrc/romgen.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

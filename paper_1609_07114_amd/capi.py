@@ -89,6 +89,10 @@ _SIGS = {
     "fdtd_rom_set_tiling": (C.c_int, [C.c_void_p, C.c_int32]),
     "fdtd_rom_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
     "fdtd_rom_set_shared_gemm": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_adjoint_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
+                                                  C.POINTER(C.c_size_t)]),
+    "fdtd_rom_adjoint": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                   C.c_size_t, _dp, _dp, _dp]),
     "fdtd_rom_destroy": (None, [C.c_void_p]),
     "fdtd_rom_strerror": (C.c_char_p, [C.c_int]),
     "fdtd_rom_last_error": (C.c_char_p, []),
@@ -283,6 +287,23 @@ def fdtd_rom_set_shared_gemm(h, enable: bool):
 
 def fdtd_rom_set_graph(h, batch: int):
     _check(lib().fdtd_rom_set_graph(h, int(batch)))
+
+
+def fdtd_rom_adjoint_workspace_size(h, nsteps: int, ckpt_every: int = 0) -> int:
+    n = C.c_size_t(0)
+    _check(lib().fdtd_rom_adjoint_workspace_size(h, int(nsteps), int(ckpt_every), C.byref(n)))
+    return int(n.value)
+
+
+def fdtd_rom_adjoint(h, nsteps: int, ckpt_every: int, probe: int, dev_ptr: int, nbytes: int,
+                     nx: int, ny: int):
+    """Returns (J, dJ/deps_r [ny, nx], dJ/dsigma [ny, nx])."""
+    J = C.c_double(0)
+    ge = np.zeros((ny, nx), dtype=np.float64)
+    gs = np.zeros((ny, nx), dtype=np.float64)
+    _check(lib().fdtd_rom_adjoint(h, int(nsteps), int(ckpt_every), int(probe), C.c_void_p(dev_ptr),
+                                  nbytes, C.byref(J), _ptr(ge), _ptr(gs)))
+    return float(J.value), ge, gs
 
 
 def fdtd_rom_destroy(h):

@@ -1,0 +1,47 @@
+// Parameters of one reverse (adjoint) step; shared by adjoint.hip and the
+// host orchestration in adjoint_rt.cpp.
+#pragma once
+
+#include "common.hpp"
+
+namespace fdtd {
+
+// Adjoint variables share the forward field layout (pitch, ownership: a
+// cell holds the adjoint of its Hz, south Ex and west Ey).  "in" holds the
+// adjoint of the state after step n+1, "out" receives that of the state
+// after step n.  lhz_in is updated in place by the coupling transpose.
+template <typename T>
+struct AdjParams {
+  T* lhz_in;
+  const T* lex_in;
+  const T* ley_in;
+  T* lhz_out;
+  T* lex_out;
+  T* ley_out;
+  const T* lx_in;    // adjoint reduced states, indexed by RomDev::x_off
+  T* lx_out;
+  const T* hz1;      // forward Hz^{n+1/2}
+  const T* ex0;      // forward E^n
+  const T* ey0;
+  const T* al;       // per-cell eps0*eps_r/dt (negative inside regions)
+  const T* be;       // per-cell sigma/2
+  double* geps;      // dJ/deps_r accumulator per cell (pitch layout)
+  double* gsig;      // dJ/dsigma accumulator per cell
+  int nx, ny, pitch;
+  T chdy, chdx, k2dy, k2dx;
+  double dx, dy;
+  double fa;         // d(eps0*eps_r/dt averaged on an edge)/d eps_r(cell) = eps0/(2 dt)
+  int64_t obj_off;   // Hz sample of the objective
+  T obj_coef;        // 2 dt
+  // coupling transpose: G^T row-major (RomDev::gt_off), row blocks of kind 0
+  const RomDev* roms;
+  const RowBlock* blocks;
+  int nblocks;
+  const T* mats;
+  const int* idx;
+};
+
+template <typename T>
+hipError_t launch_adjoint_step(const AdjParams<T>& p, size_t smem, hipStream_t s);
+
+}  // namespace fdtd

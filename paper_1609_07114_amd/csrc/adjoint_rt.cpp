@@ -1,0 +1,297 @@
+// Host orchestration of the reverse sweep (fdtd_rom_adjoint).
+//
+// Forward: the handle runs nsteps as usual; before every segment of
+// ckpt_every steps its current field set and reduced states are copied to a
+// checkpoint.  Reverse, one segment at a time from the last: the segment's
+// forward states are recomputed from its checkpoint with the step kernel
+// writing each step's output into its own slot (nothing overwritten, no
+// probe record, a private step counter), then the adjoint steps run from the
+// segment's end back to its start, each reading E^n (slot n) and
+// Hz^{n+1/2} (slot n+1).  Peak memory: checkpoints + one segment.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/fdtd_rom.h"
+#include "adjoint.hpp"
+#include "linalg.hpp"
+#include "runtime.hpp"
+
+using namespace fdtd;
+
+namespace {
+
+struct AdjLayout {
+  int K = 0, nck = 0;
+  size_t set_bytes = 0, xs_bytes = 0;
+  size_t off_ctrl = 0, off_ckpt = 0, ck_stride = 0, off_slots = 0, off_xs = 0;
+  size_t off_lam = 0, off_lx = 0, off_g = 0, off_gt = 0, off_roms = 0, total = 0;
+  size_t gt_elems = 0;
+  std::vector<size_t> slot_gt;  // element offset of each matrix slot's G^T
+};
+
+int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A) {
+  if (nsteps < 1 || nsteps > s->max_steps)
+    return fail(FDTD_EINVAL, "nsteps=%d outside [1, max_steps=%d]", nsteps, s->max_steps);
+  if (ckpt_every < 0 || ckpt_every > nsteps)
+    return fail(FDTD_EINVAL, "ckpt_every=%d outside [0, nsteps=%d]", ckpt_every, nsteps);
+  const Layout& L = s->L;
+  A.K = ckpt_every > 0 ? ckpt_every : (int)std::ceil(std::sqrt((double)nsteps));
+  A.nck = (nsteps + A.K - 1) / A.K;
+  const size_t ts = L.tsize;
+  A.set_bytes = 3 * L.field_elems * ts;
+  A.xs_bytes = align_up(std::max<size_t>(L.xs_elems, 1) * ts, 256);
+  A.slot_gt.clear();
+  size_t ge = 0;
+  for (size_t sl = 0; sl < L.slot_rep.size(); ++sl) {
+    const RomHost& h = s->roms[L.slot_rep[sl]];
+    const size_t ldg = align_up((size_t)h.q + h.np, kWave);
+    A.slot_gt.push_back(ge);
+    ge = align_up(ge + ldg * ldg, 64);
+  }
+  A.gt_elems = ge;
+  size_t o = 0;
+  A.off_ctrl = o;
+  o = align_up(o + kCtrlInts * sizeof(int), 256);
+  A.off_ckpt = o;
+  A.ck_stride = align_up(A.set_bytes, 256) + A.xs_bytes;
+  o += (size_t)A.nck * A.ck_stride;
+  A.off_slots = o;
+  o = align_up(o + (size_t)A.K * A.set_bytes, 256);
+  A.off_xs = o;
+  o += A.xs_bytes;
+  A.off_lam = o;
+  o = align_up(o + 2 * A.set_bytes, 256);
+  A.off_lx = o;
+  o += 2 * A.xs_bytes;
+  A.off_g = o;
+  o = align_up(o + 2 * L.field_elems * sizeof(double), 256);
+  A.off_gt = o;
+  o = align_up(o + A.gt_elems * ts, 256);
+  A.off_roms = o;
+  o = align_up(o + (size_t)std::max(s->nroms, 1) * sizeof(RomDev), 256);
+  A.total = o;
+  return FDTD_OK;
+}
+
+template <typename T>
+int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A, double* J,
+                 double* grad_eps, double* grad_sig) {
+  const Layout& L = s->L;
+  hipStream_t st = s->stream;
+  const size_t fe = L.field_elems;
+  char* ws = s->ws;
+  auto dev_err = [&](const char* what) {
+    return fail(FDTD_EDEVICE, "%s failed: %s", what, hipGetErrorString(hipGetLastError()));
+  };
+  // G^T of every matrix slot (row k = column k of eq. (23)'s G) and the
+  // model table pointing at it
+  {
+    std::vector<T> gt(std::max<size_t>(A.gt_elems, 1), T(0));
+    for (size_t sl = 0; sl < L.slot_rep.size(); ++sl) {
+      const RomHost& h = s->roms[L.slot_rep[sl]];
+      const int q = h.q, np = h.np;
+      const size_t ldg = align_up((size_t)q + np, kWave);
+      std::vector<double> CA((size_t)np * q), CB((size_t)np * np);
+      la::gemm(np, q, q, h.C.data(), h.A.data(), CA.data());
+      la::gemm(np, np, q, h.C.data(), h.B.data(), CB.data());
+      T* g = gt.data() + A.slot_gt[sl];
+      auto put = [&](int row, int col, double v) { g[(size_t)col * ldg + row] = (T)v; };
+      for (int a = 0; a < q; ++a) {
+        for (int c = 0; c < q; ++c) put(a, c, h.A[(size_t)a * q + c]);
+        for (int c = 0; c < np; ++c) put(a, q + c, h.B[(size_t)a * np + c]);
+      }
+      for (int k = 0; k < np; ++k) {
+        for (int c = 0; c < q; ++c) put(q + k, c, CA[(size_t)k * q + c]);
+        for (int c = 0; c < np; ++c) put(q + k, q + c, CB[(size_t)k * np + c]);
+      }
+    }
+    std::vector<RomDev> rd(s->nroms);
+    for (int k = 0; k < s->nroms; ++k) {
+      const RomHost& h = s->roms[k];
+      rd[k].q = h.q;
+      rd[k].np = h.np;
+      rd[k].n_ex = 2 * h.ni;
+      rd[k].ldg = (int)align_up((size_t)h.q + h.np, kWave);
+      rd[k].g_off = -1;
+      rd[k].x_off = (int64_t)L.x_off[k];
+      rd[k].xstride = (int64_t)align_up((size_t)h.q, 64);
+      rd[k].i_off = (int64_t)L.i_off[k];
+      rd[k].gt_off = (int64_t)A.slot_gt[L.slot_of_rom[k]];
+    }
+    if (hipMemcpyAsync(aw + A.off_gt, gt.data(), A.gt_elems * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess ||
+        (s->nroms > 0 && hipMemcpyAsync(aw + A.off_roms, rd.data(), rd.size() * sizeof(RomDev),
+                                        hipMemcpyHostToDevice, st) != hipSuccess) ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return dev_err("model upload");
+  }
+  // zero the private step counter, slots, adjoint fields, states, gradients
+  if (hipMemsetAsync(aw + A.off_ctrl, 0, kCtrlInts * sizeof(int), st) != hipSuccess ||
+      hipMemsetAsync(aw + A.off_slots, 0, A.off_gt - A.off_slots, st) != hipSuccess)
+    return dev_err("hipMemsetAsync");
+
+  auto ckpt = [&](int c) { return aw + A.off_ckpt + (size_t)c * A.ck_stride; };
+  auto ckpt_xs = [&](int c) { return ckpt(c) + align_up(A.set_bytes, 256); };
+  auto slot = [&](int k) { return aw + A.off_slots + (size_t)k * A.set_bytes; };
+  T* xs_scr = (T*)(aw + A.off_xs);
+  const size_t xs_copy = L.xs_elems * sizeof(T);
+
+  // forward with checkpoints
+  for (int c = 0; c < A.nck; ++c) {
+    const int m0 = c * A.K;
+    const int len = std::min(A.K, N - m0);
+    const char* cur = ws + L.off_fields + (size_t)(m0 & 1) * A.set_bytes;
+    if (hipMemcpyAsync(ckpt(c), cur, A.set_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        (xs_copy > 0 && hipMemcpyAsync(ckpt_xs(c), ws + L.off_xs, xs_copy, hipMemcpyDeviceToDevice, st) != hipSuccess))
+      return dev_err("checkpoint copy");
+    const int rc = run_steps_any(s, len);
+    if (rc != FDTD_OK) return rc;
+  }
+
+  // objective from the probe record
+  {
+    std::vector<double> pr((size_t)N * s->nprobes);
+    const int rc = fdtd_rom_read_probes(s, 0, N, pr.data());
+    if (rc != FDTD_OK) return rc;
+    double acc = 0;
+    for (int n = 0; n < N; ++n) {
+      const double v = pr[(size_t)n * s->nprobes + probe];
+      acc += v * v;
+    }
+    *J = s->dt * acc;
+  }
+
+  // reverse sweep
+  StepParams<T> rp = step_params<T>(s);
+  rp.ctrl = (int*)(aw + A.off_ctrl);
+  rp.nprobes = 0;
+  rp.xs = xs_scr;
+  AdjParams<T> ap{};
+  const StepParams<T>& sp = step_params<T>(s);
+  ap.al = sp.al;
+  ap.be = sp.be;
+  ap.geps = (double*)(aw + A.off_g);
+  ap.gsig = ap.geps + fe;
+  ap.nx = s->nx;
+  ap.ny = s->ny;
+  ap.pitch = s->pitch;
+  ap.chdy = sp.chdy;
+  ap.chdx = sp.chdx;
+  ap.k2dy = sp.k2dy;
+  ap.k2dx = sp.k2dx;
+  ap.dx = s->dx;
+  ap.dy = s->dy;
+  ap.fa = kEps0 / (2.0 * s->dt);
+  ap.obj_off = (int64_t)s->probes[probe].j * s->pitch + s->probes[probe].i;
+  ap.obj_coef = (T)(2.0 * s->dt);
+  ap.roms = (const RomDev*)(aw + A.off_roms);
+  ap.blocks = (const RowBlock*)(ws + L.off_blocks);
+  ap.nblocks = s->nroms > 0 ? L.nrowblocks : 0;
+  ap.mats = (const T*)(aw + A.off_gt);
+  ap.idx = (const int*)(ws + L.off_idx);
+  T* lam[2] = {(T*)(aw + A.off_lam), (T*)(aw + A.off_lam + A.set_bytes)};
+  T* lx[2] = {(T*)(aw + A.off_lx), (T*)(aw + A.off_lx + A.xs_bytes)};
+  int cur = 0;
+  for (int c = A.nck - 1; c >= 0; --c) {
+    const int m0 = c * A.K;
+    const int len = std::min(A.K, N - m0);
+    // state m0 + k: k = 0 is the checkpoint, k >= 1 is slot k - 1
+    auto state = [&](int k) -> T* { return (T*)(k == 0 ? ckpt(c) : slot(k - 1)); };
+    if (xs_copy > 0 && hipMemcpyAsync(xs_scr, ckpt_xs(c), xs_copy, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return dev_err("state restore");
+    for (int k = 0; k < len; ++k) {  // states m0+1 .. m0+len into slots 0 .. len-1
+      const int m = m0 + k;
+      const int par = m & 1;
+      T* in = state(k);
+      T* out = state(k + 1);
+      for (int f = 0; f < 3; ++f) {
+        rp.f[par][f] = in + (size_t)f * fe;
+        rp.f[par ^ 1][f] = out + (size_t)f * fe;
+      }
+      rp.step_off = m;
+      if (launch_step<T>(rp, s->seg, s->smem, st) != hipSuccess) return dev_err("recompute launch");
+    }
+    for (int k = len - 1; k >= 0; --k) {
+      T* li = lam[cur];
+      T* lo = lam[cur ^ 1];
+      ap.lhz_in = li;
+      ap.lex_in = li + fe;
+      ap.ley_in = li + 2 * fe;
+      ap.lhz_out = lo;
+      ap.lex_out = lo + fe;
+      ap.ley_out = lo + 2 * fe;
+      ap.lx_in = lx[cur];
+      ap.lx_out = lx[cur ^ 1];
+      ap.hz1 = state(k + 1);
+      ap.ex0 = state(k) + fe;
+      ap.ey0 = state(k) + 2 * fe;
+      if (launch_adjoint_step<T>(ap, L.smem_gemv, st) != hipSuccess) return dev_err("adjoint launch");
+      cur ^= 1;
+    }
+  }
+  // gradients: pitch layout -> natural, zero on regions and their rings
+  std::vector<double> g(2 * fe);
+  if (hipMemcpyAsync(g.data(), aw + A.off_g, 2 * fe * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return dev_err("gradient read");
+  const int nx = s->nx, ny = s->ny, P = s->pitch;
+  std::vector<unsigned char> held((size_t)nx * ny, 0);
+  for (const RomHost& h : s->roms)
+    for (int j = std::max(h.j0 - 1, 0); j < std::min(h.j0 + h.nj + 1, ny); ++j)
+      for (int i = std::max(h.i0 - 1, 0); i < std::min(h.i0 + h.ni + 1, nx); ++i) held[(size_t)j * nx + i] = 1;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const size_t c = (size_t)j * nx + i;
+      grad_eps[c] = held[c] ? 0.0 : g[(size_t)j * P + i];
+      grad_sig[c] = held[c] ? 0.0 : g[fe + (size_t)j * P + i];
+      if (!std::isfinite(grad_eps[c]) || !std::isfinite(grad_sig[c]))
+        return fail(FDTD_EUNSTABLE, "non-finite gradient at cell (%d,%d)", i, j);
+    }
+  return FDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdtd_rom_adjoint_workspace_size(const fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every,
+                                    size_t* bytes) {
+  if (!sim || !bytes) return fail(FDTD_EINVAL, "null argument");
+  try {
+    AdjLayout A;
+    const int rc = plan_adjoint(sim, nsteps, ckpt_every, A);
+    if (rc != FDTD_OK) return rc;
+    *bytes = A.total;
+    return FDTD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(FDTD_ENOMEM, "host allocation failed");
+  }
+}
+
+int fdtd_rom_adjoint(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int32_t probe,
+                     void* dev_adj_ws, size_t ws_bytes, double* J, double* grad_eps_r,
+                     double* grad_sigma) {
+  if (!sim || !J || !grad_eps_r || !grad_sigma) return fail(FDTD_EINVAL, "null argument");
+  if (sim->steps != 0) return fail(FDTD_ESTATE, "the adjoint starts from the initial state (%d steps taken)", sim->steps);
+  if (probe < 0 || probe >= sim->nprobes) return fail(FDTD_EINVAL, "probe %d out of range", probe);
+  if (sim->probes[probe].comp != FDTD_HZ) return fail(FDTD_EINVAL, "probe %d is not an Hz probe", probe);
+  try {
+    AdjLayout A;
+    int rc = plan_adjoint(sim, nsteps, ckpt_every, A);
+    if (rc != FDTD_OK) return rc;
+    if (!dev_adj_ws) return fail(FDTD_EINVAL, "null adjoint workspace");
+    if (((uintptr_t)dev_adj_ws) % 256) return fail(FDTD_EINVAL, "adjoint workspace must be 256-byte aligned");
+    if (ws_bytes < A.total) return fail(FDTD_ENOMEM, "adjoint workspace has %zu bytes, %zu needed", ws_bytes, A.total);
+    char* aw = (char*)dev_adj_ws;
+    return sim->dtype == FDTD_F32 ? adjoint_impl<float>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma)
+                                  : adjoint_impl<double>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma);
+  } catch (const std::bad_alloc&) {
+    return fail(FDTD_ENOMEM, "host allocation failed");
+  }
+}
+
+}  // extern "C"

@@ -20,6 +20,7 @@
 #include "../../include/fdtd_rom.h"
 #include "common.hpp"
 #include "linalg.hpp"
+#include "runtime.hpp"
 
 using namespace fdtd;
 
@@ -38,36 +39,6 @@ int fdtd::fail(int code, const char* fmt, ...) {
 }
 
 namespace {
-
-const double kC0 = FDTD_C0;
-const double kMu0 = FDTD_MU0;
-const double kEps0 = 1.0 / (kMu0 * kC0 * kC0);
-
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-struct Layout {
-  int pitch = 0;
-  size_t tsize = 0;
-  size_t field_elems = 0;
-  size_t off_ctrl = 0, off_fields = 0, off_al = 0, off_be = 0, off_src = 0;
-  size_t off_pbuf = 0, off_poff = 0, off_pcomp = 0, off_roms = 0, off_mats = 0;
-  size_t off_xs = 0, off_idx = 0, total = 0;
-  size_t mats_elems = 0, xs_elems = 0, idx_elems = 0;
-  int nrowblocks = 0;        // all-GEMV coupling list
-  int nblocks_mixed = 0;     // GEMM for eligible shared groups + GEMV for the rest
-  size_t off_blocks = 0, off_blocks_mixed = 0, off_copies = 0;
-  std::vector<char> slot_gemm;     // slot uses the MFMA GEMM path
-  std::vector<size_t> slot_gt_off; // element offset of the column-major copy
-  std::vector<int> slot_members;   // regions per slot
-  size_t ncopies = 0;
-  size_t smem_gemv = 0, smem_mixed = 0;
-  std::vector<int> slot_of_rom;     // matrix slot per region
-  std::vector<int> slot_rep;        // representative region per slot
-  std::vector<size_t> slot_off;     // element offset of each slot in the pool
-  std::vector<size_t> x_off, i_off; // per region
-};
-
-int ports_of(const fdtd_rom& r) { return 2 * (r.ni + r.nj); }
 
 // Shape-level validation and workspace plan (no numerics).
 int plan(const fdtd_problem* p, Layout& L) {
@@ -195,40 +166,6 @@ int plan(const fdtd_problem* p, Layout& L) {
   L.total = o;
   return FDTD_OK;
 }
-
-struct RomHost {
-  int i0, j0, ni, nj, q, np, slot;
-  std::vector<double> A, B, C;  // closed form, row-major
-};
-
-}  // namespace
-
-struct fdtd_rom_sim {
-  int dtype = FDTD_F32;
-  int nx = 0, ny = 0, pitch = 0;
-  double dx = 0, dy = 0, dt = 0;
-  int max_steps = 0, steps = 0, nprobes = 0, nsrc = 0, nroms = 0;
-  hipStream_t stream = nullptr;
-  char* ws = nullptr;
-  Layout L;
-  int seg = 16;
-  size_t smem = 0;        // dynamic LDS of the step kernel
-  bool shared_gemm = true;
-  std::vector<RomHost> roms;
-  StepParams<float> sp_f;
-  StepParams<double> sp_d;
-  int graph_batch = 0;               // > 0: replay captured batches of this many steps
-  hipStream_t cap_stream = nullptr;  // library-owned stream used only for capture
-  hipGraphExec_t graph = nullptr;
-  int graph_steps = 0, graph_seg = 0;
-  bool prof = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_st, ev_cp;
-  size_t used_st = 0, used_cp = 0;
-  double ms_st = 0, ms_cp = 0;
-  int64_t n_st = 0, n_cp = 0;
-};
-
-namespace {
 
 template <typename T>
 int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsigned char>& inside) {
@@ -600,12 +537,6 @@ int validate_numbers(const fdtd_problem* p, const Layout& L, std::vector<unsigne
   return FDTD_OK;
 }
 
-template <typename T>
-StepParams<T>& step_params(fdtd_rom_sim* s) {
-  if constexpr (sizeof(T) == 4) return s->sp_f;
-  else return s->sp_d;
-}
-
 // a stencil workgroup covers 64 columns x (4 waves x seg rows)
 void set_tiling(fdtd_rom_sim* s, int seg) {
   s->seg = seg;
@@ -730,6 +661,10 @@ void to_double(const std::vector<char>& raw, size_t n, double* out) {
 
 }  // namespace
 
+int fdtd::run_steps_any(fdtd_rom_sim* s, int nsteps) {
+  return s->dtype == FDTD_F32 ? run_steps<float>(s, nsteps) : run_steps<double>(s, nsteps);
+}
+
 extern "C" {
 
 const char* fdtd_rom_strerror(int status) {
@@ -786,6 +721,7 @@ int fdtd_rom_create(const fdtd_problem* prob, void* dev_workspace, size_t ws_byt
     s->nprobes = prob->nprobes;
     s->nsrc = prob->nsources;
     s->nroms = prob->nroms;
+    if (prob->nprobes > 0) s->probes.assign(prob->probes, prob->probes + prob->nprobes);
     s->stream = (hipStream_t)hip_stream;
     s->ws = (char*)dev_workspace;
     s->L = L;
@@ -812,7 +748,7 @@ int fdtd_rom_run(fdtd_rom_sim* sim, int32_t nsteps) {
   if (nsteps < 0) return fail(FDTD_EINVAL, "negative step count");
   if ((int64_t)sim->steps + nsteps > sim->max_steps)
     return fail(FDTD_ESTATE, "%d + %d steps exceed max_steps=%d", sim->steps, nsteps, sim->max_steps);
-  return sim->dtype == FDTD_F32 ? run_steps<float>(sim, nsteps) : run_steps<double>(sim, nsteps);
+  return run_steps_any(sim, nsteps);
 }
 
 int fdtd_rom_steps_done(const fdtd_rom_sim* sim, int32_t* n) {

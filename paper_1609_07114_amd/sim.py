@@ -58,6 +58,19 @@ class Simulation:
     def set_graph(self, batch):
         capi.fdtd_rom_set_graph(self.h, batch)
 
+    def adjoint(self, nsteps=None, probe=0, ckpt_every=0):
+        """Forward run from the initial state plus the reverse sweep:
+        (J, dJ/deps_r, dJ/dsigma) for J = dt * sum_n Hz_probe(n+1/2)^2."""
+        nsteps = self.prob.nsteps if nsteps is None else nsteps
+        nb = capi.fdtd_rom_adjoint_workspace_size(self.h, nsteps, ckpt_every)
+        aws = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+        try:
+            return capi.fdtd_rom_adjoint(self.h, nsteps, ckpt_every, probe, aws.data_ptr(), nb,
+                                         self.prob.nx, self.prob.ny)
+        finally:
+            self.stream.synchronize()
+            del aws
+
     def profile(self, enable=True):
         capi.fdtd_rom_profile_enable(self.h, enable)
 

@@ -59,3 +59,14 @@ def test_adjoint_lossless_two_models():
                                      abs=1e-6 * np.abs(ge).max())
     assert gs[j, i] == pytest.approx(_fd(p, roms, "sigma", i, j, 1e-5), rel=2e-6,
                                      abs=1e-6 * np.abs(gs).max())
+
+
+def test_fp32_coefficient_mode_tracks_fp64(case):
+    """The FP32-coefficient variant (the transpose of the forward an FP32 run
+    computes) stays within FP32 coefficient rounding of the FD-pinned FP64
+    gradient."""
+    p, roms, J, ge, gs = case
+    J32, ge32, gs32 = oadj.adjoint_gradient(p, roms, fp32=True)
+    assert J32 == pytest.approx(J, rel=1e-5)
+    assert np.linalg.norm(ge32 - ge) <= 1e-4 * np.linalg.norm(ge)
+    assert np.linalg.norm(gs32 - gs) <= 1e-4 * np.linalg.norm(gs)
