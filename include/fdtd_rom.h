@@ -268,6 +268,36 @@ int fdtd_rom_adjoint(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int3
                      void* dev_adj_ws, size_t ws_bytes, double* J, double* grad_eps_r,
                      double* grad_sigma);
 
+/* Batched runs: B independent problems (uneven grids, models, sources,
+ * probes; one dtype) advanced together, each step of all of them by one
+ * kernel launch, replayed from captured HIP graphs.  Every instance is
+ * validated and laid out exactly as fdtd_rom_create does (same checks, same
+ * error codes, reported with the instance index); instance b runs the same
+ * device code on the same data as its own handle would.
+ *   batch_workspace_size / batch_create: as the single-problem calls, for
+ *     the array probs[0..B); the caller's 256-B aligned device workspace
+ *     holds every instance.
+ *   batch_run: advance every instance by nsteps (asynchronous); FDTD_ESTATE
+ *     if any instance would exceed its max_steps.
+ *   batch_read_probes / batch_read_field: as the single-problem calls, for
+ *     instance b.  Synchronise.
+ *   batch_set_tiling: rows per stencil wave (8, 16, 32) of instance b, or of
+ *     every instance for b = -1 (the autotuner's knob).
+ *   batch_set_graph: steps per captured graph (0 = direct launches). */
+typedef struct fdtd_rom_batch fdtd_rom_batch; /* opaque, owned by the library */
+int fdtd_rom_batch_workspace_size(const fdtd_problem* probs, int32_t B, size_t* bytes);
+int fdtd_rom_batch_create(const fdtd_problem* probs, int32_t B, void* dev_workspace,
+                          size_t ws_bytes, void* hip_stream, fdtd_rom_batch** out);
+int fdtd_rom_batch_run(fdtd_rom_batch* batch, int32_t nsteps);
+int fdtd_rom_batch_steps_done(const fdtd_rom_batch* batch, int32_t* n);
+int fdtd_rom_batch_read_probes(const fdtd_rom_batch* batch, int32_t b, int32_t first,
+                               int32_t count, double* host_out);
+int fdtd_rom_batch_read_field(const fdtd_rom_batch* batch, int32_t b, int32_t comp,
+                              double* host_out);
+int fdtd_rom_batch_set_tiling(fdtd_rom_batch* batch, int32_t b, int32_t seg);
+int fdtd_rom_batch_set_graph(fdtd_rom_batch* batch, int32_t batch_steps);
+void fdtd_rom_batch_destroy(fdtd_rom_batch* batch);
+
 /* Release the handle (the workspace stays the caller's). */
 void fdtd_rom_destroy(fdtd_rom_sim* sim);
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 LIB_NAME = "libfdtdrom.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 SOURCES = ["csrc/kernels.hip", "csrc/adjoint.hip", "csrc/runtime.cpp", "csrc/adjoint_rt.cpp",
-           "csrc/romgen.cpp"]
+           "csrc/batch_rt.cpp", "csrc/romgen.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -93,6 +93,17 @@ _SIGS = {
                                                   C.POINTER(C.c_size_t)]),
     "fdtd_rom_adjoint": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                    C.c_size_t, _dp, _dp, _dp]),
+    "fdtd_rom_batch_workspace_size": (C.c_int, [C.POINTER(fdtd_problem), C.c_int32,
+                                                C.POINTER(C.c_size_t)]),
+    "fdtd_rom_batch_create": (C.c_int, [C.POINTER(fdtd_problem), C.c_int32, C.c_void_p, C.c_size_t,
+                                        C.c_void_p, C.POINTER(C.c_void_p)]),
+    "fdtd_rom_batch_run": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_batch_steps_done": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "fdtd_rom_batch_read_probes": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _dp]),
+    "fdtd_rom_batch_read_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _dp]),
+    "fdtd_rom_batch_set_tiling": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "fdtd_rom_batch_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_batch_destroy": (None, [C.c_void_p]),
     "fdtd_rom_destroy": (None, [C.c_void_p]),
     "fdtd_rom_strerror": (C.c_char_p, [C.c_int]),
     "fdtd_rom_last_error": (C.c_char_p, []),
@@ -304,6 +315,63 @@ def fdtd_rom_adjoint(h, nsteps: int, ckpt_every: int, probe: int, dev_ptr: int, 
     _check(lib().fdtd_rom_adjoint(h, int(nsteps), int(ckpt_every), int(probe), C.c_void_p(dev_ptr),
                                   nbytes, C.byref(J), _ptr(ge), _ptr(gs)))
     return float(J.value), ge, gs
+
+
+def _problem_array(problems):
+    arr = (fdtd_problem * len(problems))()
+    for k, ps in enumerate(problems):
+        arr[k] = ps.s
+    return arr
+
+
+def fdtd_rom_batch_workspace_size(problems) -> int:
+    n = C.c_size_t(0)
+    arr = _problem_array(problems)
+    _check(lib().fdtd_rom_batch_workspace_size(arr, len(problems), C.byref(n)))
+    return int(n.value)
+
+
+def fdtd_rom_batch_create(problems, dev_ptr: int, nbytes: int, stream: int):
+    h = C.c_void_p()
+    arr = _problem_array(problems)
+    _check(lib().fdtd_rom_batch_create(arr, len(problems), C.c_void_p(dev_ptr), nbytes,
+                                       C.c_void_p(stream), C.byref(h)))
+    return h
+
+
+def fdtd_rom_batch_run(h, nsteps: int):
+    _check(lib().fdtd_rom_batch_run(h, int(nsteps)))
+
+
+def fdtd_rom_batch_steps_done(h) -> int:
+    n = C.c_int32(0)
+    _check(lib().fdtd_rom_batch_steps_done(h, C.byref(n)))
+    return int(n.value)
+
+
+def fdtd_rom_batch_read_probes(h, b: int, first: int, count: int, nprobes: int) -> np.ndarray:
+    out = np.zeros((count, nprobes), dtype=np.float64)
+    _check(lib().fdtd_rom_batch_read_probes(h, b, first, count, _ptr(out)))
+    return out
+
+
+def fdtd_rom_batch_read_field(h, b: int, comp: int, nx: int, ny: int) -> np.ndarray:
+    shape = {FDTD_HZ: (ny, nx), FDTD_EX: (ny + 1, nx), FDTD_EY: (ny, nx + 1)}[comp]
+    out = np.zeros(shape, dtype=np.float64)
+    _check(lib().fdtd_rom_batch_read_field(h, b, comp, _ptr(out)))
+    return out
+
+
+def fdtd_rom_batch_set_tiling(h, b: int, seg: int):
+    _check(lib().fdtd_rom_batch_set_tiling(h, int(b), int(seg)))
+
+
+def fdtd_rom_batch_set_graph(h, batch: int):
+    _check(lib().fdtd_rom_batch_set_graph(h, int(batch)))
+
+
+def fdtd_rom_batch_destroy(h):
+    lib().fdtd_rom_batch_destroy(h)
 
 
 def fdtd_rom_destroy(h):

@@ -71,6 +71,7 @@ struct StepParams {
   int step_off;
   int nx, ny, pitch;
   int tiles_x, nst_blocks;
+  int seg;           // rows per stencil wave (8, 16, 32) of this tiling
   T chdy, chdx;      // dt/(mu0 dy), dt/(mu0 dx)
   T k2dy, k2dx;      // 2/dy, 2/dx
   int nsrc;
@@ -91,6 +92,17 @@ struct StepParams {
   T* probe_buf;      // [max_steps][nprobes]
 };
 
+// One workgroup of the batched step launch: instance `inst`, role `kind`
+// (0 coupling block idx of that instance, 1 stencil tile idx, 2 probe
+// block, 3 idle padding that keeps every instance's tile range aligned to
+// the 8 XCDs).
+struct BatchRef {
+  int inst;
+  int kind;
+  int idx;
+  int pad;
+};
+
 // Record a failure message for fdtd_rom_last_error() and return code.
 int fail(int code, const char* fmt, ...);
 
@@ -100,5 +112,11 @@ hipError_t launch_step(const StepParams<T>& p, int seg, size_t smem, hipStream_t
 template <typename T>
 hipError_t launch_probe_flush(const StepParams<T>& p, hipStream_t s);
 hipError_t launch_tick(int* ctrl, int k, hipStream_t s);
+template <typename T>
+hipError_t launch_batch_step(const StepParams<T>* descs, const BatchRef* table, int nblocks,
+                             const int* ctrl, int step_off, size_t smem, hipStream_t s);
+template <typename T>
+hipError_t launch_batch_probe_flush(const StepParams<T>* descs, int ninst, const int* ctrl,
+                                    int step_off, hipStream_t s);
 
 }  // namespace fdtd

@@ -93,16 +93,15 @@ struct RowIn {
 };
 
 template <typename T>
-__device__ __forceinline__ RowIn<T> load_row(const T* hz, const T* ex, const T* ey,
-                                             const StepParams<T>& p, size_t o, bool ok, bool up,
-                                             size_t P) {
+__device__ __forceinline__ RowIn<T> load_row(const T* hz, const T* ex, const T* ey, const T* al,
+                                             const T* be, size_t o, bool ok, bool up, size_t P) {
   RowIn<T> r{T(0), T(0), T(0), T(0), T(0)};
   if (ok) {
     r.h = hz[o];
     r.ex1 = up ? ex[o + P] : T(0);
     r.ey0 = ey[o];
-    r.al = p.al[o];
-    r.be = p.be[o];
+    r.al = al[o];
+    r.be = be[o];
   }
   return r;
 }
@@ -129,6 +128,11 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
   const int nx = p.nx;
   const int ny = p.ny;
   const size_t P = (size_t)p.pitch;
+  // parameters in registers: p may live in global memory (batched launch),
+  // where the field stores below would otherwise force reloads
+  const T chdy = p.chdy, chdx = p.chdx, k2dy = p.k2dy, k2dx = p.k2dx;
+  const T* al = p.al;
+  const T* be = p.be;
   const bool in = i < nx;
   const bool has_left = (lane == 0) && (i >= 1);
   const bool has_right = (lane == kWave - 1) && (i + 1 < nx);
@@ -152,8 +156,8 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
   T exl_c = has_left ? ex[(size_t)js * P + i - 1] : T(0);
   T hn_prev = T(0), a_prev = T(0), b_prev = T(0);
   // software pipeline: row j+1 is requested before row j is computed
-  RowIn<T> nxt = load_row(hz, ex, ey, p, (size_t)js * P + i, in, js + 1 < ny, P);
-  RowIn<T> nxl = load_row(hz, ex, ey, p, (size_t)js * P + i - 1, has_left, js + 1 < ny, P);
+  RowIn<T> nxt = load_row(hz, ex, ey, al, be, (size_t)js * P + i, in, js + 1 < ny, P);
+  RowIn<T> nxl = load_row(hz, ex, ey, al, be, (size_t)js * P + i - 1, has_left, js + 1 < ny, P);
   T ey1_n = has_right ? ey[(size_t)js * P + i + 1] : T(0);
   for (int j = js; j < j1; ++j) {
     const size_t o = (size_t)j * P + i;
@@ -162,14 +166,14 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
     const T ey1_r = ey1_n;
     if (j + 1 < j1) {
       const bool up2 = (j + 2) < ny;
-      nxt = load_row(hz, ex, ey, p, o + P, in, up2, P);
-      nxl = load_row(hz, ex, ey, p, o + P - 1, has_left, up2, P);
+      nxt = load_row(hz, ex, ey, al, be, o + P, in, up2, P);
+      nxl = load_row(hz, ex, ey, al, be, o + P - 1, has_left, up2, P);
       ey1_n = has_right ? ey[o + P + 1] : T(0);
     }
     T ey1 = __shfl_down(cur.ey0, 1, kWave);
     if (lane == kWave - 1) ey1 = ey1_r;
     // eq. (5): Hz^{n+1/2}
-    T hn = hz_update(cur.h, ex_c, cur.ex1, cur.ey0, ey1, p.chdy, p.chdx);
+    T hn = hz_update(cur.h, ex_c, cur.ex1, cur.ey0, ey1, chdy, chdx);
     if (any_src) hn += src_sum(p, sinc, 0, i, j);
     if (!(cur.al > T(0))) hn = T(0);
     T hnl = __shfl_up(hn, 1, kWave);
@@ -180,7 +184,7 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
       all = cul.al;
       bel = cul.be;
       if (has_left) {
-        hnl = hz_update(cul.h, exl_c, cul.ex1, cul.ey0, cur.ey0, p.chdy, p.chdx);
+        hnl = hz_update(cul.h, exl_c, cul.ex1, cul.ey0, cur.ey0, chdy, chdx);
         if (any_src) hnl += src_sum(p, sinc, 0, i - 1, j);
         if (!(all > T(0))) hnl = T(0);
         exl_c = cul.ex1;
@@ -192,7 +196,7 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
       T exn = ex_c;
       if (j >= 1 && ax) {
         T ca, cb;
-        edge_coef(cur.al + a_prev, cur.be + b_prev, p.k2dy, ca, cb);
+        edge_coef(cur.al + a_prev, cur.be + b_prev, k2dy, ca, cb);
         exn = ca * ex_c + cb * (hn - hn_prev);
       }
       // Ey^{n+1}(i,j) between cells (i-1,j) and (i,j)
@@ -200,7 +204,7 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
       T eyn = cur.ey0;
       if (i >= 1 && ay) {
         T ca, cb;
-        edge_coef(cur.al + all, cur.be + bel, p.k2dx, ca, cb);
+        edge_coef(cur.al + all, cur.be + bel, k2dx, ca, cb);
         eyn = ca * cur.ey0 - cb * (hn - hnl);
       }
       if (any_src) {
@@ -411,6 +415,63 @@ __global__ void tick_kernel(int* ctrl, int k) {
   if (threadIdx.x == 0 && blockIdx.x == 0) ctrl[0] += k;
 }
 
+// Batched step: B independent problems advance one step in one launch.
+// Workgroup b takes table[b] = (instance, role, index) and runs the same
+// device code as step_kernel on that instance's parameter block, which
+// stays in global memory (read through the scalar cache).  Each instance
+// keeps its own tile height.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+batch_step_kernel(const StepParams<T>* __restrict__ descs, const BatchRef* __restrict__ table,
+                  const int* __restrict__ ctrl, int step_off) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BatchRef r = table[blockIdx.x];
+  if (r.kind == 3) return;
+  const StepParams<T>& p = descs[r.inst];
+  const int n = ctrl[0] + step_off;
+  if (r.kind == 0) {
+    const RowBlock rb = p.blocks[r.idx];
+    if constexpr (sizeof(T) == 4) {
+      if (rb.kind == 1) {
+        coupling_gemm(p, rb, n, reinterpret_cast<float*>(smem));
+        return;
+      }
+    }
+    coupling_rows(p, rb, n, reinterpret_cast<T*>(smem));
+    return;
+  }
+  if (r.kind == 1) {
+    switch (p.seg) {
+      case 8: stencil_tile<T, 8>(p, r.idx, n); break;
+      case 32: stencil_tile<T, 32>(p, r.idx, n); break;
+      default: stencil_tile<T, 16>(p, r.idx, n); break;
+    }
+    return;
+  }
+  record_probes(p, n - 1);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+batch_probe_kernel(const StepParams<T>* __restrict__ descs, const int* __restrict__ ctrl, int step_off) {
+  record_probes(descs[blockIdx.x], ctrl[0] + step_off - 1);
+}
+
+template <typename T>
+hipError_t launch_batch_step(const StepParams<T>* descs, const BatchRef* table, int nblocks,
+                             const int* ctrl, int step_off, size_t smem, hipStream_t s) {
+  hipLaunchKernelGGL((batch_step_kernel<T>), dim3(nblocks), dim3(kBlock), smem, s, descs, table,
+                     ctrl, step_off);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_probe_flush(const StepParams<T>* descs, int ninst, const int* ctrl,
+                                    int step_off, hipStream_t s) {
+  hipLaunchKernelGGL((batch_probe_kernel<T>), dim3(ninst), dim3(kBlock), 0, s, descs, ctrl, step_off);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_step(const StepParams<T>& p, int seg, size_t smem, hipStream_t s) {
   const dim3 g(p.ncoup_blocks + p.nst_blocks + 1), b(kBlock);
@@ -438,5 +499,13 @@ template hipError_t launch_step<float>(const StepParams<float>&, int, size_t, hi
 template hipError_t launch_step<double>(const StepParams<double>&, int, size_t, hipStream_t);
 template hipError_t launch_probe_flush<float>(const StepParams<float>&, hipStream_t);
 template hipError_t launch_probe_flush<double>(const StepParams<double>&, hipStream_t);
+template hipError_t launch_batch_step<float>(const StepParams<float>*, const BatchRef*, int, const int*,
+                                             int, size_t, hipStream_t);
+template hipError_t launch_batch_step<double>(const StepParams<double>*, const BatchRef*, int,
+                                              const int*, int, size_t, hipStream_t);
+template hipError_t launch_batch_probe_flush<float>(const StepParams<float>*, int, const int*, int,
+                                                    hipStream_t);
+template hipError_t launch_batch_probe_flush<double>(const StepParams<double>*, int, const int*, int,
+                                                     hipStream_t);
 
 }  // namespace fdtd

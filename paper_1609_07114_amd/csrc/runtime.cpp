@@ -38,10 +38,8 @@ int fdtd::fail(int code, const char* fmt, ...) {
   return code;
 }
 
-namespace {
-
 // Shape-level validation and workspace plan (no numerics).
-int plan(const fdtd_problem* p, Layout& L) {
+int fdtd::plan_problem(const fdtd_problem* p, Layout& L) {
   if (!p) return fail(FDTD_EINVAL, "null problem");
   const fdtd_grid& g = p->grid;
   if (g.nx < 2 || g.ny < 2) return fail(FDTD_EINVAL, "grid must be at least 2x2 (got %dx%d)", g.nx, g.ny);
@@ -166,6 +164,8 @@ int plan(const fdtd_problem* p, Layout& L) {
   L.total = o;
   return FDTD_OK;
 }
+
+namespace {
 
 template <typename T>
 int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsigned char>& inside) {
@@ -537,8 +537,10 @@ int validate_numbers(const fdtd_problem* p, const Layout& L, std::vector<unsigne
   return FDTD_OK;
 }
 
+}  // namespace
+
 // a stencil workgroup covers 64 columns x (4 waves x seg rows)
-void set_tiling(fdtd_rom_sim* s, int seg) {
+void fdtd::set_tiling(fdtd_rom_sim* s, int seg) {
   s->seg = seg;
   const int rows = (kBlock / kWave) * seg;
   const int tx = (s->nx + kWave - 1) / kWave;
@@ -547,7 +549,11 @@ void set_tiling(fdtd_rom_sim* s, int seg) {
   s->sp_d.nst_blocks = nst;
   s->sp_f.tiles_x = tx;
   s->sp_d.tiles_x = tx;
+  s->sp_f.seg = seg;
+  s->sp_d.seg = seg;
 }
+
+namespace {
 
 int ev_pair(fdtd_rom_sim* s, std::vector<std::pair<hipEvent_t, hipEvent_t>>& pool, size_t& used,
             hipEvent_t& a, hipEvent_t& b) {
@@ -686,7 +692,7 @@ int fdtd_rom_workspace_size(const fdtd_problem* prob, size_t* bytes) {
   if (!bytes) return fail(FDTD_EINVAL, "null output");
   try {
     Layout L;
-    const int rc = plan(prob, L);
+    const int rc = plan_problem(prob, L);
     if (rc != FDTD_OK) return rc;
     *bytes = L.total;
     return FDTD_OK;
@@ -701,7 +707,7 @@ int fdtd_rom_create(const fdtd_problem* prob, void* dev_workspace, size_t ws_byt
   *out = nullptr;
   try {
     Layout L;
-    int rc = plan(prob, L);
+    int rc = plan_problem(prob, L);
     if (rc != FDTD_OK) return rc;
     if (!dev_workspace) return fail(FDTD_EINVAL, "null workspace");
     if (((uintptr_t)dev_workspace) % 256) return fail(FDTD_EINVAL, "workspace must be 256-byte aligned");
@@ -822,7 +828,7 @@ int fdtd_rom_read_rom_state(const fdtd_rom_sim* sim, int32_t k, double* host_out
 int fdtd_rom_coupled_update(const fdtd_problem* prob, int32_t k, double* A, double* B, double* C) {
   try {
     Layout L;
-    int rc = plan(prob, L);
+    int rc = plan_problem(prob, L);
     if (rc != FDTD_OK) return rc;
     if (k < 0 || k >= prob->nroms) return fail(FDTD_EINVAL, "region index out of range");
     std::vector<unsigned char> inside;

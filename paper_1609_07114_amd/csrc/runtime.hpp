@@ -86,7 +86,13 @@ StepParams<T>& step_params(fdtd_rom_sim* s) {
   else return s->sp_d;
 }
 
+// Shape-level validation and device workspace plan of one problem.
+int plan_problem(const fdtd_problem* p, Layout& L);
+
 // Advance the simulation by nsteps (graph replays or plain launches).
 int run_steps_any(fdtd_rom_sim* s, int nsteps);
+
+// Rows per stencil wave: recompute the tile grid of the handle.
+void set_tiling(fdtd_rom_sim* s, int seg);
 
 }  // namespace fdtd

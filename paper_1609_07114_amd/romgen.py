@@ -31,3 +31,25 @@ def build_roms(prob, theta=0.99, clip=True, workers=None):
         with ThreadPoolExecutor(max_workers=workers) as ex:
             built = list(ex.map(one, jobs))
     return [built[i] for i in order]
+
+
+def build_roms_many(probs, theta=0.99, clip=True, workers=None):
+    """build_roms for a list of problems, every region of every problem in
+    one thread pool."""
+    jobs = []
+    for b, prob in enumerate(probs):
+        for spec in prob.roms:
+            jobs.append((prob, spec))
+
+    def one(job):
+        prob, spec = job
+        return capi.fdtd_rom_build(spec.ni, spec.nj, spec.r, prob.dx, prob.dy, prob.dt,
+                                   spec.eps_r, spec.sigma, spec.q, spec.f_max, theta, clip)
+    workers = workers or max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        built = list(ex.map(one, jobs))
+    out, k = [], 0
+    for prob in probs:
+        out.append(built[k:k + len(prob.roms)])
+        k += len(prob.roms)
+    return out
