@@ -10,6 +10,14 @@ library's host FP64 builder (setup, not timed).
 
 Prints one JSON line (metric, value in Mcell-updates/s, roofline of the
 stencil kernel from HIP events, oracle CPU baseline on a bounded sample).
+Unless --no-forms, the line also carries the two other forms against the
+plain solver on the same GPU:
+  * "batched": the 64-instance workload (grids in [256,1024]^2, 1-8 models
+    each, FP32) in one launch per step with autotuned tiles, against the
+    same instances run one after another by single-problem handles;
+  * "adjoint": the 1024^2 probe-energy gradient (4 models q=64, 4000 steps,
+    checkpoints every 200) against the forward run alone, and the FP32
+    gradient's relative L2 distance to the FP64 run's.
 """
 from __future__ import annotations
 
@@ -96,6 +104,90 @@ def cpu_baseline(prob, nsteps):
             "seconds": dt}
 
 
+def _timed(stream, fn):
+    """Wall time and event time (ms) of fn() on `stream`, synchronised."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, e0.elapsed_time(e1)
+
+
+def bench_batched(steps=300, warmup=30, log=None):
+    import numpy as np
+    import workloads as W
+    from paper_1609_07114_amd import autotune, romgen
+    from paper_1609_07114_amd.batch import Batch
+    from paper_1609_07114_amd.sim import Simulation
+    probs = W.batch_c4(nsteps=max(3000, steps + warmup))
+    t0 = time.perf_counter()
+    roms = romgen.build_roms_many(probs)
+    t_build = time.perf_counter() - t0
+    cells = sum(p.nx * p.ny for p in probs)
+    choice = autotune.tune(probs, roms, log=log)
+    with Batch(probs, roms, max_steps=steps + warmup) as bt:
+        autotune.apply(bt, choice)
+        bt.set_graph(min(steps, 100))
+        bt.run(warmup)
+        t_b, _ = _timed(bt.stream, lambda: bt.run(steps))
+        pb = [bt.probes(b) for b in range(len(probs))]
+    sims = [Simulation(p, r, max_steps=steps + warmup) for p, r in zip(probs, roms)]
+    for s in sims:
+        s.set_graph(min(steps, 100))
+        s.run(warmup)
+    t_p, _ = _timed(sims[0].stream, lambda: [s.run(steps) for s in sims])
+    err = 0.0
+    for s, a in zip(sims, pb):
+        b = s.probes()
+        d = np.linalg.norm(a - b)
+        err = max(err, d / max(np.linalg.norm(b), 1e-300))
+        s.close()
+    rate_b = cells * steps / t_b / 1e6
+    rate_p = cells * steps / t_p / 1e6
+    return {"workload": f"{len(probs)} instances, grids in [256,1024]^2 ({cells / 1e6:.1f} M cells "
+                        f"per step), {sum(len(p.roms) for p in probs)} models of orders 16-96, FP32",
+            "steps": steps, "value": round(rate_b, 1), "unit": "Mcell-updates/s",
+            "plain_sequential": round(rate_p, 1), "speedup": round(rate_b / rate_p, 3),
+            "ms_per_step": round(t_b * 1e3 / steps, 4),
+            "tiles": choice, "max_rel_l2_vs_plain": err, "model_build_s": round(t_build, 2)}
+
+
+def bench_adjoint(ckpt=200, log=None):
+    import numpy as np
+    import workloads as W
+    from paper_1609_07114_amd import romgen
+    from paper_1609_07114_amd.sim import Simulation
+    prob = W.adjoint_c5()
+    roms = romgen.build_roms(prob)
+    n = prob.nsteps
+    with Simulation(prob, roms) as s:
+        s.set_graph(100)
+        t_f, _ = _timed(s.stream, lambda: s.run(n))
+    with Simulation(prob, roms) as s:      # untimed pass: graph capture, allocator
+        s.set_graph(100)
+        s.adjoint(n, ckpt_every=ckpt)
+    with Simulation(prob, roms) as s:
+        s.set_graph(100)
+        res = {}
+        t_a, _ = _timed(s.stream, lambda: res.setdefault("r", s.adjoint(n, ckpt_every=ckpt)))
+        J32, ge32, gs32 = res["r"]
+    with Simulation(prob, roms, dtype="f64") as s:
+        J64, ge64, gs64 = s.adjoint(n, ckpt_every=ckpt)
+    cells = prob.nx * prob.ny
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    return {"workload": f"{prob.nx}x{prob.ny}, 4 models q=64, {n} steps, checkpoint every {ckpt}, FP32",
+            "forward_s": round(t_f, 4), "adjoint_s": round(t_a, 4),
+            "ratio_vs_forward": round(t_a / t_f, 2),
+            "value": round(cells * n / t_a / 1e6, 1), "unit": "Mcell-updates/s (forward+reverse)",
+            "J_rel_err_vs_f64": abs(J32 - J64) / abs(J64),
+            "grad_eps_rel_l2_vs_f64": rel(ge32, ge64), "grad_sigma_rel_l2_vs_f64": rel(gs32, gs64)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +196,7 @@ def main():
     ap.add_argument("--n", type=int, default=2048, help="grid size (default: the 2048^2 workload)")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and adjoint forms")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -181,6 +274,12 @@ def main():
         "finite": finite,
     }
     print(f"bench: GPU {value:.0f} Mcell-updates/s, {ms_step:.4f} ms/step", file=sys.stderr, flush=True)
+    if not args.no_forms:
+        log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
+        out["batched"] = bench_batched(log=log)
+        log(f"batched {out['batched']['value']:.0f} vs plain {out['batched']['plain_sequential']:.0f} Mcell/s")
+        out["adjoint"] = bench_adjoint(log=log)
+        log(f"adjoint {out['adjoint']['ratio_vs_forward']}x forward")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     else:

@@ -155,6 +155,34 @@ int fdtd_rom_read_field(const fdtd_rom_sim* sim, int32_t comp, double* host_out)
 /* Reduced state x~ of region k into host [q].  Synchronises. */
 int fdtd_rom_read_rom_state(const fdtd_rom_sim* sim, int32_t k, double* host_out);
 
+/* Discrete energy of the current state (E^n, Hz^{n-1/2}, x~^n): the storage
+ * function of Theorem 2 (appendix), x^T R x with R the coarse analog of
+ * eq. (7)'s R plus every model's x~^T R~ x~:
+ *   sum over stored E edges of (eps/dt) * (dual area) * E^2, where the dual
+ *     area is dx*dy for an edge between two coarse cells and the outer half
+ *     cell dx*dy/2 for an interface edge (eq. (13));
+ *   + sum over coarse cells of (mu0/dt) * dx*dy * Hz^2;
+ *   - E^T K Hz over those edges (K the coarse curl of eq. (7), lengths dx
+ *     for Ex and dy for Ey);
+ *   + sum over models of x~^T R~ x~.
+ * Constant for lossless runs without sources and non-increasing with loss
+ * (Theorem 2).  Coarse part reduced on the device in FP64, models on the
+ * host.  Synchronises; FDTD_EUNSTABLE if non-finite. */
+int fdtd_rom_energy(const fdtd_rom_sim* sim, double* e);
+
+/* Checkpoint / resume.  state_size: bytes of a state blob (a 256-byte
+ * header with the step count and shape, the current field set in device
+ * layout, every model's reduced state).  get_state copies the handle's
+ * current state into dev_dst (device memory, 256-B aligned, caller-owned);
+ * set_state makes a blob from a handle of the same problem shape the current
+ * state, including its step count (FDTD_EINVAL on a shape or dtype mismatch
+ * or a step count beyond max_steps).  Probe rows already recorded are kept;
+ * rows from the restored step on are overwritten by the next run.  Both
+ * synchronise. */
+int fdtd_rom_state_size(const fdtd_rom_sim* sim, size_t* bytes);
+int fdtd_rom_get_state(const fdtd_rom_sim* sim, void* dev_dst);
+int fdtd_rom_set_state(fdtd_rom_sim* sim, const void* dev_src);
+
 /* Host-only (no device call): validate prob like fdtd_rom_create and
  * return, for region k, the FP64 closed-form matrices of eq. (23) that
  * create folds from eqs. (13)-(22):

@@ -93,6 +93,10 @@ _SIGS = {
                                                   C.POINTER(C.c_size_t)]),
     "fdtd_rom_adjoint": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                    C.c_size_t, _dp, _dp, _dp]),
+    "fdtd_rom_energy": (C.c_int, [C.c_void_p, _dp]),
+    "fdtd_rom_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "fdtd_rom_get_state": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "fdtd_rom_set_state": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fdtd_rom_batch_workspace_size": (C.c_int, [C.POINTER(fdtd_problem), C.c_int32,
                                                 C.POINTER(C.c_size_t)]),
     "fdtd_rom_batch_create": (C.c_int, [C.POINTER(fdtd_problem), C.c_int32, C.c_void_p, C.c_size_t,
@@ -315,6 +319,26 @@ def fdtd_rom_adjoint(h, nsteps: int, ckpt_every: int, probe: int, dev_ptr: int, 
     _check(lib().fdtd_rom_adjoint(h, int(nsteps), int(ckpt_every), int(probe), C.c_void_p(dev_ptr),
                                   nbytes, C.byref(J), _ptr(ge), _ptr(gs)))
     return float(J.value), ge, gs
+
+
+def fdtd_rom_energy(h) -> float:
+    e = C.c_double(0)
+    _check(lib().fdtd_rom_energy(h, C.byref(e)))
+    return float(e.value)
+
+
+def fdtd_rom_state_size(h) -> int:
+    n = C.c_size_t(0)
+    _check(lib().fdtd_rom_state_size(h, C.byref(n)))
+    return int(n.value)
+
+
+def fdtd_rom_get_state(h, dev_ptr: int):
+    _check(lib().fdtd_rom_get_state(h, C.c_void_p(dev_ptr)))
+
+
+def fdtd_rom_set_state(h, dev_ptr: int):
+    _check(lib().fdtd_rom_set_state(h, C.c_void_p(dev_ptr)))
 
 
 def _problem_array(problems):

@@ -113,6 +113,12 @@ template <typename T>
 hipError_t launch_probe_flush(const StepParams<T>& p, hipStream_t s);
 hipError_t launch_tick(int* ctrl, int k, hipStream_t s);
 template <typename T>
+hipError_t launch_energy(const T* hz, const T* ex, const T* ey, const T* al, int nx, int ny, int pitch,
+                         double ch, double half_area, double dx, double dy, double* part, hipStream_t s);
+inline int energy_blocks(int nx, int ny) {
+  return ((nx + kWave - 1) / kWave) * ((ny + kBlock / kWave - 1) / (kBlock / kWave));
+}
+template <typename T>
 hipError_t launch_batch_step(const StepParams<T>* descs, const BatchRef* table, int nblocks,
                              const int* ctrl, int step_off, size_t smem, hipStream_t s);
 template <typename T>

@@ -472,6 +472,70 @@ hipError_t launch_batch_probe_flush(const StepParams<T>* descs, int ninst, const
   return hipGetLastError();
 }
 
+// Coarse part of the discrete energy x^T R x of the leap-frog state
+// (E^n, Hz^{n-1/2}) (Theorem 2's storage function on the coarse grid): per
+// cell its Hz term mu0 dx dy/dt Hz^2 and, for the south Ex and west Ey it
+// owns, eps/dt times the edge's dual area (the two half cells that are not
+// inside a region; an interface edge keeps its outer half cell, eq. (13))
+// times E^2, minus E times the edge's row of K applied to Hz.  One FP64
+// partial sum per workgroup.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+energy_kernel(const T* __restrict__ hz, const T* __restrict__ ex, const T* __restrict__ ey,
+              const T* __restrict__ al, int nx, int ny, int pitch, double ch, double half_area,
+              double dx, double dy, double* __restrict__ part) {
+  __shared__ double red[kBlock / kWave];
+  const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+  const int j = blockIdx.y * (kBlock / kWave) + threadIdx.x / kWave;
+  double e = 0.0;
+  if (i < nx && j < ny) {
+    const size_t o = (size_t)j * pitch + i;
+    const double a = (double)al[o];
+    const double h = a > 0 ? (double)hz[o] : 0.0;
+    e += ch * h * h;
+    if (j >= 1) {
+      const double a2 = (double)al[o - pitch];
+      const double w = (a > 0 ? a : 0.0) + (a2 > 0 ? a2 : 0.0);
+      if (w > 0) {
+        const double h2 = a2 > 0 ? (double)hz[o - pitch] : 0.0;
+        const double E = (double)ex[o];
+        e += half_area * w * E * E - E * dx * (h - h2);
+      }
+    }
+    if (i >= 1) {
+      const double a2 = (double)al[o - 1];
+      const double w = (a > 0 ? a : 0.0) + (a2 > 0 ? a2 : 0.0);
+      if (w > 0) {
+        const double h2 = a2 > 0 ? (double)hz[o - 1] : 0.0;
+        const double E = (double)ey[o];
+        e += half_area * w * E * E - E * dy * (h2 - h);
+      }
+    }
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) e += __shfl_xor(e, off, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
+    part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+template <typename T>
+hipError_t launch_energy(const T* hz, const T* ex, const T* ey, const T* al, int nx, int ny, int pitch,
+                         double ch, double half_area, double dx, double dy, double* part, hipStream_t s) {
+  const dim3 g((nx + kWave - 1) / kWave, (ny + kBlock / kWave - 1) / (kBlock / kWave));
+  hipLaunchKernelGGL((energy_kernel<T>), g, dim3(kBlock), 0, s, hz, ex, ey, al, nx, ny, pitch, ch,
+                     half_area, dx, dy, part);
+  return hipGetLastError();
+}
+
+template hipError_t launch_energy<float>(const float*, const float*, const float*, const float*, int, int,
+                                         int, double, double, double, double, double*, hipStream_t);
+template hipError_t launch_energy<double>(const double*, const double*, const double*, const double*, int,
+                                          int, int, double, double, double, double, double*, hipStream_t);
+
 template <typename T>
 hipError_t launch_step(const StepParams<T>& p, int seg, size_t smem, hipStream_t s) {
   const dim3 g(p.ncoup_blocks + p.nst_blocks + 1), b(kBlock);

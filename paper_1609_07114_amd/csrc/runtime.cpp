@@ -161,6 +161,8 @@ int fdtd::plan_problem(const fdtd_problem* p, Layout& L) {
   o = align_up(o + L.xs_elems * ts, 256);
   L.off_idx = o;
   o = align_up(o + L.idx_elems * sizeof(int), 256);
+  L.off_energy = o;
+  o = align_up(o + (size_t)energy_blocks(g.nx, g.ny) * sizeof(double), 256);
   L.total = o;
   return FDTD_OK;
 }
@@ -442,7 +444,7 @@ int coupling_precompute(const fdtd_problem* p, std::vector<RomHost>& out) {
     }
     for (int c = 0; c < np; ++c)
       for (int a = 0; a < q; ++a) h.C[(size_t)c * q + a] = r.Lt[(size_t)a * np + c];
-    (void)cm;
+    h.R.assign(r.Rt, r.Rt + (size_t)q * q);
   }
   return FDTD_OK;
 }
@@ -845,6 +847,113 @@ int fdtd_rom_coupled_update(const fdtd_problem* prob, int32_t k, double* A, doub
   } catch (const std::bad_alloc&) {
     return fail(FDTD_ENOMEM, "host allocation failed");
   }
+}
+
+int fdtd_rom_energy(const fdtd_rom_sim* sim, double* e) {
+  if (!sim || !e) return fail(FDTD_EINVAL, "null argument");
+  try {
+    const Layout& L = sim->L;
+    const size_t ts = L.tsize, fe = L.field_elems;
+    const char* set = sim->ws + L.off_fields + (size_t)(sim->steps & 1) * 3 * fe * ts;
+    double* part = (double*)(sim->ws + L.off_energy);
+    const double ch = kMu0 * sim->dx * sim->dy / sim->dt;
+    const double ha = 0.5 * sim->dx * sim->dy;
+    hipError_t err;
+    if (ts == 4)
+      err = launch_energy<float>((const float*)set, (const float*)set + fe, (const float*)set + 2 * fe,
+                                 (const float*)(sim->ws + L.off_al), sim->nx, sim->ny, sim->pitch, ch, ha,
+                                 sim->dx, sim->dy, part, sim->stream);
+    else
+      err = launch_energy<double>((const double*)set, (const double*)set + fe, (const double*)set + 2 * fe,
+                                  (const double*)(sim->ws + L.off_al), sim->nx, sim->ny, sim->pitch, ch, ha,
+                                  sim->dx, sim->dy, part, sim->stream);
+    if (err != hipSuccess) return fail(FDTD_EDEVICE, "energy launch failed: %s", hipGetErrorString(err));
+    const int nb = energy_blocks(sim->nx, sim->ny);
+    std::vector<double> h(nb);
+    if (hipMemcpyAsync(h.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, sim->stream) != hipSuccess ||
+        hipStreamSynchronize(sim->stream) != hipSuccess)
+      return fail(FDTD_EDEVICE, "energy read failed");
+    double tot = 0;
+    for (double v : h) tot += v;
+    // reduced models: x~^T R~ x~
+    for (int k = 0; k < sim->nroms; ++k) {
+      const RomHost& r = sim->roms[k];
+      std::vector<double> x(r.q);
+      const int rc = fdtd_rom_read_rom_state(sim, k, x.data());
+      if (rc != FDTD_OK) return rc;
+      for (int a = 0; a < r.q; ++a) {
+        double row = 0;
+        for (int b = 0; b < r.q; ++b) row += r.R[(size_t)a * r.q + b] * x[b];
+        tot += x[a] * row;
+      }
+    }
+    *e = tot;
+    if (!std::isfinite(tot)) return fail(FDTD_EUNSTABLE, "non-finite energy");
+    return FDTD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(FDTD_ENOMEM, "host allocation failed");
+  }
+}
+
+namespace {
+constexpr int32_t kStateMagic = 0x46445453;  // state blob tag
+constexpr size_t kStateHeader = 256;
+struct StateHeader {
+  int32_t magic, dtype, steps, nx, ny, pitch;
+  int64_t field_elems, xs_elems;
+};
+size_t state_bytes(const fdtd_rom_sim* s) {
+  return kStateHeader + align_up(3 * s->L.field_elems * s->L.tsize, 256) + s->L.xs_elems * s->L.tsize;
+}
+}  // namespace
+
+int fdtd_rom_state_size(const fdtd_rom_sim* sim, size_t* bytes) {
+  if (!sim || !bytes) return fail(FDTD_EINVAL, "null argument");
+  *bytes = state_bytes(sim);
+  return FDTD_OK;
+}
+
+int fdtd_rom_get_state(const fdtd_rom_sim* sim, void* dev_dst) {
+  if (!sim || !dev_dst) return fail(FDTD_EINVAL, "null argument");
+  const Layout& L = sim->L;
+  const size_t set_bytes = 3 * L.field_elems * L.tsize;
+  StateHeader h{kStateMagic, sim->dtype, sim->steps, sim->nx, sim->ny, sim->pitch, (int64_t)L.field_elems,
+                (int64_t)L.xs_elems};
+  char* d = (char*)dev_dst;
+  if (hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, sim->stream) != hipSuccess ||
+      hipMemcpyAsync(d + kStateHeader, sim->ws + L.off_fields + (size_t)(sim->steps & 1) * set_bytes, set_bytes,
+                     hipMemcpyDeviceToDevice, sim->stream) != hipSuccess ||
+      (L.xs_elems > 0 && hipMemcpyAsync(d + kStateHeader + align_up(set_bytes, 256), sim->ws + L.off_xs,
+                                        L.xs_elems * L.tsize, hipMemcpyDeviceToDevice, sim->stream) != hipSuccess) ||
+      hipStreamSynchronize(sim->stream) != hipSuccess)
+    return fail(FDTD_EDEVICE, "state copy failed");
+  return FDTD_OK;
+}
+
+int fdtd_rom_set_state(fdtd_rom_sim* sim, const void* dev_src) {
+  if (!sim || !dev_src) return fail(FDTD_EINVAL, "null argument");
+  const Layout& L = sim->L;
+  const size_t set_bytes = 3 * L.field_elems * L.tsize;
+  StateHeader h{};
+  const char* d = (const char*)dev_src;
+  if (hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, sim->stream) != hipSuccess ||
+      hipStreamSynchronize(sim->stream) != hipSuccess)
+    return fail(FDTD_EDEVICE, "state header read failed");
+  if (h.magic != kStateMagic || h.dtype != sim->dtype || h.nx != sim->nx || h.ny != sim->ny ||
+      h.pitch != sim->pitch || h.field_elems != (int64_t)L.field_elems || h.xs_elems != (int64_t)L.xs_elems)
+    return fail(FDTD_EINVAL, "state blob does not belong to a handle of this problem shape");
+  if (h.steps < 0 || h.steps > sim->max_steps)
+    return fail(FDTD_EINVAL, "state at step %d outside [0, max_steps=%d]", h.steps, sim->max_steps);
+  int ctrl[kCtrlInts] = {h.steps, 0, 0, 0};
+  if (hipMemcpyAsync(sim->ws + L.off_fields + (size_t)(h.steps & 1) * set_bytes, d + kStateHeader, set_bytes,
+                     hipMemcpyDeviceToDevice, sim->stream) != hipSuccess ||
+      (L.xs_elems > 0 && hipMemcpyAsync(sim->ws + L.off_xs, d + kStateHeader + align_up(set_bytes, 256),
+                                        L.xs_elems * L.tsize, hipMemcpyDeviceToDevice, sim->stream) != hipSuccess) ||
+      hipMemcpyAsync(sim->ws + L.off_ctrl, ctrl, sizeof(ctrl), hipMemcpyHostToDevice, sim->stream) != hipSuccess ||
+      hipStreamSynchronize(sim->stream) != hipSuccess)
+    return fail(FDTD_EDEVICE, "state copy failed");
+  sim->steps = h.steps;
+  return FDTD_OK;
 }
 
 int fdtd_rom_profile_enable(fdtd_rom_sim* sim, int32_t enable) {

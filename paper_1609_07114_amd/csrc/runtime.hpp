@@ -26,7 +26,7 @@ struct Layout {
   size_t field_elems = 0;
   size_t off_ctrl = 0, off_fields = 0, off_al = 0, off_be = 0, off_src = 0;
   size_t off_pbuf = 0, off_poff = 0, off_pcomp = 0, off_roms = 0, off_mats = 0;
-  size_t off_xs = 0, off_idx = 0, total = 0;
+  size_t off_xs = 0, off_idx = 0, off_energy = 0, total = 0;
   size_t mats_elems = 0, xs_elems = 0, idx_elems = 0;
   int nrowblocks = 0;        // all-GEMV coupling list
   int nblocks_mixed = 0;     // GEMM for eligible shared groups + GEMV for the rest
@@ -48,6 +48,7 @@ inline int ports_of(const fdtd_rom& r) { return 2 * (r.ni + r.nj); }
 struct RomHost {
   int i0, j0, ni, nj, q, np, slot;
   std::vector<double> A, B, C;  // closed form, row-major
+  std::vector<double> R;        // R~ (energy diagnostic)
 };
 
 }  // namespace fdtd

@@ -46,6 +46,24 @@ class Simulation:
     def rom_state(self, k):
         return capi.fdtd_rom_read_rom_state(self.h, k, self.q[k])
 
+    def energy(self):
+        """Discrete energy of the current state (Theorem 2 storage function)."""
+        return capi.fdtd_rom_energy(self.h)
+
+    def get_state(self):
+        """Device tensor (uint8) holding the current state."""
+        n = capi.fdtd_rom_state_size(self.h)
+        buf = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        capi.fdtd_rom_get_state(self.h, buf.data_ptr())
+        return buf
+
+    def set_state(self, buf):
+        if buf.device != self.device or buf.dtype != self.torch.uint8:
+            raise ValueError("state must be a uint8 tensor on the simulation's device")
+        if buf.numel() < capi.fdtd_rom_state_size(self.h):
+            raise ValueError("state tensor too small")
+        capi.fdtd_rom_set_state(self.h, buf.data_ptr())
+
     def coupled_update(self, k):
         return capi.fdtd_rom_coupled_update(self.ps, k)
 
