@@ -15,6 +15,9 @@ plain solver on the same GPU:
   * "batched": the 64-instance workload (grids in [256,1024]^2, 1-8 models
     each, FP32) in one launch per step with autotuned tiles, against the
     same instances run one after another by single-problem handles;
+  * "many_copies": 4096^2 vacuum with 256 copies of one order-128 model,
+    eq. (23) for all copies as one FP32 MFMA GEMM per step, against the
+    same run with a GEMV per copy;
   * "adjoint": the 1024^2 probe-energy gradient (4 models q=64, 4000 steps,
     checkpoints every 200) against the forward run alone, and the FP32
     gradient's relative L2 distance to the FP64 run's.
@@ -157,6 +160,41 @@ def bench_batched(steps=300, warmup=30, log=None):
             "tiles": choice, "max_rel_l2_vs_plain": err, "model_build_s": round(t_build, 2)}
 
 
+PEAK_MFMA_F32_TFLOPS = 157.3
+
+
+def bench_many_copies(steps=500, warmup=50, log=None):
+    import numpy as np
+    import workloads as W
+    from paper_1609_07114_amd import romgen
+    from paper_1609_07114_amd.sim import Simulation
+    prob = W.many_copies(nsteps=steps + warmup)
+    roms = romgen.build_roms(prob)
+    cells = prob.nx * prob.ny
+    res = {}
+    for mode in ("gemm", "gemv"):
+        with Simulation(prob, roms) as s:
+            s.set_shared_gemm(mode == "gemm")
+            s.set_graph(100)
+            s.run(warmup)
+            t, ev = _timed(s.stream, lambda: s.run(steps))
+            res[mode] = (t, ev, s.probes())
+    q = prob.roms[0].q
+    m = -(-(q + prob.roms[0].n_ports) // 64) * 64          # padded rows of the update matrix
+    flops = 2.0 * m * m * len(prob.roms)                   # one GEMM (m x m) . (m x copies) per step
+    t_g = res["gemm"][1] / 1e3 / steps
+    pg, pv = res["gemm"][2], res["gemv"][2]
+    return {"workload": f"{prob.nx}x{prob.ny} vacuum, {len(prob.roms)} copies of one model "
+                        f"q={q} (np={prob.roms[0].n_ports}), FP32, {steps} steps",
+            "value": round(cells * steps / res["gemm"][0] / 1e6, 1), "unit": "Mcell-updates/s",
+            "gemv_per_copy": round(cells * steps / res["gemv"][0] / 1e6, 1),
+            "ms_per_step": round(res["gemm"][0] * 1e3 / steps, 4),
+            "gemm_flop_per_step": flops,
+            "gemm_tflops_over_step": round(flops / t_g / 1e12, 3),
+            "mfma_frac_of_fp32_peak_over_step": round(flops / t_g / 1e12 / PEAK_MFMA_F32_TFLOPS, 5),
+            "rel_l2_gemm_vs_gemv": float(np.linalg.norm(pg - pv) / max(np.linalg.norm(pv), 1e-300))}
+
+
 def bench_adjoint(ckpt=200, log=None):
     import numpy as np
     import workloads as W
@@ -196,7 +234,10 @@ def main():
     ap.add_argument("--n", type=int, default=2048, help="grid size (default: the 2048^2 workload)")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-forms", action="store_true", help="skip the batched and adjoint forms")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched, many-copies and adjoint forms")
+    ap.add_argument("--only", choices=["batched", "many_copies", "adjoint"], default=None,
+                    help="run one form alone and print its JSON (profiling)")
+    ap.add_argument("--form-steps", type=int, default=None, help="timed steps of the batched / many-copies form")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -213,6 +254,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no ROCm GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.only:
+        log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
+        kw = {} if args.form_steps is None or args.only == "adjoint" else {"steps": args.form_steps}
+        fn = {"batched": bench_batched, "many_copies": bench_many_copies, "adjoint": bench_adjoint}[args.only]
+        print(json.dumps({args.only: fn(log=log, **kw)}), flush=True)
+        return
     total = args.warmup + args.steps
     prob = W.random_media(n=args.n, nsteps=total)
     t0 = time.perf_counter()
@@ -278,6 +325,8 @@ def main():
         log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
         out["batched"] = bench_batched(log=log)
         log(f"batched {out['batched']['value']:.0f} vs plain {out['batched']['plain_sequential']:.0f} Mcell/s")
+        out["many_copies"] = bench_many_copies(log=log)
+        log(f"many copies {out['many_copies']['value']:.0f} Mcell/s (GEMV {out['many_copies']['gemv_per_copy']:.0f})")
         out["adjoint"] = bench_adjoint(log=log)
         log(f"adjoint {out['adjoint']['ratio_vs_forward']}x forward")
     if not args.no_cpu_baseline:

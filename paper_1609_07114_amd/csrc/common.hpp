@@ -45,12 +45,14 @@ struct RomDev {
 constexpr int kRowsPerWave = 4;
 constexpr int kRowsPerBlock = kRowsPerWave * (kBlock / kWave);
 constexpr int kGemmCopies = 16;    // copies (columns) per shared-model GEMM block
+constexpr int kGemmRowsPerBlock = 64;  // output rows per GEMM block: one 16-row MFMA tile per wave
 constexpr int kMaxGemmM = 512;     // q + np handled by the GEMM blocks
 constexpr int kMinGemmCopies = 8;  // shared groups at least this large use the GEMM
 
 // One coupling workgroup.  kind 0: rows [row0, row0 + kRowsPerBlock) of
 // region `a`'s update matrix (GEMV).  kind 1: FP32 MFMA GEMM of one shared
-// model for up to kGemmCopies regions listed at copies[b .. b + c).
+// model for up to kGemmCopies regions listed at copies[b .. b + c), output
+// 16-row tiles a .. a+3 (one per wave).
 struct RowBlock {
   int kind;
   int a;

@@ -300,57 +300,65 @@ __device__ void coupling_rows(const StepParams<T>& p, const RowBlock& rb, int n,
 // Shared model, many copies: Out (M x copies) = G (M x M) * Z (M x copies)
 // with Z's column c = [x~_c^n; h_c^{n+1/2}] of region copies[b + c], as FP32
 // MFMA 16x16x4 tiles.  Z is staged in LDS ([k][copy], 16 copies per row);
-// each wave takes every fourth 16-row tile of the output and walks K in
-// steps of 4.  Operand layout of v_mfma_f32_16x16x4f32 (wave64): lane l holds
-// A(l % 16, l / 16) and B(l / 16, l % 16); the result register i of lane l is
-// D(4 * (l / 16) + i, l % 16).
+// a workgroup produces 64 output rows, each wave one 16-row tile, walking K
+// in steps of 4 (short blocks: their chains of dependent loads run while
+// the stencil tiles keep HBM busy).  Operand layout of v_mfma_f32_16x16x4f32
+// (wave64): lane l holds A(l % 16, l / 16) and B(l / 16, l % 16); the
+// result register i of lane l is D(4 * (l / 16) + i, l % 16).
 __device__ void coupling_gemm(const StepParams<float>& p, const RowBlock& gb, int n, float* zs) {
   const int par = n & 1;
   const int tid = threadIdx.x;
   const int ncp = gb.c;
   const int* list = p.copies + gb.b;
-  const RomDev r = p.roms[list[0]];
-  const int M = r.ldg;  // padded q + np (multiple of 64)
+  const int M = p.roms[list[0]].ldg;  // padded q + np (multiple of 64), same for every copy
+  const int64_t gt_off = p.roms[list[0]].gt_off;
   const float* hz = fld(p, par, 0);
   const float* ex = fld(p, par, 1);
   const float* ey = fld(p, par, 2);
-  for (int e = tid; e < M * kGemmCopies; e += kBlock) {
-    const int k = e / kGemmCopies;
-    const int c = e - k * kGemmCopies;
+  // Every thread owns one copy column c = tid % 16 for the whole block: its
+  // descriptor is loaded once, and c is also the result column this thread's
+  // lane holds after the MFMA loop (lane % 16), so the scatter reuses it.
+  const int c = tid & (kGemmCopies - 1);
+  const bool has = c < ncp;
+  RomDev rc{};
+  if (has) rc = p.roms[list[c]];
+  const float* xin = p.xs + rc.x_off + par * rc.xstride;
+  const int* gi = p.idx + rc.i_off;
+#pragma unroll 4
+  for (int k = tid / kGemmCopies; k < M; k += kBlock / kGemmCopies) {
     float v = 0.f;
-    if (c < ncp) {
-      const RomDev rc = p.roms[list[c]];
+    if (has) {
       if (k < rc.q)
-        v = p.xs[rc.x_off + par * rc.xstride + k];
+        v = xin[k];
       else if (k < rc.q + rc.np)
-        v = ring_h(p, hz, ex, ey, p.idx[rc.i_off + (k - rc.q)], n);
+        v = ring_h(p, hz, ex, ey, gi[k - rc.q], n);
     }
-    zs[e] = v;
+    zs[k * kGemmCopies + c] = v;
   }
   __syncthreads();
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
-  const int lr = lane & 15;  // A row / B column / D column within the tile
+  const int lr = lane & 15;  // A row / B column / D column within the tile (== c)
   const int lk = lane >> 4;  // A column / B row / D row group
-  const float* GT = p.mats + r.gt_off;
+  const float* GT = p.mats + gt_off;
   float* exo = fld(p, par ^ 1, 1);
   float* eyo = fld(p, par ^ 1, 2);
-  for (int rt = wv; rt < M / 16; rt += kBlock / kWave) {
+  float* xout = p.xs + rc.x_off + (par ^ 1) * rc.xstride;
+  const int* si = gi + rc.np;
+  const int rt = gb.a + wv;  // this wave's 16-row output tile
+  if (rt < M / 16) {
     const int row0 = rt * 16;
     typedef float f4 __attribute__((ext_vector_type(4)));
     f4 acc = {0.f, 0.f, 0.f, 0.f};
     const float* a_ptr = GT + (size_t)lk * M + row0 + lr;
     const float* b_ptr = zs + lk * kGemmCopies + lr;
-#pragma unroll 8
+#pragma unroll 16
     for (int k0 = 0; k0 < M; k0 += 4) {
       const float a = a_ptr[(size_t)k0 * M];
       const float b = b_ptr[k0 * kGemmCopies];
       acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
     }
-    if (lr < ncp) {
-      const RomDev rc = p.roms[list[lr]];
-      float* xout = p.xs + rc.x_off + (par ^ 1) * rc.xstride;
-      const int* si = p.idx + rc.i_off + rc.np;
+    if (has) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = row0 + 4 * lk + i;

@@ -126,7 +126,11 @@ int fdtd::plan_problem(const fdtd_problem* p, Layout& L) {
     }
   }
   for (size_t sl = 0; sl < L.slot_rep.size(); ++sl)
-    if (L.slot_gemm[sl]) L.nblocks_mixed += (L.slot_members[sl] + kGemmCopies - 1) / kGemmCopies;
+    if (L.slot_gemm[sl]) {
+      const fdtd_rom& r = p->roms[L.slot_rep[sl]];
+      const size_t ldg = align_up((size_t)r.q + ports_of(r), kWave);
+      L.nblocks_mixed += (int)(((L.slot_members[sl] + kGemmCopies - 1) / kGemmCopies) * (ldg / kGemmRowsPerBlock));
+    }
   L.xs_elems = xe;
   L.idx_elems = ie;
   size_t o = 0;
@@ -281,9 +285,12 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
     std::vector<int> members;
     for (int k = 0; k < p->nroms; ++k)
       if (L.slot_of_rom[k] == (int)sl) members.push_back(k);
+    const fdtd_rom& rr = p->roms[L.slot_rep[sl]];
+    const int ldg = (int)align_up((size_t)rr.q + ports_of(rr), kWave);
     for (size_t c0 = 0; c0 < members.size(); c0 += kGemmCopies) {
       const int cnt = (int)std::min<size_t>(kGemmCopies, members.size() - c0);
-      mixed.push_back(RowBlock{1, (int)sl, (int)copies.size(), cnt});
+      for (int row0 = 0; row0 < ldg; row0 += kGemmRowsPerBlock)
+        mixed.push_back(RowBlock{1, row0 / 16, (int)copies.size(), cnt});
       for (int c = 0; c < cnt; ++c) copies.push_back(members[c0 + c]);
     }
   }
