@@ -275,6 +275,7 @@ def main():
         torch.cuda.synchronize()
 
     sim = Simulation(prob, roms, max_steps=total)
+    seg = sim.get_tiling()
     sim.run(args.warmup)
     torch.cuda.synchronize()
     # timed region: K step launches on the simulation's stream, bracketed by
@@ -304,7 +305,7 @@ def main():
     achieved = alg_bytes / st_avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "step_kernel<float,16>", "bytes_per_launch": alg_bytes,
+                "kernel": f"step_kernel<float,{seg}>", "bytes_per_launch": alg_bytes,
                 "avg_launch_us": round(st_avg_s * 1e6, 3), "launches": args.steps}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mcell-updates/s", "n_gpus": 1,

@@ -250,11 +250,14 @@ int fdtd_rom_profile_read(fdtd_rom_sim* sim, double* step_ms, int64_t* step_laun
                           double* tail_ms, int64_t* tail_launches);
 
 /* Launch configuration.  set_tiling: rows each wave of a stencil tile
- * advances (8, 16 or 32; default 16).  set_graph: batch > 0 makes run()
+ * advances (4, 8, 16 or 32; the default depends on the grid: 16 for
+ * cache-resident grids with >= 4096 waves, else 8 for large grids, 4 for
+ * small ones).  set_graph: batch > 0 makes run()
  * replay a captured HIP graph of `batch` steps (capture happens on first use
  * on a library-owned stream, replay on the handle's stream; remainders and
  * profiled runs use direct launches); 0 (default) disables graphs. */
 int fdtd_rom_set_tiling(fdtd_rom_sim* sim, int32_t seg);
+int fdtd_rom_get_tiling(const fdtd_rom_sim* sim, int32_t* seg);
 
 /* Regions sharing one model (same group >= 0, FP32, at least 8 of them,
  * q + np <= 512) are advanced by one FP32 MFMA GEMM per step over all copies
@@ -309,7 +312,7 @@ int fdtd_rom_adjoint(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int3
  *     if any instance would exceed its max_steps.
  *   batch_read_probes / batch_read_field: as the single-problem calls, for
  *     instance b.  Synchronise.
- *   batch_set_tiling: rows per stencil wave (8, 16, 32) of instance b, or of
+ *   batch_set_tiling: rows per stencil wave (4, 8, 16, 32) of instance b, or of
  *     every instance for b = -1 (the autotuner's knob).
  *   batch_set_graph: steps per captured graph (0 = direct launches). */
 typedef struct fdtd_rom_batch fdtd_rom_batch; /* opaque, owned by the library */

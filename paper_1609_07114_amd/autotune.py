@@ -1,6 +1,6 @@
 """Tile autotuner for batched runs.
 
-The knob is the number of rows each stencil wave advances (8, 16 or 32):
+The knob is the number of rows each stencil wave advances (4, 8, 16 or 32):
 short segments give more workgroups (better for small grids), long ones
 recompute fewer halo rows.  In a batch the instances share the GPU, so the
 best height for one size class depends on the whole mix; the tuner times
@@ -16,7 +16,7 @@ from __future__ import annotations
 import json
 import os
 
-CANDIDATES = (8, 16, 32)
+CANDIDATES = (4, 8, 16, 32)
 # (name, upper bound on coarse cells)
 BUCKETS = (("s", 1 << 17), ("m", 1 << 19), ("l", 1 << 62))
 

@@ -88,6 +88,7 @@ _SIGS = {
                                         C.POINTER(C.c_int64)]),
     "fdtd_rom_set_tiling": (C.c_int, [C.c_void_p, C.c_int32]),
     "fdtd_rom_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_get_tiling": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "fdtd_rom_set_shared_gemm": (C.c_int, [C.c_void_p, C.c_int32]),
     "fdtd_rom_adjoint_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
                                                   C.POINTER(C.c_size_t)]),
@@ -294,6 +295,12 @@ def fdtd_rom_profile_read(h):
 
 def fdtd_rom_set_tiling(h, seg: int):
     _check(lib().fdtd_rom_set_tiling(h, int(seg)))
+
+
+def fdtd_rom_get_tiling(h) -> int:
+    n = C.c_int32(0)
+    _check(lib().fdtd_rom_get_tiling(h, C.byref(n)))
+    return int(n.value)
 
 
 def fdtd_rom_set_shared_gemm(h, enable: bool):

@@ -61,7 +61,7 @@ int plan_batch(const fdtd_problem* probs, int B, BatchPlan& P) {
     const int rc = plan_problem(&probs[b], L);
     if (rc != FDTD_OK) return fail(rc, "instance %d: %s", b, fdtd_rom_last_error());
     sizes[b] = L.total;
-    cap += (size_t)std::max(L.nrowblocks, L.nblocks_mixed) + (size_t)tiles_for(probs[b], 8) + 7 + 1;
+    cap += (size_t)std::max(L.nrowblocks, L.nblocks_mixed) + (size_t)tiles_for(probs[b], 4) + 7 + 1;
   }
   const size_t desc_bytes = (size_t)B * (dt == FDTD_F32 ? sizeof(StepParams<float>) : sizeof(StepParams<double>));
   size_t o = 0;
@@ -288,7 +288,7 @@ int fdtd_rom_batch_read_field(const fdtd_rom_batch* bt, int32_t b, int32_t comp,
 int fdtd_rom_batch_set_tiling(fdtd_rom_batch* bt, int32_t b, int32_t seg) {
   if (!bt) return fail(FDTD_EINVAL, "null handle");
   if (b < -1 || b >= bt->B) return fail(FDTD_EINVAL, "instance %d out of range", b);
-  if (seg != 8 && seg != 16 && seg != 32) return fail(FDTD_EINVAL, "segment rows must be 8, 16 or 32");
+  if (seg != 4 && seg != 8 && seg != 16 && seg != 32) return fail(FDTD_EINVAL, "segment rows must be 4, 8, 16 or 32");
   for (int k = 0; k < bt->B; ++k)
     if (b < 0 || k == b) set_tiling(bt->sims[k], seg);
   bt->dirty = true;

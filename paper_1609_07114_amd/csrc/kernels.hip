@@ -87,22 +87,37 @@ __device__ __forceinline__ T src_sum(const StepParams<T>& p, const T* sinc, int 
   return acc;
 }
 
+// Loads and stores at a 32-bit byte offset from a wave-uniform base: every
+// access of a row shares one vector offset (the base and the row step live
+// in scalar registers), so no 64-bit address arithmetic per access.  Field
+// arrays stay below 2 GiB (checked at create).
+template <typename T>
+__device__ __forceinline__ T ld(const T* base, uint32_t off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ void st(T* base, uint32_t off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
 template <typename T>
 struct RowIn {
   T h, ex1, ey0, al, be;
 };
 
+// One lane's column of row j: Hz, Ex(j+1) (zero above the top row: `up` is
+// wave-uniform), Ey, material.  Columns up to the 64-aligned pitch are
+// inside the arrays (padding reads zero, material zero = inactive).
 template <typename T>
-__device__ __forceinline__ RowIn<T> load_row(const T* hz, const T* ex, const T* ey, const T* al,
-                                             const T* be, size_t o, bool ok, bool up, size_t P) {
-  RowIn<T> r{T(0), T(0), T(0), T(0), T(0)};
-  if (ok) {
-    r.h = hz[o];
-    r.ex1 = up ? ex[o + P] : T(0);
-    r.ey0 = ey[o];
-    r.al = al[o];
-    r.be = be[o];
-  }
+__device__ __forceinline__ RowIn<T> load_row(const T* hz, const T* ex_up, const T* ey, const T* al,
+                                             const T* be, uint32_t ob, bool up) {
+  RowIn<T> r;
+  r.h = ld(hz, ob);
+  r.ex1 = T(0);
+  if (up) r.ex1 = ld(ex_up, ob);
+  r.ey0 = ld(ey, ob);
+  r.al = ld(al, ob);
+  r.be = ld(be, ob);
   return r;
 }
 
@@ -116,23 +131,27 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
   T* exo = fld(p, par ^ 1, 1);
   T* eyo = fld(p, par ^ 1, 2);
   const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
+  // wave index as a scalar: every row condition below is wave-uniform
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int tile = xcd_tile(t, p.nst_blocks);
   const int tx = tile % p.tiles_x;
   const int tyb = tile / p.tiles_x;
   const int iw = tx * kWave;
   const int i = iw + lane;
   const int j0 = (tyb * (kBlock / kWave) + wv) * SEG;
-  if (j0 >= p.ny) return;  // uniform over the wave
+  if (j0 >= p.ny) return;
   const int j1 = min(j0 + SEG, p.ny);
   const int nx = p.nx;
   const int ny = p.ny;
-  const size_t P = (size_t)p.pitch;
+  const int P = p.pitch;
+  constexpr uint32_t ts = sizeof(T);
+  const uint32_t row_b = (uint32_t)P * ts;
   // parameters in registers: p may live in global memory (batched launch),
   // where the field stores below would otherwise force reloads
   const T chdy = p.chdy, chdx = p.chdx, k2dy = p.k2dy, k2dx = p.k2dx;
   const T* al = p.al;
   const T* be = p.be;
+  const T* ex_up = ex + P;  // Ex of the row above, same offset
   const bool in = i < nx;
   const bool has_left = (lane == 0) && (i >= 1);
   const bool has_right = (lane == kWave - 1) && (i + 1 < nx);
@@ -152,23 +171,39 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
       if (s < p.nsrc) sinc[s] = p.src[s].incr[n];
   }
 
-  T ex_c = in ? ex[(size_t)js * P + i] : T(0);
-  T exl_c = has_left ? ex[(size_t)js * P + i - 1] : T(0);
+  uint32_t ob = ((uint32_t)js * (uint32_t)P + (uint32_t)i) * ts;
+  T ex_c = ld(ex, ob);
+  T exl_c = T(0);
+  if (has_left) exl_c = ld(ex, ob - ts);
   T hn_prev = T(0), a_prev = T(0), b_prev = T(0);
-  // software pipeline: row j+1 is requested before row j is computed
-  RowIn<T> nxt = load_row(hz, ex, ey, al, be, (size_t)js * P + i, in, js + 1 < ny, P);
-  RowIn<T> nxl = load_row(hz, ex, ey, al, be, (size_t)js * P + i - 1, has_left, js + 1 < ny, P);
-  T ey1_n = has_right ? ey[(size_t)js * P + i + 1] : T(0);
-  for (int j = js; j < j1; ++j) {
-    const size_t o = (size_t)j * P + i;
-    const RowIn<T> cur = nxt;
-    const RowIn<T> cul = nxl;
-    const T ey1_r = ey1_n;
-    if (j + 1 < j1) {
-      const bool up2 = (j + 2) < ny;
-      nxt = load_row(hz, ex, ey, al, be, o + P, in, up2, P);
-      nxl = load_row(hz, ex, ey, al, be, o + P - 1, has_left, up2, P);
-      ey1_n = has_right ? ey[o + P + 1] : T(0);
+  // software pipeline, two rows deep: rows j+1 and j+2 are in flight while
+  // row j is computed
+  RowIn<T> n1 = load_row(hz, ex_up, ey, al, be, ob, js + 1 < ny);
+  RowIn<T> l1{T(0), T(0), T(0), T(0), T(0)};
+  if (has_left) l1 = load_row(hz, ex_up, ey, al, be, ob - ts, js + 1 < ny);
+  T r1 = T(0);
+  if (has_right) r1 = ld(ey, ob + ts);
+  RowIn<T> n2{T(0), T(0), T(0), T(0), T(0)}, l2{T(0), T(0), T(0), T(0), T(0)};
+  T r2 = T(0);
+  if (js + 1 < j1) {
+    const uint32_t o2 = ob + row_b;
+    n2 = load_row(hz, ex_up, ey, al, be, o2, js + 2 < ny);
+    if (has_left) l2 = load_row(hz, ex_up, ey, al, be, o2 - ts, js + 2 < ny);
+    if (has_right) r2 = ld(ey, o2 + ts);
+  }
+  for (int j = js; j < j1; ++j, ob += row_b) {
+    const RowIn<T> cur = n1;
+    const RowIn<T> cul = l1;
+    const T ey1_r = r1;
+    n1 = n2;
+    l1 = l2;
+    r1 = r2;
+    if (j + 2 < j1) {
+      const uint32_t o3 = ob + 2 * row_b;
+      const bool up3 = (j + 3) < ny;
+      n2 = load_row(hz, ex_up, ey, al, be, o3, up3);
+      if (has_left) l2 = load_row(hz, ex_up, ey, al, be, o3 - ts, up3);
+      if (has_right) r2 = ld(ey, o3 + ts);
     }
     T ey1 = __shfl_down(cur.ey0, 1, kWave);
     if (lane == kWave - 1) ey1 = ey1_r;
@@ -190,32 +225,31 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
         exl_c = cul.ex1;
       }
     }
-    if (j >= j0 && in) {
-      // eq. (3): Ex^{n+1}(i,j) between cells (i,j-1) and (i,j)
-      const bool ax = cur.al > T(0) && a_prev > T(0);
-      T exn = ex_c;
-      if (j >= 1 && ax) {
-        T ca, cb;
-        edge_coef(cur.al + a_prev, cur.be + b_prev, k2dy, ca, cb);
-        exn = ca * ex_c + cb * (hn - hn_prev);
-      }
+    if (j >= j0) {
+      // eq. (3), branch-free: both coefficients are formed on every lane and
+      // the update is selected (a division by a non-positive sum on an edge
+      // that is not updated is discarded)
+      // Ex^{n+1}(i,j) between cells (i,j-1) and (i,j)
+      const bool ax = j >= 1 && cur.al > T(0) && a_prev > T(0);
+      T cax, cbx;
+      edge_coef(cur.al + a_prev, cur.be + b_prev, k2dy, cax, cbx);
+      T exn = ax ? cax * ex_c + cbx * (hn - hn_prev) : ex_c;
       // Ey^{n+1}(i,j) between cells (i-1,j) and (i,j)
-      const bool ay = cur.al > T(0) && all > T(0);
-      T eyn = cur.ey0;
-      if (i >= 1 && ay) {
-        T ca, cb;
-        edge_coef(cur.al + all, cur.be + bel, k2dx, ca, cb);
-        eyn = ca * cur.ey0 - cb * (hn - hnl);
-      }
+      const bool ay = i >= 1 && cur.al > T(0) && all > T(0);
+      T cay, cby;
+      edge_coef(cur.al + all, cur.be + bel, k2dx, cay, cby);
+      T eyn = ay ? cay * cur.ey0 - cby * (hn - hnl) : cur.ey0;
       if (any_src) {
         exn += src_sum(p, sinc, 1, i, j);
         eyn += src_sum(p, sinc, 2, i, j);
       }
-      hzo[o] = hn;
-      // interface edges (exactly one side inside a region) belong to the
-      // coupling blocks of this launch
-      if (!((cur.al < T(0)) != (a_prev < T(0)))) exo[o] = exn;
-      if (!((cur.al < T(0)) != (all < T(0)))) eyo[o] = eyn;
+      if (in) {
+        st(hzo, ob, hn);
+        // interface edges (exactly one side inside a region) belong to the
+        // coupling blocks of this launch
+        if (!((cur.al < T(0)) != (a_prev < T(0)))) st(exo, ob, exn);
+        if (!((cur.al < T(0)) != (all < T(0)))) st(eyo, ob, eyn);
+      }
     }
     hn_prev = hn;
     a_prev = cur.al;
@@ -450,6 +484,7 @@ batch_step_kernel(const StepParams<T>* __restrict__ descs, const BatchRef* __res
   }
   if (r.kind == 1) {
     switch (p.seg) {
+      case 4: stencil_tile<T, 4>(p, r.idx, n); break;
       case 8: stencil_tile<T, 8>(p, r.idx, n); break;
       case 32: stencil_tile<T, 32>(p, r.idx, n); break;
       default: stencil_tile<T, 16>(p, r.idx, n); break;
@@ -548,6 +583,7 @@ template <typename T>
 hipError_t launch_step(const StepParams<T>& p, int seg, size_t smem, hipStream_t s) {
   const dim3 g(p.ncoup_blocks + p.nst_blocks + 1), b(kBlock);
   switch (seg) {
+    case 4: hipLaunchKernelGGL((step_kernel<T, 4>), g, b, smem, s, p); break;
     case 8: hipLaunchKernelGGL((step_kernel<T, 8>), g, b, smem, s, p); break;
     case 16: hipLaunchKernelGGL((step_kernel<T, 16>), g, b, smem, s, p); break;
     case 32: hipLaunchKernelGGL((step_kernel<T, 32>), g, b, smem, s, p); break;

@@ -54,6 +54,9 @@ int fdtd::plan_problem(const fdtd_problem* p, Layout& L) {
   L.tsize = ts;
   L.pitch = (int)align_up((size_t)g.nx, kWave);
   L.field_elems = (size_t)g.ny * L.pitch;
+  // the stencil addresses every field with 32-bit byte offsets
+  if ((double)L.field_elems * (double)ts >= 2147483648.0)
+    return fail(FDTD_EINVAL, "grid %dx%d too large: one field array must stay below 2 GiB", g.nx, g.ny);
   // matrix slots (shared by group)
   L.slot_of_rom.assign(p->nroms, -1);
   L.slot_rep.clear();
@@ -548,6 +551,20 @@ int validate_numbers(const fdtd_problem* p, const Layout& L, std::vector<unsigne
 
 }  // namespace
 
+// Default rows per stencil wave.  A wave streams its segment with two rows
+// of loads in flight, so the grid needs a few waves per SIMD (1024 SIMDs)
+// to hide memory latency: 16 rows while that still gives >= 4096 waves and
+// the working set (~32 B per cell) stays cache-resident; otherwise 8 rows
+// for large grids (HBM-bound, >= 8192 waves) and 4 for small ones.
+int fdtd::default_tiling(int nx, int ny, int ts) {
+  const long tx = (nx + kWave - 1) / kWave;
+  auto waves = [&](int seg) { return tx * ((ny + seg - 1) / seg); };
+  const double bytes = 4.0 * ts * (double)nx * (double)ny * 2.0;  // FP32: 32 B per cell
+  if (waves(16) >= 4096 && bytes <= 192.0 * (1 << 20)) return 16;
+  if (waves(8) >= 8192) return 8;
+  return 4;
+}
+
 // a stencil workgroup covers 64 columns x (4 waves x seg rows)
 void fdtd::set_tiling(fdtd_rom_sim* s, int seg) {
   s->seg = seg;
@@ -744,7 +761,7 @@ int fdtd_rom_create(const fdtd_problem* prob, void* dev_workspace, size_t ws_byt
     if (rc == FDTD_OK)
       rc = (s->dtype == FDTD_F32) ? setup_device<float>(s, prob, inside)
                                   : setup_device<double>(s, prob, inside);
-    if (rc == FDTD_OK) set_tiling(s, 16);
+    if (rc == FDTD_OK) set_tiling(s, default_tiling(s->nx, s->ny, (int)L.tsize));
     if (rc != FDTD_OK) {
       delete s;
       return rc;
@@ -996,8 +1013,14 @@ int fdtd_rom_profile_read(fdtd_rom_sim* sim, double* step_ms, int64_t* step_laun
 
 int fdtd_rom_set_tiling(fdtd_rom_sim* sim, int32_t seg) {
   if (!sim) return fail(FDTD_EINVAL, "null handle");
-  if (seg != 8 && seg != 16 && seg != 32) return fail(FDTD_EINVAL, "segment rows must be 8, 16 or 32");
+  if (seg != 4 && seg != 8 && seg != 16 && seg != 32) return fail(FDTD_EINVAL, "segment rows must be 4, 8, 16 or 32");
   set_tiling(sim, seg);
+  return FDTD_OK;
+}
+
+int fdtd_rom_get_tiling(const fdtd_rom_sim* sim, int32_t* seg) {
+  if (!sim || !seg) return fail(FDTD_EINVAL, "null argument");
+  *seg = sim->seg;
   return FDTD_OK;
 }
 

@@ -95,5 +95,7 @@ int run_steps_any(fdtd_rom_sim* s, int nsteps);
 
 // Rows per stencil wave: recompute the tile grid of the handle.
 void set_tiling(fdtd_rom_sim* s, int seg);
+// Rows per stencil wave a new handle starts with (grid size, element bytes).
+int default_tiling(int nx, int ny, int ts);
 
 }  // namespace fdtd

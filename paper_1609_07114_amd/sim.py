@@ -70,6 +70,9 @@ class Simulation:
     def set_tiling(self, seg):
         capi.fdtd_rom_set_tiling(self.h, seg)
 
+    def get_tiling(self):
+        return capi.fdtd_rom_get_tiling(self.h)
+
     def set_shared_gemm(self, enable):
         capi.fdtd_rom_set_shared_gemm(self.h, enable)
 

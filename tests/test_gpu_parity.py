@@ -244,7 +244,7 @@ def test_graph_replays_match_eager():
 
 
 @pytest.mark.parametrize("nx,ny", [(130, 77), (124, 40), (125, 33), (63, 9), (3, 20)])
-@pytest.mark.parametrize("seg", [8, 32])
+@pytest.mark.parametrize("seg", [4, 8, 32])
 def test_tilings_match(nx, ny, seg):
     """Every tiling (rows per wave segment) gives bit-identical fields,
     including ragged tails of the 62-column tiles."""
