@@ -121,6 +121,26 @@ def _timed(stream, fn):
     return time.perf_counter() - t0, e0.elapsed_time(e1)
 
 
+def copy_ceiling(sizes_mib=(64, 128, 256, 512, 1024, 2048, 4096)):
+    """Device-to-device copy rate (read + write bytes / time) of torch's copy
+    kernel at several sizes: the practical bandwidth a streaming kernel can
+    reach on this GPU, cache-resident (<= 256 MB Infinity Cache) and not."""
+    import torch
+    out = {}
+    for mb in sizes_mib:
+        n = mb << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        it = 20 if mb <= 512 else 5
+        _, ms = _timed(torch.cuda.current_stream(), lambda: [b.copy_(a) for _ in range(it)])
+        out[f"{mb}MiB"] = round(2 * n / (ms / it) / 1e6, 1)
+        del a, b
+    return {"unit": "GB/s (read+write)", "rates": out}
+
+
 def bench_batched(steps=300, warmup=30, log=None):
     import numpy as np
     import workloads as W
@@ -238,6 +258,7 @@ def main():
     ap.add_argument("--only", choices=["batched", "many_copies", "adjoint"], default=None,
                     help="run one form alone and print its JSON (profiling)")
     ap.add_argument("--form-steps", type=int, default=None, help="timed steps of the batched / many-copies form")
+    ap.add_argument("--copy-ceiling", action="store_true", help="only measure device copy rates and exit")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -254,6 +275,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no ROCm GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_ceiling:
+        print(json.dumps({"copy_ceiling": copy_ceiling()}), flush=True)
+        return
     if args.only:
         log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
         kw = {} if args.form_steps is None or args.only == "adjoint" else {"steps": args.form_steps}

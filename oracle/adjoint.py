@@ -67,23 +67,66 @@ def forward_states(prob, roms, nsteps=None, probe=0, fp32=False):
     return run, states, J
 
 
+def transpose_step(run, Gs, lam):
+    """lambda^n = M^T lambda^{n+1} for one forward step M of ``run``
+    (steps 3, 2, 1 of the module docstring transposed, in that order).
+    lam = (lam_ex, lam_ey, lam_hz, lam_x) is the adjoint of the state after
+    the step (any objective term already added to lam_hz).  Returns the
+    adjoint of the state before the step and (lex, ley), the adjoint of the
+    new E on the edges eq. (3) updates (the coefficient gradients' weights)."""
+    lam_ex, lam_ey, lam_hz, lam_x = lam
+    cell, exm, eym = run.cell, run.exm, run.eym
+    ca_x, cb_x, ca_y, cb_y, chdy, chdx = run.ca_x, run.cb_x, run.ca_y, run.cb_y, run.chdy, run.chdx
+    ny, nx = cell.shape
+    lam_h = lam_hz.copy()
+    lam_ex_in = lam_ex.copy()
+    lam_ey_in = lam_ey.copy()
+    # 3. coupling: [x'; y'] = G [x; gather(Hz')], y' into interface edges
+    new_lam_x = []
+    for c, G, lx in zip(run.cpl, Gs, lam_x):
+        ly = c.read_y(lam_ex_in, lam_ey_in)
+        back = G.T @ np.concatenate([lx, ly])
+        new_lam_x.append(back[:c.q].copy())
+        for k, (_, _, _, oi, oj, _, _) in enumerate(c.ports):
+            lam_h[oj, oi] += back[c.q + k]
+        c.scatter(lam_ex_in, lam_ey_in, np.zeros(c.np_))   # consumed
+    # 2. E' = Ca E + Cb curlH(Hz') on active edges
+    lex = np.where(exm, lam_ex_in, 0.0)
+    ley = np.where(eym, lam_ey_in, 0.0)
+    # d/dHz' of sum lex*cb_x*(Hz(j)-Hz(j-1)) + ley*cb_y*(-(Hz(i)-Hz(i-1)))
+    wx = lex * cb_x
+    wy = ley * cb_y
+    lam_h += wx[:-1, :] - wx[1:, :]       # edge (i,j) above cell (i,j-1): +, edge (i,j+1): -
+    lam_h += -wy[:, :-1] + wy[:, 1:]
+    # 1. Hz' = M (Hz + chdy (Ex(j+1)-Ex(j)) - chdx (Ey(i+1)-Ey(i)))
+    mu = lam_h * cell
+    new_ex = lex * ca_x
+    new_ey = ley * ca_y
+    new_ex[1:, :] += chdy * mu
+    new_ex[:-1, :] -= chdy * mu
+    new_ey[:, 1:] -= chdx * mu
+    new_ey[:, :-1] += chdx * mu
+    # walls carry no adjoint (E fixed at zero there)
+    new_ex[0, :] = 0.0
+    new_ex[ny, :] = 0.0
+    new_ey[:, 0] = 0.0
+    new_ey[:, nx] = 0.0
+    return (new_ex, new_ey, mu, new_lam_x), (lex, ley)
+
+
 def adjoint_gradient(prob, roms, nsteps=None, probe=0, fp32=False):
     """Return (J, dJ/deps_r [ny,nx], dJ/dsigma [ny,nx]).  fp32: transpose of
     the forward with FP32-rounded coefficients (see forward_states)."""
     nsteps = prob.nsteps if nsteps is None else nsteps
     run, states, J = forward_states(prob, roms, nsteps, probe, fp32)
     nx, ny = prob.nx, prob.ny
-    cell, exm, eym = run.cell, run.exm, run.eym
-    ca_x, cb_x, ca_y, cb_y, chdy, chdx = run.ca_x, run.cb_x, run.ca_y, run.cb_y, run.chdy, run.chdx
+    cell = run.cell
     pr = prob.probes[probe]
     if pr.comp != yee.HZ:
         raise ValueError("objective probe must be an Hz probe")
-    # interface edges of every model
     Gs = [c.G32 if fp32 else c.update_matrix() for c in run.cpl]
-    lam_ex = np.zeros((ny + 1, nx))
-    lam_ey = np.zeros((ny, nx + 1))
-    lam_hz = np.zeros((ny, nx))
-    lam_x = [np.zeros(c.q) for c in run.cpl]
+    lam = (np.zeros((ny + 1, nx)), np.zeros((ny, nx + 1)), np.zeros((ny, nx)),
+           [np.zeros(c.q) for c in run.cpl])
     g_cax = np.zeros((ny + 1, nx))
     g_cbx = np.zeros((ny + 1, nx))
     g_cay = np.zeros((ny, nx + 1))
@@ -93,22 +136,9 @@ def adjoint_gradient(prob, roms, nsteps=None, probe=0, fp32=False):
         _, _, hz1 = states[n + 1]        # Hz^{n+1/2}
         hz1 = hz1 * cell
         # objective: J += dt (Hz'_p)^2
-        lam_h = lam_hz.copy()
-        lam_h[pr.j, pr.i] += 2.0 * prob.dt * hz1[pr.j, pr.i]
-        lam_ex_in = lam_ex.copy()
-        lam_ey_in = lam_ey.copy()
-        # 3. coupling: [x'; y'] = G [x; gather(Hz')], y' into interface edges
-        new_lam_x = []
-        for c, G, lx in zip(run.cpl, Gs, lam_x):
-            ly = c.read_y(lam_ex_in, lam_ey_in)
-            back = G.T @ np.concatenate([lx, ly])
-            new_lam_x.append(back[:c.q].copy())
-            for k, (_, _, _, oi, oj, _, _) in enumerate(c.ports):
-                lam_h[oj, oi] += back[c.q + k]
-            c.scatter(lam_ex_in, lam_ey_in, np.zeros(c.np_))   # consumed
-        # 2. E' = Ca E + Cb curlH(Hz') on active edges
-        lex = np.where(exm, lam_ex_in, 0.0)
-        ley = np.where(eym, lam_ey_in, 0.0)
+        lam_hz = lam[2].copy()
+        lam_hz[pr.j, pr.i] += 2.0 * prob.dt * hz1[pr.j, pr.i]
+        lam, (lex, ley) = transpose_step(run, Gs, (lam[0], lam[1], lam_hz, lam[3]))
         dhx = np.zeros((ny + 1, nx))
         dhx[1:ny, :] = hz1[1:, :] - hz1[:-1, :]
         dhy = np.zeros((ny, nx + 1))
@@ -117,25 +147,6 @@ def adjoint_gradient(prob, roms, nsteps=None, probe=0, fp32=False):
         g_cbx += lex * dhx
         g_cay += ley * ey0
         g_cby += ley * dhy
-        # d/dHz' of sum lex*cb_x*(Hz(j)-Hz(j-1)) + ley*cb_y*(-(Hz(i)-Hz(i-1)))
-        wx = lex * cb_x
-        wy = ley * cb_y
-        lam_h += wx[:-1, :] - wx[1:, :]       # edge (i,j) above cell (i,j-1): +, edge (i,j+1): -
-        lam_h += -wy[:, :-1] + wy[:, 1:]
-        # 1. Hz' = M (Hz + chdy (Ex(j+1)-Ex(j)) - chdx (Ey(i+1)-Ey(i)))
-        mu = lam_h * cell
-        new_ex = lex * ca_x
-        new_ey = ley * ca_y
-        new_ex[1:, :] += chdy * mu
-        new_ex[:-1, :] -= chdy * mu
-        new_ey[:, 1:] -= chdx * mu
-        new_ey[:, :-1] += chdx * mu
-        # walls carry no adjoint (E fixed at zero there)
-        new_ex[0, :] = 0.0
-        new_ex[ny, :] = 0.0
-        new_ey[:, 0] = 0.0
-        new_ey[:, nx] = 0.0
-        lam_ex, lam_ey, lam_hz, lam_x = new_ex, new_ey, mu, new_lam_x
     # chain rule to cell materials
     ax, bx, ay, by = _edge_ab(prob)
     d = {}

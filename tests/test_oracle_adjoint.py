@@ -70,3 +70,42 @@ def test_fp32_coefficient_mode_tracks_fp64(case):
     assert J32 == pytest.approx(J, rel=1e-5)
     assert np.linalg.norm(ge32 - ge) <= 1e-4 * np.linalg.norm(ge)
     assert np.linalg.norm(gs32 - gs) <= 1e-4 * np.linalg.norm(gs)
+
+
+def test_transpose_step_dot_product_identity():
+    """<M ds, lam> = <ds, M^T lam> for one forward step of the oracle (no
+    sources, two models, lossy): the reverse step is the exact transpose of
+    the forward step on the state space (active and interface E, active Hz,
+    reduced states)."""
+    p = W.random_problem(34, 36, 30, 10, nroms=2, block=(5, 4), r=2, q=10,
+                         dt_frac_coarse=0.9, f_bw=3e9)
+    for s in p.sources:
+        s.incr[:] = 0.0
+    roms = osim.build_roms(p)
+    run = osim.CoupledRun(p, roms, mode="closed")
+    rng = np.random.default_rng(7)
+    mx = run.exm.astype(float)
+    my = run.eym.astype(float)
+    for c in run.cpl:
+        for (comp, ei, ej, _, _, _, _) in c.ports:
+            (mx if comp == 1 else my)[ej, ei] = 1.0
+    ds = (rng.standard_normal(mx.shape) * mx, rng.standard_normal(my.shape) * my,
+          rng.standard_normal(run.cell.shape) * run.cell,
+          [rng.standard_normal(c.q) for c in run.cpl])
+    lam = (rng.standard_normal(mx.shape) * mx, rng.standard_normal(my.shape) * my,
+           rng.standard_normal(run.cell.shape) * run.cell,
+           [rng.standard_normal(c.q) for c in run.cpl])
+    run.f.ex[...] = ds[0]
+    run.f.ey[...] = ds[1]
+    run.f.hz[...] = ds[2]
+    run.x = [x.copy() for x in ds[3]]
+    run.step()
+    Mds = (run.f.ex, run.f.ey, run.f.hz * run.cell, run.x)
+
+    def dot(a, b):
+        return (np.sum(a[0] * b[0]) + np.sum(a[1] * b[1]) + np.sum(a[2] * b[2]) +
+                sum(float(u @ v) for u, v in zip(a[3], b[3])))
+    Gs = [c.update_matrix() for c in run.cpl]
+    MTlam, _ = oadj.transpose_step(run, Gs, lam)
+    lhs, rhs = dot(Mds, lam), dot(ds, MTlam)
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0), (lhs, rhs)
