@@ -179,6 +179,7 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   ap.nx = s->nx;
   ap.ny = s->ny;
   ap.pitch = s->pitch;
+  ap.seg = std::min(default_tiling(s->nx, s->ny, (int)L.tsize), 16);
   ap.chdy = sp.chdy;
   ap.chdx = sp.chdx;
   ap.k2dy = sp.k2dy;

@@ -1,0 +1,41 @@
+// Device-side helpers shared by the gfx950 kernels (included by .hip files
+// only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace fdtd {
+
+// Loads and stores at a 32-bit byte offset from a wave-uniform base: all
+// accesses of a row can share one vector offset (base and row step in
+// scalar registers), with no 64-bit address arithmetic per access.
+template <typename T>
+__device__ __forceinline__ T ld(const T* base, uint32_t off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ void st(T* base, uint32_t off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
+// Whole-wave lane shifts by one (DPP wave_shr:1 / wave_shl:1, no LDS
+// traffic): lane_prev gives lane l the value of lane l-1 (lane 0 gets 0),
+// lane_next the value of lane l+1 (lane 63 gets 0).
+__device__ __forceinline__ int dpp_prev(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_next(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+
+__device__ __forceinline__ float lane_prev(float v) { return __builtin_bit_cast(float, dpp_prev(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ float lane_next(float v) { return __builtin_bit_cast(float, dpp_next(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ double lane_prev(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)dpp_prev((int)(uint32_t)u), hi = (uint32_t)dpp_prev((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double lane_next(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)dpp_next((int)(uint32_t)u), hi = (uint32_t)dpp_next((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+}  // namespace fdtd
