@@ -15,6 +15,8 @@ plain solver on the same GPU:
   * "batched": the 64-instance workload (grids in [256,1024]^2, 1-8 models
     each, FP32) in one launch per step with autotuned tiles, against the
     same instances run one after another by single-problem handles;
+  * "hbm_resident": the same recipe at 8192^2 (2.1 GB working set), the
+    stencil's HBM-bound rate;
   * "many_copies": 4096^2 vacuum with 256 copies of one order-128 model,
     eq. (23) for all copies as one FP32 MFMA GEMM per step, against the
     same run with a GEMV per copy;
@@ -215,6 +217,29 @@ def bench_many_copies(steps=500, warmup=50, log=None):
             "rel_l2_gemm_vs_gemv": float(np.linalg.norm(pg - pv) / max(np.linalg.norm(pv), 1e-300))}
 
 
+def bench_hbm_resident(n=8192, steps=400, warmup=50, log=None):
+    """The random-media recipe at n^2 (a working set well beyond the 256 MB
+    Infinity Cache): the stencil's HBM-bound rate."""
+    import workloads as W
+    from paper_1609_07114_amd import romgen
+    from paper_1609_07114_amd.sim import Simulation
+    prob = W.random_media(n=n, nsteps=steps + warmup)
+    roms = romgen.build_roms(prob)
+    with Simulation(prob, roms) as s:
+        seg = s.get_tiling()
+        s.set_graph(min(steps, 200))
+        s.run(warmup)
+        t, ev = _timed(s.stream, lambda: s.run(steps))
+    cells = prob.nx * prob.ny
+    alg = step_bytes(prob)
+    avg = ev / 1e3 / steps
+    return {"workload": f"random media {n}x{n}, 16 models (q 32-96), FP32, {steps} steps",
+            "value": round(cells * steps / t / 1e6, 1), "unit": "Mcell-updates/s",
+            "ms_per_step": round(t * 1e3 / steps, 4), "kernel": f"step_kernel<float,{seg}>",
+            "bytes_per_launch": alg, "achieved_GBps": round(alg / avg / 1e9, 1),
+            "frac_of_8TBps": round(alg / avg / 1e9 / PEAK_HBM_GBS, 4)}
+
+
 def bench_adjoint(ckpt=200, log=None):
     import numpy as np
     import workloads as W
@@ -255,7 +280,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched, many-copies and adjoint forms")
-    ap.add_argument("--only", choices=["batched", "many_copies", "adjoint"], default=None,
+    ap.add_argument("--only", choices=["batched", "many_copies", "adjoint", "hbm_resident"], default=None,
                     help="run one form alone and print its JSON (profiling)")
     ap.add_argument("--form-steps", type=int, default=None, help="timed steps of the batched / many-copies form")
     ap.add_argument("--copy-ceiling", action="store_true", help="only measure device copy rates and exit")
@@ -281,7 +306,8 @@ def main():
     if args.only:
         log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
         kw = {} if args.form_steps is None or args.only == "adjoint" else {"steps": args.form_steps}
-        fn = {"batched": bench_batched, "many_copies": bench_many_copies, "adjoint": bench_adjoint}[args.only]
+        fn = {"batched": bench_batched, "many_copies": bench_many_copies, "adjoint": bench_adjoint,
+              "hbm_resident": bench_hbm_resident}[args.only]
         print(json.dumps({args.only: fn(log=log, **kw)}), flush=True)
         return
     total = args.warmup + args.steps
@@ -300,6 +326,7 @@ def main():
 
     sim = Simulation(prob, roms, max_steps=total)
     seg = sim.get_tiling()
+    sim.set_graph(200)   # steps replayed from captured graphs (the production path)
     sim.run(args.warmup)
     torch.cuda.synchronize()
     # timed region: K step launches on the simulation's stream, bracketed by
@@ -350,6 +377,8 @@ def main():
         log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
         out["batched"] = bench_batched(log=log)
         log(f"batched {out['batched']['value']:.0f} vs plain {out['batched']['plain_sequential']:.0f} Mcell/s")
+        out["hbm_resident"] = bench_hbm_resident(log=log)
+        log(f"hbm-resident 8192^2: {out['hbm_resident']['achieved_GBps']:.0f} GB/s")
         out["many_copies"] = bench_many_copies(log=log)
         log(f"many copies {out['many_copies']['value']:.0f} Mcell/s (GEMV {out['many_copies']['gemv_per_copy']:.0f})")
         out["adjoint"] = bench_adjoint(log=log)

@@ -23,8 +23,8 @@
 //     carrying Ex(i,j), Hz^{n+1/2}(i,j-1) and the material of row j-1 in
 //     registers, with the loads of row j+1 issued before row j is computed;
 //     horizontal neighbours (Ey(i+1,j), Hz^{n+1/2}(i-1,j), material of cell
-//     i-1) come from adjacent lanes, lanes 0 and 63 fetch the one column
-//     outside the wave;
+//     i-1) come from adjacent lanes (DPP whole-wave shifts), lanes 0 and 63
+//     fetch the one column outside the wave;
 //   * each segment recomputes Hz^{n+1/2} of the row below it (one extra row
 //     per SEG), so the step needs no second pass;
 //   * per-edge coefficients are rebuilt from per-cell (a, b) =
@@ -36,6 +36,7 @@
 //   * workgroups are remapped so each of the 8 XCDs (own L2) takes a
 //     contiguous band of tiles, keeping the halo rows within one L2.
 #include "common.hpp"
+#include "device.hpp"
 
 namespace fdtd {
 
@@ -85,19 +86,6 @@ __device__ __forceinline__ T src_sum(const StepParams<T>& p, const T* sinc, int 
     }
   }
   return acc;
-}
-
-// Loads and stores at a 32-bit byte offset from a wave-uniform base: every
-// access of a row shares one vector offset (the base and the row step live
-// in scalar registers), so no 64-bit address arithmetic per access.  Field
-// arrays stay below 2 GiB (checked at create).
-template <typename T>
-__device__ __forceinline__ T ld(const T* base, uint32_t off) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
-}
-template <typename T>
-__device__ __forceinline__ void st(T* base, uint32_t off, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
 }
 
 template <typename T>
@@ -205,15 +193,15 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
       if (has_left) l2 = load_row(hz, ex_up, ey, al, be, o3 - ts, up3);
       if (has_right) r2 = ld(ey, o3 + ts);
     }
-    T ey1 = __shfl_down(cur.ey0, 1, kWave);
+    T ey1 = lane_next(cur.ey0);
     if (lane == kWave - 1) ey1 = ey1_r;
     // eq. (5): Hz^{n+1/2}
     T hn = hz_update(cur.h, ex_c, cur.ex1, cur.ey0, ey1, chdy, chdx);
     if (any_src) hn += src_sum(p, sinc, 0, i, j);
     if (!(cur.al > T(0))) hn = T(0);
-    T hnl = __shfl_up(hn, 1, kWave);
-    T all = __shfl_up(cur.al, 1, kWave);
-    T bel = __shfl_up(cur.be, 1, kWave);
+    T hnl = lane_prev(hn);
+    T all = lane_prev(cur.al);
+    T bel = lane_prev(cur.be);
     if (lane == 0) {
       hnl = T(0);
       all = cul.al;
