@@ -118,6 +118,8 @@ def adjoint_gradient(prob, roms, nsteps=None, probe=0, fp32=False):
     """Return (J, dJ/deps_r [ny,nx], dJ/dsigma [ny,nx]).  fp32: transpose of
     the forward with FP32-rounded coefficients (see forward_states)."""
     nsteps = prob.nsteps if nsteps is None else nsteps
+    if getattr(prob, "pml", None) is not None and prob.pml.any:
+        raise ValueError("the adjoint covers PEC-walled grids only (no absorbing layers)")
     run, states, J = forward_states(prob, roms, nsteps, probe, fp32)
     nx, ny = prob.nx, prob.ny
     cell = run.cell

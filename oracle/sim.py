@@ -27,7 +27,7 @@ from __future__ import annotations
 import numpy as np
 
 from .constants import EPS0, MU0
-from . import yee
+from . import cpml, yee
 from .coupling import RomCoupling
 from .yee import EX, EY, HZ
 
@@ -60,6 +60,8 @@ class CoupledRun:
                      if fp32 else None)
             self.cpl.append(c)
         self.x = [np.zeros(c.q) for c in self.cpl]
+        pml = getattr(prob, "pml", None)
+        self.pml = cpml.Cpml(prob, fp32) if (pml is not None and pml.any) else None
         if init is not None:
             self.f.hz[...] = init["hz"] * self.cell
             self.f.ex[...] = init["ex"] * self.exm
@@ -72,9 +74,15 @@ class CoupledRun:
 
     def step(self):
         p, f, n = self.prob, self.f, self.n
-        yee.update_h(f, self.chdy, self.chdx, self.cell)
+        if self.pml is None:
+            yee.update_h(f, self.chdy, self.chdx, self.cell)
+        else:
+            self.pml.update_h(f, self.chdy, self.chdx, self.cell)
         yee.apply_sources(f, p.sources, (HZ,), n)
-        yee.update_e(f, self.ca_x, self.cb_x, self.ca_y, self.cb_y, self.exm, self.eym)
+        if self.pml is None:
+            yee.update_e(f, self.ca_x, self.cb_x, self.ca_y, self.cb_y, self.exm, self.eym)
+        else:
+            self.pml.update_e(f, self.ca_x, self.cb_x, self.ca_y, self.cb_y, self.exm, self.eym)
         yee.apply_sources(f, p.sources, (EX, EY), n)
         for k, c in enumerate(self.cpl):
             h = c.gather(f.hz)

@@ -79,6 +79,27 @@ class RomSpec:
 
 
 @dataclasses.dataclass
+class Pml:
+    """Absorbing layers of the coarse grid (convolutional PML): thickness in
+    coarse cells on each side (0: that side stays a PEC wall) and the
+    grading parameters - polynomial order m, conductivity scale (1 = the
+    usual optimum 0.8 (m+1)/(eta0 d)), maximum stretch kappa and the
+    complex-frequency shift alpha (S/m) at the layer's inner face."""
+    n_xlo: int = 0
+    n_xhi: int = 0
+    n_ylo: int = 0
+    n_yhi: int = 0
+    m: float = 3.0
+    sigma_scale: float = 1.0
+    kappa_max: float = 1.0
+    alpha_max: float = 0.0
+
+    @property
+    def any(self) -> bool:
+        return (self.n_xlo + self.n_xhi + self.n_ylo + self.n_yhi) > 0
+
+
+@dataclasses.dataclass
 class Problem:
     name: str
     nx: int
@@ -93,6 +114,7 @@ class Problem:
     probes: List[Probe]
     nsteps: int
     dtype: str          # "f64" or "f32"
+    pml: Optional[Pml] = None
 
     @property
     def ncells(self) -> int:
