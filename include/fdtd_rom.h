@@ -101,6 +101,26 @@ typedef struct {
   int32_t comp, i, j;
 } fdtd_probe;
 
+/* Absorbing layers (convolutional PML; not in the paper, whose waveguide
+ * and reflection experiments of Sec. VI end in PML without equations).
+ * n_xlo .. n_yhi: layer thickness in coarse cells on each side (0: that side
+ * is a PEC wall; the outer face of a layer is PEC).  Inside a layer of D
+ * cells, at depth ratio rho in (0, 1] (E samples at k*d, Hz at (k+1/2)*d):
+ *   sigma = sigma_scale * 0.8 (m+1) / (eta0 d) * rho^m,
+ *   kappa = 1 + (kappa_max - 1) rho^m,  alpha = alpha_max (1 - rho),
+ *   b = exp(-(sigma/kappa + alpha) dt/eps0),
+ *   a = sigma (b - 1) / (sigma kappa + kappa^2 alpha)  (0 where sigma = 0),
+ * and every derivative of eqs. (3), (5) across the layer becomes
+ * (1/kappa) dF + psi with psi' = b psi + a dF (dF the Yee difference, psi
+ * carried per field sample).  Outside the layers the update is unchanged.
+ * m <= 0 selects 3, kappa_max < 1 selects 1, alpha_max < 0 selects 0;
+ * sigma_scale >= 0 as given (0: non-absorbing layers).  Reduced regions
+ * and their one-cell rings must lie outside every layer (FDTD_EINVAL). */
+typedef struct {
+  int32_t n_xlo, n_xhi, n_ylo, n_yhi;
+  double m, sigma_scale, kappa_max, alpha_max;
+} fdtd_pml;
+
 typedef struct {
   fdtd_grid grid;
   const fdtd_rom* roms;
@@ -110,6 +130,7 @@ typedef struct {
   const fdtd_probe* probes;
   int32_t nprobes;
   int32_t max_steps; /* capacity of the probe record and source tables */
+  fdtd_pml pml;      /* all thicknesses 0: PEC walls on every side */
 } fdtd_problem;
 
 typedef struct fdtd_rom_sim fdtd_rom_sim; /* opaque, owned by the library */
@@ -166,13 +187,15 @@ int fdtd_rom_read_rom_state(const fdtd_rom_sim* sim, int32_t k, double* host_out
  *     for Ex and dy for Ey);
  *   + sum over models of x~^T R~ x~.
  * Constant for lossless runs without sources and non-increasing with loss
- * (Theorem 2).  Coarse part reduced on the device in FP64, models on the
+ * (Theorem 2); with absorbing layers it is this same coarse-grid function
+ * (the layers' auxiliary state is not part of it).  Coarse part reduced on the device in FP64, models on the
  * host.  Synchronises; FDTD_EUNSTABLE if non-finite. */
 int fdtd_rom_energy(const fdtd_rom_sim* sim, double* e);
 
 /* Checkpoint / resume.  state_size: bytes of a state blob (a 256-byte
  * header with the step count and shape, the current field set in device
- * layout, every model's reduced state).  get_state copies the handle's
+ * layout, every model's reduced state, the absorbing layers' auxiliary
+ * fields if any).  get_state copies the handle's
  * current state into dev_dst (device memory, 256-B aligned, caller-owned);
  * set_state makes a blob from a handle of the same problem shape the current
  * state, including its step count (FDTD_EINVAL on a shape or dtype mismatch
@@ -284,7 +307,8 @@ int fdtd_rom_set_graph(fdtd_rom_sim* sim, int32_t batch);
  * reduced states, two FP64 per-cell accumulators and G^T of every model.
  *
  * fdtd_rom_adjoint: runs the forward from the handle's initial state (the
- * handle must have taken no step; FDTD_ESTATE otherwise), keeping
+ * handle must have taken no step; FDTD_ESTATE otherwise; grids with
+ * absorbing layers are not supported, FDTD_EINVAL), keeping
  * checkpoints, then sweeps back one segment at a time, recomputing each
  * segment's forward states from its checkpoint.  Afterwards the handle
  * stands at step nsteps with its probe record filled, as after

@@ -41,11 +41,17 @@ class fdtd_probe(C.Structure):
     _fields_ = [("comp", C.c_int32), ("i", C.c_int32), ("j", C.c_int32)]
 
 
+class fdtd_pml(C.Structure):
+    _fields_ = [("n_xlo", C.c_int32), ("n_xhi", C.c_int32), ("n_ylo", C.c_int32),
+                ("n_yhi", C.c_int32), ("m", C.c_double), ("sigma_scale", C.c_double),
+                ("kappa_max", C.c_double), ("alpha_max", C.c_double)]
+
+
 class fdtd_problem(C.Structure):
     _fields_ = [("grid", fdtd_grid), ("roms", C.POINTER(fdtd_rom)), ("nroms", C.c_int32),
                 ("sources", C.POINTER(fdtd_source)), ("nsources", C.c_int32),
                 ("probes", C.POINTER(fdtd_probe)), ("nprobes", C.c_int32),
-                ("max_steps", C.c_int32)]
+                ("max_steps", C.c_int32), ("pml", fdtd_pml)]
 
 
 class fdtd_rom_build_params(C.Structure):
@@ -160,7 +166,7 @@ class ProblemStruct:
     """Owns the C structs and the contiguous float64 arrays they point to."""
 
     def __init__(self, nx, ny, dx, dy, dt, dtype, eps_r, sigma, roms, sources, probes,
-                 max_steps):
+                 max_steps, pml=None):
         self._keep = []
 
         def arr(x):
@@ -185,7 +191,12 @@ class ProblemStruct:
         for k, p in enumerate(probes):
             parr[k] = fdtd_probe(p["comp"], p["i"], p["j"])
         self._keep += [rarr, sarr, parr]
-        self.s = fdtd_problem(g, rarr, len(roms), sarr, len(sources), parr, len(probes), max_steps)
+        pm = fdtd_pml(0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0)
+        if pml is not None:
+            pm = fdtd_pml(pml.n_xlo, pml.n_xhi, pml.n_ylo, pml.n_yhi, pml.m, pml.sigma_scale,
+                          pml.kappa_max, pml.alpha_max)
+        self.s = fdtd_problem(g, rarr, len(roms), sarr, len(sources), parr, len(probes), max_steps,
+                              pm)
 
     @classmethod
     def from_workload(cls, prob, rom_mats, max_steps=None, dtype=None, x0=None):
@@ -199,7 +210,7 @@ class ProblemStruct:
         prbs = [dict(comp=p.comp, i=p.i, j=p.j) for p in prob.probes]
         ms = prob.nsteps if max_steps is None else max_steps
         return cls(prob.nx, prob.ny, prob.dx, prob.dy, prob.dt, dtype or prob.dtype, prob.eps_r,
-                   prob.sigma, roms, srcs, prbs, ms)
+                   prob.sigma, roms, srcs, prbs, ms, getattr(prob, "pml", None))
 
 
 # ---------------------------------------------------------------------------

@@ -92,6 +92,19 @@ struct StepParams {
   const int* probe_off;
   const int* probe_comp;
   T* probe_buf;      // [max_steps][nprobes]
+  // absorbing layers (pml == 0: none).  Profiles of the stretched
+  // derivatives: px[k * px_stride + i] for k = 0..5 = (1/kappa, b, a) at the
+  // Ey sample x = i dx, then at the Hz sample x = (i+1/2) dx; py likewise
+  // along y (Ex at y = j dy, Hz at (j+1/2) dy).  Auxiliary fields (pitch
+  // layout): the two at Hz by step parity, the ones at Ex and Ey in place.
+  int pml;
+  int pml_xlo, pml_xhi, pml_ylo, pml_yhi;
+  int px_stride, py_stride;
+  const T* px;
+  const T* py;
+  T* psi_h[2][2];    // [parity][d/dx of Ey, d/dy of Ex]
+  T* psi_ex;         // d/dy of Hz at Ex
+  T* psi_ey;         // d/dx of Hz at Ey
 };
 
 // One workgroup of the batched step launch: instance `inst`, role `kind`

@@ -109,8 +109,31 @@ __device__ __forceinline__ RowIn<T> load_row(const T* hz, const T* ex_up, const 
   return r;
 }
 
-template <typename T, int SEG>
-__device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
+// eq. (5) with stretched derivatives inside absorbing layers: dex, dey the
+// Yee differences, ik 1/kappa, ps the updated auxiliary fields.
+template <typename T>
+__device__ __forceinline__ T hz_update_pml(T h, T dex, T dey, T chdy, T chdx, T iky, T ikx, T psy, T psx) {
+#pragma clang fp contract(off)
+  return h + (chdy * (iky * dex + psy) - chdx * (ikx * dey + psx));
+}
+
+// eq. (3): E' = Ca E + (Cb/d) dH, not contracted, so that the plain update
+// and the absorbing-layer update with identity profiles round alike
+template <typename T>
+__device__ __forceinline__ T e_update(T ca, T e, T cb, T dh) {
+#pragma clang fp contract(off)
+  return ca * e + cb * dh;
+}
+
+// psi' = b psi + a dF (recursive convolution of the stretched derivative)
+template <typename T>
+__device__ __forceinline__ T psi_next(T b, T psi, T a, T d) {
+#pragma clang fp contract(off)
+  return b * psi + a * d;
+}
+
+template <typename T, int SEG, bool PML>
+__device__ void stencil_rows(const StepParams<T>& p, int t, int n) {
   const int par = n & 1;
   const T* hz = fld(p, par, 0);
   const T* ex = fld(p, par, 1);
@@ -127,7 +150,6 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
   const int iw = tx * kWave;
   const int i = iw + lane;
   const int j0 = (tyb * (kBlock / kWave) + wv) * SEG;
-  if (j0 >= p.ny) return;
   const int j1 = min(j0 + SEG, p.ny);
   const int nx = p.nx;
   const int ny = p.ny;
@@ -157,6 +179,32 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
 #pragma unroll
     for (int s = 0; s < kMaxSrc; ++s)
       if (s < p.nsrc) sinc[s] = p.src[s].incr[n];
+  }
+  // absorbing layers: x profiles of this lane's column (and lane 0's left
+  // neighbour), auxiliary fields of this step's parity
+  T ikx_e = T(1), bx_e = T(1), ax_e = T(0), ikx_h = T(1), bx_h = T(1), ax_h = T(0);
+  T ikx_hl = T(1), bx_hl = T(1), ax_hl = T(0);
+  const T* psx_in = nullptr;
+  const T* psy_in = nullptr;
+  T* psx_out = nullptr;
+  T* psy_out = nullptr;
+  if constexpr (PML) {
+    const int S = p.px_stride;
+    ikx_e = p.px[i];
+    bx_e = p.px[S + i];
+    ax_e = p.px[2 * S + i];
+    ikx_h = p.px[3 * S + i];
+    bx_h = p.px[4 * S + i];
+    ax_h = p.px[5 * S + i];
+    if (has_left) {
+      ikx_hl = p.px[3 * S + i - 1];
+      bx_hl = p.px[4 * S + i - 1];
+      ax_hl = p.px[5 * S + i - 1];
+    }
+    psx_in = par ? p.psi_h[1][0] : p.psi_h[0][0];
+    psy_in = par ? p.psi_h[1][1] : p.psi_h[0][1];
+    psx_out = par ? p.psi_h[0][0] : p.psi_h[1][0];
+    psy_out = par ? p.psi_h[0][1] : p.psi_h[1][1];
   }
 
   uint32_t ob = ((uint32_t)js * (uint32_t)P + (uint32_t)i) * ts;
@@ -195,8 +243,28 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
     }
     T ey1 = lane_next(cur.ey0);
     if (lane == kWave - 1) ey1 = ey1_r;
+    // y profiles of this row (wave-uniform)
+    T iky_h = T(1), by_h = T(1), ay_h = T(0), iky_e = T(1), by_e = T(1), ay_e = T(0);
+    T psy = T(0), psx = T(0);
+    if constexpr (PML) {
+      const int S = p.py_stride;
+      iky_e = p.py[j];
+      by_e = p.py[S + j];
+      ay_e = p.py[2 * S + j];
+      iky_h = p.py[3 * S + j];
+      by_h = p.py[4 * S + j];
+      ay_h = p.py[5 * S + j];
+    }
     // eq. (5): Hz^{n+1/2}
-    T hn = hz_update(cur.h, ex_c, cur.ex1, cur.ey0, ey1, chdy, chdx);
+    T hn;
+    if constexpr (PML) {
+      const T dex = cur.ex1 - ex_c, dey = ey1 - cur.ey0;
+      psy = psi_next(by_h, ld(psy_in, ob), ay_h, dex);
+      psx = psi_next(bx_h, ld(psx_in, ob), ax_h, dey);
+      hn = hz_update_pml(cur.h, dex, dey, chdy, chdx, iky_h, ikx_h, psy, psx);
+    } else {
+      hn = hz_update(cur.h, ex_c, cur.ex1, cur.ey0, ey1, chdy, chdx);
+    }
     if (any_src) hn += src_sum(p, sinc, 0, i, j);
     if (!(cur.al > T(0))) hn = T(0);
     T hnl = lane_prev(hn);
@@ -207,7 +275,14 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
       all = cul.al;
       bel = cul.be;
       if (has_left) {
-        hnl = hz_update(cul.h, exl_c, cul.ex1, cul.ey0, cur.ey0, chdy, chdx);
+        if constexpr (PML) {
+          const T dex = cul.ex1 - exl_c, dey = cur.ey0 - cul.ey0;
+          const T psyl = psi_next(by_h, ld(psy_in, ob - ts), ay_h, dex);
+          const T psxl = psi_next(bx_hl, ld(psx_in, ob - ts), ax_hl, dey);
+          hnl = hz_update_pml(cul.h, dex, dey, chdy, chdx, iky_h, ikx_hl, psyl, psxl);
+        } else {
+          hnl = hz_update(cul.h, exl_c, cul.ex1, cul.ey0, cur.ey0, chdy, chdx);
+        }
         if (any_src) hnl += src_sum(p, sinc, 0, i - 1, j);
         if (!(all > T(0))) hnl = T(0);
         exl_c = cul.ex1;
@@ -221,12 +296,21 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
       const bool ax = j >= 1 && cur.al > T(0) && a_prev > T(0);
       T cax, cbx;
       edge_coef(cur.al + a_prev, cur.be + b_prev, k2dy, cax, cbx);
-      T exn = ax ? cax * ex_c + cbx * (hn - hn_prev) : ex_c;
       // Ey^{n+1}(i,j) between cells (i-1,j) and (i,j)
       const bool ay = i >= 1 && cur.al > T(0) && all > T(0);
       T cay, cby;
       edge_coef(cur.al + all, cur.be + bel, k2dx, cay, cby);
-      T eyn = ay ? cay * cur.ey0 - cby * (hn - hnl) : cur.ey0;
+      T exn, eyn, pex = T(0), pey = T(0);
+      if constexpr (PML) {
+        const T dhx = hn - hn_prev, dhy = hn - hnl;
+        pex = psi_next(by_e, ld(p.psi_ex, ob), ay_e, dhx);
+        pey = psi_next(bx_e, ld(p.psi_ey, ob), ax_e, dhy);
+        exn = ax ? e_update(cax, ex_c, cbx, psi_next(iky_e, dhx, T(1), pex)) : ex_c;
+        eyn = ay ? e_update(cay, cur.ey0, cby, -psi_next(ikx_e, dhy, T(1), pey)) : cur.ey0;
+      } else {
+        exn = ax ? e_update(cax, ex_c, cbx, hn - hn_prev) : ex_c;
+        eyn = ay ? e_update(cay, cur.ey0, cby, -(hn - hnl)) : cur.ey0;
+      }
       if (any_src) {
         exn += src_sum(p, sinc, 1, i, j);
         eyn += src_sum(p, sinc, 2, i, j);
@@ -237,6 +321,12 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
         // coupling blocks of this launch
         if (!((cur.al < T(0)) != (a_prev < T(0)))) st(exo, ob, exn);
         if (!((cur.al < T(0)) != (all < T(0)))) st(eyo, ob, eyn);
+        if constexpr (PML) {
+          st(psy_out, ob, psy);
+          st(psx_out, ob, psx);
+          if (ax) st(p.psi_ex, ob, pex);
+          if (ay) st(p.psi_ey, ob, pey);
+        }
       }
     }
     hn_prev = hn;
@@ -244,6 +334,25 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
     b_prev = cur.be;
     ex_c = cur.ex1;
   }
+}
+
+// A stencil wave takes the absorbing-layer variant only when its columns
+// [iw-1, iw+64) or rows [js, j1) reach into a layer.
+template <typename T, int SEG>
+__device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int tile = xcd_tile(t, p.nst_blocks);
+  const int iw = (tile % p.tiles_x) * kWave;
+  const int j0 = ((tile / p.tiles_x) * (kBlock / kWave) + wv) * SEG;
+  if (j0 >= p.ny) return;  // uniform over the wave
+  const int j1 = min(j0 + SEG, p.ny);
+  const int js = j0 > 0 ? j0 - 1 : 0;
+  const bool layer = p.pml && (iw - 1 < p.pml_xlo || iw + kWave > p.nx - p.pml_xhi ||
+                               js < p.pml_ylo || j1 > p.ny - p.pml_yhi);
+  if (layer)
+    stencil_rows<T, SEG, true>(p, t, n);
+  else
+    stencil_rows<T, SEG, false>(p, t, n);
 }
 
 template <typename T>

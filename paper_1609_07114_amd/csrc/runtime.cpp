@@ -170,11 +170,59 @@ int fdtd::plan_problem(const fdtd_problem* p, Layout& L) {
   o = align_up(o + L.idx_elems * sizeof(int), 256);
   L.off_energy = o;
   o = align_up(o + (size_t)energy_blocks(g.nx, g.ny) * sizeof(double), 256);
+  const fdtd_pml& pm = p->pml;
+  if (pm.n_xlo < 0 || pm.n_xhi < 0 || pm.n_ylo < 0 || pm.n_yhi < 0)
+    return fail(FDTD_EINVAL, "absorbing-layer thicknesses must be >= 0");
+  L.pml = (pm.n_xlo | pm.n_xhi | pm.n_ylo | pm.n_yhi) != 0;
+  if (L.pml) {
+    if (pm.n_xlo + pm.n_xhi >= g.nx || pm.n_ylo + pm.n_yhi >= g.ny)
+      return fail(FDTD_EINVAL, "absorbing layers leave no interior cell");
+    L.px_stride = (int)align_up((size_t)L.pitch + 1, 64);
+    L.py_stride = (int)align_up((size_t)g.ny + 1, 64);
+    L.off_prof = o;
+    o = align_up(o + 6 * ((size_t)L.px_stride + L.py_stride) * ts, 256);
+    L.off_psi = o;
+    o = align_up(o + 6 * L.field_elems * ts, 256);
+  }
   L.total = o;
   return FDTD_OK;
 }
 
 namespace {
+
+// Stretched-derivative profiles along one axis of n cells of size d (CPML,
+// see fdtd_pml in the header): for E samples k d (k = 0..n) and Hz samples
+// (k + 1/2) d (k < n), (1/kappa, b, a), written into out[0..5] at stride S;
+// entries past the axis keep the identity (1, 1, 0).
+template <typename T>
+void pml_axis(int n, double d, double dt, int nlo, int nhi, const fdtd_pml& pm, int S, T* out) {
+  const double m = pm.m > 0 ? pm.m : 3.0;
+  const double kmax = pm.kappa_max >= 1 ? pm.kappa_max : 1.0;
+  const double amax = pm.alpha_max > 0 ? pm.alpha_max : 0.0;
+  const double eta0 = kMu0 * kC0;
+  const double smax = pm.sigma_scale * 0.8 * (m + 1.0) / (eta0 * d);
+  const double len = n * d, dlo = nlo * d, dhi = nhi * d;
+  for (int k = 0; k < 6; ++k)
+    for (int i = 0; i < S; ++i) out[(size_t)k * S + i] = (T)(k % 3 == 2 ? 0.0 : 1.0);
+  auto put = [&](int base, int i, double x) {
+    double rho = 0;
+    if (nlo > 0 && x < dlo) rho = (dlo - x) / dlo;
+    if (nhi > 0 && x > len - dhi) rho = (x - (len - dhi)) / dhi;
+    if (!(rho > 0)) return;
+    const double pw = std::pow(rho, m);
+    const double sigma = smax * pw;
+    const double kappa = 1.0 + (kmax - 1.0) * pw;
+    const double alpha = amax * (1.0 - rho);
+    const double b = std::exp(-(sigma / kappa + alpha) * dt / kEps0);
+    const double den = sigma * kappa + kappa * kappa * alpha;
+    const double a = sigma > 0 ? sigma * (b - 1.0) / den : 0.0;
+    out[(size_t)(base + 0) * S + i] = (T)(1.0 / kappa);
+    out[(size_t)(base + 1) * S + i] = (T)b;
+    out[(size_t)(base + 2) * S + i] = (T)a;
+  };
+  for (int i = 0; i <= n; ++i) put(0, i, i * d);
+  for (int i = 0; i < n; ++i) put(3, i, (i + 0.5) * d);
+}
 
 template <typename T>
 int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsigned char>& inside) {
@@ -382,6 +430,32 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
   sp.probe_off = (const int*)(ws + L.off_poff);
   sp.probe_comp = (const int*)(ws + L.off_pcomp);
   sp.probe_buf = (T*)(ws + L.off_pbuf);
+  // absorbing layers
+  sp.pml = L.pml ? 1 : 0;
+  sp.pml_xlo = p->pml.n_xlo;
+  sp.pml_xhi = p->pml.n_xhi;
+  sp.pml_ylo = p->pml.n_ylo;
+  sp.pml_yhi = p->pml.n_yhi;
+  sp.px_stride = L.px_stride;
+  sp.py_stride = L.py_stride;
+  if (L.pml) {
+    std::vector<T> prof(6 * ((size_t)L.px_stride + L.py_stride));
+    pml_axis<T>(nx, g.dx, g.dt, p->pml.n_xlo, p->pml.n_xhi, p->pml, L.px_stride, prof.data());
+    pml_axis<T>(ny, g.dy, g.dt, p->pml.n_ylo, p->pml.n_yhi, p->pml, L.py_stride,
+                prof.data() + 6 * (size_t)L.px_stride);
+    if ((rc = up(L.off_prof, prof.data(), prof.size() * sizeof(T))) != FDTD_OK) return rc;
+    if (hipMemsetAsync(ws + L.off_psi, 0, 6 * fb, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+      return fail(FDTD_EDEVICE, "hipMemsetAsync failed");
+    sp.px = (const T*)(ws + L.off_prof);
+    sp.py = sp.px + 6 * (size_t)L.px_stride;
+    T* ps = (T*)(ws + L.off_psi);
+    sp.psi_h[0][0] = ps;
+    sp.psi_h[0][1] = ps + fe;
+    sp.psi_h[1][0] = ps + 2 * fe;
+    sp.psi_h[1][1] = ps + 3 * fe;
+    sp.psi_ex = ps + 4 * fe;
+    sp.psi_ey = ps + 5 * fe;
+  }
   if constexpr (sizeof(T) == 4) s->sp_f = sp;
   else s->sp_d = sp;
   return FDTD_OK;
@@ -475,6 +549,16 @@ int validate_numbers(const fdtd_problem* p, const Layout& L, std::vector<unsigne
   const double lim = 1.0 / (c * std::sqrt(1.0 / (g.dx * g.dx) + 1.0 / (g.dy * g.dy)));
   if (g.dt > lim) return fail(FDTD_EINVAL, "dt=%.6g exceeds the coarse CFL limit %.6g of eq. (1)", g.dt, lim);
   inside.assign((size_t)nx * ny, 0);
+  const fdtd_pml& pm = p->pml;
+  if (L.pml && (!std::isfinite(pm.m) || !std::isfinite(pm.sigma_scale) || pm.sigma_scale < 0 ||
+                !std::isfinite(pm.kappa_max) || !std::isfinite(pm.alpha_max)))
+    return fail(FDTD_EINVAL, "absorbing-layer parameters must be finite, sigma_scale >= 0");
+  for (int k = 0; k < p->nroms && L.pml; ++k) {
+    const fdtd_rom& r = p->roms[k];
+    if (r.i0 - 1 < pm.n_xlo || r.i0 + r.ni > nx - 1 - pm.n_xhi || r.j0 - 1 < pm.n_ylo ||
+        r.j0 + r.nj > ny - 1 - pm.n_yhi)
+      return fail(FDTD_EINVAL, "region %d: it and its one-cell ring must lie outside the absorbing layers", k);
+  }
   for (int k = 0; k < p->nroms; ++k) {
     const fdtd_rom& r = p->roms[k];
     if (r.i0 < 1 || r.j0 < 1 || r.i0 + r.ni > nx - 1 || r.j0 + r.nj > ny - 1)
@@ -925,9 +1009,22 @@ constexpr size_t kStateHeader = 256;
 struct StateHeader {
   int32_t magic, dtype, steps, nx, ny, pitch;
   int64_t field_elems, xs_elems;
+  int32_t pml, pad;
 };
+// blob: header | current field set | reduced states | (layers) the two
+// Hz auxiliary fields of the current parity, then those at Ex and Ey
+size_t state_psi_off(const fdtd_rom_sim* s) {
+  return kStateHeader + align_up(3 * s->L.field_elems * s->L.tsize, 256) +
+         align_up(s->L.xs_elems * s->L.tsize, 256);
+}
 size_t state_bytes(const fdtd_rom_sim* s) {
-  return kStateHeader + align_up(3 * s->L.field_elems * s->L.tsize, 256) + s->L.xs_elems * s->L.tsize;
+  return state_psi_off(s) + (s->L.pml ? 4 * s->L.field_elems * s->L.tsize : 0);
+}
+// device address of auxiliary field k (0,1: Hz at parity par; 2,3: Ex, Ey)
+char* psi_addr(const fdtd_rom_sim* s, int k, int par) {
+  const size_t fb = s->L.field_elems * s->L.tsize;
+  char* base = s->ws + s->L.off_psi;
+  return k < 2 ? base + (size_t)(2 * par + k) * fb : base + (size_t)(2 + k) * fb;
 }
 }  // namespace
 
@@ -942,15 +1039,20 @@ int fdtd_rom_get_state(const fdtd_rom_sim* sim, void* dev_dst) {
   const Layout& L = sim->L;
   const size_t set_bytes = 3 * L.field_elems * L.tsize;
   StateHeader h{kStateMagic, sim->dtype, sim->steps, sim->nx, sim->ny, sim->pitch, (int64_t)L.field_elems,
-                (int64_t)L.xs_elems};
+                (int64_t)L.xs_elems, L.pml ? 1 : 0, 0};
   char* d = (char*)dev_dst;
   if (hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, sim->stream) != hipSuccess ||
       hipMemcpyAsync(d + kStateHeader, sim->ws + L.off_fields + (size_t)(sim->steps & 1) * set_bytes, set_bytes,
                      hipMemcpyDeviceToDevice, sim->stream) != hipSuccess ||
       (L.xs_elems > 0 && hipMemcpyAsync(d + kStateHeader + align_up(set_bytes, 256), sim->ws + L.off_xs,
-                                        L.xs_elems * L.tsize, hipMemcpyDeviceToDevice, sim->stream) != hipSuccess) ||
-      hipStreamSynchronize(sim->stream) != hipSuccess)
+                                        L.xs_elems * L.tsize, hipMemcpyDeviceToDevice, sim->stream) != hipSuccess))
     return fail(FDTD_EDEVICE, "state copy failed");
+  const size_t fb = L.field_elems * L.tsize;
+  for (int k = 0; k < 4 && L.pml; ++k)
+    if (hipMemcpyAsync(d + state_psi_off(sim) + k * fb, psi_addr(sim, k, sim->steps & 1), fb,
+                       hipMemcpyDeviceToDevice, sim->stream) != hipSuccess)
+      return fail(FDTD_EDEVICE, "state copy failed");
+  if (hipStreamSynchronize(sim->stream) != hipSuccess) return fail(FDTD_EDEVICE, "state copy failed");
   return FDTD_OK;
 }
 
@@ -964,7 +1066,8 @@ int fdtd_rom_set_state(fdtd_rom_sim* sim, const void* dev_src) {
       hipStreamSynchronize(sim->stream) != hipSuccess)
     return fail(FDTD_EDEVICE, "state header read failed");
   if (h.magic != kStateMagic || h.dtype != sim->dtype || h.nx != sim->nx || h.ny != sim->ny ||
-      h.pitch != sim->pitch || h.field_elems != (int64_t)L.field_elems || h.xs_elems != (int64_t)L.xs_elems)
+      h.pitch != sim->pitch || h.field_elems != (int64_t)L.field_elems || h.xs_elems != (int64_t)L.xs_elems ||
+      h.pml != (L.pml ? 1 : 0))
     return fail(FDTD_EINVAL, "state blob does not belong to a handle of this problem shape");
   if (h.steps < 0 || h.steps > sim->max_steps)
     return fail(FDTD_EINVAL, "state at step %d outside [0, max_steps=%d]", h.steps, sim->max_steps);
@@ -973,9 +1076,14 @@ int fdtd_rom_set_state(fdtd_rom_sim* sim, const void* dev_src) {
                      hipMemcpyDeviceToDevice, sim->stream) != hipSuccess ||
       (L.xs_elems > 0 && hipMemcpyAsync(sim->ws + L.off_xs, d + kStateHeader + align_up(set_bytes, 256),
                                         L.xs_elems * L.tsize, hipMemcpyDeviceToDevice, sim->stream) != hipSuccess) ||
-      hipMemcpyAsync(sim->ws + L.off_ctrl, ctrl, sizeof(ctrl), hipMemcpyHostToDevice, sim->stream) != hipSuccess ||
-      hipStreamSynchronize(sim->stream) != hipSuccess)
+      hipMemcpyAsync(sim->ws + L.off_ctrl, ctrl, sizeof(ctrl), hipMemcpyHostToDevice, sim->stream) != hipSuccess)
     return fail(FDTD_EDEVICE, "state copy failed");
+  const size_t fb = L.field_elems * L.tsize;
+  for (int k = 0; k < 4 && L.pml; ++k)
+    if (hipMemcpyAsync(psi_addr(sim, k, h.steps & 1), d + state_psi_off(sim) + k * fb, fb,
+                       hipMemcpyDeviceToDevice, sim->stream) != hipSuccess)
+      return fail(FDTD_EDEVICE, "state copy failed");
+  if (hipStreamSynchronize(sim->stream) != hipSuccess) return fail(FDTD_EDEVICE, "state copy failed");
   sim->steps = h.steps;
   return FDTD_OK;
 }

@@ -27,6 +27,9 @@ struct Layout {
   size_t off_ctrl = 0, off_fields = 0, off_al = 0, off_be = 0, off_src = 0;
   size_t off_pbuf = 0, off_poff = 0, off_pcomp = 0, off_roms = 0, off_mats = 0;
   size_t off_xs = 0, off_idx = 0, off_energy = 0, total = 0;
+  bool pml = false;                 // absorbing layers present
+  int px_stride = 0, py_stride = 0; // profile row lengths (x: columns, y: rows)
+  size_t off_prof = 0, off_psi = 0; // profiles [6][px] + [6][py]; 6 auxiliary fields
   size_t mats_elems = 0, xs_elems = 0, idx_elems = 0;
   int nrowblocks = 0;        // all-GEMV coupling list
   int nblocks_mixed = 0;     // GEMM for eligible shared groups + GEMV for the rest

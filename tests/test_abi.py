@@ -147,3 +147,24 @@ def test_closed_form_matches_oracle(seed):
         assert np.max(np.abs(A - A0)) <= 1e-12 * np.max(np.abs(A0))
         assert np.max(np.abs(B - B0)) <= 1e-12 * np.max(np.abs(B0))
         assert np.array_equal(C, C0)
+
+
+def test_absorbing_layer_validation():
+    """Layer thicknesses and placement are checked on the host: negative or
+    overlapping layers, and a model ring reaching into a layer, are refused."""
+    import copy
+    p = W.random_problem(5, 60, 50, 20, nroms=1, block=(6, 5), r=2, q=8)
+    roms = [dict(Rt=np.eye(8), Ft=np.zeros((8, 8)), Lt=np.zeros((8, 22)))]
+    for bad in (W.Pml(-1, 0, 0, 0), W.Pml(30, 30, 0, 0), W.Pml(0, 0, 25, 25)):
+        q = copy.deepcopy(p)
+        q.pml = bad
+        with pytest.raises(capi.FdtdError):
+            capi.fdtd_rom_workspace_size(capi.ProblemStruct.from_workload(q, roms))
+    s = p.roms[0]
+    q = copy.deepcopy(p)
+    q.pml = W.Pml(n_xlo=s.i0, n_xhi=0, n_ylo=0, n_yhi=0)   # ring column i0-1 inside the layer
+    with pytest.raises(capi.FdtdError) as e:
+        capi.fdtd_rom_coupled_update(capi.ProblemStruct.from_workload(q, roms), 0)
+    assert "absorbing" in str(e.value)
+    q.pml = W.Pml(n_xlo=s.i0 - 1, n_xhi=2, n_ylo=2, n_yhi=2)
+    capi.fdtd_rom_coupled_update(capi.ProblemStruct.from_workload(q, roms), 0)
