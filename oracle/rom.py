@@ -117,11 +117,17 @@ def sprim_basis(model, q, p0):
 
 
 def congruence(model, V1, V2):
-    V = sp.block_diag([sp.csr_matrix(V1), sp.csr_matrix(V2)]).tocsr()
-    Rt = (V.T @ (model["R"] @ V)).toarray()
+    """Eqs. (11)-(12): R~ = V^T R V, F~ = V^T F V, L~ = V^T L with the block
+    diagonal V = diag(V1, V2) (dense; R, F, L sparse)."""
+    n1, q1 = V1.shape
+    n2, q2 = V2.shape
+    V = np.zeros((n1 + n2, q1 + q2))
+    V[:n1, :q1] = V1
+    V[n1:, q1:] = V2
+    Rt = V.T @ (model["R"] @ V)
     Rt = 0.5 * (Rt + Rt.T)
-    Ft = (V.T @ (model["F"] @ V)).toarray()
-    Lt = (V.T @ model["L"]).toarray()
+    Ft = V.T @ (model["F"] @ V)
+    Lt = V.T @ model["L"].toarray()
     return Rt, Ft, Lt
 
 
