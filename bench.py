@@ -271,6 +271,57 @@ def bench_adjoint(ckpt=200, log=None):
             "grad_eps_rel_l2_vs_f64": rel(ge32, ge64), "grad_sigma_rel_l2_vs_f64": rel(gs32, gs64)}
 
 
+# The paper's whole-run times of the proposed method (model building
+# included) for the two open guides: Matlab on one 3.6 GHz CPU, step counts
+# not stated (Tabs. II, III).  Context only.
+PAPER_RUNTIME_S = {"E3": 118.5, "E4": 23.8}
+
+
+def bench_waveguides(steps=None, log=None):
+    """The open-waveguide experiments at the paper's sizes (Sec. VI-B: two
+    order-648 models; Sec. VI-C: one order-1920 model of four copper rods),
+    models built on the host by the library, then the full run on the
+    device from captured graphs.  Each step is one launch whose cost is the
+    coupling blocks streaming the update matrices: their bytes per step are
+    sum over models of (q + ports)^2 x element size."""
+    import numpy as np
+    import workloads as W
+    from paper_1609_07114_amd import romgen
+    from paper_1609_07114_amd.sim import Simulation
+    out = {}
+    for name, mk, n in (("E3", W.iris_waveguide, 4000), ("E4", W.rods_reflection, 2000)):
+        n = steps or n
+        prob = mk(nsteps=n)
+        t0 = time.perf_counter()
+        roms = romgen.build_roms(prob)
+        t_build = time.perf_counter() - t0
+        res = {}
+        for dt_name in ("f32", "f64"):
+            es = 4 if dt_name == "f32" else 8
+            gbytes = sum((s.q + s.n_ports) ** 2 * es for s in prob.roms)
+            with Simulation(prob, roms, dtype=dt_name) as sm:
+                sm.set_graph(min(n, 200))
+                sm.run(min(n, 200))                     # untimed: capture and first replays
+            with Simulation(prob, roms, dtype=dt_name) as sm:
+                sm.set_graph(min(n, 200))
+                t, ev = _timed(sm.stream, lambda: sm.run(n))
+                pr = sm.probes()
+            res[dt_name] = {"run_s": round(t, 4), "us_per_step": round(ev * 1e3 / n, 3),
+                            "matrix_bytes_per_step": gbytes,
+                            "matrix_GBps": round(gbytes / (ev / 1e3 / n) / 1e9, 1),
+                            "finite": bool(np.all(np.isfinite(pr)))}
+        out[name] = {"workload": f"{prob.name} {prob.nx}x{prob.ny}, models q={[s.q for s in prob.roms]}, "
+                                 f"{n} steps, CFL number {prob.dt / W.courant_dt(prob.dx / prob.roms[0].r, prob.dy / prob.roms[0].r, 1.0):.2f}",
+                     "model_build_s": round(t_build, 2), **res,
+                     "total_s_f64": round(t_build + res["f64"]["run_s"], 3),
+                     "paper_runtime_s": PAPER_RUNTIME_S[name],
+                     "paper_context": "Matlab, one 3.6 GHz CPU, step count not stated"}
+        if log:
+            log(f"{name}: build {t_build:.2f} s, f32 {res['f32']['us_per_step']} us/step, "
+                f"f64 {res['f64']['us_per_step']} us/step")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,7 +331,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched, many-copies and adjoint forms")
-    ap.add_argument("--only", choices=["batched", "many_copies", "adjoint", "hbm_resident"], default=None,
+    ap.add_argument("--only", choices=["batched", "many_copies", "adjoint", "hbm_resident", "waveguides"], default=None,
                     help="run one form alone and print its JSON (profiling)")
     ap.add_argument("--form-steps", type=int, default=None, help="timed steps of the batched / many-copies form")
     ap.add_argument("--copy-ceiling", action="store_true", help="only measure device copy rates and exit")
@@ -307,7 +358,7 @@ def main():
         log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
         kw = {} if args.form_steps is None or args.only == "adjoint" else {"steps": args.form_steps}
         fn = {"batched": bench_batched, "many_copies": bench_many_copies, "adjoint": bench_adjoint,
-              "hbm_resident": bench_hbm_resident}[args.only]
+              "hbm_resident": bench_hbm_resident, "waveguides": bench_waveguides}[args.only]
         print(json.dumps({args.only: fn(log=log, **kw)}), flush=True)
         return
     total = args.warmup + args.steps
@@ -383,6 +434,7 @@ def main():
         log(f"many copies {out['many_copies']['value']:.0f} Mcell/s (GEMV {out['many_copies']['gemv_per_copy']:.0f})")
         out["adjoint"] = bench_adjoint(log=log)
         log(f"adjoint {out['adjoint']['ratio_vs_forward']}x forward")
+        out["waveguides"] = bench_waveguides(log=log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     else:

@@ -75,7 +75,8 @@ typedef struct {
  * x0: host [q] initial reduced state or NULL for zero; the interface E
  * starts at L~^T x0.  group >= 0: regions with the same group use one
  * copy of the matrices on the device (their Rt/Ft/Lt must be identical and
- * their surroundings must give identical interface half cells). */
+ * their surroundings must give identical interface half cells).
+ * Limits: 1 <= q <= 4096 and np = 2 (ni + nj) <= 1024, else FDTD_EINVAL. */
 typedef struct {
   int32_t i0, j0, ni, nj;
   int32_t q;

@@ -274,12 +274,6 @@ struct Solver {
 
 using Cols = std::vector<std::vector<double>>;  // column vectors
 
-double dot_w(const std::vector<double>& x, const std::vector<double>& y, const std::vector<double>& w) {
-  double s = 0;
-  for (size_t k = 0; k < x.size(); ++k) s += x[k] * w[k] * y[k];
-  return s;
-}
-
 // Krylov directions, ordered as described in rom builder docs.
 bool krylov_dirs(Solver& sol, const FineModel& fm, int ncols, Cols& dirs, std::string& err) {
   const int n = fm.n;
@@ -296,39 +290,61 @@ bool krylov_dirs(Solver& sol, const FineModel& fm, int ncols, Cols& dirs, std::s
   }
   double ref = -1;
   const double tol = 1e-12;
-  std::vector<double> Mv(n);
+  Cols MX;
+  std::vector<double> C;
   while ((int)dirs.size() < ncols) {
     const int m = (int)X.size();
-    // two passes of mass-orthogonalisation against earlier directions
-    for (int pass = 0; pass < 2; ++pass)
-      for (auto& y : X) {
-        for (int k = 0; k < n; ++k) Mv[k] = mass[k] * y[k];
-        for (auto& d : dirs) {
-          double cf = 0;
-          for (int k = 0; k < n; ++k) cf += d[k] * Mv[k];
-          for (int k = 0; k < n; ++k) y[k] -= cf * d[k];
-        }
+    std::vector<double*> Xp(m);
+    std::vector<const double*> MXp(m);
+    MX.assign(m, std::vector<double>(n));
+    for (int i = 0; i < m; ++i) {
+      Xp[i] = X[i].data();
+      MXp[i] = MX[i].data();
+    }
+    auto weigh = [&]() {
+      for (int i = 0; i < m; ++i)
+        for (int k = 0; k < n; ++k) MX[i][k] = mass[k] * X[i][k];
+    };
+    // two passes of mass-orthogonalisation of the block against all
+    // earlier directions: X -= D (D^T M X)
+    if (!dirs.empty()) {
+      const int kd = (int)dirs.size();
+      std::vector<const double*> Dp(kd);
+      for (int j = 0; j < kd; ++j) Dp[j] = dirs[j].data();
+      C.resize((size_t)kd * m);
+      for (int pass = 0; pass < 2; ++pass) {
+        weigh();
+        fdtd::la::gram(Dp.data(), kd, MXp.data(), m, n, C.data(), m);
+        for (double& c : C) c = -c;
+        fdtd::la::add_comb(Xp.data(), m, Dp.data(), kd, C.data(), m, n);
       }
+    }
     std::vector<double> G((size_t)m * m), Q((size_t)m * m), w(m);
+    weigh();
+    std::vector<const double*> Xc(Xp.begin(), Xp.end());
+    fdtd::la::gram(Xc.data(), m, MXp.data(), m, n, G.data(), m, false, true);
     for (int i = 0; i < m; ++i)
-      for (int j = 0; j <= i; ++j) G[(size_t)i * m + j] = G[(size_t)j * m + i] = dot_w(X[i], X[j], mass);
-    fdtd::la::sym_eig(m, G.data(), Q.data(), w.data());
+      for (int j = 0; j < i; ++j) G[(size_t)j * m + i] = G[(size_t)i * m + j];
+    if (!fdtd::la::sym_eig(m, G.data(), Q.data(), w.data())) {
+      err = "eigen-decomposition of a Krylov block did not converge";
+      return false;
+    }
     std::vector<int> order(m);
     for (int i = 0; i < m; ++i) order[i] = i;
     std::sort(order.begin(), order.end(), [&](int x, int y) { return w[x] > w[y]; });
     if (ref < 0) ref = w[order[0]];
-    Cols W;
-    for (int oi : order) {
-      if (!(w[oi] > tol * tol * ref)) break;
-      std::vector<double> v(n, 0.0);
-      for (int j = 0; j < m; ++j) {
-        const double z = Q[(size_t)j * m + oi];
-        if (z == 0.0) continue;
-        for (int k = 0; k < n; ++k) v[k] += z * X[j][k];
-      }
-      const double s = 1.0 / std::sqrt(w[oi]);
-      for (int k = 0; k < n; ++k) v[k] *= s;
-      W.push_back(std::move(v));
+    // new directions: eigenvectors of the block's mass Gram matrix in
+    // decreasing order, W_o = X z_o / sqrt(w_o)
+    int nw = 0;
+    while (nw < m && w[order[nw]] > tol * tol * ref) ++nw;
+    Cols W(nw, std::vector<double>(n, 0.0));
+    if (nw > 0) {
+      std::vector<double*> Wp(nw);
+      for (int o = 0; o < nw; ++o) Wp[o] = W[o].data();
+      std::vector<double> Z((size_t)m * nw);
+      for (int j = 0; j < m; ++j)
+        for (int o = 0; o < nw; ++o) Z[(size_t)j * nw + o] = Q[(size_t)j * m + order[o]] / std::sqrt(w[order[o]]);
+      fdtd::la::add_comb(Wp.data(), nw, Xc.data(), m, Z.data(), nw, n);
     }
     if (W.empty()) break;
     if (dirs.size() + W.size() >= (size_t)ncols) {
@@ -344,48 +360,54 @@ bool krylov_dirs(Solver& sol, const FineModel& fm, int ncols, Cols& dirs, std::s
     for (auto& v : W) dirs.push_back(std::move(v));
     X.swap(Xn);
   }
-  (void)err;
   return true;
 }
 
-// Gram-Schmidt in order over rows [r0, r0+len) of the directions.
+// Gram-Schmidt in order over rows [r0, r0+len) of the directions: each
+// direction, orthogonalised (two passes) against the ones already kept, is
+// kept if its residual stays above 1e-10 of its norm, until q are kept.
+// Worked in blocks of 32 directions: two block passes against the vectors
+// kept before the block, then in order within the block.
 Cols gs_part(const Cols& dirs, int r0, int len, int q) {
   Cols out;
-  for (const auto& d : dirs) {
-    if ((int)out.size() >= q) break;
-    std::vector<double> v(d.begin() + r0, d.begin() + r0 + len);
-    double nv = 0;
-    for (double x : v) nv += x * x;
-    nv = std::sqrt(nv);
-    if (nv == 0.0) continue;
-    for (int pass = 0; pass < 2; ++pass)
-      for (const auto& u : out) {
-        double cf = 0;
-        for (int k = 0; k < len; ++k) cf += u[k] * v[k];
-        for (int k = 0; k < len; ++k) v[k] -= cf * u[k];
+  constexpr size_t kB = 32;
+  std::vector<double> C;
+  for (size_t next = 0; next < dirs.size() && (int)out.size() < q; next += kB) {
+    const int b = (int)std::min(kB, dirs.size() - next);
+    Cols blk(b);
+    std::vector<double> nv(b);
+    std::vector<double*> Bp(b);
+    for (int i = 0; i < b; ++i) {
+      blk[i].assign(dirs[next + i].begin() + r0, dirs[next + i].begin() + r0 + len);
+      nv[i] = std::sqrt(fdtd::la::dot(blk[i].data(), blk[i].data(), len));
+      Bp[i] = blk[i].data();
+    }
+    if (!out.empty()) {
+      const int k = (int)out.size();
+      std::vector<const double*> U(k);
+      for (int j = 0; j < k; ++j) U[j] = out[j].data();
+      C.resize((size_t)k * b);
+      std::vector<const double*> Bc(Bp.begin(), Bp.end());
+      for (int pass = 0; pass < 2; ++pass) {
+        fdtd::la::gram(U.data(), k, Bc.data(), b, len, C.data(), b);
+        for (double& c : C) c = -c;
+        fdtd::la::add_comb(Bp.data(), b, U.data(), k, C.data(), b, len);
       }
-    double nr = 0;
-    for (double x : v) nr += x * x;
-    nr = std::sqrt(nr);
-    if (nr <= 1e-10 * nv) continue;
-    for (double& x : v) x /= nr;
-    out.push_back(std::move(v));
+    }
+    const size_t first = out.size();
+    for (int i = 0; i < b && (int)out.size() < q; ++i) {
+      if (nv[i] == 0.0) continue;
+      double* v = blk[i].data();
+      for (int pass = 0; pass < 2; ++pass)
+        for (size_t u = first; u < out.size(); ++u)
+          fdtd::la::axpy(-fdtd::la::dot(out[u].data(), v, len), out[u].data(), v, len);
+      const double nr = std::sqrt(fdtd::la::dot(v, v, len));
+      if (nr <= 1e-10 * nv[i]) continue;
+      for (int t = 0; t < len; ++t) v[t] /= nr;
+      out.push_back(std::move(blk[i]));
+    }
   }
   return out;
-}
-
-// symmetric matrix function A^p via Jacobi, row-major n x n
-void sym_pow(int n, const double* A, double p, double* out) {
-  std::vector<double> W(A, A + (size_t)n * n), Q((size_t)n * n), w(n);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < i; ++j) W[(size_t)i * n + j] = W[(size_t)j * n + i] = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
-  fdtd::la::sym_eig(n, W.data(), Q.data(), w.data());
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      double s = 0;
-      for (int k = 0; k < n; ++k) s += Q[(size_t)i * n + k] * std::pow(w[k], p) * Q[(size_t)j * n + k];
-      out[(size_t)i * n + j] = s;
-    }
 }
 
 }  // namespace
@@ -416,7 +438,7 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
     Cols dirs;
     std::string err;
     const int need = std::max(q1, q2);
-    krylov_dirs(sol, fm, need + 8, dirs, err);
+    if (!krylov_dirs(sol, fm, need + 8, dirs, err)) return fail(FDTD_EINVAL, "%s", err.c_str());
     Cols V1 = gs_part(dirs, 0, fm.nE, q1);
     Cols V2 = gs_part(dirs, fm.nE, fm.nH, q2);
     if ((int)V1.size() < q1 || (int)V2.size() < q2)
@@ -424,53 +446,76 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
     const int q = q1 + q2, np = fm.np;
     // congruence (eqs. (11)-(12))
     std::vector<double> R((size_t)q * q, 0.0), F((size_t)q * q, 0.0);
-    for (int a = 0; a < q1; ++a)
-      for (int b2 = 0; b2 <= a; ++b2) {
-        double sr = 0, sf = 0;
-        for (int e = 0; e < fm.nE; ++e) {
-          const double pr = V1[a][e] * V1[b2][e];
-          sr += pr * fm.De[e];
-          sf += pr * fm.Ds[e];
-        }
-        R[(size_t)a * q + b2] = R[(size_t)b2 * q + a] = sr / P.dt;
-        F[(size_t)a * q + b2] = F[(size_t)b2 * q + a] = 0.5 * sf;
-      }
-    std::vector<double> KV(fm.nE);
-    std::vector<double> Kt((size_t)q1 * q2);  // K~ = V1^T K V2
-    for (int c = 0; c < q2; ++c) {
-      spmv(fm.K, V2[c].data(), KV.data());
+    {
+      Cols VD(q1, std::vector<double>(fm.nE)), VS(q1, std::vector<double>(fm.nE));
+      std::vector<const double*> V1p(q1), VDp(q1), VSp(q1);
       for (int a = 0; a < q1; ++a) {
-        double s = 0;
-        for (int e = 0; e < fm.nE; ++e) s += V1[a][e] * KV[e];
-        Kt[(size_t)a * q2 + c] = s;
+        for (int e = 0; e < fm.nE; ++e) {
+          VD[a][e] = V1[a][e] * fm.De[e];
+          VS[a][e] = V1[a][e] * fm.Ds[e];
+        }
+        V1p[a] = V1[a].data();
+        VDp[a] = VD[a].data();
+        VSp[a] = VS[a].data();
       }
+      std::vector<double> GR((size_t)q1 * q1), GF((size_t)q1 * q1);
+      fdtd::la::gram(VDp.data(), q1, V1p.data(), q1, fm.nE, GR.data(), q1, false, true);
+      fdtd::la::gram(VSp.data(), q1, V1p.data(), q1, fm.nE, GF.data(), q1, false, true);
+      for (int a = 0; a < q1; ++a)
+        for (int b2 = 0; b2 <= a; ++b2) {
+          R[(size_t)a * q + b2] = R[(size_t)b2 * q + a] = GR[(size_t)a * q1 + b2] / P.dt;
+          F[(size_t)a * q + b2] = F[(size_t)b2 * q + a] = 0.5 * GF[(size_t)a * q1 + b2];
+        }
     }
-    for (int a = 0; a < q2; ++a)
-      for (int b2 = 0; b2 <= a; ++b2) {
-        double s = 0;
-        for (int h = 0; h < fm.nH; ++h) s += V2[a][h] * V2[b2][h];
-        R[(size_t)(q1 + a) * q + q1 + b2] = R[(size_t)(q1 + b2) * q + q1 + a] = fm.Dm / P.dt * s;
+    std::vector<double> Kt((size_t)q1 * q2);  // K~ = V1^T K V2
+    {
+      Cols KV(q2, std::vector<double>(fm.nE));
+      std::vector<const double*> KVp(q2), V1p(q1), V2p(q2);
+      for (int c = 0; c < q2; ++c) {
+        spmv(fm.K, V2[c].data(), KV[c].data());
+        KVp[c] = KV[c].data();
+        V2p[c] = V2[c].data();
       }
-    // eq. (27): s_k of R11^{-1/2} K~ R22^{-1/2} against 2/dt
-    std::vector<double> R11((size_t)q1 * q1), R22((size_t)q2 * q2);
+      for (int a = 0; a < q1; ++a) V1p[a] = V1[a].data();
+      fdtd::la::gram(V1p.data(), q1, KVp.data(), q2, fm.nE, Kt.data(), q2);
+      std::vector<double> GH((size_t)q2 * q2);
+      fdtd::la::gram(V2p.data(), q2, V2p.data(), q2, fm.nH, GH.data(), q2, false, true);
+      for (int a = 0; a < q2; ++a)
+        for (int b2 = 0; b2 <= a; ++b2)
+          R[(size_t)(q1 + a) * q + q1 + b2] = R[(size_t)(q1 + b2) * q + q1 + a] = fm.Dm / P.dt * GH[(size_t)a * q2 + b2];
+    }
+    // eq. (27): singular values s_k of R11^{-1/2} K~ R22^{-1/2} against 2/dt.
+    // With Cholesky factors R11 = L1 L1^T, R22 = L2 L2^T the matrix
+    // M = L1^{-1} K~ L2^{-T} is orthogonally equivalent to it (R^{1/2} =
+    // L Omega with Omega orthogonal), and lowering singular values commutes
+    // with orthogonal factors, so K~' = L1 clip(M) L2^T is the same update.
+    std::vector<double> L1((size_t)q1 * q1), L2((size_t)q2 * q2);
     for (int a = 0; a < q1; ++a)
-      for (int b2 = 0; b2 < q1; ++b2) R11[(size_t)a * q1 + b2] = P.dt * R[(size_t)a * q + b2];
+      for (int b2 = 0; b2 < q1; ++b2) L1[(size_t)a * q1 + b2] = P.dt * R[(size_t)a * q + b2];
     for (int a = 0; a < q2; ++a)
-      for (int b2 = 0; b2 < q2; ++b2) R22[(size_t)a * q2 + b2] = P.dt * R[(size_t)(q1 + a) * q + q1 + b2];
-    std::vector<double> R11m((size_t)q1 * q1), R22m((size_t)q2 * q2), R11p((size_t)q1 * q1), R22p((size_t)q2 * q2);
-    sym_pow(q1, R11.data(), -0.5, R11m.data());
-    sym_pow(q2, R22.data(), -0.5, R22m.data());
-    std::vector<double> tmp((size_t)q1 * q2), M((size_t)q1 * q2);
-    fdtd::la::gemm(q1, q2, q1, R11m.data(), Kt.data(), tmp.data());
-    fdtd::la::gemm(q1, q2, q2, tmp.data(), R22m.data(), M.data());
+      for (int b2 = 0; b2 < q2; ++b2) L2[(size_t)a * q2 + b2] = P.dt * R[(size_t)(q1 + a) * q + q1 + b2];
+    if (!fdtd::la::cholesky(q1, L1.data()) || !fdtd::la::cholesky(q2, L2.data()))
+      return fail(FDTD_EINVAL, "reduced R~ not positive definite (basis lost rank)");
+    // X = L1^{-1} K~ by rows, then each row m of M solves L2 m^T = x^T
+    std::vector<double> M(Kt);
+    for (int a = 0; a < q1; ++a) {
+      double* xa = M.data() + (size_t)a * q2;
+      for (int b2 = 0; b2 < a; ++b2) fdtd::la::axpy(-L1[(size_t)a * q1 + b2], M.data() + (size_t)b2 * q2, xa, q2);
+      const double inv = 1.0 / L1[(size_t)a * q1 + a];
+      for (int c = 0; c < q2; ++c) xa[c] *= inv;
+    }
+    for (int a = 0; a < q1; ++a) {
+      double* ma = M.data() + (size_t)a * q2;
+      for (int c = 0; c < q2; ++c) ma[c] = (ma[c] - fdtd::la::dot(L2.data() + (size_t)c * q2, ma, c)) / L2[(size_t)c * q2 + c];
+    }
     std::vector<double> MtM((size_t)q2 * q2, 0.0), Wv((size_t)q2 * q2), s2(q2);
-    for (int i = 0; i < q2; ++i)
-      for (int j = 0; j < q2; ++j) {
-        double s = 0;
-        for (int k = 0; k < q1; ++k) s += M[(size_t)k * q2 + i] * M[(size_t)k * q2 + j];
-        MtM[(size_t)i * q2 + j] = s;
-      }
-    fdtd::la::sym_eig(q2, MtM.data(), Wv.data(), s2.data());
+    for (int a = 0; a < q1; ++a) {
+      const double* ma = M.data() + (size_t)a * q2;
+      for (int i = 0; i < q2; ++i)
+        if (ma[i] != 0.0) fdtd::la::axpy(ma[i], ma, MtM.data() + (size_t)i * q2, q2);
+    }
+    if (!fdtd::la::sym_eig(q2, MtM.data(), Wv.data(), s2.data()))
+      return fail(FDTD_EINVAL, "eigen-decomposition for the CFL clip did not converge");
     double smax = 0;
     for (int k = 0; k < q2; ++k) smax = std::max(smax, std::sqrt(std::max(0.0, s2[k])));
     const double lim = theta * 2.0 / P.dt;
@@ -479,6 +524,7 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
     if (P.clip && smax > lim) {
       clipped = 1;
       smax_after = 0;
+      std::vector<double> wk(q2), uk(q1);
       for (int k = 0; k < q2; ++k) {
         const double sk = std::sqrt(std::max(0.0, s2[k]));
         if (sk <= lim) {
@@ -487,20 +533,18 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
         }
         smax_after = std::max(smax_after, lim);
         // M -= (s_k - lim) u_k w_k^T with u_k = M w_k / s_k
-        std::vector<double> wk(q2), uk(q1);
         for (int i = 0; i < q2; ++i) wk[i] = Wv[(size_t)i * q2 + k];
-        for (int a = 0; a < q1; ++a) {
-          double s = 0;
-          for (int i = 0; i < q2; ++i) s += M[(size_t)a * q2 + i] * wk[i];
-          uk[a] = s / sk;
-        }
-        for (int a = 0; a < q1; ++a)
-          for (int i = 0; i < q2; ++i) M[(size_t)a * q2 + i] -= (sk - lim) * uk[a] * wk[i];
+        for (int a = 0; a < q1; ++a) uk[a] = fdtd::la::dot(M.data() + (size_t)a * q2, wk.data(), q2) / sk;
+        for (int a = 0; a < q1; ++a) fdtd::la::axpy(-(sk - lim) * uk[a], wk.data(), M.data() + (size_t)a * q2, q2);
       }
-      sym_pow(q1, R11.data(), 0.5, R11p.data());
-      sym_pow(q2, R22.data(), 0.5, R22p.data());
-      fdtd::la::gemm(q1, q2, q1, R11p.data(), M.data(), tmp.data());
-      fdtd::la::gemm(q1, q2, q2, tmp.data(), R22p.data(), Kt.data());
+      // K~ = L1 M L2^T
+      std::vector<double> T((size_t)q1 * q2, 0.0);
+      for (int a = 0; a < q1; ++a)
+        for (int b2 = 0; b2 <= a; ++b2)
+          fdtd::la::axpy(L1[(size_t)a * q1 + b2], M.data() + (size_t)b2 * q2, T.data() + (size_t)a * q2, q2);
+      for (int a = 0; a < q1; ++a)
+        for (int c = 0; c < q2; ++c)
+          Kt[(size_t)a * q2 + c] = fdtd::la::dot(T.data() + (size_t)a * q2, L2.data() + (size_t)c * q2, c + 1);
     }
     for (int a = 0; a < q1; ++a)
       for (int c = 0; c < q2; ++c) {

@@ -168,3 +168,22 @@ def test_absorbing_layer_validation():
     assert "absorbing" in str(e.value)
     q.pml = W.Pml(n_xlo=s.i0 - 1, n_xhi=2, n_ylo=2, n_yhi=2)
     capi.fdtd_rom_coupled_update(capi.ProblemStruct.from_workload(q, roms), 0)
+
+
+def test_model_order_limits():
+    """Orders up to 4096 are accepted (the rods region of Sec. VI-C needs
+    1920), larger ones are refused before any device work."""
+    import copy
+    p = W.rods_reflection(nsteps=10)
+    np_ = p.roms[0].n_ports
+
+    def model(q):
+        return [dict(Rt=np.eye(q), Ft=np.zeros((q, q)), Lt=np.zeros((q, np_)))]
+
+    n = capi.fdtd_rom_workspace_size(_struct(p, model(1920)))
+    assert n > (1920 + np_) ** 2 * 8
+    q = copy.deepcopy(p)
+    q.roms[0].q = 4097
+    with pytest.raises(capi.FdtdError) as e:
+        capi.fdtd_rom_workspace_size(_struct(q, model(4097)))
+    assert "4096" in str(e.value)

@@ -1,0 +1,138 @@
+"""The paper's open-waveguide experiments on the oracle (Sec. VI-B, VI-C):
+geometry and model sizes as the paper states them, the CFL extension that
+its time steps need, and the reflections it reports qualitatively (the
+transition into an empty reduced region reflects almost nothing, the rods
+and irises reflect far more).  Thresholds are stated per test; the paper
+prints curves, not numbers, for these reflections."""
+import copy
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fine, rom
+from oracle import sim as osim
+
+NSTEPS = 1500
+
+
+def _fine_cfl_number(p):
+    """dt over the vacuum Courant limit of the finest mesh (eq. (1))."""
+    r = p.roms[0].r
+    return p.dt / W.courant_dt(p.dx / r, p.dy / r, 1.0)
+
+
+def _run(p, roms, nsteps=NSTEPS):
+    run = osim.CoupledRun(p, roms, mode="closed")
+    out = np.empty((nsteps, len(p.probes)))
+    peak = 0.0
+    for n in range(nsteps):
+        run.step()
+        out[n] = run.probes()
+        peak = max(peak, float(np.abs(run.f.ey).max()))
+    return out, peak
+
+
+def _bare(p):
+    """The same guide with the regions left as plain coarse cells."""
+    q = copy.deepcopy(p)
+    q.roms = []
+    return q
+
+
+@pytest.fixture(scope="module")
+def rods():
+    p = W.rods_reflection(nsteps=NSTEPS)
+    e = W.rods_reflection(nsteps=NSTEPS, rods=False)
+    s = p.roms[0]
+    full = rom.build_rom(s.eps_r, s.sigma, s.r, p.dx, p.dy, p.dt, s.q, s.f_max)
+    return dict(p=p, m=[dict(Rt=full["Rt"], Ft=full["Ft"], Lt=full["Lt"])], full=full, e=e,
+                me=osim.build_roms(e))
+
+
+@pytest.fixture(scope="module")
+def irises():
+    p = W.iris_waveguide(nsteps=NSTEPS)
+    e = W.iris_waveguide(nsteps=NSTEPS, irises=False)
+    return dict(p=p, m=osim.build_roms(p), e=e, me=osim.build_roms(e))
+
+
+def test_iris_geometry_and_sizes():
+    p = W.iris_waveguide()
+    assert (p.nx, p.ny) == (80, 14) and p.nx * p.dx == pytest.approx(4.0) and p.ny * p.dy == pytest.approx(0.7)
+    assert (p.pml.n_xlo, p.pml.n_xhi, p.pml.n_ylo, p.pml.n_yhi) == (10, 10, 0, 0)
+    assert len(p.roms) == 2
+    for s in p.roms:
+        assert s.r == 3 and s.ni * p.dx == pytest.approx(0.5) and s.nj * p.dy == pytest.approx(0.5)
+        # 2,760 fine states per region and order 648 (Sec. VI-B)
+        assert fine.state_count(s.r * s.ni, s.r * s.nj) == 2760 and s.q == 648
+        # region and its one-cell ring clear of the layers
+        assert s.i0 - 1 >= p.pml.n_xlo and s.i0 + s.ni + 1 <= p.nx - p.pml.n_xhi
+    # 0.99 x a two-fold extension of the fine limit: the CFL number 1.98
+    assert _fine_cfl_number(p) == pytest.approx(1.98, rel=1e-12)
+    # each iris: metal on one fine column but for an aperture of 18 cells
+    for s in p.roms:
+        metal = s.sigma > 0
+        assert metal.sum() == 30 - 18 and np.all(metal.any(axis=0) == (np.arange(30) == 15))
+
+
+def test_rods_geometry_and_sizes():
+    p = W.rods_reflection()
+    assert (p.nx, p.ny) == (66, 40) and p.dx == 1e-3
+    assert (p.pml.n_xlo, p.pml.n_xhi) == (15, 15)
+    (s,) = p.roms
+    assert (s.i0, s.j0, s.ni, s.nj, s.r) == (39, 16, 8, 8, 6)
+    assert fine.state_count(48, 48) == 7008 and s.q == 1920
+    assert _fine_cfl_number(p) == pytest.approx(2.97, rel=1e-12)
+    # four disjoint rods of 1 mm radius: about pi (6 cells)^2 fine cells each
+    metal = s.sigma > 0
+    assert metal.sum() == pytest.approx(4 * np.pi * 36, rel=0.03)
+    assert metal[:24, :24].sum() == metal[24:, 24:].sum() == metal[:24, 24:].sum() == metal[24:, :24].sum()
+    assert p.sources[0].i0 == 17 and {pr.i for pr in p.probes} == {19} and len(p.probes) == 40
+
+
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")
+def test_rods_clip_is_what_makes_the_step_stable(rods):
+    """At the paper's 2.97 CFL number the reduced model needs the eq. (27)
+    clip: the same model unclipped (the oracle's basis and congruence,
+    no clip) sends the coupled run off to infinity within the run, the
+    clipped one stays bounded by the pulse's peak."""
+    p = rods["p"]
+    m = rods["full"]
+    assert m["clipped"] and m["smax_before"] > 2 / p.dt and m["smax_after"] <= 0.99 * 2 / p.dt * (1 + 1e-12)
+    Rt, Ft, Lt = rom.congruence(m["model"], m["V1"], m["V2"])
+    raw = dict(Rt=Rt, Ft=Ft, Lt=Lt)
+    _, peak_raw = _run(p, [raw], 400)
+    _, peak_ok = _run(p, rods["m"], 400)
+    assert peak_ok < 10.0
+    assert not np.isfinite(peak_raw) or peak_raw > 1e6 * peak_ok
+
+
+def test_rod_reflection_exceeds_interface_reflection(rods):
+    """Reflected energy on the probe line (line sum of Ey, i.e. the guide's
+    fundamental mode) relative to the incident pulse: the empty region's
+    interface reflects below 1e-4 of it, the rods at least ten times
+    as much as the interface."""
+    bare, _ = _run(_bare(rods["e"]), [])
+    full, _ = _run(rods["p"], rods["m"])
+    empty, _ = _run(rods["e"], rods["me"])
+    line = lambda s: s.sum(axis=1)
+    inc = np.sum(line(bare) ** 2)
+    r_rods = np.sum(line(full - bare) ** 2) / inc
+    r_face = np.sum(line(empty - bare) ** 2) / inc
+    assert r_face < 1e-4, r_face
+    assert r_rods > 10 * r_face and r_rods > 5e-4, (r_rods, r_face)
+
+
+def test_irises_reflect_and_empty_regions_do_not(irises):
+    """Near-source Hz: the irises send back more than 1 % of the incident
+    energy, the empty reduced regions less than 1e-4 of it."""
+    bare, _ = _run(_bare(irises["e"]), [])
+    full, _ = _run(irises["p"], irises["m"])
+    empty, _ = _run(irises["e"], irises["me"])
+    inc = np.sum(bare[:, 2] ** 2)
+    assert np.sum((full - bare)[:, 2] ** 2) / inc > 1e-2
+    assert np.sum((empty - bare)[:, 2] ** 2) / inc < 1e-4
+    # with empty regions the far-end signal is the bare guide's up to the
+    # refined regions' lower numerical dispersion (3e-4 of the energy here)
+    assert np.sum((empty - bare)[:, 0] ** 2) < 1e-3 * np.sum(bare[:, 0] ** 2)

@@ -393,6 +393,87 @@ def stencil_only(n: int = 8192, nsteps: int = 200, material: bool = True,
                    [Probe(HZ, n // 4, n // 4)], nsteps, dtype)
 
 
+# Conductivity standing in for metal: copper for the rods (Sec. VI-C) and
+# for the "PEC" irises (Sec. VI-B), whose thickness the paper does not give.
+SIGMA_COPPER = 5.8e7
+
+
+def iris_waveguide(nsteps: int = 4000, q: int = 648, irises: bool = True,
+                   dtype: str = "f64", aperture: int = 18, f_bw: float = 0.4e9,
+                   cfl_gain: float = 2.0) -> Problem:
+    """Waveguide with two thin metal irises (Sec. VI-B): 4 m x 0.7 m, 5 cm
+    coarse cells (80 x 14), PEC walls at y = 0 and 0.7 m, absorbing layers 10
+    coarse cells deep at both x ends.  Two 0.5 m x 0.5 m regions (10 x 10
+    coarse cells at i0 = 25 and 45, j0 = 2) refined 3-fold (30 x 30 fine
+    cells, 2,760 states) are replaced by order-``q`` models.
+
+    The iris geometry is only drawn in the paper; here each iris is one fine
+    cell thick, on the fine column at the region's middle (x = 1.5 m and
+    2.5 m), metal from both walls to a centred aperture of ``aperture`` fine
+    cells (0.3 m); outside the region the plates continue as metal coarse
+    cells of the same column.  Excitation: a Gaussian current pulse
+    (``f_bw`` bandwidth) on an Ey line across the guide at i = 12; probes at
+    the far end (Hz, Ey at i = 67) and near the source (Hz at i = 14).
+    dt = cfl_gain x 0.99 x the fine mesh's vacuum Courant limit."""
+    nx, ny = 80, 14
+    dx = dy = 0.05
+    r = 3
+    dt = cfl_gain * courant_dt(dx / r, dy / r, 0.99)
+    eps = np.ones((ny, nx))
+    sig = np.zeros((ny, nx))
+    roms = []
+    for i0 in (25, 45):
+        fe = uniform_fine(10, 10, r, 1.0)
+        fs = uniform_fine(10, 10, r, 0.0)
+        if irises:
+            mid = r * 10 // 2
+            lo = (r * 10 - aperture) // 2
+            fs[:lo, mid] = SIGMA_COPPER
+            fs[lo + aperture:, mid] = SIGMA_COPPER
+            ci = i0 + 10 // 2
+            sig[:2, ci] = SIGMA_COPPER
+            sig[12:, ci] = SIGMA_COPPER
+        roms.append(RomSpec(i0=i0, j0=2, ni=10, nj=10, r=r, q=q, eps_r=fe, sigma=fs,
+                            f_max=f_bw))
+    src = Source(EY, 12, 13, 0, ny, gaussian(nsteps, dt, f_bw, t_offset=0.5 * dt))
+    probes = [Probe(HZ, 67, 7), Probe(EY, 67, 7), Probe(HZ, 14, 7)]
+    return Problem("E3-irises" if irises else "E3-empty", nx, ny, dx, dy, dt, eps, sig, roms,
+                   [src], probes, nsteps, dtype, Pml(10, 10, 0, 0))
+
+
+def rods_reflection(nsteps: int = 2000, q: int = 1920, rods: bool = True,
+                    dtype: str = "f64", f_bw: float = 30e9, cfl_gain: float = 3.0) -> Problem:
+    """Reflection test (Sec. VI-C): 66 mm x 40 mm waveguide, 1 mm coarse
+    cells, PEC walls at y = 0 and 40 mm, absorbing layers 15 mm deep at both
+    x ends.  The 8 mm x 8 mm region x in [39, 47] mm, y in [16, 24] mm is
+    refined 6-fold (48 x 48 fine cells, 7,008 states) and replaced by an
+    order-``q`` model.  Scatterer (``rods``): four copper rods of 1 mm
+    radius centred at (41, 22), (41, 18), (45, 22), (45, 18) mm, as the fine
+    cells whose centres lie within the radius; without rods the region is
+    vacuum (the interface-reflection run).  Excitation: a Gaussian Jy line
+    current at x = 17 mm (pulse bandwidth ``f_bw``: not given in the paper);
+    line probe: Ey at x = 19 mm on every row.  dt = cfl_gain x 0.99 x the
+    fine mesh's vacuum Courant limit."""
+    nx, ny = 66, 40
+    dx = dy = 1e-3
+    r = 6
+    i0, j0, nb = 39, 16, 8
+    dt = cfl_gain * courant_dt(dx / r, dy / r, 0.99)
+    fe = uniform_fine(nb, nb, r, 1.0)
+    fs = uniform_fine(nb, nb, r, 0.0)
+    if rods:
+        xc = i0 + (np.arange(r * nb) + 0.5) / r          # fine cell centres in mm
+        yc = j0 + (np.arange(r * nb) + 0.5) / r
+        X, Y = np.meshgrid(xc, yc)
+        for cx, cy in ((41.0, 22.0), (41.0, 18.0), (45.0, 22.0), (45.0, 18.0)):
+            fs[(X - cx) ** 2 + (Y - cy) ** 2 <= 1.0] = SIGMA_COPPER
+    rom = RomSpec(i0=i0, j0=j0, ni=nb, nj=nb, r=r, q=q, eps_r=fe, sigma=fs, f_max=f_bw)
+    src = Source(EY, 17, 18, 0, ny, gaussian(nsteps, dt, f_bw, t_offset=0.5 * dt))
+    probes = [Probe(EY, 19, j) for j in range(ny)]
+    return Problem("E4-rods" if rods else "E4-empty", nx, ny, dx, dy, dt, np.ones((ny, nx)),
+                   np.zeros((ny, nx)), [rom], [src], probes, nsteps, dtype, Pml(15, 15, 0, 0))
+
+
 def random_problem(seed: int, nx: int, ny: int, nsteps: int, nroms: int = 2,
                    block: Tuple[int, int] = (6, 5), r: int = 2, q: int = 12,
                    dtype: str = "f64", lossy: bool = True,
