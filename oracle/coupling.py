@@ -106,20 +106,33 @@ class RomCoupling:
         return z
 
     # closed form ----------------------------------------------------------
-    def closed_form(self):
+    def closed_form(self, solver="lu"):
+        """Eq. (23) eliminated: A~ = M^{-1} N, B~' = M^{-1} L~ Sc, C~ = L~^T
+        with M = R~ + F~ + L~ C+ L~^T, N = R~ - F~ + L~ C- L~^T.  ``solver``
+        'lu' (partial pivoting) or 'qr' (Householder): two backward-stable
+        routes to the same matrices, whose difference measures how well
+        FP64 determines them for an ill-conditioned M."""
         Lt = self.Lt
         M = self.Rt + self.Ft + (Lt * self.Cp[None, :]) @ Lt.T
         N = self.Rt - self.Ft + (Lt * self.Cm[None, :]) @ Lt.T
-        A = np.linalg.solve(M, N)
-        B = np.linalg.solve(M, Lt * self.Sc[None, :])
+        LS = Lt * self.Sc[None, :]
+        if solver == "lu":
+            A = np.linalg.solve(M, N)
+            B = np.linalg.solve(M, LS)
+        elif solver == "qr":
+            Qm, Rm = np.linalg.qr(M)
+            A = sla.solve_triangular(Rm, Qm.T @ N)
+            B = sla.solve_triangular(Rm, Qm.T @ LS)
+        else:
+            raise ValueError(solver)
         C = Lt.T.copy()
         return A, B, C
 
-    def update_matrix(self):
+    def update_matrix(self, solver="lu"):
         """Eq. (23) as one map on [x~^n; h^{n+1/2}] -> [x~^{n+1}; y^{n+1}]:
         G = [[A~, B~'], [C~ A~, C~ B~']] (y^{n+1} taken directly from the
         step-n quantities, as eq. (23) gives it)."""
-        A, B, C = self.closed_form()
+        A, B, C = self.closed_form(solver)
         return np.block([[A, B], [C @ A, C @ B]])
 
     def gather(self, hz):

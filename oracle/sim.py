@@ -33,7 +33,7 @@ from .yee import EX, EY, HZ
 
 
 class CoupledRun:
-    def __init__(self, prob, roms, mode="literal", fp32=False, init=None):
+    def __init__(self, prob, roms, mode="literal", fp32=False, init=None, solver="lu"):
         """``roms``: list of dict(Rt, Ft, Lt) aligned with prob.roms.
         mode 'literal' solves eq. (19); 'closed' applies eq. (23).  With
         fp32=True the stencil coefficients and eq. (23)'s update matrix on
@@ -53,10 +53,10 @@ class CoupledRun:
             c = RomCoupling(m["Rt"], m["Ft"], m["Lt"], spec.i0, spec.j0, spec.ni,
                             spec.nj, prob.eps_r, prob.sigma, prob.dx, prob.dy,
                             prob.dt)
-            A, B, C = c.closed_form()
+            A, B, C = c.closed_form(solver)
             c.Ac, c.Bc, c.Cc = A, B, C
             # an FP32 run rounds eq. (23)'s update matrix on [x~^n; h]
-            c.G32 = (np.asarray(c.update_matrix(), np.float32).astype(np.float64)
+            c.G32 = (np.asarray(c.update_matrix(solver), np.float32).astype(np.float64)
                      if fp32 else None)
             self.cpl.append(c)
         self.x = [np.zeros(c.q) for c in self.cpl]

@@ -230,6 +230,21 @@ def test_literal_equals_closed_form_c1():
     assert rel_l2(b, a) < 1e-13
 
 
+def test_closed_form_qr_route_equals_literal():
+    """The QR route to eq. (23)'s closed form (used to measure how well FP64
+    determines it) gives the literal eq. (19) run on a well-conditioned
+    model, as the LU route does."""
+    p = W.cavity_c1(nsteps=600)
+    ms = sim.build_roms(p)
+    a = sim.run(p, ms, mode="literal")
+    r = sim.CoupledRun(p, ms, mode="closed", solver="qr")
+    b = np.empty_like(a)
+    for n in range(p.nsteps):
+        r.step()
+        b[n] = r.probes()
+    assert rel_l2(b, a) < 1e-13
+
+
 @pytest.mark.parametrize("lossy", [True, False])
 def test_energy_balance_exact(lossy):
     p = W.random_problem(4, 24, 22, 60, nroms=2, block=(5, 4), r=2, q=12, lossy=lossy)
