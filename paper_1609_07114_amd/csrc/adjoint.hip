@@ -34,28 +34,26 @@ __global__ void __launch_bounds__(kBlock) adj_coupling(const AdjParams<T> p) {
   T* lxout = p.lx_out + r.x_off;
   const int* gi = p.idx + r.i_off;
   const int* si = gi + r.np;
-  for (int c = tid; c < r.ldg; c += kBlock) {
-    T v = T(0);
-    if (c < r.q) {
-      v = lxin[c];
-    } else if (c < r.q + r.np) {
-      const int pp = c - r.q;
-      v = (pp < r.n_ex ? p.lex_in : p.ley_in)[si[pp]];
-    }
-    z[c] = v;
-  }
-  __syncthreads();
   const int lane = tid & (kWave - 1);
   const int row0 = rb.b + (tid / kWave) * kRowsPerWave;
   const T* GT = p.mats + r.gt_off + (size_t)row0 * r.ldg;  // row k of G^T = column k of G
   T acc[kRowsPerWave];
 #pragma unroll
   for (int k = 0; k < kRowsPerWave; ++k) acc[k] = T(0);
-  for (int c = lane; c < r.ldg; c += kWave) {
-    const T zc = z[c];
-#pragma unroll
-    for (int k = 0; k < kRowsPerWave; ++k) acc[k] += GT[(size_t)k * r.ldg + c] * zc;
-  }
+  auto stage = [&]() {
+    for (int c = tid; c < r.ldg; c += kBlock) {
+      T v = T(0);
+      if (c < r.q) {
+        v = lxin[c];
+      } else if (c < r.q + r.np) {
+        const int pp = c - r.q;
+        v = (pp < r.n_ex ? p.lex_in : p.ley_in)[si[pp]];
+      }
+      z[c] = v;
+    }
+    lds_barrier();
+  };
+  lane_row_dots<T, kRowsPerWave>(GT, r.ldg, z, lane, acc, stage);
 #pragma unroll
   for (int k = 0; k < kRowsPerWave; ++k)
     for (int o = kWave / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, kWave);

@@ -38,4 +38,52 @@ __device__ __forceinline__ double lane_next(double v) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// Workgroup barrier that publishes LDS writes only: global loads still in
+// flight (row prefetches) are not waited for, unlike __syncthreads().
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// acc[k] += sum over this lane's columns c = lane + 64 i (c < ld, ld a
+// multiple of 64) of rows[k * ld + c] * z[c], for kRows consecutive rows of
+// a row-major matrix.  Loads go in groups of 8 column slices (8 * kRows per
+// lane in flight): the first group is issued before stage() - which fills
+// z and ends with a barrier - and each later group before the previous one
+// is consumed.  Each lane accumulates its columns in increasing order.
+template <typename T, int kRows, typename Stage>
+__device__ __forceinline__ void lane_row_dots(const T* __restrict__ rows, int ld, const T* z, int lane,
+                                              T (&acc)[kRows], Stage&& stage) {
+  constexpr int U = 8;
+  const int nit = ld / 64;
+  T g[U][kRows];
+  auto fetch = [&](int it) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (it + u < nit) {
+        const int c = lane + (it + u) * 64;
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) g[u][k] = rows[(size_t)k * ld + c];
+      }
+  };
+  fetch(0);
+  stage();
+  for (int it = 0; it < nit; it += U) {
+    T cur[U][kRows];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) cur[u][k] = g[u][k];
+    if (it + U < nit) fetch(it + U);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (it + u < nit) {
+        const T zc = z[lane + (it + u) * 64];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) acc[k] += cur[u][k] * zc;
+      }
+  }
+}
+
 }  // namespace fdtd

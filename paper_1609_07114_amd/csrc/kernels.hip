@@ -393,20 +393,32 @@ __device__ void coupling_rows(const StepParams<T>& p, const RowBlock& rb, int n,
   const T* hz = fld(p, par, 0);
   const T* ex = fld(p, par, 1);
   const T* ey = fld(p, par, 2);
-  for (int c = tid; c < r.ldg; c += kBlock)
-    z[c] = c < r.q ? xin[c] : (c < r.q + r.np ? ring_h(p, hz, ex, ey, gi[c - r.q], n) : T(0));
-  __syncthreads();
   const int lane = tid & (kWave - 1);
   const int row0 = rb.b + (tid / kWave) * kRowsPerWave;
   const T* G = p.mats + r.g_off + (size_t)row0 * r.ldg;
   T acc[kRowsPerWave];
 #pragma unroll
   for (int k = 0; k < kRowsPerWave; ++k) acc[k] = T(0);
-  for (int c = lane; c < r.ldg; c += kWave) {
-    const T zc = z[c];
+  // z = [x~^n; h^{n+1/2}] in LDS: reduced-state loads of all rounds issued
+  // together, then the ring Hz
+  auto stage = [&]() {
+    for (int c0 = 0; c0 < r.ldg; c0 += 4 * kBlock) {
+      T v[4];
 #pragma unroll
-    for (int k = 0; k < kRowsPerWave; ++k) acc[k] += G[(size_t)k * r.ldg + c] * zc;
-  }
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + u * kBlock + tid;
+        v[u] = c < r.q ? xin[c] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + u * kBlock + tid;
+        if (c >= r.q && c < r.q + r.np) v[u] = ring_h(p, hz, ex, ey, gi[c - r.q], n);
+        if (c < r.ldg) z[c] = v[u];
+      }
+    }
+    lds_barrier();
+  };
+  lane_row_dots<T, kRowsPerWave>(G, r.ldg, z, lane, acc, stage);
 #pragma unroll
   for (int k = 0; k < kRowsPerWave; ++k) acc[k] = wave_sum(acc[k]);
   if (lane == 0) {
