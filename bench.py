@@ -51,9 +51,14 @@ def step_bytes(prob):
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "stencil_c2_2048_hbm_counters.json")
 
 
+KERNEL_SOURCES = ("paper_1609_07114_amd/csrc/kernels.hip", "paper_1609_07114_amd/csrc/common.hpp",
+                  "paper_1609_07114_amd/csrc/device.hpp")
+
+
 def kernel_source_hash():
+    """Hash of the sources the step kernel is compiled from."""
     h = hashlib.sha256()
-    for f in ("paper_1609_07114_amd/csrc/kernels.hip", "paper_1609_07114_amd/csrc/common.hpp"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -28,6 +28,7 @@ struct fdtd_rom_batch {
   size_t table_cap = 0;
   std::vector<BatchRef> table;
   size_t smem = 0;
+  bool layers = false;  // some instance has absorbing layers: launch the kernel variant with them
   bool dirty = true;  // descriptors / table must be uploaded before the next launch
   int steps = 0;
   int graph_batch = 0;
@@ -98,7 +99,11 @@ void build_table(fdtd_rom_batch* bt) {
   }
   for (int b = 0; b < bt->B; ++b) t.push_back(BatchRef{b, 2, 0, 0});
   bt->smem = 0;
-  for (int b = 0; b < bt->B; ++b) bt->smem = std::max(bt->smem, bt->sims[b]->smem);
+  bt->layers = false;
+  for (int b = 0; b < bt->B; ++b) {
+    bt->smem = std::max(bt->smem, bt->sims[b]->smem);
+    bt->layers = bt->layers || bt->sims[b]->L.pml;
+  }
 }
 
 void drop_batch_graph(fdtd_rom_batch* bt) {
@@ -129,7 +134,7 @@ int enqueue_batch(fdtd_rom_batch* bt, int nsteps, hipStream_t st) {
   const BatchRef* tab = (const BatchRef*)(bt->ws + bt->off_table);
   int* ctrl = (int*)(bt->ws + bt->off_ctrl);
   for (int k = 0; k < nsteps; ++k)
-    if (launch_batch_step<T>(d, tab, (int)bt->table.size(), ctrl, k, bt->smem, st) != hipSuccess)
+    if (launch_batch_step<T>(d, tab, (int)bt->table.size(), ctrl, k, bt->smem, bt->layers, st) != hipSuccess)
       return fail(FDTD_EDEVICE, "batch step launch failed: %s", hipGetErrorString(hipGetLastError()));
   if (launch_batch_probe_flush<T>(d, bt->B, ctrl, nsteps, st) != hipSuccess || launch_tick(ctrl, nsteps, st) != hipSuccess)
     return fail(FDTD_EDEVICE, "batch probe/tick launch failed");

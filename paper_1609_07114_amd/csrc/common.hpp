@@ -135,7 +135,7 @@ inline int energy_blocks(int nx, int ny) {
 }
 template <typename T>
 hipError_t launch_batch_step(const StepParams<T>* descs, const BatchRef* table, int nblocks,
-                             const int* ctrl, int step_off, size_t smem, hipStream_t s);
+                             const int* ctrl, int step_off, size_t smem, bool layers, hipStream_t s);
 template <typename T>
 hipError_t launch_batch_probe_flush(const StepParams<T>* descs, int ninst, const int* ctrl,
                                     int step_off, hipStream_t s);

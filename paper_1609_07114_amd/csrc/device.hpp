@@ -48,14 +48,16 @@ __device__ __forceinline__ void lds_barrier() {
 
 // acc[k] += sum over this lane's columns c = lane + 64 i (c < ld, ld a
 // multiple of 64) of rows[k * ld + c] * z[c], for kRows consecutive rows of
-// a row-major matrix.  Loads go in groups of 8 column slices (8 * kRows per
-// lane in flight): the first group is issued before stage() - which fills
-// z and ends with a barrier - and each later group before the previous one
-// is consumed.  Each lane accumulates its columns in increasing order.
+// a row-major matrix.  Loads go in groups of 4 column slices (4 * kRows per
+// lane in flight, one register buffer; larger groups raise the register
+// count of every kernel that contains this code, stencil waves included):
+// the first group is issued before stage() - which fills z and ends with a
+// barrier - so it overlaps the staging loads.  Each lane accumulates its
+// columns in increasing order.
 template <typename T, int kRows, typename Stage>
 __device__ __forceinline__ void lane_row_dots(const T* __restrict__ rows, int ld, const T* z, int lane,
                                               T (&acc)[kRows], Stage&& stage) {
-  constexpr int U = 8;
+  constexpr int U = 4;
   const int nit = ld / 64;
   T g[U][kRows];
   auto fetch = [&](int it) {
@@ -70,18 +72,13 @@ __device__ __forceinline__ void lane_row_dots(const T* __restrict__ rows, int ld
   fetch(0);
   stage();
   for (int it = 0; it < nit; it += U) {
-    T cur[U][kRows];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int k = 0; k < kRows; ++k) cur[u][k] = g[u][k];
-    if (it + U < nit) fetch(it + U);
+    if (it > 0) fetch(it);
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (it + u < nit) {
         const T zc = z[lane + (it + u) * 64];
 #pragma unroll
-        for (int k = 0; k < kRows; ++k) acc[k] += cur[u][k] * zc;
+        for (int k = 0; k < kRows; ++k) acc[k] += g[u][k] * zc;
       }
   }
 }

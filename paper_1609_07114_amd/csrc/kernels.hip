@@ -337,14 +337,20 @@ __device__ void stencil_rows(const StepParams<T>& p, int t, int n) {
 }
 
 // A stencil wave takes the absorbing-layer variant only when its columns
-// [iw-1, iw+64) or rows [js, j1) reach into a layer.
-template <typename T, int SEG>
+// [iw-1, iw+64) or rows [js, j1) reach into a layer.  Kernels built with
+// Layers = false (problems without layers) contain the plain variant only,
+// so its register budget is not raised by the layer code.
+template <typename T, int SEG, bool Layers>
 __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int tile = xcd_tile(t, p.nst_blocks);
   const int iw = (tile % p.tiles_x) * kWave;
   const int j0 = ((tile / p.tiles_x) * (kBlock / kWave) + wv) * SEG;
-  if (j0 >= p.ny) return;  // uniform over the wave
+  if (j0 >= p.ny) return;  // uniform over the wave: no rows left for it
+  if constexpr (!Layers) {
+    stencil_rows<T, SEG, false>(p, t, n);
+    return;
+  }
   const int j1 = min(j0 + SEG, p.ny);
   const int js = j0 > 0 ? j0 - 1 : 0;
   const bool layer = p.pml && (iw - 1 < p.pml_xlo || iw + kWave > p.nx - p.pml_xhi ||
@@ -399,10 +405,10 @@ __device__ void coupling_rows(const StepParams<T>& p, const RowBlock& rb, int n,
   T acc[kRowsPerWave];
 #pragma unroll
   for (int k = 0; k < kRowsPerWave; ++k) acc[k] = T(0);
-  // z = [x~^n; h^{n+1/2}] in LDS: reduced-state loads of all rounds issued
-  // together, then the ring Hz
+  // z = [x~^n; h^{n+1/2}; 0] in LDS: reduced-state loads four rounds at a
+  // time, then the ring Hz, then the padding
   auto stage = [&]() {
-    for (int c0 = 0; c0 < r.ldg; c0 += 4 * kBlock) {
+    for (int c0 = 0; c0 < r.q; c0 += 4 * kBlock) {
       T v[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -412,10 +418,11 @@ __device__ void coupling_rows(const StepParams<T>& p, const RowBlock& rb, int n,
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int c = c0 + u * kBlock + tid;
-        if (c >= r.q && c < r.q + r.np) v[u] = ring_h(p, hz, ex, ey, gi[c - r.q], n);
-        if (c < r.ldg) z[c] = v[u];
+        if (c < r.q) z[c] = v[u];
       }
     }
+    for (int c = r.q + tid; c < r.q + r.np; c += kBlock) z[c] = ring_h(p, hz, ex, ey, gi[c - r.q], n);
+    for (int c = r.q + r.np + tid; c < r.ldg; c += kBlock) z[c] = T(0);
     lds_barrier();
   };
   lane_row_dots<T, kRowsPerWave>(G, r.ldg, z, lane, acc, stage);
@@ -531,7 +538,7 @@ __device__ void record_probes(const StepParams<T>& p, int m) {
   }
 }
 
-template <typename T, int SEG>
+template <typename T, int SEG, bool Layers>
 __global__ void __launch_bounds__(kBlock) step_kernel(const StepParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = p.ctrl[0] + p.step_off;
@@ -551,7 +558,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepParams<T> p) {
   }
   const int t = b - p.ncoup_blocks;
   if (t < p.nst_blocks) {
-    stencil_tile<T, SEG>(p, t, n);
+    stencil_tile<T, SEG, Layers>(p, t, n);
     return;
   }
   record_probes(p, n - 1);
@@ -571,7 +578,7 @@ __global__ void tick_kernel(int* ctrl, int k) {
 // device code as step_kernel on that instance's parameter block, which
 // stays in global memory (read through the scalar cache).  Each instance
 // keeps its own tile height.
-template <typename T>
+template <typename T, bool Layers>
 __global__ void __launch_bounds__(kBlock)
 batch_step_kernel(const StepParams<T>* __restrict__ descs, const BatchRef* __restrict__ table,
                   const int* __restrict__ ctrl, int step_off) {
@@ -593,10 +600,10 @@ batch_step_kernel(const StepParams<T>* __restrict__ descs, const BatchRef* __res
   }
   if (r.kind == 1) {
     switch (p.seg) {
-      case 4: stencil_tile<T, 4>(p, r.idx, n); break;
-      case 8: stencil_tile<T, 8>(p, r.idx, n); break;
-      case 32: stencil_tile<T, 32>(p, r.idx, n); break;
-      default: stencil_tile<T, 16>(p, r.idx, n); break;
+      case 4: stencil_tile<T, 4, Layers>(p, r.idx, n); break;
+      case 8: stencil_tile<T, 8, Layers>(p, r.idx, n); break;
+      case 32: stencil_tile<T, 32, Layers>(p, r.idx, n); break;
+      default: stencil_tile<T, 16, Layers>(p, r.idx, n); break;
     }
     return;
   }
@@ -611,9 +618,13 @@ batch_probe_kernel(const StepParams<T>* __restrict__ descs, const int* __restric
 
 template <typename T>
 hipError_t launch_batch_step(const StepParams<T>* descs, const BatchRef* table, int nblocks,
-                             const int* ctrl, int step_off, size_t smem, hipStream_t s) {
-  hipLaunchKernelGGL((batch_step_kernel<T>), dim3(nblocks), dim3(kBlock), smem, s, descs, table,
-                     ctrl, step_off);
+                             const int* ctrl, int step_off, size_t smem, bool layers, hipStream_t s) {
+  if (layers)
+    hipLaunchKernelGGL((batch_step_kernel<T, true>), dim3(nblocks), dim3(kBlock), smem, s, descs, table,
+                       ctrl, step_off);
+  else
+    hipLaunchKernelGGL((batch_step_kernel<T, false>), dim3(nblocks), dim3(kBlock), smem, s, descs, table,
+                       ctrl, step_off);
   return hipGetLastError();
 }
 
@@ -691,12 +702,22 @@ template hipError_t launch_energy<double>(const double*, const double*, const do
 template <typename T>
 hipError_t launch_step(const StepParams<T>& p, int seg, size_t smem, hipStream_t s) {
   const dim3 g(p.ncoup_blocks + p.nst_blocks + 1), b(kBlock);
-  switch (seg) {
-    case 4: hipLaunchKernelGGL((step_kernel<T, 4>), g, b, smem, s, p); break;
-    case 8: hipLaunchKernelGGL((step_kernel<T, 8>), g, b, smem, s, p); break;
-    case 16: hipLaunchKernelGGL((step_kernel<T, 16>), g, b, smem, s, p); break;
-    case 32: hipLaunchKernelGGL((step_kernel<T, 32>), g, b, smem, s, p); break;
-    default: return hipErrorInvalidValue;
+  if (p.pml) {
+    switch (seg) {
+      case 4: hipLaunchKernelGGL((step_kernel<T, 4, true>), g, b, smem, s, p); break;
+      case 8: hipLaunchKernelGGL((step_kernel<T, 8, true>), g, b, smem, s, p); break;
+      case 16: hipLaunchKernelGGL((step_kernel<T, 16, true>), g, b, smem, s, p); break;
+      case 32: hipLaunchKernelGGL((step_kernel<T, 32, true>), g, b, smem, s, p); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (seg) {
+      case 4: hipLaunchKernelGGL((step_kernel<T, 4, false>), g, b, smem, s, p); break;
+      case 8: hipLaunchKernelGGL((step_kernel<T, 8, false>), g, b, smem, s, p); break;
+      case 16: hipLaunchKernelGGL((step_kernel<T, 16, false>), g, b, smem, s, p); break;
+      case 32: hipLaunchKernelGGL((step_kernel<T, 32, false>), g, b, smem, s, p); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
@@ -717,9 +738,9 @@ template hipError_t launch_step<double>(const StepParams<double>&, int, size_t, 
 template hipError_t launch_probe_flush<float>(const StepParams<float>&, hipStream_t);
 template hipError_t launch_probe_flush<double>(const StepParams<double>&, hipStream_t);
 template hipError_t launch_batch_step<float>(const StepParams<float>*, const BatchRef*, int, const int*,
-                                             int, size_t, hipStream_t);
+                                             int, size_t, bool, hipStream_t);
 template hipError_t launch_batch_step<double>(const StepParams<double>*, const BatchRef*, int,
-                                              const int*, int, size_t, hipStream_t);
+                                              const int*, int, size_t, bool, hipStream_t);
 template hipError_t launch_batch_probe_flush<float>(const StepParams<float>*, int, const int*, int,
                                                     hipStream_t);
 template hipError_t launch_batch_probe_flush<double>(const StepParams<double>*, int, const int*, int,
