@@ -39,15 +39,17 @@ sys.path.insert(0, ROOT)
 METRIC = "Mcell-updates/s + % HBM roofline; batched & adjoint vs plain, 1 GPU, 1e-5 err"
 PEAK_HBM_GBS = 8000.0
 # algorithmic bytes of one step launch (FP32): per coarse cell Hz, Ex, Ey read
-# + write (24 B) and the per-cell material pair (a, b) read (8 B); per model
-# the (q+np)^2 update matrix of eq. (23) read once
-BYTES_PER_CELL_F32 = 32
+# + write (24 B) and the material - a 16-bit table index (2 B; the table of
+# distinct (a, b) pairs is a few KB) or the per-cell pair (a, b) (8 B); per
+# model the (q+np)^2 update matrix of eq. (23) read once
+FIELD_BYTES_PER_CELL_F32 = 24
+MATERIAL_BYTES_PER_CELL_F32 = {1: 2, 0: 8}
 
 
-def step_bytes(prob):
+def step_bytes(prob, material_mode=1):
     cells = prob.nx * prob.ny
     mats = sum(4 * (s.q + s.n_ports) ** 2 for s in prob.roms)
-    return BYTES_PER_CELL_F32 * cells + mats
+    return (FIELD_BYTES_PER_CELL_F32 + MATERIAL_BYTES_PER_CELL_F32[material_mode]) * cells + mats
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "stencil_c2_2048_hbm_counters.json")
 
 
@@ -64,15 +66,16 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(material_mode):
     """HBM bytes per stencil launch from committed rocprofv3 counter runs,
-    if they were taken on the current kernel source (else None)."""
+    if they were taken on the current kernel source in the same material
+    mode (else None)."""
     try:
         with open(COUNTERS_FILE) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("material_mode", 0) != material_mode:
         return None
     return d.get("bytes_per_launch")
 
@@ -232,15 +235,18 @@ def bench_hbm_resident(n=8192, steps=400, warmup=50, log=None):
     roms = romgen.build_roms(prob)
     with Simulation(prob, roms) as s:
         seg = s.get_tiling()
+        mmode, nmat = s.material_mode()
         s.set_graph(min(steps, 200))
         s.run(warmup)
         t, ev = _timed(s.stream, lambda: s.run(steps))
     cells = prob.nx * prob.ny
-    alg = step_bytes(prob)
+    alg = step_bytes(prob, mmode)
     avg = ev / 1e3 / steps
     return {"workload": f"random media {n}x{n}, 16 models (q 32-96), FP32, {steps} steps",
             "value": round(cells * steps / t / 1e6, 1), "unit": "Mcell-updates/s",
-            "ms_per_step": round(t * 1e3 / steps, 4), "kernel": f"step_kernel<float,{seg}>",
+            "ms_per_step": round(t * 1e3 / steps, 4),
+            "kernel": f"step_kernel<float,{seg},false,{'true' if mmode else 'false'}>",
+            "material": {"mode": "table" if mmode else "per-cell", "entries": nmat},
             "bytes_per_launch": alg, "achieved_GBps": round(alg / avg / 1e9, 1),
             "frac_of_8TBps": round(alg / avg / 1e9 / PEAK_HBM_GBS, 4)}
 
@@ -340,6 +346,8 @@ def main():
                     help="run one form alone and print its JSON (profiling)")
     ap.add_argument("--form-steps", type=int, default=None, help="timed steps of the batched / many-copies form")
     ap.add_argument("--copy-ceiling", action="store_true", help="only measure device copy rates and exit")
+    ap.add_argument("--material-mode", type=int, choices=[0, 1], default=None,
+                    help="0: per-cell material arrays, 1: 16-bit index + table (default: table when available)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -382,6 +390,9 @@ def main():
 
     sim = Simulation(prob, roms, max_steps=total)
     seg = sim.get_tiling()
+    if args.material_mode is not None:
+        sim.set_material_mode(args.material_mode)
+    mmode, nmat = sim.material_mode()
     sim.set_graph(200)   # steps replayed from captured graphs (the production path)
     sim.run(args.warmup)
     torch.cuda.synchronize()
@@ -408,11 +419,13 @@ def main():
     # one launch per step; the region's event time also holds the run's
     # closing probe-flush and tick launches (~8 us over all K steps)
     st_avg_s = ev_ms / args.steps / 1e3
-    alg_bytes = step_bytes(prob)
+    alg_bytes = step_bytes(prob, mmode)
     achieved = alg_bytes / st_avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
-                "kernel": f"step_kernel<float,{seg}>", "bytes_per_launch": alg_bytes,
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(mmode),
+                "kernel": f"step_kernel<float,{seg},false,{'true' if mmode else 'false'}>",
+                "material": {"mode": "table" if mmode else "per-cell", "entries": nmat},
+                "bytes_per_launch": alg_bytes,
                 "avg_launch_us": round(st_avg_s * 1e6, 3), "launches": args.steps}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mcell-updates/s", "n_gpus": 1,

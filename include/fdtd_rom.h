@@ -289,6 +289,18 @@ int fdtd_rom_get_tiling(const fdtd_rom_sim* sim, int32_t* seg);
  * region uses its own row-parallel GEMV.  Both give the same result up to
  * FP32 summation order. */
 int fdtd_rom_set_shared_gemm(fdtd_rom_sim* sim, int32_t enable);
+
+/* How the coarse stencil reads the per-cell material of eq. (3) (the edge
+ * coefficients come from a = eps0 eps_r/dt and b = sigma/2 of the two cells
+ * sharing an edge).  mode 1: a 16-bit index per cell into a table of the
+ * problem's distinct (a, b) pairs - available when there are at most 65536
+ * of them, and then the default; mode 0: the two per-cell arrays.  The
+ * values are the same bit patterns, so both modes give identical results;
+ * mode 1 moves 6 (FP32) or 14 (FP64) bytes fewer per cell update.
+ * set: FDTD_EINVAL for another mode, or for mode 1 when no table exists.
+ * get: the current mode and the table size (0: no table). */
+int fdtd_rom_set_material_mode(fdtd_rom_sim* sim, int32_t mode);
+int fdtd_rom_get_material_mode(fdtd_rom_sim* sim, int32_t* mode, int32_t* entries);
 int fdtd_rom_set_graph(fdtd_rom_sim* sim, int32_t batch);
 
 /* Discrete adjoint (reverse-time sweep) of the coupled leap-frog run for the

@@ -96,6 +96,8 @@ _SIGS = {
     "fdtd_rom_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
     "fdtd_rom_get_tiling": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "fdtd_rom_set_shared_gemm": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_set_material_mode": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_get_material_mode": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fdtd_rom_adjoint_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
                                                   C.POINTER(C.c_size_t)]),
     "fdtd_rom_adjoint": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
@@ -316,6 +318,18 @@ def fdtd_rom_get_tiling(h) -> int:
 
 def fdtd_rom_set_shared_gemm(h, enable: bool):
     _check(lib().fdtd_rom_set_shared_gemm(h, 1 if enable else 0))
+
+
+def fdtd_rom_set_material_mode(h, mode: int):
+    _check(lib().fdtd_rom_set_material_mode(h, int(mode)))
+
+
+def fdtd_rom_get_material_mode(h):
+    """(mode, table entries): mode 1 = 16-bit index + table, 0 = per-cell arrays."""
+    m = C.c_int32(0)
+    n = C.c_int32(0)
+    _check(lib().fdtd_rom_get_material_mode(h, C.byref(m), C.byref(n)))
+    return int(m.value), int(n.value)
 
 
 def fdtd_rom_set_graph(h, batch: int):

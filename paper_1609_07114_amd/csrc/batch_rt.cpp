@@ -29,6 +29,7 @@ struct fdtd_rom_batch {
   std::vector<BatchRef> table;
   size_t smem = 0;
   bool layers = false;  // some instance has absorbing layers: launch the kernel variant with them
+  bool midx = false;    // every instance reads its material from a table
   bool dirty = true;  // descriptors / table must be uploaded before the next launch
   int steps = 0;
   int graph_batch = 0;
@@ -100,9 +101,12 @@ void build_table(fdtd_rom_batch* bt) {
   for (int b = 0; b < bt->B; ++b) t.push_back(BatchRef{b, 2, 0, 0});
   bt->smem = 0;
   bt->layers = false;
+  bt->midx = true;
   for (int b = 0; b < bt->B; ++b) {
-    bt->smem = std::max(bt->smem, bt->sims[b]->smem);
-    bt->layers = bt->layers || bt->sims[b]->L.pml;
+    const fdtd_rom_sim* sb = bt->sims[b];
+    bt->smem = std::max(bt->smem, sb->smem);
+    bt->layers = bt->layers || sb->L.pml;
+    bt->midx = bt->midx && (bt->dtype == FDTD_F32 ? sb->sp_f.midx : sb->sp_d.midx) != 0;
   }
 }
 
@@ -134,7 +138,8 @@ int enqueue_batch(fdtd_rom_batch* bt, int nsteps, hipStream_t st) {
   const BatchRef* tab = (const BatchRef*)(bt->ws + bt->off_table);
   int* ctrl = (int*)(bt->ws + bt->off_ctrl);
   for (int k = 0; k < nsteps; ++k)
-    if (launch_batch_step<T>(d, tab, (int)bt->table.size(), ctrl, k, bt->smem, bt->layers, st) != hipSuccess)
+    if (launch_batch_step<T>(d, tab, (int)bt->table.size(), ctrl, k, bt->smem, bt->layers, bt->midx, st) !=
+        hipSuccess)
       return fail(FDTD_EDEVICE, "batch step launch failed: %s", hipGetErrorString(hipGetLastError()));
   if (launch_batch_probe_flush<T>(d, bt->B, ctrl, nsteps, st) != hipSuccess || launch_tick(ctrl, nsteps, st) != hipSuccess)
     return fail(FDTD_EDEVICE, "batch probe/tick launch failed");

@@ -64,11 +64,24 @@ struct RowBlock {
 // the coarse grid and every embedded model from step n to n+1, where
 // n = ctrl[0] + step_off (ctrl[0] is advanced by a tick launch after each
 // batch of steps, so a captured batch can be replayed).
+// One entry of the material table: a = eps0*eps_r/dt (negative inside
+// reduced regions), b = sigma/2 - the two per-cell numbers of eq. (3).
+template <typename T>
+struct alignas(2 * sizeof(T)) MatPair {
+  T a, b;
+};
+constexpr int kMaxMaterials = 65536;
+
 template <typename T>
 struct StepParams {
   T* f[2][3];        // field sets [parity][Hz, Ex, Ey]
   const T* al;       // per cell eps0*eps_r/dt; negative inside reduced regions
   const T* be;       // per cell sigma/2
+  // the same material as a 16-bit index per cell into a table of (a, b)
+  // pairs, when the problem has at most kMaxMaterials distinct pairs
+  const uint16_t* mi;
+  const MatPair<T>* mt;
+  int midx;          // 1: mi/mt hold the material (the stencil may use them)
   int* ctrl;
   int step_off;
   int nx, ny, pitch;
@@ -135,7 +148,8 @@ inline int energy_blocks(int nx, int ny) {
 }
 template <typename T>
 hipError_t launch_batch_step(const StepParams<T>* descs, const BatchRef* table, int nblocks,
-                             const int* ctrl, int step_off, size_t smem, bool layers, hipStream_t s);
+                             const int* ctrl, int step_off, size_t smem, bool layers, bool midx,
+                             hipStream_t s);
 template <typename T>
 hipError_t launch_batch_probe_flush(const StepParams<T>* descs, int ninst, const int* ctrl,
                                     int step_off, hipStream_t s);

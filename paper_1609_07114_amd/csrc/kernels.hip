@@ -35,6 +35,8 @@
 //     inside keep their (zero) value and interface edges are not written;
 //   * workgroups are remapped so each of the 8 XCDs (own L2) takes a
 //     contiguous band of tiles, keeping the halo rows within one L2.
+#include <type_traits>
+
 #include "common.hpp"
 #include "device.hpp"
 
@@ -109,6 +111,28 @@ __device__ __forceinline__ RowIn<T> load_row(const T* hz, const T* ex_up, const 
   return r;
 }
 
+// The same row with the material from the table: `id` is the cell's 16-bit
+// material index, loaded earlier (see stencil_rows).
+template <typename T>
+__device__ __forceinline__ RowIn<T> load_row_tab(const T* hz, const T* ex_up, const T* ey,
+                                                 const MatPair<T>* mt, uint32_t id, uint32_t ob, bool up) {
+  RowIn<T> r;
+  r.h = ld(hz, ob);
+  r.ex1 = T(0);
+  if (up) r.ex1 = ld(ex_up, ob);
+  r.ey0 = ld(ey, ob);
+  const MatPair<T> m = mt[id];
+  r.al = m.a;
+  r.be = m.b;
+  return r;
+}
+
+// 16-bit material index of the cell at byte offset `ob` of a T-sized array
+template <typename T>
+__device__ __forceinline__ uint32_t mat_id(const uint16_t* mi, uint32_t ob) {
+  return ld(mi, ob / (uint32_t)(sizeof(T) / sizeof(uint16_t)));
+}
+
 // eq. (5) with stretched derivatives inside absorbing layers: dex, dey the
 // Yee differences, ik 1/kappa, ps the updated auxiliary fields.
 template <typename T>
@@ -132,8 +156,8 @@ __device__ __forceinline__ T psi_next(T b, T psi, T a, T d) {
   return b * psi + a * d;
 }
 
-template <typename T, int SEG, bool PML>
-__device__ void stencil_rows(const StepParams<T>& p, int t, int n) {
+template <typename T, int SEG, bool PML, bool MIdx>
+__device__ __forceinline__ void stencil_rows(const StepParams<T>& p, int t, int n) {
   const int par = n & 1;
   const T* hz = fld(p, par, 0);
   const T* ex = fld(p, par, 1);
@@ -164,7 +188,6 @@ __device__ void stencil_rows(const StepParams<T>& p, int t, int n) {
   const T* ex_up = ex + P;  // Ex of the row above, same offset
   const bool in = i < nx;
   const bool has_left = (lane == 0) && (i >= 1);
-  const bool has_right = (lane == kWave - 1) && (i + 1 < nx);
   const int js = j0 > 0 ? j0 - 1 : 0;
   // wave-uniform: does any source touch columns [iw-1, iw+64) x rows [js, j1)?
   bool any_src = false;
@@ -208,39 +231,86 @@ __device__ void stencil_rows(const StepParams<T>& p, int t, int n) {
   }
 
   uint32_t ob = ((uint32_t)js * (uint32_t)P + (uint32_t)i) * ts;
+  // The wave's west and east neighbour columns (read by lanes 0 and 63) are
+  // addressed at wave-uniform offsets and loaded by every lane, and the Ex
+  // row above the top row is replaced by a read of the row itself, so all
+  // loads of a row are unconditional: the loads in flight are the same on
+  // every path and the waits the compiler places are exact.
+  const bool west = iw > 0;
+  const bool east = iw + kWave < nx;
+  const uint32_t dW = (uint32_t)(west ? lane + 1 : lane) * ts;            // own column -> west column
+  const uint32_t dE = (uint32_t)(east ? kWave - lane : 0) * ts;           // own column -> east column
+  const uint32_t dEn = (uint32_t)(east ? 0 : lane) * ts;                  // ... or back to column iw
+  const uint16_t* mi = p.mi;
+  const MatPair<T>* mt = p.mt;
+  struct RowSet {
+    RowIn<T> c, w;
+    T eyE;
+  };
+  // row at byte offset o; ids: the material indices of its own and west
+  // cells.  Values that do not exist (Ex above the top row, the east column
+  // of the last tile) are zeroed where they are used, not here: zeroing a
+  // register whose load is still in flight would wait for it.
+  auto fetch = [&](uint32_t o, bool up, uint32_t id, uint32_t idw) {
+    RowSet r;
+    const T* exr = up ? ex_up : ex;
+    const uint32_t ow = o - dW;
+    r.c.h = ld(hz, o);
+    r.c.ex1 = ld(exr, o);
+    r.c.ey0 = ld(ey, o);
+    r.w.h = ld(hz, ow);
+    r.w.ex1 = ld(exr, ow);
+    r.w.ey0 = ld(ey, ow);
+    r.eyE = ld(ey, o + dE - dEn);
+    if constexpr (MIdx) {
+      const MatPair<T> m = mt[id], mw = mt[idw];
+      r.c.al = m.a;
+      r.c.be = m.b;
+      r.w.al = mw.a;
+      r.w.be = mw.b;
+    } else {
+      r.c.al = ld(al, o);
+      r.c.be = ld(be, o);
+      r.w.al = ld(al, ow);
+      r.w.be = ld(be, ow);
+    }
+    return r;
+  };
+  // row offset of row r (< j1)
+  auto orow = [&](int r) { return ob + (uint32_t)(r - js) * row_b; };
   T ex_c = ld(ex, ob);
-  T exl_c = T(0);
-  if (has_left) exl_c = ld(ex, ob - ts);
+  T exl_c = ld(ex, ob - dW);  // used by lane 0 only when the west column exists
   T hn_prev = T(0), a_prev = T(0), b_prev = T(0);
   // software pipeline, two rows deep: rows j+1 and j+2 are in flight while
-  // row j is computed
-  RowIn<T> n1 = load_row(hz, ex_up, ey, al, be, ob, js + 1 < ny);
-  RowIn<T> l1{T(0), T(0), T(0), T(0), T(0)};
-  if (has_left) l1 = load_row(hz, ex_up, ey, al, be, ob - ts, js + 1 < ny);
-  T r1 = T(0);
-  if (has_right) r1 = ld(ey, ob + ts);
-  RowIn<T> n2{T(0), T(0), T(0), T(0), T(0)}, l2{T(0), T(0), T(0), T(0), T(0)};
-  T r2 = T(0);
-  if (js + 1 < j1) {
-    const uint32_t o2 = ob + row_b;
-    n2 = load_row(hz, ex_up, ey, al, be, o2, js + 2 < ny);
-    if (has_left) l2 = load_row(hz, ex_up, ey, al, be, o2 - ts, js + 2 < ny);
-    if (has_right) r2 = ld(ey, o2 + ts);
+  // row j is computed.  With a material table the 16-bit indices run two
+  // rows further ahead (loaded two iterations before their table gather),
+  // so a gather never waits on a load issued after the rows it needs.
+  uint32_t idA = 0, idB = 0, idAw = 0, idBw = 0;
+  RowSet n1, n2;
+  if constexpr (MIdx) {
+    const uint32_t o0 = orow(js), o1 = orow(js + 1);
+    const uint32_t oA = orow(min(js + 2, j1 - 1)), oB = orow(min(js + 3, j1 - 1));
+    const uint32_t i0 = mat_id<T>(mi, o0), i0w = mat_id<T>(mi, o0 - dW);
+    const uint32_t i1 = mat_id<T>(mi, o1), i1w = mat_id<T>(mi, o1 - dW);
+    idA = mat_id<T>(mi, oA);
+    idAw = mat_id<T>(mi, oA - dW);
+    idB = mat_id<T>(mi, oB);
+    idBw = mat_id<T>(mi, oB - dW);
+    n1 = fetch(o0, js + 1 < ny, i0, i0w);
+    n2 = fetch(o1, js + 2 < ny, i1, i1w);
+  } else {
+    n1 = fetch(orow(js), js + 1 < ny, 0, 0);
+    n2 = fetch(orow(js + 1), js + 2 < ny, 0, 0);
   }
-  for (int j = js; j < j1; ++j, ob += row_b) {
-    const RowIn<T> cur = n1;
-    const RowIn<T> cul = l1;
-    const T ey1_r = r1;
-    n1 = n2;
-    l1 = l2;
-    r1 = r2;
-    if (j + 2 < j1) {
-      const uint32_t o3 = ob + 2 * row_b;
-      const bool up3 = (j + 3) < ny;
-      n2 = load_row(hz, ex_up, ey, al, be, o3, up3);
-      if (has_left) l2 = load_row(hz, ex_up, ey, al, be, o3 - ts, up3);
-      if (has_right) r2 = ld(ey, o3 + ts);
+  // one row: compute row j from `cur` (own, west, east data of row j)
+  auto compute = [&](int j, const RowSet& cs) {
+    RowIn<T> cur = cs.c;
+    RowIn<T> cul = cs.w;  // used by lane 0 only when the west column exists
+    if (j + 1 >= ny) {
+      cur.ex1 = T(0);
+      cul.ex1 = T(0);
     }
+    const T ey1_r = east ? cs.eyE : T(0);
     T ey1 = lane_next(cur.ey0);
     if (lane == kWave - 1) ey1 = ey1_r;
     // y profiles of this row (wave-uniform)
@@ -333,6 +403,29 @@ __device__ void stencil_rows(const StepParams<T>& p, int t, int n) {
     a_prev = cur.al;
     b_prev = cur.be;
     ex_c = cur.ex1;
+  };
+  int j = js;
+  for (; j + 2 < j1; ++j, ob += row_b) {
+    const RowSet cur = n1;
+    n1 = n2;
+    const uint32_t o3 = ob + 2 * row_b;
+    if constexpr (MIdx) {
+      const uint32_t oC = o3 + (j + 3 < j1 ? row_b : 0u) + (j + 4 < j1 ? row_b : 0u);
+      const uint32_t idC = mat_id<T>(mi, oC), idCw = mat_id<T>(mi, oC - dW);
+      n2 = fetch(o3, j + 3 < ny, idA, idAw);
+      idA = idB;
+      idAw = idBw;
+      idB = idC;
+      idBw = idCw;
+    } else {
+      n2 = fetch(o3, j + 3 < ny, 0, 0);
+    }
+    compute(j, cur);
+  }
+  for (; j < j1; ++j, ob += row_b) {
+    const RowSet cur = n1;
+    n1 = n2;
+    compute(j, cur);
   }
 }
 
@@ -340,15 +433,15 @@ __device__ void stencil_rows(const StepParams<T>& p, int t, int n) {
 // [iw-1, iw+64) or rows [js, j1) reach into a layer.  Kernels built with
 // Layers = false (problems without layers) contain the plain variant only,
 // so its register budget is not raised by the layer code.
-template <typename T, int SEG, bool Layers>
-__device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
+template <typename T, int SEG, bool Layers, bool MIdx>
+__device__ __forceinline__ void stencil_tile(const StepParams<T>& p, int t, int n) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int tile = xcd_tile(t, p.nst_blocks);
   const int iw = (tile % p.tiles_x) * kWave;
   const int j0 = ((tile / p.tiles_x) * (kBlock / kWave) + wv) * SEG;
   if (j0 >= p.ny) return;  // uniform over the wave: no rows left for it
   if constexpr (!Layers) {
-    stencil_rows<T, SEG, false>(p, t, n);
+    stencil_rows<T, SEG, false, MIdx>(p, t, n);
     return;
   }
   const int j1 = min(j0 + SEG, p.ny);
@@ -356,9 +449,9 @@ __device__ void stencil_tile(const StepParams<T>& p, int t, int n) {
   const bool layer = p.pml && (iw - 1 < p.pml_xlo || iw + kWave > p.nx - p.pml_xhi ||
                                js < p.pml_ylo || j1 > p.ny - p.pml_yhi);
   if (layer)
-    stencil_rows<T, SEG, true>(p, t, n);
+    stencil_rows<T, SEG, true, MIdx>(p, t, n);
   else
-    stencil_rows<T, SEG, false>(p, t, n);
+    stencil_rows<T, SEG, false, MIdx>(p, t, n);
 }
 
 template <typename T>
@@ -371,7 +464,7 @@ __device__ __forceinline__ T wave_sum(T v) {
 // Coarse Hz^{n+1/2} of an active cell from the step-n fields (the value the
 // stencil computes for it).
 template <typename T>
-__device__ T ring_h(const StepParams<T>& p, const T* hz, const T* ex, const T* ey, int off, int n) {
+__device__ __forceinline__ T ring_h(const StepParams<T>& p, const T* hz, const T* ex, const T* ey, int off, int n) {
   const int P = p.pitch;
   const int j = off / P;
   const int i = off - j * P;
@@ -388,7 +481,7 @@ __device__ T ring_h(const StepParams<T>& p, const T* hz, const T* ex, const T* e
 
 // Rows [row0, row0 + kRowsPerBlock) of one model's eq. (23) update matrix.
 template <typename T>
-__device__ void coupling_rows(const StepParams<T>& p, const RowBlock& rb, int n, T* z) {
+__device__ __forceinline__ void coupling_rows(const StepParams<T>& p, const RowBlock& rb, int n, T* z) {
   const int par = n & 1;
   const int tid = threadIdx.x;
   const RomDev r = p.roms[rb.a];
@@ -455,7 +548,7 @@ __device__ void coupling_rows(const StepParams<T>& p, const RowBlock& rb, int n,
 // the stencil tiles keep HBM busy).  Operand layout of v_mfma_f32_16x16x4f32
 // (wave64): lane l holds A(l % 16, l / 16) and B(l / 16, l % 16); the
 // result register i of lane l is D(4 * (l / 16) + i, l % 16).
-__device__ void coupling_gemm(const StepParams<float>& p, const RowBlock& gb, int n, float* zs) {
+__device__ __forceinline__ void coupling_gemm(const StepParams<float>& p, const RowBlock& gb, int n, float* zs) {
   const int par = n & 1;
   const int tid = threadIdx.x;
   const int ncp = gb.c;
@@ -528,7 +621,7 @@ __device__ void coupling_gemm(const StepParams<float>& p, const RowBlock& gb, in
 
 // Probe row m (m >= 0) from the set holding the state after m+1 steps.
 template <typename T>
-__device__ void record_probes(const StepParams<T>& p, int m) {
+__device__ __forceinline__ void record_probes(const StepParams<T>& p, int m) {
   if (m < 0) return;
   const int par = (m + 1) & 1;
   for (int t = threadIdx.x; t < p.nprobes; t += kBlock) {
@@ -538,7 +631,7 @@ __device__ void record_probes(const StepParams<T>& p, int m) {
   }
 }
 
-template <typename T, int SEG, bool Layers>
+template <typename T, int SEG, bool Layers, bool MIdx>
 __global__ void __launch_bounds__(kBlock) step_kernel(const StepParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = p.ctrl[0] + p.step_off;
@@ -558,7 +651,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepParams<T> p) {
   }
   const int t = b - p.ncoup_blocks;
   if (t < p.nst_blocks) {
-    stencil_tile<T, SEG, Layers>(p, t, n);
+    stencil_tile<T, SEG, Layers, MIdx>(p, t, n);
     return;
   }
   record_probes(p, n - 1);
@@ -578,7 +671,7 @@ __global__ void tick_kernel(int* ctrl, int k) {
 // device code as step_kernel on that instance's parameter block, which
 // stays in global memory (read through the scalar cache).  Each instance
 // keeps its own tile height.
-template <typename T, bool Layers>
+template <typename T, bool Layers, bool MIdx>
 __global__ void __launch_bounds__(kBlock)
 batch_step_kernel(const StepParams<T>* __restrict__ descs, const BatchRef* __restrict__ table,
                   const int* __restrict__ ctrl, int step_off) {
@@ -600,10 +693,10 @@ batch_step_kernel(const StepParams<T>* __restrict__ descs, const BatchRef* __res
   }
   if (r.kind == 1) {
     switch (p.seg) {
-      case 4: stencil_tile<T, 4, Layers>(p, r.idx, n); break;
-      case 8: stencil_tile<T, 8, Layers>(p, r.idx, n); break;
-      case 32: stencil_tile<T, 32, Layers>(p, r.idx, n); break;
-      default: stencil_tile<T, 16, Layers>(p, r.idx, n); break;
+      case 4: stencil_tile<T, 4, Layers, MIdx>(p, r.idx, n); break;
+      case 8: stencil_tile<T, 8, Layers, MIdx>(p, r.idx, n); break;
+      case 32: stencil_tile<T, 32, Layers, MIdx>(p, r.idx, n); break;
+      default: stencil_tile<T, 16, Layers, MIdx>(p, r.idx, n); break;
     }
     return;
   }
@@ -618,13 +711,17 @@ batch_probe_kernel(const StepParams<T>* __restrict__ descs, const int* __restric
 
 template <typename T>
 hipError_t launch_batch_step(const StepParams<T>* descs, const BatchRef* table, int nblocks,
-                             const int* ctrl, int step_off, size_t smem, bool layers, hipStream_t s) {
-  if (layers)
-    hipLaunchKernelGGL((batch_step_kernel<T, true>), dim3(nblocks), dim3(kBlock), smem, s, descs, table,
-                       ctrl, step_off);
+                             const int* ctrl, int step_off, size_t smem, bool layers, bool midx,
+                             hipStream_t s) {
+  const dim3 g(nblocks), b(kBlock);
+  if (layers && midx)
+    hipLaunchKernelGGL((batch_step_kernel<T, true, true>), g, b, smem, s, descs, table, ctrl, step_off);
+  else if (layers)
+    hipLaunchKernelGGL((batch_step_kernel<T, true, false>), g, b, smem, s, descs, table, ctrl, step_off);
+  else if (midx)
+    hipLaunchKernelGGL((batch_step_kernel<T, false, true>), g, b, smem, s, descs, table, ctrl, step_off);
   else
-    hipLaunchKernelGGL((batch_step_kernel<T, false>), dim3(nblocks), dim3(kBlock), smem, s, descs, table,
-                       ctrl, step_off);
+    hipLaunchKernelGGL((batch_step_kernel<T, false, false>), g, b, smem, s, descs, table, ctrl, step_off);
   return hipGetLastError();
 }
 
@@ -702,23 +799,22 @@ template hipError_t launch_energy<double>(const double*, const double*, const do
 template <typename T>
 hipError_t launch_step(const StepParams<T>& p, int seg, size_t smem, hipStream_t s) {
   const dim3 g(p.ncoup_blocks + p.nst_blocks + 1), b(kBlock);
-  if (p.pml) {
+  // kernel variant: tile height, absorbing layers present, material table
+  auto go = [&](auto layers, auto midx) -> hipError_t {
+    constexpr bool Lf = decltype(layers)::value, Mf = decltype(midx)::value;
     switch (seg) {
-      case 4: hipLaunchKernelGGL((step_kernel<T, 4, true>), g, b, smem, s, p); break;
-      case 8: hipLaunchKernelGGL((step_kernel<T, 8, true>), g, b, smem, s, p); break;
-      case 16: hipLaunchKernelGGL((step_kernel<T, 16, true>), g, b, smem, s, p); break;
-      case 32: hipLaunchKernelGGL((step_kernel<T, 32, true>), g, b, smem, s, p); break;
+      case 4: hipLaunchKernelGGL((step_kernel<T, 4, Lf, Mf>), g, b, smem, s, p); break;
+      case 8: hipLaunchKernelGGL((step_kernel<T, 8, Lf, Mf>), g, b, smem, s, p); break;
+      case 16: hipLaunchKernelGGL((step_kernel<T, 16, Lf, Mf>), g, b, smem, s, p); break;
+      case 32: hipLaunchKernelGGL((step_kernel<T, 32, Lf, Mf>), g, b, smem, s, p); break;
       default: return hipErrorInvalidValue;
     }
-  } else {
-    switch (seg) {
-      case 4: hipLaunchKernelGGL((step_kernel<T, 4, false>), g, b, smem, s, p); break;
-      case 8: hipLaunchKernelGGL((step_kernel<T, 8, false>), g, b, smem, s, p); break;
-      case 16: hipLaunchKernelGGL((step_kernel<T, 16, false>), g, b, smem, s, p); break;
-      case 32: hipLaunchKernelGGL((step_kernel<T, 32, false>), g, b, smem, s, p); break;
-      default: return hipErrorInvalidValue;
-    }
-  }
+    return hipSuccess;
+  };
+  using Y = std::true_type;
+  using N = std::false_type;
+  const hipError_t e = p.pml ? (p.midx ? go(Y{}, Y{}) : go(Y{}, N{})) : (p.midx ? go(N{}, Y{}) : go(N{}, N{}));
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
@@ -738,9 +834,9 @@ template hipError_t launch_step<double>(const StepParams<double>&, int, size_t, 
 template hipError_t launch_probe_flush<float>(const StepParams<float>&, hipStream_t);
 template hipError_t launch_probe_flush<double>(const StepParams<double>&, hipStream_t);
 template hipError_t launch_batch_step<float>(const StepParams<float>*, const BatchRef*, int, const int*,
-                                             int, size_t, bool, hipStream_t);
+                                             int, size_t, bool, bool, hipStream_t);
 template hipError_t launch_batch_step<double>(const StepParams<double>*, const BatchRef*, int,
-                                              const int*, int, size_t, bool, hipStream_t);
+                                              const int*, int, size_t, bool, bool, hipStream_t);
 template hipError_t launch_batch_probe_flush<float>(const StepParams<float>*, int, const int*, int,
                                                     hipStream_t);
 template hipError_t launch_batch_probe_flush<double>(const StepParams<double>*, int, const int*, int,

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -145,6 +146,10 @@ int fdtd::plan_problem(const fdtd_problem* p, Layout& L) {
   o = align_up(o + L.field_elems * ts, 256);
   L.off_be = o;
   o = align_up(o + L.field_elems * ts, 256);
+  L.off_midx = o;
+  o = align_up(o + L.field_elems * sizeof(uint16_t), 256);
+  L.off_mtab = o;
+  o = align_up(o + (size_t)kMaxMaterials * 2 * ts, 256);
   L.off_src = o;
   // at least one (zero) row so unused source slots point at valid memory
   o = align_up(o + (size_t)std::max(p->nsources, 1) * p->max_steps * ts, 256);
@@ -280,6 +285,52 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
     }
   if ((rc = up(L.off_al, al.data(), fb)) != FDTD_OK) return rc;
   if ((rc = up(L.off_be, be.data(), fb)) != FDTD_OK) return rc;
+  // the same material as a 16-bit index into a table of the distinct (a, b)
+  // pairs (exact bit patterns), when there are at most kMaxMaterials of them
+  {
+    struct Key {
+      uint64_t a, b;
+      bool operator==(const Key& o) const { return a == o.a && b == o.b; }
+    };
+    struct KeyHash {
+      size_t operator()(const Key& k) const {
+        return (size_t)(k.a * 0x9E3779B97F4A7C15ull ^ (k.b + 0x632BE59BD9B4E019ull + (k.a << 6) + (k.a >> 2)));
+      }
+    };
+    auto bits = [](T v) {
+      uint64_t u = 0;
+      std::memcpy(&u, &v, sizeof(T));
+      return u;
+    };
+    std::unordered_map<Key, uint16_t, KeyHash> ids;
+    std::vector<uint16_t> mid(fe);
+    std::vector<MatPair<T>> tab;
+    bool fits = true;
+    Key last{~0ull, ~0ull};
+    uint16_t last_id = 0;
+    for (size_t k = 0; k < fe && fits; ++k) {
+      const Key key{bits(al[k]), bits(be[k])};
+      if (!(key == last)) {
+        auto it = ids.find(key);
+        if (it == ids.end()) {
+          if (tab.size() == (size_t)kMaxMaterials) {
+            fits = false;
+            break;
+          }
+          it = ids.emplace(key, (uint16_t)tab.size()).first;
+          tab.push_back(MatPair<T>{al[k], be[k]});
+        }
+        last = key;
+        last_id = it->second;
+      }
+      mid[k] = last_id;
+    }
+    s->nmat = fits ? (int)tab.size() : 0;
+    if (fits) {
+      if ((rc = up(L.off_midx, mid.data(), fe * sizeof(uint16_t))) != FDTD_OK) return rc;
+      if ((rc = up(L.off_mtab, tab.data(), tab.size() * sizeof(MatPair<T>))) != FDTD_OK) return rc;
+    }
+  }
   // sources
   std::vector<T> sv((size_t)std::max(p->nsources, 1) * p->max_steps, T(0));
   for (int k = 0; k < p->nsources; ++k)
@@ -391,6 +442,9 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
     for (int c = 0; c < 3; ++c) sp.f[set][c] = (T*)(ws + L.off_fields + (3 * set + c) * fb);
   sp.al = (const T*)(ws + L.off_al);
   sp.be = (const T*)(ws + L.off_be);
+  sp.mi = (const uint16_t*)(ws + L.off_midx);
+  sp.mt = (const MatPair<T>*)(ws + L.off_mtab);
+  sp.midx = s->nmat > 0 ? 1 : 0;
   sp.ctrl = (int*)(ws + L.off_ctrl);
   sp.step_off = 0;
   sp.nx = nx;
@@ -1152,6 +1206,24 @@ int fdtd_rom_set_shared_gemm(fdtd_rom_sim* sim, int32_t enable) {
   sim->smem = on ? L.smem_mixed : L.smem_gemv;
   sim->shared_gemm = on;
   drop_graph(sim);
+  return FDTD_OK;
+}
+
+int fdtd_rom_set_material_mode(fdtd_rom_sim* sim, int32_t mode) {
+  if (!sim) return fail(FDTD_EINVAL, "null handle");
+  if (mode != 0 && mode != 1) return fail(FDTD_EINVAL, "material mode must be 0 or 1");
+  if (mode == 1 && sim->nmat == 0)
+    return fail(FDTD_EINVAL, "material table unavailable: more than %d distinct (eps_r, sigma) pairs", kMaxMaterials);
+  sim->sp_f.midx = mode;
+  sim->sp_d.midx = mode;
+  drop_graph(sim);
+  return FDTD_OK;
+}
+
+int fdtd_rom_get_material_mode(fdtd_rom_sim* sim, int32_t* mode, int32_t* entries) {
+  if (!sim || !mode || !entries) return fail(FDTD_EINVAL, "null argument");
+  *mode = sim->dtype == FDTD_F32 ? sim->sp_f.midx : sim->sp_d.midx;
+  *entries = sim->nmat;
   return FDTD_OK;
 }
 

@@ -27,6 +27,7 @@ struct Layout {
   size_t off_ctrl = 0, off_fields = 0, off_al = 0, off_be = 0, off_src = 0;
   size_t off_pbuf = 0, off_poff = 0, off_pcomp = 0, off_roms = 0, off_mats = 0;
   size_t off_xs = 0, off_idx = 0, off_energy = 0, total = 0;
+  size_t off_midx = 0, off_mtab = 0;  // 16-bit material index per cell; (a, b) table
   bool pml = false;                 // absorbing layers present
   int px_stride = 0, py_stride = 0; // profile row lengths (x: columns, y: rows)
   size_t off_prof = 0, off_psi = 0; // profiles [6][px] + [6][py]; 6 auxiliary fields
@@ -65,6 +66,7 @@ struct fdtd_rom_sim {
   char* ws = nullptr;
   fdtd::Layout L;
   int seg = 16;
+  int nmat = 0;           // material table entries (0: more distinct pairs than the table holds)
   size_t smem = 0;        // dynamic LDS of the step kernel
   bool shared_gemm = true;
   std::vector<fdtd::RomHost> roms;

@@ -76,6 +76,12 @@ class Simulation:
     def set_shared_gemm(self, enable):
         capi.fdtd_rom_set_shared_gemm(self.h, enable)
 
+    def set_material_mode(self, mode):
+        capi.fdtd_rom_set_material_mode(self.h, mode)
+
+    def material_mode(self):
+        return capi.fdtd_rom_get_material_mode(self.h)
+
     def set_graph(self, batch):
         capi.fdtd_rom_set_graph(self.h, batch)
 
