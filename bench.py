@@ -333,6 +333,57 @@ def bench_waveguides(steps=None, log=None):
     return out
 
 
+# Tabs. II and III: whole-run Matlab times of the method variants on one
+# 3.6 GHz CPU (model building included), context only.
+PAPER_VARIANT_S = {"E3": {"coarse": 28.9, "mor_only": 245.4, "cfl_only": 484.3, "proposed": 118.5},
+                   "E4": {"coarse": 4.0, "mor_only": 68.4, "cfl_only": 537.2, "proposed": 23.8}}
+
+
+def bench_ablations(steps=None, log=None, dtype="f64"):
+    """The method variants of Tabs. II and III on the two open guides over
+    the same simulated time: all-coarse Yee, MOR only (reduced models at the
+    fine step, no clip), CFL extension only (identity basis + eq. (27) clip,
+    a dense update of the whole restricted fine model per region) and the
+    proposed method.  Per variant: host model build, handle creation (the
+    FP64 closed form of eq. (23), passivity check, upload) and the device
+    run from captured graphs."""
+    import numpy as np
+    import workloads as W
+    from paper_1609_07114_amd import romgen
+    from paper_1609_07114_amd.sim import Simulation
+    out = {}
+    for name, mk, n in (("E3", W.iris_waveguide, 4000), ("E4", W.rods_reflection, 2000)):
+        n = steps or n
+        res = {}
+        for mode in ("coarse", "mor_only", "cfl_only", "proposed"):
+            prob = W.ablation(mk, mode, n)
+            cfg = W.ABLATIONS[mode]
+            t0 = time.perf_counter()
+            roms = romgen.build_roms(prob, basis=cfg["basis"], clip=cfg["clip"]) if prob.roms else []
+            t_build = time.perf_counter() - t0
+            for s, m in zip(prob.roms, roms):
+                s.q = m["Rt"].shape[0]
+            t0 = time.perf_counter()
+            sim = Simulation(prob, roms, dtype=dtype)
+            t_setup = time.perf_counter() - t0
+            sim.set_graph(min(prob.nsteps, 200))
+            t_run, ev = _timed(sim.stream, lambda: sim.run(prob.nsteps))
+            pr = sim.probes()
+            sim.close()
+            res[mode] = {"steps": prob.nsteps, "model_states": [s.q for s in prob.roms],
+                         "model_build_s": round(t_build, 3), "setup_s": round(t_setup, 3),
+                         "run_s": round(t_run, 4), "us_per_step": round(ev * 1e3 / prob.nsteps, 2),
+                         "total_s": round(t_build + t_setup + t_run, 3),
+                         "finite": bool(np.all(np.isfinite(pr))),
+                         "paper_runtime_s": PAPER_VARIANT_S[name][mode]}
+            if log:
+                log(f"{name} {mode}: build {t_build:.1f} s, setup {t_setup:.1f} s, run {t_run:.3f} s "
+                    f"({res[mode]['us_per_step']} us/step, {prob.nsteps} steps)")
+        out[name] = {"dtype": dtype, "variants": res,
+                     "paper_context": "Matlab, one 3.6 GHz CPU, model building included, step counts not stated"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,7 +393,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched, many-copies and adjoint forms")
-    ap.add_argument("--only", choices=["batched", "many_copies", "adjoint", "hbm_resident", "waveguides"], default=None,
+    ap.add_argument("--only", choices=["batched", "many_copies", "adjoint", "hbm_resident", "waveguides",
+                                       "ablations"], default=None,
                     help="run one form alone and print its JSON (profiling)")
     ap.add_argument("--form-steps", type=int, default=None, help="timed steps of the batched / many-copies form")
     ap.add_argument("--copy-ceiling", action="store_true", help="only measure device copy rates and exit")
@@ -371,7 +423,8 @@ def main():
         log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
         kw = {} if args.form_steps is None or args.only == "adjoint" else {"steps": args.form_steps}
         fn = {"batched": bench_batched, "many_copies": bench_many_copies, "adjoint": bench_adjoint,
-              "hbm_resident": bench_hbm_resident, "waveguides": bench_waveguides}[args.only]
+              "hbm_resident": bench_hbm_resident, "waveguides": bench_waveguides,
+              "ablations": bench_ablations}[args.only]
         print(json.dumps({args.only: fn(log=log, **kw)}), flush=True)
         return
     total = args.warmup + args.steps

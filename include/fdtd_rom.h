@@ -76,7 +76,9 @@ typedef struct {
  * starts at L~^T x0.  group >= 0: regions with the same group use one
  * copy of the matrices on the device (their Rt/Ft/Lt must be identical and
  * their surroundings must give identical interface half cells).
- * Limits: 1 <= q <= 4096 and np = 2 (ni + nj) <= 1024, else FDTD_EINVAL. */
+ * Limits: 1 <= q <= 16384, np = 2 (ni + nj) <= 1024, and q + np rounded up
+ * to 64 must fit 64 KB of elements (16384 FP32, 8192 FP64: the coupling
+ * workgroups stage [x~; h] in LDS), else FDTD_EINVAL. */
 typedef struct {
   int32_t i0, j0, ni, nj;
   int32_t q;
@@ -236,10 +238,16 @@ int fdtd_rom_coupled_update(const fdtd_problem* prob, int32_t k, double* A, doub
  *      R11^{-1/2} K~ R22^{-1/2} exceeds theta * 2/dt (eq. (27)), the
  *      singular values above that bound are lowered to it and K~ is
  *      replaced in R~ and F~ (theta <= 0 selects 0.99).
+ * basis 1 replaces steps 2-4 by V = I (no reduction: R~, F~, L~ are the
+ * restricted fine model's own, q must equal its state count); with clip
+ * this is the paper's "CFL extension only" configuration (Tabs. I-III), with
+ * basis 0 and clip = 0 at dt within the fine limit its "MOR only" one.
  * eps_r, sigma: host fine-cell maps [(r*nj) * (r*ni)], row-major.
  * Outputs (caller-allocated, row-major): Rt [q*q], Ft [q*q], Lt [q*np];
- * state order: q1 E coordinates then q2 H coordinates.  FDTD_EINVAL if the
- * Krylov space deflates below q.  Thread-safe (no shared state). */
+ * state order: q1 E coordinates then q2 H coordinates.  With Rt, Ft and Lt
+ * all NULL the call only fills info (q1, q2 and the restricted state count
+ * for these parameters).  FDTD_EINVAL if the Krylov space deflates below q.
+ * Thread-safe (no shared state). */
 typedef struct {
   int32_t ni, nj, r;
   double dx, dy, dt;
@@ -249,6 +257,7 @@ typedef struct {
   double f_max;
   double theta;
   int32_t clip;
+  int32_t basis;  /* 0: SPRIM (steps 2-4), 1: identity */
 } fdtd_rom_build_params;
 
 typedef struct {

@@ -58,7 +58,7 @@ class fdtd_rom_build_params(C.Structure):
     _fields_ = [("ni", C.c_int32), ("nj", C.c_int32), ("r", C.c_int32), ("dx", C.c_double),
                 ("dy", C.c_double), ("dt", C.c_double), ("eps_r", _dp), ("sigma", _dp),
                 ("q", C.c_int32), ("f_max", C.c_double), ("theta", C.c_double),
-                ("clip", C.c_int32)]
+                ("clip", C.c_int32), ("basis", C.c_int32)]
 
 
 class fdtd_rom_build_info(C.Structure):
@@ -275,18 +275,25 @@ def fdtd_rom_coupled_update(problem: ProblemStruct, k: int):
     return A, B, Cm
 
 
-def fdtd_rom_build(ni, nj, r, dx, dy, dt, eps_r, sigma, q, f_max, theta=0.99, clip=True):
-    """Reduced model of one refined region (host FP64 in the library)."""
+def fdtd_rom_build(ni, nj, r, dx, dy, dt, eps_r, sigma, q, f_max, theta=0.99, clip=True,
+                   basis="sprim"):
+    """Model of one refined region (host FP64 in the library).  basis
+    'sprim' reduces to order q; 'identity' keeps the restricted fine model
+    (q is then its state count and the argument is ignored)."""
     er = np.ascontiguousarray(eps_r, dtype=np.float64)
     sg = np.ascontiguousarray(sigma, dtype=np.float64)
     assert er.shape == (r * nj, r * ni) and sg.shape == er.shape
+    b = {"sprim": 0, "identity": 1}[basis]
     np_ = 2 * (ni + nj)
+    prm = fdtd_rom_build_params(ni, nj, r, dx, dy, dt, _ptr(er), _ptr(sg), q, f_max, theta,
+                                1 if clip else 0, b)
+    info = fdtd_rom_build_info()
+    if b == 1:
+        _check(lib().fdtd_rom_build(C.byref(prm), None, None, None, C.byref(info)))
+        q = prm.q = info.n_fine_states
     Rt = np.zeros((q, q))
     Ft = np.zeros((q, q))
     Lt = np.zeros((q, np_))
-    prm = fdtd_rom_build_params(ni, nj, r, dx, dy, dt, _ptr(er), _ptr(sg), q, f_max, theta,
-                                1 if clip else 0)
-    info = fdtd_rom_build_info()
     _check(lib().fdtd_rom_build(C.byref(prm), _ptr(Rt), _ptr(Ft), _ptr(Lt), C.byref(info)))
     return dict(Rt=Rt, Ft=Ft, Lt=Lt, q1=info.q1, q2=info.q2, p0=info.p0,
                 smax_before=info.smax_before, smax_after=info.smax_after,

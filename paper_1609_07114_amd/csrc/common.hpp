@@ -9,7 +9,8 @@ namespace fdtd {
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kBlock = 256;        // threads per workgroup (4 waves)
 constexpr int kMaxSrc = 4;         // sources applied inside the stencil kernel
-constexpr int kMaxQ = 4096;        // reduced order handled by the coupling kernels ((q + np) staged in LDS: <= 40 KB FP64)
+constexpr int kMaxQ = 16384;       // model order handled by the coupling kernels (also bounded by kMaxStageBytes)
+constexpr int kMaxStageBytes = 65536;  // LDS of a coupling workgroup's staged [x~; h] (padded q + np elements)
 constexpr int kMaxPorts = 1024;    // ports per region
 constexpr int kCtrlInts = 4;       // ctrl[0] = step, ctrl[1] = finished-block count
 

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstddef>
 #include <limits>
+#include <thread>
 #include <vector>
 
 namespace fdtd {
@@ -154,6 +155,41 @@ inline void gram(const double* const* A, int ka, const double* const* B, int kb,
     for (; i < ka; ++i)
       for (int j = 0; j < (lower ? std::min(kb, i + 1) : kb); ++j) C[(size_t)i * ldc + j] += dot(A[i] + t0, B[j] + t0, len);
   }
+}
+
+// gram() with the rows of A split over host threads when the product is
+// large (the setup of models with thousands of states); small products run
+// on the calling thread.
+inline void gram_mt(const double* const* A, int ka, const double* const* B, int kb, size_t n, double* C,
+                    size_t ldc, bool lower = false) {
+  const double work = (double)ka * kb * (double)n;
+  int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+  if (work < 2e8 || nt < 2 || ka < 8 * nt) {
+    gram(A, ka, B, kb, n, C, ldc, false, lower);
+    return;
+  }
+  std::vector<std::thread> th;
+  // rows in chunks of 4 (the register block), balanced by work when lower
+  std::vector<int> cut(nt + 1, 0);
+  for (int t = 1; t <= nt; ++t) {
+    const double f = (double)t / nt;
+    int r = lower ? (int)(ka * std::sqrt(f)) : (int)(ka * f);
+    cut[t] = std::min(ka, (r + 3) / 4 * 4);
+  }
+  cut[nt] = ka;
+  for (int t = 0; t < nt; ++t) {
+    const int r0 = cut[t], r1 = cut[t + 1];
+    if (r1 <= r0) continue;
+    th.emplace_back([=]() {
+      if (lower) {
+        // rows r0..r1 need columns up to r1 only
+        gram(A + r0, r1 - r0, B, std::min(kb, r1), n, C + (size_t)r0 * ldc, ldc, false, false);
+      } else {
+        gram(A + r0, r1 - r0, B, kb, n, C + (size_t)r0 * ldc, ldc, false, false);
+      }
+    });
+  }
+  for (auto& x : th) x.join();
 }
 
 // Y[i] += sum_j C[j * ldc + i] D[j] for i < m, j < k over n elements (a

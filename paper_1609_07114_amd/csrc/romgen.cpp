@@ -416,14 +416,19 @@ using fdtd::fail;
 
 extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, double* Ft, double* Lt,
                               fdtd_rom_build_info* info) {
-  if (!prm || !Rt || !Ft || !Lt) return fail(FDTD_EINVAL, "null argument");
+  if (!prm) return fail(FDTD_EINVAL, "null argument");
+  const bool query = !Rt && !Ft && !Lt;
+  if (query ? !info : (!Rt || !Ft || !Lt)) return fail(FDTD_EINVAL, "null argument");
   const fdtd_rom_build_params& P = *prm;
   if (P.ni < 1 || P.nj < 1 || P.r < 1) return fail(FDTD_EINVAL, "bad region size");
   if (!(P.dx > 0) || !(P.dy > 0) || !(P.dt > 0)) return fail(FDTD_EINVAL, "dx, dy, dt must be positive");
   if (!P.eps_r || !P.sigma) return fail(FDTD_EINVAL, "fine material maps required");
-  if (P.q < 2) return fail(FDTD_EINVAL, "order q must be >= 2");
+  if (P.basis != 0 && P.basis != 1) return fail(FDTD_EINVAL, "basis must be 0 (SPRIM) or 1 (identity)");
+  const bool ident = P.basis == 1;
+  if (!ident && !query && P.q < 2) return fail(FDTD_EINVAL, "order q must be >= 2");
   const double p0 = 3.14159265358979323846 * P.f_max * P.dt;
-  if (!(p0 > 0.0 && p0 < 1.0)) return fail(FDTD_EINVAL, "expansion point p0 = pi f_max dt = %g outside (0, 1)", p0);
+  if (!ident && !(p0 > 0.0 && p0 < 1.0))
+    return fail(FDTD_EINVAL, "expansion point p0 = pi f_max dt = %g outside (0, 1)", p0);
   const double theta = P.theta > 0 ? P.theta : 0.99;
   const size_t nf = (size_t)P.r * P.ni * P.r * P.nj;
   for (size_t k = 0; k < nf; ++k)
@@ -431,83 +436,133 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
   try {
     FineModel fm;
     assemble(fm, P.ni, P.nj, P.r, P.dx, P.dy, P.dt, P.eps_r, P.sigma);
-    const int q1 = (P.q + 1) / 2, q2 = P.q / 2;
-    if (q1 > fm.nE || q2 > fm.nH) return fail(FDTD_EINVAL, "order q=%d exceeds the fine model", P.q);
-    Solver sol;
-    if (!sol.init(fm, p0)) return fail(FDTD_EINVAL, "Schur complement not positive definite");
-    Cols dirs;
-    std::string err;
-    const int need = std::max(q1, q2);
-    if (!krylov_dirs(sol, fm, need + 8, dirs, err)) return fail(FDTD_EINVAL, "%s", err.c_str());
-    Cols V1 = gs_part(dirs, 0, fm.nE, q1);
-    Cols V2 = gs_part(dirs, fm.nE, fm.nH, q2);
-    if ((int)V1.size() < q1 || (int)V2.size() < q2)
-      return fail(FDTD_EINVAL, "Krylov space too small for q=%d (got %zu E, %zu H)", P.q, V1.size(), V2.size());
-    const int q = q1 + q2, np = fm.np;
-    // congruence (eqs. (11)-(12))
-    std::vector<double> R((size_t)q * q, 0.0), F((size_t)q * q, 0.0);
-    {
-      Cols VD(q1, std::vector<double>(fm.nE)), VS(q1, std::vector<double>(fm.nE));
-      std::vector<const double*> V1p(q1), VDp(q1), VSp(q1);
-      for (int a = 0; a < q1; ++a) {
-        for (int e = 0; e < fm.nE; ++e) {
-          VD[a][e] = V1[a][e] * fm.De[e];
-          VS[a][e] = V1[a][e] * fm.Ds[e];
-        }
-        V1p[a] = V1[a].data();
-        VDp[a] = VD[a].data();
-        VSp[a] = VS[a].data();
-      }
-      std::vector<double> GR((size_t)q1 * q1), GF((size_t)q1 * q1);
-      fdtd::la::gram(VDp.data(), q1, V1p.data(), q1, fm.nE, GR.data(), q1, false, true);
-      fdtd::la::gram(VSp.data(), q1, V1p.data(), q1, fm.nE, GF.data(), q1, false, true);
-      for (int a = 0; a < q1; ++a)
-        for (int b2 = 0; b2 <= a; ++b2) {
-          R[(size_t)a * q + b2] = R[(size_t)b2 * q + a] = GR[(size_t)a * q1 + b2] / P.dt;
-          F[(size_t)a * q + b2] = F[(size_t)b2 * q + a] = 0.5 * GF[(size_t)a * q1 + b2];
-        }
+    const int q1 = ident ? fm.nE : (P.q + 1) / 2, q2 = ident ? fm.nH : P.q / 2;
+    if (query) {
+      info->q1 = q1;
+      info->q2 = q2;
+      info->p0 = p0;
+      info->smax_before = info->smax_after = 0.0;
+      info->clipped = 0;
+      info->n_fine_states = fm.n;
+      return FDTD_OK;
     }
-    std::vector<double> Kt((size_t)q1 * q2);  // K~ = V1^T K V2
-    {
-      Cols KV(q2, std::vector<double>(fm.nE));
-      std::vector<const double*> KVp(q2), V1p(q1), V2p(q2);
-      for (int c = 0; c < q2; ++c) {
-        spmv(fm.K, V2[c].data(), KV[c].data());
-        KVp[c] = KV[c].data();
-        V2p[c] = V2[c].data();
+    if (ident && P.q != fm.n)
+      return fail(FDTD_EINVAL, "identity basis: q must equal the restricted state count %d (got %d)", fm.n, P.q);
+    if (q1 > fm.nE || q2 > fm.nH) return fail(FDTD_EINVAL, "order q=%d exceeds the fine model", P.q);
+    const int q = q1 + q2, np = fm.np;
+    double* R = Rt;  // written in place: R~ and F~ of eqs. (11)-(12), q x q row-major
+    double* F = Ft;
+    std::fill(R, R + (size_t)q * q, 0.0);
+    std::fill(F, F + (size_t)q * q, 0.0);
+    std::vector<double> Kt((size_t)q1 * q2, 0.0);  // K~ = V1^T K V2
+    Cols V1;
+    if (ident) {
+      // V = I: R~ = R, F~ = F, L~ = Lc of the restricted fine model
+      for (int e = 0; e < q1; ++e) {
+        R[(size_t)e * q + e] = fm.De[e] / P.dt;
+        F[(size_t)e * q + e] = 0.5 * fm.Ds[e];
+        for (int k = fm.K.ptr[e]; k < fm.K.ptr[e + 1]; ++k) Kt[(size_t)e * q2 + fm.K.col[k]] = fm.K.val[k];
       }
-      for (int a = 0; a < q1; ++a) V1p[a] = V1[a].data();
-      fdtd::la::gram(V1p.data(), q1, KVp.data(), q2, fm.nE, Kt.data(), q2);
-      std::vector<double> GH((size_t)q2 * q2);
-      fdtd::la::gram(V2p.data(), q2, V2p.data(), q2, fm.nH, GH.data(), q2, false, true);
-      for (int a = 0; a < q2; ++a)
-        for (int b2 = 0; b2 <= a; ++b2)
-          R[(size_t)(q1 + a) * q + q1 + b2] = R[(size_t)(q1 + b2) * q + q1 + a] = fm.Dm / P.dt * GH[(size_t)a * q2 + b2];
+      for (int h = 0; h < q2; ++h) R[(size_t)(q1 + h) * q + q1 + h] = fm.Dm / P.dt;
+    } else {
+      Solver sol;
+      if (!sol.init(fm, p0)) return fail(FDTD_EINVAL, "Schur complement not positive definite");
+      Cols dirs;
+      std::string err;
+      const int need = std::max(q1, q2);
+      if (!krylov_dirs(sol, fm, need + 8, dirs, err)) return fail(FDTD_EINVAL, "%s", err.c_str());
+      V1 = gs_part(dirs, 0, fm.nE, q1);
+      Cols V2 = gs_part(dirs, fm.nE, fm.nH, q2);
+      if ((int)V1.size() < q1 || (int)V2.size() < q2)
+        return fail(FDTD_EINVAL, "Krylov space too small for q=%d (got %zu E, %zu H)", P.q, V1.size(), V2.size());
+      // congruence (eqs. (11)-(12))
+      {
+        Cols VD(q1, std::vector<double>(fm.nE)), VS(q1, std::vector<double>(fm.nE));
+        std::vector<const double*> V1p(q1), VDp(q1), VSp(q1);
+        for (int a = 0; a < q1; ++a) {
+          for (int e = 0; e < fm.nE; ++e) {
+            VD[a][e] = V1[a][e] * fm.De[e];
+            VS[a][e] = V1[a][e] * fm.Ds[e];
+          }
+          V1p[a] = V1[a].data();
+          VDp[a] = VD[a].data();
+          VSp[a] = VS[a].data();
+        }
+        std::vector<double> GR((size_t)q1 * q1), GF((size_t)q1 * q1);
+        fdtd::la::gram(VDp.data(), q1, V1p.data(), q1, fm.nE, GR.data(), q1, false, true);
+        fdtd::la::gram(VSp.data(), q1, V1p.data(), q1, fm.nE, GF.data(), q1, false, true);
+        for (int a = 0; a < q1; ++a)
+          for (int b2 = 0; b2 <= a; ++b2) {
+            R[(size_t)a * q + b2] = R[(size_t)b2 * q + a] = GR[(size_t)a * q1 + b2] / P.dt;
+            F[(size_t)a * q + b2] = F[(size_t)b2 * q + a] = 0.5 * GF[(size_t)a * q1 + b2];
+          }
+      }
+      {
+        Cols KV(q2, std::vector<double>(fm.nE));
+        std::vector<const double*> KVp(q2), V1p(q1), V2p(q2);
+        for (int c = 0; c < q2; ++c) {
+          spmv(fm.K, V2[c].data(), KV[c].data());
+          KVp[c] = KV[c].data();
+          V2p[c] = V2[c].data();
+        }
+        for (int a = 0; a < q1; ++a) V1p[a] = V1[a].data();
+        fdtd::la::gram(V1p.data(), q1, KVp.data(), q2, fm.nE, Kt.data(), q2);
+        std::vector<double> GH((size_t)q2 * q2);
+        fdtd::la::gram(V2p.data(), q2, V2p.data(), q2, fm.nH, GH.data(), q2, false, true);
+        for (int a = 0; a < q2; ++a)
+          for (int b2 = 0; b2 <= a; ++b2)
+            R[(size_t)(q1 + a) * q + q1 + b2] = R[(size_t)(q1 + b2) * q + q1 + a] = fm.Dm / P.dt * GH[(size_t)a * q2 + b2];
+      }
     }
     // eq. (27): singular values s_k of R11^{-1/2} K~ R22^{-1/2} against 2/dt.
     // With Cholesky factors R11 = L1 L1^T, R22 = L2 L2^T the matrix
     // M = L1^{-1} K~ L2^{-T} is orthogonally equivalent to it (R^{1/2} =
     // L Omega with Omega orthogonal), and lowering singular values commutes
     // with orthogonal factors, so K~' = L1 clip(M) L2^T is the same update.
-    std::vector<double> L1((size_t)q1 * q1), L2((size_t)q2 * q2);
-    for (int a = 0; a < q1; ++a)
-      for (int b2 = 0; b2 < q1; ++b2) L1[(size_t)a * q1 + b2] = P.dt * R[(size_t)a * q + b2];
-    for (int a = 0; a < q2; ++a)
-      for (int b2 = 0; b2 < q2; ++b2) L2[(size_t)a * q2 + b2] = P.dt * R[(size_t)(q1 + a) * q + q1 + b2];
-    if (!fdtd::la::cholesky(q1, L1.data()) || !fdtd::la::cholesky(q2, L2.data()))
+    // Diagonal R11 or R22 (the identity basis) make the factors scalings.
+    auto block_diag = [&](int o, int n) {
+      for (int a = 0; a < n; ++a)
+        for (int b2 = 0; b2 < n; ++b2)
+          if (a != b2 && R[(size_t)(o + a) * q + o + b2] != 0.0) return false;
+      return true;
+    };
+    const bool d1 = block_diag(0, q1), d2 = block_diag(q1, q2);
+    std::vector<double> L1, L2;  // dense lower factors, or the diagonal of the factor
+    auto factor = [&](int o, int n, bool diag, std::vector<double>& L) {
+      if (diag) {
+        L.resize(n);
+        for (int a = 0; a < n; ++a) {
+          const double v = P.dt * R[(size_t)(o + a) * q + o + a];
+          if (!(v > 0.0)) return false;
+          L[a] = std::sqrt(v);
+        }
+        return true;
+      }
+      L.assign((size_t)n * n, 0.0);
+      for (int a = 0; a < n; ++a)
+        for (int b2 = 0; b2 < n; ++b2) L[(size_t)a * n + b2] = P.dt * R[(size_t)(o + a) * q + o + b2];
+      return fdtd::la::cholesky(n, L.data());
+    };
+    if (!factor(0, q1, d1, L1) || !factor(q1, q2, d2, L2))
       return fail(FDTD_EINVAL, "reduced R~ not positive definite (basis lost rank)");
-    // X = L1^{-1} K~ by rows, then each row m of M solves L2 m^T = x^T
+    // M = L1^{-1} K~ L2^{-T}: rows by forward substitution with L1, then each
+    // row m solves L2 m^T = x^T
     std::vector<double> M(Kt);
     for (int a = 0; a < q1; ++a) {
       double* xa = M.data() + (size_t)a * q2;
-      for (int b2 = 0; b2 < a; ++b2) fdtd::la::axpy(-L1[(size_t)a * q1 + b2], M.data() + (size_t)b2 * q2, xa, q2);
-      const double inv = 1.0 / L1[(size_t)a * q1 + a];
+      if (!d1)
+        for (int b2 = 0; b2 < a; ++b2) fdtd::la::axpy(-L1[(size_t)a * q1 + b2], M.data() + (size_t)b2 * q2, xa, q2);
+      const double inv = 1.0 / (d1 ? L1[a] : L1[(size_t)a * q1 + a]);
       for (int c = 0; c < q2; ++c) xa[c] *= inv;
     }
     for (int a = 0; a < q1; ++a) {
       double* ma = M.data() + (size_t)a * q2;
-      for (int c = 0; c < q2; ++c) ma[c] = (ma[c] - fdtd::la::dot(L2.data() + (size_t)c * q2, ma, c)) / L2[(size_t)c * q2 + c];
+      if (d2)
+        for (int c = 0; c < q2; ++c) ma[c] /= L2[c];
+      else
+        for (int c = 0; c < q2; ++c) ma[c] = (ma[c] - fdtd::la::dot(L2.data() + (size_t)c * q2, ma, c)) / L2[(size_t)c * q2 + c];
     }
+    // M^T M by rank-one row updates (rows of a sparse M cost their nonzeros)
     std::vector<double> MtM((size_t)q2 * q2, 0.0), Wv((size_t)q2 * q2), s2(q2);
     for (int a = 0; a < q1; ++a) {
       const double* ma = M.data() + (size_t)a * q2;
@@ -524,27 +579,52 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
     if (P.clip && smax > lim) {
       clipped = 1;
       smax_after = 0;
-      std::vector<double> wk(q2), uk(q1);
+      // lowering s_k to lim along the right singular vector w_k is
+      // M <- M (I - sum_k d_k w_k w_k^T), d_k = (s_k - lim) / s_k (the w_k
+      // are orthonormal, so the rank-one changes do not interact)
+      std::vector<int> cl;
       for (int k = 0; k < q2; ++k) {
         const double sk = std::sqrt(std::max(0.0, s2[k]));
-        if (sk <= lim) {
-          smax_after = std::max(smax_after, sk);
-          continue;
-        }
-        smax_after = std::max(smax_after, lim);
-        // M -= (s_k - lim) u_k w_k^T with u_k = M w_k / s_k
-        for (int i = 0; i < q2; ++i) wk[i] = Wv[(size_t)i * q2 + k];
-        for (int a = 0; a < q1; ++a) uk[a] = fdtd::la::dot(M.data() + (size_t)a * q2, wk.data(), q2) / sk;
-        for (int a = 0; a < q1; ++a) fdtd::la::axpy(-(sk - lim) * uk[a], wk.data(), M.data() + (size_t)a * q2, q2);
+        if (sk > lim) cl.push_back(k);
+        smax_after = std::max(smax_after, std::min(sk, lim));
       }
-      // K~ = L1 M L2^T
-      std::vector<double> T((size_t)q1 * q2, 0.0);
-      for (int a = 0; a < q1; ++a)
-        for (int b2 = 0; b2 <= a; ++b2)
-          fdtd::la::axpy(L1[(size_t)a * q1 + b2], M.data() + (size_t)b2 * q2, T.data() + (size_t)a * q2, q2);
+      const int nc = (int)cl.size();
+      Cols Wc(q2, std::vector<double>(nc));
+      std::vector<const double*> Wp(q2);
+      for (int i = 0; i < q2; ++i) {
+        for (int c = 0; c < nc; ++c) {
+          const double sk = std::sqrt(s2[cl[c]]);
+          Wc[i][c] = Wv[(size_t)i * q2 + cl[c]] * std::sqrt((sk - lim) / sk);
+        }
+        Wp[i] = Wc[i].data();
+      }
+      std::vector<double> Pm((size_t)q2 * q2);
+      fdtd::la::gram(Wp.data(), q2, Wp.data(), q2, nc, Pm.data(), q2);
+      for (size_t k = 0; k < Pm.size(); ++k) Pm[k] = -Pm[k];
+      for (int i = 0; i < q2; ++i) Pm[(size_t)i * q2 + i] += 1.0;
+      // M' = M P row by row over each row's nonzeros; then K~ = L1 M' L2^T
+      std::vector<double> Mc((size_t)q1 * q2, 0.0);
+      for (int a = 0; a < q1; ++a) {
+        const double* ma = M.data() + (size_t)a * q2;
+        double* out = Mc.data() + (size_t)a * q2;
+        for (int i = 0; i < q2; ++i)
+          if (ma[i] != 0.0) fdtd::la::axpy(ma[i], Pm.data() + (size_t)i * q2, out, q2);
+      }
+      std::vector<double> T;
+      if (d1) {
+        for (int a = 0; a < q1; ++a)
+          for (int c = 0; c < q2; ++c) Mc[(size_t)a * q2 + c] *= L1[a];
+      } else {
+        T.assign((size_t)q1 * q2, 0.0);
+        for (int a = 0; a < q1; ++a)
+          for (int b2 = 0; b2 <= a; ++b2)
+            fdtd::la::axpy(L1[(size_t)a * q1 + b2], Mc.data() + (size_t)b2 * q2, T.data() + (size_t)a * q2, q2);
+        Mc.swap(T);
+      }
       for (int a = 0; a < q1; ++a)
         for (int c = 0; c < q2; ++c)
-          Kt[(size_t)a * q2 + c] = fdtd::la::dot(T.data() + (size_t)a * q2, L2.data() + (size_t)c * q2, c + 1);
+          Kt[(size_t)a * q2 + c] = d2 ? Mc[(size_t)a * q2 + c] * L2[c]
+                                      : fdtd::la::dot(Mc.data() + (size_t)a * q2, L2.data() + (size_t)c * q2, c + 1);
     }
     for (int a = 0; a < q1; ++a)
       for (int c = 0; c < q2; ++c) {
@@ -554,10 +634,9 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
         F[(size_t)a * q + q1 + c] = -0.5 * k;
         F[(size_t)(q1 + c) * q + a] = +0.5 * k;
       }
-    std::memcpy(Rt, R.data(), R.size() * sizeof(double));
-    std::memcpy(Ft, F.data(), F.size() * sizeof(double));
     for (int a = 0; a < q; ++a)
-      for (int p = 0; p < np; ++p) Lt[(size_t)a * np + p] = a < q1 ? V1[a][fm.port_row[p]] : 0.0;
+      for (int p = 0; p < np; ++p)
+        Lt[(size_t)a * np + p] = a < q1 ? (ident ? (a == fm.port_row[p] ? 1.0 : 0.0) : V1[a][fm.port_row[p]]) : 0.0;
     if (info) {
       info->q1 = q1;
       info->q2 = q2;

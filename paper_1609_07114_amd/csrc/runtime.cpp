@@ -68,6 +68,9 @@ int fdtd::plan_problem(const fdtd_problem* p, Layout& L) {
     if (r.ni < 1 || r.nj < 1) return fail(FDTD_EINVAL, "region %d: empty footprint", k);
     if (r.q < 1 || r.q > kMaxQ) return fail(FDTD_EINVAL, "region %d: order q=%d outside [1, %d]", k, r.q, kMaxQ);
     if (ports_of(r) > kMaxPorts) return fail(FDTD_EINVAL, "region %d: %d ports exceed %d", k, ports_of(r), kMaxPorts);
+    if (align_up((size_t)r.q + ports_of(r), kWave) * (g.dtype == FDTD_F64 ? 8 : 4) > (size_t)kMaxStageBytes)
+      return fail(FDTD_EINVAL, "region %d: q + np = %d exceeds the coupling staging (%d bytes)", k,
+                  r.q + ports_of(r), kMaxStageBytes);
     if (!r.Rt || !r.Ft || !r.Lt) return fail(FDTD_EINVAL, "region %d: missing matrices", k);
     int slot = -1;
     if (r.group >= 0) {
@@ -515,6 +518,79 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
   return FDTD_OK;
 }
 
+// RHS <- M^{-1} RHS (q x (q + np)).  When M = [[D1, M12], [0, D2]] with D1
+// and D2 diagonal (a model kept in the identity basis: R~ + F~ is block
+// upper triangular and its diagonal blocks are diagonal, the interface
+// terms L~ C+ L~^T touch distinct port rows), block back substitution
+// X2 = D2^{-1} RHS2, X1 = D1^{-1} (RHS1 - M12 X2) with one threaded product;
+// otherwise LU with partial pivoting.  False if M is singular.
+bool solve_closed_form(int q, int np, std::vector<double>& M, std::vector<double>& RHS) {
+  const int m = q + np;
+  auto diag_only = [&](int r, int c0, int c1) {
+    for (int c = c0; c < c1; ++c)
+      if (c != r && M[(size_t)r * q + c] != 0.0) return false;
+    return M[(size_t)r * q + r] != 0.0;
+  };
+  int t = 0;  // trailing rows with only their diagonal
+  while (t < q && diag_only(q - 1 - t, 0, q)) ++t;
+  const int q1 = q - t;
+  bool structured = t > 0 && q1 > 0;
+  for (int r = 0; r < q1 && structured; ++r) structured = diag_only(r, 0, q1);
+  if (!structured) {
+    std::vector<int> piv;
+    if (!la::lu_factor(q, M.data(), piv)) return false;
+    la::lu_solve(q, M.data(), piv, RHS.data(), m);
+    return true;
+  }
+  for (int r = q1; r < q; ++r) {
+    const double inv = 1.0 / M[(size_t)r * q + r];
+    for (int c = 0; c < m; ++c) RHS[(size_t)r * m + c] *= inv;
+  }
+  // P = M12 X2 as C[i][j] = dot(M12 row i, X2 column j)
+  std::vector<std::vector<double>> X2t(m, std::vector<double>(t));
+  for (int r = 0; r < t; ++r)
+    for (int c = 0; c < m; ++c) X2t[c][r] = RHS[(size_t)(q1 + r) * m + c];
+  std::vector<const double*> Ap(q1), Bp(m);
+  for (int r = 0; r < q1; ++r) Ap[r] = M.data() + (size_t)r * q + q1;
+  for (int c = 0; c < m; ++c) Bp[c] = X2t[c].data();
+  std::vector<double> Pm((size_t)q1 * m);
+  la::gram_mt(Ap.data(), q1, Bp.data(), m, (size_t)t, Pm.data(), m);
+  for (int r = 0; r < q1; ++r) {
+    const double inv = 1.0 / M[(size_t)r * q + r];
+    for (int c = 0; c < m; ++c) RHS[(size_t)r * m + c] = (RHS[(size_t)r * m + c] - Pm[(size_t)r * m + c]) * inv;
+  }
+  return true;
+}
+
+// Is the symmetric q x q matrix A positive definite?  With A = [D B; B^T C]
+// and D its largest leading diagonal block (the whole E block of a model
+// kept in the identity basis), A > 0 exactly when D > 0 and the Schur
+// complement C - B^T D^{-1} B > 0 (checked by Cholesky); with no diagonal
+// leading block this is a Cholesky of A itself.
+bool positive_definite(int q, const double* A) {
+  int k = 0;
+  for (; k < q; ++k) {
+    bool diag_row = true;
+    for (int b = 0; b < k && diag_row; ++b) diag_row = A[(size_t)k * q + b] == 0.0;
+    if (!diag_row || !(A[(size_t)k * q + k] > 0.0)) break;
+  }
+  const int m = q - k;
+  if (m == 0) return true;
+  // rows of D^{-1/2} B as columns: Bt[c][a] = A[a][k + c] / sqrt(A[a][a])
+  std::vector<std::vector<double>> Bt(m, std::vector<double>(k));
+  for (int a = 0; a < k; ++a) {
+    const double s = 1.0 / std::sqrt(A[(size_t)a * q + a]);
+    for (int c = 0; c < m; ++c) Bt[c][a] = A[(size_t)a * q + k + c] * s;
+  }
+  std::vector<const double*> Bp(m);
+  for (int c = 0; c < m; ++c) Bp[c] = Bt[c].data();
+  std::vector<double> S((size_t)m * m, 0.0);
+  if (k > 0) la::gram_mt(Bp.data(), m, Bp.data(), m, (size_t)k, S.data(), m, true);
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; b <= a; ++b) S[(size_t)a * m + b] = A[(size_t)(k + a) * q + k + b] - S[(size_t)a * m + b];
+  return la::cholesky(m, S.data());
+}
+
 int coupling_precompute(const fdtd_problem* p, std::vector<RomHost>& out) {
   const fdtd_grid& g = p->grid;
   const int nx = g.nx;
@@ -534,8 +610,7 @@ int coupling_precompute(const fdtd_problem* p, std::vector<RomHost>& out) {
       }
     if (!(asym <= 1e-12 * rmax))
       return fail(FDTD_ENOTPASSIVE, "region %d: R~ not symmetric (%.3g relative)", k, asym / rmax);
-    std::vector<double> ch(r.Rt, r.Rt + (size_t)q * q);
-    if (!la::cholesky(q, ch.data()))
+    if (!positive_definite(q, r.Rt))
       return fail(FDTD_ENOTPASSIVE, "region %d: R~ is not positive definite at dt (eq. 26a)", k);
     // coarse half cells of eq. (13): Dl Dl' (eps/dt +- sigma/2), outside material
     std::vector<double> cp(np), cm(np), sc(np);
@@ -554,25 +629,36 @@ int coupling_precompute(const fdtd_problem* p, std::vector<RomHost>& out) {
       sc[c] = s;
     }
     // M = R~ + F~ + L~ C+ L~^T ;  RHS = [R~ - F~ + L~ C- L~^T | L~ Sc]
+    // (the L~ C L~^T terms summed over the rows of L~ that are not zero)
     std::vector<double> M((size_t)q * q), RHS((size_t)q * (q + np));
     for (int a = 0; a < q; ++a)
       for (int b = 0; b < q; ++b) {
+        const double R = r.Rt[(size_t)a * q + b], F = r.Ft[(size_t)a * q + b];
+        M[(size_t)a * q + b] = R + F;
+        RHS[(size_t)a * (q + np) + b] = R - F;
+      }
+    std::vector<int> lrows;
+    for (int a = 0; a < q; ++a)
+      for (int c = 0; c < np; ++c)
+        if (r.Lt[(size_t)a * np + c] != 0.0) {
+          lrows.push_back(a);
+          break;
+        }
+    for (int a : lrows)
+      for (int b : lrows) {
         double sp = 0, sm = 0;
         for (int c = 0; c < np; ++c) {
           const double l = r.Lt[(size_t)a * np + c] * r.Lt[(size_t)b * np + c];
           sp += l * cp[c];
           sm += l * cm[c];
         }
-        const double R = r.Rt[(size_t)a * q + b], F = r.Ft[(size_t)a * q + b];
-        M[(size_t)a * q + b] = R + F + sp;
-        RHS[(size_t)a * (q + np) + b] = R - F + sm;
+        M[(size_t)a * q + b] += sp;
+        RHS[(size_t)a * (q + np) + b] += sm;
       }
     for (int a = 0; a < q; ++a)
       for (int c = 0; c < np; ++c) RHS[(size_t)a * (q + np) + q + c] = r.Lt[(size_t)a * np + c] * sc[c];
-    std::vector<int> piv;
-    if (!la::lu_factor(q, M.data(), piv))
+    if (!solve_closed_form(q, np, M, RHS))
       return fail(FDTD_ENOTPASSIVE, "region %d: coupled update matrix is singular", k);
-    la::lu_solve(q, M.data(), piv, RHS.data(), q + np);
     h.A.assign((size_t)q * q, 0.0);
     h.B.assign((size_t)q * np, 0.0);
     h.C.assign((size_t)np * q, 0.0);

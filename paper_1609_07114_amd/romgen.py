@@ -10,7 +10,7 @@ from concurrent.futures import ThreadPoolExecutor
 from . import capi
 
 
-def build_roms(prob, theta=0.99, clip=True, workers=None):
+def build_roms(prob, theta=0.99, clip=True, workers=None, basis="sprim"):
     jobs = []
     slot = {}
     order = []
@@ -23,7 +23,7 @@ def build_roms(prob, theta=0.99, clip=True, workers=None):
 
     def one(spec):
         return capi.fdtd_rom_build(spec.ni, spec.nj, spec.r, prob.dx, prob.dy, prob.dt,
-                                   spec.eps_r, spec.sigma, spec.q, spec.f_max, theta, clip)
+                                   spec.eps_r, spec.sigma, spec.q, spec.f_max, theta, clip, basis)
     workers = workers or min(len(jobs), max(1, min(16, os.cpu_count() or 1))) or 1
     if len(jobs) <= 1:
         built = [one(s) for s in jobs]

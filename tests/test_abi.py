@@ -171,19 +171,46 @@ def test_absorbing_layer_validation():
 
 
 def test_model_order_limits():
-    """Orders up to 4096 are accepted (the rods region of Sec. VI-C needs
-    1920), larger ones are refused before any device work."""
+    """Orders up to what the coupling staging holds are accepted (the rods
+    region of Sec. VI-C needs 1920 reduced, 6848 unreduced), larger ones are
+    refused before any device work: (q + np) padded to 64 elements must fit
+    64 KB (16384 FP32, 8192 FP64)."""
     import copy
-    p = W.rods_reflection(nsteps=10)
+    p = W.rods_reflection(nsteps=10, dtype="f32")
     np_ = p.roms[0].n_ports
 
     def model(q):
         return [dict(Rt=np.eye(q), Ft=np.zeros((q, q)), Lt=np.zeros((q, np_)))]
 
     n = capi.fdtd_rom_workspace_size(_struct(p, model(1920)))
-    assert n > (1920 + np_) ** 2 * 8
+    assert n > (1920 + np_) ** 2 * 4
     q = copy.deepcopy(p)
-    q.roms[0].q = 4097
+    q.roms[0].q = 6848
+    assert capi.fdtd_rom_workspace_size(_struct(q, model(6848))) > 6848 ** 2 * 4
+    q.dtype = "f64"
+    q.roms[0].q = 8200
     with pytest.raises(capi.FdtdError) as e:
-        capi.fdtd_rom_workspace_size(_struct(q, model(4097)))
-    assert "4096" in str(e.value)
+        capi.fdtd_rom_workspace_size(_struct(q, model(8200)))
+    assert "staging" in str(e.value)
+
+
+def test_closed_form_identity_basis_matches_oracle():
+    """A model kept in the identity basis (clip active) makes eq. (23)'s
+    matrix block upper triangular with diagonal blocks; the library solves
+    it by block back substitution.  Same A~, B~' as the oracle's dense solve."""
+    import copy
+    p = W.random_problem(15, 20, 18, 10, nroms=1, block=(4, 3), r=3, q=0, lossy=True)
+    s = p.roms[0]
+    p.dt = 2.9 * W.courant_dt(p.dx / s.r, p.dy / s.r, 0.99)
+    m = capi.fdtd_rom_build(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, 0, s.f_max,
+                            basis="identity")
+    q = copy.deepcopy(p)
+    q.roms[0].q = m["Rt"].shape[0]
+    roms = [dict(Rt=m["Rt"], Ft=m["Ft"], Lt=m["Lt"])]
+    c = ocp.RomCoupling(m["Rt"], m["Ft"], m["Lt"], s.i0, s.j0, s.ni, s.nj, p.eps_r, p.sigma,
+                        p.dx, p.dy, p.dt)
+    A0, B0, C0 = c.closed_form()
+    A, B, C = capi.fdtd_rom_coupled_update(_struct(q, roms), 0)
+    assert np.max(np.abs(A - A0)) <= 1e-12 * np.max(np.abs(A0))
+    assert np.max(np.abs(B - B0)) <= 1e-12 * np.max(np.abs(B0))
+    assert np.array_equal(C, C0)

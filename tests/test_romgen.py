@@ -89,3 +89,45 @@ def test_build_roms_groups_and_threads():
     p2 = W.random_media(n=256, nsteps=10, spacing=128, offset=48, block=16, qs=(16, 24, 32, 48))
     r2 = romgen.build_roms(p2)
     assert [m["Rt"].shape[0] for m in r2] == [s.q for s in p2.roms]
+
+
+def test_identity_basis_matches_oracle():
+    """basis 'identity' (no reduction, the paper's "CFL extension only"
+    configuration): same restricted fine model as the oracle's identity
+    basis, clip of eq. (27) active at 2.9x the fine step, same transfer
+    function; the size query reports the restricted state count."""
+    p = W.random_problem(13, 12, 11, 10, nroms=1, block=(4, 3), r=3, q=0, lossy=True)
+    s = p.roms[0]
+    p.dt = 2.9 * W.courant_dt(p.dx / s.r, p.dy / s.r, 0.99)
+    a = capi.fdtd_rom_build(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, 0, s.f_max,
+                            basis="identity")
+    b = orom.build_rom(s.eps_r, s.sigma, s.r, p.dx, p.dy, p.dt, 0, s.f_max, basis="identity")
+    assert a["Rt"].shape == b["Rt"].shape == (a["n_fine_states"],) * 2
+    assert (a["q1"], a["q2"]) == (b["q1"], b["q2"])
+    assert a["clipped"] and b["clipped"]
+    assert a["smax_before"] == pytest.approx(b["smax_before"], rel=1e-9)
+    assert a["smax_after"] == pytest.approx(b["smax_after"], rel=1e-9)
+    np.linalg.cholesky(a["Rt"])
+    for pv in PVALS:
+        assert _tf_err(a, b, pv) < 1e-9, pv
+    # R~11 and R~22 stay diagonal, F~ has no H-H block
+    q1 = a["q1"]
+    R11 = a["Rt"][:q1, :q1]
+    assert np.array_equal(R11, np.diag(np.diag(R11)))
+    assert np.all(a["Ft"][q1:, q1:] == 0)
+
+
+def test_identity_basis_unclipped_is_the_fine_model():
+    """Below the fine CFL limit nothing is clipped: the identity-basis
+    model is the restricted fine model, equal to the oracle's entry by entry
+    up to the order of the states (compared through H(p) and R~ spectra)."""
+    p = W.random_problem(14, 12, 11, 10, nroms=1, block=(3, 3), r=2, q=0, lossy=True)
+    s = p.roms[0]
+    a = capi.fdtd_rom_build(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, 0, s.f_max,
+                            basis="identity")
+    b = orom.build_rom(s.eps_r, s.sigma, s.r, p.dx, p.dy, p.dt, 0, s.f_max, basis="identity")
+    assert not a["clipped"]
+    ea, eb = np.sort(np.linalg.eigvalsh(a["Rt"])), np.sort(np.linalg.eigvalsh(b["Rt"]))
+    assert np.max(np.abs(ea - eb)) <= 1e-12 * eb.max()
+    for pv in PVALS:
+        assert _tf_err(a, b, pv) < 1e-11, pv

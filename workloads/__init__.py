@@ -474,6 +474,62 @@ def rods_reflection(nsteps: int = 2000, q: int = 1920, rods: bool = True,
                    np.zeros((ny, nx)), [rom], [src], probes, nsteps, dtype, Pml(15, 15, 0, 0))
 
 
+# The method variants compared in Tabs. I-III, as (basis, clip, CFL number
+# relative to the fine mesh's limit): "mor_only" reduces without the CFL
+# extension (so its step stays within the fine limit), "cfl_only" keeps the
+# whole fine model and extends the limit, "proposed" does both; "coarse" is
+# the all-coarse Yee run (no regions, the coarse mesh's own limit).
+ABLATIONS = {
+    "coarse": dict(basis=None, clip=False),
+    "mor_only": dict(basis="sprim", clip=False),
+    "cfl_only": dict(basis="identity", clip=True),
+    "proposed": dict(basis="sprim", clip=True),
+}
+
+
+def ablation(make, mode: str, proposed_steps: int, **kw) -> Problem:
+    """Problem for one method variant of an experiment built by ``make``
+    (``iris_waveguide`` or ``rods_reflection``), simulating the same time as
+    ``proposed_steps`` steps of the proposed method: MOR only runs at 0.99x
+    the fine limit, CFL extension only at the proposed step, the all-coarse
+    run at 0.99x the coarse limit with each region's fine material sampled
+    at the coarse cell centres."""
+    base = make(nsteps=proposed_steps, **kw)
+    r = base.roms[0].r
+    fine_dt = courant_dt(base.dx / r, base.dy / r, 0.99)
+    if mode == "proposed":
+        return base
+    if mode == "cfl_only":
+        return dataclasses.replace(base, name=base.name + "-cfl-only")
+    if mode == "mor_only":
+        n = int(math.ceil(proposed_steps * base.dt / fine_dt))
+        p = make(nsteps=n, cfl_gain=1.0, **kw)
+        # per-step increments of a current scale with the step
+        src = [dataclasses.replace(x, incr=x.incr * (p.dt / base.dt)) for x in p.sources]
+        return dataclasses.replace(p, name=p.name + "-mor-only", sources=src)
+    if mode == "coarse":
+        dt = courant_dt(base.dx, base.dy, 0.99)
+        n = int(math.ceil(proposed_steps * base.dt / dt))
+        p = make(nsteps=n, **kw)
+        eps, sig = p.eps_r.copy(), p.sigma.copy()
+        for s in p.roms:
+            c = s.r // 2
+            eps[s.j0:s.j0 + s.nj, s.i0:s.i0 + s.ni] = s.eps_r[c::s.r, c::s.r]
+            sig[s.j0:s.j0 + s.nj, s.i0:s.i0 + s.ni] = s.sigma[c::s.r, c::s.r]
+        src = [dataclasses.replace(x, incr=_resample(x.incr, p.dt, dt, n)) for x in p.sources]
+        return dataclasses.replace(p, name=p.name + "-coarse", dt=dt, eps_r=eps, sigma=sig, roms=[],
+                                   sources=src, nsteps=n)
+    raise ValueError(mode)
+
+
+def _resample(incr: np.ndarray, dt_old: float, dt_new: float, n: int) -> np.ndarray:
+    """A source waveform sampled at another step (linear interpolation in
+    time, scaled by the step ratio so the injected charge stays the same)."""
+    t_old = np.arange(len(incr)) * dt_old
+    t_new = np.arange(n) * dt_new
+    return np.interp(t_new, t_old, incr, right=0.0) * (dt_new / dt_old)
+
+
 def random_problem(seed: int, nx: int, ny: int, nsteps: int, nroms: int = 2,
                    block: Tuple[int, int] = (6, 5), r: int = 2, q: int = 12,
                    dtype: str = "f64", lossy: bool = True,
