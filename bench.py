@@ -336,6 +336,50 @@ def bench_waveguides(steps=None, log=None):
     return out
 
 
+def bench_sweep(steps=None, log=None, count=64):
+    """A design sweep of the iris guide (Sec. VI-B): ``count`` guides with
+    different apertures (two order-648 models each) as one batch - one launch
+    per step over every guide, replayed from captured graphs - against the
+    same guides run one after another through single-problem handles.  Each
+    batched step streams every guide's model rows ((q+np)^2 FP32 per region,
+    3.8 MB per guide)."""
+    import numpy as np
+    import workloads as W
+    from paper_1609_07114_amd import romgen
+    from paper_1609_07114_amd.batch import Batch
+    from paper_1609_07114_amd.sim import Simulation
+    n = steps or 2000
+    probs = W.iris_sweep(count=count, nsteps=n)
+    t0 = time.perf_counter()
+    roms = romgen.build_roms_many(probs)
+    t_build = time.perf_counter() - t0
+    w = min(200, n // 4)
+    with Batch(probs, roms, max_steps=n) as bt:
+        bt.set_graph(min(n, 200))
+        bt.run(w)
+        t_b, ev_b = _timed(bt.stream, lambda: bt.run(n - w))
+        pb = [bt.probes(b) for b in range(count)]
+    t_p = 0.0
+    err = 0.0
+    for p, r, a in zip(probs, roms, pb):
+        with Simulation(p, r, max_steps=n) as s:
+            s.set_graph(min(n, 200))
+            s.run(w)
+            t, _ = _timed(s.stream, lambda: s.run(n - w))
+            t_p += t
+            b = s.probes()
+            err = max(err, float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)))
+    rows = sum((sp.q + sp.n_ports) ** 2 * 4 for p in probs for sp in p.roms)
+    per = ev_b / 1e3 / (n - w)
+    return {"workload": f"{count} iris guides (apertures 4-26 fine cells), 2 models q=648 each, FP32, "
+                        f"{n} steps ({w} untimed)",
+            "guide_steps_per_s": round(count * (n - w) / t_b, 1),
+            "sequential_guide_steps_per_s": round(count * (n - w) / t_p, 1),
+            "speedup": round(t_p / t_b, 2), "us_per_batched_step": round(per * 1e6, 2),
+            "model_bytes_per_step": rows, "model_GBps": round(rows / per / 1e9, 1),
+            "max_rel_l2_vs_single": err, "model_build_s": round(t_build, 2)}
+
+
 # Tabs. II and III: whole-run Matlab times of the method variants on one
 # 3.6 GHz CPU (model building included), context only.
 PAPER_VARIANT_S = {"E3": {"coarse": 28.9, "mor_only": 245.4, "cfl_only": 484.3, "proposed": 118.5},
@@ -402,7 +446,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched, many-copies and adjoint forms")
     ap.add_argument("--only", choices=["batched", "many_copies", "adjoint", "hbm_resident", "waveguides",
-                                       "ablations"], default=None,
+                                       "ablations", "sweep"], default=None,
                     help="run one form alone and print its JSON (profiling)")
     ap.add_argument("--form-steps", type=int, default=None, help="timed steps of the batched / many-copies form")
     ap.add_argument("--copy-ceiling", action="store_true", help="only measure device copy rates and exit")
@@ -432,7 +476,7 @@ def main():
         kw = {} if args.form_steps is None or args.only == "adjoint" else {"steps": args.form_steps}
         fn = {"batched": bench_batched, "many_copies": bench_many_copies, "adjoint": bench_adjoint,
               "hbm_resident": bench_hbm_resident, "waveguides": bench_waveguides,
-              "ablations": bench_ablations}[args.only]
+              "ablations": bench_ablations, "sweep": bench_sweep}[args.only]
         print(json.dumps({args.only: fn(log=log, **kw)}), flush=True)
         return
     total = args.warmup + args.steps

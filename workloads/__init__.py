@@ -474,6 +474,19 @@ def rods_reflection(nsteps: int = 2000, q: int = 1920, rods: bool = True,
                    np.zeros((ny, nx)), [rom], [src], probes, nsteps, dtype, Pml(15, 15, 0, 0))
 
 
+def iris_sweep(count: int = 64, nsteps: int = 4000, dtype: str = "f32", q: int = 648) -> List[Problem]:
+    """A design sweep over the iris guide of Sec. VI-B: ``count`` guides whose
+    iris apertures step through 4..26 fine cells (two sizes per even value
+    repeat when count > 12), otherwise identical - the kind of parameter
+    study a batch of independent runs serves."""
+    out = []
+    for k in range(count):
+        ap = 4 + 2 * (k % 12)
+        p = iris_waveguide(nsteps=nsteps, q=q, dtype=dtype, aperture=ap)
+        out.append(dataclasses.replace(p, name=f"E3-irises-ap{ap}-{k}"))
+    return out
+
+
 # The method variants compared in Tabs. I-III, as (basis, clip, CFL number
 # relative to the fine mesh's limit): "mor_only" reduces without the CFL
 # extension (so its step stays within the fine limit), "cfl_only" keeps the
