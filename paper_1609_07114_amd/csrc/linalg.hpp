@@ -337,3 +337,34 @@ inline void gemm(int m, int n, int k, const double* A, const double* B, double* 
 
 }  // namespace la
 }  // namespace fdtd
+
+namespace fdtd {
+namespace la {
+
+// add_comb() with the columns split over host threads when the update is
+// large; small updates run on the calling thread.
+inline void add_comb_mt(double* const* Y, int m, const double* const* D, int k, const double* C, size_t ldc,
+                        size_t n) {
+  const double work = (double)m * k * (double)n;
+  const int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+  if (work < 2e8 || nt < 2 || n < (size_t)nt * 1024) {
+    add_comb(Y, m, D, k, C, ldc, n);
+    return;
+  }
+  const size_t chunk = (n + nt - 1) / nt / 1024 * 1024 + 1024;
+  std::vector<std::thread> th;
+  for (size_t c0 = 0; c0 < n; c0 += chunk) {
+    const size_t len = std::min(chunk, n - c0);
+    th.emplace_back([=]() {
+      std::vector<double*> Yc(m);
+      std::vector<const double*> Dc(k);
+      for (int i = 0; i < m; ++i) Yc[i] = Y[i] + c0;
+      for (int j = 0; j < k; ++j) Dc[j] = D[j] + c0;
+      add_comb(Yc.data(), m, Dc.data(), k, C, ldc, len);
+    });
+  }
+  for (auto& x : th) x.join();
+}
+
+}  // namespace la
+}  // namespace fdtd

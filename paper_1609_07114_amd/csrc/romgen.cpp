@@ -314,9 +314,9 @@ bool krylov_dirs(Solver& sol, const FineModel& fm, int ncols, Cols& dirs, std::s
       C.resize((size_t)kd * m);
       for (int pass = 0; pass < 2; ++pass) {
         weigh();
-        fdtd::la::gram(Dp.data(), kd, MXp.data(), m, n, C.data(), m);
+        fdtd::la::gram_mt(Dp.data(), kd, MXp.data(), m, n, C.data(), m);
         for (double& c : C) c = -c;
-        fdtd::la::add_comb(Xp.data(), m, Dp.data(), kd, C.data(), m, n);
+        fdtd::la::add_comb_mt(Xp.data(), m, Dp.data(), kd, C.data(), m, n);
       }
     }
     std::vector<double> G((size_t)m * m), Q((size_t)m * m), w(m);
@@ -344,7 +344,7 @@ bool krylov_dirs(Solver& sol, const FineModel& fm, int ncols, Cols& dirs, std::s
       std::vector<double> Z((size_t)m * nw);
       for (int j = 0; j < m; ++j)
         for (int o = 0; o < nw; ++o) Z[(size_t)j * nw + o] = Q[(size_t)j * m + order[o]] / std::sqrt(w[order[o]]);
-      fdtd::la::add_comb(Wp.data(), nw, Xc.data(), m, Z.data(), nw, n);
+      fdtd::la::add_comb_mt(Wp.data(), nw, Xc.data(), m, Z.data(), nw, n);
     }
     if (W.empty()) break;
     if (dirs.size() + W.size() >= (size_t)ncols) {
@@ -389,9 +389,9 @@ Cols gs_part(const Cols& dirs, int r0, int len, int q) {
       C.resize((size_t)k * b);
       std::vector<const double*> Bc(Bp.begin(), Bp.end());
       for (int pass = 0; pass < 2; ++pass) {
-        fdtd::la::gram(U.data(), k, Bc.data(), b, len, C.data(), b);
+        fdtd::la::gram_mt(U.data(), k, Bc.data(), b, len, C.data(), b);
         for (double& c : C) c = -c;
-        fdtd::la::add_comb(Bp.data(), b, U.data(), k, C.data(), b, len);
+        fdtd::la::add_comb_mt(Bp.data(), b, U.data(), k, C.data(), b, len);
       }
     }
     const size_t first = out.size();
@@ -489,8 +489,8 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
           VSp[a] = VS[a].data();
         }
         std::vector<double> GR((size_t)q1 * q1), GF((size_t)q1 * q1);
-        fdtd::la::gram(VDp.data(), q1, V1p.data(), q1, fm.nE, GR.data(), q1, false, true);
-        fdtd::la::gram(VSp.data(), q1, V1p.data(), q1, fm.nE, GF.data(), q1, false, true);
+        fdtd::la::gram_mt(VDp.data(), q1, V1p.data(), q1, fm.nE, GR.data(), q1, true);
+        fdtd::la::gram_mt(VSp.data(), q1, V1p.data(), q1, fm.nE, GF.data(), q1, true);
         for (int a = 0; a < q1; ++a)
           for (int b2 = 0; b2 <= a; ++b2) {
             R[(size_t)a * q + b2] = R[(size_t)b2 * q + a] = GR[(size_t)a * q1 + b2] / P.dt;
@@ -506,9 +506,9 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
           V2p[c] = V2[c].data();
         }
         for (int a = 0; a < q1; ++a) V1p[a] = V1[a].data();
-        fdtd::la::gram(V1p.data(), q1, KVp.data(), q2, fm.nE, Kt.data(), q2);
+        fdtd::la::gram_mt(V1p.data(), q1, KVp.data(), q2, fm.nE, Kt.data(), q2);
         std::vector<double> GH((size_t)q2 * q2);
-        fdtd::la::gram(V2p.data(), q2, V2p.data(), q2, fm.nH, GH.data(), q2, false, true);
+        fdtd::la::gram_mt(V2p.data(), q2, V2p.data(), q2, fm.nH, GH.data(), q2, true);
         for (int a = 0; a < q2; ++a)
           for (int b2 = 0; b2 <= a; ++b2)
             R[(size_t)(q1 + a) * q + q1 + b2] = R[(size_t)(q1 + b2) * q + q1 + a] = fm.Dm / P.dt * GH[(size_t)a * q2 + b2];
@@ -599,7 +599,7 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
         Wp[i] = Wc[i].data();
       }
       std::vector<double> Pm((size_t)q2 * q2);
-      fdtd::la::gram(Wp.data(), q2, Wp.data(), q2, nc, Pm.data(), q2);
+      fdtd::la::gram_mt(Wp.data(), q2, Wp.data(), q2, nc, Pm.data(), q2);
       for (size_t k = 0; k < Pm.size(); ++k) Pm[k] = -Pm[k];
       for (int i = 0; i < q2; ++i) Pm[(size_t)i * q2 + i] += 1.0;
       // M' = M P row by row over each row's nonzeros; then K~ = L1 M' L2^T
