@@ -442,7 +442,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=2048, help="grid size (default: the 2048^2 workload)")
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--cpu-steps", type=int, default=400,
+                    help="oracle steps timed for cpu_baseline (about 20 s of one host core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched, many-copies and adjoint forms")
     ap.add_argument("--only", choices=["batched", "many_copies", "adjoint", "hbm_resident", "waveguides",
