@@ -20,8 +20,21 @@ Ca = (a-b)/(a+b) and Cb/d = 1/((a+b) d):
 Cells inside reduced regions and their one-cell rings (whose half cells
 enter C+- of eq. (13)) get zero gradient: the models are held fixed.
 
+With absorbing layers (oracle.cpml) the state also holds the auxiliary
+fields psi, and steps 1-2 become (per cell / active edge, b, a, 1/kappa the
+layer profiles):
+  psi_hy' = b psi_hy + a dEx,  psi_hx' = b psi_hx + a dEy,
+  Hz' = Hz + M (chdy (dEx/kappa + psi_hy') - chdx (dEy/kappa + psi_hx')),
+  psi_ex' = b psi_ex + a dHz,  Ex' = Ca Ex + Cb (dHz/kappa + psi_ex')  (Ey: - Cb),
+so in reverse each psi' collects its own adjoint plus the +-chdy mu /
++-Cb lambda_E term, hands b times that to the old psi and a times it to the
+difference it filters; dJ/dCb then weighs the stretched difference
+dHz/kappa + psi'.  Outside the layers (a = 0, b = 1/kappa = 1) this is the
+plain transpose above.
+
 Parity: pinned by central finite differences of the oracle's own forward
-run and by the transpose identity <lambda, delta s> of one step.
+run and by the transpose identity <lambda, delta s> of one step (with and
+without layers).
 """
 from __future__ import annotations
 
@@ -57,12 +70,18 @@ def forward_states(prob, roms, nsteps=None, probe=0, fp32=False):
     as an FP32 run holds them (arithmetic stays FP64)."""
     run = osim.CoupledRun(prob, roms, mode="closed", fp32=fp32)
     nsteps = prob.nsteps if nsteps is None else nsteps
-    states = [(run.f.ex.copy(), run.f.ey.copy(), run.f.hz.copy())]
+
+    def snap():
+        s = (run.f.ex.copy(), run.f.ey.copy(), run.f.hz.copy())
+        if run.pml is not None:
+            s += (run.pml.psi_ex.copy(), run.pml.psi_ey.copy())
+        return s
+    states = [snap()]
     J = 0.0
     pr = prob.probes[probe]
     for n in range(nsteps):
         run.step()
-        states.append((run.f.ex.copy(), run.f.ey.copy(), run.f.hz.copy()))
+        states.append(snap())
         J += prob.dt * run.f.hz[pr.j, pr.i] ** 2
     return run, states, J
 
@@ -71,10 +90,13 @@ def transpose_step(run, Gs, lam):
     """lambda^n = M^T lambda^{n+1} for one forward step M of ``run``
     (steps 3, 2, 1 of the module docstring transposed, in that order).
     lam = (lam_ex, lam_ey, lam_hz, lam_x) is the adjoint of the state after
-    the step (any objective term already added to lam_hz).  Returns the
-    adjoint of the state before the step and (lex, ley), the adjoint of the
-    new E on the edges eq. (3) updates (the coefficient gradients' weights)."""
-    lam_ex, lam_ey, lam_hz, lam_x = lam
+    the step (any objective term already added to lam_hz), followed with
+    absorbing layers by (lam_psi_hx, lam_psi_hy, lam_psi_ex, lam_psi_ey).
+    Returns the adjoint of the state before the step (same layout) and
+    (lex, ley), the adjoint of the new E on the edges eq. (3) updates (the
+    coefficient gradients' weights)."""
+    pml = run.pml
+    lam_ex, lam_ey, lam_hz, lam_x = lam[:4]
     cell, exm, eym = run.cell, run.exm, run.eym
     ca_x, cb_x, ca_y, cb_y, chdy, chdx = run.ca_x, run.cb_x, run.ca_y, run.cb_y, run.chdy, run.chdx
     ny, nx = cell.shape
@@ -90,37 +112,58 @@ def transpose_step(run, Gs, lam):
         for k, (_, _, _, oi, oj, _, _) in enumerate(c.ports):
             lam_h[oj, oi] += back[c.q + k]
         c.scatter(lam_ex_in, lam_ey_in, np.zeros(c.np_))   # consumed
-    # 2. E' = Ca E + Cb curlH(Hz') on active edges
+    # 2. E' = Ca E + Cb curlH(Hz') on active edges; vx, vy: the adjoints of
+    # the Hz differences dHz = Hz(j)-Hz(j-1) (Ex), Hz(i)-Hz(i-1) (Ey)
     lex = np.where(exm, lam_ex_in, 0.0)
     ley = np.where(eym, lam_ey_in, 0.0)
-    # d/dHz' of sum lex*cb_x*(Hz(j)-Hz(j-1)) + ley*cb_y*(-(Hz(i)-Hz(i-1)))
-    wx = lex * cb_x
-    wy = ley * cb_y
-    lam_h += wx[:-1, :] - wx[1:, :]       # edge (i,j) above cell (i,j-1): +, edge (i,j+1): -
-    lam_h += -wy[:, :-1] + wy[:, 1:]
-    # 1. Hz' = M (Hz + chdy (Ex(j+1)-Ex(j)) - chdx (Ey(i+1)-Ey(i)))
+    if pml is None:
+        vx = lex * cb_x
+        vy = -ley * cb_y
+    else:
+        l_phx, l_phy, l_pex, l_pey = lam[4:]
+        tx = l_pex + cb_x * lex            # adjoint of psi_ex' (its own + through Ex')
+        ty = l_pey - cb_y * ley
+        vx = np.where(exm, cb_x * pml.iky_e[:, None] * lex + pml.ay_e[:, None] * tx, 0.0)
+        vy = np.where(eym, -cb_y * pml.ikx_e[None, :] * ley + pml.ax_e[None, :] * ty, 0.0)
+        new_pex = np.where(exm, pml.by_e[:, None] * tx, l_pex)
+        new_pey = np.where(eym, pml.bx_e[None, :] * ty, l_pey)
+    lam_h += vx[:-1, :] - vx[1:, :]       # edge (i,j) above cell (i,j-1): +, edge (i,j+1): -
+    lam_h += vy[:, :-1] - vy[:, 1:]
+    # 1. Hz' = M (Hz + chdy dEx - chdx dEy), dEx = Ex(j+1)-Ex(j), dEy = Ey(i+1)-Ey(i)
     mu = lam_h * cell
+    if pml is None:
+        ldex = chdy * mu
+        ldey = -chdx * mu
+    else:
+        thy = l_phy + chdy * mu            # adjoint of psi_hy' (its own + through Hz')
+        thx = l_phx - chdx * mu
+        ldex = chdy * pml.iky_h[:, None] * mu + pml.ay_h[:, None] * thy
+        ldey = -chdx * pml.ikx_h[None, :] * mu + pml.ax_h[None, :] * thx
+        new_phy = pml.by_h[:, None] * thy
+        new_phx = pml.bx_h[None, :] * thx
     new_ex = lex * ca_x
     new_ey = ley * ca_y
-    new_ex[1:, :] += chdy * mu
-    new_ex[:-1, :] -= chdy * mu
-    new_ey[:, 1:] -= chdx * mu
-    new_ey[:, :-1] += chdx * mu
+    new_ex[1:, :] += ldex
+    new_ex[:-1, :] -= ldex
+    new_ey[:, 1:] += ldey
+    new_ey[:, :-1] -= ldey
     # walls carry no adjoint (E fixed at zero there)
     new_ex[0, :] = 0.0
     new_ex[ny, :] = 0.0
     new_ey[:, 0] = 0.0
     new_ey[:, nx] = 0.0
-    return (new_ex, new_ey, mu, new_lam_x), (lex, ley)
+    out = (new_ex, new_ey, mu, new_lam_x)
+    if pml is not None:
+        out += (new_phx, new_phy, new_pex, new_pey)
+    return out, (lex, ley)
 
 
 def adjoint_gradient(prob, roms, nsteps=None, probe=0, fp32=False):
     """Return (J, dJ/deps_r [ny,nx], dJ/dsigma [ny,nx]).  fp32: transpose of
     the forward with FP32-rounded coefficients (see forward_states)."""
     nsteps = prob.nsteps if nsteps is None else nsteps
-    if getattr(prob, "pml", None) is not None and prob.pml.any:
-        raise ValueError("the adjoint covers PEC-walled grids only (no absorbing layers)")
     run, states, J = forward_states(prob, roms, nsteps, probe, fp32)
+    pml = run.pml
     nx, ny = prob.nx, prob.ny
     cell = run.cell
     pr = prob.probes[probe]
@@ -129,26 +172,31 @@ def adjoint_gradient(prob, roms, nsteps=None, probe=0, fp32=False):
     Gs = [c.G32 if fp32 else c.update_matrix() for c in run.cpl]
     lam = (np.zeros((ny + 1, nx)), np.zeros((ny, nx + 1)), np.zeros((ny, nx)),
            [np.zeros(c.q) for c in run.cpl])
+    if pml is not None:
+        lam += (np.zeros((ny, nx)), np.zeros((ny, nx)), np.zeros((ny + 1, nx)), np.zeros((ny, nx + 1)))
     g_cax = np.zeros((ny + 1, nx))
     g_cbx = np.zeros((ny + 1, nx))
     g_cay = np.zeros((ny, nx + 1))
     g_cby = np.zeros((ny, nx + 1))
     for n in range(nsteps - 1, -1, -1):
-        ex0, ey0, _ = states[n]          # E^n
-        _, _, hz1 = states[n + 1]        # Hz^{n+1/2}
+        ex0, ey0 = states[n][:2]         # E^n
+        hz1 = states[n + 1][2]           # Hz^{n+1/2}
         hz1 = hz1 * cell
         # objective: J += dt (Hz'_p)^2
         lam_hz = lam[2].copy()
         lam_hz[pr.j, pr.i] += 2.0 * prob.dt * hz1[pr.j, pr.i]
-        lam, (lex, ley) = transpose_step(run, Gs, (lam[0], lam[1], lam_hz, lam[3]))
+        lam, (lex, ley) = transpose_step(run, Gs, (lam[0], lam[1], lam_hz) + tuple(lam[3:]))
         dhx = np.zeros((ny + 1, nx))
         dhx[1:ny, :] = hz1[1:, :] - hz1[:-1, :]
         dhy = np.zeros((ny, nx + 1))
-        dhy[:, 1:nx] = -(hz1[:, 1:] - hz1[:, :-1])
+        dhy[:, 1:nx] = hz1[:, 1:] - hz1[:, :-1]
+        if pml is not None:              # the stretched differences dHz/kappa + psi'
+            dhx = pml.iky_e[:, None] * dhx + states[n + 1][3]
+            dhy = pml.ikx_e[None, :] * dhy + states[n + 1][4]
         g_cax += lex * ex0
         g_cbx += lex * dhx
         g_cay += ley * ey0
-        g_cby += ley * dhy
+        g_cby -= ley * dhy
     # chain rule to cell materials
     ax, bx, ay, by = _edge_ab(prob)
     d = {}

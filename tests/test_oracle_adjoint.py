@@ -109,3 +109,75 @@ def test_transpose_step_dot_product_identity():
     MTlam, _ = oadj.transpose_step(run, Gs, lam)
     lhs, rhs = dot(Mds, lam), dot(ds, MTlam)
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0), (lhs, rhs)
+
+
+def _layered(seed, nsteps=250, pml=None):
+    p = W.random_problem(seed, 34, 30, nsteps, nroms=1, block=(4, 4), r=2, q=10,
+                         dt_frac_coarse=0.9, f_bw=3e9)
+    s = p.roms[0]
+    p.pml = pml or W.Pml(n_xlo=min(5, s.i0 - 1), n_xhi=min(5, p.nx - s.i0 - s.ni - 1),
+                         n_ylo=min(4, s.j0 - 1), n_yhi=min(4, p.ny - s.j0 - s.nj - 1),
+                         kappa_max=3.0, alpha_max=0.03)
+    assert p.pml.any
+    return p
+
+
+def test_transpose_step_with_layers():
+    """The dot-product identity of one step with absorbing layers: the
+    state now also holds the four auxiliary fields (random in the test)."""
+    p = _layered(35, nsteps=10)
+    for s in p.sources:
+        s.incr[:] = 0.0
+    roms = osim.build_roms(p)
+    run = osim.CoupledRun(p, roms, mode="closed")
+    rng = np.random.default_rng(8)
+    mx = run.exm.astype(float)
+    my = run.eym.astype(float)
+    for c in run.cpl:
+        for (comp, ei, ej, _, _, _, _) in c.ports:
+            (mx if comp == 1 else my)[ej, ei] = 1.0
+    shapes = [run.pml.psi_hx.shape, run.pml.psi_hy.shape, run.pml.psi_ex.shape, run.pml.psi_ey.shape]
+
+    def draw():
+        return ((rng.standard_normal(mx.shape) * mx, rng.standard_normal(my.shape) * my,
+                 rng.standard_normal(run.cell.shape) * run.cell, [rng.standard_normal(c.q) for c in run.cpl])
+                + tuple(rng.standard_normal(sh) for sh in shapes))
+    ds, lam = draw(), draw()
+    run.f.ex[...] = ds[0]
+    run.f.ey[...] = ds[1]
+    run.f.hz[...] = ds[2]
+    run.x = [x.copy() for x in ds[3]]
+    run.pml.psi_hx, run.pml.psi_hy, run.pml.psi_ex, run.pml.psi_ey = (a.copy() for a in ds[4:])
+    run.step()
+    Mds = (run.f.ex, run.f.ey, run.f.hz * run.cell, run.x,
+           run.pml.psi_hx, run.pml.psi_hy, run.pml.psi_ex, run.pml.psi_ey)
+
+    def dot(a, b):
+        return (sum(np.sum(u * v) for k, (u, v) in enumerate(zip(a, b)) if k != 3) +
+                sum(float(u @ v) for u, v in zip(a[3], b[3])))
+    Gs = [c.update_matrix() for c in run.cpl]
+    MTlam, _ = oadj.transpose_step(run, Gs, lam)
+    lhs, rhs = dot(Mds, lam), dot(ds, MTlam)
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0), (lhs, rhs)
+
+
+def test_adjoint_with_layers_matches_central_differences():
+    """Gradients through absorbing layers (kappa and alpha active) against
+    central differences, at cells inside a layer and in the interior."""
+    p = _layered(36)
+    roms = osim.build_roms(p)
+    J, ge, gs = oadj.adjoint_gradient(p, roms)
+    m = oadj.gradient_mask(p)
+    L = p.pml
+    in_layer = [(i, j) for j in range(1, p.ny - 1) for i in range(1, p.nx - 1)
+                if m[j, i] and (i < L.n_xlo or i >= p.nx - L.n_xhi or j < L.n_ylo or j >= p.ny - L.n_yhi)]
+    interior = [(i, j) for j in range(1, p.ny - 1) for i in range(1, p.nx - 1)
+                if m[j, i] and (i, j) not in in_layer]
+    rng = np.random.default_rng(2)
+    picks = [in_layer[k] for k in rng.choice(len(in_layer), 3, replace=False)] + \
+            [interior[k] for k in rng.choice(len(interior), 2, replace=False)]
+    for (i, j) in picks:
+        fd_e = _fd(p, roms, "eps_r", i, j, 1e-4)
+        fd_s = _fd(p, roms, "sigma", i, j, 1e-5)
+        assert ge[j, i] == pytest.approx(fd_e, rel=2e-6, abs=1e-6 * np.abs(ge).max()), (i, j)
+        assert gs[j, i] == pytest.approx(fd_s, rel=2e-6, abs=1e-6 * np.abs(gs).max()), (i, j)
