@@ -327,12 +327,17 @@ int fdtd_rom_set_graph(fdtd_rom_sim* sim, int32_t batch);
  * ceil(nsteps/ckpt_every) checkpoints of the fields and reduced states,
  * ckpt_every recomputed field sets, two adjoint field sets, the adjoint
  * reduced states, two FP64 per-cell accumulators and G^T of every model.
+ * With absorbing layers a checkpoint also holds the four auxiliary fields,
+ * a recomputed set the two at Ex and Ey, an adjoint set the adjoints of
+ * all four (plus one private pair of the two at Hz).
  *
  * fdtd_rom_adjoint: runs the forward from the handle's initial state (the
- * handle must have taken no step; FDTD_ESTATE otherwise; grids with
- * absorbing layers are not supported, FDTD_EINVAL), keeping
+ * handle must have taken no step; FDTD_ESTATE otherwise), keeping
  * checkpoints, then sweeps back one segment at a time, recomputing each
- * segment's forward states from its checkpoint.  Afterwards the handle
+ * segment's forward states from its checkpoint.  Inside absorbing layers
+ * the sweep transposes the auxiliary-field recursions as well, so the
+ * gradient is that of the layered run (no material gradient of the layer
+ * profiles themselves, which are fixed by fdtd_pml).  Afterwards the handle
  * stands at step nsteps with its probe record filled, as after
  * fdtd_rom_run(sim, nsteps).
  *   probe: index of an Hz probe of the problem (FDTD_EINVAL otherwise).

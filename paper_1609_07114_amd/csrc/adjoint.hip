@@ -10,6 +10,8 @@
 //                  accumulation, streamed up the rows (one launch).
 // The forward coefficients are rebuilt exactly as the step kernel builds
 // them.
+#include <type_traits>
+
 #include "adjoint.hpp"
 #include "device.hpp"
 
@@ -84,21 +86,26 @@ __device__ __forceinline__ void edge_grad(T lam, T e_old, T dh, T s, T t, T rcp,
   gb += r2 * (-dca * s - u);
 }
 
-// One lane's column of row j for the reverse sweep.
+// One lane's column of row j for the reverse sweep.  With absorbing layers
+// also the adjoints of the four auxiliary fields the column owns and the
+// forward auxiliary fields at its Ex and Ey after the step.
 template <typename T>
 struct AdjRow {
   T a, b, h;      // material (a < 0 inside regions, 0 in padding), forward Hz^{n+1/2}
   T lx, e;        // adjoint and forward value of the row's south Ex
   T lh, ly, ey;   // adjoint Hz, adjoint and forward value of the west Ey
+  T lpx, lpy;     // adjoints of the cell's psi (d/dx of Ey, d/dy of Ex)
+  T lpe, lpw;     // adjoints of psi at the south Ex and at the west Ey
+  T pe, pw;       // forward psi at the south Ex and the west Ey, after the step
 };
 
 // Loads are unconditional from a valid offset (`ob` when `ok`, else cell
 // (0,0)) and the values of lanes without data are selected to zero: no
 // lane-divergent branches.
-template <typename T>
+template <typename T, bool PML>
 __device__ __forceinline__ AdjRow<T> adj_load(const AdjParams<T>& p, uint32_t ob, bool ok) {
   const uint32_t o = ok ? ob : 0u;
-  AdjRow<T> r;
+  AdjRow<T> r{};
   r.a = ld(p.al, o);
   r.b = ld(p.be, o);
   r.h = ld(p.hz1, o);
@@ -107,8 +114,29 @@ __device__ __forceinline__ AdjRow<T> adj_load(const AdjParams<T>& p, uint32_t ob
   r.lh = ld(p.lhz_in, o);
   r.ly = ld(p.ley_in, o);
   r.ey = ld(p.ey0, o);
-  if (!ok) r = AdjRow<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+  if constexpr (PML) {
+    r.lpx = ld(p.lps_in[0], o);
+    r.lpy = ld(p.lps_in[1], o);
+    r.lpe = ld(p.lps_in[2], o);
+    r.lpw = ld(p.lps_in[3], o);
+    r.pe = ld(p.pex1, o);
+    r.pw = ld(p.pey1, o);
+  }
+  if (!ok) r = AdjRow<T>{};
   return r;
+}
+
+// Stretched-derivative profiles at one column (x) or row (y): 1/kappa, b, a
+// at the E sample and at the Hz sample; the identity (1, 1, 0) outside the
+// layers.
+template <typename T>
+struct Prof {
+  T ik_e, b_e, a_e, ik_h, b_h, a_h;
+};
+
+template <typename T>
+__device__ __forceinline__ Prof<T> prof_at(const T* pr, int S, int k) {
+  return Prof<T>{pr[k], pr[S + k], pr[2 * S + k], pr[3 * S + k], pr[4 * S + k], pr[5 * S + k]};
 }
 
 constexpr int kAdjOwned = kWave - 3;  // columns a reverse-sweep wave owns
@@ -129,14 +157,23 @@ constexpr int kAdjOwned = kWave - 3;  // columns a reverse-sweep wave owns
 //   edge is formed once and credited to both of its cells (a cell's total is
 //   stored after its north edge, the next row's south edge, is known).
 // Horizontal neighbours move between lanes with DPP whole-wave shifts.
-template <typename T, int SEG>
-__global__ void __launch_bounds__(kBlock) adj_stream(const AdjParams<T> p) {
+//
+// PML: the absorbing-layer form.  An E update E' = Ca E + Cb (dH/kappa +
+// psi'), psi' = b psi + a dH hands its Hz difference the adjoint
+//   v = Cb lam_E / kappa + a t,  t = lam_psi + Cb lam_E  (Ey: Cb -> -Cb),
+// which replaces Cb lam_E in mu, and leaves b t to psi (edges the step
+// updates; others keep their adjoint).  The Hz update hands
+//   ldE = chdy mu / kappa_y + a_y (lam_psiy + chdy mu)  (x: chdx -> -chdx)
+// to its E difference and b (lam_psi +- chd mu) to its own psi; the E
+// adjoints become ldE(below) - ldE(own), and the Cb weights take the
+// stretched difference dH/kappa + psi'.
+template <typename T, int SEG, bool PML>
+__device__ __forceinline__ void adj_rows(const AdjParams<T>& p) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int iw = blockIdx.x * kAdjOwned;
   const int ic = iw - 2 + lane;
   const int j0 = (blockIdx.y * (kBlock / kWave) + wv) * SEG;
-  if (j0 >= p.ny) return;
   const int j1 = min(j0 + SEG, p.ny);
   const int js = j0 > 0 ? j0 - 1 : 0;
   const int nx = p.nx, ny = p.ny;
@@ -152,11 +189,19 @@ __global__ void __launch_bounds__(kBlock) adj_stream(const AdjParams<T> p) {
   const uint32_t obj_b = (uint32_t)(p.obj_off * ts);
   // byte offset of the same cell in the FP64 accumulators
   auto o8 = [](uint32_t obt) -> uint32_t { return obt / ts * 8u; };
+  // x profiles of this column and the east edge's (column ic+1)
+  Prof<T> px{T(1), T(1), T(0), T(1), T(1), T(0)};
+  T ikxE = T(1), axE = T(0);
+  if constexpr (PML) {
+    px = prof_at(p.px, p.px_stride, in ? ic : 0);
+    ikxE = lane_next(px.ik_e);
+    axE = lane_next(px.a_e);
+  }
 
-  AdjRow<T> prv = adj_load(p, ob - row_b, in && js >= 1);
-  AdjRow<T> cur = adj_load(p, ob, in);
-  AdjRow<T> nxt = adj_load(p, ob + row_b, in && js + 1 < ny);
-  T mu_p = T(0);
+  AdjRow<T> prv = adj_load<T, PML>(p, ob - row_b, in && js >= 1);
+  AdjRow<T> cur = adj_load<T, PML>(p, ob, in);
+  AdjRow<T> nxt = adj_load<T, PML>(p, ob + row_b, in && js + 1 < ny);
+  T mu_p = T(0), ld_p = T(0);
   T gpa = T(0), gpb = T(0);             // previous row's cell: dJ/da, dJ/db of all edges but its north
   double acc_e = 0.0, acc_s = 0.0;      // its accumulators, read one row ahead
   T cas = T(0), cbs = T(0), rs = T(0);  // current row's south edge
@@ -168,7 +213,7 @@ __global__ void __launch_bounds__(kBlock) adj_stream(const AdjParams<T> p) {
     const bool up = j + 1 < ny;
     // row j+2 in flight (needed as the north row of the next iteration)
     const bool up2 = j + 2 < ny && j + 1 < j1;
-    const AdjRow<T> nn = adj_load(p, ob + 2 * row_b, in && up2);
+    const AdjRow<T> nn = adj_load<T, PML>(p, ob + 2 * row_b, in && up2);
     // this row's accumulators (this wave is their only writer), stored next row
     const bool acc_row = j >= j0 && own;
     double nacc_e = ld(p.geps, acc_row ? o8(ob) : 0u);
@@ -188,17 +233,57 @@ __global__ void __launch_bounds__(kBlock) adj_stream(const AdjParams<T> p) {
     const bool actE = ic + 1 < nx && act && ae > T(0);
     T mu = cur.lh;
     mu += (in && ob == obj_b) ? p.obj_coef * cur.h : T(0);
-    mu += actS ? cbs * cur.lx : T(0);
-    mu -= actN ? cbn * nxt.lx : T(0);
-    mu -= actW ? cbw * cur.ly : T(0);
-    mu += actE ? cbe * lye : T(0);
+    // y profiles of this row and of its north edge (wave-uniform)
+    Prof<T> py{T(1), T(1), T(0), T(1), T(1), T(0)};
+    T ikyN = T(1), ayN = T(0);
+    T tS = T(0), tW = T(0), pwE = T(0);
+    if constexpr (PML) {
+      py = prof_at(p.py, p.py_stride, j);
+      ikyN = p.py[j + 1];
+      ayN = p.py[2 * p.py_stride + j + 1];
+      const T lpwE = lane_next(cur.lpw);
+      pwE = lane_next(cur.pw);
+      tS = cur.lpe + cbs * cur.lx;
+      tW = cur.lpw - cbw * cur.ly;
+      const T tN = nxt.lpe + cbn * nxt.lx;
+      const T tE = lpwE - cbe * lye;
+      mu += actS ? cbs * py.ik_e * cur.lx + py.a_e * tS : T(0);
+      mu -= actN ? cbn * ikyN * nxt.lx + ayN * tN : T(0);
+      mu += actW ? -cbw * px.ik_e * cur.ly + px.a_e * tW : T(0);
+      mu -= actE ? -cbe * ikxE * lye + axE * tE : T(0);
+    } else {
+      mu += actS ? cbs * cur.lx : T(0);
+      mu -= actN ? cbn * nxt.lx : T(0);
+      mu -= actW ? cbw * cur.ly : T(0);
+      mu += actE ? cbe * lye : T(0);
+    }
     mu = act ? mu : T(0);
-    const T mu_w = lane_prev(mu);
-    // gradient shares of the south, west and east edges
+    // adjoints handed to the E differences of the Hz update (layers)
+    T ldx = T(0), ldy = T(0), thx = T(0), thy = T(0);
+    if constexpr (PML) {
+      thy = cur.lpy + chdy * mu;
+      thx = cur.lpx - chdx * mu;
+      ldx = chdy * py.ik_h * mu + py.a_h * thy;
+      ldy = -chdx * px.ik_h * mu + px.a_h * thx;
+    }
+    // west neighbour's value (all lanes take part in the shift)
+    T mu_w = T(0), ldy_w = T(0);
+    if constexpr (PML)
+      ldy_w = lane_prev(ldy);
+    else
+      mu_w = lane_prev(mu);
+    // gradient shares of the south, west and east edges; Cb weights the
+    // (stretched) Hz difference
+    T dhs = cur.h - prv.h, dhw = -(cur.h - hw), dhe = -(he - cur.h);
+    if constexpr (PML) {
+      dhs = py.ik_e * (cur.h - prv.h) + cur.pe;
+      dhw = -(px.ik_e * (cur.h - hw) + cur.pw);
+      dhe = -(ikxE * (he - cur.h) + pwE);
+    }
     T gas = T(0), gbs = T(0), gaw = T(0), gbw = T(0), gae = T(0), gbe = T(0);
-    edge_grad(cur.lx, cur.e, cur.h - prv.h, cur.a + prv.a, cur.b + prv.b, rs, idy, gas, gbs);
-    edge_grad(cur.ly, cur.ey, -(cur.h - hw), cur.a + aw, cur.b + bw, rw, idx, gaw, gbw);
-    edge_grad(lye, eye, -(he - cur.h), ae + cur.a, be_ + cur.b, re, idx, gae, gbe);
+    edge_grad(cur.lx, cur.e, dhs, cur.a + prv.a, cur.b + prv.b, rs, idy, gas, gbs);
+    edge_grad(cur.ly, cur.ey, dhw, cur.a + aw, cur.b + bw, rw, idx, gaw, gbw);
+    edge_grad(lye, eye, dhe, ae + cur.a, be_ + cur.b, re, idx, gae, gbe);
     gas = actS ? gas : T(0);
     gbs = actS ? gbs : T(0);
     gaw = actW ? gaw : T(0);
@@ -206,8 +291,18 @@ __global__ void __launch_bounds__(kBlock) adj_stream(const AdjParams<T> p) {
     gae = actE ? gae : T(0);
     gbe = actE ? gbe : T(0);
     if (acc_row) {
-      const T lxo = chdy * (mu_p - mu) + (actS ? cas * cur.lx : T(0));
-      const T lyo = chdx * (mu - mu_w) + (actW ? caw * cur.ly : T(0));
+      T lxo, lyo;
+      if constexpr (PML) {
+        lxo = (ld_p - ldx) + (actS ? cas * cur.lx : T(0));
+        lyo = (ldy_w - ldy) + (actW ? caw * cur.ly : T(0));
+        st(p.lps_out[0], ob, px.b_h * thx);
+        st(p.lps_out[1], ob, py.b_h * thy);
+        st(p.lps_out[2], ob, actS ? py.b_e * tS : cur.lpe);
+        st(p.lps_out[3], ob, actW ? px.b_e * tW : cur.lpw);
+      } else {
+        lxo = chdy * (mu_p - mu) + (actS ? cas * cur.lx : T(0));
+        lyo = chdx * (mu - mu_w) + (actW ? caw * cur.ly : T(0));
+      }
       st(p.lhz_out, ob, mu);
       st(p.lex_out, ob, j >= 1 ? lxo : T(0));
       st(p.ley_out, ob, ic >= 1 ? lyo : T(0));
@@ -222,6 +317,7 @@ __global__ void __launch_bounds__(kBlock) adj_stream(const AdjParams<T> p) {
     acc_e = nacc_e;
     acc_s = nacc_s;
     mu_p = mu;
+    ld_p = ldx;
     prv = cur;
     cur = nxt;
     nxt = nn;
@@ -234,10 +330,40 @@ __global__ void __launch_bounds__(kBlock) adj_stream(const AdjParams<T> p) {
   if (own && j1 - 1 >= j0) {
     const uint32_t oc = o8(ob - row_b);
     T gna = T(0), gnb = T(0);
-    if (j1 < ny && prv.a > T(0) && cur.a > T(0))
-      edge_grad(cur.lx, cur.e, cur.h - prv.h, cur.a + prv.a, cur.b + prv.b, rs, idy, gna, gnb);
+    if (j1 < ny && prv.a > T(0) && cur.a > T(0)) {
+      T dhn = cur.h - prv.h;
+      if constexpr (PML) dhn = p.py[j1] * (cur.h - prv.h) + cur.pe;
+      edge_grad(cur.lx, cur.e, dhn, cur.a + prv.a, cur.b + prv.b, rs, idy, gna, gnb);
+    }
     st(p.geps, oc, acc_e + fa * (double)(gpa + gna));
     st(p.gsig, oc, acc_s + 0.25 * (double)(gpb + gnb));
+  }
+}
+
+// A wave takes the absorbing-layer form only when the profiles it reads
+// (columns iw-2 .. iw+61, rows js .. j1) reach into a layer; kernels built
+// for problems without layers contain the plain form only.  The adjoints
+// of the auxiliary fields are written by layer waves alone: outside the
+// layers every a is zero, so the entries other waves own stay zero and
+// are never weighted.
+template <typename T, int SEG, bool Layers>
+__global__ void __launch_bounds__(kBlock) adj_stream(const AdjParams<T> p) {
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int j0 = (blockIdx.y * (kBlock / kWave) + wv) * SEG;
+  if (j0 >= p.ny) return;
+  if constexpr (!Layers) {
+    adj_rows<T, SEG, false>(p);
+  } else {
+    const int iw = blockIdx.x * kAdjOwned;
+    const int js = j0 > 0 ? j0 - 1 : 0;
+    const int j1 = min(j0 + SEG, p.ny);
+    const bool layer = (p.pml_xlo > 0 && iw - 2 < p.pml_xlo) ||
+                       (p.pml_xhi > 0 && iw + kWave - 3 >= p.nx - p.pml_xhi) ||
+                       (p.pml_ylo > 0 && js < p.pml_ylo) || (p.pml_yhi > 0 && j1 >= p.ny - p.pml_yhi);
+    if (layer)
+      adj_rows<T, SEG, true>(p);
+    else
+      adj_rows<T, SEG, false>(p);
   }
 }
 
@@ -246,13 +372,17 @@ hipError_t launch_adjoint_step(const AdjParams<T>& p, size_t smem, hipStream_t s
   if (p.nblocks > 0) hipLaunchKernelGGL((adj_coupling<T>), dim3(p.nblocks), dim3(kBlock), smem, s, p);
   const int rows = (kBlock / kWave) * p.seg;
   const dim3 g((p.nx + kAdjOwned - 1) / kAdjOwned, (p.ny + rows - 1) / rows);
-  switch (p.seg) {
-    case 4: hipLaunchKernelGGL((adj_stream<T, 4>), g, dim3(kBlock), 0, s, p); break;
-    case 8: hipLaunchKernelGGL((adj_stream<T, 8>), g, dim3(kBlock), 0, s, p); break;
-    case 16: hipLaunchKernelGGL((adj_stream<T, 16>), g, dim3(kBlock), 0, s, p); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  auto go = [&](auto layers) -> hipError_t {
+    constexpr bool Ly = decltype(layers)::value;
+    switch (p.seg) {
+      case 4: hipLaunchKernelGGL((adj_stream<T, 4, Ly>), g, dim3(kBlock), 0, s, p); break;
+      case 8: hipLaunchKernelGGL((adj_stream<T, 8, Ly>), g, dim3(kBlock), 0, s, p); break;
+      case 16: hipLaunchKernelGGL((adj_stream<T, 16, Ly>), g, dim3(kBlock), 0, s, p); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  };
+  return p.pml ? go(std::true_type{}) : go(std::false_type{});
 }
 
 template hipError_t launch_adjoint_step<float>(const AdjParams<float>&, size_t, hipStream_t);

@@ -40,6 +40,19 @@ struct AdjParams {
   int nblocks;
   const T* mats;
   const int* idx;
+  // absorbing layers (pml == 0: none): profiles and extents as in
+  // StepParams; adjoints of the four auxiliary fields [psi at Hz (d/dx of
+  // Ey, d/dy of Ex), psi at Ex, psi at Ey], in/out like the fields; the
+  // forward auxiliary fields at Ex and Ey after step n+1
+  int pml;
+  int pml_xlo, pml_xhi, pml_ylo, pml_yhi;
+  int px_stride, py_stride;
+  const T* px;
+  const T* py;
+  const T* lps_in[4];
+  T* lps_out[4];
+  const T* pex1;
+  const T* pey1;
 };
 
 template <typename T>

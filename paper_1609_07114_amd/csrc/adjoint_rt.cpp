@@ -8,6 +8,12 @@
 // probe record, a private step counter), then the adjoint steps run from the
 // segment's end back to its start, each reading E^n (slot n) and
 // Hz^{n+1/2} (slot n+1).  Peak memory: checkpoints + one segment.
+//
+// Absorbing layers add the auxiliary fields: a checkpoint also holds the
+// four of its step, a slot also the two at Ex and Ey (the reverse step
+// weighs the stretched Hz differences with them), the recompute runs the
+// two at Hz through a private ping-pong pair, and the adjoint sets carry
+// the four adjoint auxiliary fields.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,7 +34,8 @@ namespace {
 struct AdjLayout {
   int K = 0, nck = 0;
   size_t set_bytes = 0, xs_bytes = 0;
-  size_t off_ctrl = 0, off_ckpt = 0, ck_stride = 0, off_slots = 0, off_xs = 0;
+  size_t slot_bytes = 0, lam_bytes = 0, ck_psi = 0;  // per slot / adjoint set; checkpoint's psi offset
+  size_t off_ctrl = 0, off_ckpt = 0, ck_stride = 0, off_slots = 0, off_xs = 0, off_psih = 0;
   size_t off_lam = 0, off_lx = 0, off_g = 0, off_gt = 0, off_roms = 0, total = 0;
   size_t gt_elems = 0;
   std::vector<size_t> slot_gt;  // element offset of each matrix slot's G^T
@@ -43,7 +50,10 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
   A.K = ckpt_every > 0 ? ckpt_every : (int)std::ceil(std::sqrt((double)nsteps));
   A.nck = (nsteps + A.K - 1) / A.K;
   const size_t ts = L.tsize;
-  A.set_bytes = 3 * L.field_elems * ts;
+  const size_t fb = L.field_elems * ts;
+  A.set_bytes = 3 * fb;
+  A.slot_bytes = (L.pml ? 5 : 3) * fb;   // Hz, Ex, Ey (+ psi at Ex, Ey)
+  A.lam_bytes = (L.pml ? 7 : 3) * fb;    // + adjoints of the four psi
   A.xs_bytes = align_up(std::max<size_t>(L.xs_elems, 1) * ts, 256);
   A.slot_gt.clear();
   size_t ge = 0;
@@ -58,14 +68,17 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
   A.off_ctrl = o;
   o = align_up(o + kCtrlInts * sizeof(int), 256);
   A.off_ckpt = o;
-  A.ck_stride = align_up(A.set_bytes, 256) + A.xs_bytes;
+  A.ck_psi = align_up(A.set_bytes, 256) + A.xs_bytes;
+  A.ck_stride = A.ck_psi + (L.pml ? align_up(4 * fb, 256) : 0);
   o += (size_t)A.nck * A.ck_stride;
   A.off_slots = o;
-  o = align_up(o + (size_t)A.K * A.set_bytes, 256);
+  o = align_up(o + (size_t)A.K * A.slot_bytes, 256);
   A.off_xs = o;
   o += A.xs_bytes;
+  A.off_psih = o;
+  o = align_up(o + (L.pml ? 4 * fb : 0), 256);
   A.off_lam = o;
-  o = align_up(o + 2 * A.set_bytes, 256);
+  o = align_up(o + 2 * A.lam_bytes, 256);
   A.off_lx = o;
   o += 2 * A.xs_bytes;
   A.off_g = o;
@@ -136,9 +149,14 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
 
   auto ckpt = [&](int c) { return aw + A.off_ckpt + (size_t)c * A.ck_stride; };
   auto ckpt_xs = [&](int c) { return ckpt(c) + align_up(A.set_bytes, 256); };
-  auto slot = [&](int k) { return aw + A.off_slots + (size_t)k * A.set_bytes; };
+  // checkpoint's auxiliary fields: [psi at Hz (2), psi at Ex, psi at Ey]
+  auto ckpt_psi = [&](int c) { return (T*)(ckpt(c) + A.ck_psi); };
+  auto slot = [&](int k) { return aw + A.off_slots + (size_t)k * A.slot_bytes; };
   T* xs_scr = (T*)(aw + A.off_xs);
+  T* psih = (T*)(aw + A.off_psih);  // recompute's psi at Hz, [parity][2]
   const size_t xs_copy = L.xs_elems * sizeof(T);
+  const size_t fb = fe * sizeof(T);
+  const StepParams<T>& sp = step_params<T>(s);
 
   // forward with checkpoints
   for (int c = 0; c < A.nck; ++c) {
@@ -148,6 +166,12 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
     if (hipMemcpyAsync(ckpt(c), cur, A.set_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
         (xs_copy > 0 && hipMemcpyAsync(ckpt_xs(c), ws + L.off_xs, xs_copy, hipMemcpyDeviceToDevice, st) != hipSuccess))
       return dev_err("checkpoint copy");
+    if (L.pml) {
+      const T* src[4] = {sp.psi_h[m0 & 1][0], sp.psi_h[m0 & 1][1], sp.psi_ex, sp.psi_ey};
+      for (int k = 0; k < 4; ++k)
+        if (hipMemcpyAsync(ckpt_psi(c) + k * fe, src[k], fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+          return dev_err("checkpoint copy");
+    }
     const int rc = run_steps_any(s, len);
     if (rc != FDTD_OK) return rc;
   }
@@ -171,7 +195,6 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   rp.nprobes = 0;
   rp.xs = xs_scr;
   AdjParams<T> ap{};
-  const StepParams<T>& sp = step_params<T>(s);
   ap.al = sp.al;
   ap.be = sp.be;
   ap.geps = (double*)(aw + A.off_g);
@@ -194,7 +217,16 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   ap.nblocks = s->nroms > 0 ? L.nrowblocks : 0;
   ap.mats = (const T*)(aw + A.off_gt);
   ap.idx = (const int*)(ws + L.off_idx);
-  T* lam[2] = {(T*)(aw + A.off_lam), (T*)(aw + A.off_lam + A.set_bytes)};
+  ap.pml = L.pml ? 1 : 0;
+  ap.pml_xlo = sp.pml_xlo;
+  ap.pml_xhi = sp.pml_xhi;
+  ap.pml_ylo = sp.pml_ylo;
+  ap.pml_yhi = sp.pml_yhi;
+  ap.px_stride = sp.px_stride;
+  ap.py_stride = sp.py_stride;
+  ap.px = sp.px;
+  ap.py = sp.py;
+  T* lam[2] = {(T*)(aw + A.off_lam), (T*)(aw + A.off_lam + A.lam_bytes)};
   T* lx[2] = {(T*)(aw + A.off_lx), (T*)(aw + A.off_lx + A.xs_bytes)};
   int cur = 0;
   for (int c = A.nck - 1; c >= 0; --c) {
@@ -202,7 +234,12 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
     const int len = std::min(A.K, N - m0);
     // state m0 + k: k = 0 is the checkpoint, k >= 1 is slot k - 1
     auto state = [&](int k) -> T* { return (T*)(k == 0 ? ckpt(c) : slot(k - 1)); };
+    // psi at Ex then at Ey of state m0 + k (contiguous)
+    auto psi_e = [&](int k) -> T* { return k == 0 ? ckpt_psi(c) + 2 * fe : state(k) + 3 * fe; };
     if (xs_copy > 0 && hipMemcpyAsync(xs_scr, ckpt_xs(c), xs_copy, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return dev_err("state restore");
+    if (L.pml && hipMemcpyAsync(psih + (size_t)(m0 & 1) * 2 * fe, ckpt_psi(c), 2 * fb, hipMemcpyDeviceToDevice,
+                                st) != hipSuccess)
       return dev_err("state restore");
     for (int k = 0; k < len; ++k) {  // states m0+1 .. m0+len into slots 0 .. len-1
       const int m = m0 + k;
@@ -212,6 +249,18 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
       for (int f = 0; f < 3; ++f) {
         rp.f[par][f] = in + (size_t)f * fe;
         rp.f[par ^ 1][f] = out + (size_t)f * fe;
+      }
+      if (L.pml) {
+        // the step updates psi at Ex and Ey in place: start the new slot's
+        // pair from this state's
+        if (hipMemcpyAsync(psi_e(k + 1), psi_e(k), 2 * fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+          return dev_err("recompute copy");
+        for (int q = 0; q < 2; ++q) {
+          rp.psi_h[q][0] = psih + (size_t)q * 2 * fe;
+          rp.psi_h[q][1] = psih + (size_t)q * 2 * fe + fe;
+        }
+        rp.psi_ex = psi_e(k + 1);
+        rp.psi_ey = psi_e(k + 1) + fe;
       }
       rp.step_off = m;
       if (launch_step<T>(rp, s->seg, s->smem, st) != hipSuccess) return dev_err("recompute launch");
@@ -230,6 +279,14 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
       ap.hz1 = state(k + 1);
       ap.ex0 = state(k) + fe;
       ap.ey0 = state(k) + 2 * fe;
+      if (L.pml) {
+        for (int q = 0; q < 4; ++q) {
+          ap.lps_in[q] = li + (size_t)(3 + q) * fe;
+          ap.lps_out[q] = lo + (size_t)(3 + q) * fe;
+        }
+        ap.pex1 = psi_e(k + 1);
+        ap.pey1 = psi_e(k + 1) + fe;
+      }
       if (launch_adjoint_step<T>(ap, L.smem_gemv, st) != hipSuccess) return dev_err("adjoint launch");
       cur ^= 1;
     }
@@ -278,7 +335,6 @@ int fdtd_rom_adjoint(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int3
                      double* grad_sigma) {
   if (!sim || !J || !grad_eps_r || !grad_sigma) return fail(FDTD_EINVAL, "null argument");
   if (sim->steps != 0) return fail(FDTD_ESTATE, "the adjoint starts from the initial state (%d steps taken)", sim->steps);
-  if (sim->L.pml) return fail(FDTD_EINVAL, "the adjoint covers PEC-walled grids only (no absorbing layers)");
   if (probe < 0 || probe >= sim->nprobes) return fail(FDTD_EINVAL, "probe %d out of range", probe);
   if (sim->probes[probe].comp != FDTD_HZ) return fail(FDTD_EINVAL, "probe %d is not an Hz probe", probe);
   try {

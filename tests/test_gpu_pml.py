@@ -2,7 +2,7 @@
 oracle (FP64 <= 1e-12, FP32 <= 1e-5 relative L2 on probes and fields), with
 embedded models, stretched and shifted layers, layers on some sides only,
 every tiling, batches, checkpoint/resume; non-absorbing layers reproduce
-the PEC-walled run."""
+the PEC-walled run.  The reverse sweep through layers has its own file."""
 import copy
 
 import numpy as np
@@ -10,7 +10,6 @@ import pytest
 
 import workloads as W
 from oracle import sim as osim
-from paper_1609_07114_amd import capi
 from paper_1609_07114_amd.batch import Batch
 from paper_1609_07114_amd.sim import Simulation
 from tests._util import rel_l2
@@ -138,13 +137,6 @@ def test_layers_in_a_batch_and_resume():
         s2.set_state(st)
         s2.run(120)
         assert np.array_equal(s2.probes(80, 120), ref)
-
-
-def test_adjoint_refuses_layers():
-    p = _box(80, 60, 50, W.Pml(6, 6, 6, 6))
-    with Simulation(p, []) as s:
-        with pytest.raises(capi.FdtdError):
-            s.adjoint(50)
 
 
 def test_energy_leaves_through_layers_on_device():
