@@ -312,6 +312,21 @@ int fdtd_rom_set_material_mode(fdtd_rom_sim* sim, int32_t mode);
 int fdtd_rom_get_material_mode(fdtd_rom_sim* sim, int32_t* mode, int32_t* entries);
 int fdtd_rom_set_graph(fdtd_rom_sim* sim, int32_t batch);
 
+/* Two leap-frog steps (eq. (5) then eq. (3), twice) per pass over the
+ * coarse grid.  on = 1: steps go in pairs of launches.  The first launch
+ * runs the step-n coupling blocks of eq. (23) and advances every tile of the
+ * grid whose reads stay clear of the regions by two steps at once, holding
+ * step n+1 in registers; the tiles near a region advance one step.  The
+ * second launch advances the near tiles and the coupling by the second
+ * step.  An odd last step runs as a single launch.  The arithmetic per cell
+ * is that of the single-step launch, so results are identical; far cells
+ * move their fields through memory once per two steps.  Graph batches
+ * (fdtd_rom_set_graph) are rounded down to a multiple of 4 steps.
+ * set: synchronises the stream; FDTD_EINVAL for a value other than 0/1 or
+ * for a grid with absorbing layers.  get: the current setting. */
+int fdtd_rom_set_time_blocking(fdtd_rom_sim* sim, int32_t on);
+int fdtd_rom_get_time_blocking(const fdtd_rom_sim* sim, int32_t* on);
+
 /* Discrete adjoint (reverse-time sweep) of the coupled leap-frog run for the
  * objective J = dt * sum_{n=0}^{nsteps-1} (Hz_p^{n+1/2})^2 at Hz probe p:
  * the gradient of J with respect to the relative permittivity and the

@@ -162,7 +162,7 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   for (int c = 0; c < A.nck; ++c) {
     const int m0 = c * A.K;
     const int len = std::min(A.K, N - m0);
-    const char* cur = ws + L.off_fields + (size_t)(m0 & 1) * A.set_bytes;
+    const char* cur = ws + L.off_fields + (size_t)cur_set(s) * A.set_bytes;
     if (hipMemcpyAsync(ckpt(c), cur, A.set_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
         (xs_copy > 0 && hipMemcpyAsync(ckpt_xs(c), ws + L.off_xs, xs_copy, hipMemcpyDeviceToDevice, st) != hipSuccess))
       return dev_err("checkpoint copy");

@@ -119,7 +119,19 @@ struct StepParams {
   T* psi_h[2][2];    // [parity][d/dx of Ey, d/dy of Ex]
   T* psi_ex;         // d/dy of Hz at Ex
   T* psi_ey;         // d/dx of Hz at Ey
+  // two-step launches (no absorbing layers): tiles of kOwned2 columns x
+  // 4 SEG rows; role2[tile] 0 = two steps into f2, 1 = near a region (one
+  // step, written with a one-cell halo into the step-(n+1) set); near_list:
+  // the near tiles, which the second launch of the pair advances; probe_near:
+  // the probe lies in a near tile (recorded by the second launch)
+  T* f2[3];
+  int tiles_x2, nst2_blocks, n_near;
+  const uint8_t* role2;
+  const int* near_list;
+  const uint8_t* probe_near;
 };
+
+constexpr int kOwned2 = kWave - 2;  // columns a two-step wave owns (lanes 1..62)
 
 // One workgroup of the batched step launch: instance `inst`, role `kind`
 // (0 coupling block idx of that instance, 1 stencil tile idx, 2 probe
@@ -138,6 +150,9 @@ int fail(int code, const char* fmt, ...);
 // launchers (kernels.hip)
 template <typename T>
 hipError_t launch_step(const StepParams<T>& p, int seg, size_t smem, hipStream_t s);
+// the pair of launches that advances steps n, n+1 (n = ctrl[0] + step_off)
+template <typename T>
+hipError_t launch_step2(const StepParams<T>& a, const StepParams<T>& b, int seg, size_t smem, hipStream_t s);
 template <typename T>
 hipError_t launch_probe_flush(const StepParams<T>& p, hipStream_t s);
 hipError_t launch_tick(int* ctrl, int k, hipStream_t s);

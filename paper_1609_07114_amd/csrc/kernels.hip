@@ -454,6 +454,293 @@ __device__ __forceinline__ void stencil_tile(const StepParams<T>& p, int t, int 
     stencil_rows<T, SEG, false, MIdx>(p, t, n);
 }
 
+// ---------------------------------------------------------------------------
+// Two steps per pass (time blocking) for grids without absorbing layers.
+// A wave holds 64 lanes = columns iw-1 .. iw+62 (iw = kOwned2 * tile column)
+// and makes one sweep up its rows doing two steps: stage 1 advances rows
+// [rs, re] from step n to n+1 with exactly the arithmetic of stencil_rows
+// (lane 0 also forms the Hz of column iw-2 from the west column, lane 63
+// reads Ey of column iw+63); stage 2 trails one row behind and advances the
+// stage-1 row below from n+1 to n+2 in registers.  Lanes 1..62 own their
+// columns: every stage-2 input they need is in the wave.  Stage-1 rows
+// [j0-2, j1] feed stage-2 rows [j0-1, j1), so only step n+2 goes to memory:
+// 26 bytes per cell for two steps instead of 52.
+//
+// Mode 0: a far tile, whose reads never reach a reduced region or its ring:
+//   two steps into f2.
+// Mode 1: a tile near a region, first launch: stage 1 only, stored for all
+//   64 lanes and rows [j0-1, j1] (the halo the second launch reads) into the
+//   step-(n+1) set, except interface edges (written by the coupling blocks).
+// Mode 2: a near tile, second launch: one step n+1 -> n+2 of its own cells.
+template <typename T>
+struct RowSet2 {
+  RowIn<T> c, w;
+  T eyE;
+};
+
+// stage-1 result of one row, kept for stage 2
+template <typename T>
+struct Stage1 {
+  T h, ex, ey;              // Hz^{n+1/2}, Ex^{n+1}, Ey^{n+1}
+  T cax, cbx, cay, cby;     // eq. (3) coefficients of the row's south Ex and west Ey
+  bool act, ax, ay, ixf, iyf;  // active cell, updated edges, interface edges
+};
+
+template <typename T, bool MIdx, int Mode>
+__device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, int n, int j0, int j1) {
+  constexpr bool kTwo = Mode == 0;
+  const int par = n & 1;
+  const T* hz = fld(p, par, 0);
+  const T* ex = fld(p, par, 1);
+  const T* ey = fld(p, par, 2);
+  T* hzo = kTwo ? p.f2[0] : fld(p, par ^ 1, 0);
+  T* exo = kTwo ? p.f2[1] : fld(p, par ^ 1, 1);
+  T* eyo = kTwo ? p.f2[2] : fld(p, par ^ 1, 2);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int iw = (tile % p.tiles_x2) * kOwned2;
+  const int c = iw - 1 + lane;
+  const int nx = p.nx, ny = p.ny, P = p.pitch;
+  // stage-1 rows [rs, re]
+  const int rs = Mode == 2 ? max(j0 - 1, 0) : max(j0 - 2, 0);
+  const int re = Mode == 2 ? j1 - 1 : min(j1, ny - 1);
+  const int r2lo = max(j0 - 1, 0);  // first stage-2 row (its Hz only, unless j0 = 0)
+  constexpr uint32_t ts = sizeof(T);
+  const uint32_t row_b = (uint32_t)P * ts;
+  const T chdy = p.chdy, chdx = p.chdx, k2dy = p.k2dy, k2dx = p.k2dx;
+  const T* al = p.al;
+  const T* be = p.be;
+  const T* ex_up = ex + P;
+  const bool in = c >= 0 && c < nx;
+  const bool has_left = lane == 0 && c >= 1;
+  const bool own = in && lane >= 1 && lane <= kWave - 2;
+  // sources of both steps touching columns [iw-2, iw+63) x rows [rs, re]
+  bool any_src = false;
+  for (int s = 0; s < p.nsrc; ++s) {
+    const Src<T>& S = p.src[s];
+    any_src |= S.i0 < iw + kWave - 1 && S.i1 > iw - 2 && S.j0 <= re && S.j1 > rs;
+  }
+  T sinc[kMaxSrc], sinc2[kMaxSrc];
+#pragma unroll
+  for (int s = 0; s < kMaxSrc; ++s) {
+    sinc[s] = T(0);
+    sinc2[s] = T(0);
+  }
+  if (any_src) {
+#pragma unroll
+    for (int s = 0; s < kMaxSrc; ++s)
+      if (s < p.nsrc) {
+        sinc[s] = p.src[s].incr[n];
+        if constexpr (kTwo) sinc2[s] = p.src[s].incr[n + 1];
+      }
+  }
+  // Loaded columns: the lane's own (clamped into the row: lanes outside the
+  // grid read a valid address and their values are never used), the west
+  // column iw-2 (read by every lane at one wave-uniform address, used by
+  // lane 0) and the east column iw+63 (used by lane 63 when it exists).
+  const int cl = min(max(c, 0), P - 1);
+  const int wl = max(iw - 2, 0);
+  const bool east = iw + kWave - 1 < nx;
+  const int el = min(iw + kWave - 1, P - 1);
+  const uint32_t dW = (uint32_t)(cl - wl) * ts;
+  const uint32_t dEp = (uint32_t)max(el - cl, 0) * ts;
+  const uint32_t dEn = (uint32_t)max(cl - el, 0) * ts;
+  uint32_t ob = ((uint32_t)rs * (uint32_t)P + (uint32_t)cl) * ts;
+  const uint16_t* mi = p.mi;
+  const MatPair<T>* mt = p.mt;
+  auto fetch = [&](uint32_t o, bool up, uint32_t id, uint32_t idw) {
+    RowSet2<T> r;
+    const T* exr = up ? ex_up : ex;
+    const uint32_t ow = o - dW;
+    r.c.h = ld(hz, o);
+    r.c.ex1 = ld(exr, o);
+    r.c.ey0 = ld(ey, o);
+    r.w.h = ld(hz, ow);
+    r.w.ex1 = ld(exr, ow);
+    r.w.ey0 = ld(ey, ow);
+    r.eyE = ld(ey, o + dEp - dEn);
+    if constexpr (MIdx) {
+      const MatPair<T> m = mt[id], mw = mt[idw];
+      r.c.al = m.a;
+      r.c.be = m.b;
+      r.w.al = mw.a;
+      r.w.be = mw.b;
+    } else {
+      r.c.al = ld(al, o);
+      r.c.be = ld(be, o);
+      r.w.al = ld(al, ow);
+      r.w.be = ld(be, ow);
+    }
+    return r;
+  };
+  auto orow = [&](int r) { return ob + (uint32_t)(r - rs) * row_b; };
+  T ex_c = ld(ex, ob);
+  T exl_c = ld(ex, ob - dW);  // used by lane 0 only when the west column exists
+  T hn_prev = T(0), a_prev = T(0), b_prev = T(0);
+  Stage1<T> prv1{};
+  T h2_prev = T(0);
+  // stage 2 for row r2 from its stage-1 values `a` and Ex^{n+1} of the row
+  // above (exN), stored at byte offset o2
+  auto stage2 = [&](int r2, const Stage1<T>& a, T exN, uint32_t o2) {
+    T eye = lane_next(a.ey);
+    if (c + 1 >= nx) eye = T(0);
+    T h2 = hz_update(a.h, a.ex, exN, a.ey, eye, chdy, chdx);
+    if (any_src) h2 += src_sum(p, sinc2, 0, c, r2);
+    if (!a.act) h2 = T(0);
+    const T h2w = lane_prev(h2);
+    if (r2 >= j0 && own) {
+      T ex2 = a.ax ? e_update(a.cax, a.ex, a.cbx, h2 - h2_prev) : a.ex;
+      T ey2 = a.ay ? e_update(a.cay, a.ey, a.cby, -(h2 - h2w)) : a.ey;
+      if (any_src) {
+        ex2 += src_sum(p, sinc2, 1, c, r2);
+        ey2 += src_sum(p, sinc2, 2, c, r2);
+      }
+      st(hzo, o2, h2);
+      if (!a.ixf) st(exo, o2, ex2);
+      if (!a.iyf) st(eyo, o2, ey2);
+    }
+    h2_prev = h2;
+  };
+  // stage 1 for row r from its loaded data
+  auto compute = [&](int r, const RowSet2<T>& cs) {
+    RowIn<T> cur = cs.c;
+    RowIn<T> cul = cs.w;
+    if (r + 1 >= ny) {
+      cur.ex1 = T(0);
+      cul.ex1 = T(0);
+    }
+    T ey1 = lane_next(cur.ey0);
+    if (lane == kWave - 1) ey1 = east ? cs.eyE : T(0);
+    if (c + 1 >= nx) ey1 = T(0);
+    const bool act = in && cur.al > T(0);
+    T hn = hz_update(cur.h, ex_c, cur.ex1, cur.ey0, ey1, chdy, chdx);
+    if (any_src) hn += src_sum(p, sinc, 0, c, r);
+    if (!act) hn = T(0);
+    T hnl = lane_prev(hn);
+    T all = lane_prev(cur.al);
+    T bel = lane_prev(cur.be);
+    if (lane == 0) {
+      hnl = T(0);
+      all = cul.al;
+      bel = cul.be;
+      if (has_left) {
+        hnl = hz_update(cul.h, exl_c, cul.ex1, cul.ey0, cur.ey0, chdy, chdx);
+        if (any_src) hnl += src_sum(p, sinc, 0, c - 1, r);
+        if (!(all > T(0))) hnl = T(0);
+        exl_c = cul.ex1;
+      }
+    }
+    Stage1<T> o;
+    o.act = act;
+    o.ax = r >= 1 && act && a_prev > T(0);
+    edge_coef(cur.al + a_prev, cur.be + b_prev, k2dy, o.cax, o.cbx);
+    o.ay = c >= 1 && act && all > T(0);
+    edge_coef(cur.al + all, cur.be + bel, k2dx, o.cay, o.cby);
+    T exn = o.ax ? e_update(o.cax, ex_c, o.cbx, hn - hn_prev) : ex_c;
+    T eyn = o.ay ? e_update(o.cay, cur.ey0, o.cby, -(hn - hnl)) : cur.ey0;
+    if (any_src) {
+      exn += src_sum(p, sinc, 1, c, r);
+      eyn += src_sum(p, sinc, 2, c, r);
+    }
+    o.h = hn;
+    o.ex = exn;
+    o.ey = eyn;
+    o.ixf = (cur.al < T(0)) != (a_prev < T(0));
+    o.iyf = (cur.al < T(0)) != (all < T(0));
+    if constexpr (Mode != 0) {
+      const bool st_lane = Mode == 1 ? in : own;
+      if (st_lane && r >= (Mode == 1 ? r2lo : j0)) {
+        st(hzo, ob, hn);
+        if (!o.ixf) st(exo, ob, exn);
+        if (!o.iyf) st(eyo, ob, eyn);
+      }
+    } else {
+      if (r - 1 >= r2lo) stage2(r - 1, prv1, exn, ob - row_b);
+      prv1 = o;
+    }
+    hn_prev = hn;
+    a_prev = cur.al;
+    b_prev = cur.be;
+    ex_c = cur.ex1;
+  };
+  // software pipeline as in stencil_rows: rows r+1 and r+2 in flight while
+  // row r is computed; material indices two rows further ahead
+  const int rend = re + 1;
+  uint32_t idA = 0, idB = 0, idAw = 0, idBw = 0;
+  RowSet2<T> n1, n2;
+  if constexpr (MIdx) {
+    const uint32_t o0 = orow(rs), o1 = orow(min(rs + 1, re));
+    const uint32_t oA = orow(min(rs + 2, re)), oB = orow(min(rs + 3, re));
+    const uint32_t i0 = mat_id<T>(mi, o0), i0w = mat_id<T>(mi, o0 - dW);
+    const uint32_t i1 = mat_id<T>(mi, o1), i1w = mat_id<T>(mi, o1 - dW);
+    idA = mat_id<T>(mi, oA);
+    idAw = mat_id<T>(mi, oA - dW);
+    idB = mat_id<T>(mi, oB);
+    idBw = mat_id<T>(mi, oB - dW);
+    n1 = fetch(o0, rs + 1 < ny, i0, i0w);
+    n2 = fetch(o1, rs + 2 < ny, i1, i1w);
+  } else {
+    n1 = fetch(orow(rs), rs + 1 < ny, 0, 0);
+    n2 = fetch(orow(min(rs + 1, re)), rs + 2 < ny, 0, 0);
+  }
+  int r = rs;
+  for (; r + 2 < rend; ++r, ob += row_b) {
+    const RowSet2<T> cur = n1;
+    n1 = n2;
+    const uint32_t o3 = ob + 2 * row_b;
+    if constexpr (MIdx) {
+      const uint32_t oC = o3 + (r + 3 < rend ? row_b : 0u) + (r + 4 < rend ? row_b : 0u);
+      const uint32_t idC = mat_id<T>(mi, oC), idCw = mat_id<T>(mi, oC - dW);
+      n2 = fetch(o3, r + 3 < ny, idA, idAw);
+      idA = idB;
+      idAw = idBw;
+      idB = idC;
+      idBw = idCw;
+    } else {
+      n2 = fetch(o3, r + 3 < ny, 0, 0);
+    }
+    compute(r, cur);
+  }
+  for (; r < rend; ++r, ob += row_b) {
+    const RowSet2<T> cur = n1;
+    n1 = n2;
+    compute(r, cur);
+  }
+  // the top row of the grid: its stage 2 has the north wall above it
+  if constexpr (kTwo) {
+    if (j1 == ny) stage2(ny - 1, prv1, T(0), ob - row_b);
+  }
+}
+
+// First launch: workgroup t takes tile t (XCD-remapped), wave w its rows
+// [j0, j0+SEG).  Second launch: the near tiles' single step is short work
+// bound by the latency of each wave's row chain, so every near tile is
+// split over kNearSplit workgroups, each wave taking SEG/kNearSplit rows.
+constexpr int kNearSplit = 4;
+
+template <typename T, int SEG, bool MIdx, bool Second>
+__device__ __forceinline__ void stencil2_tile(const StepParams<T>& p, int t, int n) {
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if constexpr (Second) {
+    constexpr int rows = SEG / kNearSplit > 0 ? SEG / kNearSplit : 1;
+    const int u = xcd_tile(t, p.n_near * kNearSplit);
+    const int tile = p.near_list[u / kNearSplit];
+    const int jb0 = (tile / p.tiles_x2) * (kBlock / kWave) * SEG;
+    const int jb1 = min(jb0 + (kBlock / kWave) * SEG, p.ny);
+    const int j0 = jb0 + ((u % kNearSplit) * (kBlock / kWave) + wv) * rows;
+    if (j0 >= jb1) return;  // uniform over the wave
+    stencil2_rows<T, MIdx, 2>(p, tile, n, j0, min(j0 + rows, jb1));
+  } else {
+    const int tile = xcd_tile(t, p.nst2_blocks);
+    const int j0 = ((tile / p.tiles_x2) * (kBlock / kWave) + wv) * SEG;
+    if (j0 >= p.ny) return;  // uniform over the wave
+    const int j1 = min(j0 + SEG, p.ny);
+    if (p.role2[tile])
+      stencil2_rows<T, MIdx, 1>(p, tile, n, j0, j1);
+    else
+      stencil2_rows<T, MIdx, 0>(p, tile, n, j0, j1);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -657,6 +944,106 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepParams<T> p) {
   record_probes(p, n - 1);
 }
 
+// Value of probe t after step n+1 from the step-n set, formed exactly as the
+// stencil forms it (its cell and neighbours are ordinary coarse cells: only
+// probes of far tiles come here).
+template <typename T>
+__device__ __forceinline__ T probe_next(const StepParams<T>& p, int t, int n) {
+  const int par = n & 1;
+  const T* hz = fld(p, par, 0);
+  const T* ex = fld(p, par, 1);
+  const T* ey = fld(p, par, 2);
+  const int P = p.pitch;
+  const int o = p.probe_off[t];
+  const int j = o / P;
+  const int i = o - j * P;
+  auto mat = [&](int oc, T& a, T& b) {
+    if (p.midx) {
+      const MatPair<T> m = p.mt[p.mi[oc]];
+      a = m.a;
+      b = m.b;
+    } else {
+      a = p.al[oc];
+      b = p.be[oc];
+    }
+  };
+  auto srcs = [&](int comp, int ii, int jj) {
+    T acc = T(0);
+    for (int s = 0; s < p.nsrc; ++s) {
+      const Src<T>& S = p.src[s];
+      if (S.comp == comp && ii >= S.i0 && ii < S.i1 && jj >= S.j0 && jj < S.j1) acc += S.incr[n];
+    }
+    return acc;
+  };
+  auto hnext = [&](int ii, int jj) {
+    const int oc = jj * P + ii;
+    const T ex1 = jj + 1 < p.ny ? ex[oc + P] : T(0);
+    const T ey1 = ii + 1 < p.nx ? ey[oc + 1] : T(0);
+    T h = hz_update(hz[oc], ex[oc], ex1, ey[oc], ey1, p.chdy, p.chdx);
+    if (p.nsrc > 0) h += srcs(0, ii, jj);
+    T a, b;
+    mat(oc, a, b);
+    return a > T(0) ? h : T(0);
+  };
+  const int comp = p.probe_comp[t];
+  if (comp == 0) return hnext(i, j);
+  T a, b, a2 = T(0), b2 = T(0);
+  mat(o, a, b);
+  T v = comp == 1 ? ex[o] : ey[o];
+  const bool edge = comp == 1 ? j >= 1 : i >= 1;
+  if (edge) mat(comp == 1 ? o - P : o - 1, a2, b2);
+  if (edge && a > T(0) && a2 > T(0)) {
+    T ca, cb;
+    edge_coef(a + a2, b + b2, comp == 1 ? p.k2dy : p.k2dx, ca, cb);
+    const T h = hnext(i, j);
+    v = comp == 1 ? e_update(ca, v, cb, h - hnext(i, j - 1)) : e_update(ca, v, cb, -(h - hnext(i - 1, j)));
+  }
+  if (p.nsrc > 0) v += srcs(comp, i, j);
+  return v;
+}
+
+// The pair of launches that advances steps n and n+1 (time blocking):
+//   first (Second = false): coupling blocks of step n (interface E^{n+1} into
+//     the step-(n+1) set), every tile (far: two steps into f2; near: one step
+//     with halo into the step-(n+1) set), probe block (row n-1 from the
+//     step-n set; row n of far probes formed from the step-n set);
+//   second: coupling blocks of step n+1 (reading the step-(n+1) set, writing
+//     f2's interface edges), the near tiles' step n+1 -> n+2 into f2 (here
+//     f[(n+1)&1 ^ 1]), probe block (row n of near probes).
+template <typename T, int SEG, bool MIdx, bool Second>
+__global__ void __launch_bounds__(kBlock) step2_kernel(const StepParams<T> p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = p.ctrl[0] + p.step_off;
+  const int b = blockIdx.x;
+  if (b < p.ncoup_blocks) {
+    if (b < p.nrowblocks) {
+      const RowBlock rb = p.blocks[b];
+      if constexpr (sizeof(T) == 4) {
+        if (rb.kind == 1) {
+          coupling_gemm(p, rb, n, reinterpret_cast<float*>(smem));
+          return;
+        }
+      }
+      coupling_rows(p, rb, n, reinterpret_cast<T*>(smem));
+    }
+    return;
+  }
+  const int t = b - p.ncoup_blocks;
+  if (t < (Second ? p.n_near * kNearSplit : p.nst2_blocks)) {
+    stencil2_tile<T, SEG, MIdx, Second>(p, t, n);
+    return;
+  }
+  if constexpr (Second) {
+    const int par = n & 1;  // the step-n set of this launch (step n+1 of the pair)
+    for (int k = threadIdx.x; k < p.nprobes; k += kBlock)
+      if (p.probe_near[k]) p.probe_buf[(size_t)(n - 1) * p.nprobes + k] = fld(p, par, p.probe_comp[k])[p.probe_off[k]];
+  } else {
+    record_probes(p, n - 1);
+    for (int k = threadIdx.x; k < p.nprobes; k += kBlock)
+      if (!p.probe_near[k]) p.probe_buf[(size_t)n * p.nprobes + k] = probe_next(p, k, n);
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) probe_kernel(const StepParams<T> p) {
   record_probes(p, p.ctrl[0] + p.step_off - 1);
@@ -819,6 +1206,37 @@ hipError_t launch_step(const StepParams<T>& p, int seg, size_t smem, hipStream_t
 }
 
 template <typename T>
+hipError_t launch_step2(const StepParams<T>& a, const StepParams<T>& b, int seg, size_t smem, hipStream_t s) {
+  const dim3 ga(a.ncoup_blocks + a.nst2_blocks + 1), gb(b.ncoup_blocks + b.n_near * kNearSplit + 1), blk(kBlock);
+  auto go = [&](auto midx) -> hipError_t {
+    constexpr bool Mf = decltype(midx)::value;
+    switch (seg) {
+      case 4:
+        hipLaunchKernelGGL((step2_kernel<T, 4, Mf, false>), ga, blk, smem, s, a);
+        hipLaunchKernelGGL((step2_kernel<T, 4, Mf, true>), gb, blk, smem, s, b);
+        break;
+      case 8:
+        hipLaunchKernelGGL((step2_kernel<T, 8, Mf, false>), ga, blk, smem, s, a);
+        hipLaunchKernelGGL((step2_kernel<T, 8, Mf, true>), gb, blk, smem, s, b);
+        break;
+      case 16:
+        hipLaunchKernelGGL((step2_kernel<T, 16, Mf, false>), ga, blk, smem, s, a);
+        hipLaunchKernelGGL((step2_kernel<T, 16, Mf, true>), gb, blk, smem, s, b);
+        break;
+      case 32:
+        hipLaunchKernelGGL((step2_kernel<T, 32, Mf, false>), ga, blk, smem, s, a);
+        hipLaunchKernelGGL((step2_kernel<T, 32, Mf, true>), gb, blk, smem, s, b);
+        break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+  };
+  const hipError_t e = a.midx ? go(std::true_type{}) : go(std::false_type{});
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_probe_flush(const StepParams<T>& p, hipStream_t s) {
   hipLaunchKernelGGL((probe_kernel<T>), dim3(1), dim3(kBlock), 0, s, p);
   return hipGetLastError();
@@ -831,6 +1249,8 @@ hipError_t launch_tick(int* ctrl, int k, hipStream_t s) {
 
 template hipError_t launch_step<float>(const StepParams<float>&, int, size_t, hipStream_t);
 template hipError_t launch_step<double>(const StepParams<double>&, int, size_t, hipStream_t);
+template hipError_t launch_step2<float>(const StepParams<float>&, const StepParams<float>&, int, size_t, hipStream_t);
+template hipError_t launch_step2<double>(const StepParams<double>&, const StepParams<double>&, int, size_t, hipStream_t);
 template hipError_t launch_probe_flush<float>(const StepParams<float>&, hipStream_t);
 template hipError_t launch_probe_flush<double>(const StepParams<double>&, hipStream_t);
 template hipError_t launch_batch_step<float>(const StepParams<float>*, const BatchRef*, int, const int*,

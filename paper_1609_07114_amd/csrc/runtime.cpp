@@ -191,6 +191,17 @@ int fdtd::plan_problem(const fdtd_problem* p, Layout& L) {
     o = align_up(o + 6 * ((size_t)L.px_stride + L.py_stride) * ts, 256);
     L.off_psi = o;
     o = align_up(o + 6 * L.field_elems * ts, 256);
+  } else {
+    L.tb_ok = true;
+    L.max_tiles2 = ((g.nx + kOwned2 - 1) / kOwned2) * ((g.ny + 15) / 16);  // at 4 rows per wave
+    L.off_fc = o;
+    o = align_up(o + 3 * L.field_elems * ts, 256);
+    L.off_role2 = o;
+    o = align_up(o + (size_t)L.max_tiles2, 256);
+    L.off_near = o;
+    o = align_up(o + (size_t)L.max_tiles2 * sizeof(int), 256);
+    L.off_pnear = o;
+    o = align_up(o + (size_t)std::max(p->nprobes, 1), 256);
   }
   L.total = o;
   return FDTD_OK;
@@ -275,6 +286,11 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
     if ((rc = up(L.off_fields + (3 * set + 0) * fb, host.data(), fb)) != FDTD_OK) return rc;
     if ((rc = up(L.off_fields + (3 * set + 1) * fb, ex.data(), fb)) != FDTD_OK) return rc;
     if ((rc = up(L.off_fields + (3 * set + 2) * fb, ey.data(), fb)) != FDTD_OK) return rc;
+  }
+  if (L.tb_ok) {  // the two-step launches' step-(n+1) set starts as a copy of the state
+    if ((rc = up(L.off_fc, host.data(), fb)) != FDTD_OK) return rc;
+    if ((rc = up(L.off_fc + fb, ex.data(), fb)) != FDTD_OK) return rc;
+    if ((rc = up(L.off_fc + 2 * fb, ey.data(), fb)) != FDTD_OK) return rc;
   }
   // per-cell material: a = eps0*eps_r/dt (negative inside regions), b = sigma/2
   std::vector<T> al(fe, T(0)), be(fe, T(0));
@@ -822,17 +838,108 @@ int ev_pair(fdtd_rom_sim* s, std::vector<std::pair<hipEvent_t, hipEvent_t>>& poo
   return FDTD_OK;
 }
 
-// Enqueue nsteps step launches, the probe flush and the tick on `stream`.
+// Tile roles of the two-step launches for the handle's tiling.  A tile of
+// kOwned2 columns x 4 SEG rows is far when everything its two-step sweep
+// reads (columns iw-2 .. iw+63, rows j0-2 .. j1+1, widened by one) stays
+// clear of every region's zone [i0-2, i0+ni+1] x [j0-2, j0+nj+1] (the
+// region, its ring of port cells and the edges between them, with one
+// cell to spare); otherwise it is near.  A probe is near when the tile that
+// owns its cell is.  Uploaded synchronously (never while capturing).
 template <typename T>
-int enqueue_steps(fdtd_rom_sim* s, int nsteps, hipStream_t stream, bool prof) {
+int prepare_tb(fdtd_rom_sim* s) {
+  const Layout& L = s->L;
+  if (s->tb_seg == s->seg) return FDTD_OK;
+  const int rows = (kBlock / kWave) * s->seg;
+  const int tx2 = (s->nx + kOwned2 - 1) / kOwned2;
+  const int nt = tx2 * ((s->ny + rows - 1) / rows);
+  if (nt > L.max_tiles2) return fail(FDTD_EINVAL, "internal: two-step tile count %d exceeds %d", nt, L.max_tiles2);
+  std::vector<uint8_t> role(nt, 0);
+  std::vector<int> near;
+  for (int t = 0; t < nt; ++t) {
+    const int iw = (t % tx2) * kOwned2;
+    const int jb0 = (t / tx2) * rows;
+    const int jb1 = std::min(jb0 + rows, s->ny);
+    const int fx0 = iw - 3, fx1 = iw + kWave, fy0 = jb0 - 3, fy1 = jb1 + 2;
+    for (const RomHost& h : s->roms) {
+      const int zx0 = h.i0 - 2, zx1 = h.i0 + h.ni + 1, zy0 = h.j0 - 2, zy1 = h.j0 + h.nj + 1;
+      if (fx0 <= zx1 && zx0 <= fx1 && fy0 <= zy1 && zy0 <= fy1) role[t] = 1;
+    }
+    if (role[t]) near.push_back(t);
+  }
+  std::vector<uint8_t> pnear(std::max(s->nprobes, 1), 0);
+  for (int k = 0; k < s->nprobes; ++k) {
+    const fdtd_probe& pr = s->probes[k];
+    pnear[k] = role[(pr.j / rows) * tx2 + pr.i / kOwned2];
+  }
+  hipStream_t st = s->stream;
+  if (hipMemcpyAsync(s->ws + L.off_role2, role.data(), role.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      (!near.empty() && hipMemcpyAsync(s->ws + L.off_near, near.data(), near.size() * sizeof(int),
+                                       hipMemcpyHostToDevice, st) != hipSuccess) ||
+      hipMemcpyAsync(s->ws + L.off_pnear, pnear.data(), pnear.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(FDTD_EDEVICE, "two-step tile upload failed");
+  auto fill = [&](auto& sp) {
+    sp.tiles_x2 = tx2;
+    sp.nst2_blocks = nt;
+    sp.n_near = (int)near.size();
+    sp.role2 = (const uint8_t*)(s->ws + L.off_role2);
+    sp.near_list = (const int*)(s->ws + L.off_near);
+    sp.probe_near = (const uint8_t*)(s->ws + L.off_pnear);
+  };
+  fill(s->sp_f);
+  fill(s->sp_d);
+  s->tb_seg = s->seg;
+  return FDTD_OK;
+}
+
+// Enqueue nsteps steps, the probe flush and the tick on `stream`, the
+// handle's state standing at step steps0.  With two-step launches the steps
+// go in pairs (a last odd step as a single launch); each pair leaves step
+// n+2 in the set that held n+1's place, so the two sets trade places.
+// Returns the number of pairs through `pairs`.
+template <typename T>
+int enqueue_steps(fdtd_rom_sim* s, int nsteps, hipStream_t stream, bool prof, int steps0, int* pairs) {
   StepParams<T> sp = step_params<T>(s);
-  for (int k = 0; k < nsteps; ++k) {
+  int k = 0;
+  *pairs = 0;
+  auto ev_begin = [&](hipEvent_t& e0, hipEvent_t& e1) -> int {
+    const int rc = ev_pair(s, s->ev_st, s->used_st, e0, e1);
+    if (rc != FDTD_OK) return rc;
+    if (hipEventRecord(e0, stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
+    return FDTD_OK;
+  };
+  if (s->tb) {
+    T* fc[3];
+    for (int c = 0; c < 3; ++c) fc[c] = (T*)(s->ws + s->L.off_fc + c * s->L.field_elems * sizeof(T));
+    for (; k + 2 <= nsteps; k += 2) {
+      const int par = (steps0 + k) & 1;
+      StepParams<T> a = sp, b = sp;
+      for (int c = 0; c < 3; ++c) {
+        a.f[par ^ 1][c] = fc[c];
+        a.f2[c] = sp.f[par ^ 1][c];
+        b.f[par ^ 1][c] = fc[c];
+        b.f[par][c] = sp.f[par ^ 1][c];
+      }
+      a.step_off = k;
+      b.step_off = k + 1;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (prof) {
+        const int rc = ev_begin(e0, e1);
+        if (rc != FDTD_OK) return rc;
+      }
+      if (launch_step2<T>(a, b, s->seg, s->smem, stream) != hipSuccess)
+        return fail(FDTD_EDEVICE, "two-step launch failed: %s", hipGetErrorString(hipGetLastError()));
+      if (prof && hipEventRecord(e1, stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
+      for (int c = 0; c < 3; ++c) std::swap(sp.f[0][c], sp.f[1][c]);
+      ++*pairs;
+    }
+  }
+  for (; k < nsteps; ++k) {
     sp.step_off = k;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof) {
-      const int rc = ev_pair(s, s->ev_st, s->used_st, e0, e1);
+      const int rc = ev_begin(e0, e1);
       if (rc != FDTD_OK) return rc;
-      if (hipEventRecord(e0, stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
     }
     if (launch_step<T>(sp, s->seg, s->smem, stream) != hipSuccess)
       return fail(FDTD_EDEVICE, "step launch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -862,15 +969,17 @@ void drop_graph(fdtd_rom_sim* s) {
 // library's own stream; it is replayed on the caller's stream.  Every launch
 // reads its step index from the device base, so one graph serves any start.
 template <typename T>
-int capture_graph(fdtd_rom_sim* s) {
+int capture_graph(fdtd_rom_sim* s, int gb, int key) {
   drop_graph(s);
   if (!s->cap_stream && hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return fail(FDTD_EDEVICE, "hipStreamCreateWithFlags failed");
   if (hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return fail(FDTD_EDEVICE, "hipStreamBeginCapture failed");
-  int rc = enqueue_steps<T>(s, s->graph_batch, s->cap_stream, false);
+  int pairs = 0;
+  int rc = enqueue_steps<T>(s, gb, s->cap_stream, false, s->steps, &pairs);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+  if (rc == FDTD_OK && (pairs & 1)) rc = fail(FDTD_EINVAL, "internal: odd pair count in a captured batch");
   if (rc != FDTD_OK) {
     if (g) (void)hipGraphDestroy(g);
     return rc;
@@ -881,29 +990,46 @@ int capture_graph(fdtd_rom_sim* s) {
   (void)hipGraphDestroy(g);
   if (ei != hipSuccess) return fail(FDTD_EDEVICE, "hipGraphInstantiate failed");
   s->graph = ex;
-  s->graph_steps = s->graph_batch;
+  s->graph_steps = gb;
   s->graph_seg = s->seg;
+  s->graph_key = key;
   return FDTD_OK;
 }
 
+// A captured batch holds fixed set pointers.  Single-step batches serve any
+// start; two-step batches (a multiple of 4 steps: an even number of pairs,
+// so the sets are back in place afterwards) are keyed on the start parity
+// and the set order they were captured for.
 template <typename T>
 int run_steps(fdtd_rom_sim* s, int nsteps) {
   if (nsteps == 0) return FDTD_OK;
+  if (s->tb) {
+    const int rc = prepare_tb<T>(s);
+    if (rc != FDTD_OK) return rc;
+  }
   int done = 0;
-  if (s->graph_batch > 0 && !s->prof && nsteps >= s->graph_batch) {
-    if (!s->graph || s->graph_steps != s->graph_batch || s->graph_seg != s->seg) {
-      const int rc = capture_graph<T>(s);
+  const int gb = s->tb ? s->graph_batch / 4 * 4 : s->graph_batch;
+  if (gb > 0 && !s->prof && nsteps >= gb) {
+    const int key = s->tb ? 1 | ((s->steps & 1) << 1) | (s->flip << 2) : 0;
+    if (!s->graph || s->graph_steps != gb || s->graph_seg != s->seg || s->graph_key != key) {
+      const int rc = capture_graph<T>(s, gb, key);
       if (rc != FDTD_OK) return rc;
     }
-    while (nsteps - done >= s->graph_batch) {
+    while (nsteps - done >= gb) {
       if (hipGraphLaunch(s->graph, s->stream) != hipSuccess)
         return fail(FDTD_EDEVICE, "hipGraphLaunch failed: %s", hipGetErrorString(hipGetLastError()));
-      done += s->graph_batch;
+      done += gb;
     }
   }
   if (nsteps > done) {
-    const int rc = enqueue_steps<T>(s, nsteps - done, s->stream, s->prof);
+    int pairs = 0;
+    const int rc = enqueue_steps<T>(s, nsteps - done, s->stream, s->prof, s->steps + done, &pairs);
     if (rc != FDTD_OK) return rc;
+    if (pairs & 1) {
+      StepParams<T>& sp = step_params<T>(s);
+      for (int c = 0; c < 3; ++c) std::swap(sp.f[0][c], sp.f[1][c]);
+      s->flip ^= 1;
+    }
   }
   s->steps += nsteps;
   return FDTD_OK;
@@ -1037,7 +1163,7 @@ int fdtd_rom_read_field(const fdtd_rom_sim* sim, int32_t comp, double* host_out)
   if (comp < 0 || comp > 2) return fail(FDTD_EINVAL, "bad component");
   const size_t ts = sim->L.tsize, fe = sim->L.field_elems;
   std::vector<char> raw(fe * ts);
-  const char* src = sim->ws + sim->L.off_fields + (3 * (sim->steps & 1) + comp) * fe * ts;
+  const char* src = sim->ws + sim->L.off_fields + (3 * cur_set(sim) + comp) * fe * ts;
   if (hipMemcpyAsync(raw.data(), src, fe * ts, hipMemcpyDeviceToHost, sim->stream) != hipSuccess ||
       hipStreamSynchronize(sim->stream) != hipSuccess)
     return fail(FDTD_EDEVICE, "field read failed");
@@ -1102,7 +1228,7 @@ int fdtd_rom_energy(const fdtd_rom_sim* sim, double* e) {
   try {
     const Layout& L = sim->L;
     const size_t ts = L.tsize, fe = L.field_elems;
-    const char* set = sim->ws + L.off_fields + (size_t)(sim->steps & 1) * 3 * fe * ts;
+    const char* set = sim->ws + L.off_fields + (size_t)cur_set(sim) * 3 * fe * ts;
     double* part = (double*)(sim->ws + L.off_energy);
     const double ch = kMu0 * sim->dx * sim->dy / sim->dt;
     const double ha = 0.5 * sim->dx * sim->dy;
@@ -1182,7 +1308,7 @@ int fdtd_rom_get_state(const fdtd_rom_sim* sim, void* dev_dst) {
                 (int64_t)L.xs_elems, L.pml ? 1 : 0, 0};
   char* d = (char*)dev_dst;
   if (hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, sim->stream) != hipSuccess ||
-      hipMemcpyAsync(d + kStateHeader, sim->ws + L.off_fields + (size_t)(sim->steps & 1) * set_bytes, set_bytes,
+      hipMemcpyAsync(d + kStateHeader, sim->ws + L.off_fields + (size_t)cur_set(sim) * set_bytes, set_bytes,
                      hipMemcpyDeviceToDevice, sim->stream) != hipSuccess ||
       (L.xs_elems > 0 && hipMemcpyAsync(d + kStateHeader + align_up(set_bytes, 256), sim->ws + L.off_xs,
                                         L.xs_elems * L.tsize, hipMemcpyDeviceToDevice, sim->stream) != hipSuccess))
@@ -1212,7 +1338,7 @@ int fdtd_rom_set_state(fdtd_rom_sim* sim, const void* dev_src) {
   if (h.steps < 0 || h.steps > sim->max_steps)
     return fail(FDTD_EINVAL, "state at step %d outside [0, max_steps=%d]", h.steps, sim->max_steps);
   int ctrl[kCtrlInts] = {h.steps, 0, 0, 0};
-  if (hipMemcpyAsync(sim->ws + L.off_fields + (size_t)(h.steps & 1) * set_bytes, d + kStateHeader, set_bytes,
+  if (hipMemcpyAsync(sim->ws + L.off_fields + (size_t)((h.steps & 1) ^ sim->flip) * set_bytes, d + kStateHeader, set_bytes,
                      hipMemcpyDeviceToDevice, sim->stream) != hipSuccess ||
       (L.xs_elems > 0 && hipMemcpyAsync(sim->ws + L.off_xs, d + kStateHeader + align_up(set_bytes, 256),
                                         L.xs_elems * L.tsize, hipMemcpyDeviceToDevice, sim->stream) != hipSuccess) ||
@@ -1310,6 +1436,22 @@ int fdtd_rom_get_material_mode(fdtd_rom_sim* sim, int32_t* mode, int32_t* entrie
   if (!sim || !mode || !entries) return fail(FDTD_EINVAL, "null argument");
   *mode = sim->dtype == FDTD_F32 ? sim->sp_f.midx : sim->sp_d.midx;
   *entries = sim->nmat;
+  return FDTD_OK;
+}
+
+int fdtd_rom_set_time_blocking(fdtd_rom_sim* sim, int32_t on) {
+  if (!sim) return fail(FDTD_EINVAL, "null handle");
+  if (on != 0 && on != 1) return fail(FDTD_EINVAL, "time blocking must be 0 or 1");
+  if (on && !sim->L.tb_ok) return fail(FDTD_EINVAL, "two-step launches need a grid without absorbing layers");
+  if (hipStreamSynchronize(sim->stream) != hipSuccess) return fail(FDTD_EDEVICE, "synchronize failed");
+  sim->tb = on != 0;
+  drop_graph(sim);
+  return FDTD_OK;
+}
+
+int fdtd_rom_get_time_blocking(const fdtd_rom_sim* sim, int32_t* on) {
+  if (!sim || !on) return fail(FDTD_EINVAL, "null argument");
+  *on = sim->tb ? 1 : 0;
   return FDTD_OK;
 }
 

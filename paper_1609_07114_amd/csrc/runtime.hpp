@@ -31,6 +31,11 @@ struct Layout {
   bool pml = false;                 // absorbing layers present
   int px_stride = 0, py_stride = 0; // profile row lengths (x: columns, y: rows)
   size_t off_prof = 0, off_psi = 0; // profiles [6][px] + [6][py]; 6 auxiliary fields
+  // two-step launches (grids without layers): the step-(n+1) field set the
+  // pair writes near regions, tile roles, near-tile list, near-probe flags
+  bool tb_ok = false;
+  int max_tiles2 = 0;
+  size_t off_fc = 0, off_role2 = 0, off_near = 0, off_pnear = 0;
   size_t mats_elems = 0, xs_elems = 0, idx_elems = 0;
   int nrowblocks = 0;        // all-GEMV coupling list
   int nblocks_mixed = 0;     // GEMM for eligible shared groups + GEMV for the rest
@@ -76,7 +81,13 @@ struct fdtd_rom_sim {
   int graph_batch = 0;               // > 0: replay captured batches of this many steps
   hipStream_t cap_stream = nullptr;  // library-owned stream used only for capture
   hipGraphExec_t graph = nullptr;
-  int graph_steps = 0, graph_seg = 0;
+  int graph_steps = 0, graph_seg = 0, graph_key = 0;
+  // two steps per pass: on, tiling its roles were built for, and whether
+  // the two field sets have traded places (state n lives in set
+  // (n & 1) ^ flip; a pair of launches writes step n+2 into the other set)
+  bool tb = false;
+  int tb_seg = 0;
+  int flip = 0;
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_st, ev_cp;
   size_t used_st = 0, used_cp = 0;
@@ -85,6 +96,9 @@ struct fdtd_rom_sim {
 };
 
 namespace fdtd {
+
+// physical field set (0 or 1) holding the handle's current state
+inline int cur_set(const fdtd_rom_sim* s) { return (s->steps & 1) ^ s->flip; }
 
 template <typename T>
 StepParams<T>& step_params(fdtd_rom_sim* s) {

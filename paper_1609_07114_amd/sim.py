@@ -85,6 +85,12 @@ class Simulation:
     def set_graph(self, batch):
         capi.fdtd_rom_set_graph(self.h, batch)
 
+    def set_time_blocking(self, on):
+        capi.fdtd_rom_set_time_blocking(self.h, on)
+
+    def time_blocking(self):
+        return capi.fdtd_rom_get_time_blocking(self.h)
+
     def adjoint(self, nsteps=None, probe=0, ckpt_every=0):
         """Forward run from the initial state plus the reverse sweep:
         (J, dJ/deps_r, dJ/dsigma) for J = dt * sum_n Hz_probe(n+1/2)^2."""
