@@ -131,7 +131,7 @@ struct StepParams {
   const uint8_t* probe_near;
 };
 
-constexpr int kOwned2 = kWave - 2;  // columns a two-step wave owns (lanes 1..62)
+constexpr int kOwned2 = kWave - 4;  // columns a two-step wave owns (lanes 2..61)
 
 // One workgroup of the batched step launch: instance `inst`, role `kind`
 // (0 coupling block idx of that instance, 1 stencil tile idx, 2 probe

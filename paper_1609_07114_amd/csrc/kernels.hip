@@ -456,26 +456,26 @@ __device__ __forceinline__ void stencil_tile(const StepParams<T>& p, int t, int 
 
 // ---------------------------------------------------------------------------
 // Two steps per pass (time blocking) for grids without absorbing layers.
-// A wave holds 64 lanes = columns iw-1 .. iw+62 (iw = kOwned2 * tile column)
-// and makes one sweep up its rows doing two steps: stage 1 advances rows
-// [rs, re] from step n to n+1 with exactly the arithmetic of stencil_rows
-// (lane 0 also forms the Hz of column iw-2 from the west column, lane 63
-// reads Ey of column iw+63); stage 2 trails one row behind and advances the
-// stage-1 row below from n+1 to n+2 in registers.  Lanes 1..62 own their
-// columns: every stage-2 input they need is in the wave.  Stage-1 rows
-// [j0-2, j1] feed stage-2 rows [j0-1, j1), so only step n+2 goes to memory:
-// 26 bytes per cell for two steps instead of 52.
+// A wave holds 64 lanes = columns iw-2 .. iw+61 (iw = kOwned2 * tile
+// column) and makes one sweep up its rows doing two steps: stage 1 advances
+// rows [rs, re] from step n to n+1 with exactly the arithmetic of
+// stencil_rows; stage 2 trails one row behind and advances the stage-1 row
+// below from n+1 to n+2 in registers.  Every horizontal neighbour comes from
+// the adjacent lane, so the wave reads only its own 64 columns: stage-1
+// values are exact on lanes 1..62 (lane 0 lacks its west Hz, lane 63 its
+// east Ey), stage-2 values on lanes 2..61, which own their columns.  Stage-1
+// rows [j0-2, j1] feed stage-2 rows [j0-1, j1), so only step n+2 goes to
+// memory: 26 bytes per cell for two steps instead of 52.
 //
 // Mode 0: a far tile, whose reads never reach a reduced region or its ring:
 //   two steps into f2.
-// Mode 1: a tile near a region, first launch: stage 1 only, stored for all
-//   64 lanes and rows [j0-1, j1] (the halo the second launch reads) into the
+// Mode 1: a tile near a region, first launch: stage 1 only, stored for lanes
+//   1..62 and rows [j0-1, j1] (the halo the second launch reads) into the
 //   step-(n+1) set, except interface edges (written by the coupling blocks).
 // Mode 2: a near tile, second launch: one step n+1 -> n+2 of its own cells.
 template <typename T>
-struct RowSet2 {
-  RowIn<T> c, w;
-  T eyE;
+struct RowIn2 {
+  T h, ex1, ey0, al, be;
 };
 
 // stage-1 result of one row, kept for stage 2
@@ -498,7 +498,7 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
   T* eyo = kTwo ? p.f2[2] : fld(p, par ^ 1, 2);
   const int lane = threadIdx.x & (kWave - 1);
   const int iw = (tile % p.tiles_x2) * kOwned2;
-  const int c = iw - 1 + lane;
+  const int c = iw - 2 + lane;
   const int nx = p.nx, ny = p.ny, P = p.pitch;
   // stage-1 rows [rs, re]
   const int rs = Mode == 2 ? max(j0 - 1, 0) : max(j0 - 2, 0);
@@ -511,13 +511,12 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
   const T* be = p.be;
   const T* ex_up = ex + P;
   const bool in = c >= 0 && c < nx;
-  const bool has_left = lane == 0 && c >= 1;
-  const bool own = in && lane >= 1 && lane <= kWave - 2;
-  // sources of both steps touching columns [iw-2, iw+63) x rows [rs, re]
+  const bool own = in && lane >= 2 && lane <= kWave - 3;
+  // sources of both steps touching columns [iw-2, iw+62) x rows [rs, re]
   bool any_src = false;
   for (int s = 0; s < p.nsrc; ++s) {
     const Src<T>& S = p.src[s];
-    any_src |= S.i0 < iw + kWave - 1 && S.i1 > iw - 2 && S.j0 <= re && S.j1 > rs;
+    any_src |= S.i0 < iw + kWave - 2 && S.i1 > iw - 2 && S.j0 <= re && S.j1 > rs;
   }
   T sinc[kMaxSrc], sinc2[kMaxSrc];
 #pragma unroll
@@ -533,48 +532,29 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
         if constexpr (kTwo) sinc2[s] = p.src[s].incr[n + 1];
       }
   }
-  // Loaded columns: the lane's own (clamped into the row: lanes outside the
-  // grid read a valid address and their values are never used), the west
-  // column iw-2 (read by every lane at one wave-uniform address, used by
-  // lane 0) and the east column iw+63 (used by lane 63 when it exists).
+  // the lane's column, clamped into the row: lanes outside the grid read a
+  // valid address and their values are never used
   const int cl = min(max(c, 0), P - 1);
-  const int wl = max(iw - 2, 0);
-  const bool east = iw + kWave - 1 < nx;
-  const int el = min(iw + kWave - 1, P - 1);
-  const uint32_t dW = (uint32_t)(cl - wl) * ts;
-  const uint32_t dEp = (uint32_t)max(el - cl, 0) * ts;
-  const uint32_t dEn = (uint32_t)max(cl - el, 0) * ts;
   uint32_t ob = ((uint32_t)rs * (uint32_t)P + (uint32_t)cl) * ts;
   const uint16_t* mi = p.mi;
   const MatPair<T>* mt = p.mt;
-  auto fetch = [&](uint32_t o, bool up, uint32_t id, uint32_t idw) {
-    RowSet2<T> r;
-    const T* exr = up ? ex_up : ex;
-    const uint32_t ow = o - dW;
-    r.c.h = ld(hz, o);
-    r.c.ex1 = ld(exr, o);
-    r.c.ey0 = ld(ey, o);
-    r.w.h = ld(hz, ow);
-    r.w.ex1 = ld(exr, ow);
-    r.w.ey0 = ld(ey, ow);
-    r.eyE = ld(ey, o + dEp - dEn);
+  auto fetch = [&](uint32_t o, bool up, uint32_t id) {
+    RowIn2<T> r;
+    r.h = ld(hz, o);
+    r.ex1 = ld(up ? ex_up : ex, o);
+    r.ey0 = ld(ey, o);
     if constexpr (MIdx) {
-      const MatPair<T> m = mt[id], mw = mt[idw];
-      r.c.al = m.a;
-      r.c.be = m.b;
-      r.w.al = mw.a;
-      r.w.be = mw.b;
+      const MatPair<T> m = mt[id];
+      r.al = m.a;
+      r.be = m.b;
     } else {
-      r.c.al = ld(al, o);
-      r.c.be = ld(be, o);
-      r.w.al = ld(al, ow);
-      r.w.be = ld(be, ow);
+      r.al = ld(al, o);
+      r.be = ld(be, o);
     }
     return r;
   };
   auto orow = [&](int r) { return ob + (uint32_t)(r - rs) * row_b; };
   T ex_c = ld(ex, ob);
-  T exl_c = ld(ex, ob - dW);  // used by lane 0 only when the west column exists
   T hn_prev = T(0), a_prev = T(0), b_prev = T(0);
   Stage1<T> prv1{};
   T h2_prev = T(0);
@@ -601,34 +581,18 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
     h2_prev = h2;
   };
   // stage 1 for row r from its loaded data
-  auto compute = [&](int r, const RowSet2<T>& cs) {
-    RowIn<T> cur = cs.c;
-    RowIn<T> cul = cs.w;
-    if (r + 1 >= ny) {
-      cur.ex1 = T(0);
-      cul.ex1 = T(0);
-    }
+  auto compute = [&](int r, const RowIn2<T>& cs) {
+    RowIn2<T> cur = cs;
+    if (r + 1 >= ny) cur.ex1 = T(0);
     T ey1 = lane_next(cur.ey0);
-    if (lane == kWave - 1) ey1 = east ? cs.eyE : T(0);
     if (c + 1 >= nx) ey1 = T(0);
     const bool act = in && cur.al > T(0);
     T hn = hz_update(cur.h, ex_c, cur.ex1, cur.ey0, ey1, chdy, chdx);
     if (any_src) hn += src_sum(p, sinc, 0, c, r);
     if (!act) hn = T(0);
-    T hnl = lane_prev(hn);
-    T all = lane_prev(cur.al);
-    T bel = lane_prev(cur.be);
-    if (lane == 0) {
-      hnl = T(0);
-      all = cul.al;
-      bel = cul.be;
-      if (has_left) {
-        hnl = hz_update(cul.h, exl_c, cul.ex1, cul.ey0, cur.ey0, chdy, chdx);
-        if (any_src) hnl += src_sum(p, sinc, 0, c - 1, r);
-        if (!(all > T(0))) hnl = T(0);
-        exl_c = cul.ex1;
-      }
-    }
+    const T hnl = lane_prev(hn);
+    const T all = lane_prev(cur.al);
+    const T bel = lane_prev(cur.be);
     Stage1<T> o;
     o.act = act;
     o.ax = r >= 1 && act && a_prev > T(0);
@@ -647,7 +611,7 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
     o.ixf = (cur.al < T(0)) != (a_prev < T(0));
     o.iyf = (cur.al < T(0)) != (all < T(0));
     if constexpr (Mode != 0) {
-      const bool st_lane = Mode == 1 ? in : own;
+      const bool st_lane = Mode == 1 ? in && lane >= 1 && lane <= kWave - 2 : own;
       if (st_lane && r >= (Mode == 1 ? r2lo : j0)) {
         st(hzo, ob, hn);
         if (!o.ixf) st(exo, ob, exn);
@@ -665,43 +629,37 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
   // software pipeline as in stencil_rows: rows r+1 and r+2 in flight while
   // row r is computed; material indices two rows further ahead
   const int rend = re + 1;
-  uint32_t idA = 0, idB = 0, idAw = 0, idBw = 0;
-  RowSet2<T> n1, n2;
+  uint32_t idA = 0, idB = 0;
+  RowIn2<T> n1, n2;
   if constexpr (MIdx) {
     const uint32_t o0 = orow(rs), o1 = orow(min(rs + 1, re));
-    const uint32_t oA = orow(min(rs + 2, re)), oB = orow(min(rs + 3, re));
-    const uint32_t i0 = mat_id<T>(mi, o0), i0w = mat_id<T>(mi, o0 - dW);
-    const uint32_t i1 = mat_id<T>(mi, o1), i1w = mat_id<T>(mi, o1 - dW);
-    idA = mat_id<T>(mi, oA);
-    idAw = mat_id<T>(mi, oA - dW);
-    idB = mat_id<T>(mi, oB);
-    idBw = mat_id<T>(mi, oB - dW);
-    n1 = fetch(o0, rs + 1 < ny, i0, i0w);
-    n2 = fetch(o1, rs + 2 < ny, i1, i1w);
+    const uint32_t i0 = mat_id<T>(mi, o0), i1 = mat_id<T>(mi, o1);
+    idA = mat_id<T>(mi, orow(min(rs + 2, re)));
+    idB = mat_id<T>(mi, orow(min(rs + 3, re)));
+    n1 = fetch(o0, rs + 1 < ny, i0);
+    n2 = fetch(o1, rs + 2 < ny, i1);
   } else {
-    n1 = fetch(orow(rs), rs + 1 < ny, 0, 0);
-    n2 = fetch(orow(min(rs + 1, re)), rs + 2 < ny, 0, 0);
+    n1 = fetch(orow(rs), rs + 1 < ny, 0);
+    n2 = fetch(orow(min(rs + 1, re)), rs + 2 < ny, 0);
   }
   int r = rs;
   for (; r + 2 < rend; ++r, ob += row_b) {
-    const RowSet2<T> cur = n1;
+    const RowIn2<T> cur = n1;
     n1 = n2;
     const uint32_t o3 = ob + 2 * row_b;
     if constexpr (MIdx) {
       const uint32_t oC = o3 + (r + 3 < rend ? row_b : 0u) + (r + 4 < rend ? row_b : 0u);
-      const uint32_t idC = mat_id<T>(mi, oC), idCw = mat_id<T>(mi, oC - dW);
-      n2 = fetch(o3, r + 3 < ny, idA, idAw);
+      const uint32_t idC = mat_id<T>(mi, oC);
+      n2 = fetch(o3, r + 3 < ny, idA);
       idA = idB;
-      idAw = idBw;
       idB = idC;
-      idBw = idCw;
     } else {
-      n2 = fetch(o3, r + 3 < ny, 0, 0);
+      n2 = fetch(o3, r + 3 < ny, 0);
     }
     compute(r, cur);
   }
   for (; r < rend; ++r, ob += row_b) {
-    const RowSet2<T> cur = n1;
+    const RowIn2<T> cur = n1;
     n1 = n2;
     compute(r, cur);
   }
