@@ -50,6 +50,32 @@ def step_bytes(prob, material_mode=1):
     cells = prob.nx * prob.ny
     mats = sum(4 * (s.q + s.n_ports) ** 2 for s in prob.roms)
     return (FIELD_BYTES_PER_CELL_F32 + MATERIAL_BYTES_PER_CELL_F32[material_mode]) * cells + mats
+
+
+def pair_bytes(prob, material_mode=1):
+    """Algorithmic bytes of one two-step pair of launches (FP32): the fields
+    read and written once and the material read once for two steps, the
+    update matrices read once per step."""
+    cells = prob.nx * prob.ny
+    mats = sum(4 * (s.q + s.n_ports) ** 2 for s in prob.roms)
+    return (FIELD_BYTES_PER_CELL_F32 + MATERIAL_BYTES_PER_CELL_F32[material_mode]) * cells + 2 * mats
+
+
+def stencil_roofline(prob, steps, ev_ms, mmode, tb, seg):
+    """Algorithmic bytes per unit over the unit's average duration from the
+    timed region's HIP events: the unit is one step launch, or with two
+    steps per pass one pair of launches."""
+    m = "true" if mmode else "false"
+    if tb:
+        units = steps / 2  # an odd step count ends with one single launch
+        alg = pair_bytes(prob, mmode)
+        kernel = f"step2_kernel<float,{seg},{m},false> + step2_kernel<float,{seg},{m},true> (one pair = two steps)"
+    else:
+        units = steps
+        alg = step_bytes(prob, mmode)
+        kernel = f"step_kernel<float,{seg},false,{m}>"
+    avg_s = ev_ms / 1e3 / units
+    return alg, avg_s, units, kernel
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "stencil_c2_2048_hbm_counters.json")
 
 
@@ -66,18 +92,19 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(material_mode):
-    """HBM bytes per stencil launch from committed rocprofv3 counter runs,
-    if they were taken on the current kernel source in the same material
-    mode (else None)."""
+def measured_traffic(material_mode, tb=False):
+    """HBM bytes per unit (step launch, or two-step pair) from committed
+    rocprofv3 counter runs, if they were taken on the current kernel source
+    in the same material and stepping mode (else None)."""
     try:
         with open(COUNTERS_FILE) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("material_mode", 0) != material_mode:
+    if (d.get("kernel_source_hash") != kernel_source_hash() or d.get("material_mode", 0) != material_mode
+            or bool(d.get("time_blocking", 0)) != bool(tb)):
         return None
-    return d.get("bytes_per_launch")
+    return d.get("bytes_per_unit", d.get("bytes_per_launch"))
 
 
 def cpu_baseline(prob, nsteps):
@@ -236,18 +263,18 @@ def bench_hbm_resident(n=8192, steps=400, warmup=50, log=None):
     with Simulation(prob, roms) as s:
         seg = s.get_tiling()
         mmode, nmat = s.material_mode()
+        tb = s.time_blocking()
         s.set_graph(min(steps, 200))
         s.run(warmup)
         t, ev = _timed(s.stream, lambda: s.run(steps))
     cells = prob.nx * prob.ny
-    alg = step_bytes(prob, mmode)
-    avg = ev / 1e3 / steps
+    alg, avg, units, kernel = stencil_roofline(prob, steps, ev, mmode, tb, seg)
     return {"workload": f"random media {n}x{n}, 16 models (q 32-96), FP32, {steps} steps",
             "value": round(cells * steps / t / 1e6, 1), "unit": "Mcell-updates/s",
-            "ms_per_step": round(t * 1e3 / steps, 4),
-            "kernel": f"step_kernel<float,{seg},false,{'true' if mmode else 'false'}>",
+            "ms_per_step": round(t * 1e3 / steps, 4), "time_blocking": tb,
+            "kernel": kernel,
             "material": {"mode": "table" if mmode else "per-cell", "entries": nmat},
-            "bytes_per_launch": alg, "achieved_GBps": round(alg / avg / 1e9, 1),
+            "bytes_per_unit": alg, "achieved_GBps": round(alg / avg / 1e9, 1),
             "frac_of_8TBps": round(alg / avg / 1e9 / PEAK_HBM_GBS, 4)}
 
 
@@ -453,6 +480,8 @@ def main():
     ap.add_argument("--copy-ceiling", action="store_true", help="only measure device copy rates and exit")
     ap.add_argument("--material-mode", type=int, choices=[0, 1], default=None,
                     help="0: per-cell material arrays, 1: 16-bit index + table (default: table when available)")
+    ap.add_argument("--time-blocking", type=int, choices=[0, 1], default=1,
+                    help="two steps per pass over the grid (1, default) or one launch per step (0)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -499,6 +528,8 @@ def main():
     if args.material_mode is not None:
         sim.set_material_mode(args.material_mode)
     mmode, nmat = sim.material_mode()
+    sim.set_time_blocking(bool(args.time_blocking))
+    tb = sim.time_blocking()
     sim.set_graph(200)   # steps replayed from captured graphs (the production path)
     sim.run(args.warmup)
     torch.cuda.synchronize()
@@ -522,17 +553,17 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     cells = prob.nx * prob.ny
     value = cells * args.steps / elapsed / 1e6
-    # one launch per step; the region's event time also holds the run's
-    # closing probe-flush and tick launches (~8 us over all K steps)
-    st_avg_s = ev_ms / args.steps / 1e3
-    alg_bytes = step_bytes(prob, mmode)
+    # one launch per step, or one pair of launches per two steps; the
+    # region's event time also holds the run's closing probe-flush and tick
+    # launches (~8 us over all K steps)
+    alg_bytes, st_avg_s, units, kernel = stencil_roofline(prob, args.steps, ev_ms, mmode, tb, seg)
     achieved = alg_bytes / st_avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(mmode),
-                "kernel": f"step_kernel<float,{seg},false,{'true' if mmode else 'false'}>",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(mmode, tb),
+                "kernel": kernel, "time_blocking": tb,
                 "material": {"mode": "table" if mmode else "per-cell", "entries": nmat},
-                "bytes_per_launch": alg_bytes,
-                "avg_launch_us": round(st_avg_s * 1e6, 3), "launches": args.steps}
+                "bytes_per_unit": alg_bytes, "unit_of_work": "two-step pair" if tb else "step launch",
+                "avg_unit_us": round(st_avg_s * 1e6, 3), "units": units}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
@@ -540,7 +571,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"C2 random media {prob.nx}x{prob.ny}, 16 embedded 32x32-cell "
                                f"models (r=4, q in 32/48/64/96), dt=0.95 coarse CFL, "
-                               f"{args.steps} timed steps, 64 probes",
+                               f"{args.steps} timed steps, 64 probes"
+                               + (", two steps per pass" if tb else ""),
                    "nx": prob.nx, "ny": prob.ny, "n_models": len(prob.roms),
                    "orders": sorted({s.q for s in prob.roms}), "parallelism": "single GPU"},
         "roofline": roofline,

@@ -318,7 +318,8 @@ int fdtd_rom_set_graph(fdtd_rom_sim* sim, int32_t batch);
  * grid whose reads stay clear of the regions by two steps at once, holding
  * step n+1 in registers; the tiles near a region advance one step.  The
  * second launch advances the near tiles and the coupling by the second
- * step.  An odd last step runs as a single launch.  The arithmetic per cell
+ * step.  An odd last step runs as a single launch.  On by default for grids
+ * without absorbing layers (batches always step singly).  The arithmetic per cell
  * is that of the single-step launch, so results are identical; far cells
  * move their fields through memory once per two steps.  Graph batches
  * (fdtd_rom_set_graph) are rounded down to a multiple of 4 steps.

@@ -1112,6 +1112,7 @@ int fdtd_rom_create(const fdtd_problem* prob, void* dev_workspace, size_t ws_byt
       rc = (s->dtype == FDTD_F32) ? setup_device<float>(s, prob, inside)
                                   : setup_device<double>(s, prob, inside);
     if (rc == FDTD_OK) set_tiling(s, default_tiling(s->nx, s->ny, (int)L.tsize));
+    s->tb = L.tb_ok;  // two steps per pass wherever the grid allows it
     if (rc != FDTD_OK) {
       delete s;
       return rc;
