@@ -242,6 +242,9 @@ int fdtd_rom_batch_create(const fdtd_problem* probs, int32_t B, void* dev_worksp
         rc = fail(rc, "instance %d: %s", b, fdtd_rom_last_error());
         break;
       }
+      // a batch advances every instance by one launch per step
+      s->tb = false;
+      set_tiling(s, default_tiling(s->nx, s->ny, (int)s->L.tsize));
       bt->sims.push_back(s);
     }
     int ctrl[kCtrlInts] = {0, 0, 0, 0};

@@ -673,7 +673,7 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
 // [j0, j0+SEG).  Second launch: the near tiles' single step is short work
 // bound by the latency of each wave's row chain, so every near tile is
 // split over kNearSplit workgroups, each wave taking SEG/kNearSplit rows.
-constexpr int kNearSplit = 4;
+constexpr int kNearSplit = 8;
 
 template <typename T, int SEG, bool MIdx, bool Second>
 __device__ __forceinline__ void stencil2_tile(const StepParams<T>& p, int t, int n) {

@@ -805,6 +805,15 @@ int fdtd::default_tiling(int nx, int ny, int ts) {
   return 4;
 }
 
+// Default rows per wave of the two-step launches: their waves carry twice
+// the arithmetic per row and 60 owned columns, and 8 rows measured best from
+// 2048^2 (cache-resident) to 8192^2 (HBM-bound); small grids take 4 rows so
+// that the launch still holds >= 4096 waves.
+int fdtd::default_tiling2(int nx, int ny) {
+  const long tx = (nx + kOwned2 - 1) / kOwned2;
+  return tx * ((ny + 7) / 8) >= 4096 ? 8 : 4;
+}
+
 // a stencil workgroup covers 64 columns x (4 waves x seg rows)
 void fdtd::set_tiling(fdtd_rom_sim* s, int seg) {
   s->seg = seg;
@@ -1111,8 +1120,9 @@ int fdtd_rom_create(const fdtd_problem* prob, void* dev_workspace, size_t ws_byt
     if (rc == FDTD_OK)
       rc = (s->dtype == FDTD_F32) ? setup_device<float>(s, prob, inside)
                                   : setup_device<double>(s, prob, inside);
-    if (rc == FDTD_OK) set_tiling(s, default_tiling(s->nx, s->ny, (int)L.tsize));
     s->tb = L.tb_ok;  // two steps per pass wherever the grid allows it
+    if (rc == FDTD_OK)
+      set_tiling(s, s->tb ? default_tiling2(s->nx, s->ny) : default_tiling(s->nx, s->ny, (int)L.tsize));
     if (rc != FDTD_OK) {
       delete s;
       return rc;

@@ -116,5 +116,7 @@ int run_steps_any(fdtd_rom_sim* s, int nsteps);
 void set_tiling(fdtd_rom_sim* s, int seg);
 // Rows per stencil wave a new handle starts with (grid size, element bytes).
 int default_tiling(int nx, int ny, int ts);
+// The same for the two-step launches.
+int default_tiling2(int nx, int ny);
 
 }  // namespace fdtd
