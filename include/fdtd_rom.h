@@ -381,7 +381,8 @@ int fdtd_rom_adjoint(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int3
  *     instance b.  Synchronise.
  *   batch_set_tiling: rows per stencil wave (4, 8, 16, 32) of instance b, or of
  *     every instance for b = -1 (the autotuner's knob).
- *   batch_set_graph: steps per captured graph (0 = direct launches). */
+ *   batch_set_graph: steps per captured graph (0 = direct launches; with
+ *     two steps per pass rounded down to a multiple of 4). */
 typedef struct fdtd_rom_batch fdtd_rom_batch; /* opaque, owned by the library */
 int fdtd_rom_batch_workspace_size(const fdtd_problem* probs, int32_t B, size_t* bytes);
 int fdtd_rom_batch_create(const fdtd_problem* probs, int32_t B, void* dev_workspace,
@@ -394,6 +395,11 @@ int fdtd_rom_batch_read_field(const fdtd_rom_batch* batch, int32_t b, int32_t co
                               double* host_out);
 int fdtd_rom_batch_set_tiling(fdtd_rom_batch* batch, int32_t b, int32_t seg);
 int fdtd_rom_batch_set_graph(fdtd_rom_batch* batch, int32_t batch_steps);
+/* Two steps per pass for every instance (as fdtd_rom_set_time_blocking, all
+ * instances in lockstep): on by default when no instance has absorbing
+ * layers; FDTD_EINVAL for on = 1 otherwise or a value other than 0/1. */
+int fdtd_rom_batch_set_time_blocking(fdtd_rom_batch* batch, int32_t on);
+int fdtd_rom_batch_get_time_blocking(const fdtd_rom_batch* batch, int32_t* on);
 void fdtd_rom_batch_destroy(fdtd_rom_batch* batch);
 
 /* Release the handle (the workspace stays the caller's). */

@@ -54,6 +54,12 @@ class Batch:
     def set_graph(self, steps):
         capi.fdtd_rom_batch_set_graph(self.h, steps)
 
+    def set_time_blocking(self, on):
+        capi.fdtd_rom_batch_set_time_blocking(self.h, on)
+
+    def time_blocking(self):
+        return capi.fdtd_rom_batch_get_time_blocking(self.h)
+
     def close(self):
         if getattr(self, "h", None) is not None:
             self.stream.synchronize()

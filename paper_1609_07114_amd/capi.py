@@ -99,6 +99,8 @@ _SIGS = {
     "fdtd_rom_set_material_mode": (C.c_int, [C.c_void_p, C.c_int32]),
     "fdtd_rom_get_material_mode": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fdtd_rom_set_time_blocking": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_batch_set_time_blocking": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_batch_get_time_blocking": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fdtd_rom_get_time_blocking": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fdtd_rom_adjoint_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
                                                   C.POINTER(C.c_size_t)]),
@@ -348,6 +350,16 @@ def fdtd_rom_set_time_blocking(h, on: bool):
 def fdtd_rom_get_time_blocking(h) -> bool:
     v = C.c_int32(0)
     _check(lib().fdtd_rom_get_time_blocking(h, C.byref(v)))
+    return bool(v.value)
+
+
+def fdtd_rom_batch_set_time_blocking(h, on: bool):
+    _check(lib().fdtd_rom_batch_set_time_blocking(h, 1 if on else 0))
+
+
+def fdtd_rom_batch_get_time_blocking(h) -> bool:
+    v = C.c_int32(0)
+    _check(lib().fdtd_rom_batch_get_time_blocking(h, C.byref(v)))
     return bool(v.value)
 
 

@@ -132,6 +132,7 @@ struct StepParams {
 };
 
 constexpr int kOwned2 = kWave - 4;  // columns a two-step wave owns (lanes 2..61)
+constexpr int kNearSplit = 8;       // workgroups per near tile in the second launch of a pair
 
 // One workgroup of the batched step launch: instance `inst`, role `kind`
 // (0 coupling block idx of that instance, 1 stencil tile idx, 2 probe
@@ -166,6 +167,11 @@ template <typename T>
 hipError_t launch_batch_step(const StepParams<T>* descs, const BatchRef* table, int nblocks,
                              const int* ctrl, int step_off, size_t smem, bool layers, bool midx,
                              hipStream_t s);
+// the pair of batched launches advancing steps n, n+1 of every instance
+template <typename T>
+hipError_t launch_batch_step2(const StepParams<T>* da, const BatchRef* ta, int na, const StepParams<T>* db,
+                              const BatchRef* tb, int nb, const int* ctrl, int step_off, size_t smem, bool midx,
+                              hipStream_t s);
 template <typename T>
 hipError_t launch_batch_probe_flush(const StepParams<T>* descs, int ninst, const int* ctrl,
                                     int step_off, hipStream_t s);

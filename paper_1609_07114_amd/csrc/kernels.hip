@@ -673,7 +673,6 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
 // [j0, j0+SEG).  Second launch: the near tiles' single step is short work
 // bound by the latency of each wave's row chain, so every near tile is
 // split over kNearSplit workgroups, each wave taking SEG/kNearSplit rows.
-constexpr int kNearSplit = 8;
 
 template <typename T, int SEG, bool MIdx, bool Second>
 __device__ __forceinline__ void stencil2_tile(const StepParams<T>& p, int t, int n) {
@@ -960,6 +959,22 @@ __device__ __forceinline__ T probe_next(const StepParams<T>& p, int t, int n) {
   return v;
 }
 
+// Probe block of a pair launch: the first records row n-1 (the step-n set)
+// and, for probes of far tiles, row n formed from step n; the second records
+// row n of the near probes from its step-n set (step n+1 of the pair).
+template <typename T, bool Second>
+__device__ __forceinline__ void pair_probes(const StepParams<T>& p, int n) {
+  if constexpr (Second) {
+    const int par = n & 1;
+    for (int k = threadIdx.x; k < p.nprobes; k += kBlock)
+      if (p.probe_near[k]) p.probe_buf[(size_t)(n - 1) * p.nprobes + k] = fld(p, par, p.probe_comp[k])[p.probe_off[k]];
+  } else {
+    record_probes(p, n - 1);
+    for (int k = threadIdx.x; k < p.nprobes; k += kBlock)
+      if (!p.probe_near[k]) p.probe_buf[(size_t)n * p.nprobes + k] = probe_next(p, k, n);
+  }
+}
+
 // The pair of launches that advances steps n and n+1 (time blocking):
 //   first (Second = false): coupling blocks of step n (interface E^{n+1} into
 //     the step-(n+1) set), every tile (far: two steps into f2; near: one step
@@ -991,15 +1006,7 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const StepParams<T> p) {
     stencil2_tile<T, SEG, MIdx, Second>(p, t, n);
     return;
   }
-  if constexpr (Second) {
-    const int par = n & 1;  // the step-n set of this launch (step n+1 of the pair)
-    for (int k = threadIdx.x; k < p.nprobes; k += kBlock)
-      if (p.probe_near[k]) p.probe_buf[(size_t)(n - 1) * p.nprobes + k] = fld(p, par, p.probe_comp[k])[p.probe_off[k]];
-  } else {
-    record_probes(p, n - 1);
-    for (int k = threadIdx.x; k < p.nprobes; k += kBlock)
-      if (!p.probe_near[k]) p.probe_buf[(size_t)n * p.nprobes + k] = probe_next(p, k, n);
-  }
+  pair_probes<T, Second>(p, n);
 }
 
 template <typename T>
@@ -1052,6 +1059,56 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
 batch_probe_kernel(const StepParams<T>* __restrict__ descs, const int* __restrict__ ctrl, int step_off) {
   record_probes(descs[blockIdx.x], ctrl[0] + step_off - 1);
+}
+
+// Batched pair launch: as batch_step_kernel, with the roles of the pair
+// launches (tiles of kind 1 are two-step tiles of the first launch or
+// near-tile pieces of the second; kind 2 is the pair's probe block).
+template <typename T, bool MIdx, bool Second>
+__global__ void __launch_bounds__(kBlock)
+batch_step2_kernel(const StepParams<T>* __restrict__ descs, const BatchRef* __restrict__ table,
+                   const int* __restrict__ ctrl, int step_off) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BatchRef r = table[blockIdx.x];
+  if (r.kind == 3) return;
+  const StepParams<T>& p = descs[r.inst];
+  const int n = ctrl[0] + step_off;
+  if (r.kind == 0) {
+    const RowBlock rb = p.blocks[r.idx];
+    if constexpr (sizeof(T) == 4) {
+      if (rb.kind == 1) {
+        coupling_gemm(p, rb, n, reinterpret_cast<float*>(smem));
+        return;
+      }
+    }
+    coupling_rows(p, rb, n, reinterpret_cast<T*>(smem));
+    return;
+  }
+  if (r.kind == 1) {
+    switch (p.seg) {
+      case 4: stencil2_tile<T, 4, MIdx, Second>(p, r.idx, n); break;
+      case 16: stencil2_tile<T, 16, MIdx, Second>(p, r.idx, n); break;
+      case 32: stencil2_tile<T, 32, MIdx, Second>(p, r.idx, n); break;
+      default: stencil2_tile<T, 8, MIdx, Second>(p, r.idx, n); break;
+    }
+    return;
+  }
+  pair_probes<T, Second>(p, n);
+}
+
+template <typename T>
+hipError_t launch_batch_step2(const StepParams<T>* da, const BatchRef* ta, int na, const StepParams<T>* db,
+                              const BatchRef* tb, int nb, const int* ctrl, int step_off, size_t smem, bool midx,
+                              hipStream_t s) {
+  const dim3 blk(kBlock);
+  if (midx) {
+    hipLaunchKernelGGL((batch_step2_kernel<T, true, false>), dim3(na), blk, smem, s, da, ta, ctrl, step_off);
+    hipLaunchKernelGGL((batch_step2_kernel<T, true, true>), dim3(nb), blk, smem, s, db, tb, ctrl, step_off + 1);
+  } else {
+    hipLaunchKernelGGL((batch_step2_kernel<T, false, false>), dim3(na), blk, smem, s, da, ta, ctrl, step_off);
+    hipLaunchKernelGGL((batch_step2_kernel<T, false, true>), dim3(nb), blk, smem, s, db, tb, ctrl, step_off + 1);
+  }
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -1215,6 +1272,11 @@ template hipError_t launch_batch_step<float>(const StepParams<float>*, const Bat
                                              int, size_t, bool, bool, hipStream_t);
 template hipError_t launch_batch_step<double>(const StepParams<double>*, const BatchRef*, int,
                                               const int*, int, size_t, bool, bool, hipStream_t);
+template hipError_t launch_batch_step2<float>(const StepParams<float>*, const BatchRef*, int, const StepParams<float>*,
+                                              const BatchRef*, int, const int*, int, size_t, bool, hipStream_t);
+template hipError_t launch_batch_step2<double>(const StepParams<double>*, const BatchRef*, int,
+                                               const StepParams<double>*, const BatchRef*, int, const int*, int,
+                                               size_t, bool, hipStream_t);
 template hipError_t launch_batch_probe_flush<float>(const StepParams<float>*, int, const int*, int,
                                                     hipStream_t);
 template hipError_t launch_batch_probe_flush<double>(const StepParams<double>*, int, const int*, int,

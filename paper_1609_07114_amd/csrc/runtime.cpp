@@ -828,25 +828,6 @@ void fdtd::set_tiling(fdtd_rom_sim* s, int seg) {
   s->sp_d.seg = seg;
 }
 
-namespace {
-
-int ev_pair(fdtd_rom_sim* s, std::vector<std::pair<hipEvent_t, hipEvent_t>>& pool, size_t& used,
-            hipEvent_t& a, hipEvent_t& b) {
-  if (used >= pool.size()) {
-    hipEvent_t x, y;
-    // timing-only events: no system-scope release/acquire (no cache flush
-    // between the launches being timed)
-    if (hipEventCreateWithFlags(&x, hipEventDisableSystemFence) != hipSuccess ||
-        hipEventCreateWithFlags(&y, hipEventDisableSystemFence) != hipSuccess)
-      return fail(FDTD_EDEVICE, "hipEventCreate failed");
-    pool.emplace_back(x, y);
-  }
-  a = pool[used].first;
-  b = pool[used].second;
-  ++used;
-  return FDTD_OK;
-}
-
 // Tile roles of the two-step launches for the handle's tiling.  A tile of
 // kOwned2 columns x 4 SEG rows is far when everything its two-step sweep
 // reads (columns iw-2 .. iw+63, rows j0-2 .. j1+1, widened by one) stays
@@ -855,7 +836,7 @@ int ev_pair(fdtd_rom_sim* s, std::vector<std::pair<hipEvent_t, hipEvent_t>>& poo
 // cell to spare); otherwise it is near.  A probe is near when the tile that
 // owns its cell is.  Uploaded synchronously (never while capturing).
 template <typename T>
-int prepare_tb(fdtd_rom_sim* s) {
+int fdtd::prepare_tb(fdtd_rom_sim* s) {
   const Layout& L = s->L;
   if (s->tb_seg == s->seg) return FDTD_OK;
   const int rows = (kBlock / kWave) * s->seg;
@@ -898,6 +879,28 @@ int prepare_tb(fdtd_rom_sim* s) {
   fill(s->sp_f);
   fill(s->sp_d);
   s->tb_seg = s->seg;
+  return FDTD_OK;
+}
+
+template int fdtd::prepare_tb<float>(fdtd_rom_sim*);
+template int fdtd::prepare_tb<double>(fdtd_rom_sim*);
+
+namespace {
+
+int ev_pair(fdtd_rom_sim* s, std::vector<std::pair<hipEvent_t, hipEvent_t>>& pool, size_t& used,
+            hipEvent_t& a, hipEvent_t& b) {
+  if (used >= pool.size()) {
+    hipEvent_t x, y;
+    // timing-only events: no system-scope release/acquire (no cache flush
+    // between the launches being timed)
+    if (hipEventCreateWithFlags(&x, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&y, hipEventDisableSystemFence) != hipSuccess)
+      return fail(FDTD_EDEVICE, "hipEventCreate failed");
+    pool.emplace_back(x, y);
+  }
+  a = pool[used].first;
+  b = pool[used].second;
+  ++used;
   return FDTD_OK;
 }
 

@@ -118,5 +118,9 @@ void set_tiling(fdtd_rom_sim* s, int seg);
 int default_tiling(int nx, int ny, int ts);
 // The same for the two-step launches.
 int default_tiling2(int nx, int ny);
+// Tile roles of the two-step launches for the handle's current tiling,
+// uploaded synchronously on its stream (a no-op when already current).
+template <typename T>
+int prepare_tb(fdtd_rom_sim* s);
 
 }  // namespace fdtd

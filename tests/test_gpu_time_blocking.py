@@ -168,3 +168,54 @@ def test_layers_refuse_two_steps():
         with pytest.raises(capi.FdtdError):
             s.set_time_blocking(True)
         assert not s.time_blocking()
+
+
+def _batch_run(probs, models, tb, pieces, graph=0, seg=None):
+    from paper_1609_07114_amd.batch import Batch
+    with Batch(probs, models, dtype="f32") as bt:
+        if seg:
+            bt.set_tiling(-1, seg)
+        bt.set_graph(graph)
+        bt.set_time_blocking(tb)
+        assert bt.time_blocking() == tb
+        for k in pieces:
+            bt.run(k)
+        return [bt.probes(b) for b in range(len(probs))], [[bt.field(b, c) for c in range(3)] for b in range(len(probs))]
+
+
+@pytest.fixture(scope="module")
+def mix():
+    probs = [W.random_problem(81 + k, nx, ny, 130, nroms=nr, block=(5, 4), r=2, q=10, dtype="f32",
+                              dt_frac_coarse=0.9, f_bw=3e9)
+             for k, (nx, ny, nr) in enumerate([(203, 150, 3), (64, 300, 1), (130, 41, 0), (250, 250, 4)])]
+    probs = [_with_all_probes(p, 5 + k) for k, p in enumerate(probs)]
+    return probs, [osim.build_roms(p) for p in probs]
+
+
+@pytest.mark.parametrize("graph,seg", [(0, None), (8, None), (64, 4), (0, 32)])
+def test_batch_two_step_equals_single_step(mix, graph, seg):
+    """Four uneven instances in one batch, pairs and odd pieces, graph
+    batches, every tiling: two steps per pass equals one launch per step,
+    and each instance equals its own handle."""
+    probs, models = mix
+    pieces = (3, 64, 1, 40, 22)
+    a = _batch_run(probs, models, True, pieces, graph, seg)
+    b = _batch_run(probs, models, False, pieces, graph, seg)
+    for k in range(len(probs)):
+        assert np.array_equal(a[0][k], b[0][k]), k
+        for c in range(3):
+            assert np.array_equal(a[1][k][c], b[1][k][c]), (k, c)
+    for k, p in enumerate(probs):
+        ref = _run(p, models[k], False, sum(pieces), dtype="f32")
+        assert np.array_equal(a[0][k], ref[0]), k
+
+
+def test_batch_with_layers_steps_singly():
+    from paper_1609_07114_amd.batch import Batch
+    p = W.random_problem(90, 60, 50, 20, nroms=0, dtype="f32", dt_frac_coarse=0.9)
+    q = W.random_problem(91, 60, 50, 20, nroms=0, dtype="f32", dt_frac_coarse=0.9)
+    q.pml = W.Pml(5, 5, 5, 5)
+    with Batch([p, q], [[], []]) as bt:
+        assert not bt.time_blocking()
+        with pytest.raises(capi.FdtdError):
+            bt.set_time_blocking(True)
