@@ -10,6 +10,7 @@
 //                  accumulation, streamed up the rows (one launch).
 // The forward coefficients are rebuilt exactly as the step kernel builds
 // them.
+#include <algorithm>
 #include <type_traits>
 
 #include "adjoint.hpp"
@@ -183,12 +184,10 @@ __device__ __forceinline__ void adj_rows(const AdjParams<T>& p) {
   const bool own = in && lane >= 2 && lane <= kWave - 2;
   const T chdy = p.chdy, chdx = p.chdx, k2dy = p.k2dy, k2dx = p.k2dx;
   const T idx = T(1.0 / p.dx), idy = T(1.0 / p.dy);  // reciprocal lengths
-  const double fa = p.fa;
+  const T fa = T(p.fa);
   // byte offset of (ic, js); only dereferenced where `in`
   uint32_t ob = ((uint32_t)js * (uint32_t)p.pitch + (uint32_t)ic) * ts;
   const uint32_t obj_b = (uint32_t)(p.obj_off * ts);
-  // byte offset of the same cell in the FP64 accumulators
-  auto o8 = [](uint32_t obt) -> uint32_t { return obt / ts * 8u; };
   // x profiles of this column and the east edge's (column ic+1)
   Prof<T> px{T(1), T(1), T(0), T(1), T(1), T(0)};
   T ikxE = T(1), axE = T(0);
@@ -203,7 +202,7 @@ __device__ __forceinline__ void adj_rows(const AdjParams<T>& p) {
   AdjRow<T> nxt = adj_load<T, PML>(p, ob + row_b, in && js + 1 < ny);
   T mu_p = T(0), ld_p = T(0);
   T gpa = T(0), gpb = T(0);             // previous row's cell: dJ/da, dJ/db of all edges but its north
-  double acc_e = 0.0, acc_s = 0.0;      // its accumulators, read one row ahead
+  T acc_e = T(0), acc_s = T(0);         // its accumulators, read one row ahead
   T cas = T(0), cbs = T(0), rs = T(0);  // current row's south edge
   adj_coef(cur.a + prv.a, cur.b + prv.b, k2dy, cas, cbs, rs);
 #pragma unroll
@@ -216,8 +215,8 @@ __device__ __forceinline__ void adj_rows(const AdjParams<T>& p) {
     const AdjRow<T> nn = adj_load<T, PML>(p, ob + 2 * row_b, in && up2);
     // this row's accumulators (this wave is their only writer), stored next row
     const bool acc_row = j >= j0 && own;
-    double nacc_e = ld(p.geps, acc_row ? o8(ob) : 0u);
-    double nacc_s = ld(p.gsig, acc_row ? o8(ob) : 0u);
+    T nacc_e = ld(p.ga_e, acc_row ? ob : 0u);
+    T nacc_s = ld(p.ga_s, acc_row ? ob : 0u);
     // horizontal neighbours
     const T aw = lane_prev(cur.a), bw = lane_prev(cur.b), hw = lane_prev(cur.h);
     const T ae = lane_next(cur.a), be_ = lane_next(cur.b), he = lane_next(cur.h);
@@ -308,8 +307,8 @@ __device__ __forceinline__ void adj_rows(const AdjParams<T>& p) {
       st(p.ley_out, ob, ic >= 1 ? lyo : T(0));
       // the previous row's cell is complete with its north edge (= this row's south)
       if (j - 1 >= j0) {
-        st(p.geps, o8(ob - row_b), acc_e + fa * (double)(gpa + gas));
-        st(p.gsig, o8(ob - row_b), acc_s + 0.25 * (double)(gpb + gbs));
+        st(p.ga_e, ob - row_b, acc_e + fa * (gpa + gas));
+        st(p.ga_s, ob - row_b, acc_s + T(0.25) * (gpb + gbs));
       }
     }
     gpa = gas + gaw + gae;
@@ -328,15 +327,15 @@ __device__ __forceinline__ void adj_rows(const AdjParams<T>& p) {
   }
   // last row's cell: add its north edge (the south edge of row j1)
   if (own && j1 - 1 >= j0) {
-    const uint32_t oc = o8(ob - row_b);
+    const uint32_t oc = ob - row_b;
     T gna = T(0), gnb = T(0);
     if (j1 < ny && prv.a > T(0) && cur.a > T(0)) {
       T dhn = cur.h - prv.h;
       if constexpr (PML) dhn = p.py[j1] * (cur.h - prv.h) + cur.pe;
       edge_grad(cur.lx, cur.e, dhn, cur.a + prv.a, cur.b + prv.b, rs, idy, gna, gnb);
     }
-    st(p.geps, oc, acc_e + fa * (double)(gpa + gna));
-    st(p.gsig, oc, acc_s + 0.25 * (double)(gpb + gnb));
+    st(p.ga_e, oc, acc_e + fa * (gpa + gna));
+    st(p.ga_s, oc, acc_s + T(0.25) * (gpb + gnb));
   }
 }
 
@@ -383,6 +382,19 @@ hipError_t launch_adjoint_step(const AdjParams<T>& p, size_t smem, hipStream_t s
     return hipGetLastError();
   };
   return p.pml ? go(std::true_type{}) : go(std::false_type{});
+}
+
+__global__ void __launch_bounds__(kBlock) adj_flush(float* __restrict__ a, double* __restrict__ g, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (size_t)gridDim.x * kBlock) {
+    g[k] += (double)a[k];
+    a[k] = 0.0f;
+  }
+}
+
+hipError_t launch_adjoint_flush(float* a, double* g, size_t n, hipStream_t s) {
+  const size_t nb = std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
+  if (nb > 0) hipLaunchKernelGGL(adj_flush, dim3((unsigned)nb), dim3(kBlock), 0, s, a, g, n);
+  return hipGetLastError();
 }
 
 template hipError_t launch_adjoint_step<float>(const AdjParams<float>&, size_t, hipStream_t);

@@ -25,8 +25,12 @@ struct AdjParams {
   const T* ey0;
   const T* al;       // per-cell eps0*eps_r/dt (negative inside regions)
   const T* be;       // per-cell sigma/2
-  double* geps;      // dJ/deps_r accumulator per cell (pitch layout)
-  double* gsig;      // dJ/dsigma accumulator per cell
+  // dJ/deps_r and dJ/dsigma accumulators per cell (pitch layout) in the
+  // run's precision: the FP64 totals themselves in FP64 runs; in FP32 runs
+  // per-segment sums, folded into the FP64 totals after every checkpoint
+  // segment (adj_flush)
+  T* ga_e;
+  T* ga_s;
   int nx, ny, pitch;
   int seg;           // rows per wave of the streamed reverse step (4, 8, 16)
   T chdy, chdx, k2dy, k2dx;
@@ -57,5 +61,7 @@ struct AdjParams {
 
 template <typename T>
 hipError_t launch_adjoint_step(const AdjParams<T>& p, size_t smem, hipStream_t s);
+// g[k] += a[k], a[k] = 0 for k < n (both accumulator pairs: a, g hold 2n)
+hipError_t launch_adjoint_flush(float* a, double* g, size_t n, hipStream_t s);
 
 }  // namespace fdtd

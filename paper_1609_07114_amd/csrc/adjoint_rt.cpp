@@ -36,7 +36,7 @@ struct AdjLayout {
   size_t set_bytes = 0, xs_bytes = 0;
   size_t slot_bytes = 0, lam_bytes = 0, ck_psi = 0;  // per slot / adjoint set; checkpoint's psi offset
   size_t off_ctrl = 0, off_ckpt = 0, ck_stride = 0, off_slots = 0, off_xs = 0, off_psih = 0;
-  size_t off_lam = 0, off_lx = 0, off_g = 0, off_gt = 0, off_roms = 0, total = 0;
+  size_t off_lam = 0, off_lx = 0, off_g = 0, off_gseg = 0, off_gt = 0, off_roms = 0, total = 0;
   size_t gt_elems = 0;
   std::vector<size_t> slot_gt;  // element offset of each matrix slot's G^T
 };
@@ -83,6 +83,8 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
   o += 2 * A.xs_bytes;
   A.off_g = o;
   o = align_up(o + 2 * L.field_elems * sizeof(double), 256);
+  A.off_gseg = o;  // FP32 runs: per-segment accumulators in FP32
+  o = align_up(o + (ts == 4 ? 2 * L.field_elems * ts : 0), 256);
   A.off_gt = o;
   o = align_up(o + A.gt_elems * ts, 256);
   A.off_roms = o;
@@ -197,8 +199,14 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   AdjParams<T> ap{};
   ap.al = sp.al;
   ap.be = sp.be;
-  ap.geps = (double*)(aw + A.off_g);
-  ap.gsig = ap.geps + fe;
+  double* g64 = (double*)(aw + A.off_g);
+  constexpr bool kSeg = sizeof(T) == 4;  // FP32: segment sums, folded into g64 per segment
+  if constexpr (kSeg) {
+    ap.ga_e = (T*)(aw + A.off_gseg);
+  } else {
+    ap.ga_e = (T*)g64;
+  }
+  ap.ga_s = ap.ga_e + fe;
   ap.nx = s->nx;
   ap.ny = s->ny;
   ap.pitch = s->pitch;
@@ -289,6 +297,9 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
       }
       if (launch_adjoint_step<T>(ap, L.smem_gemv, st) != hipSuccess) return dev_err("adjoint launch");
       cur ^= 1;
+    }
+    if constexpr (kSeg) {
+      if (launch_adjoint_flush((float*)ap.ga_e, g64, 2 * fe, st) != hipSuccess) return dev_err("gradient flush");
     }
   }
   // gradients: pitch layout -> natural, zero on regions and their rings
