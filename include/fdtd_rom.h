@@ -274,10 +274,12 @@ int fdtd_rom_build(const fdtd_rom_build_params* params, double* Rt, double* Ft, 
 /* Per-kernel timing with HIP events on the handle's stream.  One step is
  * one launch of the step kernel (coarse stencil, every model's eq. (23)
  * update and the probe record run as concurrent workgroups of that launch);
- * each run() call ends with a probe-flush and a step-counter launch.  While
- * enabled, every step launch and every end-of-run pair are bracketed by
- * events; fdtd_rom_profile_read synchronises and returns the summed
- * durations (ms) and counts since the last read. */
+ * with two steps per pass (fdtd_rom_set_time_blocking) one unit is the pair
+ * of launches that advances two steps.  Each run() call ends with a
+ * probe-flush and a step-counter launch.  While enabled, every unit and
+ * every end-of-run pair are bracketed by events; fdtd_rom_profile_read
+ * synchronises and returns the summed durations (ms) and counts since the
+ * last read (step_launches counts units: a pair counts once). */
 int fdtd_rom_profile_enable(fdtd_rom_sim* sim, int32_t enable);
 int fdtd_rom_profile_read(fdtd_rom_sim* sim, double* step_ms, int64_t* step_launches,
                           double* tail_ms, int64_t* tail_launches);

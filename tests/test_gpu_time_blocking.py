@@ -219,3 +219,18 @@ def test_batch_with_layers_steps_singly():
         assert not bt.time_blocking()
         with pytest.raises(capi.FdtdError):
             bt.set_time_blocking(True)
+
+
+def test_profile_counts_pairs_as_units(mixed):
+    """With two steps per pass the profiling events bracket each pair: 11
+    steps are 5 pairs and one single launch."""
+    p, roms = mixed
+    with Simulation(p, roms, max_steps=p.nsteps, dtype="f32") as s:
+        s.profile(True)
+        s.run(11)
+        ms, units, tail_ms, tails = s.profile_read()
+        assert units == 6 and tails == 1 and ms > 0
+        s.set_time_blocking(False)
+        s.run(4)
+        ms, units, _, _ = s.profile_read()
+        assert units == 4
