@@ -138,7 +138,10 @@ typedef struct {
 
 typedef struct fdtd_rom_sim fdtd_rom_sim; /* opaque, owned by the library */
 
-/* Device workspace (bytes) that fdtd_rom_create needs for this problem. */
+/* Device workspace (bytes) that fdtd_rom_create needs for this problem:
+ * two field sets (three on grids without absorbing layers, for the
+ * two-step launches), the per-cell material, the models, the probe record
+ * and the source tables. */
 int fdtd_rom_workspace_size(const fdtd_problem* prob, size_t* bytes);
 
 /* Validate the problem, fold the coarse interface half cells into the
