@@ -234,3 +234,36 @@ def test_profile_counts_pairs_as_units(mixed):
         s.run(4)
         ms, units, _, _ = s.profile_read()
         assert units == 4
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_two_step_per_cell_material(mixed, dtype):
+    """Material mode 0 (per-cell arrays instead of the 16-bit table): the
+    two-step kernels' other material path, against one launch per step."""
+    p, roms = mixed
+    out = []
+    for tb in (True, False):
+        with Simulation(p, roms, max_steps=p.nsteps, dtype=dtype) as s:
+            s.set_material_mode(0)
+            s.set_time_blocking(tb)
+            s.run(p.nsteps)
+            out.append((s.probes(), [s.field(c) for c in range(3)], s.energy()))
+    _same(out[0], out[1])
+
+
+def test_batch_two_step_without_material_tables():
+    """A batch with an instance of more than 65,536 distinct materials runs
+    the per-cell material variant of the batched pair."""
+    probs = [W.random_problem(95, 300, 260, 60, nroms=2, block=(5, 4), r=2, q=10, dtype="f32",
+                              dt_frac_coarse=0.9, f_bw=3e9),
+             W.random_problem(96, 90, 70, 60, nroms=1, block=(5, 4), r=2, q=10, dtype="f32",
+                              dt_frac_coarse=0.9, f_bw=3e9)]
+    models = [osim.build_roms(p) for p in probs]
+    with Simulation(probs[0], models[0], dtype="f32") as s:
+        assert s.material_mode() == (0, 0)   # no table for this instance
+    a = _batch_run(probs, models, True, (7, 53))
+    b = _batch_run(probs, models, False, (7, 53))
+    for k in range(2):
+        assert np.array_equal(a[0][k], b[0][k]), k
+        for c in range(3):
+            assert np.array_equal(a[1][k][c], b[1][k][c]), (k, c)
