@@ -267,3 +267,20 @@ def test_batch_two_step_without_material_tables():
         assert np.array_equal(a[0][k], b[0][k]), k
         for c in range(3):
             assert np.array_equal(a[1][k][c], b[1][k][c]), (k, c)
+
+
+def test_switching_modes_mid_run(mixed):
+    """Two-step launches switched off after an odd number of pairs (the
+    field sets have traded places) and on again: the run continues exactly
+    as one launch per step throughout."""
+    p, roms = mixed
+    ref = _run(p, roms, False, p.nsteps, dtype="f32")
+    with Simulation(p, roms, max_steps=p.nsteps, dtype="f32") as s:
+        s.set_graph(8)
+        s.run(10)                      # 5 pairs
+        s.set_time_blocking(False)
+        s.run(11)
+        s.set_time_blocking(True)
+        s.run(p.nsteps - 21)
+        got = (s.probes(), [s.field(c) for c in range(3)], s.energy())
+    _same(got, ref[:3])
