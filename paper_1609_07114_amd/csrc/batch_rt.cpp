@@ -373,7 +373,7 @@ int fdtd_rom_batch_create(const fdtd_problem* probs, int32_t B, void* dev_worksp
       bt->tb = true;
       for (fdtd_rom_sim* s : bt->sims) bt->tb = bt->tb && s->L.tb_ok;
       for (fdtd_rom_sim* s : bt->sims)
-        set_tiling(s, bt->tb ? default_tiling2(s->nx, s->ny) : default_tiling(s->nx, s->ny, (int)s->L.tsize));
+        set_tiling(s, bt->tb ? default_tiling2(s->nx, s->ny, (int)s->L.tsize) : default_tiling(s->nx, s->ny, (int)s->L.tsize));
     }
     int ctrl[kCtrlInts] = {0, 0, 0, 0};
     if (rc == FDTD_OK &&

@@ -467,8 +467,8 @@ __device__ __forceinline__ void stencil_tile(const StepParams<T>& p, int t, int 
 // rows [j0-2, j1] feed stage-2 rows [j0-1, j1), so only step n+2 goes to
 // memory: 26 bytes per cell for two steps instead of 52.
 //
-// Mode 0: a far tile, whose reads never reach a reduced region or its ring:
-//   two steps into f2.
+// Mode 0: a far tile, whose reads never reach a reduced region, its ring or
+//   a source: two steps into f2.
 // Mode 1: a tile near a region, first launch: stage 1 only, stored for lanes
 //   1..62 and rows [j0-1, j1] (the halo the second launch reads) into the
 //   step-(n+1) set, except interface edges (written by the coupling blocks).
@@ -483,7 +483,7 @@ template <typename T>
 struct Stage1 {
   T h, ex, ey;              // Hz^{n+1/2}, Ex^{n+1}, Ey^{n+1}
   T cax, cbx, cay, cby;     // eq. (3) coefficients of the row's south Ex and west Ey
-  bool act, ax, ay, ixf, iyf;  // active cell, updated edges, interface edges
+  bool act, ax, ay;         // active cell, updated edges
 };
 
 template <typename T, bool MIdx, int Mode>
@@ -512,25 +512,23 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
   const T* ex_up = ex + P;
   const bool in = c >= 0 && c < nx;
   const bool own = in && lane >= 2 && lane <= kWave - 3;
-  // sources of both steps touching columns [iw-2, iw+62) x rows [rs, re]
+  // sources touching columns [iw-2, iw+62) x rows [rs, re]; far tiles have
+  // none in reach (sources make a tile near), so their code holds no source
+  // terms and keeps the register count of the two-step sweep down
   bool any_src = false;
-  for (int s = 0; s < p.nsrc; ++s) {
-    const Src<T>& S = p.src[s];
-    any_src |= S.i0 < iw + kWave - 2 && S.i1 > iw - 2 && S.j0 <= re && S.j1 > rs;
+  if constexpr (Mode != 0) {
+    for (int s = 0; s < p.nsrc; ++s) {
+      const Src<T>& S = p.src[s];
+      any_src |= S.i0 < iw + kWave - 2 && S.i1 > iw - 2 && S.j0 <= re && S.j1 > rs;
+    }
   }
-  T sinc[kMaxSrc], sinc2[kMaxSrc];
+  T sinc[kMaxSrc];
 #pragma unroll
-  for (int s = 0; s < kMaxSrc; ++s) {
-    sinc[s] = T(0);
-    sinc2[s] = T(0);
-  }
+  for (int s = 0; s < kMaxSrc; ++s) sinc[s] = T(0);
   if (any_src) {
 #pragma unroll
     for (int s = 0; s < kMaxSrc; ++s)
-      if (s < p.nsrc) {
-        sinc[s] = p.src[s].incr[n];
-        if constexpr (kTwo) sinc2[s] = p.src[s].incr[n + 1];
-      }
+      if (s < p.nsrc) sinc[s] = p.src[s].incr[n];
   }
   // the lane's column, clamped into the row: lanes outside the grid read a
   // valid address and their values are never used
@@ -564,19 +562,15 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
     T eye = lane_next(a.ey);
     if (c + 1 >= nx) eye = T(0);
     T h2 = hz_update(a.h, a.ex, exN, a.ey, eye, chdy, chdx);
-    if (any_src) h2 += src_sum(p, sinc2, 0, c, r2);
     if (!a.act) h2 = T(0);
     const T h2w = lane_prev(h2);
     if (r2 >= j0 && own) {
-      T ex2 = a.ax ? e_update(a.cax, a.ex, a.cbx, h2 - h2_prev) : a.ex;
-      T ey2 = a.ay ? e_update(a.cay, a.ey, a.cby, -(h2 - h2w)) : a.ey;
-      if (any_src) {
-        ex2 += src_sum(p, sinc2, 1, c, r2);
-        ey2 += src_sum(p, sinc2, 2, c, r2);
-      }
+      const T ex2 = a.ax ? e_update(a.cax, a.ex, a.cbx, h2 - h2_prev) : a.ex;
+      const T ey2 = a.ay ? e_update(a.cay, a.ey, a.cby, -(h2 - h2w)) : a.ey;
+      // far tiles have no interface edges in reach: every edge is stored
       st(hzo, o2, h2);
-      if (!a.ixf) st(exo, o2, ex2);
-      if (!a.iyf) st(eyo, o2, ey2);
+      st(exo, o2, ex2);
+      st(eyo, o2, ey2);
     }
     h2_prev = h2;
   };
@@ -608,14 +602,16 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
     o.h = hn;
     o.ex = exn;
     o.ey = eyn;
-    o.ixf = (cur.al < T(0)) != (a_prev < T(0));
-    o.iyf = (cur.al < T(0)) != (all < T(0));
     if constexpr (Mode != 0) {
+      // interface edges (exactly one side inside a region) belong to the
+      // coupling blocks
+      const bool ixf = (cur.al < T(0)) != (a_prev < T(0));
+      const bool iyf = (cur.al < T(0)) != (all < T(0));
       const bool st_lane = Mode == 1 ? in && lane >= 1 && lane <= kWave - 2 : own;
       if (st_lane && r >= (Mode == 1 ? r2lo : j0)) {
         st(hzo, ob, hn);
-        if (!o.ixf) st(exo, ob, exn);
-        if (!o.iyf) st(eyo, ob, eyn);
+        if (!ixf) st(exo, ob, exn);
+        if (!iyf) st(eyo, ob, eyn);
       }
     } else {
       if (r - 1 >= r2lo) stage2(r - 1, prv1, exn, ob - row_b);

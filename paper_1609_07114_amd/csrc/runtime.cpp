@@ -805,13 +805,17 @@ int fdtd::default_tiling(int nx, int ny, int ts) {
   return 4;
 }
 
-// Default rows per wave of the two-step launches: their waves carry twice
-// the arithmetic per row and 60 owned columns, and 8 rows measured best from
-// 2048^2 (cache-resident) to 8192^2 (HBM-bound); small grids take 4 rows so
-// that the launch still holds >= 4096 waves.
-int fdtd::default_tiling2(int nx, int ny) {
+// Default rows per wave of the two-step launches (60 owned columns per
+// wave): 16 while the launch still holds >= 4096 waves and the three field
+// sets and the material stay Infinity-Cache resident (2048^2 FP32: 14.8 us
+// per step at 16 rows, 15.0 at 8), else 8 for large grids (8192^2: 246 us
+// at 8 rows, 262 at 16) and 4 for small ones.
+int fdtd::default_tiling2(int nx, int ny, int ts) {
   const long tx = (nx + kOwned2 - 1) / kOwned2;
-  return tx * ((ny + 7) / 8) >= 4096 ? 8 : 4;
+  auto waves = [&](int seg) { return tx * ((ny + seg - 1) / seg); };
+  const double bytes = (9.0 * ts + 2.0) * (double)nx * (double)ny;  // three field sets + material index
+  if (waves(16) >= 4096 && bytes <= 192.0 * (1 << 20)) return 16;
+  return waves(8) >= 4096 ? 8 : 4;
 }
 
 // a stencil workgroup covers 64 columns x (4 waves x seg rows)
@@ -833,7 +837,8 @@ void fdtd::set_tiling(fdtd_rom_sim* s, int seg) {
 // reads (columns iw-2 .. iw+63, rows j0-2 .. j1+1, widened by one) stays
 // clear of every region's zone [i0-2, i0+ni+1] x [j0-2, j0+nj+1] (the
 // region, its ring of port cells and the edges between them, with one
-// cell to spare); otherwise it is near.  A probe is near when the tile that
+// cell to spare) and of every source rectangle (widened by one); otherwise
+// it is near.  A probe is near when the tile that
 // owns its cell is.  Uploaded synchronously (never while capturing).
 template <typename T>
 int fdtd::prepare_tb(fdtd_rom_sim* s) {
@@ -853,6 +858,12 @@ int fdtd::prepare_tb(fdtd_rom_sim* s) {
     for (const RomHost& h : s->roms) {
       const int zx0 = h.i0 - 2, zx1 = h.i0 + h.ni + 1, zy0 = h.j0 - 2, zy1 = h.j0 + h.nj + 1;
       if (fx0 <= zx1 && zx0 <= fx1 && fy0 <= zy1 && zy0 <= fy1) role[t] = 1;
+    }
+    // the far-tile code holds no source terms
+    const StepParams<T>& sp = step_params<T>(s);
+    for (int k = 0; k < sp.nsrc; ++k) {
+      const Src<T>& so = sp.src[k];
+      if (fx0 <= so.i1 && so.i0 - 1 <= fx1 && fy0 <= so.j1 && so.j0 - 1 <= fy1) role[t] = 1;
     }
     if (role[t]) near.push_back(t);
   }
@@ -1125,7 +1136,7 @@ int fdtd_rom_create(const fdtd_problem* prob, void* dev_workspace, size_t ws_byt
                                   : setup_device<double>(s, prob, inside);
     s->tb = L.tb_ok;  // two steps per pass wherever the grid allows it
     if (rc == FDTD_OK)
-      set_tiling(s, s->tb ? default_tiling2(s->nx, s->ny) : default_tiling(s->nx, s->ny, (int)L.tsize));
+      set_tiling(s, s->tb ? default_tiling2(s->nx, s->ny, (int)L.tsize) : default_tiling(s->nx, s->ny, (int)L.tsize));
     if (rc != FDTD_OK) {
       delete s;
       return rc;

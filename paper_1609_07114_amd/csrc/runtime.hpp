@@ -117,7 +117,7 @@ void set_tiling(fdtd_rom_sim* s, int seg);
 // Rows per stencil wave a new handle starts with (grid size, element bytes).
 int default_tiling(int nx, int ny, int ts);
 // The same for the two-step launches.
-int default_tiling2(int nx, int ny);
+int default_tiling2(int nx, int ny, int ts);
 // Tile roles of the two-step launches for the handle's current tiling,
 // uploaded synchronously on its stream (a no-op when already current).
 template <typename T>
