@@ -284,3 +284,20 @@ def test_switching_modes_mid_run(mixed):
         s.run(p.nsteps - 21)
         got = (s.probes(), [s.field(c) for c in range(3)], s.energy())
     _same(got, ref[:3])
+
+
+def test_restore_into_handle_with_traded_sets(mixed):
+    """A state restored into a handle whose own field sets have traded
+    places (an odd number of pairs run before) continues identically."""
+    p, roms = mixed
+    ref = _run(p, roms, False, p.nsteps, dtype="f32")
+    with Simulation(p, roms, max_steps=p.nsteps, dtype="f32") as s:
+        s.run(42)
+        st = s.get_state()
+    with Simulation(p, roms, max_steps=p.nsteps, dtype="f32") as s2:
+        s2.run(6)                      # 3 pairs: this handle's sets have traded places
+        s2.set_state(st)
+        s2.run(p.nsteps - 42)
+        assert np.array_equal(s2.probes(42, p.nsteps - 42), ref[0][42:])
+        for c in range(3):
+            assert np.array_equal(s2.field(c), ref[1][c])
