@@ -1,28 +1,35 @@
 """Benchmark: coarse-grid FDTD with embedded reduced models on one MI355X.
 
-Workload (default): the 2048 x 2048 FP32 random-medium run - eps_r in
-[1, 10], sigma in [0, 0.05] S/m per 32x32 patch (seeded), 16 embedded
-32x32-cell regions refined 4x with orders {32, 48, 64, 96}, dt = 0.95 x the
-coarse vacuum CFL limit, 10,000 steps, 64 probes.  A step is one leap-frog
-step of the whole hot path: fused Hz/E stencil, every model's gather /
-reduced update / scatter, probe record.  Reduced models come from the
-library's host FP64 builder (setup, not timed).
+Workload (default, the headline): the many-copies run - a 4096 x 4096 FP32
+vacuum guide with PEC walls holding 256 identical 32x32-cell regions refined
+4x (eps_r = 4, sigma = 0.01 S/m) that share one order-128 reduced model,
+dt = 0.95 x the coarse CFL limit, a Gaussian Ey line source (plane wave)
+on column 8, 16 Hz probes.  Eq. (23) for all 256 copies runs as one FP32
+MFMA GEMM per step.  A step is one leap-frog step of the whole hot path:
+coarse Hz/E stencil, every model's gather / reduced update / scatter,
+probe record.  The reduced model comes from the library's host FP64
+builder (setup, not timed).  `--workload c2` selects the 2048^2 random
+medium instead (16 models of orders 32-96, per-cell material).
 
-Prints one JSON line (metric, value in Mcell-updates/s, roofline of the
-stencil kernel from HIP events, oracle CPU baseline on a bounded sample).
-Unless --no-forms, the line also carries the two other forms against the
-plain solver on the same GPU:
+Prints one JSON line: value in Mcell-updates/s, the roofline of the
+dominant kernel from HIP events over the timed region, and the oracle's
+CPU rate on a bounded sample of the same workload.  Unless --no-forms, the
+line also carries the other forms against the plain solver on the same GPU:
+  * "random_media_2048": the 2048^2 random-medium run (16 models);
   * "batched": the 64-instance workload (grids in [256,1024]^2, 1-8 models
-    each, FP32) in one launch per step with autotuned tiles, against the
-    same instances run one after another by single-problem handles;
-  * "hbm_resident": the same recipe at 8192^2 (2.1 GB working set), the
-    stencil's HBM-bound rate;
-  * "many_copies": 4096^2 vacuum with 256 copies of one order-128 model,
-    eq. (23) for all copies as one FP32 MFMA GEMM per step, against the
-    same run with a GEMV per copy;
+    each, FP32) in one launch per step (pair) with autotuned tiles, against
+    the same instances run one after another by single-problem handles;
+  * "hbm_resident": the random-medium recipe at 8192^2 (2.1 GB working set);
   * "adjoint": the 1024^2 probe-energy gradient (4 models q=64, 4000 steps,
     checkpoints every 200) against the forward run alone, and the FP32
-    gradient's relative L2 distance to the FP64 run's.
+    gradient's relative L2 distance to the FP64 run's;
+  * "waveguides": the two open guides of Sec. VI-B/VI-C at the paper's sizes.
+Errors against the oracle come from separate, untimed runs of the same
+workloads with the oracle-built models stored under tests/golden (written
+by scripts there that call only the oracle): "vs_oracle" is the FP32 run
+against the oracle evaluated on the same FP32-rounded coefficients and
+update matrices, "vs_fp64" against the oracle's run of the unrounded FP64
+problem (arithmetic plus coefficient rounding).
 """
 from __future__ import annotations
 
@@ -30,57 +37,84 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+GOLD = os.path.join(ROOT, "tests", "golden")
 
 METRIC = "Mcell-updates/s + % HBM roofline; batched & adjoint vs plain, 1 GPU, 1e-5 err"
 PEAK_HBM_GBS = 8000.0
-# algorithmic bytes of one step launch (FP32): per coarse cell Hz, Ex, Ey read
-# + write (24 B) and the material - a 16-bit table index (2 B; the table of
-# distinct (a, b) pairs is a few KB) or the per-cell pair (a, b) (8 B); per
-# model the (q+np)^2 update matrix of eq. (23) read once
+# Bytes per coarse cell (FP32) that one two-step pair must move at least
+# (compulsory): Hz, Ex, Ey read once and written once (24 B) and the 16-bit
+# material index read once (2 B) for two steps; per model the (q+np)^2
+# update matrix of eq. (23) once per step (one copy per shared group).
+# With one launch per step the same bytes move every step.
 FIELD_BYTES_PER_CELL_F32 = 24
 MATERIAL_BYTES_PER_CELL_F32 = {1: 2, 0: 8}
+# The per-cell-step figure of the scope table's measurement section (24 B:
+# fields, scalar coefficients; 32 B with per-cell eps_r, sigma): what a
+# schedule that moves the fields every step would move.  Over a pair it
+# counts two cell-steps, so "effective" rates of the two-step schedule can
+# exceed the bandwidth they use.
+EFFECTIVE_BYTES_PER_CELL_STEP = {"vacuum": 24, "material": 32}
 
 
-def step_bytes(prob, material_mode=1):
+def model_bytes(prob):
+    """Update-matrix bytes of one step: one (q+np)^2 FP32 matrix per distinct model."""
+    seen, tot = set(), 0
+    for k, s in enumerate(prob.roms):
+        key = s.group if s.group >= 0 else ("own", k)
+        if key in seen:
+            continue
+        seen.add(key)
+        tot += 4 * (s.q + s.n_ports) ** 2
+    return tot
+
+
+def unit_bytes(prob, material_mode=1, tb=True):
+    """Compulsory bytes of one unit of work (FP32): a two-step pair (fields
+    and material once, matrices twice) or one step launch."""
     cells = prob.nx * prob.ny
-    mats = sum(4 * (s.q + s.n_ports) ** 2 for s in prob.roms)
-    return (FIELD_BYTES_PER_CELL_F32 + MATERIAL_BYTES_PER_CELL_F32[material_mode]) * cells + mats
+    per_cell = FIELD_BYTES_PER_CELL_F32 + MATERIAL_BYTES_PER_CELL_F32[material_mode]
+    return per_cell * cells + (2 if tb else 1) * model_bytes(prob)
 
 
-def pair_bytes(prob, material_mode=1):
-    """Algorithmic bytes of one two-step pair of launches (FP32): the fields
-    read and written once and the material read once for two steps, the
-    update matrices read once per step."""
-    cells = prob.nx * prob.ny
-    mats = sum(4 * (s.q + s.n_ports) ** 2 for s in prob.roms)
-    return (FIELD_BYTES_PER_CELL_F32 + MATERIAL_BYTES_PER_CELL_F32[material_mode]) * cells + 2 * mats
-
-
-def stencil_roofline(prob, steps, ev_ms, mmode, tb, seg):
-    """Algorithmic bytes per unit over the unit's average duration from the
-    timed region's HIP events: the unit is one step launch, or with two
-    steps per pass one pair of launches."""
+def stencil_roofline(prob, steps, ev_ms, mmode, tb, seg, kind):
+    """Compulsory bytes per unit over the unit's average duration from the
+    timed region's HIP events (unit: one step launch, or with two steps per
+    pass one pair of launches), and the effective figure at the
+    per-cell-step bytes of the scope table."""
     m = "true" if mmode else "false"
     if tb:
         units = steps / 2  # an odd step count ends with one single launch
-        alg = pair_bytes(prob, mmode)
-        kernel = f"step2_kernel<float,{seg},{m},false> + step2_kernel<float,{seg},{m},true> (one pair = two steps)"
+        kernel = (f"step2_kernel<float,{seg},{m},false> + step2_kernel<float,{seg},{m},true> "
+                  f"(one pair = two steps)")
     else:
         units = steps
-        alg = step_bytes(prob, mmode)
         kernel = f"step_kernel<float,{seg},false,{m}>"
+    alg = unit_bytes(prob, mmode, tb)
     avg_s = ev_ms / 1e3 / units
-    return alg, avg_s, units, kernel
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "stencil_c2_2048_hbm_counters.json")
+    achieved = alg / avg_s / 1e9
+    eff_bytes = EFFECTIVE_BYTES_PER_CELL_STEP[kind] * prob.nx * prob.ny * (2 if tb else 1) + \
+        (2 if tb else 1) * model_bytes(prob)
+    eff = eff_bytes / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "kernel": kernel,
+            "bytes": "compulsory",
+            "bytes_per_unit": alg, "unit_of_work": "two-step pair" if tb else "step launch",
+            "avg_unit_us": round(avg_s * 1e6, 3), "units": units,
+            "effective": {"bytes_per_unit": eff_bytes,
+                          "per_cell_step_B": EFFECTIVE_BYTES_PER_CELL_STEP[kind],
+                          "achieved": round(eff, 1), "frac": round(eff / PEAK_HBM_GBS, 4)}}
 
 
 KERNEL_SOURCES = ("paper_1609_07114_amd/csrc/kernels.hip", "paper_1609_07114_amd/csrc/common.hpp",
                   "paper_1609_07114_amd/csrc/device.hpp")
+COUNTERS = {"c3": os.path.join(ROOT, "profiles", "step2_pair_c3_4096_hbm_counters.json"),
+            "c2": os.path.join(ROOT, "profiles", "stencil_c2_2048_hbm_counters.json")}
 
 
 def kernel_source_hash():
@@ -92,14 +126,14 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(material_mode, tb=False):
+def measured_traffic(workload, material_mode, tb=False):
     """HBM bytes per unit (step launch, or two-step pair) from committed
     rocprofv3 counter runs, if they were taken on the current kernel source
     in the same material and stepping mode (else None)."""
     try:
-        with open(COUNTERS_FILE) as fh:
+        with open(COUNTERS[workload]) as fh:
             d = json.load(fh)
-    except (OSError, ValueError):
+    except (OSError, ValueError, KeyError):
         return None
     if (d.get("kernel_source_hash") != kernel_source_hash() or d.get("material_mode", 0) != material_mode
             or bool(d.get("time_blocking", 0)) != bool(tb)):
@@ -107,26 +141,51 @@ def measured_traffic(material_mode, tb=False):
     return d.get("bytes_per_unit", d.get("bytes_per_launch"))
 
 
-def cpu_baseline(prob, nsteps):
-    """The oracle (NumPy FP64, closed form of eq. (23)) stepping the same
-    grid for a bounded number of steps.  Model matrices are placeholders of
-    the same orders (building oracle models is setup and is not timed)."""
+def host_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        avail = os.cpu_count()
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "cpus_available": avail}
+
+
+def cpu_baseline(nsteps=20, n=4096):
+    """The oracle (NumPy FP64; closed form of eq. (23) for every region;
+    FP32-rounded coefficients and update matrices, the way an FP32 run is
+    checked) stepping the headline workload - 4096^2 with 256 regions of
+    the oracle-built order-128 model - for a bounded number of steps on its
+    own problem instance (nsteps + 2 steps of sources).  Setup (the model
+    build and the per-region closed forms) is not timed; BLAS is held to
+    one thread, the stencil is single-threaded NumPy."""
     import numpy as np
+    import workloads as W
     from oracle import sim as osim
     try:
-        from threadpoolctl import threadpool_limits
+        from threadpoolctl import threadpool_info, threadpool_limits
     except ImportError:  # pragma: no cover
-        threadpool_limits = None
-    rng = np.random.default_rng(0)
-    roms = []
-    for s in prob.roms:
-        q, npt = s.q, s.n_ports
-        roms.append(dict(Rt=np.eye(q), Ft=np.zeros((q, q)),
-                         Lt=1e-3 * rng.standard_normal((q, npt))))
+        threadpool_info = threadpool_limits = None
+    prob = W.many_copies(n=n, nsteps=nsteps + 2)
+    one = W.many_copies(n=n, nsteps=nsteps + 2)
+    one.roms = one.roms[:1]
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
     try:
-        run = osim.CoupledRun(prob, roms, mode="closed", fp32=True)
+        blas = [{"api": d.get("internal_api"), "num_threads": d.get("num_threads")}
+                for d in threadpool_info()] if threadpool_info else []
+        t0 = time.perf_counter()
+        m = osim.build_roms(one)[0]
+        run = osim.CoupledRun(prob, [m] * len(prob.roms), mode="closed", fp32=True)
+        t_setup = time.perf_counter() - t0
         run.step()
+        run.probes()
         t0 = time.perf_counter()
         for _ in range(nsteps):
             run.step()
@@ -137,11 +196,12 @@ def cpu_baseline(prob, nsteps):
             ctx.__exit__(None, None, None)
     rate = prob.nx * prob.ny * nsteps / dt / 1e6
     return {"value": rate, "unit": "Mcell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle NumPy FP64 (closed-form eq. (23), FP32-rounded coefficients) on the "
-                      f"same {prob.nx}x{prob.ny} grid with {len(prob.roms)} models of the same "
-                      f"orders, {nsteps} steps after 1 untimed step, single thread; model "
-                      f"matrices are same-shape placeholders",
-            "seconds": dt}
+            "sample": f"oracle (NumPy FP64, closed-form eq. (23), FP32-rounded coefficients and update "
+                      f"matrices) on the headline workload {prob.nx}x{prob.ny} with {len(prob.roms)} "
+                      f"regions of the oracle-built q={prob.roms[0].q} model: {nsteps} steps timed after "
+                      f"1 untimed step, one thread (BLAS limited to 1, NumPy stencil single-threaded)",
+            "seconds": round(dt, 3), "setup_s": round(t_setup, 2),
+            "host": {**host_info(), "blas_threads_during_timing": blas}}
 
 
 def _timed(stream, fn):
@@ -178,7 +238,7 @@ def copy_ceiling(sizes_mib=(64, 128, 256, 512, 1024, 2048, 4096)):
     return {"unit": "GB/s (read+write)", "rates": out}
 
 
-def bench_batched(steps=300, warmup=30, log=None):
+def bench_batched(steps=300, warmup=100, log=None):
     import numpy as np
     import workloads as W
     from paper_1609_07114_amd import autotune, romgen
@@ -193,7 +253,7 @@ def bench_batched(steps=300, warmup=30, log=None):
     with Batch(probs, roms, max_steps=steps + warmup) as bt:
         autotune.apply(bt, choice)
         bt.set_graph(min(steps, 100))
-        bt.run(warmup)
+        bt.run(warmup)          # captures the graph batch the timed run replays
         t_b, _ = _timed(bt.stream, lambda: bt.run(steps))
         pb = [bt.probes(b) for b in range(len(probs))]
     sims = [Simulation(p, r, max_steps=steps + warmup) for p, r in zip(probs, roms)]
@@ -220,7 +280,113 @@ def bench_batched(steps=300, warmup=30, log=None):
 PEAK_MFMA_F32_TFLOPS = 157.3
 
 
-def bench_many_copies(steps=500, warmup=50, log=None):
+def _rel(a, b):
+    import numpy as np
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def golden_errors(workload):
+    """Untimed run of the workload with the oracle-built models stored under
+    tests/golden, compared with the oracle's stored probe series: FP32 run
+    vs the oracle on the FP32-rounded problem ("vs_oracle") and vs the
+    unrounded FP64 problem ("vs_fp64"), relative L2 over [steps x probes].
+    None where the stored data are absent."""
+    import numpy as np
+    import workloads as W
+    from paper_1609_07114_amd.sim import Simulation
+    if workload == "c3":
+        mpath, ppath = os.path.join(GOLD, "c3_model.npz"), os.path.join(GOLD, "c3_probes.npz")
+        if not (os.path.exists(mpath) and os.path.exists(ppath)):
+            return None
+        z = np.load(ppath)
+        n = int(z["steps"])
+        prob = W.many_copies(nsteps=n)
+        zm = np.load(mpath)
+        roms = [dict(Rt=zm["Rt"], Ft=zm["Ft"], Lt=zm["Lt"])] * len(prob.roms)
+        ref32, ref64 = z["probes_f32"], z["probes_f64"]
+    else:
+        mpath, ppath = os.path.join(GOLD, "c2_models.npz"), os.path.join(GOLD, "c2_probes_f32.npz")
+        if not (os.path.exists(mpath) and os.path.exists(ppath)):
+            return None
+        z = np.load(ppath)
+        n = int(z["steps"])
+        prob = W.random_media(n=2048, nsteps=n)
+        zm = np.load(mpath)
+        roms = [dict(Rt=zm[f"R{k}"], Ft=zm[f"F{k}"], Lt=zm[f"L{k}"]) for k in range(len(prob.roms))]
+        ref32 = z["probes"]
+        ref64 = z["probes_f64"] if "probes_f64" in z.files else None
+    with Simulation(prob, roms, max_steps=n) as s:
+        s.set_graph(200)
+        s.run(n)
+        got = s.probes()
+    out = {"steps": n, "models": "oracle-built (tests/golden)", "vs_oracle": _rel(got, ref32)}
+    out["vs_fp64"] = _rel(got, ref64) if ref64 is not None else None
+    return out
+
+
+def run_headline(prob, roms, steps, warmup, kind, workload, time_blocking=1, material_mode=None,
+                 log=None):
+    """Time exactly `steps` steps of one handle after `warmup` untimed ones
+    (graph batches captured before the timed region), bracketed by
+    synchronisation and one HIP event pair on the handle's stream."""
+    import numpy as np
+    import torch
+    from paper_1609_07114_amd.sim import Simulation
+    total = warmup + steps
+    sim = Simulation(prob, roms, max_steps=total)
+    seg = sim.get_tiling()
+    if material_mode is not None:
+        sim.set_material_mode(material_mode)
+    mmode, nmat = sim.material_mode()
+    sim.set_time_blocking(bool(time_blocking))
+    tb = sim.time_blocking()
+    gb = min(200, steps) // 4 * 4
+    sim.set_graph(gb)   # steps replayed from captured graphs (the production path)
+    sim.run(warmup)
+    sim.prepare_run(steps)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(sim.stream)
+    sim.run(steps)
+    ev1.record(sim.stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ev_ms = ev0.elapsed_time(ev1)
+    probes = sim.probes(0, total)
+    sim.close()
+    elapsed = t1 - t0
+    cells = prob.nx * prob.ny
+    roof = stencil_roofline(prob, steps, ev_ms, mmode, tb, seg, kind)
+    roof["traffic"] = measured_traffic(workload, mmode, tb)
+    roof["material"] = {"mode": "table" if mmode else "per-cell", "entries": nmat}
+    return {"value": cells * steps / elapsed / 1e6, "ms_per_step": elapsed * 1e3 / steps,
+            "event_ms": ev_ms, "roofline": roof, "finite": bool(np.all(np.isfinite(probes))),
+            "graph_batch": gb, "time_blocking": tb, "tiling": seg}
+
+
+def bench_random_media(steps=2000, warmup=200, log=None):
+    """The 2048^2 random-medium form (16 models of orders 32-96, per-cell
+    material in 32x32 patches): same timing as the headline."""
+    import workloads as W
+    from paper_1609_07114_amd import romgen
+    prob = W.random_media(n=2048, nsteps=steps + warmup)
+    t0 = time.perf_counter()
+    roms = romgen.build_roms(prob)
+    t_build = time.perf_counter() - t0
+    r = run_headline(prob, roms, steps, warmup, "material", "c2", log=log)
+    return {"workload": f"random media {prob.nx}x{prob.ny}, 16 models (q 32-96), FP32, {steps} steps",
+            "value": round(r["value"], 1), "unit": "Mcell-updates/s",
+            "ms_per_step": round(r["ms_per_step"], 5), "roofline": r["roofline"],
+            "model_build_s": round(t_build, 2), "errors": golden_errors("c2")}
+
+
+def bench_gemv_vs_gemm(steps=500, warmup=52, log=None):
+    """The headline workload with a GEMV per copy instead of the shared
+    MFMA GEMM (same handle settings otherwise), probes compared."""
     import numpy as np
     import workloads as W
     from paper_1609_07114_amd import romgen
@@ -234,48 +400,34 @@ def bench_many_copies(steps=500, warmup=50, log=None):
             s.set_shared_gemm(mode == "gemm")
             s.set_graph(100)
             s.run(warmup)
+            s.prepare_run(steps)
             t, ev = _timed(s.stream, lambda: s.run(steps))
             res[mode] = (t, ev, s.probes())
     q = prob.roms[0].q
-    m = -(-(q + prob.roms[0].n_ports) // 64) * 64          # padded rows of the update matrix
+    m = q + prob.roms[0].n_ports
     flops = 2.0 * m * m * len(prob.roms)                   # one GEMM (m x m) . (m x copies) per step
     t_g = res["gemm"][1] / 1e3 / steps
-    pg, pv = res["gemm"][2], res["gemv"][2]
-    return {"workload": f"{prob.nx}x{prob.ny} vacuum, {len(prob.roms)} copies of one model "
-                        f"q={q} (np={prob.roms[0].n_ports}), FP32, {steps} steps",
-            "value": round(cells * steps / res["gemm"][0] / 1e6, 1), "unit": "Mcell-updates/s",
-            "gemv_per_copy": round(cells * steps / res["gemv"][0] / 1e6, 1),
-            "ms_per_step": round(res["gemm"][0] * 1e3 / steps, 4),
+    return {"workload": f"{prob.nx}x{prob.ny} vacuum, {len(prob.roms)} copies of one model q={q}, "
+                        f"FP32, {steps} steps",
+            "gemm": round(cells * steps / res["gemm"][0] / 1e6, 1),
+            "gemv_per_copy": round(cells * steps / res["gemv"][0] / 1e6, 1), "unit": "Mcell-updates/s",
             "gemm_flop_per_step": flops,
             "gemm_tflops_over_step": round(flops / t_g / 1e12, 3),
             "mfma_frac_of_fp32_peak_over_step": round(flops / t_g / 1e12 / PEAK_MFMA_F32_TFLOPS, 5),
-            "rel_l2_gemm_vs_gemv": float(np.linalg.norm(pg - pv) / max(np.linalg.norm(pv), 1e-300))}
+            "rel_l2_gemm_vs_gemv": _rel(res["gemm"][2], res["gemv"][2])}
 
 
-def bench_hbm_resident(n=8192, steps=400, warmup=50, log=None):
+def bench_hbm_resident(n=8192, steps=400, warmup=52, log=None):
     """The random-media recipe at n^2 (a working set well beyond the 256 MB
     Infinity Cache): the stencil's HBM-bound rate."""
     import workloads as W
     from paper_1609_07114_amd import romgen
-    from paper_1609_07114_amd.sim import Simulation
     prob = W.random_media(n=n, nsteps=steps + warmup)
     roms = romgen.build_roms(prob)
-    with Simulation(prob, roms) as s:
-        seg = s.get_tiling()
-        mmode, nmat = s.material_mode()
-        tb = s.time_blocking()
-        s.set_graph(min(steps, 200))
-        s.run(warmup)
-        t, ev = _timed(s.stream, lambda: s.run(steps))
-    cells = prob.nx * prob.ny
-    alg, avg, units, kernel = stencil_roofline(prob, steps, ev, mmode, tb, seg)
+    r = run_headline(prob, roms, steps, warmup, "material", "hbm", log=log)
     return {"workload": f"random media {n}x{n}, 16 models (q 32-96), FP32, {steps} steps",
-            "value": round(cells * steps / t / 1e6, 1), "unit": "Mcell-updates/s",
-            "ms_per_step": round(t * 1e3 / steps, 4), "time_blocking": tb,
-            "kernel": kernel,
-            "material": {"mode": "table" if mmode else "per-cell", "entries": nmat},
-            "bytes_per_unit": alg, "achieved_GBps": round(alg / avg / 1e9, 1),
-            "frac_of_8TBps": round(alg / avg / 1e9 / PEAK_HBM_GBS, 4)}
+            "value": round(r["value"], 1), "unit": "Mcell-updates/s",
+            "ms_per_step": round(r["ms_per_step"], 5), "roofline": r["roofline"]}
 
 
 def bench_adjoint(ckpt=200, log=None):
@@ -466,17 +618,19 @@ def bench_ablations(steps=None, log=None, dtype="f64"):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--n", type=int, default=2048, help="grid size (default: the 2048^2 workload)")
-    ap.add_argument("--cpu-steps", type=int, default=400,
+    ap.add_argument("--workload", choices=["c3", "c2"], default="c3",
+                    help="c3: 4096^2, 256 copies of one q=128 model (default); c2: 2048^2 random medium")
+    ap.add_argument("--cpu-steps", type=int, default=20,
                     help="oracle steps timed for cpu_baseline (about 20 s of one host core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-forms", action="store_true", help="skip the batched, many-copies and adjoint forms")
-    ap.add_argument("--only", choices=["batched", "many_copies", "adjoint", "hbm_resident", "waveguides",
-                                       "ablations", "sweep"], default=None,
+    ap.add_argument("--no-forms", action="store_true", help="skip the other forms")
+    ap.add_argument("--no-errors", action="store_true", help="skip the untimed runs against the oracle's data")
+    ap.add_argument("--only", choices=["batched", "gemv_vs_gemm", "adjoint", "hbm_resident", "waveguides",
+                                       "ablations", "sweep", "random_media"], default=None,
                     help="run one form alone and print its JSON (profiling)")
-    ap.add_argument("--form-steps", type=int, default=None, help="timed steps of the batched / many-copies form")
+    ap.add_argument("--form-steps", type=int, default=None, help="timed steps of the form run by --only")
     ap.add_argument("--copy-ceiling", action="store_true", help="only measure device copy rates and exit")
     ap.add_argument("--material-mode", type=int, choices=[0, 1], default=None,
                     help="0: per-cell material arrays, 1: 16-bit index + table (default: table when available)")
@@ -489,32 +643,44 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("bench.py: --steps must be >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
 
     import torch
     import workloads as W
     from paper_1609_07114_amd import romgen
-    from paper_1609_07114_amd.sim import Simulation
 
     if not torch.cuda.is_available():
         print("bench.py: no ROCm GPU visible", file=sys.stderr)
         sys.exit(1)
+    log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
     if args.copy_ceiling:
         print(json.dumps({"copy_ceiling": copy_ceiling()}), flush=True)
         return
     if args.only:
-        log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
         kw = {} if args.form_steps is None or args.only == "adjoint" else {"steps": args.form_steps}
-        fn = {"batched": bench_batched, "many_copies": bench_many_copies, "adjoint": bench_adjoint,
+        fn = {"batched": bench_batched, "gemv_vs_gemm": bench_gemv_vs_gemm, "adjoint": bench_adjoint,
               "hbm_resident": bench_hbm_resident, "waveguides": bench_waveguides,
-              "ablations": bench_ablations, "sweep": bench_sweep}[args.only]
+              "ablations": bench_ablations, "sweep": bench_sweep, "random_media": bench_random_media}[args.only]
         print(json.dumps({args.only: fn(log=log, **kw)}), flush=True)
         return
     total = args.warmup + args.steps
-    prob = W.random_media(n=args.n, nsteps=total)
+    if args.workload == "c3":
+        prob = W.many_copies(nsteps=total)
+        kind = "vacuum"
+        desc = (f"C3 many copies {prob.nx}x{prob.ny} vacuum, {len(prob.roms)} embedded 32x32-cell regions "
+                f"(r=4, eps_r=4, sigma=0.01) sharing one q={prob.roms[0].q} model (FP32 MFMA GEMM over the "
+                f"copies), dt=0.95 coarse CFL, Ey plane-wave line source, {len(prob.probes)} probes")
+    else:
+        prob = W.random_media(n=2048, nsteps=total)
+        kind = "material"
+        desc = (f"C2 random media {prob.nx}x{prob.ny}, 16 embedded 32x32-cell models (r=4, q in "
+                f"32/48/64/96), dt=0.95 coarse CFL, 64 probes")
     t0 = time.perf_counter()
     roms = romgen.build_roms(prob)
     t_build = time.perf_counter() - t0
-    print(f"bench: {len(roms)} reduced models built in {t_build:.1f} s", file=sys.stderr, flush=True)
+    log(f"{len(roms)} reduced models built in {t_build:.1f} s")
 
     if args.calibrate_copy_mib:
         nb = args.calibrate_copy_mib << 20
@@ -523,76 +689,42 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
-    sim = Simulation(prob, roms, max_steps=total)
-    seg = sim.get_tiling()
-    if args.material_mode is not None:
-        sim.set_material_mode(args.material_mode)
-    mmode, nmat = sim.material_mode()
-    sim.set_time_blocking(bool(args.time_blocking))
-    tb = sim.time_blocking()
-    sim.set_graph(200)   # steps replayed from captured graphs (the production path)
-    sim.run(args.warmup)
-    torch.cuda.synchronize()
-    # timed region: K step launches on the simulation's stream, bracketed by
-    # synchronisation and by one HIP event pair on that stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(sim.stream)
-    sim.run(args.steps)
-    ev1.record(sim.stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ev_ms = ev0.elapsed_time(ev1)
-    probes = sim.probes(0, total)
-    sim.close()
-    import numpy as np
-    finite = bool(np.all(np.isfinite(probes)))
-
-    elapsed = t1 - t0
-    ms_step = elapsed * 1e3 / args.steps
-    cells = prob.nx * prob.ny
-    value = cells * args.steps / elapsed / 1e6
-    # one launch per step, or one pair of launches per two steps; the
-    # region's event time also holds the run's closing probe-flush and tick
-    # launches (~8 us over all K steps)
-    alg_bytes, st_avg_s, units, kernel = stencil_roofline(prob, args.steps, ev_ms, mmode, tb, seg)
-    achieved = alg_bytes / st_avg_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(mmode, tb),
-                "kernel": kernel, "time_blocking": tb,
-                "material": {"mode": "table" if mmode else "per-cell", "entries": nmat},
-                "bytes_per_unit": alg_bytes, "unit_of_work": "two-step pair" if tb else "step launch",
-                "avg_unit_us": round(st_avg_s * 1e6, 3), "units": units}
+    r = run_headline(prob, roms, args.steps, args.warmup, kind, args.workload, args.time_blocking,
+                     args.material_mode, log=log)
+    tb = r["time_blocking"]
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "Mcell-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "metric": METRIC, "value": round(r["value"], 1), "unit": "Mcell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"C2 random media {prob.nx}x{prob.ny}, 16 embedded 32x32-cell "
-                               f"models (r=4, q in 32/48/64/96), dt=0.95 coarse CFL, "
-                               f"{args.steps} timed steps, 64 probes"
-                               + (", two steps per pass" if tb else ""),
+        "config": {"workload": desc + (", two steps per pass" if tb else ""),
                    "nx": prob.nx, "ny": prob.ny, "n_models": len(prob.roms),
                    "orders": sorted({s.q for s in prob.roms}), "parallelism": "single GPU"},
-        "roofline": roofline,
+        "roofline": r["roofline"],
         "model_build_s": round(t_build, 2),
-        "finite": finite,
+        "finite": r["finite"],
     }
-    print(f"bench: GPU {value:.0f} Mcell-updates/s, {ms_step:.4f} ms/step", file=sys.stderr, flush=True)
+    log(f"GPU {r['value']:.0f} Mcell-updates/s, {r['ms_per_step']:.4f} ms/step, "
+        f"frac {r['roofline']['frac']}")
+    if not args.no_errors:
+        out["errors"] = golden_errors(args.workload)
+        log(f"errors {out['errors']}")
     if not args.no_forms:
-        log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
+        out["gemv_vs_gemm"] = bench_gemv_vs_gemm(log=log)
+        log(f"gemm {out['gemv_vs_gemm']['gemm']:.0f} vs gemv {out['gemv_vs_gemm']['gemv_per_copy']:.0f} Mcell/s")
+        if args.workload != "c2":
+            out["random_media_2048"] = bench_random_media(log=log)
+            log(f"random media 2048^2 {out['random_media_2048']['value']:.0f} Mcell/s")
         out["batched"] = bench_batched(log=log)
         log(f"batched {out['batched']['value']:.0f} vs plain {out['batched']['plain_sequential']:.0f} Mcell/s")
         out["hbm_resident"] = bench_hbm_resident(log=log)
-        log(f"hbm-resident 8192^2: {out['hbm_resident']['achieved_GBps']:.0f} GB/s")
-        out["many_copies"] = bench_many_copies(log=log)
-        log(f"many copies {out['many_copies']['value']:.0f} Mcell/s (GEMV {out['many_copies']['gemv_per_copy']:.0f})")
+        log(f"hbm-resident 8192^2: {out['hbm_resident']['roofline']['achieved']:.0f} GB/s")
         out["adjoint"] = bench_adjoint(log=log)
         log(f"adjoint {out['adjoint']['ratio_vs_forward']}x forward")
         out["waveguides"] = bench_waveguides(log=log)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+        log(f"cpu baseline {out['cpu_baseline']['value']:.1f} Mcell/s")
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -161,9 +161,33 @@ int fdtd_rom_create(const fdtd_problem* prob, void* dev_workspace, size_t ws_byt
                     void* hip_stream, fdtd_rom_sim** out);
 
 /* Advance one leap-frog step / nsteps steps (asynchronous on the stream).
- * FDTD_ESTATE if the step count would exceed max_steps. */
+ * FDTD_ESTATE if the step count would exceed max_steps.
+ * Periodic finiteness check (the method is stable by construction, Theorem
+ * 2, so a non-finite value means bad inputs - a source increment, a model
+ * that is not passive - or an unstable configuration): every K steps
+ * (fdtd_rom_set_check_interval, default K = 1024, counted across calls)
+ * run() launches a kernel that reads the whole current field set (3 * 4 or
+ * 8 bytes per cell, about 0.1 % of K steps' traffic) and raises a device
+ * flag on any NaN or infinity.  The check is ordered on the stream between
+ * graph replays (it is never captured).  A run() call that launched a check
+ * synchronises the stream before it returns and reports a raised flag as
+ * FDTD_EUNSTABLE; the steps have been taken, the flag stays raised (every
+ * later call that checks reports it again) until fdtd_rom_set_state.
+ * Calls that launch no check stay asynchronous. */
 int fdtd_rom_step(fdtd_rom_sim* sim);
 int fdtd_rom_run(fdtd_rom_sim* sim, int32_t nsteps);
+
+/* Check interval K in steps (0 disables the check; FDTD_EINVAL if < 0);
+ * setting it restarts the count. */
+int fdtd_rom_set_check_interval(fdtd_rom_sim* sim, int32_t every);
+int fdtd_rom_get_check_interval(const fdtd_rom_sim* sim, int32_t* every);
+
+/* Do the set-up the next fdtd_rom_run(sim, nsteps) would do before its
+ * first launch (two-step tile roles; capture of the graph batch it will
+ * replay, when graphs are on and nsteps >= the batch), without taking a
+ * step, so that a timed run starts with launches only.  Synchronises if
+ * it uploads tile roles. */
+int fdtd_rom_prepare_run(fdtd_rom_sim* sim, int32_t nsteps);
 
 /* Number of steps taken so far. */
 int fdtd_rom_steps_done(const fdtd_rom_sim* sim, int32_t* n);
@@ -173,6 +197,14 @@ int fdtd_rom_steps_done(const fdtd_rom_sim* sim, int32_t* n);
  * stream. */
 int fdtd_rom_read_probes(const fdtd_rom_sim* sim, int32_t first, int32_t count,
                          double* host_out);
+
+/* Probe-energy objective of the recorded run, the J of fdtd_rom_adjoint:
+ * J = dt * sum_{n = first}^{first+count-1} (probe row n of Hz probe p)^2,
+ * summed in FP64 on the host from the probe record.  FDTD_EINVAL if p is
+ * not an Hz probe or the rows were not recorded; FDTD_EUNSTABLE if a value
+ * is not finite.  Synchronises the stream. */
+int fdtd_rom_probe_objective(const fdtd_rom_sim* sim, int32_t probe, int32_t first, int32_t count,
+                             double* J);
 
 /* Current field comp in the natural layout into host memory:
  * Hz [ny*nx], Ex [(ny+1)*nx], Ey [ny*(nx+1)] (walls included, zero).

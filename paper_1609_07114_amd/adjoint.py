@@ -37,8 +37,7 @@ def _function():
                                           torch.from_numpy(gs).to(sigma.device, sigma.dtype))
                 else:
                     sim.run(nsteps)
-                    pr = sim.probes(0, nsteps)[:, probe]
-                    J = p.dt * float(np.sum(pr * pr))
+                    J = sim.objective(probe, 0, nsteps)
             return torch.tensor(J, dtype=torch.float64, device=eps_r.device)
 
         @staticmethod

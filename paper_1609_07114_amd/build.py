@@ -57,15 +57,21 @@ def build(verbose: bool = False) -> str:
     inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(rocm_path(), "include")]
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in HIP_SOURCES:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        _run([hipcc(), *HIPCC_FLAGS, *inc, "-c", os.path.join(HERE, src), "-o", obj], verbose)
+        cmds.append([hipcc(), *HIPCC_FLAGS, *inc, "-c", os.path.join(HERE, src), "-o", obj])
         objs.append(obj)
     for src in CPP_SOURCES:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        _run([cxx(), *CXX_FLAGS, *inc, "-c", os.path.join(HERE, src), "-o", obj], verbose)
+        cmds.append([cxx(), *CXX_FLAGS, *inc, "-c", os.path.join(HERE, src), "-o", obj])
         objs.append(obj)
+    # one compiler process per source file, side by side
+    from concurrent.futures import ThreadPoolExecutor
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
     tmp = LIB_PATH + ".tmp"
     _run([hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB_PATH)

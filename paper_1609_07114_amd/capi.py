@@ -82,9 +82,13 @@ _SIGS = {
                                   C.POINTER(C.c_void_p)]),
     "fdtd_rom_step": (C.c_int, [C.c_void_p]),
     "fdtd_rom_run": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_prepare_run": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_set_check_interval": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_get_check_interval": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "fdtd_rom_steps_done": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "fdtd_rom_read_probes": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _dp]),
     "fdtd_rom_read_field": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
+    "fdtd_rom_probe_objective": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _dp]),
     "fdtd_rom_read_rom_state": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
     "fdtd_rom_coupled_update": (C.c_int, [C.POINTER(fdtd_problem), C.c_int32, _dp, _dp, _dp]),
     "fdtd_rom_build": (C.c_int, [C.POINTER(fdtd_rom_build_params), _dp, _dp, _dp,
@@ -244,6 +248,20 @@ def fdtd_rom_run(h, nsteps: int):
     _check(lib().fdtd_rom_run(h, int(nsteps)))
 
 
+def fdtd_rom_prepare_run(h, nsteps: int):
+    _check(lib().fdtd_rom_prepare_run(h, int(nsteps)))
+
+
+def fdtd_rom_set_check_interval(h, every: int):
+    _check(lib().fdtd_rom_set_check_interval(h, int(every)))
+
+
+def fdtd_rom_get_check_interval(h) -> int:
+    n = C.c_int32(0)
+    _check(lib().fdtd_rom_get_check_interval(h, C.byref(n)))
+    return int(n.value)
+
+
 def fdtd_rom_steps_done(h) -> int:
     n = C.c_int32(0)
     _check(lib().fdtd_rom_steps_done(h, C.byref(n)))
@@ -254,6 +272,12 @@ def fdtd_rom_read_probes(h, first: int, count: int, nprobes: int) -> np.ndarray:
     out = np.zeros((count, nprobes), dtype=np.float64)
     _check(lib().fdtd_rom_read_probes(h, first, count, _ptr(out)))
     return out
+
+
+def fdtd_rom_probe_objective(h, probe: int, first: int, count: int) -> float:
+    J = C.c_double(0.0)
+    _check(lib().fdtd_rom_probe_objective(h, probe, first, count, C.byref(J)))
+    return float(J.value)
 
 
 def fdtd_rom_read_field(h, comp: int, nx: int, ny: int) -> np.ndarray:

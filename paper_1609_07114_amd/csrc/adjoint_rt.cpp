@@ -180,15 +180,8 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
 
   // objective from the probe record
   {
-    std::vector<double> pr((size_t)N * s->nprobes);
-    const int rc = fdtd_rom_read_probes(s, 0, N, pr.data());
+    const int rc = fdtd_rom_probe_objective(s, probe, 0, N, J);
     if (rc != FDTD_OK) return rc;
-    double acc = 0;
-    for (int n = 0; n < N; ++n) {
-      const double v = pr[(size_t)n * s->nprobes + probe];
-      acc += v * v;
-    }
-    *J = s->dt * acc;
   }
 
   // reverse sweep

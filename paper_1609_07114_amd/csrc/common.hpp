@@ -12,7 +12,7 @@ constexpr int kMaxSrc = 4;         // sources applied inside the stencil kernel
 constexpr int kMaxQ = 16384;       // model order handled by the coupling kernels (also bounded by kMaxStageBytes)
 constexpr int kMaxStageBytes = 65536;  // LDS of a coupling workgroup's staged [x~; h] (padded q + np elements)
 constexpr int kMaxPorts = 1024;    // ports per region
-constexpr int kCtrlInts = 4;       // ctrl[0] = step, ctrl[1] = finished-block count
+constexpr int kCtrlInts = 4;       // ctrl[0] = step, ctrl[2] = non-finite flag (finite_check_kernel)
 
 template <typename T>
 struct Src {
@@ -157,6 +157,10 @@ hipError_t launch_step2(const StepParams<T>& a, const StepParams<T>& b, int seg,
 template <typename T>
 hipError_t launch_probe_flush(const StepParams<T>& p, hipStream_t s);
 hipError_t launch_tick(int* ctrl, int k, hipStream_t s);
+// Sets *flag = 1 if any of the n elements at f is not finite (n a multiple
+// of 16 bytes of elements, f 16-byte aligned); the flag is not cleared.
+template <typename T>
+hipError_t launch_finite_check(const T* f, size_t n, int* flag, hipStream_t s);
 template <typename T>
 hipError_t launch_energy(const T* hz, const T* ex, const T* ey, const T* al, int nx, int ny, int pitch,
                          double ch, double half_area, double dx, double dy, double* part, hipStream_t s);

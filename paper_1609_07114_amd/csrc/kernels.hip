@@ -35,6 +35,7 @@
 //     inside keep their (zero) value and interface edges are not written;
 //   * workgroups are remapped so each of the 8 XCDs (own L2) takes a
 //     contiguous band of tiles, keeping the halo rows within one L2.
+#include <algorithm>
 #include <type_traits>
 
 #include "common.hpp"
@@ -1014,6 +1015,28 @@ __global__ void tick_kernel(int* ctrl, int k) {
   if (threadIdx.x == 0 && blockIdx.x == 0) ctrl[0] += k;
 }
 
+// Any non-finite value among n elements of a field set (n a multiple of the
+// 16-byte vector width, the base 16-byte aligned): grid-stride 16-byte loads;
+// a thread that finds one stores 1 into *flag (every writer stores the same
+// value, so no atomics are needed; the host clears the flag).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) finite_check_kernel(const T* __restrict__ f, size_t n, int* flag) {
+  using V = std::conditional_t<sizeof(T) == 4, float4, double2>;
+  constexpr int W = 16 / sizeof(T);
+  const V* v = reinterpret_cast<const V*>(f);
+  const size_t nv = n / W;
+  bool bad = false;
+  for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < nv; k += (size_t)gridDim.x * kBlock) {
+    const V x = v[k];
+    if constexpr (sizeof(T) == 4)
+      bad |= !(__builtin_isfinite(x.x) && __builtin_isfinite(x.y) && __builtin_isfinite(x.z) &&
+               __builtin_isfinite(x.w));
+    else
+      bad |= !(__builtin_isfinite(x.x) && __builtin_isfinite(x.y));
+  }
+  if (bad) flag[0] = 1;
+}
+
 // Batched step: B independent problems advance one step in one launch.
 // Workgroup b takes table[b] = (instance, role, index) and runs the same
 // device code as step_kernel on that instance's parameter block, which
@@ -1257,6 +1280,18 @@ hipError_t launch_tick(int* ctrl, int k, hipStream_t s) {
   hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, s, ctrl, k);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_finite_check(const T* f, size_t n, int* flag, hipStream_t s) {
+  if (n % (16 / sizeof(T)) != 0 || ((uintptr_t)f) % 16 != 0) return hipErrorInvalidValue;
+  const size_t nv = n / (16 / sizeof(T));
+  const size_t want = (nv + kBlock - 1) / kBlock;
+  const unsigned g = (unsigned)std::max<size_t>(1, std::min<size_t>(want, 2048));
+  hipLaunchKernelGGL((finite_check_kernel<T>), dim3(g), dim3(kBlock), 0, s, f, n, flag);
+  return hipGetLastError();
+}
+template hipError_t launch_finite_check<float>(const float*, size_t, int*, hipStream_t);
+template hipError_t launch_finite_check<double>(const double*, size_t, int*, hipStream_t);
 
 template hipError_t launch_step<float>(const StepParams<float>&, int, size_t, hipStream_t);
 template hipError_t launch_step<double>(const StepParams<double>&, int, size_t, hipStream_t);

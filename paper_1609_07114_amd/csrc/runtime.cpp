@@ -1023,6 +1023,31 @@ int capture_graph(fdtd_rom_sim* s, int gb, int key) {
 // start; two-step batches (a multiple of 4 steps: an even number of pairs,
 // so the sets are back in place afterwards) are keyed on the start parity
 // and the set order they were captured for.
+int graph_key(const fdtd_rom_sim* s) { return s->tb ? 1 | ((s->steps & 1) << 1) | (s->flip << 2) : 0; }
+
+int graph_batch_steps(const fdtd_rom_sim* s) { return s->tb ? s->graph_batch / 4 * 4 : s->graph_batch; }
+
+template <typename T>
+int ensure_graph(fdtd_rom_sim* s) {
+  const int gb = graph_batch_steps(s);
+  const int key = graph_key(s);
+  if (!s->graph || s->graph_steps != gb || s->graph_seg != s->seg || s->graph_key != key)
+    return capture_graph<T>(s, gb, key);
+  return FDTD_OK;
+}
+
+// Launch the finiteness check on the physical field set holding the state
+// after `at` steps (the handle's flip bit already current).
+template <typename T>
+int launch_check(fdtd_rom_sim* s, int at) {
+  const Layout& L = s->L;
+  const int set = (at & 1) ^ s->flip;
+  const T* f = (const T*)(s->ws + L.off_fields + (size_t)3 * set * L.field_elems * sizeof(T));
+  if (launch_finite_check<T>(f, 3 * L.field_elems, (int*)(s->ws + L.off_ctrl) + 2, s->stream) != hipSuccess)
+    return fail(FDTD_EDEVICE, "finiteness check launch failed: %s", hipGetErrorString(hipGetLastError()));
+  return FDTD_OK;
+}
+
 template <typename T>
 int run_steps(fdtd_rom_sim* s, int nsteps) {
   if (nsteps == 0) return FDTD_OK;
@@ -1031,30 +1056,70 @@ int run_steps(fdtd_rom_sim* s, int nsteps) {
     if (rc != FDTD_OK) return rc;
   }
   int done = 0;
-  const int gb = s->tb ? s->graph_batch / 4 * 4 : s->graph_batch;
-  if (gb > 0 && !s->prof && nsteps >= gb) {
-    const int key = s->tb ? 1 | ((s->steps & 1) << 1) | (s->flip << 2) : 0;
-    if (!s->graph || s->graph_steps != gb || s->graph_seg != s->seg || s->graph_key != key) {
-      const int rc = capture_graph<T>(s, gb, key);
+  bool checked = false;
+  // after k more steps (state now at `at` steps): check every check_every
+  auto after = [&](int k, int at) -> int {
+    s->since_check += k;
+    if (s->check_every > 0 && s->since_check >= s->check_every) {
+      const int rc = launch_check<T>(s, at);
       if (rc != FDTD_OK) return rc;
+      s->since_check = 0;
+      checked = true;
     }
+    return FDTD_OK;
+  };
+  const int gb = graph_batch_steps(s);
+  if (gb > 0 && !s->prof && nsteps >= gb) {
+    int rc = ensure_graph<T>(s);
+    if (rc != FDTD_OK) return rc;
     while (nsteps - done >= gb) {
       if (hipGraphLaunch(s->graph, s->stream) != hipSuccess)
         return fail(FDTD_EDEVICE, "hipGraphLaunch failed: %s", hipGetErrorString(hipGetLastError()));
       done += gb;
+      if ((rc = after(gb, s->steps + done)) != FDTD_OK) return rc;
     }
   }
-  if (nsteps > done) {
+  // direct launches, in chunks that end where a check is due (even-sized
+  // where possible, so two-step runs keep their pairs)
+  while (nsteps > done) {
+    int c = nsteps - done;
+    if (s->check_every > 0) {
+      c = std::min(c, std::max(s->check_every - s->since_check, 1));
+      if (s->tb && (c & 1) && c < nsteps - done) ++c;
+    }
     int pairs = 0;
-    const int rc = enqueue_steps<T>(s, nsteps - done, s->stream, s->prof, s->steps + done, &pairs);
+    int rc = enqueue_steps<T>(s, c, s->stream, s->prof, s->steps + done, &pairs);
     if (rc != FDTD_OK) return rc;
     if (pairs & 1) {
       StepParams<T>& sp = step_params<T>(s);
-      for (int c = 0; c < 3; ++c) std::swap(sp.f[0][c], sp.f[1][c]);
+      for (int k = 0; k < 3; ++k) std::swap(sp.f[0][k], sp.f[1][k]);
       s->flip ^= 1;
     }
+    done += c;
+    if ((rc = after(c, s->steps + done)) != FDTD_OK) return rc;
   }
   s->steps += nsteps;
+  if (checked) {
+    int flag = 0;
+    if (hipMemcpyAsync(&flag, (int*)(s->ws + s->L.off_ctrl) + 2, sizeof(int), hipMemcpyDeviceToHost,
+                       s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+      return fail(FDTD_EDEVICE, "finiteness flag read failed: %s", hipGetErrorString(hipGetLastError()));
+    if (flag)
+      return fail(FDTD_EUNSTABLE, "non-finite field value found by the periodic check (state at step %d)",
+                  s->steps);
+  }
+  return FDTD_OK;
+}
+
+template <typename T>
+int prepare_run(fdtd_rom_sim* s, int nsteps) {
+  if (s->tb) {
+    const int rc = prepare_tb<T>(s);
+    if (rc != FDTD_OK) return rc;
+  }
+  const int gb = graph_batch_steps(s);
+  if (gb > 0 && !s->prof && nsteps >= gb) return ensure_graph<T>(s);
   return FDTD_OK;
 }
 
@@ -1158,6 +1223,26 @@ int fdtd_rom_run(fdtd_rom_sim* sim, int32_t nsteps) {
   return run_steps_any(sim, nsteps);
 }
 
+int fdtd_rom_prepare_run(fdtd_rom_sim* sim, int32_t nsteps) {
+  if (!sim) return fail(FDTD_EINVAL, "null handle");
+  if (nsteps < 0) return fail(FDTD_EINVAL, "negative step count");
+  return sim->dtype == FDTD_F32 ? prepare_run<float>(sim, nsteps) : prepare_run<double>(sim, nsteps);
+}
+
+int fdtd_rom_set_check_interval(fdtd_rom_sim* sim, int32_t every) {
+  if (!sim) return fail(FDTD_EINVAL, "null handle");
+  if (every < 0) return fail(FDTD_EINVAL, "check interval must be >= 0");
+  sim->check_every = every;
+  sim->since_check = 0;
+  return FDTD_OK;
+}
+
+int fdtd_rom_get_check_interval(const fdtd_rom_sim* sim, int32_t* every) {
+  if (!sim || !every) return fail(FDTD_EINVAL, "null argument");
+  *every = sim->check_every;
+  return FDTD_OK;
+}
+
 int fdtd_rom_steps_done(const fdtd_rom_sim* sim, int32_t* n) {
   if (!sim || !n) return fail(FDTD_EINVAL, "null argument");
   *n = sim->steps;
@@ -1180,6 +1265,22 @@ int fdtd_rom_read_probes(const fdtd_rom_sim* sim, int32_t first, int32_t count, 
   else to_double<double>(raw, n, host_out);
   for (size_t k = 0; k < n; ++k)
     if (!std::isfinite(host_out[k])) return fail(FDTD_EUNSTABLE, "non-finite probe value at row %zu", first + k / sim->nprobes);
+  return FDTD_OK;
+}
+
+int fdtd_rom_probe_objective(const fdtd_rom_sim* sim, int32_t probe, int32_t first, int32_t count, double* J) {
+  if (!sim || !J) return fail(FDTD_EINVAL, "null argument");
+  if (probe < 0 || probe >= sim->nprobes || sim->probes[probe].comp != FDTD_HZ)
+    return fail(FDTD_EINVAL, "probe %d is not an Hz probe of this problem", probe);
+  std::vector<double> pr((size_t)count * sim->nprobes);
+  const int rc = fdtd_rom_read_probes(sim, first, count, pr.data());
+  if (rc != FDTD_OK) return rc;
+  double acc = 0;
+  for (int n = 0; n < count; ++n) {
+    const double v = pr[(size_t)n * sim->nprobes + probe];
+    acc += v * v;
+  }
+  *J = sim->dt * acc;
   return FDTD_OK;
 }
 
@@ -1376,6 +1477,7 @@ int fdtd_rom_set_state(fdtd_rom_sim* sim, const void* dev_src) {
       return fail(FDTD_EDEVICE, "state copy failed");
   if (hipStreamSynchronize(sim->stream) != hipSuccess) return fail(FDTD_EDEVICE, "state copy failed");
   sim->steps = h.steps;
+  sim->since_check = 0;  // the control block copy above cleared the non-finite flag
   return FDTD_OK;
 }
 

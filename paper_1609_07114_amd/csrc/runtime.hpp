@@ -88,6 +88,11 @@ struct fdtd_rom_sim {
   bool tb = false;
   int tb_seg = 0;
   int flip = 0;
+  // periodic finiteness check of the field set: every check_every steps
+  // (0: never) run() launches finite_check_kernel; a run that launched one
+  // synchronises and reports a non-finite value as FDTD_EUNSTABLE
+  int check_every = 1024;
+  int since_check = 0;
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_st, ev_cp;
   size_t used_st = 0, used_cp = 0;

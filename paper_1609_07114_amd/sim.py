@@ -31,6 +31,16 @@ class Simulation:
     def step(self):
         capi.fdtd_rom_step(self.h)
 
+    def prepare_run(self, nsteps):
+        """Set-up (tile roles, graph capture) of the next run(nsteps), no step."""
+        capi.fdtd_rom_prepare_run(self.h, nsteps)
+
+    def set_check_interval(self, every):
+        capi.fdtd_rom_set_check_interval(self.h, every)
+
+    def check_interval(self):
+        return capi.fdtd_rom_get_check_interval(self.h)
+
     @property
     def steps_done(self):
         return capi.fdtd_rom_steps_done(self.h)
@@ -39,6 +49,12 @@ class Simulation:
         if count is None:
             count = self.steps_done - first
         return capi.fdtd_rom_read_probes(self.h, first, count, self.nprobes)
+
+    def objective(self, probe=0, first=0, count=None):
+        """J = dt * sum over recorded rows of Hz_probe^2 (the adjoint's objective)."""
+        if count is None:
+            count = self.steps_done - first
+        return capi.fdtd_rom_probe_objective(self.h, probe, first, count)
 
     def field(self, comp):
         return capi.fdtd_rom_read_field(self.h, comp, self.prob.nx, self.prob.ny)
