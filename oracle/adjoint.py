@@ -57,10 +57,13 @@ def _edge_ab(prob):
 
 def gradient_mask(prob):
     """True for cells whose gradient is reported (outside every region and
-    its one-cell ring)."""
+    its one-cell ring, and not a PEC cell, whose material takes no part)."""
     m = np.ones((prob.ny, prob.nx), dtype=bool)
     for s in prob.roms:
         m[max(s.j0 - 1, 0):s.j0 + s.nj + 1, max(s.i0 - 1, 0):s.i0 + s.ni + 1] = False
+    pec = getattr(prob, "pec", None)
+    if pec is not None:
+        m &= ~np.asarray(pec, dtype=bool)
     return m
 
 

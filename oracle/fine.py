@@ -30,6 +30,13 @@ the r fine boundary E samples lying on one coarse interface edge are equal
 to that coarse E (eq. (15)); P slaves them to one coordinate.  The restricted
 model R' = P^T R P, F' = P^T F P has input U = (1/r) T^T u (eq. (16)) and
 B' = P^T B T = Lc Sc with Sc = diag(-dx, +dx, +dy, -dy).
+
+PEC cells (the thin metal irises of Sec. VI-B): every edge of a PEC fine
+cell carries zero tangential E and the cell's Hz stays zero, so those
+samples are not unknowns.  P leaves them out (they are pinned to zero);
+a coarse port whose r fine edges are all pinned has no coordinate and its
+column of Lc is zero.  A port with only some of its fine edges pinned
+would contradict eq. (15) and is rejected.
 """
 from __future__ import annotations
 
@@ -132,35 +139,72 @@ def assemble(eps_r, sigma, dxh, dyh, dt):
                 Dm=Dm, K=K, index=ix)
 
 
-def restriction(ix: FineIndex, r: int):
+def pinned_edges(pec, Nx, Ny):
+    """Fine edges on a PEC cell (zero tangential E): (pin_ex [Ny+1, Nx],
+    pin_ey [Ny, Nx+1]).  ``pec``: [Ny, Nx] bool or None."""
+    pin_ex = np.zeros((Ny + 1, Nx), dtype=bool)
+    pin_ey = np.zeros((Ny, Nx + 1), dtype=bool)
+    if pec is not None:
+        pec = np.asarray(pec, dtype=bool)
+        pin_ex[:-1, :] |= pec      # south edge of each PEC cell
+        pin_ex[1:, :] |= pec       # north edge
+        pin_ey[:, :-1] |= pec      # west edge
+        pin_ey[:, 1:] |= pec       # east edge
+    return pin_ex, pin_ey
+
+
+def restriction(ix: FineIndex, r: int, pec=None):
     """P (full -> restricted) and T (fine ports <- coarse ports).
 
     Restricted state: [interior Ex (j=1..Ny-1, i); interior Ey (j; i=1..Nx-1);
-    coarse ports S (ni), N (ni), W (nj), E (nj); Hz (all)]."""
+    coarse ports S (ni), N (ni), W (nj), E (nj); Hz (all)], leaving out the
+    samples pinned by PEC cells (``pec`` [Ny, Nx] bool) and the ports whose
+    fine edges are all pinned."""
     Nx, Ny = ix.Nx, ix.Ny
     ni, nj = Nx // r, Ny // r
+    pin_ex, pin_ey = pinned_edges(pec, Nx, Ny)
+    pec_c = np.zeros((Ny, Nx), dtype=bool) if pec is None else np.asarray(pec, dtype=bool)
     rows, cols = [], []
     col = 0
     for j in range(1, Ny):
         for i in range(Nx):
-            rows.append(ix.ex(i, j)); cols.append(col); col += 1
+            if not pin_ex[j, i]:
+                rows.append(ix.ex(i, j)); cols.append(col); col += 1
     for j in range(Ny):
         for i in range(1, Nx):
-            rows.append(ix.ey(i, j)); cols.append(col); col += 1
+            if not pin_ey[j, i]:
+                rows.append(ix.ey(i, j)); cols.append(col); col += 1
     n_int = col
-    # coarse ports
-    port_base = {"S": n_int, "N": n_int + ni, "W": n_int + 2 * ni, "E": n_int + 2 * ni + nj}
-    for i in range(Nx):
-        rows.append(ix.ex(i, 0)); cols.append(port_base["S"] + i // r)
-        rows.append(ix.ex(i, Ny)); cols.append(port_base["N"] + i // r)
-    for j in range(Ny):
-        rows.append(ix.ey(0, j)); cols.append(port_base["W"] + j // r)
-        rows.append(ix.ey(Nx, j)); cols.append(port_base["E"] + j // r)
+    # coarse ports, S (ni), N (ni), W (nj), E (nj): the fine boundary edges
+    # of each, all pinned (no coordinate) or none
+    sides = ([[(pin_ex, 0, i) for i in range(c * r, (c + 1) * r)] for c in range(ni)]
+             + [[(pin_ex, Ny, i) for i in range(c * r, (c + 1) * r)] for c in range(ni)]
+             + [[(pin_ey, j, 0) for j in range(c * r, (c + 1) * r)] for c in range(nj)]
+             + [[(pin_ey, j, Nx) for j in range(c * r, (c + 1) * r)] for c in range(nj)])
     n_pc = 2 * (ni + nj)
-    n_e_r = n_int + n_pc
-    for h in range(ix.n_h):
-        rows.append(ix.n_e + h); cols.append(n_e_r + h)
-    n_r = n_e_r + ix.n_h
+    port_col = []
+    for k, edges in enumerate(sides):
+        pins = [bool(m[a, b]) for (m, a, b) in edges]
+        if any(pins) and not all(pins):
+            raise ValueError(f"coarse port {k}: only some of its fine edges lie on PEC cells")
+        if all(pins):
+            port_col.append(-1)
+        else:
+            port_col.append(col)
+            col += 1
+    for k, edges in enumerate(sides):
+        if port_col[k] < 0:
+            continue
+        for (m, a, b) in edges:
+            rows.append(ix.ex(b, a) if m is pin_ex else ix.ey(b, a))
+            cols.append(port_col[k])
+    n_e_r = col
+    for j in range(Ny):
+        for i in range(Nx):
+            if not pec_c[j, i]:
+                rows.append(ix.hz(i, j)); cols.append(col); col += 1
+    n_h_r = col - n_e_r
+    n_r = col
     P = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(ix.n, n_r))
     # T: fine port p (S,N,W,E order) -> coarse port
     trow, tcol = [], []
@@ -173,9 +217,11 @@ def restriction(ix: FineIndex, r: int):
     for j in range(Ny):
         trow.append(2 * Nx + Ny + j); tcol.append(2 * ni + nj + j // r)
     T = sp.csr_matrix((np.ones(len(trow)), (trow, tcol)), shape=(2 * (Nx + Ny), n_pc))
-    Lc = sp.csr_matrix((np.ones(n_pc), (n_int + np.arange(n_pc), np.arange(n_pc))),
+    live = [k for k in range(n_pc) if port_col[k] >= 0]
+    Lc = sp.csr_matrix((np.ones(len(live)), ([port_col[k] for k in live], live)),
                        shape=(n_r, n_pc))
-    return dict(P=P, T=T, Lc=Lc, n_e=n_e_r, n_h=ix.n_h, n=n_r, n_ports=n_pc)
+    return dict(P=P, T=T, Lc=Lc, n_e=n_e_r, n_h=n_h_r, n=n_r, n_ports=n_pc,
+                dead_ports=[k for k in range(n_pc) if port_col[k] < 0])
 
 
 def coarse_port_scale(ni, nj, dx, dy):
@@ -184,11 +230,12 @@ def coarse_port_scale(ni, nj, dx, dy):
                            np.full(nj, +dy), np.full(nj, -dy)])
 
 
-def restricted_model(eps_r, sigma, r, dx, dy, dt):
-    """Fine model restricted to coarse ports: R', F', Lc, B' = Lc Sc."""
+def restricted_model(eps_r, sigma, r, dx, dy, dt, pec=None):
+    """Fine model restricted to coarse ports (and without the samples PEC
+    cells pin): R', F', Lc, B' = Lc Sc."""
     Ny, Nx = np.asarray(eps_r).shape
     full = assemble(eps_r, sigma, dx / r, dy / r, dt)
-    rs = restriction(full["index"], r)
+    rs = restriction(full["index"], r, pec)
     P = rs["P"]
     Rr = (P.T @ full["R"] @ P).tocsr()
     Fr = (P.T @ full["F"] @ P).tocsr()

@@ -170,12 +170,14 @@ def cfl_clip(Rt, Ft, q1, dt, theta=0.99):
 
 
 def build_rom(eps_r, sigma, r, dx, dy, dt, q, f_max, basis="sprim", clip=True,
-              theta=0.99):
+              theta=0.99, pec=None):
     """Reduced model of one refined region.
 
     Returns dict(Rt, Ft, Lt, q1, q2, Sc, smax_before, smax_after, clipped, p0).
-    ``basis='identity'`` skips reduction (V = I, q = restricted state size)."""
-    model = fine.restricted_model(eps_r, sigma, r, dx, dy, dt)
+    ``basis='identity'`` skips reduction (V = I, q = restricted state size).
+    ``pec``: fine cells that are perfect conductors (their samples are
+    left out of the model, see ``fine``)."""
+    model = fine.restricted_model(eps_r, sigma, r, dx, dy, dt, pec)
     if basis == "identity":
         n_e, n_h = model["n_e"], model["n_h"]
         V1 = np.eye(n_e)

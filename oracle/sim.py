@@ -44,7 +44,7 @@ class CoupledRun:
         nx, ny = prob.nx, prob.ny
         self.f = yee.CoarseFields(nx, ny)
         blocks = [(s.i0, s.j0, s.ni, s.nj) for s in prob.roms]
-        self.cell, self.exm, self.eym = yee.masks(nx, ny, blocks)
+        self.cell, self.exm, self.eym = yee.masks(nx, ny, blocks, getattr(prob, "pec", None))
         (self.ca_x, self.cb_x, self.ca_y, self.cb_y, self.chdy,
          self.chdx) = yee.edge_coefficients(prob.eps_r, prob.sigma, prob.dt,
                                             prob.dx, prob.dy, fp32=fp32)
@@ -213,7 +213,8 @@ def build_roms(prob, basis="sprim", clip=True, theta=0.99):
             out.append(cache[key])
             continue
         m = build_rom(spec.eps_r, spec.sigma, spec.r, prob.dx, prob.dy, prob.dt,
-                      spec.q, spec.f_max, basis=basis, clip=clip, theta=theta)
+                      spec.q, spec.f_max, basis=basis, clip=clip, theta=theta,
+                      pec=getattr(spec, "pec", None))
         m = dict(Rt=m["Rt"], Ft=m["Ft"], Lt=m["Lt"], q1=m["q1"], q2=m["q2"],
                  clipped=m["clipped"], smax_before=m["smax_before"],
                  smax_after=m["smax_after"])

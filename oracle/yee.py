@@ -88,13 +88,16 @@ def edge_coefficients(eps_r, sigma, dt, dx, dy, fp32=False):
     return ca_x, cb_x, ca_y, cb_y, chdy, chdx
 
 
-def masks(nx, ny, blocks):
+def masks(nx, ny, blocks, pec=None):
     """Active cells / edges of the coarse grid.
 
-    ``blocks``: iterable of (i0, j0, ni, nj) reduced regions.  A cell is
-    active outside every block.  An edge is active when it is not on a PEC
-    wall and neither inside nor on the boundary of a block (boundary edges
-    are the interface E, written by the reduced-model update)."""
+    ``blocks``: iterable of (i0, j0, ni, nj) reduced regions; ``pec``:
+    [ny, nx] bool of perfectly conducting cells, or None.  A cell is active
+    outside every block and every PEC cell (a PEC cell's Hz stays zero).  An
+    edge is active when it is not on a PEC wall, not on a side of a PEC cell
+    (zero tangential E) and neither inside nor on the boundary of a block
+    (boundary edges are the interface E, written by the reduced-model
+    update)."""
     cell = np.ones((ny, nx), dtype=bool)
     ex = np.zeros((ny + 1, nx), dtype=bool)
     ey = np.zeros((ny, nx + 1), dtype=bool)
@@ -104,6 +107,13 @@ def masks(nx, ny, blocks):
         cell[j0:j0 + nj, i0:i0 + ni] = False
         ex[j0:j0 + nj + 1, i0:i0 + ni] = False
         ey[j0:j0 + nj, i0:i0 + ni + 1] = False
+    if pec is not None:
+        pec = np.asarray(pec, dtype=bool)
+        cell &= ~pec
+        ex[:-1, :] &= ~pec
+        ex[1:, :] &= ~pec
+        ey[:, :-1] &= ~pec
+        ey[:, 1:] &= ~pec
     return cell, ex, ey
 
 

@@ -181,3 +181,26 @@ def test_adjoint_with_layers_matches_central_differences():
         fd_s = _fd(p, roms, "sigma", i, j, 1e-5)
         assert ge[j, i] == pytest.approx(fd_e, rel=2e-6, abs=1e-6 * np.abs(ge).max()), (i, j)
         assert gs[j, i] == pytest.approx(fd_s, rel=2e-6, abs=1e-6 * np.abs(gs).max()), (i, j)
+
+
+def test_adjoint_with_pec_cells_matches_central_differences():
+    """PEC cells on the coarse grid and inside the region (a plate touching
+    a port): cells next to the metal against central differences of the
+    forward, and zero gradient on the PEC cells themselves."""
+    p = W.pec_problem(7, r=2, q=10, nsteps=200)
+    roms = osim.build_roms(p)
+    J, ge, gs = oadj.adjoint_gradient(p, roms)
+    m = oadj.gradient_mask(p)
+    assert not m[p.pec].any()
+    assert np.all(ge[p.pec] == 0) and np.all(gs[p.pec] == 0)
+    s = p.roms[0]
+    # cells beside the coarse PEC plate (below the region's ring) and a far one
+    ci = s.i0 + 2
+    cells = [(ci - 1, s.j0 - 3), (ci + 1, s.j0 - 3)]
+    cells = [(i, j) for (i, j) in cells if 0 <= j and m[j, i]]
+    assert cells
+    for (i, j) in cells:
+        assert ge[j, i] == pytest.approx(_fd(p, roms, "eps_r", i, j, 1e-4), rel=2e-6,
+                                         abs=1e-6 * np.abs(ge).max())
+        assert gs[j, i] == pytest.approx(_fd(p, roms, "sigma", i, j, 1e-5), rel=2e-6,
+                                         abs=1e-6 * np.abs(gs).max())

@@ -267,3 +267,75 @@ def test_energy_balance_exact(lossy):
         if not lossy:
             assert d <= 1e-14 * e_first
     assert run.energy() <= e_first * (1 + 1e-13)
+
+
+def _pec_problem(r, q=0, seed=1, nsteps=150):
+    p = W.pec_problem(seed, r=r, q=q, nsteps=nsteps)
+    s = p.roms[0]
+    cell, exm, eym = yee.masks(p.nx, p.ny, [(s.i0, s.j0, s.ni, s.nj)], p.pec)
+    for src in p.sources:
+        m = (cell, exm, eym)[src.comp]
+        assert np.all(m[src.j0:src.j1, src.i0:src.i1])
+    for pr in p.probes:
+        assert (cell, exm, eym)[pr.comp][pr.j, pr.i]
+    return p
+
+
+def test_identity_basis_r1_with_pec_is_plain_yee_with_pec():
+    """PEC cells inside a region (fine model without their samples, dead
+    ports) and on its ring: with r = 1 and the identity basis the embedded
+    run equals plain Yee on the whole grid with the same PEC cells (two
+    independent codings of the pinned samples), to round-off."""
+    p = _pec_problem(1)
+    ms = sim.build_roms(p, basis="identity", clip=False)
+    s = p.roms[0]
+    m = fine.restricted_model(s.eps_r, s.sigma, 1, p.dx, p.dy, p.dt, s.pec)
+    assert m["restriction"]["dead_ports"] == [2, 9, 17]
+    assert np.all(ms[0]["Lt"][:, [2, 9, 17]] == 0)
+    a = sim.run(p, ms, mode="literal")
+    b_lit = sim.run(p, ms, mode="closed")
+    pp = copy.deepcopy(p)
+    pp.eps_r[s.j0:s.j0 + s.nj, s.i0:s.i0 + s.ni] = s.eps_r
+    pp.sigma[s.j0:s.j0 + s.nj, s.i0:s.i0 + s.ni] = s.sigma
+    pp.pec[s.j0:s.j0 + s.nj, s.i0:s.i0 + s.ni] = s.pec
+    pp.roms = []
+    b = sim.run(pp, [])
+    assert np.abs(b).max() > 0
+    assert rel_l2(a, b) < 1e-13
+    assert rel_l2(b_lit, b) < 1e-13
+
+
+def test_partially_pinned_port_rejected():
+    p = _pec_problem(2)
+    s = p.roms[0]
+    s.pec = np.zeros_like(s.pec)
+    s.pec[0, 0] = True                         # one of S port 0's two fine edges
+    with pytest.raises(ValueError):
+        fine.restricted_model(s.eps_r, s.sigma, 2, p.dx, p.dy, p.dt, s.pec)
+
+
+def test_pec_reduced_models_passive_and_energy_exact():
+    """SPRIM models of a region with PEC cells (r = 2): Theorem 1 invariants,
+    the coupled one-step map's spectral radius <= 1 (Theorem 2) and the
+    exact energy balance of a lossy run."""
+    p = _pec_problem(2, q=12, seed=5, nsteps=40)
+    zero_sources(p)
+    ms = sim.build_roms(p)
+    m = ms[0]
+    assert np.all(np.linalg.eigvalsh(m["Rt"]) > 0)
+    assert np.min(np.linalg.eigvalsh(m["Ft"] + m["Ft"].T)) > -1e-12 * np.abs(m["Ft"]).max()
+    assert np.all(m["Lt"][:, [2, 9, 17]] == 0)
+    rho = np.max(np.abs(np.linalg.eigvals(one_step_matrix(p, ms))))
+    assert rho < 1 + 1e-9
+    rng = np.random.default_rng(2)
+    init = dict(hz=rng.standard_normal((p.ny, p.nx)), ex=rng.standard_normal((p.ny + 1, p.nx)) * 300,
+                ey=rng.standard_normal((p.ny, p.nx + 1)) * 300, x=[rng.standard_normal(m["Rt"].shape[0])])
+    run = sim.CoupledRun(p, ms, mode="literal", init=init)
+    e_first = run.energy()
+    for n in range(40):
+        e0 = run.energy()
+        ex0, ey0, x0 = run.f.ex.copy(), run.f.ey.copy(), [x.copy() for x in run.x]
+        run.step()
+        d = run.dissipation(ex0, ey0, x0)
+        assert abs(run.energy() - e0 + d) <= 1e-13 * e_first
+        assert d >= -1e-14 * e_first

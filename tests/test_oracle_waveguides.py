@@ -70,10 +70,25 @@ def test_iris_geometry_and_sizes():
         assert s.i0 - 1 >= p.pml.n_xlo and s.i0 + s.ni + 1 <= p.nx - p.pml.n_xhi
     # 0.99 x a two-fold extension of the fine limit: the CFL number 1.98
     assert _fine_cfl_number(p) == pytest.approx(1.98, rel=1e-12)
-    # each iris: metal on one fine column but for an aperture of 18 cells
+    # each iris: a PEC plate one fine cell thick (fine column 16) but for an
+    # aperture of 18 fine cells, as wide as the coarse column in the first
+    # and last fine rows, continued by PEC coarse cells up to the walls
     for s in p.roms:
-        metal = s.sigma > 0
-        assert metal.sum() == 30 - 18 and np.all(metal.any(axis=0) == (np.arange(30) == 15))
+        assert not np.any(s.sigma) and np.all(s.eps_r == 1.0)
+        assert s.pec.sum() == (30 - 18) + 4
+        assert np.all(s.pec[1:-1].any(axis=0) == (np.arange(30) == 16))
+        assert np.all(s.pec[0] == s.pec[-1]) and np.all(s.pec[0] == ((np.arange(30) >= 15) & (np.arange(30) < 18)))
+        assert np.all(s.pec.any(axis=1) == ((np.arange(30) < 6) | (np.arange(30) >= 24)))
+        ci = s.i0 + s.ni // 2
+        assert np.all(p.pec[:, ci] == ((np.arange(14) < 2) | (np.arange(14) >= 12)))
+    assert p.pec.sum() == 8
+    # restricted model: the plates' 16 Hz, 16 Ex and 28 Ey samples and the
+    # two coarse ports they cover (S and N of the middle column) drop out
+    s = p.roms[0]
+    m = fine.restricted_model(s.eps_r, s.sigma, s.r, p.dx, p.dy, p.dt, s.pec)
+    assert m["n"] == 2680 - 16 - 16 - 28 - 2
+    assert m["restriction"]["dead_ports"] == [5, 15]
+    assert np.all(m["L"].toarray()[:, [5, 15]] == 0)
 
 
 def test_rods_geometry_and_sizes():
@@ -144,7 +159,8 @@ def test_method_variants_agree_and_all_coarse_does_not():
     the whole fine model with the extended step ("CFL extension only")
     agrees with the proposed method within 5e-3, reducing without the
     extension ("MOR only", half the step) within 5e-2, while the all-coarse
-    mesh, which cannot resolve the irises, is off by more than 10 % (the
+    mesh, which cannot resolve the thin irises (it sees each as a plate one
+    coarse cell thick), is off by more than 5 %, above either variant (the
     paper's reading of its frequency responses; thresholds are ours)."""
     n = 1500
     series = {}
@@ -153,7 +169,7 @@ def test_method_variants_agree_and_all_coarse_does_not():
         cfg = W.ABLATIONS[mode]
         roms = osim.build_roms(p, basis=cfg["basis"], clip=cfg["clip"]) if p.roms else []
         if mode == "cfl_only":
-            assert [m["Rt"].shape[0] for m in roms] == [2680, 2680]
+            assert [m["Rt"].shape[0] for m in roms] == [2618, 2618]
         pr, _ = _run(p, roms, p.nsteps)
         series[mode] = (np.arange(p.nsteps) * p.dt, pr[:, 0])
     t0, ref = series["proposed"]
@@ -162,6 +178,7 @@ def test_method_variants_agree_and_all_coarse_does_not():
         t, v = series[mode]
         return np.linalg.norm(np.interp(t0, t, v) - ref) / np.linalg.norm(ref)
 
+    print({m: float(err(m)) for m in ("cfl_only", "mor_only", "coarse")})
     assert err("cfl_only") < 5e-3, err("cfl_only")
     assert err("mor_only") < 5e-2, err("mor_only")
-    assert err("coarse") > 0.1, err("coarse")
+    assert err("coarse") > 5e-2 and err("coarse") > err("mor_only"), err("coarse")

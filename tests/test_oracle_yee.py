@@ -131,3 +131,42 @@ def test_fp32_coefficients_match_formula():
     assert a[0][4, 4] == pytest.approx((e / dt - s / 2) / (e / dt + s / 2), rel=1e-14)
     assert a[1][4, 4] == pytest.approx(1 / (e / dt + s / 2) / dy, rel=1e-14)
     assert a[4] == pytest.approx(dt / (MU0 * dy), rel=1e-15)
+
+
+def test_pec_column_splits_cavity_into_two():
+    """A column of PEC cells across a cavity: every edge of those cells stays
+    zero and their Hz too, so the one-step map falls apart into the two
+    PEC cavities on either side - its non-zero eigenvalues are exactly the
+    textbook Yee spectra of those two boxes (walls at the PEC cells' west
+    and east faces)."""
+    nx, ny, dx, dy = 13, 5, 0.01, 0.012
+    c = C0
+    dt = 0.9 * yee.cfl_dt(dx, dy, c)
+    p = _cavity(nx, ny, dx, dy, dt)
+    p.pec = np.zeros((ny, nx), dtype=bool)
+    p.pec[:, 6] = True
+    M = one_step_matrix(p)
+    lam = np.linalg.eigvals(M)
+    lam = lam[np.abs(lam) > 1e-6]
+    assert np.allclose(np.abs(lam), 1.0, atol=1e-10)
+    ang = np.sort(np.abs(np.angle(lam)))
+    expect = []
+    for sub_nx in (6, 6):
+        for m in range(sub_nx):
+            for n in range(ny):
+                if m == 0 and n == 0:
+                    continue
+                s = c * dt * math.sqrt(math.sin(m * math.pi / (2 * sub_nx)) ** 2 / dx ** 2
+                                       + math.sin(n * math.pi / (2 * ny)) ** 2 / dy ** 2)
+                w = 2 * math.asin(s)
+                expect += [w, w]
+        expect += [0.0] * ((sub_nx - 1) * (ny - 1) + 1)
+    expect = np.sort(np.array(expect))
+    assert ang.size == expect.size
+    assert np.max(np.abs(ang - expect)) < 1e-8
+    # and a run keeps the PEC samples at zero
+    run = sim.CoupledRun(p, [], init=dict(hz=np.ones((ny, nx)), ex=np.ones((ny + 1, nx)),
+                                          ey=np.ones((ny, nx + 1)), x=[]))
+    for _ in range(5):
+        run.step()
+    assert not np.any(run.f.hz[:, 6]) and not np.any(run.f.ey[:, 6:8]) and not np.any(run.f.ex[:, 6])

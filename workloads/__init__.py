@@ -72,6 +72,7 @@ class RomSpec:
     sigma: np.ndarray   # fine-cell conductivity in S/m  [r*nj, r*ni]
     f_max: float        # source bandwidth in Hz (sets the expansion point)
     group: int = -1     # regions with equal group >= 0 share one model
+    pec: Optional[np.ndarray] = None   # fine cells that are perfect conductors [r*nj, r*ni]
 
     @property
     def n_ports(self) -> int:
@@ -115,6 +116,7 @@ class Problem:
     nsteps: int
     dtype: str          # "f64" or "f32"
     pml: Optional[Pml] = None
+    pec: Optional[np.ndarray] = None   # coarse cells that are perfect conductors [ny, nx]
 
     @property
     def ncells(self) -> int:
@@ -393,52 +395,63 @@ def stencil_only(n: int = 8192, nsteps: int = 200, material: bool = True,
                    [Probe(HZ, n // 4, n // 4)], nsteps, dtype)
 
 
-# Conductivity standing in for metal: copper for the rods (Sec. VI-C) and
-# for the "PEC" irises (Sec. VI-B), whose thickness the paper does not give.
+# Conductivity of the copper rods (Sec. VI-C).
 SIGMA_COPPER = 5.8e7
 
 
 def iris_waveguide(nsteps: int = 4000, q: int = 648, irises: bool = True,
                    dtype: str = "f64", aperture: int = 18, f_bw: float = 0.4e9,
                    cfl_gain: float = 2.0) -> Problem:
-    """Waveguide with two thin metal irises (Sec. VI-B): 4 m x 0.7 m, 5 cm
+    """Waveguide with two thin PEC irises (Sec. VI-B): 4 m x 0.7 m, 5 cm
     coarse cells (80 x 14), PEC walls at y = 0 and 0.7 m, absorbing layers 10
     coarse cells deep at both x ends.  Two 0.5 m x 0.5 m regions (10 x 10
     coarse cells at i0 = 25 and 45, j0 = 2) refined 3-fold (30 x 30 fine
     cells, 2,760 states) are replaced by order-``q`` models.
 
-    The iris geometry is only drawn in the paper; here each iris is one fine
-    cell thick, on the fine column at the region's middle (x = 1.5 m and
-    2.5 m), metal from both walls to a centred aperture of ``aperture`` fine
-    cells (0.3 m); outside the region the plates continue as metal coarse
-    cells of the same column.  Excitation: a Gaussian current pulse
-    (``f_bw`` bandwidth) on an Ey line across the guide at i = 12; probes at
-    the far end (Hz, Ey at i = 67) and near the source (Hz at i = 14).
-    dt = cfl_gain x 0.99 x the fine mesh's vacuum Courant limit."""
+    The iris geometry is only drawn in the paper and its thickness is not
+    given; here each iris is a perfectly conducting plate one fine cell
+    (1.67 cm) thick on the middle fine column of the region's middle coarse
+    column (x in [1.517, 1.533] m and [2.517, 2.533] m), from both edges of
+    the region to a centred aperture of ``aperture`` fine cells (0.3 m).
+    Between the region and the walls the plates continue as PEC coarse
+    cells of that coarse column (the coarse mesh has nothing thinner); in
+    the region's first and last fine rows the plate takes the whole coarse
+    column's width, so that the coarse interface edge where it meets the
+    continuation is PEC over all its fine edges (eq. (15) ties them).
+    Excitation: a Gaussian current pulse (``f_bw`` bandwidth) on an Ey line
+    across the guide at i = 12; probes at the far end (Hz, Ey at i = 67)
+    and near the source (Hz at i = 14).  dt = cfl_gain x 0.99 x the fine
+    mesh's vacuum Courant limit."""
     nx, ny = 80, 14
     dx = dy = 0.05
     r = 3
     dt = cfl_gain * courant_dt(dx / r, dy / r, 0.99)
     eps = np.ones((ny, nx))
     sig = np.zeros((ny, nx))
+    pec = np.zeros((ny, nx), dtype=bool)
     roms = []
     for i0 in (25, 45):
         fe = uniform_fine(10, 10, r, 1.0)
         fs = uniform_fine(10, 10, r, 0.0)
+        fp = None
         if irises:
-            mid = r * 10 // 2
+            c0 = r * (10 // 2)
+            mid = c0 + r // 2
             lo = (r * 10 - aperture) // 2
-            fs[:lo, mid] = SIGMA_COPPER
-            fs[lo + aperture:, mid] = SIGMA_COPPER
+            fp = np.zeros((r * 10, r * 10), dtype=bool)
+            fp[:lo, mid] = True
+            fp[lo + aperture:, mid] = True
+            fp[0, c0:c0 + r] = True
+            fp[-1, c0:c0 + r] = True
             ci = i0 + 10 // 2
-            sig[:2, ci] = SIGMA_COPPER
-            sig[12:, ci] = SIGMA_COPPER
+            pec[:2, ci] = True
+            pec[12:, ci] = True
         roms.append(RomSpec(i0=i0, j0=2, ni=10, nj=10, r=r, q=q, eps_r=fe, sigma=fs,
-                            f_max=f_bw))
+                            f_max=f_bw, pec=fp))
     src = Source(EY, 12, 13, 0, ny, gaussian(nsteps, dt, f_bw, t_offset=0.5 * dt))
     probes = [Probe(HZ, 67, 7), Probe(EY, 67, 7), Probe(HZ, 14, 7)]
     return Problem("E3-irises" if irises else "E3-empty", nx, ny, dx, dy, dt, eps, sig, roms,
-                   [src], probes, nsteps, dtype, Pml(10, 10, 0, 0))
+                   [src], probes, nsteps, dtype, Pml(10, 10, 0, 0), pec if irises else None)
 
 
 def rods_reflection(nsteps: int = 2000, q: int = 1920, rods: bool = True,
@@ -525,13 +538,16 @@ def ablation(make, mode: str, proposed_steps: int, **kw) -> Problem:
         n = int(math.ceil(proposed_steps * base.dt / dt))
         p = make(nsteps=n, **kw)
         eps, sig = p.eps_r.copy(), p.sigma.copy()
+        pec = np.zeros((p.ny, p.nx), dtype=bool) if p.pec is None else p.pec.copy()
         for s in p.roms:
             c = s.r // 2
             eps[s.j0:s.j0 + s.nj, s.i0:s.i0 + s.ni] = s.eps_r[c::s.r, c::s.r]
             sig[s.j0:s.j0 + s.nj, s.i0:s.i0 + s.ni] = s.sigma[c::s.r, c::s.r]
+            if s.pec is not None:
+                pec[s.j0:s.j0 + s.nj, s.i0:s.i0 + s.ni] = s.pec[c::s.r, c::s.r]
         src = [dataclasses.replace(x, incr=_resample(x.incr, p.dt, dt, n)) for x in p.sources]
         return dataclasses.replace(p, name=p.name + "-coarse", dt=dt, eps_r=eps, sigma=sig, roms=[],
-                                   sources=src, nsteps=n)
+                                   sources=src, nsteps=n, pec=pec if pec.any() else None)
     raise ValueError(mode)
 
 
@@ -541,6 +557,37 @@ def _resample(incr: np.ndarray, dt_old: float, dt_new: float, n: int) -> np.ndar
     t_old = np.arange(len(incr)) * dt_old
     t_new = np.arange(n) * dt_new
     return np.interp(t_new, t_old, incr, right=0.0) * (dt_new / dt_old)
+
+
+def pec_problem(seed: int = 1, r: int = 2, q: int = 12, nsteps: int = 150, dtype: str = "f64",
+                nx: int = 20, ny: int = 18) -> Problem:
+    """A small random problem with one 5 x 4 region that holds PEC fine
+    cells: a plate from the region's South boundary (continued by PEC coarse
+    cells down to the wall, so the port it covers carries no field), a PEC
+    fine cell in the North-East corner (two more such ports) and one
+    interior PEC fine cell; sources and probes stay on free samples."""
+    p = random_problem(seed, nx, ny, nsteps, nroms=1, block=(5, 4), r=r, q=q, dtype=dtype)
+    s = p.roms[0]
+    fp = np.zeros((r * s.nj, r * s.ni), dtype=bool)
+    fp[: 2 * r, 2 * r:3 * r] = True             # plate over South port 2
+    fp[3 * r:, 4 * r:] = True                   # North-East corner cell: North port 4, East port 3
+    fp[r, r] = True                             # an interior fine cell
+    s.pec = fp
+    pec = np.zeros((p.ny, p.nx), dtype=bool)
+    pec[: s.j0, s.i0 + 2] = True                # the plate's coarse continuation
+    p.pec = pec
+
+    def free(comp, i, j):
+        if comp == HZ:
+            return not pec[j, i]
+        if comp == EX:
+            return not (pec[j, i] if j < p.ny else False) and not (pec[j - 1, i] if j >= 1 else False)
+        return not (pec[j, i] if i < p.nx else False) and not (pec[j, i - 1] if i >= 1 else False)
+    for src in p.sources:
+        assert all(free(src.comp, i, j) for j in range(src.j0, src.j1) for i in range(src.i0, src.i1))
+    p.probes = [pr for pr in p.probes if free(pr.comp, pr.i, pr.j)]
+    assert p.probes
+    return p
 
 
 def random_problem(seed: int, nx: int, ny: int, nsteps: int, nroms: int = 2,
