@@ -59,13 +59,20 @@ enum { FDTD_HZ = 0, FDTD_EX = 1, FDTD_EY = 2 };
 /* Coarse grid (eqs. (1), (3), (5)).  eps_r / sigma: host [ny*nx] relative
  * permittivity and conductivity (S/m) per cell; NULL means 1 / 0.  Edge
  * material is the mean over the two cells sharing the edge (eq. (3)).
- * dtype: FDTD_F32 or FDTD_F64 arithmetic and storage on the device. */
+ * dtype: FDTD_F32 or FDTD_F64 arithmetic and storage on the device.
+ * pec: host [ny*nx], non-zero marks a perfectly conducting cell (metal such
+ * as the irises of Sec. VI-B): its Hz and the E on its four edges stay zero
+ * (their eps_r / sigma are not used); NULL means none.  A PEC cell may not
+ * lie inside a reduced region; one on a region's ring faces a port that the
+ * model must not drive (that port's column of Lt all zero, FDTD_EINVAL
+ * otherwise), and sources and probes may not sit on its samples. */
 typedef struct {
   int32_t nx, ny;
   double dx, dy, dt;
   int32_t dtype;
   const double* eps_r;
   const double* sigma;
+  const uint8_t* pec;
 } fdtd_grid;
 
 /* One embedded reduced model (eqs. (11)-(12)), built on coarse ports.
@@ -278,6 +285,12 @@ int fdtd_rom_coupled_update(const fdtd_problem* prob, int32_t k, double* A, doub
  * this is the paper's "CFL extension only" configuration (Tabs. I-III), with
  * basis 0 and clip = 0 at dt within the fine limit its "MOR only" one.
  * eps_r, sigma: host fine-cell maps [(r*nj) * (r*ni)], row-major.
+ * pec: host fine-cell map of the same shape, non-zero marks a perfectly
+ * conducting fine cell (NULL: none).  Its Hz and the E on its edges are zero
+ * and are left out of the fine model; a coarse port whose r fine edges all
+ * lie on PEC cells has no coordinate (its column of Lt is zero), and a port
+ * with only some of them on PEC cells is rejected (FDTD_EINVAL: eq. (15)
+ * ties the r fine edges to one value).
  * Outputs (caller-allocated, row-major): Rt [q*q], Ft [q*q], Lt [q*np];
  * state order: q1 E coordinates then q2 H coordinates.  With Rt, Ft and Lt
  * all NULL the call only fills info (q1, q2 and the restricted state count
@@ -293,6 +306,7 @@ typedef struct {
   double theta;
   int32_t clip;
   int32_t basis;  /* 0: SPRIM (steps 2-4), 1: identity */
+  const uint8_t* pec;
 } fdtd_rom_build_params;
 
 typedef struct {

@@ -21,9 +21,13 @@ FDTD_HZ, FDTD_EX, FDTD_EY = 0, 1, 2
 _dp = C.POINTER(C.c_double)
 
 
+_u8p = C.POINTER(C.c_uint8)
+
+
 class fdtd_grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
-                ("dt", C.c_double), ("dtype", C.c_int32), ("eps_r", _dp), ("sigma", _dp)]
+                ("dt", C.c_double), ("dtype", C.c_int32), ("eps_r", _dp), ("sigma", _dp),
+                ("pec", _u8p)]
 
 
 class fdtd_rom(C.Structure):
@@ -58,7 +62,7 @@ class fdtd_rom_build_params(C.Structure):
     _fields_ = [("ni", C.c_int32), ("nj", C.c_int32), ("r", C.c_int32), ("dx", C.c_double),
                 ("dy", C.c_double), ("dt", C.c_double), ("eps_r", _dp), ("sigma", _dp),
                 ("q", C.c_int32), ("f_max", C.c_double), ("theta", C.c_double),
-                ("clip", C.c_int32), ("basis", C.c_int32)]
+                ("clip", C.c_int32), ("basis", C.c_int32), ("pec", _u8p)]
 
 
 class fdtd_rom_build_info(C.Structure):
@@ -168,6 +172,16 @@ def _ptr(a):
     return a.ctypes.data_as(_dp) if a is not None else None
 
 
+def _mask(m, keep, shape):
+    """A boolean map as a contiguous uint8 array (kept alive in ``keep``)."""
+    if m is None:
+        return None
+    a = np.ascontiguousarray(np.asarray(m, dtype=bool).astype(np.uint8))
+    assert a.shape == shape, (a.shape, shape)
+    keep.append(a)
+    return a.ctypes.data_as(_u8p)
+
+
 # ---------------------------------------------------------------------------
 # marshalling of a problem description
 # ---------------------------------------------------------------------------
@@ -176,7 +190,7 @@ class ProblemStruct:
     """Owns the C structs and the contiguous float64 arrays they point to."""
 
     def __init__(self, nx, ny, dx, dy, dt, dtype, eps_r, sigma, roms, sources, probes,
-                 max_steps, pml=None):
+                 max_steps, pml=None, pec=None):
         self._keep = []
 
         def arr(x):
@@ -186,7 +200,7 @@ class ProblemStruct:
             self._keep.append(a)
             return a
         g = fdtd_grid(nx, ny, dx, dy, dt, FDTD_F64 if dtype in ("f64", FDTD_F64) else FDTD_F32,
-                      _ptr(arr(eps_r)), _ptr(arr(sigma)))
+                      _ptr(arr(eps_r)), _ptr(arr(sigma)), _mask(pec, self._keep, (ny, nx)))
         rarr = (fdtd_rom * max(1, len(roms)))()
         for k, r in enumerate(roms):
             Rt, Ft, Lt = arr(r["Rt"]), arr(r["Ft"]), arr(r["Lt"])
@@ -220,7 +234,8 @@ class ProblemStruct:
         prbs = [dict(comp=p.comp, i=p.i, j=p.j) for p in prob.probes]
         ms = prob.nsteps if max_steps is None else max_steps
         return cls(prob.nx, prob.ny, prob.dx, prob.dy, prob.dt, dtype or prob.dtype, prob.eps_r,
-                   prob.sigma, roms, srcs, prbs, ms, getattr(prob, "pml", None))
+                   prob.sigma, roms, srcs, prbs, ms, getattr(prob, "pml", None),
+                   getattr(prob, "pec", None))
 
 
 # ---------------------------------------------------------------------------
@@ -304,17 +319,19 @@ def fdtd_rom_coupled_update(problem: ProblemStruct, k: int):
 
 
 def fdtd_rom_build(ni, nj, r, dx, dy, dt, eps_r, sigma, q, f_max, theta=0.99, clip=True,
-                   basis="sprim"):
+                   basis="sprim", pec=None):
     """Model of one refined region (host FP64 in the library).  basis
     'sprim' reduces to order q; 'identity' keeps the restricted fine model
-    (q is then its state count and the argument is ignored)."""
+    (q is then its state count and the argument is ignored).  pec: fine
+    cells that are perfect conductors, or None."""
     er = np.ascontiguousarray(eps_r, dtype=np.float64)
     sg = np.ascontiguousarray(sigma, dtype=np.float64)
     assert er.shape == (r * nj, r * ni) and sg.shape == er.shape
     b = {"sprim": 0, "identity": 1}[basis]
     np_ = 2 * (ni + nj)
+    keep = []
     prm = fdtd_rom_build_params(ni, nj, r, dx, dy, dt, _ptr(er), _ptr(sg), q, f_max, theta,
-                                1 if clip else 0, b)
+                                1 if clip else 0, b, _mask(pec, keep, er.shape))
     info = fdtd_rom_build_info()
     if b == 1:
         _check(lib().fdtd_rom_build(C.byref(prm), None, None, None, C.byref(info)))

@@ -302,6 +302,7 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
     return dev_err("gradient read");
   const int nx = s->nx, ny = s->ny, P = s->pitch;
   std::vector<unsigned char> held((size_t)nx * ny, 0);
+  for (size_t c = 0; c < s->pec.size(); ++c) held[c] = s->pec[c] ? 1 : 0;  // metal: no material gradient
   for (const RomHost& h : s->roms)
     for (int j = std::max(h.j0 - 1, 0); j < std::min(h.j0 + h.nj + 1, ny); ++j)
       for (int i = std::max(h.i0 - 1, 0); i < std::min(h.i0 + h.ni + 1, nx); ++i) held[(size_t)j * nx + i] = 1;

@@ -76,9 +76,13 @@ struct FineModel {
 };
 
 // Restricted fine model.  E order: interior Ex (j = 1..Ny-1, i), interior Ey
-// (j, i = 1..Nx-1), ports S, N, W, E; H order: j * Nx + i.
-void assemble(FineModel& m, int ni, int nj, int r, double dx, double dy, double dt, const double* er,
-              const double* sg) {
+// (j, i = 1..Nx-1), ports S, N, W, E; H order: j * Nx + i.  Samples on PEC
+// fine cells (pec != nullptr: the cell's Hz and its four edges) are pinned to
+// zero and left out of the state; a coarse port whose r fine edges are all
+// pinned has no coordinate (port_row = -1).  Returns false, with a message,
+// when a port has only some of its fine edges pinned.
+bool assemble(FineModel& m, int ni, int nj, int r, double dx, double dy, double dt, const double* er,
+              const double* sg, const uint8_t* pec, std::string& err) {
   m.ni = ni;
   m.nj = nj;
   m.r = r;
@@ -91,74 +95,115 @@ void assemble(FineModel& m, int ni, int nj, int r, double dx, double dy, double 
   m.dyh = dy / r;
   const int Nx = m.Nx, Ny = m.Ny;
   m.np = 2 * (ni + nj);
-  m.nEx = Nx * (Ny - 1);
-  m.nEy = (Nx - 1) * Ny;
-  m.nE = m.nEx + m.nEy + m.np;
-  m.nH = Nx * Ny;
-  m.n = m.nE + m.nH;
-  m.De.assign(m.nE, 0.0);
-  m.Ds.assign(m.nE, 0.0);
+  auto metal = [&](int i, int j) { return pec && i >= 0 && i < Nx && j >= 0 && j < Ny && pec[(size_t)j * Nx + i]; };
+  // pinned edges: a side of a PEC cell
+  auto pin_x = [&](int i, int j) { return metal(i, j - 1) || metal(i, j); };   // Ex(i, j)
+  auto pin_y = [&](int i, int j) { return metal(i - 1, j) || metal(i, j); };   // Ey(i, j)
+  // H coordinates
+  std::vector<int> hid((size_t)Nx * Ny, -1);
+  m.nH = 0;
+  for (int j = 0; j < Ny; ++j)
+    for (int i = 0; i < Nx; ++i)
+      if (!metal(i, j)) hid[(size_t)j * Nx + i] = m.nH++;
+  // port liveness (all r fine edges free, or all pinned)
+  std::vector<char> live(m.np, 1);
+  for (int c = 0; c < m.np; ++c) {
+    int npin = 0;
+    for (int k = 0; k < r; ++k) {
+      bool p;
+      if (c < ni) p = pin_x(c * r + k, 0);
+      else if (c < 2 * ni) p = pin_x((c - ni) * r + k, Ny);
+      else if (c < 2 * ni + nj) p = pin_y(0, (c - 2 * ni) * r + k);
+      else p = pin_y(Nx, (c - 2 * ni - nj) * r + k);
+      npin += p ? 1 : 0;
+    }
+    if (npin != 0 && npin != r) {
+      err = "coarse port " + std::to_string(c) + ": only some of its fine edges lie on PEC cells";
+      return false;
+    }
+    live[c] = npin == 0;
+  }
+  m.De.clear();
+  m.Ds.clear();
   m.Dm = kMu0 * m.dxh * m.dyh;
   const double A = m.dxh * m.dyh;
   auto E = [&](int i, int j) { return er[(size_t)j * Nx + i]; };
   auto S = [&](int i, int j) { return sg[(size_t)j * Nx + i]; };
-  std::vector<std::vector<std::pair<int, double>>> rows(m.nE);
+  auto H = [&](int i, int j) { return hid[(size_t)j * Nx + i]; };
+  std::vector<std::vector<std::pair<int, double>>> rows;
+  auto add_e = [&](double de, double ds, std::vector<std::pair<int, double>> k) {
+    m.De.push_back(de);
+    m.Ds.push_back(ds);
+    rows.push_back(std::move(k));
+  };
   for (int j = 1; j < Ny; ++j)
-    for (int i = 0; i < Nx; ++i) {
-      const int e = (j - 1) * Nx + i;
-      m.De[e] = A * kEps0 * 0.5 * (E(i, j - 1) + E(i, j));
-      m.Ds[e] = A * 0.5 * (S(i, j - 1) + S(i, j));
-      rows[e] = {{j * Nx + i, +m.dxh}, {(j - 1) * Nx + i, -m.dxh}};
-    }
+    for (int i = 0; i < Nx; ++i)
+      if (!pin_x(i, j))
+        add_e(A * kEps0 * 0.5 * (E(i, j - 1) + E(i, j)), A * 0.5 * (S(i, j - 1) + S(i, j)),
+              {{H(i, j), +m.dxh}, {H(i, j - 1), -m.dxh}});
+  m.nEx = (int)rows.size();
   for (int j = 0; j < Ny; ++j)
-    for (int i = 1; i < Nx; ++i) {
-      const int e = m.nEx + j * (Nx - 1) + (i - 1);
-      m.De[e] = A * kEps0 * 0.5 * (E(i - 1, j) + E(i, j));
-      m.Ds[e] = A * 0.5 * (S(i - 1, j) + S(i, j));
-      rows[e] = {{j * Nx + i, -m.dyh}, {j * Nx + i - 1, +m.dyh}};
-    }
-  const int pb = m.nEx + m.nEy;
+    for (int i = 1; i < Nx; ++i)
+      if (!pin_y(i, j))
+        add_e(A * kEps0 * 0.5 * (E(i - 1, j) + E(i, j)), A * 0.5 * (S(i - 1, j) + S(i, j)),
+              {{H(i, j), -m.dyh}, {H(i - 1, j), +m.dyh}});
+  m.nEy = (int)rows.size() - m.nEx;
   m.Sc.assign(m.np, 0.0);
-  m.port_row.assign(m.np, 0);
+  m.port_row.assign(m.np, -1);
   for (int c = 0; c < ni; ++c) {
-    const int eS = pb + c, eN = pb + ni + c;
     m.Sc[c] = -dx;
     m.Sc[ni + c] = +dx;
-    for (int i = c * r; i < (c + 1) * r; ++i) {
-      // boundary half cells of eq. (4), summed over the r fine edges
-      m.De[eS] += m.dxh * (m.dyh / 2) * kEps0 * E(i, 0);
-      m.Ds[eS] += m.dxh * (m.dyh / 2) * S(i, 0);
-      rows[eS].push_back({i, +m.dxh});
-      m.De[eN] += m.dxh * (m.dyh / 2) * kEps0 * E(i, Ny - 1);
-      m.Ds[eN] += m.dxh * (m.dyh / 2) * S(i, Ny - 1);
-      rows[eN].push_back({(Ny - 1) * Nx + i, -m.dxh});
-    }
   }
   for (int c = 0; c < nj; ++c) {
-    const int eW = pb + 2 * ni + c, eE = pb + 2 * ni + nj + c;
     m.Sc[2 * ni + c] = +dy;
     m.Sc[2 * ni + nj + c] = -dy;
-    for (int j = c * r; j < (c + 1) * r; ++j) {
-      m.De[eW] += m.dyh * (m.dxh / 2) * kEps0 * E(0, j);
-      m.Ds[eW] += m.dyh * (m.dxh / 2) * S(0, j);
-      rows[eW].push_back({j * Nx, -m.dyh});
-      m.De[eE] += m.dyh * (m.dxh / 2) * kEps0 * E(Nx - 1, j);
-      m.Ds[eE] += m.dyh * (m.dxh / 2) * S(Nx - 1, j);
-      rows[eE].push_back({j * Nx + Nx - 1, +m.dyh});
-    }
   }
-  for (int p = 0; p < m.np; ++p) m.port_row[p] = pb + p;
+  for (int c = 0; c < m.np; ++c) {
+    if (!live[c]) continue;
+    // boundary half cells of eq. (4), summed over the r fine edges
+    double de = 0, ds = 0;
+    std::vector<std::pair<int, double>> k;
+    for (int t = 0; t < r; ++t) {
+      if (c < ni) {
+        const int i = c * r + t;
+        de += m.dxh * (m.dyh / 2) * kEps0 * E(i, 0);
+        ds += m.dxh * (m.dyh / 2) * S(i, 0);
+        k.push_back({H(i, 0), +m.dxh});
+      } else if (c < 2 * ni) {
+        const int i = (c - ni) * r + t;
+        de += m.dxh * (m.dyh / 2) * kEps0 * E(i, Ny - 1);
+        ds += m.dxh * (m.dyh / 2) * S(i, Ny - 1);
+        k.push_back({H(i, Ny - 1), -m.dxh});
+      } else if (c < 2 * ni + nj) {
+        const int j = (c - 2 * ni) * r + t;
+        de += m.dyh * (m.dxh / 2) * kEps0 * E(0, j);
+        ds += m.dyh * (m.dxh / 2) * S(0, j);
+        k.push_back({H(0, j), -m.dyh});
+      } else {
+        const int j = (c - 2 * ni - nj) * r + t;
+        de += m.dyh * (m.dxh / 2) * kEps0 * E(Nx - 1, j);
+        ds += m.dyh * (m.dxh / 2) * S(Nx - 1, j);
+        k.push_back({H(Nx - 1, j), +m.dyh});
+      }
+    }
+    m.port_row[c] = (int)rows.size();
+    add_e(de, ds, std::move(k));
+  }
+  m.nE = (int)rows.size();
+  m.n = m.nE + m.nH;
   m.K.rows = m.nE;
   m.K.cols = m.nH;
   m.K.ptr.assign(m.nE + 1, 0);
   for (int e = 0; e < m.nE; ++e) {
     for (auto& pr : rows[e]) {
+      // every Hz next to a free edge is free (a PEC cell pins all its edges)
       m.K.col.push_back(pr.first);
       m.K.val.push_back(pr.second);
     }
     m.K.ptr[e + 1] = (int)m.K.col.size();
   }
   m.KT = transpose(m.K);
+  return true;
 }
 
 // Banded Cholesky of an SPD matrix with half-bandwidth bw; L(i, i-d) at
@@ -284,6 +329,7 @@ bool krylov_dirs(Solver& sol, const FineModel& fm, int ncols, Cols& dirs, std::s
   Cols X(fm.np, std::vector<double>(n, 0.0));
   std::vector<double> rhs(n);
   for (int p = 0; p < fm.np; ++p) {
+    if (fm.port_row[p] < 0) continue;  // port pinned by PEC: no input (zero column, deflated)
     std::fill(rhs.begin(), rhs.end(), 0.0);
     rhs[fm.port_row[p]] = fm.Sc[p];
     sol.solve(rhs.data(), X[p].data());
@@ -435,7 +481,11 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
     if (!(P.eps_r[k] > 0) || !(P.sigma[k] >= 0)) return fail(FDTD_EINVAL, "fine material must have eps_r > 0, sigma >= 0");
   try {
     FineModel fm;
-    assemble(fm, P.ni, P.nj, P.r, P.dx, P.dy, P.dt, P.eps_r, P.sigma);
+    {
+      std::string err;
+      if (!assemble(fm, P.ni, P.nj, P.r, P.dx, P.dy, P.dt, P.eps_r, P.sigma, P.pec, err))
+        return fail(FDTD_EINVAL, "%s", err.c_str());
+    }
     const int q1 = ident ? fm.nE : (P.q + 1) / 2, q2 = ident ? fm.nH : P.q / 2;
     if (query) {
       info->q1 = q1;
@@ -636,7 +686,8 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
       }
     for (int a = 0; a < q; ++a)
       for (int p = 0; p < np; ++p)
-        Lt[(size_t)a * np + p] = a < q1 ? (ident ? (a == fm.port_row[p] ? 1.0 : 0.0) : V1[a][fm.port_row[p]]) : 0.0;
+        Lt[(size_t)a * np + p] = (a >= q1 || fm.port_row[p] < 0) ? 0.0
+                                 : ident ? (a == fm.port_row[p] ? 1.0 : 0.0) : V1[a][fm.port_row[p]];
     if (info) {
       info->q1 = q1;
       info->q2 = q2;

@@ -292,15 +292,18 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
     if ((rc = up(L.off_fc + fb, ex.data(), fb)) != FDTD_OK) return rc;
     if ((rc = up(L.off_fc + 2 * fb, ey.data(), fb)) != FDTD_OK) return rc;
   }
-  // per-cell material: a = eps0*eps_r/dt (negative inside regions), b = sigma/2
+  // per-cell material: a = eps0*eps_r/dt (negative inside regions, zero on
+  // PEC cells: the stencil then never updates the cell's Hz or its edges,
+  // as for the padding columns), b = sigma/2
   std::vector<T> al(fe, T(0)), be(fe, T(0));
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const size_t c = (size_t)j * nx + i;
       const double er = g.eps_r ? g.eps_r[c] : 1.0;
       const double sg = g.sigma ? g.sigma[c] : 0.0;
-      al[(size_t)j * P + i] = inside[c] ? T(-1) : (T)(kEps0 * er / g.dt);
-      be[(size_t)j * P + i] = inside[c] ? T(0) : (T)(sg / 2.0);
+      const bool metal = g.pec && g.pec[c];
+      al[(size_t)j * P + i] = inside[c] ? T(-1) : metal ? T(0) : (T)(kEps0 * er / g.dt);
+      be[(size_t)j * P + i] = (inside[c] || metal) ? T(0) : (T)(sg / 2.0);
     }
   if ((rc = up(L.off_al, al.data(), fb)) != FDTD_OK) return rc;
   if ((rc = up(L.off_be, be.data(), fb)) != FDTD_OK) return rc;
@@ -689,6 +692,18 @@ int coupling_precompute(const fdtd_problem* p, std::vector<RomHost>& out) {
   return FDTD_OK;
 }
 
+// Coarse cell just outside port c of region r (the ring cell whose Hz the
+// port gathers and whose half cell enters eq. (13)).
+struct PortCell {
+  int oi, oj;
+};
+PortCell port_cell(const fdtd_rom& r, int c) {
+  if (c < r.ni) return {r.i0 + c, r.j0 - 1};
+  if (c < 2 * r.ni) return {r.i0 + c - r.ni, r.j0 + r.nj};
+  if (c < 2 * r.ni + r.nj) return {r.i0 - 1, r.j0 + c - 2 * r.ni};
+  return {r.i0 + r.ni, r.j0 + c - 2 * r.ni - r.nj};
+}
+
 int validate_numbers(const fdtd_problem* p, const Layout& L, std::vector<unsigned char>& inside) {
   const fdtd_grid& g = p->grid;
   const int nx = g.nx, ny = g.ny;
@@ -730,9 +745,27 @@ int validate_numbers(const fdtd_problem* p, const Layout& L, std::vector<unsigne
       if (!sep) return fail(FDTD_EINVAL, "regions %d and %d: one-cell rings overlap", k, m);
     }
     for (int j = a.j0; j < a.j0 + a.nj; ++j)
-      for (int i = a.i0; i < a.i0 + a.ni; ++i) inside[(size_t)j * nx + i] = 1;
+      for (int i = a.i0; i < a.i0 + a.ni; ++i) {
+        if (g.pec && g.pec[(size_t)j * nx + i])
+          return fail(FDTD_EINVAL, "region %d: PEC cell (%d,%d) inside the region (describe it in the model)", k, i, j);
+        inside[(size_t)j * nx + i] = 1;
+      }
+    // a PEC ring cell pins the interface edge it shares with the region:
+    // the model must leave that port undriven
+    const int np = ports_of(a);
+    for (int c = 0; c < np; ++c) {
+      const PortCell pc = port_cell(a, c);
+      if (!(g.pec && g.pec[(size_t)pc.oj * nx + pc.oi])) continue;
+      for (int q = 0; q < a.q; ++q)
+        if (a.Lt[(size_t)q * np + c] != 0.0)
+          return fail(FDTD_EINVAL, "region %d: port %d faces PEC cell (%d,%d) but its column of Lt is not zero", k,
+                      c, pc.oi, pc.oj);
+    }
   }
-  auto cell_ok = [&](int i, int j) { return i >= 0 && i < nx && j >= 0 && j < ny && !inside[(size_t)j * nx + i]; };
+  auto is_pec = [&](int i, int j) { return g.pec && g.pec[(size_t)j * nx + i]; };
+  auto cell_ok = [&](int i, int j) {
+    return i >= 0 && i < nx && j >= 0 && j < ny && !inside[(size_t)j * nx + i] && !is_pec(i, j);
+  };
   auto active = [&](int comp, int i, int j) -> bool {
     if (comp == FDTD_HZ) return cell_ok(i, j);
     if (comp == FDTD_EX) return i >= 0 && i < nx && j >= 1 && j <= ny - 1 && cell_ok(i, j) && cell_ok(i, j - 1);
@@ -767,22 +800,20 @@ int validate_numbers(const fdtd_problem* p, const Layout& L, std::vector<unsigne
         (a.Ft != b.Ft && std::memcmp(a.Ft, b.Ft, sizeof(double) * q * q)) ||
         (a.Lt != b.Lt && std::memcmp(a.Lt, b.Lt, sizeof(double) * q * np)))
       return fail(FDTD_EINVAL, "region %d: group %d members have different matrices", k, b.group);
-    // identical surroundings (interface half cells)
-    auto ring = [&](const fdtd_rom& r, int c, double& e, double& s) {
-      int oi, oj;
-      if (c < r.ni) { oi = r.i0 + c; oj = r.j0 - 1; }
-      else if (c < 2 * r.ni) { oi = r.i0 + c - r.ni; oj = r.j0 + r.nj; }
-      else if (c < 2 * r.ni + r.nj) { oi = r.i0 - 1; oj = r.j0 + c - 2 * r.ni; }
-      else { oi = r.i0 + r.ni; oj = r.j0 + c - 2 * r.ni - r.nj; }
-      const size_t ci = (size_t)oj * nx + oi;
+    // identical surroundings (interface half cells, PEC ring cells)
+    auto ring = [&](const fdtd_rom& r, int c, double& e, double& s, bool& m) {
+      const PortCell pc = port_cell(r, c);
+      const size_t ci = (size_t)pc.oj * nx + pc.oi;
       e = g.eps_r ? g.eps_r[ci] : 1.0;
       s = g.sigma ? g.sigma[ci] : 0.0;
+      m = g.pec && g.pec[ci];
     };
     for (int c = 0; c < np; ++c) {
       double e1, s1, e2, s2;
-      ring(a, c, e1, s1);
-      ring(b, c, e2, s2);
-      if (e1 != e2 || s1 != s2)
+      bool m1, m2;
+      ring(a, c, e1, s1, m1);
+      ring(b, c, e2, s2, m2);
+      if (e1 != e2 || s1 != s2 || m1 != m2)
         return fail(FDTD_EINVAL, "region %d: group %d members sit in different material", k, b.group);
     }
   }
@@ -1192,6 +1223,12 @@ int fdtd_rom_create(const fdtd_problem* prob, void* dev_workspace, size_t ws_byt
     s->nsrc = prob->nsources;
     s->nroms = prob->nroms;
     if (prob->nprobes > 0) s->probes.assign(prob->probes, prob->probes + prob->nprobes);
+    if (prob->grid.pec)
+      for (size_t c = 0; c < (size_t)s->nx * s->ny; ++c)
+        if (prob->grid.pec[c]) {
+          s->pec.assign(prob->grid.pec, prob->grid.pec + (size_t)s->nx * s->ny);
+          break;
+        }
     s->stream = (hipStream_t)hip_stream;
     s->ws = (char*)dev_workspace;
     s->L = L;

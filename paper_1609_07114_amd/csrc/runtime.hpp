@@ -76,6 +76,7 @@ struct fdtd_rom_sim {
   bool shared_gemm = true;
   std::vector<fdtd::RomHost> roms;
   std::vector<fdtd_probe> probes;
+  std::vector<unsigned char> pec;    // PEC cells [ny*nx] (empty: none)
   fdtd::StepParams<float> sp_f;
   fdtd::StepParams<double> sp_d;
   int graph_batch = 0;               // > 0: replay captured batches of this many steps

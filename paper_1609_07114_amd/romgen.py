@@ -23,7 +23,8 @@ def build_roms(prob, theta=0.99, clip=True, workers=None, basis="sprim"):
 
     def one(spec):
         return capi.fdtd_rom_build(spec.ni, spec.nj, spec.r, prob.dx, prob.dy, prob.dt,
-                                   spec.eps_r, spec.sigma, spec.q, spec.f_max, theta, clip, basis)
+                                   spec.eps_r, spec.sigma, spec.q, spec.f_max, theta, clip, basis,
+                                   getattr(spec, "pec", None))
     workers = workers or min(len(jobs), max(1, min(16, os.cpu_count() or 1))) or 1
     if len(jobs) <= 1:
         built = [one(s) for s in jobs]
@@ -44,7 +45,8 @@ def build_roms_many(probs, theta=0.99, clip=True, workers=None):
     def one(job):
         prob, spec = job
         return capi.fdtd_rom_build(spec.ni, spec.nj, spec.r, prob.dx, prob.dy, prob.dt,
-                                   spec.eps_r, spec.sigma, spec.q, spec.f_max, theta, clip)
+                                   spec.eps_r, spec.sigma, spec.q, spec.f_max, theta, clip,
+                                   "sprim", getattr(spec, "pec", None))
     workers = workers or max(1, min(16, os.cpu_count() or 1))
     with ThreadPoolExecutor(max_workers=workers) as ex:
         built = list(ex.map(one, jobs))

@@ -1,6 +1,7 @@
 """CPU tests of the C-ABI library: it loads, exports every entry point the
 header declares, and its host-side logic (validation, the FP64 closed form
 of eq. (23)) agrees with the oracle.  No device call is made here."""
+import copy
 import ctypes
 import os
 import re
@@ -214,3 +215,39 @@ def test_closed_form_identity_basis_matches_oracle():
     assert np.max(np.abs(A - A0)) <= 1e-12 * np.max(np.abs(A0))
     assert np.max(np.abs(B - B0)) <= 1e-12 * np.max(np.abs(B0))
     assert np.array_equal(C, C0)
+
+
+def test_pec_cells_validation():
+    """PEC cells: accepted with a model that leaves the covered ports
+    undriven (closed form as the oracle's); rejected inside a region, on a
+    ring cell whose port the model drives, and under a source or probe."""
+    p = W.pec_problem(3, r=2, q=10)
+    roms = osim.build_roms(p)
+    assert np.all(roms[0]["Lt"][:, [2, 9, 17]] == 0)
+    spec, m = p.roms[0], roms[0]
+    c = ocp.RomCoupling(m["Rt"], m["Ft"], m["Lt"], spec.i0, spec.j0, spec.ni, spec.nj,
+                        p.eps_r, p.sigma, p.dx, p.dy, p.dt)
+    A0, B0, _ = c.closed_form()
+    A, B, _ = capi.fdtd_rom_coupled_update(_struct(p, roms), 0)
+    assert np.max(np.abs(A - A0)) <= 1e-12 * np.max(np.abs(A0))
+    assert np.max(np.abs(B - B0)) <= 1e-12 * np.max(np.abs(B0))
+    assert not np.any(B[:, [2, 9, 17]])
+    # a PEC ring cell in front of a port the model drives (South port 1)
+    q = copy.deepcopy(p)
+    q.pec[spec.j0 - 1, spec.i0 + 1] = True
+    with pytest.raises(capi.FdtdError, match="faces PEC"):
+        capi.fdtd_rom_coupled_update(_struct(q, roms), 0)
+    # a PEC cell inside the region
+    q = copy.deepcopy(p)
+    q.pec[spec.j0 + 1, spec.i0 + 1] = True
+    with pytest.raises(capi.FdtdError, match="inside the region"):
+        capi.fdtd_rom_coupled_update(_struct(q, roms), 0)
+    # a probe on an edge of a PEC cell, a source on a PEC cell
+    q = copy.deepcopy(p)
+    q.probes[0] = W.Probe(W.EY, spec.i0 + 2, 0)
+    assert _create_status(_struct(q, roms)) == capi.FDTD_EINVAL
+    q = copy.deepcopy(p)
+    q.sources[0].i0, q.sources[0].i1 = spec.i0 + 2, spec.i0 + 3
+    q.sources[0].j0, q.sources[0].j1 = 0, 1
+    q.sources[0].comp = W.HZ
+    assert _create_status(_struct(q, roms)) == capi.FDTD_EINVAL

@@ -1,11 +1,13 @@
 """The method variants of Tabs. I-III on the device, on the iris guide of
-Sec. VI-B: the all-coarse run (no regions), "MOR only" (order-648 models
-at the fine step) and "CFL extension only" (the whole restricted fine model,
-2680 states per region, clipped by eq. (27), at 1.98 of the fine limit: a
-dense 2720 x 2720 update per region and step) against the oracle on the
-same model inputs.  Bars as for the open guides: FP32 1e-5 relative L2 on
-the probes (fields relative to their peak norm); FP64 10x the oracle's own
-LU-vs-QR spread of eq. (23), never below 1e-12."""
+Sec. VI-B (Tab. II) and the rod reflection test of Sec. VI-C (Tab. III):
+the all-coarse run (no regions), "MOR only" (the reduced models at the fine
+step) and "CFL extension only" (the whole restricted fine model clipped by
+eq. (27) at the proposed step: a dense update of every fine state per region
+and step - 6,848 states for the rods) against the oracle on the same model
+inputs.  Bars as for the open guides: FP32 1e-5 relative L2 on the probes
+(fields relative to their peak norm); FP64 1e-12, except where copper
+conductivity makes eq. (23)'s matrix ill-conditioned (the rods): there 10x
+the oracle's own LU-vs-QR spread of eq. (23), never below 1e-12."""
 import numpy as np
 import pytest
 
@@ -17,21 +19,29 @@ from tests._util import rel_l2
 
 pytestmark = pytest.mark.gpu
 
-N = 600
+# guides whose eq. (23) matrix is ill-conditioned (copper at 5.8e7 S/m)
+ILL_CONDITIONED = {"E4"}
+
+# proposed-method steps whose simulated time every variant covers
+N = {"E3": 600, "E4": 300}
+GUIDES = {"E3": W.iris_waveguide, "E4": W.rods_reflection}
 
 
 @pytest.fixture(scope="module")
 def variants():
-    out = {}
-    for mode in ("coarse", "mor_only", "cfl_only"):
-        print(f"[gpu-abl] oracle models for {mode}", flush=True)
-        p = W.ablation(W.iris_waveguide, mode, N)
-        cfg = W.ABLATIONS[mode]
-        roms = osim.build_roms(p, basis=cfg["basis"], clip=cfg["clip"]) if p.roms else []
-        for s, m in zip(p.roms, roms):
-            s.q = m["Rt"].shape[0]
-        out[mode] = (p, roms)
-    return out
+    cache = {}
+
+    def get(guide, mode):
+        if (guide, mode) not in cache:
+            print(f"[gpu-abl] oracle models for {guide} {mode}", flush=True)
+            p = W.ablation(GUIDES[guide], mode, N[guide])
+            cfg = W.ABLATIONS[mode]
+            roms = osim.build_roms(p, basis=cfg["basis"], clip=cfg["clip"]) if p.roms else []
+            for s, m in zip(p.roms, roms):
+                s.q = m["Rt"].shape[0]
+            cache[(guide, mode)] = (p, roms)
+        return cache[(guide, mode)]
+    return get
 
 
 def _oracle(prob, roms, fp32, solver="lu"):
@@ -46,11 +56,12 @@ def _oracle(prob, roms, fp32, solver="lu"):
     return pr, [run.f.hz * run.cell, run.f.ex, run.f.ey], peak
 
 
+@pytest.mark.parametrize("guide", ["E3", "E4"])
 @pytest.mark.parametrize("mode", ["coarse", "mor_only", "cfl_only"])
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
-def test_variant_vs_oracle(variants, mode, dtype, tol):
-    p, roms = variants[mode]
-    print(f"[gpu-abl] {mode} {dtype} steps={p.nsteps} q={[s.q for s in p.roms]}", flush=True)
+def test_variant_vs_oracle(variants, guide, mode, dtype, tol):
+    p, roms = variants(guide, mode)
+    print(f"[gpu-abl] {guide} {mode} {dtype} steps={p.nsteps} q={[s.q for s in p.roms]}", flush=True)
     with Simulation(p, roms, dtype=dtype) as s:
         s.run(p.nsteps)
         g = s.probes(), [s.field(c) for c in range(3)]
@@ -62,9 +73,10 @@ def test_variant_vs_oracle(variants, mode, dtype, tol):
             for c in range(3)]
 
     bars = [tol] * 4
-    if dtype == "f64" and roms:
+    if dtype == "f64" and roms and guide in ILL_CONDITIONED:
         spread = errors(_oracle(p, roms, False, solver="qr"))
-        print(f"[gpu-abl] {mode} FP64 oracle LU vs QR spread {['%.2e' % v for v in spread]}", flush=True)
+        print(f"[gpu-abl] {guide} {mode} FP64 oracle LU vs QR spread {['%.2e' % v for v in spread]}",
+              flush=True)
         bars = [max(tol, 10.0 * v) for v in spread]
     for what, e, b in zip(("probes", "hz", "ex", "ey"), errors(g), bars):
         assert e <= b, (what, e, b)
@@ -74,7 +86,7 @@ def test_library_identity_build_runs_cfl_only(variants):
     """The same variant with the library's own identity-basis builder: the
     device run stays bounded and tracks the oracle-model run closely (two
     builds of the same clipped fine model)."""
-    p, roms = variants["cfl_only"]
+    p, roms = variants("E3", "cfl_only")
     lib = romgen.build_roms(p, basis="identity")
     assert [m["Rt"].shape[0] for m in lib] == [s.q for s in p.roms]
     with Simulation(p, lib) as s:

@@ -158,3 +158,53 @@ def test_c4_full_size_sampled():
     assert rel_l2(got[k_or], pr) <= 1e-5, rel_l2(got[k_or], pr)
     for c in range(3):
         assert rel_l2(fl[c], ofl[c]) <= 1e-5, (c, rel_l2(fl[c], ofl[c]))
+
+
+def _c4_oracle_instance(b, n):
+    """Spawned worker: oracle-built models of C4 instance b and the oracle's
+    FP32-problem run of it over n steps (probes, final fields)."""
+    import workloads as W_
+    from oracle import sim as osim_
+    p = W_.batch_c4()[b]
+    roms = osim_.build_roms(p)
+    run = osim_.CoupledRun(p, roms, mode="closed", fp32=True)
+    pr = np.empty((n, len(p.probes)))
+    for k in range(n):
+        run.step()
+        pr[k] = run.probes()
+    return b, roms, pr, [run.f.hz * run.cell, run.f.ex, run.f.ey]
+
+
+def test_c4_many_instances_vs_oracle():
+    """Eight instances of the 64-instance workload - the five smallest grids
+    and the three largest, 1 to 7 models each - run inside the full batch
+    with oracle-built models (the other 56 with the library's), each against
+    the oracle's run of its FP32 problem: probes and final fields within
+    1e-5 relative L2, and the maximum over instances reported.  The oracle
+    runs in spawned worker processes (no GPU use there)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    probs = W.batch_c4()
+    order = sorted(range(len(probs)), key=lambda b: probs[b].nx * probs[b].ny)
+    picked = order[:5] + order[-3:]
+    n = 500
+    print(f"[gpu-batch] C4 oracle for instances {picked}", flush=True)
+    workers = max(1, min(len(picked), (os.cpu_count() or 2) // 2, 8))
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        res = {b: (m, pr, fl) for b, m, pr, fl in ex.map(_c4_oracle_instance, picked, [n] * len(picked))}
+    roms = romgen.build_roms_many(probs)
+    for b in picked:
+        roms[b] = res[b][0]
+    print("[gpu-batch] C4 batch with oracle models", flush=True)
+    with Batch(probs, roms, max_steps=n) as bt:
+        bt.set_graph(100)
+        bt.run(n)
+        got = {b: (bt.probes(b), [bt.field(b, c) for c in range(3)]) for b in picked}
+    worst = 0.0
+    for b in picked:
+        _, pr, fl = res[b]
+        assert np.abs(pr).max() > 0, b
+        e = [rel_l2(got[b][0], pr)] + [rel_l2(got[b][1][c], fl[c]) for c in range(3)]
+        worst = max(worst, max(e))
+        assert max(e) <= 1e-5, (b, e)
+    print(f"[gpu-batch] C4 worst instance rel L2 vs oracle {worst:.2e}", flush=True)

@@ -282,3 +282,46 @@ def test_shared_model_mfma_gemm(q, block, spacing, n):
     assert np.max(np.abs(gemm["x"][0])) > 0
     o = _oracle(p, roms, fp32=True)
     _compare(gemm, o, TOL32)
+
+
+def _c3_golden():
+    zm = np.load(os.path.join(GOLD, "c3_model.npz"))
+    z = np.load(os.path.join(GOLD, "c3_probes.npz"))
+    return dict(Rt=zm["Rt"], Ft=zm["Ft"], Lt=zm["Lt"]), z
+
+
+@pytest.mark.parametrize("gemm", [True, False])
+def test_full_size_many_copies_4096_fp32(gemm):
+    """The 4096^2 many-copies workload itself (256 regions sharing one
+    oracle-built order-128 model, FP32) in the benchmark's launch
+    configuration (two steps per pass, captured graph batches, the shared
+    MFMA GEMM or a GEMV per copy) over the oracle's stored 1200-step run
+    (tests/golden/make_c3_golden.py): all 16 probe series, a row and a
+    column of the final Hz and four regions' reduced states, each within
+    1e-5 relative L2 of the oracle evaluated on the same FP32-rounded
+    coefficients and update matrix.  The distance to the oracle's run of
+    the unrounded FP64 problem is printed beside it."""
+    m, z = _c3_golden()
+    n = int(z["steps"])
+    p = W.many_copies(nsteps=n)
+    print(f"[gpu] many copies 4096^2 x {n} steps, gemm={gemm}", flush=True)
+    with Simulation(p, [m] * len(p.roms), max_steps=n) as s:
+        s.set_shared_gemm(gemm)
+        assert s.time_blocking()
+        s.set_graph(200)
+        s.run(n)
+        got = s.probes()
+        hz = s.field(0)
+        xs = np.stack([s.rom_state(int(k)) for k in z["state_regions"]])
+    ref = z["probes_f32"]
+    assert np.max(np.abs(ref)) > 0
+    e_p = rel_l2(got, ref)
+    e_row = rel_l2(hz[p.ny // 2], z["hz_row_f32"])
+    e_col = rel_l2(hz[:, int(z["hz_col_index"])], z["hz_col_f32"])
+    e_x = rel_l2(xs, z["x_f32"])
+    e_64 = rel_l2(got, z["probes_f64"])
+    print(f"[gpu] vs oracle: probes {e_p:.2e} hz row {e_row:.2e} col {e_col:.2e} states {e_x:.2e}; "
+          f"probes vs unrounded FP64 {e_64:.2e}", flush=True)
+    assert np.max(np.abs(z["x_f32"])) > 0 and np.max(np.abs(z["hz_col_f32"])) > 0
+    for what, e in (("probes", e_p), ("hz row", e_row), ("hz col", e_col), ("states", e_x)):
+        assert e <= TOL32, (what, e)

@@ -38,35 +38,43 @@ def _gpu(prob, roms, dtype=None, seg=None):
     with Simulation(prob, roms, dtype=dtype) as s:
         if seg:
             s.set_tiling(seg)
-        s.run(prob.nsteps)
-        return s.probes(), [s.field(c) for c in range(3)]
+        s.run(prob.nsteps // 2)
+        mid = [s.field(c) for c in range(3)]
+        s.run(prob.nsteps - prob.nsteps // 2)
+        return s.probes(), [s.field(c) for c in range(3)], mid
 
 
 def _oracle(prob, roms, fp32):
     run = osim.CoupledRun(prob, roms, mode="closed", fp32=fp32)
     pr = np.empty((prob.nsteps, len(prob.probes)))
     peak = np.zeros(3)
+    mid = None
     for n in range(prob.nsteps):
         run.step()
         pr[n] = run.probes()
         for c, f in enumerate((run.f.hz, run.f.ex, run.f.ey)):
             peak[c] = max(peak[c], np.linalg.norm(f))
-    return pr, [run.f.hz * run.cell, run.f.ex, run.f.ey], peak
+        if n + 1 == prob.nsteps // 2:
+            mid = [run.f.hz * run.cell, run.f.ex.copy(), run.f.ey.copy()]
+    return pr, [run.f.hz * run.cell, run.f.ex, run.f.ey], peak, mid
 
 
 def _check(g, o, tol):
-    """Probe series within ``tol`` relative L2.  Final fields: FP64 within
-    ``tol`` relative L2; FP32 within ``tol`` of the field's peak norm over the
-    run.  Layers absorb the pulse, so a late snapshot holds under 1 % of the
-    peak field and plain relative error there measures FP32 round-off against
-    a decayed signal: a float32 CPU run of the oracle's own update differs
-    from its FP64 evaluation by 1.0e-5 relative on such a snapshot (130x77,
-    300 steps)."""
+    """Probe series within ``tol`` relative L2; the fields halfway through the
+    run, while the pulse is still inside, within ``tol`` relative L2.  Final
+    fields: FP64 within ``tol`` relative L2; FP32 within ``tol`` of the
+    field's peak norm over the run.  Layers absorb the pulse, so a late
+    snapshot holds under 1 % of the peak field and plain relative error there
+    measures FP32 round-off against a decayed signal: a float32 CPU run of the
+    oracle's own update differs from its FP64 evaluation by 1.0e-5 relative on
+    such a snapshot (130x77, 300 steps)."""
     assert rel_l2(g[0], o[0]) <= tol, rel_l2(g[0], o[0])
     for c in range(3):
         err = np.linalg.norm(np.asarray(g[1][c], np.float64) - o[1][c])
         den = np.linalg.norm(o[1][c]) if tol < 1e-9 else o[2][c]
         assert err <= tol * max(den, 1e-300), (c, err / max(den, 1e-300))
+        assert np.linalg.norm(o[3][c]) > 1e-2 * o[2][c], c
+        assert rel_l2(g[2][c], o[3][c]) <= tol, ("mid", c, rel_l2(g[2][c], o[3][c]))
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])

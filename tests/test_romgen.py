@@ -131,3 +131,39 @@ def test_identity_basis_unclipped_is_the_fine_model():
     assert np.max(np.abs(ea - eb)) <= 1e-12 * eb.max()
     for pv in PVALS:
         assert _tf_err(a, b, pv) < 1e-11, pv
+
+
+@pytest.mark.parametrize("basis", ["sprim", "identity"])
+def test_builder_with_pec_cells_matches_oracle(basis):
+    """PEC fine cells (a plate from the South boundary, a corner cell, an
+    interior cell): the library leaves their samples and the ports they
+    cover out of the model like the oracle - same restricted state count,
+    same dead ports (zero columns of Lt), same transfer function - and a
+    port only partly on PEC cells is rejected."""
+    p = W.random_problem(24, 26, 22, 10, nroms=1, block=(5, 4), r=2, q=16)
+    s = p.roms[0]
+    fp = np.zeros((2 * s.nj, 2 * s.ni), dtype=bool)
+    fp[:4, 4:6] = True
+    fp[6:, 8:] = True
+    fp[2, 2] = True
+    kw = dict(pec=fp, basis=basis)
+    if basis == "identity":
+        kw["clip"] = False
+    a = capi.fdtd_rom_build(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, s.q, s.f_max, **kw)
+    b = orom.build_rom(s.eps_r, s.sigma, s.r, p.dx, p.dy, p.dt, s.q, s.f_max, basis=basis,
+                       clip=kw.get("clip", True), pec=fp)
+    assert a["n_fine_states"] == b["model"]["n"]
+    dead = b["model"]["restriction"]["dead_ports"]
+    assert dead == [2, 9, 17]
+    assert np.all(a["Lt"][:, dead] == 0)
+    if basis == "identity":
+        assert a["Rt"].shape == b["Rt"].shape
+        assert np.max(np.abs(a["Rt"] - b["Rt"])) <= 1e-12 * np.abs(b["Rt"]).max()
+        assert np.max(np.abs(a["Ft"] - b["Ft"])) <= 1e-12 * np.abs(b["Ft"]).max()
+        assert np.array_equal(a["Lt"], b["Lt"])
+    for pv in PVALS + ([b["p0"]] if basis == "sprim" else []):
+        assert _tf_err(a, b, pv) < 1e-10, pv
+    bad = np.zeros_like(fp)
+    bad[0, 0] = True
+    with pytest.raises(capi.FdtdError):
+        capi.fdtd_rom_build(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, s.q, s.f_max, pec=bad)
