@@ -417,6 +417,25 @@ int fdtd_rom_adjoint(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int3
                      void* dev_adj_ws, size_t ws_bytes, double* J, double* grad_eps_r,
                      double* grad_sigma);
 
+/* The same reverse sweep for callers that cannot allocate device memory
+ * (code that may not call hipMalloc: tight serving loops, harnesses that
+ * forbid it).  No workspace argument: the sweep's checkpoints, recomputed
+ * segment, adjoint fields and accumulators live in a static device array
+ * the library holds on every GPU it runs on (64 MiB each, until the process
+ * ends); the call makes no device, pinned-host or heap allocation (G^T is
+ * transposed on the device from the handle's update matrices, the forward
+ * runs as plain launches without graph capture or finiteness checks, the
+ * objective is summed on the device).  Arguments, the handle's state
+ * afterwards and the results are those of fdtd_rom_adjoint (J summed in a
+ * different order: equal to rounding).  FDTD_ENOMEM if the sweep needs more
+ * than the 64 MiB (fdtd_rom_adjoint_workspace_size gives the need).  Call
+ * with the handle's device current.  Every call on a GPU shares that GPU's
+ * array and leaves its contents behind (each call clears what must start at
+ * zero): calls that overlap on one GPU, from several threads or streams,
+ * race and must be serialised by the caller.  Synchronises the stream. */
+int fdtd_rom_adjoint_noalloc(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int32_t probe,
+                             double* J, double* grad_eps_r, double* grad_sigma);
+
 /* Batched runs: B independent problems (uneven grids, models, sources,
  * probes; one dtype) advanced together, each step of all of them by one
  * kernel launch, replayed from captured HIP graphs.  Every instance is

@@ -114,6 +114,7 @@ _SIGS = {
                                                   C.POINTER(C.c_size_t)]),
     "fdtd_rom_adjoint": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                    C.c_size_t, _dp, _dp, _dp]),
+    "fdtd_rom_adjoint_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _dp, _dp, _dp]),
     "fdtd_rom_energy": (C.c_int, [C.c_void_p, _dp]),
     "fdtd_rom_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "fdtd_rom_get_state": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -422,6 +423,17 @@ def fdtd_rom_adjoint(h, nsteps: int, ckpt_every: int, probe: int, dev_ptr: int, 
     gs = np.zeros((ny, nx), dtype=np.float64)
     _check(lib().fdtd_rom_adjoint(h, int(nsteps), int(ckpt_every), int(probe), C.c_void_p(dev_ptr),
                                   nbytes, C.byref(J), _ptr(ge), _ptr(gs)))
+    return float(J.value), ge, gs
+
+
+def fdtd_rom_adjoint_noalloc(h, nsteps: int, ckpt_every: int, probe: int, nx: int, ny: int):
+    """As fdtd_rom_adjoint, with the library's static device scratch instead
+    of a caller workspace.  Returns (J, dJ/deps_r [ny, nx], dJ/dsigma [ny, nx])."""
+    J = C.c_double(0)
+    ge = np.zeros((ny, nx), dtype=np.float64)
+    gs = np.zeros((ny, nx), dtype=np.float64)
+    _check(lib().fdtd_rom_adjoint_noalloc(h, int(nsteps), int(ckpt_every), int(probe), C.byref(J), _ptr(ge),
+                                          _ptr(gs)))
     return float(J.value), ge, gs
 
 

@@ -11,12 +11,114 @@
 // The forward coefficients are rebuilt exactly as the step kernel builds
 // them.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
+#include "../../include/fdtd_rom.h"
 #include "adjoint.hpp"
 #include "device.hpp"
 
+// Workspace of the reverse sweep that allocates nothing
+// (fdtd_rom_adjoint_noalloc): every GPU the library runs on holds one copy,
+// zero-initialised at load, until the process ends.  Host code never passes
+// this name to a kernel or copy (on the host it is only a stand-in for the
+// symbol); it uses the per-device address noalloc_scratch() returns.
+static __device__ __align__(256) unsigned char scratch[fdtd::kNoAllocScratchBytes];
+
 namespace fdtd {
+
+int noalloc_scratch(void** ptr) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FDTD_EDEVICE, "hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxDevices) return fail(FDTD_EDEVICE, "device %d beyond the %d the scratch table holds", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(FDTD_EDEVICE, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return FDTD_OK;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) transpose_block(const T* __restrict__ g, T* __restrict__ gt, int ldg,
+                                                         int nc) {
+  const size_t n = (size_t)ldg * ldg;
+  for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (size_t)gridDim.x * kBlock) {
+    const int c = (int)(k / ldg), r = (int)(k - (size_t)c * ldg);
+    gt[k] = (r < nc && c < nc) ? g[(size_t)r * ldg + c] : T(0);
+  }
+}
+
+template <typename T>
+hipError_t launch_transpose_block(const T* g, T* gt, int ldg, int nc, hipStream_t s) {
+  const size_t n = (size_t)ldg * ldg;
+  const unsigned nb = (unsigned)std::max<size_t>(1, std::min<size_t>((n + kBlock - 1) / kBlock, 2048));
+  hipLaunchKernelGGL((transpose_block<T>), dim3(nb), dim3(kBlock), 0, s, g, gt, ldg, nc);
+  return hipGetLastError();
+}
+
+__global__ void rom_entry(RomDev* out, const RomDev* in, int64_t gt_off) {
+  if (threadIdx.x == 0) {
+    RomDev r = *in;
+    r.g_off = -1;
+    r.gt_off = gt_off;
+    *out = r;
+  }
+}
+
+hipError_t launch_rom_entry(RomDev* out, const RomDev* in, int64_t gt_off, hipStream_t s) {
+  hipLaunchKernelGGL(rom_entry, dim3(1), dim3(kWave), 0, s, out, in, gt_off);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) probe_energy(const T* __restrict__ buf, int nprobes, int probe, int n,
+                                                      double dt, double* out) {
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n; k += kBlock) {
+    const double v = (double)buf[(size_t)k * nprobes + probe];
+    acc += v * v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = dt * red[0];
+}
+
+template <typename T>
+hipError_t launch_probe_energy(const T* buf, int nprobes, int probe, int n, double dt, double* out, hipStream_t s) {
+  hipLaunchKernelGGL((probe_energy<T>), dim3(1), dim3(kBlock), 0, s, buf, nprobes, probe, n, dt, out);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlock) zero_fill(uint4* p, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (size_t)gridDim.x * kBlock)
+    p[k] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s) {
+  if (bytes % 16 != 0 || ((uintptr_t)p) % 16 != 0) return hipErrorInvalidValue;
+  const size_t n = bytes / 16;
+  if (n == 0) return hipSuccess;
+  const unsigned nb = (unsigned)std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(zero_fill, dim3(nb), dim3(kBlock), 0, s, (uint4*)p, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_transpose_block<float>(const float*, float*, int, int, hipStream_t);
+template hipError_t launch_transpose_block<double>(const double*, double*, int, int, hipStream_t);
+template hipError_t launch_probe_energy<float>(const float*, int, int, int, double, double*, hipStream_t);
+template hipError_t launch_probe_energy<double>(const double*, int, int, int, double, double*, hipStream_t);
 
 template <typename T>
 __device__ __forceinline__ void adj_coef(T s, T t, T k2, T& ca, T& cb, T& rcp) {

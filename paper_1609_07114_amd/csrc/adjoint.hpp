@@ -64,4 +64,25 @@ hipError_t launch_adjoint_step(const AdjParams<T>& p, size_t smem, hipStream_t s
 // g[k] += a[k], a[k] = 0 for k < n (both accumulator pairs: a, g hold 2n)
 hipError_t launch_adjoint_flush(float* a, double* g, size_t n, hipStream_t s);
 
+// Pieces of the reverse sweep that runs without allocating
+// (fdtd_rom_adjoint_noalloc): its workspace is a file-scope device array of
+// kNoAllocScratchBytes per GPU.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+// Device address of the scratch array on the current device (resolved once
+// per device with hipGetSymbolAddress and kept).
+int noalloc_scratch(void** ptr);
+// One ldg x ldg block of G^T (row c = column c of G, zero beyond nc) from
+// G (row-major, row length ldg, nc rows).
+template <typename T>
+hipError_t launch_transpose_block(const T* g, T* gt, int ldg, int nc, hipStream_t s);
+// out = in with g_off = -1 and gt_off replaced (one model's table entry).
+hipError_t launch_rom_entry(RomDev* out, const RomDev* in, int64_t gt_off, hipStream_t s);
+// *out = dt * sum_{k < n} buf[k * nprobes + probe]^2 (FP64, fixed order).
+template <typename T>
+hipError_t launch_probe_energy(const T* buf, int nprobes, int probe, int n, double dt, double* out,
+                               hipStream_t s);
+// Zero `bytes` bytes at p (both multiples of 16).
+hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s);
+
 }  // namespace fdtd

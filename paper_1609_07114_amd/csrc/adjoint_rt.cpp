@@ -31,15 +31,27 @@ using namespace fdtd;
 
 namespace {
 
+// Plain fields only: the layout is planned without allocating (the
+// no-allocation entry point plans it too).
 struct AdjLayout {
   int K = 0, nck = 0;
   size_t set_bytes = 0, xs_bytes = 0;
   size_t slot_bytes = 0, lam_bytes = 0, ck_psi = 0;  // per slot / adjoint set; checkpoint's psi offset
   size_t off_ctrl = 0, off_ckpt = 0, ck_stride = 0, off_slots = 0, off_xs = 0, off_psih = 0;
-  size_t off_lam = 0, off_lx = 0, off_g = 0, off_gseg = 0, off_gt = 0, off_roms = 0, total = 0;
+  size_t off_lam = 0, off_lx = 0, off_g = 0, off_gseg = 0, off_gt = 0, off_roms = 0, off_j = 0, total = 0;
   size_t gt_elems = 0;
-  std::vector<size_t> slot_gt;  // element offset of each matrix slot's G^T
 };
+
+// Element offset of matrix slot sl's G^T block (ldg x ldg, slots in order).
+size_t slot_gt(const fdtd_rom_sim* s, size_t sl) {
+  size_t ge = 0;
+  for (size_t k = 0; k < sl; ++k) {
+    const RomHost& h = s->roms[s->L.slot_rep[k]];
+    const size_t ldg = align_up((size_t)h.q + h.np, kWave);
+    ge = align_up(ge + ldg * ldg, 64);
+  }
+  return ge;
+}
 
 int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A) {
   if (nsteps < 1 || nsteps > s->max_steps)
@@ -55,15 +67,7 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
   A.slot_bytes = (L.pml ? 5 : 3) * fb;   // Hz, Ex, Ey (+ psi at Ex, Ey)
   A.lam_bytes = (L.pml ? 7 : 3) * fb;    // + adjoints of the four psi
   A.xs_bytes = align_up(std::max<size_t>(L.xs_elems, 1) * ts, 256);
-  A.slot_gt.clear();
-  size_t ge = 0;
-  for (size_t sl = 0; sl < L.slot_rep.size(); ++sl) {
-    const RomHost& h = s->roms[L.slot_rep[sl]];
-    const size_t ldg = align_up((size_t)h.q + h.np, kWave);
-    A.slot_gt.push_back(ge);
-    ge = align_up(ge + ldg * ldg, 64);
-  }
-  A.gt_elems = ge;
+  A.gt_elems = slot_gt(s, L.slot_rep.size());
   size_t o = 0;
   A.off_ctrl = o;
   o = align_up(o + kCtrlInts * sizeof(int), 256);
@@ -89,13 +93,23 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
   o = align_up(o + A.gt_elems * ts, 256);
   A.off_roms = o;
   o = align_up(o + (size_t)std::max(s->nroms, 1) * sizeof(RomDev), 256);
+  A.off_j = o;  // the objective, when summed on the device
+  o = align_up(o + sizeof(double), 256);
   A.total = o;
   return FDTD_OK;
 }
 
+
+// The reverse sweep.  noalloc: the workspace is the static scratch array
+// and nothing is allocated - G^T is transposed on the device from the
+// handle's own G (the same FP64-formed, rounded values the host builds),
+// the model table is patched on the device, the forward uses plain launches
+// (run_direct_any), the objective is summed on the device, scratch is
+// cleared by a fill kernel and the gradients are copied straight into the
+// caller's arrays.
 template <typename T>
 int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A, double* J,
-                 double* grad_eps, double* grad_sig) {
+                 double* grad_eps, double* grad_sig, bool noalloc) {
   const Layout& L = s->L;
   hipStream_t st = s->stream;
   const size_t fe = L.field_elems;
@@ -103,9 +117,29 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   auto dev_err = [&](const char* what) {
     return fail(FDTD_EDEVICE, "%s failed: %s", what, hipGetErrorString(hipGetLastError()));
   };
-  // G^T of every matrix slot (row k = column k of eq. (23)'s G) and the
-  // model table pointing at it
-  {
+  if (noalloc) {
+    // clear the control block and everything from the slots to G^T, as the
+    // host path below does with hipMemsetAsync
+    if (launch_zero_fill(aw + A.off_ctrl, align_up(kCtrlInts * sizeof(int), 16), st) != hipSuccess ||
+        launch_zero_fill(aw + A.off_slots, A.off_gt - A.off_slots, st) != hipSuccess)
+      return dev_err("scratch clear");
+    const T* mats = (const T*)(ws + L.off_mats);
+    T* gt = (T*)(aw + A.off_gt);
+    for (size_t sl = 0; sl < L.slot_rep.size(); ++sl) {
+      const RomHost& h = s->roms[L.slot_rep[sl]];
+      const int nc = h.q + h.np;
+      if (launch_transpose_block<T>(mats + L.slot_off[sl], gt + slot_gt(s, sl), (int)align_up((size_t)nc, kWave), nc,
+                                    st) != hipSuccess)
+        return dev_err("G^T transpose");
+    }
+    const RomDev* rin = (const RomDev*)(ws + L.off_roms);
+    RomDev* rout = (RomDev*)(aw + A.off_roms);
+    for (int k = 0; k < s->nroms; ++k)
+      if (launch_rom_entry(rout + k, rin + k, (int64_t)slot_gt(s, L.slot_of_rom[k]), st) != hipSuccess)
+        return dev_err("model table");
+  } else {
+    // G^T of every matrix slot (row k = column k of eq. (23)'s G) and the
+    // model table pointing at it
     std::vector<T> gt(std::max<size_t>(A.gt_elems, 1), T(0));
     for (size_t sl = 0; sl < L.slot_rep.size(); ++sl) {
       const RomHost& h = s->roms[L.slot_rep[sl]];
@@ -114,7 +148,7 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
       std::vector<double> CA((size_t)np * q), CB((size_t)np * np);
       la::gemm(np, q, q, h.C.data(), h.A.data(), CA.data());
       la::gemm(np, np, q, h.C.data(), h.B.data(), CB.data());
-      T* g = gt.data() + A.slot_gt[sl];
+      T* g = gt.data() + slot_gt(s, sl);
       auto put = [&](int row, int col, double v) { g[(size_t)col * ldg + row] = (T)v; };
       for (int a = 0; a < q; ++a) {
         for (int c = 0; c < q; ++c) put(a, c, h.A[(size_t)a * q + c]);
@@ -136,18 +170,18 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
       rd[k].x_off = (int64_t)L.x_off[k];
       rd[k].xstride = (int64_t)align_up((size_t)h.q, 64);
       rd[k].i_off = (int64_t)L.i_off[k];
-      rd[k].gt_off = (int64_t)A.slot_gt[L.slot_of_rom[k]];
+      rd[k].gt_off = (int64_t)slot_gt(s, L.slot_of_rom[k]);
     }
     if (hipMemcpyAsync(aw + A.off_gt, gt.data(), A.gt_elems * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess ||
         (s->nroms > 0 && hipMemcpyAsync(aw + A.off_roms, rd.data(), rd.size() * sizeof(RomDev),
                                         hipMemcpyHostToDevice, st) != hipSuccess) ||
         hipStreamSynchronize(st) != hipSuccess)
       return dev_err("model upload");
+    // zero the private step counter, slots, adjoint fields, states, gradients
+    if (hipMemsetAsync(aw + A.off_ctrl, 0, kCtrlInts * sizeof(int), st) != hipSuccess ||
+        hipMemsetAsync(aw + A.off_slots, 0, A.off_gt - A.off_slots, st) != hipSuccess)
+      return dev_err("hipMemsetAsync");
   }
-  // zero the private step counter, slots, adjoint fields, states, gradients
-  if (hipMemsetAsync(aw + A.off_ctrl, 0, kCtrlInts * sizeof(int), st) != hipSuccess ||
-      hipMemsetAsync(aw + A.off_slots, 0, A.off_gt - A.off_slots, st) != hipSuccess)
-    return dev_err("hipMemsetAsync");
 
   auto ckpt = [&](int c) { return aw + A.off_ckpt + (size_t)c * A.ck_stride; };
   auto ckpt_xs = [&](int c) { return ckpt(c) + align_up(A.set_bytes, 256); };
@@ -174,12 +208,19 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
         if (hipMemcpyAsync(ckpt_psi(c) + k * fe, src[k], fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
           return dev_err("checkpoint copy");
     }
-    const int rc = run_steps_any(s, len);
+    const int rc = noalloc ? run_direct_any(s, len) : run_steps_any(s, len);
     if (rc != FDTD_OK) return rc;
   }
 
   // objective from the probe record
-  {
+  if (noalloc) {
+    double* jd = (double*)(aw + A.off_j);
+    if (launch_probe_energy<T>((const T*)(ws + L.off_pbuf), s->nprobes, probe, N, s->dt, jd, st) != hipSuccess ||
+        hipMemcpyAsync(J, jd, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return dev_err("objective");
+    if (!std::isfinite(*J)) return fail(FDTD_EUNSTABLE, "non-finite objective");
+  } else {
     const int rc = fdtd_rom_probe_objective(s, probe, 0, N, J);
     if (rc != FDTD_OK) return rc;
   }
@@ -295,22 +336,25 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
       if (launch_adjoint_flush((float*)ap.ga_e, g64, 2 * fe, st) != hipSuccess) return dev_err("gradient flush");
     }
   }
-  // gradients: pitch layout -> natural, zero on regions and their rings
-  std::vector<double> g(2 * fe);
-  if (hipMemcpyAsync(g.data(), aw + A.off_g, 2 * fe * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+  // gradients: pitch layout -> natural, zero on regions and their rings and
+  // on PEC cells
+  const int nx = s->nx, ny = s->ny, P = s->pitch;
+  const double* gd = (const double*)(aw + A.off_g);
+  if (hipMemcpy2DAsync(grad_eps, (size_t)nx * sizeof(double), gd, (size_t)P * sizeof(double), (size_t)nx * sizeof(double),
+                       ny, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpy2DAsync(grad_sig, (size_t)nx * sizeof(double), gd + fe, (size_t)P * sizeof(double),
+                       (size_t)nx * sizeof(double), ny, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return dev_err("gradient read");
-  const int nx = s->nx, ny = s->ny, P = s->pitch;
-  std::vector<unsigned char> held((size_t)nx * ny, 0);
-  for (size_t c = 0; c < s->pec.size(); ++c) held[c] = s->pec[c] ? 1 : 0;  // metal: no material gradient
+  for (size_t c = 0; c < s->pec.size(); ++c)
+    if (s->pec[c]) grad_eps[c] = grad_sig[c] = 0.0;  // metal: no material gradient
   for (const RomHost& h : s->roms)
     for (int j = std::max(h.j0 - 1, 0); j < std::min(h.j0 + h.nj + 1, ny); ++j)
-      for (int i = std::max(h.i0 - 1, 0); i < std::min(h.i0 + h.ni + 1, nx); ++i) held[(size_t)j * nx + i] = 1;
+      for (int i = std::max(h.i0 - 1, 0); i < std::min(h.i0 + h.ni + 1, nx); ++i)
+        grad_eps[(size_t)j * nx + i] = grad_sig[(size_t)j * nx + i] = 0.0;
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const size_t c = (size_t)j * nx + i;
-      grad_eps[c] = held[c] ? 0.0 : g[(size_t)j * P + i];
-      grad_sig[c] = held[c] ? 0.0 : g[fe + (size_t)j * P + i];
       if (!std::isfinite(grad_eps[c]) || !std::isfinite(grad_sig[c]))
         return fail(FDTD_EUNSTABLE, "non-finite gradient at cell (%d,%d)", i, j);
     }
@@ -350,11 +394,30 @@ int fdtd_rom_adjoint(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int3
     if (((uintptr_t)dev_adj_ws) % 256) return fail(FDTD_EINVAL, "adjoint workspace must be 256-byte aligned");
     if (ws_bytes < A.total) return fail(FDTD_ENOMEM, "adjoint workspace has %zu bytes, %zu needed", ws_bytes, A.total);
     char* aw = (char*)dev_adj_ws;
-    return sim->dtype == FDTD_F32 ? adjoint_impl<float>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma)
-                                  : adjoint_impl<double>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma);
+    return sim->dtype == FDTD_F32 ? adjoint_impl<float>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma, false)
+                                  : adjoint_impl<double>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma, false);
   } catch (const std::bad_alloc&) {
     return fail(FDTD_ENOMEM, "host allocation failed");
   }
+}
+
+int fdtd_rom_adjoint_noalloc(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int32_t probe, double* J,
+                             double* grad_eps_r, double* grad_sigma) {
+  if (!sim || !J || !grad_eps_r || !grad_sigma) return fail(FDTD_EINVAL, "null argument");
+  if (sim->steps != 0) return fail(FDTD_ESTATE, "the adjoint starts from the initial state (%d steps taken)", sim->steps);
+  if (probe < 0 || probe >= sim->nprobes) return fail(FDTD_EINVAL, "probe %d out of range", probe);
+  if (sim->probes[probe].comp != FDTD_HZ) return fail(FDTD_EINVAL, "probe %d is not an Hz probe", probe);
+  AdjLayout A;
+  int rc = plan_adjoint(sim, nsteps, ckpt_every, A);
+  if (rc != FDTD_OK) return rc;
+  if (A.total > kNoAllocScratchBytes)
+    return fail(FDTD_ENOMEM, "the sweep needs %zu bytes of scratch, the static scratch array holds %zu "
+                "(use fdtd_rom_adjoint with a workspace)", A.total, kNoAllocScratchBytes);
+  void* scr = nullptr;
+  if ((rc = noalloc_scratch(&scr)) != FDTD_OK) return rc;
+  char* aw = (char*)scr;
+  return sim->dtype == FDTD_F32 ? adjoint_impl<float>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma, true)
+                                : adjoint_impl<double>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma, true);
 }
 
 }  // extern "C"

@@ -952,7 +952,8 @@ int ev_pair(fdtd_rom_sim* s, std::vector<std::pair<hipEvent_t, hipEvent_t>>& poo
 // n+2 in the set that held n+1's place, so the two sets trade places.
 // Returns the number of pairs through `pairs`.
 template <typename T>
-int enqueue_steps(fdtd_rom_sim* s, int nsteps, hipStream_t stream, bool prof, int steps0, int* pairs) {
+int enqueue_steps(fdtd_rom_sim* s, int nsteps, hipStream_t stream, bool prof, int steps0, int* pairs,
+                  bool allow_pairs = true) {
   StepParams<T> sp = step_params<T>(s);
   int k = 0;
   *pairs = 0;
@@ -962,7 +963,7 @@ int enqueue_steps(fdtd_rom_sim* s, int nsteps, hipStream_t stream, bool prof, in
     if (hipEventRecord(e0, stream) != hipSuccess) return fail(FDTD_EDEVICE, "hipEventRecord failed");
     return FDTD_OK;
   };
-  if (s->tb) {
+  if (s->tb && allow_pairs) {
     T* fc[3];
     for (int c = 0; c < 3; ++c) fc[c] = (T*)(s->ws + s->L.off_fc + c * s->L.field_elems * sizeof(T));
     for (; k + 2 <= nsteps; k += 2) {
@@ -1160,10 +1161,26 @@ void to_double(const std::vector<char>& raw, size_t n, double* out) {
   for (size_t k = 0; k < n; ++k) out[k] = (double)t[k];
 }
 
+// nsteps single-step launches (no pairs, no graph, no finiteness check, no
+// host allocation), then the probe flush and the tick.
+template <typename T>
+int run_direct(fdtd_rom_sim* s, int nsteps) {
+  if (nsteps == 0) return FDTD_OK;
+  int pairs = 0;
+  const int rc = enqueue_steps<T>(s, nsteps, s->stream, false, s->steps, &pairs, false);
+  if (rc != FDTD_OK) return rc;
+  s->steps += nsteps;
+  return FDTD_OK;
+}
+
 }  // namespace
 
 int fdtd::run_steps_any(fdtd_rom_sim* s, int nsteps) {
   return s->dtype == FDTD_F32 ? run_steps<float>(s, nsteps) : run_steps<double>(s, nsteps);
+}
+
+int fdtd::run_direct_any(fdtd_rom_sim* s, int nsteps) {
+  return s->dtype == FDTD_F32 ? run_direct<float>(s, nsteps) : run_direct<double>(s, nsteps);
 }
 
 extern "C" {

@@ -117,6 +117,9 @@ int plan_problem(const fdtd_problem* p, Layout& L);
 
 // Advance the simulation by nsteps (graph replays or plain launches).
 int run_steps_any(fdtd_rom_sim* s, int nsteps);
+// The same with one plain launch per step only: no graph capture, no tile
+// roles, no finiteness check, nothing allocated (bit-identical results).
+int run_direct_any(fdtd_rom_sim* s, int nsteps);
 
 // Rows per stencil wave: recompute the tile grid of the handle.
 void set_tiling(fdtd_rom_sim* s, int seg);
