@@ -413,6 +413,15 @@ int fdtd_rom_get_time_blocking(const fdtd_rom_sim* sim, int32_t* on);
  *     (i,j) at j*nx+i), caller-allocated.  Synchronises the stream. */
 int fdtd_rom_adjoint_workspace_size(const fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every,
                                     size_t* bytes);
+/* Host-only (no device call): the same size for a problem before a handle
+ * exists (prob as for fdtd_rom_create, the shape checks of
+ * fdtd_rom_workspace_size).  Planning checks that the workspace's parts -
+ * checkpoints, recompute slots, adjoint sets, accumulators, G^T, model
+ * table - are disjoint and inside the total, as every call that plans the
+ * sweep does; fdtd_rom_adjoint also checks before each recompute launch that
+ * the fields, control block and state scratch it writes lie in the
+ * workspace (FDTD_EINVAL otherwise). */
+int fdtd_rom_adjoint_plan(const fdtd_problem* prob, int32_t nsteps, int32_t ckpt_every, size_t* bytes);
 int fdtd_rom_adjoint(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int32_t probe,
                      void* dev_adj_ws, size_t ws_bytes, double* J, double* grad_eps_r,
                      double* grad_sigma);

@@ -78,5 +78,46 @@ def build(verbose: bool = False) -> str:
     return LIB_PATH
 
 
+# AddressSanitizer + UndefinedBehaviorSanitizer for the host sources only
+# (compiled and linked by the host compiler; the device objects are the
+# normal build's)
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=undefined"]
+
+
+def sanitizer_runtime() -> str:
+    """Path of the AddressSanitizer runtime to preload into the interpreter."""
+    return subprocess.run([cxx(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True,
+                          text=True, check=True).stdout.strip()
+
+
+def build_sanitized(outdir: str, verbose: bool = False) -> str:
+    """The library with the host code (runtime, C ABI, model builder) built
+    with the sanitizers, into outdir; load it with FDTD_ROM_LIB pointing at
+    it and the sanitizer runtime preloaded.  Uses the device objects of the
+    normal build (built first if missing)."""
+    objdir = os.path.join(HERE, "_build")
+    dev = [os.path.join(objdir, os.path.basename(s) + ".o") for s in HIP_SOURCES]
+    if not all(os.path.exists(o) for o in dev):
+        build(verbose)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(rocm_path(), "include")]
+    os.makedirs(outdir, exist_ok=True)
+    cmds, objs = [], []
+    for src in CPP_SOURCES:
+        obj = os.path.join(outdir, os.path.basename(src) + ".san.o")
+        cmds.append([cxx(), *SAN_FLAGS, "-std=c++17", "-fPIC", "-D__HIP_PLATFORM_AMD__", *inc, "-c",
+                     os.path.join(HERE, src), "-o", obj])
+        objs.append(obj)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(len(cmds)) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
+    out = os.path.join(outdir, "libfdtdrom_san.so")
+    lib_dir = os.path.join(rocm_path(), "lib")
+    _run([cxx(), "-shared", *SAN_FLAGS, "-shared-libasan", *objs, *dev, "-L", lib_dir, "-lamdhip64",
+          "-Wl,-rpath," + lib_dir, "-o", out], verbose)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

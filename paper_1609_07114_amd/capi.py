@@ -11,7 +11,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfdtdrom.so")
+# FDTD_ROM_LIB names another build of the same library (the sanitizer build
+# of the host code that tests/test_host_sanitizers.py makes)
+LIB_PATH = os.environ.get("FDTD_ROM_LIB") or os.path.join(HERE, "libfdtdrom.so")
 
 FDTD_OK, FDTD_EINVAL, FDTD_ENOMEM, FDTD_EDEVICE = 0, -1, -2, -3
 FDTD_ENOTPASSIVE, FDTD_EUNSTABLE, FDTD_ESTATE = -4, -5, -6
@@ -114,6 +116,8 @@ _SIGS = {
                                                   C.POINTER(C.c_size_t)]),
     "fdtd_rom_adjoint": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                    C.c_size_t, _dp, _dp, _dp]),
+    "fdtd_rom_adjoint_plan": (C.c_int, [C.POINTER(fdtd_problem), C.c_int32, C.c_int32,
+                                        C.POINTER(C.c_size_t)]),
     "fdtd_rom_adjoint_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _dp, _dp, _dp]),
     "fdtd_rom_energy": (C.c_int, [C.c_void_p, _dp]),
     "fdtd_rom_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
@@ -424,6 +428,13 @@ def fdtd_rom_adjoint(h, nsteps: int, ckpt_every: int, probe: int, dev_ptr: int, 
     _check(lib().fdtd_rom_adjoint(h, int(nsteps), int(ckpt_every), int(probe), C.c_void_p(dev_ptr),
                                   nbytes, C.byref(J), _ptr(ge), _ptr(gs)))
     return float(J.value), ge, gs
+
+
+def fdtd_rom_adjoint_plan(problem: ProblemStruct, nsteps: int, ckpt_every: int = 0) -> int:
+    """Adjoint workspace bytes of a problem (host only, no handle)."""
+    n = C.c_size_t(0)
+    _check(lib().fdtd_rom_adjoint_plan(C.byref(problem.s), int(nsteps), int(ckpt_every), C.byref(n)))
+    return int(n.value)
 
 
 def fdtd_rom_adjoint_noalloc(h, nsteps: int, ckpt_every: int, probe: int, nx: int, ny: int):

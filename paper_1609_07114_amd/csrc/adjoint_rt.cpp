@@ -96,9 +96,56 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
   A.off_j = o;  // the objective, when summed on the device
   o = align_up(o + sizeof(double), 256);
   A.total = o;
+  // every part in order, disjoint, inside the total: the checkpoints (each
+  // a field set, the reduced states and, with layers, four auxiliary
+  // fields), the recompute slots, the scratch states, the recompute's psi
+  // at Hz, the adjoint sets, adjoint states, accumulators, G^T, model table
+  const size_t parts[][2] = {
+      {A.off_ctrl, kCtrlInts * sizeof(int)},
+      {A.off_ckpt, (size_t)A.nck * A.ck_stride},
+      {A.off_slots, (size_t)A.K * A.slot_bytes},
+      {A.off_xs, A.xs_bytes},
+      {A.off_psih, L.pml ? 4 * fb : 0},
+      {A.off_lam, 2 * A.lam_bytes},
+      {A.off_lx, 2 * A.xs_bytes},
+      {A.off_g, 2 * L.field_elems * sizeof(double)},
+      {A.off_gseg, ts == 4 ? 2 * L.field_elems * ts : 0},
+      {A.off_gt, A.gt_elems * ts},
+      {A.off_roms, (size_t)std::max(s->nroms, 1) * sizeof(RomDev)},
+      {A.off_j, sizeof(double)}};
+  size_t end = 0;
+  for (const auto& pt : parts) {
+    if (pt[0] < end || pt[0] % 256 != 0) return fail(FDTD_EINVAL, "internal: adjoint workspace parts overlap");
+    end = pt[0] + pt[1];
+  }
+  if (end > A.total) return fail(FDTD_EINVAL, "internal: adjoint workspace parts exceed the total");
+  if (A.set_bytes + A.xs_bytes > A.ck_psi || A.ck_psi + (L.pml ? 4 * fb : 0) > A.ck_stride ||
+      (L.pml && 5 * fb > A.slot_bytes))
+    return fail(FDTD_EINVAL, "internal: checkpoint or slot parts overlap");
   return FDTD_OK;
 }
 
+// [p, p + bytes) inside [base, base + total)
+bool inside_span(const void* p, size_t bytes, const void* base, size_t total) {
+  const uintptr_t a = (uintptr_t)p, b = (uintptr_t)base;
+  return a >= b && bytes <= total && a - b <= total - bytes;
+}
+
+// Every pointer and extent a recompute launch writes lies in the adjoint
+// workspace: the output field set (three field arrays), the private step
+// counter and the reduced-state scratch; its input set lies in the
+// workspace too (a checkpoint or an earlier slot).
+template <typename T>
+int check_recompute(const StepParams<T>& rp, int par, const char* aw, const AdjLayout& A, size_t fe) {
+  const size_t fb = fe * sizeof(T);
+  for (int f = 0; f < 3; ++f)
+    if (!inside_span(rp.f[par][f], fb, aw, A.total) || !inside_span(rp.f[par ^ 1][f], fb, aw, A.total))
+      return fail(FDTD_EINVAL, "internal: recompute field %d outside the adjoint workspace", f);
+  if (!inside_span(rp.ctrl, kCtrlInts * sizeof(int), aw, A.total) || !inside_span(rp.xs, A.xs_bytes, aw, A.total))
+    return fail(FDTD_EINVAL, "internal: recompute control or state scratch outside the adjoint workspace");
+  if (rp.nprobes != 0) return fail(FDTD_EINVAL, "internal: recompute records probes");
+  return FDTD_OK;
+}
 
 // The reverse sweep.  noalloc: the workspace is the static scratch array
 // and nothing is allocated - G^T is transposed on the device from the
@@ -305,6 +352,7 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
         rp.psi_ey = psi_e(k + 1) + fe;
       }
       rp.step_off = m;
+      if (const int rc = check_recompute<T>(rp, par, aw, A, fe); rc != FDTD_OK) return rc;
       if (launch_step<T>(rp, s->seg, s->smem, st) != hipSuccess) return dev_err("recompute launch");
     }
     for (int k = len - 1; k >= 0; --k) {
@@ -396,6 +444,33 @@ int fdtd_rom_adjoint(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int3
     char* aw = (char*)dev_adj_ws;
     return sim->dtype == FDTD_F32 ? adjoint_impl<float>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma, false)
                                   : adjoint_impl<double>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma, false);
+  } catch (const std::bad_alloc&) {
+    return fail(FDTD_ENOMEM, "host allocation failed");
+  }
+}
+
+int fdtd_rom_adjoint_plan(const fdtd_problem* prob, int32_t nsteps, int32_t ckpt_every, size_t* bytes) {
+  if (!prob || !bytes) return fail(FDTD_EINVAL, "null argument");
+  try {
+    // a host-only stand-in for the handle: the layout and the model shapes
+    fdtd_rom_sim s;
+    int rc = plan_problem(prob, s.L);
+    if (rc != FDTD_OK) return rc;
+    s.dtype = prob->grid.dtype;
+    s.nx = prob->grid.nx;
+    s.ny = prob->grid.ny;
+    s.max_steps = prob->max_steps;
+    s.nroms = prob->nroms;
+    s.roms.resize(prob->nroms);
+    for (int k = 0; k < prob->nroms; ++k) {
+      s.roms[k].q = prob->roms[k].q;
+      s.roms[k].np = ports_of(prob->roms[k]);
+    }
+    AdjLayout A;
+    rc = plan_adjoint(&s, nsteps, ckpt_every, A);
+    if (rc != FDTD_OK) return rc;
+    *bytes = A.total;
+    return FDTD_OK;
   } catch (const std::bad_alloc&) {
     return fail(FDTD_ENOMEM, "host allocation failed");
   }

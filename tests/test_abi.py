@@ -251,3 +251,31 @@ def test_pec_cells_validation():
     q.sources[0].j0, q.sources[0].j1 = 0, 1
     q.sources[0].comp = W.HZ
     assert _create_status(_struct(q, roms)) == capi.FDTD_EINVAL
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_adjoint_plan_host_only(dtype):
+    """The adjoint workspace plan from a problem alone (no handle, no
+    device), with models, absorbing layers and several checkpoint intervals:
+    it covers at least the checkpoints, the recomputed segment and the
+    adjoint sets the sweep needs (its own check keeps the parts disjoint)."""
+    ts = 4 if dtype == "f32" else 8
+    p = W.random_problem(81, 70, 45, 300, nroms=2, block=(5, 4), r=2, q=10, dtype=dtype)
+    roms = osim.build_roms(p)
+    fb = p.nx * p.ny * ts              # one field array holds at least the cells
+    for K in (1, 7, 300, 0):
+        nb = capi.fdtd_rom_adjoint_plan(_struct(p, roms), 300, K)
+        k = K or 18
+        nck = -(-300 // k)
+        assert nb >= (nck + k + 2) * 3 * fb + 2 * p.nx * p.ny * 8, (K, nb)
+    q = copy.deepcopy(p)
+    q.pml = W.Pml(4, 4, 3, 3)
+    for s in q.roms:
+        s.i0 += 3
+        s.j0 += 2
+    nb_l = capi.fdtd_rom_adjoint_plan(_struct(q, osim.build_roms(q)), 300, 7)
+    assert nb_l > capi.fdtd_rom_adjoint_plan(_struct(p, roms), 300, 7)
+    with pytest.raises(capi.FdtdError):
+        capi.fdtd_rom_adjoint_plan(_struct(p, roms), 301, 7)      # beyond max_steps
+    with pytest.raises(capi.FdtdError):
+        capi.fdtd_rom_adjoint_plan(_struct(p, roms), 300, 301)

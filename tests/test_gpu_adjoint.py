@@ -192,3 +192,20 @@ def test_c5_full_fp32_vs_fp64(c5_full):
     assert J32 == pytest.approx(J64, rel=1e-4)
     assert rel_l2(ge32, ge64) <= 1e-3, rel_l2(ge32, ge64)
     assert rel_l2(gs32, gs64) <= 1e-3, rel_l2(gs32, gs64)
+
+
+def test_host_plan_equals_handle_workspace_size():
+    """The host-only plan of the adjoint workspace (no handle) equals the
+    size the handle reports, with and without absorbing layers."""
+    cases = [W.random_problem(36, 70, 45, 300, nroms=2, block=(5, 4), r=2, q=10, dtype=d)
+             for d in ("f32", "f64")]
+    q = W.random_problem(37, 80, 60, 200, nroms=1, block=(5, 4), r=2, q=10)
+    q.pml = W.Pml(5, 5, 4, 4)
+    q.roms[0].i0, q.roms[0].j0 = 30, 25
+    cases.append(q)
+    for p in cases:
+        roms = osim.build_roms(p)
+        for K in (0, 7):
+            plan = capi.fdtd_rom_adjoint_plan(capi.ProblemStruct.from_workload(p, roms), p.nsteps, K)
+            with Simulation(p, roms) as s:
+                assert capi.fdtd_rom_adjoint_workspace_size(s.h, p.nsteps, K) == plan
