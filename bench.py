@@ -425,7 +425,7 @@ def bench_hbm_resident(n=8192, steps=400, warmup=52, log=None):
     prob = W.random_media(n=n, nsteps=steps + warmup)
     roms = romgen.build_roms(prob)
     r = run_headline(prob, roms, steps, warmup, "material", "hbm", log=log)
-    return {"workload": f"random media {n}x{n}, 16 models (q 32-96), FP32, {steps} steps",
+    return {"workload": f"random media {n}x{n}, {len(prob.roms)} models (q 32-96), FP32, {steps} steps",
             "value": round(r["value"], 1), "unit": "Mcell-updates/s",
             "ms_per_step": round(r["ms_per_step"], 5), "roofline": r["roofline"]}
 

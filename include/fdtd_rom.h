@@ -365,12 +365,14 @@ int fdtd_rom_set_graph(fdtd_rom_sim* sim, int32_t batch);
 
 /* Two leap-frog steps (eq. (5) then eq. (3), twice) per pass over the
  * coarse grid.  on = 1: steps go in pairs of launches.  The first launch
- * runs the step-n coupling blocks of eq. (23) and advances every tile of the
- * grid whose reads stay clear of the regions by two steps at once, holding
- * step n+1 in registers; the tiles near a region advance one step.  The
- * second launch advances the near tiles and the coupling by the second
- * step.  An odd last step runs as a single launch.  On by default for grids
- * without absorbing layers (batches always step singly).  The arithmetic per cell
+ * runs the step-n coupling blocks of eq. (23) and advances the tiles of the
+ * grid by two steps at once, holding step n+1 in registers - except, next
+ * to each region, the band of ring cells and their edges, whose second step
+ * needs the step-(n+1) interface E of eq. (23).  The second launch runs the
+ * step-(n+1) coupling blocks, advances the bands by the second step and
+ * takes a share of the far tiles (fdtd_rom_set_pair_split).  An odd last
+ * step runs as a single launch.  On by default for grids without absorbing
+ * layers (batches of such grids too).  The arithmetic per cell
  * is that of the single-step launch, so results are identical; far cells
  * move their fields through memory once per two steps.  Graph batches
  * (fdtd_rom_set_graph) are rounded down to a multiple of 4 steps.
@@ -378,6 +380,18 @@ int fdtd_rom_set_graph(fdtd_rom_sim* sim, int32_t batch);
  * for a grid with absorbing layers.  get: the current setting. */
 int fdtd_rom_set_time_blocking(fdtd_rom_sim* sim, int32_t on);
 int fdtd_rom_get_time_blocking(const fdtd_rom_sim* sim, int32_t* on);
+
+/* Two steps per pass: the share of the far tiles (percent of the two-step
+ * tiles, 0..90) that the second launch of each pair advances instead of the
+ * first.  Far tiles read only step n and write step n+2, so either launch
+ * may take them; in the second they run beside the coupling blocks of step
+ * n+1, whose chain of dependent loads would otherwise run alone there.
+ * -1 (default) picks 50 when the grid's tiles do not fit on the GPU at once
+ * and a shared model runs as the MFMA GEMM (fdtd_rom_set_shared_gemm; its
+ * blocks form the longest chain), else 0.  Results do not depend on it.  get: the share in
+ * effect (after the next pair's set-up), else the requested value. */
+int fdtd_rom_set_pair_split(fdtd_rom_sim* sim, int32_t percent);
+int fdtd_rom_get_pair_split(const fdtd_rom_sim* sim, int32_t* percent);
 
 /* Discrete adjoint (reverse-time sweep) of the coupled leap-frog run for the
  * objective J = dt * sum_{n=0}^{nsteps-1} (Hz_p^{n+1/2})^2 at Hz probe p:

@@ -109,6 +109,8 @@ _SIGS = {
     "fdtd_rom_set_material_mode": (C.c_int, [C.c_void_p, C.c_int32]),
     "fdtd_rom_get_material_mode": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fdtd_rom_set_time_blocking": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_set_pair_split": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_get_pair_split": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "fdtd_rom_batch_set_time_blocking": (C.c_int, [C.c_void_p, C.c_int32]),
     "fdtd_rom_batch_get_time_blocking": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fdtd_rom_get_time_blocking": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -391,6 +393,16 @@ def fdtd_rom_get_material_mode(h):
 
 def fdtd_rom_set_time_blocking(h, on: bool):
     _check(lib().fdtd_rom_set_time_blocking(h, 1 if on else 0))
+
+
+def fdtd_rom_set_pair_split(h, percent: int):
+    _check(lib().fdtd_rom_set_pair_split(h, int(percent)))
+
+
+def fdtd_rom_get_pair_split(h) -> int:
+    v = C.c_int32(0)
+    _check(lib().fdtd_rom_get_pair_split(h, C.byref(v)))
+    return int(v.value)
 
 
 def fdtd_rom_get_time_blocking(h) -> bool:

@@ -388,12 +388,26 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   // on PEC cells
   const int nx = s->nx, ny = s->ny, P = s->pitch;
   const double* gd = (const double*)(aw + A.off_g);
-  if (hipMemcpy2DAsync(grad_eps, (size_t)nx * sizeof(double), gd, (size_t)P * sizeof(double), (size_t)nx * sizeof(double),
-                       ny, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpy2DAsync(grad_sig, (size_t)nx * sizeof(double), gd + fe, (size_t)P * sizeof(double),
-                       (size_t)nx * sizeof(double), ny, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return dev_err("gradient read");
+  if (noalloc) {
+    // straight into the caller's arrays, row by row
+    if (hipMemcpy2DAsync(grad_eps, (size_t)nx * sizeof(double), gd, (size_t)P * sizeof(double),
+                         (size_t)nx * sizeof(double), ny, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpy2DAsync(grad_sig, (size_t)nx * sizeof(double), gd + fe, (size_t)P * sizeof(double),
+                         (size_t)nx * sizeof(double), ny, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return dev_err("gradient read");
+  } else {
+    // one contiguous copy (much faster than rows into pageable memory)
+    std::vector<double> g(2 * fe);
+    if (hipMemcpyAsync(g.data(), gd, 2 * fe * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return dev_err("gradient read");
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        grad_eps[(size_t)j * nx + i] = g[(size_t)j * P + i];
+        grad_sig[(size_t)j * nx + i] = g[fe + (size_t)j * P + i];
+      }
+  }
   for (size_t c = 0; c < s->pec.size(); ++c)
     if (s->pec[c]) grad_eps[c] = grad_sig[c] = 0.0;  // metal: no material gradient
   for (const RomHost& h : s->roms)

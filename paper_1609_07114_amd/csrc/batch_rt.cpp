@@ -10,8 +10,8 @@
 // Two steps per pass (the default when no instance has absorbing layers):
 // steps go in pairs of launches of batch_step2_kernel over two more tables
 // (first launch: coupling blocks, every instance's two-step tiles, probe
-// blocks; second: coupling blocks, every instance's near-tile pieces, probe
-// blocks).  All instances step in lockstep, so one parity and one set-order
+// blocks; second: coupling blocks, every instance's band blocks, one per
+// region).  All instances step in lockstep, so one parity and one set-order
 // bit describe them all; the descriptors of both set orders (single-step,
 // first and second launch) are uploaded for the parity the pairs start at.
 #include <hip/hip_runtime.h>
@@ -80,7 +80,11 @@ int plan_batch(const fdtd_problem* probs, int B, BatchPlan& P) {
     if (rc != FDTD_OK) return fail(rc, "instance %d: %s", b, fdtd_rom_last_error());
     sizes[b] = L.total;
     cap += (size_t)std::max(L.nrowblocks, L.nblocks_mixed) + (size_t)tiles_for(probs[b], 4) + 7 + 1;
-    cap2 += (size_t)std::max(L.nrowblocks, L.nblocks_mixed) + (size_t)L.max_tiles2 * kNearSplit + 7 + 1;
+    // first table: coupling blocks, near-tile pieces (at most twice the
+    // tile count of 4-row waves: a near tile of SEG-row waves is SEG/2
+    // pieces), tiles, two paddings, probe block; second: coupling and band
+    cap2 += (size_t)std::max(L.nrowblocks, L.nblocks_mixed) +
+            std::max((size_t)L.max_tiles2 * 3 + 16, (size_t)L.max_tiles2 + (size_t)probs[b].nroms * kBandSplit) + 14 + 1;
   }
   const size_t desc_bytes = (size_t)B * (dt == FDTD_F32 ? sizeof(StepParams<float>) : sizeof(StepParams<double>));
   P.desc_stride = align_up(desc_bytes, 256);
@@ -130,11 +134,26 @@ void build_table(fdtd_rom_batch* bt) {
       for (int b = 0; b < bt->B; ++b) {
         while (u.size() % 8) u.push_back(BatchRef{0, 3, 0, 0});
         const fdtd_rom_sim* sb = bt->sims[b];
-        const int nt = bt->dtype == FDTD_F32 ? (second ? sb->sp_f.n_near * kNearSplit : sb->sp_f.nst2_blocks)
-                                             : (second ? sb->sp_d.n_near * kNearSplit : sb->sp_d.nst2_blocks);
-        for (int k = 0; k < nt; ++k) u.push_back(BatchRef{b, 1, k, 0});
+        // first launch: the instance's near-tile pieces, then its two-step
+        // tiles (the near ones return at once); second: its band blocks
+        // (one per region)
+        const int n_near = bt->dtype == FDTD_F32 ? sb->sp_f.n_near : sb->sp_d.n_near;
+        const int near_rows = bt->dtype == FDTD_F32 ? sb->sp_f.near_rows : sb->sp_d.near_rows;
+        const int nt = bt->dtype == FDTD_F32 ? sb->sp_f.nst2_blocks : sb->sp_d.nst2_blocks;
+        const int split = bt->dtype == FDTD_F32 ? sb->sp_f.far_split : sb->sp_d.far_split;
+        if (second) {
+          for (int k = 0; k < sb->nroms * kBandSplit; ++k) u.push_back(BatchRef{b, 1, k, 0});
+          while (u.size() % 8) u.push_back(BatchRef{0, 3, 0, 0});
+          for (int k = 0; k < nt - split; ++k) u.push_back(BatchRef{b, 5, k, 0});
+        } else {
+          const int nn = n_near * (sb->seg / std::min(near_rows, sb->seg));
+          for (int k = 0; k < nn; ++k) u.push_back(BatchRef{b, 4, k, 0});
+          while (u.size() % 8) u.push_back(BatchRef{0, 3, 0, 0});
+          for (int k = 0; k < split; ++k) u.push_back(BatchRef{b, 1, k, 0});
+        }
       }
-      for (int b = 0; b < bt->B; ++b) u.push_back(BatchRef{b, 2, 0, 0});
+      if (!second)
+        for (int b = 0; b < bt->B; ++b) u.push_back(BatchRef{b, 2, 0, 0});
     };
     two(bt->tab2a, false);
     two(bt->tab2b, true);
@@ -189,6 +208,7 @@ int upload(fdtd_rom_batch* bt) {
         a.f2[c] = sp.f[par ^ 1][c];
         b2.f[par ^ 1][c] = fc[c];
         b2.f[par][c] = sp.f[par ^ 1][c];
+        b2.f2[c] = sp.f[par][c];  // the second launch's far tiles read step n
       }
       d[(size_t)(3 * o + 1) * bt->B + b] = a;
       d[(size_t)(3 * o + 2) * bt->B + b] = b2;

@@ -120,19 +120,21 @@ struct StepParams {
   T* psi_ex;         // d/dy of Hz at Ex
   T* psi_ey;         // d/dx of Hz at Ey
   // two-step launches (no absorbing layers): tiles of kOwned2 columns x
-  // 4 SEG rows; role2[tile] 0 = two steps into f2, 1 = near a region (one
-  // step, written with a one-cell halo into the step-(n+1) set); near_list:
-  // the near tiles, which the second launch of the pair advances; probe_near:
-  // the probe lies in a near tile (recorded by the second launch)
+  // 4 SEG rows; role2[tile] 0 = far (two steps into f2), 1 = near a region
+  // or a source (two steps into f2 except the band around each region, and
+  // step n+1 of its cells into the step-(n+1) set); near_list: the n_near
+  // near tiles, run as pieces of near_rows-row waves; far tiles [0,
+  // far_split) run in the first launch, the rest in the second; n_band:
+  // regions whose band the second launch advances.  In the second launch's
+  // parameters f2 is the pair's step-n set.
   T* f2[3];
-  int tiles_x2, nst2_blocks, n_near;
+  int tiles_x2, nst2_blocks, n_near, n_band, near_rows, far_split;
   const uint8_t* role2;
   const int* near_list;
-  const uint8_t* probe_near;
 };
 
 constexpr int kOwned2 = kWave - 4;  // columns a two-step wave owns (lanes 2..61)
-constexpr int kNearSplit = 8;       // workgroups per near tile in the second launch of a pair
+constexpr int kBandSplit = 4;       // workgroups per region's band in the second launch of a pair
 
 // One workgroup of the batched step launch: instance `inst`, role `kind`
 // (0 coupling block idx of that instance, 1 stencil tile idx, 2 probe

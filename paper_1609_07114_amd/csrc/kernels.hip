@@ -468,12 +468,18 @@ __device__ __forceinline__ void stencil_tile(const StepParams<T>& p, int t, int 
 // rows [j0-2, j1] feed stage-2 rows [j0-1, j1), so only step n+2 goes to
 // memory: 26 bytes per cell for two steps instead of 52.
 //
-// Mode 0: a far tile, whose reads never reach a reduced region, its ring or
-//   a source: two steps into f2.
-// Mode 1: a tile near a region, first launch: stage 1 only, stored for lanes
-//   1..62 and rows [j0-1, j1] (the halo the second launch reads) into the
-//   step-(n+1) set, except interface edges (written by the coupling blocks).
-// Mode 2: a near tile, second launch: one step n+1 -> n+2 of its own cells.
+// Near = false: a far tile, whose reads never reach a reduced region, its
+//   ring or a source: two steps into f2, every owned sample stored.
+// Near = true: a tile near a region or a source (first launch of the pair):
+//   the same two steps with source terms, storing
+//   * stage 1 (step n+1) of every owned sample into the step-(n+1) set,
+//     except interface edges (the step-n coupling writes them);
+//   * stage 2 (step n+2) into f2, except the band around each region - the
+//     Hz of ring cells (active cells with a side on a region cell) and E on
+//     every edge of a ring cell - and the interface edges.  The band's step
+//     n+2 depends on the step-(n+1) interface E of eq. (23), which only the
+//     coupling blocks of this launch produce; the second launch's band
+//     blocks compute it from the step-(n+1) set.
 template <typename T>
 struct RowIn2 {
   T h, ex1, ey0, al, be;
@@ -485,25 +491,62 @@ struct Stage1 {
   T h, ex, ey;              // Hz^{n+1/2}, Ex^{n+1}, Ey^{n+1}
   T cax, cbx, cay, cby;     // eq. (3) coefficients of the row's south Ex and west Ey
   bool act, ax, ay;         // active cell, updated edges
+  bool ix, iy;              // south Ex / west Ey are interface edges (near tiles)
 };
 
-template <typename T, bool MIdx, int Mode>
-__device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, int n, int j0, int j1) {
-  constexpr bool kTwo = Mode == 0;
+// The sets a two-step sweep reads (step n) and writes (step n+2; near
+// tiles also step n+1)
+template <typename T>
+struct Sets2 {
+  const T* hz;
+  const T* ex;
+  const T* ey;
+  T* hzo;
+  T* exo;
+  T* eyo;
+  T* hz1;
+  T* ex1o;
+  T* ey1o;
+};
+
+// The first launch's sets: step n is set n & 1, step n+1 the other (the
+// third field set), step n+2 is f2.
+template <typename T>
+__device__ __forceinline__ Sets2<T> sets_first(const StepParams<T>& p, int n) {
   const int par = n & 1;
-  const T* hz = fld(p, par, 0);
-  const T* ex = fld(p, par, 1);
-  const T* ey = fld(p, par, 2);
-  T* hzo = kTwo ? p.f2[0] : fld(p, par ^ 1, 0);
-  T* exo = kTwo ? p.f2[1] : fld(p, par ^ 1, 1);
-  T* eyo = kTwo ? p.f2[2] : fld(p, par ^ 1, 2);
+  return Sets2<T>{fld(p, par, 0), fld(p, par, 1), fld(p, par, 2), p.f2[0], p.f2[1], p.f2[2],
+                  fld(p, par ^ 1, 0), fld(p, par ^ 1, 1), fld(p, par ^ 1, 2)};
+}
+
+// The second launch (its step index n is the pair's n+1): far tiles moved
+// into it read the pair's step-n set, which the host passes as f2, and
+// write the pair's output set, the set this launch's coupling writes.
+template <typename T>
+__device__ __forceinline__ Sets2<T> sets_second(const StepParams<T>& p, int n) {
+  const int po = (n & 1) ^ 1;
+  return Sets2<T>{p.f2[0], p.f2[1], p.f2[2], fld(p, po, 0), fld(p, po, 1), fld(p, po, 2), nullptr, nullptr, nullptr};
+}
+
+template <typename T, bool MIdx, bool Near>
+__device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, const Sets2<T>& S, int tile, int n, int j0,
+                                              int j1) {
+  const T* hz = S.hz;
+  const T* ex = S.ex;
+  const T* ey = S.ey;
+  T* hzo = S.hzo;
+  T* exo = S.exo;
+  T* eyo = S.eyo;
+  // near tiles: the step-(n+1) set receives stage 1
+  T* hz1 = S.hz1;
+  T* ex1o = S.ex1o;
+  T* ey1o = S.ey1o;
   const int lane = threadIdx.x & (kWave - 1);
   const int iw = (tile % p.tiles_x2) * kOwned2;
   const int c = iw - 2 + lane;
   const int nx = p.nx, ny = p.ny, P = p.pitch;
   // stage-1 rows [rs, re]
-  const int rs = Mode == 2 ? max(j0 - 1, 0) : max(j0 - 2, 0);
-  const int re = Mode == 2 ? j1 - 1 : min(j1, ny - 1);
+  const int rs = max(j0 - 2, 0);
+  const int re = min(j1, ny - 1);
   const int r2lo = max(j0 - 1, 0);  // first stage-2 row (its Hz only, unless j0 = 0)
   constexpr uint32_t ts = sizeof(T);
   const uint32_t row_b = (uint32_t)P * ts;
@@ -517,19 +560,22 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
   // none in reach (sources make a tile near), so their code holds no source
   // terms and keeps the register count of the two-step sweep down
   bool any_src = false;
-  if constexpr (Mode != 0) {
+  if constexpr (Near) {
     for (int s = 0; s < p.nsrc; ++s) {
       const Src<T>& S = p.src[s];
       any_src |= S.i0 < iw + kWave - 2 && S.i1 > iw - 2 && S.j0 <= re && S.j1 > rs;
     }
   }
-  T sinc[kMaxSrc];
+  T sinc[kMaxSrc], sinc2[kMaxSrc];  // increments of steps n and n+1
 #pragma unroll
-  for (int s = 0; s < kMaxSrc; ++s) sinc[s] = T(0);
+  for (int s = 0; s < kMaxSrc; ++s) sinc[s] = sinc2[s] = T(0);
   if (any_src) {
 #pragma unroll
     for (int s = 0; s < kMaxSrc; ++s)
-      if (s < p.nsrc) sinc[s] = p.src[s].incr[n];
+      if (s < p.nsrc) {
+        sinc[s] = p.src[s].incr[n];
+        sinc2[s] = p.src[s].incr[n + 1];
+      }
   }
   // the lane's column, clamped into the row: lanes outside the grid read a
   // valid address and their values are never used
@@ -555,25 +601,48 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
   auto orow = [&](int r) { return ob + (uint32_t)(r - rs) * row_b; };
   T ex_c = ld(ex, ob);
   T hn_prev = T(0), a_prev = T(0), b_prev = T(0);
+  T a_prev2 = T(0);     // near tiles: material a of the row below the stage-2 row
+  bool ring_prev = false;  // near tiles: the row below the stage-2 row is a ring cell
   Stage1<T> prv1{};
   T h2_prev = T(0);
   // stage 2 for row r2 from its stage-1 values `a` and Ex^{n+1} of the row
-  // above (exN), stored at byte offset o2
-  auto stage2 = [&](int r2, const Stage1<T>& a, T exN, uint32_t o2) {
+  // above (exN), stored at byte offset o2; near tiles also take the
+  // material a of the cells at and around (c, r2) to find the band
+  auto stage2 = [&](int r2, const Stage1<T>& a, T exN, uint32_t o2, T a_c, T a_up) {
     T eye = lane_next(a.ey);
     if (c + 1 >= nx) eye = T(0);
     T h2 = hz_update(a.h, a.ex, exN, a.ey, eye, chdy, chdx);
+    if (any_src) h2 += src_sum(p, sinc2, 0, c, r2);
     if (!a.act) h2 = T(0);
     const T h2w = lane_prev(h2);
+    bool ring = false, ring_w = false;
+    if constexpr (Near) {
+      ring = a_c > T(0) && (a_prev2 < T(0) || a_up < T(0) || lane_prev(a_c) < T(0) || lane_next(a_c) < T(0));
+      ring_w = dpp_prev(ring ? 1 : 0) != 0;
+    }
     if (r2 >= j0 && own) {
-      const T ex2 = a.ax ? e_update(a.cax, a.ex, a.cbx, h2 - h2_prev) : a.ex;
-      const T ey2 = a.ay ? e_update(a.cay, a.ey, a.cby, -(h2 - h2w)) : a.ey;
-      // far tiles have no interface edges in reach: every edge is stored
-      st(hzo, o2, h2);
-      st(exo, o2, ex2);
-      st(eyo, o2, ey2);
+      T ex2 = a.ax ? e_update(a.cax, a.ex, a.cbx, h2 - h2_prev) : a.ex;
+      T ey2 = a.ay ? e_update(a.cay, a.ey, a.cby, -(h2 - h2w)) : a.ey;
+      if constexpr (Near) {
+        if (any_src) {
+          ex2 += src_sum(p, sinc2, 1, c, r2);
+          ey2 += src_sum(p, sinc2, 2, c, r2);
+        }
+        if (!ring) st(hzo, o2, h2);
+        if (!(ring || ring_prev || a.ix)) st(exo, o2, ex2);
+        if (!(ring || ring_w || a.iy)) st(eyo, o2, ey2);
+      } else {
+        // far tiles have no interface edges in reach: every edge is stored
+        st(hzo, o2, h2);
+        st(exo, o2, ex2);
+        st(eyo, o2, ey2);
+      }
     }
     h2_prev = h2;
+    if constexpr (Near) {
+      ring_prev = ring;
+      a_prev2 = a_c;
+    }
   };
   // stage 1 for row r from its loaded data
   auto compute = [&](int r, const RowIn2<T>& cs) {
@@ -603,21 +672,21 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
     o.h = hn;
     o.ex = exn;
     o.ey = eyn;
-    if constexpr (Mode != 0) {
+    o.ix = o.iy = false;
+    if constexpr (Near) {
       // interface edges (exactly one side inside a region) belong to the
       // coupling blocks
-      const bool ixf = (cur.al < T(0)) != (a_prev < T(0));
-      const bool iyf = (cur.al < T(0)) != (all < T(0));
-      const bool st_lane = Mode == 1 ? in && lane >= 1 && lane <= kWave - 2 : own;
-      if (st_lane && r >= (Mode == 1 ? r2lo : j0)) {
-        st(hzo, ob, hn);
-        if (!ixf) st(exo, ob, exn);
-        if (!iyf) st(eyo, ob, eyn);
+      o.ix = (cur.al < T(0)) != (a_prev < T(0));
+      o.iy = (cur.al < T(0)) != (all < T(0));
+      if (own && r >= j0 && r < j1) {
+        st(hz1, ob, hn);
+        if (!o.ix) st(ex1o, ob, exn);
+        if (!o.iy) st(ey1o, ob, eyn);
       }
-    } else {
-      if (r - 1 >= r2lo) stage2(r - 1, prv1, exn, ob - row_b);
-      prv1 = o;
     }
+    if (r - 1 >= r2lo) stage2(r - 1, prv1, exn, ob - row_b, a_prev, cur.al);
+    else if constexpr (Near) a_prev2 = a_prev;  // rows below the first stage-2 row
+    prv1 = o;
     hn_prev = hn;
     a_prev = cur.al;
     b_prev = cur.be;
@@ -661,38 +730,121 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, int tile, 
     compute(r, cur);
   }
   // the top row of the grid: its stage 2 has the north wall above it
-  if constexpr (kTwo) {
-    if (j1 == ny) stage2(ny - 1, prv1, T(0), ob - row_b);
+  if (j1 == ny) stage2(ny - 1, prv1, T(0), ob - row_b, a_prev, T(0));
+}
+
+// Second launch of a pair, part `part` of region k's band, step n (the
+// pair's second step): the band around the region - Hz of every ring cell
+// (the coarse cell outside each port) and E on its edges other than
+// interface edges - advanced from the step-n set (stage-1 values of the
+// near tiles, interface E of the first launch's coupling) into the
+// step-(n+1) set with the stencil's arithmetic.  Hz^{n+1/2} of a ring cell
+// and of its neighbours is formed from the step-n set as the stencil forms
+// it (ring_h), so every value equals the one a single-step launch would
+// produce; an edge shared by two ring cells is formed by both, equal bit for
+// bit.  A region's 5 np samples (Hz and four edges per port) are dealt to
+// kBandSplit workgroups.
+template <typename T>
+__device__ __forceinline__ void band_block(const StepParams<T>& p, int k, int part, int n) {
+  const int par = n & 1;
+  const T* hz = fld(p, par, 0);
+  const T* ex = fld(p, par, 1);
+  const T* ey = fld(p, par, 2);
+  T* hzo = fld(p, par ^ 1, 0);
+  T* exo = fld(p, par ^ 1, 1);
+  T* eyo = fld(p, par ^ 1, 2);
+  const RomDev r = p.roms[k];
+  const int* gi = p.idx + r.i_off;
+  const int P = p.pitch;
+  auto mat = [&](int oc, T& a, T& b) {
+    if (p.midx) {
+      const MatPair<T> m = p.mt[p.mi[oc]];
+      a = m.a;
+      b = m.b;
+    } else {
+      a = p.al[oc];
+      b = p.be[oc];
+    }
+  };
+  auto srcs = [&](int comp, int ii, int jj) {
+    T acc = T(0);
+    for (int s = 0; s < p.nsrc; ++s) {
+      const Src<T>& S = p.src[s];
+      if (S.comp == comp && ii >= S.i0 && ii < S.i1 && jj >= S.j0 && jj < S.j1) acc += S.incr[n];
+    }
+    return acc;
+  };
+  const int items = 5 * r.np;
+  const int per = (items + kBandSplit - 1) / kBandSplit;
+  const int u1 = min(items, (part + 1) * per);
+  for (int u = part * per + threadIdx.x; u < u1; u += kBlock) {
+    const int port = u / 5, what = u - 5 * port;
+    const int o = gi[port];
+    const int j = o / P, i = o - j * P;
+    if (what == 0) {
+      T a, b;
+      mat(o, a, b);
+      hzo[o] = a > T(0) ? ring_h(p, hz, ex, ey, o, n) : T(0);
+      continue;
+    }
+    // edge between cells lo (south / west) and hi (north / east)
+    const bool isx = what <= 2;
+    const int hi = what == 1 ? o : what == 2 ? o + P : what == 3 ? o : o + 1;
+    const int lo = isx ? hi - P : hi - 1;
+    const int ei = isx ? i : (what == 3 ? i : i + 1);
+    const int ej = isx ? (what == 1 ? j : j + 1) : j;
+    if (isx ? (ej < 1 || ej > p.ny - 1) : (ei < 1 || ei > p.nx - 1)) continue;  // a wall
+    T a_hi, b_hi, a_lo, b_lo;
+    mat(hi, a_hi, b_hi);
+    mat(lo, a_lo, b_lo);
+    if ((a_hi < T(0)) != (a_lo < T(0))) continue;  // an interface edge: the coupling's
+    T v = isx ? ex[hi] : ey[hi];
+    if (a_hi > T(0) && a_lo > T(0)) {
+      T ca, cb;
+      edge_coef(a_hi + a_lo, b_hi + b_lo, isx ? p.k2dy : p.k2dx, ca, cb);
+      const T d = ring_h(p, hz, ex, ey, hi, n) - ring_h(p, hz, ex, ey, lo, n);
+      v = isx ? e_update(ca, v, cb, d) : e_update(ca, v, cb, -d);
+    }
+    if (p.nsrc > 0) v += srcs(isx ? 1 : 2, ei, ej);
+    (isx ? exo : eyo)[hi] = v;
   }
 }
 
-// First launch: workgroup t takes tile t (XCD-remapped), wave w its rows
-// [j0, j0+SEG).  Second launch: the near tiles' single step is short work
-// bound by the latency of each wave's row chain, so every near tile is
-// split over kNearSplit workgroups, each wave taking SEG/kNearSplit rows.
-
+// Far tiles of a pair: [0, far_split) go in the first launch, the rest in
+// the second (both only read step n and write step n+2, so either launch
+// may take them; the share in the second launch runs beside its coupling
+// blocks, whose chain of dependent loads would otherwise be alone there).
+// Workgroup t takes far slot t of its launch (XCD-remapped), wave w its rows
+// [j0, j0+SEG); a near tile in that slot returns (its pieces run
+// separately).
 template <typename T, int SEG, bool MIdx, bool Second>
 __device__ __forceinline__ void stencil2_tile(const StepParams<T>& p, int t, int n) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  if constexpr (Second) {
-    constexpr int rows = SEG / kNearSplit > 0 ? SEG / kNearSplit : 1;
-    const int u = xcd_tile(t, p.n_near * kNearSplit);
-    const int tile = p.near_list[u / kNearSplit];
-    const int jb0 = (tile / p.tiles_x2) * (kBlock / kWave) * SEG;
-    const int jb1 = min(jb0 + (kBlock / kWave) * SEG, p.ny);
-    const int j0 = jb0 + ((u % kNearSplit) * (kBlock / kWave) + wv) * rows;
-    if (j0 >= jb1) return;  // uniform over the wave
-    stencil2_rows<T, MIdx, 2>(p, tile, n, j0, min(j0 + rows, jb1));
-  } else {
-    const int tile = xcd_tile(t, p.nst2_blocks);
-    const int j0 = ((tile / p.tiles_x2) * (kBlock / kWave) + wv) * SEG;
-    if (j0 >= p.ny) return;  // uniform over the wave
-    const int j1 = min(j0 + SEG, p.ny);
-    if (p.role2[tile])
-      stencil2_rows<T, MIdx, 1>(p, tile, n, j0, j1);
-    else
-      stencil2_rows<T, MIdx, 0>(p, tile, n, j0, j1);
-  }
+  const int lo = Second ? p.far_split : 0, cnt = Second ? p.nst2_blocks - p.far_split : p.far_split;
+  const int tile = lo + xcd_tile(t, cnt);
+  if (p.role2[tile]) return;
+  const int j0 = ((tile / p.tiles_x2) * (kBlock / kWave) + wv) * SEG;
+  if (j0 >= p.ny) return;  // uniform over the wave
+  stencil2_rows<T, MIdx, false>(p, Second ? sets_second(p, n) : sets_first(p, n), tile, Second ? n - 1 : n, j0,
+                                min(j0 + SEG, p.ny));
+}
+
+// First launch, near tiles: each is split over pieces of near_rows-row waves.
+// Their sweep does more per row than a far tile's (stage-1 stores, source
+// terms, the band test); where the whole grid is resident at once the
+// longest wave sets the launch's length, so near waves are kept short there
+// (near_rows = 2), while larger grids keep whole tiles (less halo reread).
+template <typename T, int SEG, bool MIdx>
+__device__ __forceinline__ void stencil2_near(const StepParams<T>& p, int u, int n) {
+  const int rows = min(p.near_rows, SEG);
+  const int pieces = SEG / rows;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int tile = p.near_list[u / pieces];
+  const int jb0 = (tile / p.tiles_x2) * (kBlock / kWave) * SEG;
+  const int jb1 = min(jb0 + (kBlock / kWave) * SEG, p.ny);
+  const int j0 = jb0 + ((u % pieces) * (kBlock / kWave) + wv) * rows;
+  if (j0 >= jb1) return;  // uniform over the wave
+  stencil2_rows<T, MIdx, true>(p, sets_first(p, n), tile, n, j0, min(j0 + rows, jb1));
 }
 
 template <typename T>
@@ -956,30 +1108,24 @@ __device__ __forceinline__ T probe_next(const StepParams<T>& p, int t, int n) {
   return v;
 }
 
-// Probe block of a pair launch: the first records row n-1 (the step-n set)
-// and, for probes of far tiles, row n formed from step n; the second records
-// row n of the near probes from its step-n set (step n+1 of the pair).
-template <typename T, bool Second>
+// Probe block of a pair's first launch: row n-1 from the step-n set and
+// row n formed from step n (every probe: none sits on an interface edge).
+template <typename T>
 __device__ __forceinline__ void pair_probes(const StepParams<T>& p, int n) {
-  if constexpr (Second) {
-    const int par = n & 1;
-    for (int k = threadIdx.x; k < p.nprobes; k += kBlock)
-      if (p.probe_near[k]) p.probe_buf[(size_t)(n - 1) * p.nprobes + k] = fld(p, par, p.probe_comp[k])[p.probe_off[k]];
-  } else {
-    record_probes(p, n - 1);
-    for (int k = threadIdx.x; k < p.nprobes; k += kBlock)
-      if (!p.probe_near[k]) p.probe_buf[(size_t)n * p.nprobes + k] = probe_next(p, k, n);
-  }
+  record_probes(p, n - 1);
+  for (int k = threadIdx.x; k < p.nprobes; k += kBlock)
+    p.probe_buf[(size_t)n * p.nprobes + k] = probe_next(p, k, n);
 }
 
 // The pair of launches that advances steps n and n+1 (time blocking):
 //   first (Second = false): coupling blocks of step n (interface E^{n+1} into
-//     the step-(n+1) set), every tile (far: two steps into f2; near: one step
-//     with halo into the step-(n+1) set), probe block (row n-1 from the
-//     step-n set; row n of far probes formed from the step-n set);
+//     the step-(n+1) set), every tile (far: two steps into f2; near: two
+//     steps into f2 but for the band around each region, and step n+1 of
+//     its cells into the step-(n+1) set), probe block (row n-1 from the
+//     step-n set; row n formed from the step-n set);
 //   second: coupling blocks of step n+1 (reading the step-(n+1) set, writing
-//     f2's interface edges), the near tiles' step n+1 -> n+2 into f2 (here
-//     f[(n+1)&1 ^ 1]), probe block (row n of near probes).
+//     f2's interface edges) and one band block per region (the band's step
+//     n+1 -> n+2 into f2, here f[(n+1)&1 ^ 1]).
 template <typename T, int SEG, bool MIdx, bool Second>
 __global__ void __launch_bounds__(kBlock) step2_kernel(const StepParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -999,11 +1145,27 @@ __global__ void __launch_bounds__(kBlock) step2_kernel(const StepParams<T> p) {
     return;
   }
   const int t = b - p.ncoup_blocks;
-  if (t < (Second ? p.n_near * kNearSplit : p.nst2_blocks)) {
-    stencil2_tile<T, SEG, MIdx, Second>(p, t, n);
-    return;
+  if constexpr (Second) {
+    // band blocks padded to a multiple of 8 workgroups (XCD remap of the
+    // far tiles that follow)
+    const int nb = p.n_band * kBandSplit, nb8 = (nb + 7) & ~7;
+    if (t < nb8) {
+      if (t < nb) band_block(p, t / kBandSplit, t % kBandSplit, n);
+    } else {
+      stencil2_tile<T, SEG, MIdx, true>(p, t - nb8, n);
+    }
+  } else {
+    // near pieces padded to a multiple of 8 workgroups, so that the far
+    // tiles' XCD remap still sees workgroup t on XCD t % 8
+    const int nn = p.n_near * (SEG / min(p.near_rows, SEG)), nn8 = (nn + 7) & ~7;
+    if (t < nn8) {
+      if (t < nn) stencil2_near<T, SEG, MIdx>(p, t, n);
+    } else if (t < nn8 + p.far_split) {
+      stencil2_tile<T, SEG, MIdx, false>(p, t - nn8, n);
+    } else {
+      pair_probes(p, n);
+    }
   }
-  pair_probes<T, Second>(p, n);
 }
 
 template <typename T>
@@ -1081,8 +1243,9 @@ batch_probe_kernel(const StepParams<T>* __restrict__ descs, const int* __restric
 }
 
 // Batched pair launch: as batch_step_kernel, with the roles of the pair
-// launches (tiles of kind 1 are two-step tiles of the first launch or
-// near-tile pieces of the second; kind 2 is the pair's probe block).
+// launches (kind 1: far two-step tiles of the first launch, band blocks of
+// the second; kind 4: near-tile pieces of the first launch; kind 5: far
+// tiles of the second launch; kind 2: the first launch's probe block).
 template <typename T, bool MIdx, bool Second>
 __global__ void __launch_bounds__(kBlock)
 batch_step2_kernel(const StepParams<T>* __restrict__ descs, const BatchRef* __restrict__ table,
@@ -1103,16 +1266,38 @@ batch_step2_kernel(const StepParams<T>* __restrict__ descs, const BatchRef* __re
     coupling_rows(p, rb, n, reinterpret_cast<T*>(smem));
     return;
   }
-  if (r.kind == 1) {
-    switch (p.seg) {
-      case 4: stencil2_tile<T, 4, MIdx, Second>(p, r.idx, n); break;
-      case 16: stencil2_tile<T, 16, MIdx, Second>(p, r.idx, n); break;
-      case 32: stencil2_tile<T, 32, MIdx, Second>(p, r.idx, n); break;
-      default: stencil2_tile<T, 8, MIdx, Second>(p, r.idx, n); break;
+  if constexpr (Second) {
+    if (r.kind == 1) {
+      band_block(p, r.idx / kBandSplit, r.idx % kBandSplit, n);
+    } else if (r.kind == 5) {
+      switch (p.seg) {
+        case 4: stencil2_tile<T, 4, MIdx, true>(p, r.idx, n); break;
+        case 16: stencil2_tile<T, 16, MIdx, true>(p, r.idx, n); break;
+        case 32: stencil2_tile<T, 32, MIdx, true>(p, r.idx, n); break;
+        default: stencil2_tile<T, 8, MIdx, true>(p, r.idx, n); break;
+      }
     }
-    return;
+  } else {
+    if (r.kind == 1) {
+      switch (p.seg) {
+        case 4: stencil2_tile<T, 4, MIdx, false>(p, r.idx, n); break;
+        case 16: stencil2_tile<T, 16, MIdx, false>(p, r.idx, n); break;
+        case 32: stencil2_tile<T, 32, MIdx, false>(p, r.idx, n); break;
+        default: stencil2_tile<T, 8, MIdx, false>(p, r.idx, n); break;
+      }
+      return;
+    }
+    if (r.kind == 4) {
+      switch (p.seg) {
+        case 4: stencil2_near<T, 4, MIdx>(p, r.idx, n); break;
+        case 16: stencil2_near<T, 16, MIdx>(p, r.idx, n); break;
+        case 32: stencil2_near<T, 32, MIdx>(p, r.idx, n); break;
+        default: stencil2_near<T, 8, MIdx>(p, r.idx, n); break;
+      }
+      return;
+    }
+    pair_probes(p, n);
   }
-  pair_probes<T, Second>(p, n);
 }
 
 template <typename T>
@@ -1122,10 +1307,10 @@ hipError_t launch_batch_step2(const StepParams<T>* da, const BatchRef* ta, int n
   const dim3 blk(kBlock);
   if (midx) {
     hipLaunchKernelGGL((batch_step2_kernel<T, true, false>), dim3(na), blk, smem, s, da, ta, ctrl, step_off);
-    hipLaunchKernelGGL((batch_step2_kernel<T, true, true>), dim3(nb), blk, smem, s, db, tb, ctrl, step_off + 1);
+    if (nb > 0) hipLaunchKernelGGL((batch_step2_kernel<T, true, true>), dim3(nb), blk, smem, s, db, tb, ctrl, step_off + 1);
   } else {
     hipLaunchKernelGGL((batch_step2_kernel<T, false, false>), dim3(na), blk, smem, s, da, ta, ctrl, step_off);
-    hipLaunchKernelGGL((batch_step2_kernel<T, false, true>), dim3(nb), blk, smem, s, db, tb, ctrl, step_off + 1);
+    if (nb > 0) hipLaunchKernelGGL((batch_step2_kernel<T, false, true>), dim3(nb), blk, smem, s, db, tb, ctrl, step_off + 1);
   }
   return hipGetLastError();
 }
@@ -1241,25 +1426,29 @@ hipError_t launch_step(const StepParams<T>& p, int seg, size_t smem, hipStream_t
 
 template <typename T>
 hipError_t launch_step2(const StepParams<T>& a, const StepParams<T>& b, int seg, size_t smem, hipStream_t s) {
-  const dim3 ga(a.ncoup_blocks + a.nst2_blocks + 1), gb(b.ncoup_blocks + b.n_near * kNearSplit + 1), blk(kBlock);
+  // the second launch has nothing to do without regions and with every far
+  // tile in the first
+  const int nn = a.n_near * (seg / std::min(a.near_rows, seg));
+  const dim3 ga(a.ncoup_blocks + ((nn + 7) & ~7) + a.far_split + 1),
+      gb(b.ncoup_blocks + ((b.n_band * kBandSplit + 7) & ~7) + (b.nst2_blocks - b.far_split)), blk(kBlock);
   auto go = [&](auto midx) -> hipError_t {
     constexpr bool Mf = decltype(midx)::value;
     switch (seg) {
       case 4:
         hipLaunchKernelGGL((step2_kernel<T, 4, Mf, false>), ga, blk, smem, s, a);
-        hipLaunchKernelGGL((step2_kernel<T, 4, Mf, true>), gb, blk, smem, s, b);
+        if (gb.x > 0) hipLaunchKernelGGL((step2_kernel<T, 4, Mf, true>), gb, blk, smem, s, b);
         break;
       case 8:
         hipLaunchKernelGGL((step2_kernel<T, 8, Mf, false>), ga, blk, smem, s, a);
-        hipLaunchKernelGGL((step2_kernel<T, 8, Mf, true>), gb, blk, smem, s, b);
+        if (gb.x > 0) hipLaunchKernelGGL((step2_kernel<T, 8, Mf, true>), gb, blk, smem, s, b);
         break;
       case 16:
         hipLaunchKernelGGL((step2_kernel<T, 16, Mf, false>), ga, blk, smem, s, a);
-        hipLaunchKernelGGL((step2_kernel<T, 16, Mf, true>), gb, blk, smem, s, b);
+        if (gb.x > 0) hipLaunchKernelGGL((step2_kernel<T, 16, Mf, true>), gb, blk, smem, s, b);
         break;
       case 32:
         hipLaunchKernelGGL((step2_kernel<T, 32, Mf, false>), ga, blk, smem, s, a);
-        hipLaunchKernelGGL((step2_kernel<T, 32, Mf, true>), gb, blk, smem, s, b);
+        if (gb.x > 0) hipLaunchKernelGGL((step2_kernel<T, 32, Mf, true>), gb, blk, smem, s, b);
         break;
       default: return hipErrorInvalidValue;
     }

@@ -200,8 +200,6 @@ int fdtd::plan_problem(const fdtd_problem* p, Layout& L) {
     o = align_up(o + (size_t)L.max_tiles2, 256);
     L.off_near = o;
     o = align_up(o + (size_t)L.max_tiles2 * sizeof(int), 256);
-    L.off_pnear = o;
-    o = align_up(o + (size_t)std::max(p->nprobes, 1), 256);
   }
   L.total = o;
   return FDTD_OK;
@@ -869,8 +867,9 @@ void fdtd::set_tiling(fdtd_rom_sim* s, int seg) {
 // clear of every region's zone [i0-2, i0+ni+1] x [j0-2, j0+nj+1] (the
 // region, its ring of port cells and the edges between them, with one
 // cell to spare) and of every source rectangle (widened by one); otherwise
-// it is near.  A probe is near when the tile that
-// owns its cell is.  Uploaded synchronously (never while capturing).
+// it is near.  Every cell whose step-(n+1) values the second launch's band
+// blocks read (ring cells, their neighbours and the neighbours' edges) is
+// owned by a near tile.  Uploaded synchronously (never while capturing).
 template <typename T>
 int fdtd::prepare_tb(fdtd_rom_sim* s) {
   const Layout& L = s->L;
@@ -898,25 +897,34 @@ int fdtd::prepare_tb(fdtd_rom_sim* s) {
     }
     if (role[t]) near.push_back(t);
   }
-  std::vector<uint8_t> pnear(std::max(s->nprobes, 1), 0);
-  for (int k = 0; k < s->nprobes; ++k) {
-    const fdtd_probe& pr = s->probes[k];
-    pnear[k] = role[(pr.j / rows) * tx2 + pr.i / kOwned2];
-  }
   hipStream_t st = s->stream;
   if (hipMemcpyAsync(s->ws + L.off_role2, role.data(), role.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       (!near.empty() && hipMemcpyAsync(s->ws + L.off_near, near.data(), near.size() * sizeof(int),
                                        hipMemcpyHostToDevice, st) != hipSuccess) ||
-      hipMemcpyAsync(s->ws + L.off_pnear, pnear.data(), pnear.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(FDTD_EDEVICE, "two-step tile upload failed");
+  // pieces of near tiles and the far tiles' share in the second launch
+  // (set_pair_split; the default keeps every far tile in the first launch
+  // where the whole grid's tiles are resident at once, else moves a share
+  // that runs beside the second launch's coupling blocks)
+  const int resident = 256 * 7;  // two-step tiles the GPU holds at once (256 CUs, 7 per CU)
+  // the long chain of a shared model's MFMA GEMM blocks is worth hiding
+  // under far tiles (4096^2 with 256 copies of one order-128 model: 176 ->
+  // 155 us per pair at 50 %); row-parallel GEMV blocks are short (8192^2
+  // with 256 models of orders 32-96: 490 us per pair at 0 %, 555 at 50 %)
+  bool gemm = false;
+  for (size_t sl = 0; sl < L.slot_gemm.size(); ++sl) gemm = gemm || (L.slot_gemm[sl] && s->shared_gemm);
+  const int split_pct = s->pair_split >= 0 ? s->pair_split : (nt > resident && gemm ? 50 : 0);
+  const int near_rows = nt <= resident ? 2 : s->seg;
   auto fill = [&](auto& sp) {
     sp.tiles_x2 = tx2;
     sp.nst2_blocks = nt;
     sp.n_near = (int)near.size();
+    sp.n_band = s->nroms;
+    sp.near_rows = near_rows;
+    sp.far_split = nt - (int)((int64_t)nt * split_pct / 100);
     sp.role2 = (const uint8_t*)(s->ws + L.off_role2);
     sp.near_list = (const int*)(s->ws + L.off_near);
-    sp.probe_near = (const uint8_t*)(s->ws + L.off_pnear);
   };
   fill(s->sp_f);
   fill(s->sp_d);
@@ -974,6 +982,7 @@ int enqueue_steps(fdtd_rom_sim* s, int nsteps, hipStream_t stream, bool prof, in
         a.f2[c] = sp.f[par ^ 1][c];
         b.f[par ^ 1][c] = fc[c];
         b.f[par][c] = sp.f[par ^ 1][c];
+        b.f2[c] = sp.f[par][c];  // the second launch's far tiles read step n
       }
       a.step_off = k;
       b.step_off = k + 1;
@@ -1573,6 +1582,25 @@ int fdtd_rom_set_tiling(fdtd_rom_sim* sim, int32_t seg) {
   return FDTD_OK;
 }
 
+int fdtd_rom_set_pair_split(fdtd_rom_sim* sim, int32_t percent) {
+  if (!sim) return fail(FDTD_EINVAL, "null handle");
+  if (percent != -1 && (percent < 0 || percent > 90)) return fail(FDTD_EINVAL, "split must be -1 or 0..90 percent");
+  sim->pair_split = percent;
+  sim->tb_seg = 0;  // tile roles and launch shapes are rebuilt before the next pair
+  drop_graph(sim);
+  return FDTD_OK;
+}
+
+int fdtd_rom_get_pair_split(const fdtd_rom_sim* sim, int32_t* percent) {
+  if (!sim || !percent) return fail(FDTD_EINVAL, "null argument");
+  const StepParams<float>& sp = sim->sp_f;
+  const StepParams<double>& sd = sim->sp_d;
+  const int nt = sim->dtype == FDTD_F32 ? sp.nst2_blocks : sd.nst2_blocks;
+  const int split = sim->dtype == FDTD_F32 ? sp.far_split : sd.far_split;
+  *percent = (sim->tb_seg == sim->seg && nt > 0) ? (int)((int64_t)(nt - split) * 100 / nt) : sim->pair_split;
+  return FDTD_OK;
+}
+
 int fdtd_rom_get_tiling(const fdtd_rom_sim* sim, int32_t* seg) {
   if (!sim || !seg) return fail(FDTD_EINVAL, "null argument");
   *seg = sim->seg;
@@ -1598,6 +1626,7 @@ int fdtd_rom_set_shared_gemm(fdtd_rom_sim* sim, int32_t enable) {
   }
   sim->smem = on ? L.smem_mixed : L.smem_gemv;
   sim->shared_gemm = on;
+  sim->tb_seg = 0;  // the default far-tile split follows the coupling path
   drop_graph(sim);
   return FDTD_OK;
 }

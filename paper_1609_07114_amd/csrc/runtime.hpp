@@ -35,7 +35,7 @@ struct Layout {
   // pair writes near regions, tile roles, near-tile list, near-probe flags
   bool tb_ok = false;
   int max_tiles2 = 0;
-  size_t off_fc = 0, off_role2 = 0, off_near = 0, off_pnear = 0;
+  size_t off_fc = 0, off_role2 = 0, off_near = 0;
   size_t mats_elems = 0, xs_elems = 0, idx_elems = 0;
   int nrowblocks = 0;        // all-GEMV coupling list
   int nblocks_mixed = 0;     // GEMM for eligible shared groups + GEMV for the rest
@@ -88,6 +88,7 @@ struct fdtd_rom_sim {
   // (n & 1) ^ flip; a pair of launches writes step n+2 into the other set)
   bool tb = false;
   int tb_seg = 0;
+  int pair_split = -1;   // percent of far tiles in a pair's second launch (-1: default)
   int flip = 0;
   // periodic finiteness check of the field set: every check_every steps
   // (0: never) run() launches finite_check_kernel; a run that launched one

@@ -107,6 +107,12 @@ class Simulation:
     def time_blocking(self):
         return capi.fdtd_rom_get_time_blocking(self.h)
 
+    def set_pair_split(self, percent):
+        capi.fdtd_rom_set_pair_split(self.h, percent)
+
+    def pair_split(self):
+        return capi.fdtd_rom_get_pair_split(self.h)
+
     def adjoint(self, nsteps=None, probe=0, ckpt_every=0):
         """Forward run from the initial state plus the reverse sweep:
         (J, dJ/deps_r, dJ/dsigma) for J = dt * sum_n Hz_probe(n+1/2)^2."""

@@ -301,3 +301,24 @@ def test_restore_into_handle_with_traded_sets(mixed):
         assert np.array_equal(s2.probes(42, p.nsteps - 42), ref[0][42:])
         for c in range(3):
             assert np.array_equal(s2.field(c), ref[1][c])
+
+
+@pytest.mark.parametrize("split", [0, 30, 90])
+def test_far_tiles_in_second_launch_bit_identical(split):
+    """Far tiles moved into the second launch of each pair (any share) give
+    the same bits as one launch per step, with regions, sources and graphs."""
+    p = W.random_problem(91, 300, 170, 120, nroms=3, block=(5, 4), r=2, q=12, dtype="f32")
+    roms = osim.build_roms(p)
+    with Simulation(p, roms, max_steps=120) as s:
+        s.set_time_blocking(False)
+        s.run(120)
+        ref = (s.probes(), s.field(0), s.field(1), s.field(2))
+    with Simulation(p, roms, max_steps=120) as s:
+        s.set_pair_split(split)
+        s.set_graph(24)
+        s.run(50)
+        s.run(70)
+        assert s.pair_split() == pytest.approx(split, abs=1)
+        got = (s.probes(), s.field(0), s.field(1), s.field(2))
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
