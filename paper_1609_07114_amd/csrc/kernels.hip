@@ -1025,7 +1025,8 @@ __device__ __forceinline__ void record_probes(const StepParams<T>& p, int m) {
 }
 
 template <typename T, int SEG, bool Layers, bool MIdx>
-__global__ void __launch_bounds__(kBlock) step_kernel(const StepParams<T> p) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !Layers ? 8 : 1, 8)))
+step_kernel(const StepParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = p.ctrl[0] + p.step_off;
   const int b = blockIdx.x;
@@ -1126,8 +1127,12 @@ __device__ __forceinline__ void pair_probes(const StepParams<T>& p, int n) {
 //   second: coupling blocks of step n+1 (reading the step-(n+1) set, writing
 //     f2's interface edges) and one band block per region (the band's step
 //     n+1 -> n+2 into f2, here f[(n+1)&1 ^ 1]).
+// FP32: eight waves per SIMD (the scalar registers the near tiles' source
+// terms take would otherwise hold it to seven; the compiler keeps them in
+// vector lanes, no scratch)
 template <typename T, int SEG, bool MIdx, bool Second>
-__global__ void __launch_bounds__(kBlock) step2_kernel(const StepParams<T> p) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8)))
+step2_kernel(const StepParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = p.ctrl[0] + p.step_off;
   const int b = blockIdx.x;
