@@ -17,6 +17,8 @@ Modules
   sim        whole coupled run: probes, energy (Sec. IV, Sec. V, Appendix)
   subgrid    direct merged-edge subgridding (an independent check of the coupling)
   adjoint    discrete adjoint of the coupled run (gradients w.r.t. cell materials)
+  model_grad gradients through the reduced models: eq. (23) closed form, ring
+             cells, the eq. (27) clip and the congruence (fine-cell materials)
 
 Parity status per function is stated in each module header.
 """

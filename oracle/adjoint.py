@@ -80,16 +80,18 @@ def forward_states(prob, roms, nsteps=None, probe=0, fp32=False):
             s += (run.pml.psi_ex.copy(), run.pml.psi_ey.copy())
         return s
     states = [snap()]
+    run.x_hist = [[x.copy() for x in run.x]]   # reduced states x~^n, n = 0..N
     J = 0.0
     pr = prob.probes[probe]
     for n in range(nsteps):
         run.step()
         states.append(snap())
+        run.x_hist.append([x.copy() for x in run.x])
         J += prob.dt * run.f.hz[pr.j, pr.i] ** 2
     return run, states, J
 
 
-def transpose_step(run, Gs, lam):
+def transpose_step(run, Gs, lam, lam_out=None):
     """lambda^n = M^T lambda^{n+1} for one forward step M of ``run``
     (steps 3, 2, 1 of the module docstring transposed, in that order).
     lam = (lam_ex, lam_ey, lam_hz, lam_x) is the adjoint of the state after
@@ -97,7 +99,9 @@ def transpose_step(run, Gs, lam):
     absorbing layers by (lam_psi_hx, lam_psi_hy, lam_psi_ex, lam_psi_ey).
     Returns the adjoint of the state before the step (same layout) and
     (lex, ley), the adjoint of the new E on the edges eq. (3) updates (the
-    coefficient gradients' weights)."""
+    coefficient gradients' weights).  ``lam_out`` (a list, optional)
+    receives per model the adjoint of the step's eq. (23) outputs
+    [x~^{n+1}; y^{n+1}]."""
     pml = run.pml
     lam_ex, lam_ey, lam_hz, lam_x = lam[:4]
     cell, exm, eym = run.cell, run.exm, run.eym
@@ -110,6 +114,8 @@ def transpose_step(run, Gs, lam):
     new_lam_x = []
     for c, G, lx in zip(run.cpl, Gs, lam_x):
         ly = c.read_y(lam_ex_in, lam_ey_in)
+        if lam_out is not None:
+            lam_out.append(np.concatenate([lx, ly]))
         back = G.T @ np.concatenate([lx, ly])
         new_lam_x.append(back[:c.q].copy())
         for k, (_, _, _, oi, oj, _, _) in enumerate(c.ports):
@@ -161,10 +167,12 @@ def transpose_step(run, Gs, lam):
     return out, (lex, ley)
 
 
-def adjoint_gradient(prob, roms, nsteps=None, probe=0, fp32=False):
-    """Return (J, dJ/deps_r [ny,nx], dJ/dsigma [ny,nx]).  fp32: transpose of
-    the forward with FP32-rounded coefficients (see forward_states)."""
-    nsteps = prob.nsteps if nsteps is None else nsteps
+def _sweep(prob, roms, nsteps, probe, fp32, models):
+    """Forward run and reverse sweep.  Returns (run, J, [g_ca_x, g_cb_x,
+    g_ca_y, g_cb_y], dG): the gradients of J with respect to the eq. (3)
+    coefficients of every E edge, and with ``models`` per model the
+    gradient with respect to its eq. (23) update matrix G,
+    dJ/dG = sum_n lam_out^{n+1} [x~^n; h^{n+1/2}]^T (else None)."""
     run, states, J = forward_states(prob, roms, nsteps, probe, fp32)
     pml = run.pml
     nx, ny = prob.nx, prob.ny
@@ -173,6 +181,7 @@ def adjoint_gradient(prob, roms, nsteps=None, probe=0, fp32=False):
     if pr.comp != yee.HZ:
         raise ValueError("objective probe must be an Hz probe")
     Gs = [c.G32 if fp32 else c.update_matrix() for c in run.cpl]
+    dG = [np.zeros_like(G) for G in Gs] if models else None
     lam = (np.zeros((ny + 1, nx)), np.zeros((ny, nx + 1)), np.zeros((ny, nx)),
            [np.zeros(c.q) for c in run.cpl])
     if pml is not None:
@@ -188,7 +197,12 @@ def adjoint_gradient(prob, roms, nsteps=None, probe=0, fp32=False):
         # objective: J += dt (Hz'_p)^2
         lam_hz = lam[2].copy()
         lam_hz[pr.j, pr.i] += 2.0 * prob.dt * hz1[pr.j, pr.i]
-        lam, (lex, ley) = transpose_step(run, Gs, (lam[0], lam[1], lam_hz) + tuple(lam[3:]))
+        lam_out = [] if models else None
+        lam, (lex, ley) = transpose_step(run, Gs, (lam[0], lam[1], lam_hz) + tuple(lam[3:]), lam_out)
+        if models:
+            for k, c in enumerate(run.cpl):
+                z = np.concatenate([run.x_hist[n][k], c.gather(hz1)])
+                dG[k] += np.outer(lam_out[k], z)
         dhx = np.zeros((ny + 1, nx))
         dhx[1:ny, :] = hz1[1:, :] - hz1[:-1, :]
         dhy = np.zeros((ny, nx + 1))
@@ -200,7 +214,14 @@ def adjoint_gradient(prob, roms, nsteps=None, probe=0, fp32=False):
         g_cbx += lex * dhx
         g_cay += ley * ey0
         g_cby -= ley * dhy
-    # chain rule to cell materials
+    return run, J, (g_cax, g_cbx, g_cay, g_cby), dG
+
+
+def _cell_gradient(prob, g_edges):
+    """Chain rule from the eq. (3) coefficients of the updated edges to the
+    per-cell eps_r and sigma (unmasked)."""
+    g_cax, g_cbx, g_cay, g_cby = g_edges
+    nx, ny = prob.nx, prob.ny
     ax, bx, ay, by = _edge_ab(prob)
     d = {}
     for (gca, gcb, a, b, dd, sl) in ((g_cax, g_cbx, ax, bx, prob.dy, (slice(1, ny), slice(None))),
@@ -226,6 +247,15 @@ def adjoint_gradient(prob, roms, nsteps=None, probe=0, fp32=False):
     gsig[1:, :] += fb * gex_b
     gsig[:, :-1] += fb * gey_b
     gsig[:, 1:] += fb * gey_b
+    return geps, gsig
+
+
+def adjoint_gradient(prob, roms, nsteps=None, probe=0, fp32=False):
+    """Return (J, dJ/deps_r [ny,nx], dJ/dsigma [ny,nx]).  fp32: transpose of
+    the forward with FP32-rounded coefficients (see forward_states)."""
+    nsteps = prob.nsteps if nsteps is None else nsteps
+    _, J, g_edges, _ = _sweep(prob, roms, nsteps, probe, fp32, models=False)
+    geps, gsig = _cell_gradient(prob, g_edges)
     m = gradient_mask(prob)
     return J, np.where(m, geps, 0.0), np.where(m, gsig, 0.0)
 

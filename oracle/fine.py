@@ -136,7 +136,7 @@ def assemble(eps_r, sigma, dxh, dyh, dt):
                         np.full(Ny, +dyh), np.full(Ny, -dyh)])
     B = L @ sp.diags(S)
     return dict(R=R.tocsr(), F=F.tocsr(), B=B.tocsr(), L=L, S=S, De=De, Ds=Ds,
-                Dm=Dm, K=K, index=ix)
+                Dm=Dm, K=K, index=ix, dxh=dxh, dyh=dyh)
 
 
 def pinned_edges(pec, Nx, Ny):

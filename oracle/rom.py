@@ -173,12 +173,18 @@ def build_rom(eps_r, sigma, r, dx, dy, dt, q, f_max, basis="sprim", clip=True,
               theta=0.99, pec=None):
     """Reduced model of one refined region.
 
-    Returns dict(Rt, Ft, Lt, q1, q2, Sc, smax_before, smax_after, clipped, p0).
-    ``basis='identity'`` skips reduction (V = I, q = restricted state size).
+    Returns dict(Rt, Ft, Lt, q1, q2, Sc, smax_before, smax_after, clipped, p0,
+    V1, V2, K0 (K~ before the clip), model).
+    ``basis='identity'`` skips reduction (V = I, q = restricted state size);
+    ``basis=(V1, V2)`` projects on the given basis (a basis built earlier,
+    held fixed while the material changes).
     ``pec``: fine cells that are perfect conductors (their samples are
     left out of the model, see ``fine``)."""
     model = fine.restricted_model(eps_r, sigma, r, dx, dy, dt, pec)
-    if basis == "identity":
+    if isinstance(basis, tuple):
+        V1, V2 = basis
+        p0 = float("nan")
+    elif basis == "identity":
         n_e, n_h = model["n_e"], model["n_h"]
         V1 = np.eye(n_e)
         V2 = np.eye(n_h)
@@ -191,13 +197,14 @@ def build_rom(eps_r, sigma, r, dx, dy, dt, q, f_max, basis="sprim", clip=True,
     q1 = V1.shape[1]
     q2 = V2.shape[1]
     Rt, Ft, Lt = congruence(model, V1, V2)
+    K0 = -2.0 * Rt[:q1, q1:]
     smax0 = smax1 = float("nan")
     clipped = False
     if clip:
         Rt, Ft, smax0, smax1, clipped = cfl_clip(Rt, Ft, q1, dt, theta)
     return dict(Rt=Rt, Ft=Ft, Lt=Lt, q1=q1, q2=q2, Sc=model["S"], p0=p0,
                 smax_before=smax0, smax_after=smax1, clipped=clipped,
-                V1=V1, V2=V2, model=model)
+                V1=V1, V2=V2, K0=K0, model=model, theta=theta, dt=dt)
 
 
 def transfer(Rt, Ft, Lt, Sc, p):
