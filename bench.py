@@ -114,7 +114,8 @@ def stencil_roofline(prob, steps, ev_ms, mmode, tb, seg, kind):
 KERNEL_SOURCES = ("paper_1609_07114_amd/csrc/kernels.hip", "paper_1609_07114_amd/csrc/common.hpp",
                   "paper_1609_07114_amd/csrc/device.hpp")
 COUNTERS = {"c3": os.path.join(ROOT, "profiles", "step2_pair_c3_4096_hbm_counters.json"),
-            "c2": os.path.join(ROOT, "profiles", "stencil_c2_2048_hbm_counters.json")}
+            "c2": os.path.join(ROOT, "profiles", "step2_pair_c2_2048_hbm_counters.json"),
+            "hbm": os.path.join(ROOT, "profiles", "step2_pair_hbm_8192_counters.json")}
 
 
 def kernel_source_hash():
@@ -658,6 +659,13 @@ def main():
     if args.copy_ceiling:
         print(json.dumps({"copy_ceiling": copy_ceiling()}), flush=True)
         return
+    if args.calibrate_copy_mib:
+        nb = args.calibrate_copy_mib << 20
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if args.only:
         kw = {} if args.form_steps is None or args.only == "adjoint" else {"steps": args.form_steps}
         fn = {"batched": bench_batched, "gemv_vs_gemm": bench_gemv_vs_gemm, "adjoint": bench_adjoint,
@@ -681,13 +689,6 @@ def main():
     roms = romgen.build_roms(prob)
     t_build = time.perf_counter() - t0
     log(f"{len(roms)} reduced models built in {t_build:.1f} s")
-
-    if args.calibrate_copy_mib:
-        nb = args.calibrate_copy_mib << 20
-        a = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
 
     r = run_headline(prob, roms, args.steps, args.warmup, kind, args.workload, args.time_blocking,
                      args.material_mode, log=log)

@@ -320,6 +320,29 @@ typedef struct {
 int fdtd_rom_build(const fdtd_rom_build_params* params, double* Rt, double* Ft, double* Lt,
                    fdtd_rom_build_info* info);
 
+/* Gradient through the model builder: given dJ/dR~ and dJ/dF~ of the model
+ * fdtd_rom_build makes from params (e.g. from fdtd_rom_adjoint_models), the
+ * gradient of J with respect to the fine cells' eps_r and sigma, with the
+ * projection basis V = blkdiag(V1, V2) held at the one built from params
+ * (the parametric model R~(p) = V^T R(p) V; for basis 1 nothing is held).
+ * Steps, reversed: the eq. (27) clip when it is active (K~_c =
+ * R11^{1/2} M g(M^T M) R22^{1/2}, M = R11^{-1/2} K~ R22^{-1/2},
+ * g(mu) = min(1, lim / sqrt(mu)), lim = theta 2/dt; only R11 = dt R~11
+ * depends on the material, its path goes through the eigen-decompositions
+ * of R11 and M^T M by the Daleckii-Krein rule), the congruence of
+ * eqs. (11)-(12) (dJ/dDe_e = (V1 dR~11 V1^T)_ee / dt,
+ * dJ/dDs_e = (V1 dF~11 V1^T)_ee / 2 per fine edge coordinate), then eqs.
+ * (3)-(4): each fine edge holds half the cell area of each adjacent fine
+ * cell (De = area/2 eps0 eps_r, Ds = area/2 sigma per cell).  L~ does not
+ * depend on the material.  The result depends on V only through its
+ * column spaces.  PEC fine cells report zero.
+ *   grad_Rt, grad_Ft: host [q*q] row-major; outputs grad_eps_r, grad_sigma:
+ *   host fine maps [(r*nj) * (r*ni)], caller-allocated.  Same errors as
+ *   fdtd_rom_build, plus FDTD_EINVAL if an eigen-decomposition of the clip
+ *   does not converge.  Thread-safe. */
+int fdtd_rom_build_vjp(const fdtd_rom_build_params* params, const double* grad_Rt, const double* grad_Ft,
+                       double* grad_eps_r, double* grad_sigma);
+
 /* Per-kernel timing with HIP events on the handle's stream.  One step is
  * one launch of the step kernel (coarse stencil, every model's eq. (23)
  * update and the probe record run as concurrent workgroups of that launch);
@@ -439,6 +462,37 @@ int fdtd_rom_adjoint_plan(const fdtd_problem* prob, int32_t nsteps, int32_t ckpt
 int fdtd_rom_adjoint(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int32_t probe,
                      void* dev_adj_ws, size_t ws_bytes, double* J, double* grad_eps_r,
                      double* grad_sigma);
+
+/* Gradients through the reduced models.  The same objective and reverse
+ * sweep as fdtd_rom_adjoint; in addition the sweep sums, per region, the
+ * gradient of J with respect to its eq. (23) update matrix G on
+ * [x~^n; h^{n+1/2}] (dJ/dG = sum_n (adjoint of [x~^{n+1}; y^{n+1}]) x
+ * [x~^n; h^{n+1/2}]^T, FP64 accumulators), and the host carries it through
+ * the closed form of eq. (23) (Sec. IV-C: M = R~ + F~ + L~ C+ L~^T,
+ * N = R~ - F~ + L~ C- L~^T, A~ = M^{-1} N, B~' = M^{-1} L~ Sc, C~ = L~^T)
+ * to each region's R~, F~, L~ and to the eq. (13) half cells
+ * C+- = Dl Dl' (eps0 eps_r/dt +- sigma/2) of the coarse cells just outside
+ * its ports.  Those ring cells therefore report their whole gradient (the
+ * coarse stencil's part plus the half cells' part); cells inside a region
+ * report zero (their coarse material takes no part in the run).  Feed
+ * dJ/dR~ and dJ/dF~ to fdtd_rom_build_vjp for the fine cells' gradient.
+ *
+ * fdtd_rom_adjoint_models_workspace_size: the adjoint workspace plus one
+ * FP64 accumulator of (q+np)^2 (rows padded to 64) per region.
+ * fdtd_rom_adjoint_models: arguments as fdtd_rom_adjoint, plus
+ *   grad_Rt, grad_Ft, grad_Lt: host arrays of nroms pointers (an array, or
+ *     any entry, may be NULL to skip it): region k's dJ/dR~ and dJ/dF~
+ *     (q x q) and dJ/dL~ (q x np), row-major like the fdtd_rom inputs,
+ *     caller-allocated.  The matrices' gradients are taken at the FP64
+ *     models given to fdtd_rom_create (an FP32 run's trajectories, FP64
+ *     algebra).  FDTD_ENOTPASSIVE if a region's M is singular.
+ * Synchronises the stream. */
+int fdtd_rom_adjoint_models_workspace_size(const fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every,
+                                           size_t* bytes);
+int fdtd_rom_adjoint_models(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int32_t probe,
+                            void* dev_adj_ws, size_t ws_bytes, double* J, double* grad_eps_r,
+                            double* grad_sigma, double* const* grad_Rt, double* const* grad_Ft,
+                            double* const* grad_Lt);
 
 /* The same reverse sweep for callers that cannot allocate device memory
  * (code that may not call hipMalloc: tight serving loops, harnesses that

@@ -121,6 +121,12 @@ _SIGS = {
     "fdtd_rom_adjoint_plan": (C.c_int, [C.POINTER(fdtd_problem), C.c_int32, C.c_int32,
                                         C.POINTER(C.c_size_t)]),
     "fdtd_rom_adjoint_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _dp, _dp, _dp]),
+    "fdtd_rom_adjoint_models_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
+                                                         C.POINTER(C.c_size_t)]),
+    "fdtd_rom_adjoint_models": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                          C.c_size_t, _dp, _dp, _dp, C.POINTER(_dp), C.POINTER(_dp),
+                                          C.POINTER(_dp)]),
+    "fdtd_rom_build_vjp": (C.c_int, [C.POINTER(fdtd_rom_build_params), _dp, _dp, _dp, _dp]),
     "fdtd_rom_energy": (C.c_int, [C.c_void_p, _dp]),
     "fdtd_rom_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "fdtd_rom_get_state": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -352,6 +358,31 @@ def fdtd_rom_build(ni, nj, r, dx, dy, dt, eps_r, sigma, q, f_max, theta=0.99, cl
                 clipped=bool(info.clipped), n_fine_states=info.n_fine_states)
 
 
+def fdtd_rom_build_vjp(ni, nj, r, dx, dy, dt, eps_r, sigma, q, f_max, grad_Rt, grad_Ft, theta=0.99,
+                       clip=True, basis="sprim", pec=None):
+    """Fine-cell gradients (dJ/deps_r, dJ/dsigma, each [r*nj, r*ni]) from
+    dJ/dR~ and dJ/dF~ of the model fdtd_rom_build makes from the same
+    arguments, with its projection basis held (library, host FP64)."""
+    er = np.ascontiguousarray(eps_r, dtype=np.float64)
+    sg = np.ascontiguousarray(sigma, dtype=np.float64)
+    assert er.shape == (r * nj, r * ni) and sg.shape == er.shape
+    gR = np.ascontiguousarray(grad_Rt, dtype=np.float64)
+    gF = np.ascontiguousarray(grad_Ft, dtype=np.float64)
+    b = {"sprim": 0, "identity": 1}[basis]
+    keep = []
+    prm = fdtd_rom_build_params(ni, nj, r, dx, dy, dt, _ptr(er), _ptr(sg), q, f_max, theta,
+                                1 if clip else 0, b, _mask(pec, keep, er.shape))
+    if b == 1:
+        info = fdtd_rom_build_info()
+        _check(lib().fdtd_rom_build(C.byref(prm), None, None, None, C.byref(info)))
+        prm.q = info.n_fine_states
+    assert gR.shape == (prm.q, prm.q) and gF.shape == gR.shape, (gR.shape, prm.q)
+    ge = np.zeros(er.shape)
+    gs = np.zeros(er.shape)
+    _check(lib().fdtd_rom_build_vjp(C.byref(prm), _ptr(gR), _ptr(gF), _ptr(ge), _ptr(gs)))
+    return ge, gs
+
+
 def fdtd_rom_profile_enable(h, enable: bool):
     _check(lib().fdtd_rom_profile_enable(h, 1 if enable else 0))
 
@@ -440,6 +471,29 @@ def fdtd_rom_adjoint(h, nsteps: int, ckpt_every: int, probe: int, dev_ptr: int, 
     _check(lib().fdtd_rom_adjoint(h, int(nsteps), int(ckpt_every), int(probe), C.c_void_p(dev_ptr),
                                   nbytes, C.byref(J), _ptr(ge), _ptr(gs)))
     return float(J.value), ge, gs
+
+
+def fdtd_rom_adjoint_models_workspace_size(h, nsteps: int, ckpt_every: int = 0) -> int:
+    n = C.c_size_t(0)
+    _check(lib().fdtd_rom_adjoint_models_workspace_size(h, int(nsteps), int(ckpt_every), C.byref(n)))
+    return int(n.value)
+
+
+def fdtd_rom_adjoint_models(h, nsteps: int, ckpt_every: int, probe: int, dev_ptr: int, nbytes: int,
+                            nx: int, ny: int, shapes):
+    """Returns (J, dJ/deps_r [ny, nx], dJ/dsigma [ny, nx], [dict(Rt, Ft, Lt)]
+    per region); shapes: [(q, np)] per region."""
+    J = C.c_double(0)
+    ge = np.zeros((ny, nx), dtype=np.float64)
+    gs = np.zeros((ny, nx), dtype=np.float64)
+    outs = [dict(Rt=np.zeros((q, q)), Ft=np.zeros((q, q)), Lt=np.zeros((q, n))) for (q, n) in shapes]
+    arr = (_dp * max(len(outs), 1))
+    rt = arr(*[_ptr(o["Rt"]) for o in outs])
+    ft = arr(*[_ptr(o["Ft"]) for o in outs])
+    lt = arr(*[_ptr(o["Lt"]) for o in outs])
+    _check(lib().fdtd_rom_adjoint_models(h, int(nsteps), int(ckpt_every), int(probe), C.c_void_p(dev_ptr),
+                                         nbytes, C.byref(J), _ptr(ge), _ptr(gs), rt, ft, lt))
+    return float(J.value), ge, gs, outs
 
 
 def fdtd_rom_adjoint_plan(problem: ProblemStruct, nsteps: int, ckpt_every: int = 0) -> int:

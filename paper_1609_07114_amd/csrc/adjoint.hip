@@ -115,6 +115,37 @@ hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void rom_xstride(RomDev* out, const RomDev* in, int nroms, int64_t xstride) {
+  for (int k = threadIdx.x; k < nroms; k += blockDim.x) {
+    RomDev r = in[k];
+    r.xstride = xstride;
+    out[k] = r;
+  }
+}
+
+hipError_t launch_rom_xstride(RomDev* out, const RomDev* in, int nroms, int64_t xstride, hipStream_t s) {
+  if (nroms <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rom_xstride, dim3(1), dim3(kBlock), 0, s, out, in, nroms, xstride);
+  return hipGetLastError();
+}
+
+// one workgroup per region
+template <typename T>
+__global__ void __launch_bounds__(kBlock) states_to_image(const T* __restrict__ src, T* __restrict__ dst,
+                                                        const RomDev* __restrict__ roms, int par) {
+  const RomDev r = roms[blockIdx.x];
+  for (int a = threadIdx.x; a < r.q; a += kBlock) dst[r.x_off + a] = src[r.x_off + par * r.xstride + a];
+}
+
+template <typename T>
+hipError_t launch_states_to_image(const T* src, T* dst, const RomDev* roms, int nroms, int par, hipStream_t s) {
+  if (nroms <= 0) return hipSuccess;
+  hipLaunchKernelGGL((states_to_image<T>), dim3(nroms), dim3(kBlock), 0, s, src, dst, roms, par);
+  return hipGetLastError();
+}
+
+template hipError_t launch_states_to_image<float>(const float*, float*, const RomDev*, int, int, hipStream_t);
+template hipError_t launch_states_to_image<double>(const double*, double*, const RomDev*, int, int, hipStream_t);
 template hipError_t launch_transpose_block<float>(const float*, float*, int, int, hipStream_t);
 template hipError_t launch_transpose_block<double>(const double*, double*, int, int, hipStream_t);
 template hipError_t launch_probe_energy<float>(const float*, int, int, int, double, double*, hipStream_t);
@@ -159,6 +190,19 @@ __global__ void __launch_bounds__(kBlock) adj_coupling(const AdjParams<T> p) {
     lds_barrier();
   };
   lane_row_dots<T, kRowsPerWave>(GT, r.ldg, z, lane, acc, stage);
+  if (p.dgt) {
+    // dJ/dG^T row c += (input c of step n) x (adjoint of the outputs), FP64
+    const int nc = r.q + r.np;
+    double* dg = p.dgt + p.dg_off[rb.a];
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) {
+      const int row = row0 + k;
+      if (row >= nc) break;
+      const double zin = (double)(row < r.q ? p.xn[r.x_off + row] : p.hz1[gi[row - r.q]]);
+      double* d = dg + (size_t)row * r.ldg;
+      for (int c = lane; c < nc; c += kWave) d[c] += zin * (double)z[c];
+    }
+  }
 #pragma unroll
   for (int k = 0; k < kRowsPerWave; ++k)
     for (int o = kWave / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, kWave);

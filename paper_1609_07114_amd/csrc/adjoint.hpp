@@ -57,6 +57,14 @@ struct AdjParams {
   T* lps_out[4];
   const T* pex1;
   const T* pey1;
+  // gradients through the models (dgt != nullptr): per region k an FP64
+  // accumulator of dJ/dG^T at dgt + dg_off[k] (row c = column c of eq.
+  // (23)'s G, ldg entries), summed over the steps as
+  // [x~^n; h^{n+1/2}]_c [x~^{n+1}; y^{n+1}]-adjoint; xn holds the forward
+  // reduced states x~^n at each region's x_off
+  double* dgt;
+  const int64_t* dg_off;
+  const T* xn;
 };
 
 template <typename T>
@@ -84,5 +92,18 @@ hipError_t launch_probe_energy(const T* buf, int nprobes, int probe, int n, doub
                                hipStream_t s);
 // Zero `bytes` bytes at p (both multiples of 16).
 hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s);
+
+// Forward reduced states kept per step while a segment is recomputed: the
+// image of step k holds every region's x~ at its x_off (the parity-0 place
+// of the handle's layout).  The recompute's model tables are the handle's
+// with xstride = +img (even steps: read image k at rp.xs = image k, write
+// image k+1) or -img (odd steps: rp.xs = image k+1), so the step kernel's
+// parity addressing lands on consecutive images.
+// out[k] = in[k] with xstride replaced, k < nroms.
+hipError_t launch_rom_xstride(RomDev* out, const RomDev* in, int nroms, int64_t xstride, hipStream_t s);
+// dst[x_off + a] = src[x_off + par * xstride + a] for every region (a < q):
+// a checkpoint's states into the parity-0 places of an image.
+template <typename T>
+hipError_t launch_states_to_image(const T* src, T* dst, const RomDev* roms, int nroms, int par, hipStream_t s);
 
 }  // namespace fdtd

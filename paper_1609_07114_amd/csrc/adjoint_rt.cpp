@@ -37,10 +37,24 @@ struct AdjLayout {
   int K = 0, nck = 0;
   size_t set_bytes = 0, xs_bytes = 0;
   size_t slot_bytes = 0, lam_bytes = 0, ck_psi = 0;  // per slot / adjoint set; checkpoint's psi offset
-  size_t off_ctrl = 0, off_ckpt = 0, ck_stride = 0, off_slots = 0, off_xs = 0, off_psih = 0;
-  size_t off_lam = 0, off_lx = 0, off_g = 0, off_gseg = 0, off_gt = 0, off_roms = 0, off_j = 0, total = 0;
+  size_t off_ctrl = 0, off_ckpt = 0, ck_stride = 0, off_slots = 0, off_xrec = 0, off_psih = 0;
+  size_t off_lam = 0, off_lx = 0, off_g = 0, off_gseg = 0, off_gt = 0, off_roms = 0, off_j = 0;
+  size_t off_rtab = 0, off_dgoff = 0, off_dg = 0, total = 0;
   size_t gt_elems = 0;
+  size_t img = 0;        // elements per image of reduced states (one per step of a segment)
+  bool models = false;   // gradients through the models: dJ/dG accumulators
+  size_t dg_elems = 0;
 };
+
+// Element offset of region k's dJ/dG^T accumulator (ldg x ldg, regions in order).
+size_t region_dg(const fdtd_rom_sim* s, int k) {
+  size_t o = 0;
+  for (int a = 0; a < k; ++a) {
+    const size_t ldg = align_up((size_t)s->roms[a].q + s->roms[a].np, kWave);
+    o += ldg * ldg;
+  }
+  return o;
+}
 
 // Element offset of matrix slot sl's G^T block (ldg x ldg, slots in order).
 size_t slot_gt(const fdtd_rom_sim* s, size_t sl) {
@@ -53,7 +67,7 @@ size_t slot_gt(const fdtd_rom_sim* s, size_t sl) {
   return ge;
 }
 
-int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A) {
+int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A, bool models = false) {
   if (nsteps < 1 || nsteps > s->max_steps)
     return fail(FDTD_EINVAL, "nsteps=%d outside [1, max_steps=%d]", nsteps, s->max_steps);
   if (ckpt_every < 0 || ckpt_every > nsteps)
@@ -77,8 +91,10 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
   o += (size_t)A.nck * A.ck_stride;
   A.off_slots = o;
   o = align_up(o + (size_t)A.K * A.slot_bytes, 256);
-  A.off_xs = o;
-  o += A.xs_bytes;
+  // reduced states of every step of a segment: K + 1 images (256-B aligned)
+  A.img = align_up(std::max<size_t>(L.xs_elems, 1), 64);
+  A.off_xrec = o;
+  o = align_up(o + (size_t)(A.K + 1) * A.img * ts, 256);
   A.off_psih = o;
   o = align_up(o + (L.pml ? 4 * fb : 0), 256);
   A.off_lam = o;
@@ -95,6 +111,14 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
   o = align_up(o + (size_t)std::max(s->nroms, 1) * sizeof(RomDev), 256);
   A.off_j = o;  // the objective, when summed on the device
   o = align_up(o + sizeof(double), 256);
+  A.off_rtab = o;  // the recompute's two model tables (xstride +img, -img)
+  o = align_up(o + 2 * (size_t)std::max(s->nroms, 1) * sizeof(RomDev), 256);
+  A.models = models;
+  A.dg_elems = models ? region_dg(s, s->nroms) : 0;
+  A.off_dgoff = o;  // models: per region the offset of its dJ/dG^T accumulator
+  o = align_up(o + (models ? (size_t)std::max(s->nroms, 1) * sizeof(int64_t) : 0), 256);
+  A.off_dg = o;
+  o = align_up(o + A.dg_elems * sizeof(double), 256);
   A.total = o;
   // every part in order, disjoint, inside the total: the checkpoints (each
   // a field set, the reduced states and, with layers, four auxiliary
@@ -104,7 +128,7 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
       {A.off_ctrl, kCtrlInts * sizeof(int)},
       {A.off_ckpt, (size_t)A.nck * A.ck_stride},
       {A.off_slots, (size_t)A.K * A.slot_bytes},
-      {A.off_xs, A.xs_bytes},
+      {A.off_xrec, (size_t)(A.K + 1) * A.img * ts},
       {A.off_psih, L.pml ? 4 * fb : 0},
       {A.off_lam, 2 * A.lam_bytes},
       {A.off_lx, 2 * A.xs_bytes},
@@ -112,7 +136,10 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
       {A.off_gseg, ts == 4 ? 2 * L.field_elems * ts : 0},
       {A.off_gt, A.gt_elems * ts},
       {A.off_roms, (size_t)std::max(s->nroms, 1) * sizeof(RomDev)},
-      {A.off_j, sizeof(double)}};
+      {A.off_j, sizeof(double)},
+      {A.off_rtab, 2 * (size_t)std::max(s->nroms, 1) * sizeof(RomDev)},
+      {A.off_dgoff, models ? (size_t)std::max(s->nroms, 1) * sizeof(int64_t) : 0},
+      {A.off_dg, A.dg_elems * sizeof(double)}};
   size_t end = 0;
   for (const auto& pt : parts) {
     if (pt[0] < end || pt[0] % 256 != 0) return fail(FDTD_EINVAL, "internal: adjoint workspace parts overlap");
@@ -133,16 +160,23 @@ bool inside_span(const void* p, size_t bytes, const void* base, size_t total) {
 
 // Every pointer and extent a recompute launch writes lies in the adjoint
 // workspace: the output field set (three field arrays), the private step
-// counter and the reduced-state scratch; its input set lies in the
-// workspace too (a checkpoint or an earlier slot).
+// counter, the two images of reduced states it reads and writes (xs +
+// x_off + par * xstride with xstride = +img or -img) and its model table;
+// its input set lies in the workspace too (a checkpoint or an earlier slot).
 template <typename T>
-int check_recompute(const StepParams<T>& rp, int par, const char* aw, const AdjLayout& A, size_t fe) {
+int check_recompute(const StepParams<T>& rp, int par, const char* aw, const AdjLayout& A, size_t fe, int nroms) {
   const size_t fb = fe * sizeof(T);
   for (int f = 0; f < 3; ++f)
     if (!inside_span(rp.f[par][f], fb, aw, A.total) || !inside_span(rp.f[par ^ 1][f], fb, aw, A.total))
       return fail(FDTD_EINVAL, "internal: recompute field %d outside the adjoint workspace", f);
-  if (!inside_span(rp.ctrl, kCtrlInts * sizeof(int), aw, A.total) || !inside_span(rp.xs, A.xs_bytes, aw, A.total))
-    return fail(FDTD_EINVAL, "internal: recompute control or state scratch outside the adjoint workspace");
+  const char* xlo = (const char*)rp.xs - (par ? A.img * sizeof(T) : 0);
+  const char* rec = aw + A.off_xrec;
+  if (!inside_span(rp.ctrl, kCtrlInts * sizeof(int), aw, A.total) ||
+      !inside_span(xlo, 2 * A.img * sizeof(T), rec, (size_t)(A.K + 1) * A.img * sizeof(T)))
+    return fail(FDTD_EINVAL, "internal: recompute control or reduced-state images outside the adjoint workspace");
+  if (nroms > 0 && !inside_span(rp.roms, (size_t)nroms * sizeof(RomDev), aw + A.off_rtab,
+                                2 * (size_t)nroms * sizeof(RomDev)))
+    return fail(FDTD_EINVAL, "internal: recompute model table outside the adjoint workspace");
   if (rp.nprobes != 0) return fail(FDTD_EINVAL, "internal: recompute records probes");
   return FDTD_OK;
 }
@@ -154,9 +188,97 @@ int check_recompute(const StepParams<T>& rp, int par, const char* aw, const AdjL
 // (run_direct_any), the objective is summed on the device, scratch is
 // cleared by a fill kernel and the gradients are copied straight into the
 // caller's arrays.
+// Host outputs of the gradients through the models: per region dJ/dR~,
+// dJ/dF~ (q x q) and dJ/dL~ (q x np), row-major; null entries are skipped.
+struct ModelOut {
+  double* const* rt;
+  double* const* ft;
+  double* const* lt;
+};
+
+// Reverse-mode step through the closed form of eq. (23) for one region:
+// from dJ/dG (gG, nc x nc row-major, nc = q + np) to dJ/dR~, dJ/dF~,
+// dJ/dL~ and to the port half cells C+, C- of eq. (13).  With
+// M = R~ + F~ + L~ C+ L~^T, N = R~ - F~ + L~ C- L~^T, A~ = M^{-1} N,
+// B~' = M^{-1} L~ Sc, C~ = L~^T and G = [[A~, B~'], [C~A~, C~B~']]:
+//   dA~ = gG_xx + C~^T gG_yx,  dB~' = gG_xu + C~^T gG_yu,
+//   dC~ = gG_yx A~^T + gG_yu B~'^T,  [W_A | W_B] = M^{-T} [dA~ | dB~'],
+//   dN = W_A,  dM = -(W_A A~^T + W_B B~'^T),  dR~ = dM + dN,  dF~ = dM - dN,
+//   dL~ = (dM + dM^T) L~ C+ + (dN + dN^T) L~ C- + W_B Sc + dC~^T,
+//   dC+_k = l_k^T dM l_k,  dC-_k = l_k^T dN l_k  (l_k column k of L~).
+bool model_vjp(const RomHost& h, const std::vector<double>& gG, std::vector<double>& gR, std::vector<double>& gF,
+               std::vector<double>& gL, std::vector<double>& gcp, std::vector<double>& gcm) {
+  const int q = h.q, np = h.np, nc = q + np;
+  auto G = [&](int r, int c) { return gG[(size_t)r * nc + c]; };
+  auto Lt = [&](int a, int k) { return h.C[(size_t)k * q + a]; };
+  // W = [dA~ | dB~'] (q x nc), then M^{-T} W
+  std::vector<double> W((size_t)q * nc), gC((size_t)np * q, 0.0);
+  for (int a = 0; a < q; ++a)
+    for (int c = 0; c < nc; ++c) {
+      double v = G(a, c);
+      for (int k = 0; k < np; ++k) v += Lt(a, k) * G(q + k, c);
+      W[(size_t)a * nc + c] = v;
+    }
+  for (int k = 0; k < np; ++k)
+    for (int a = 0; a < q; ++a) {
+      double v = 0;
+      for (int b = 0; b < q; ++b) v += G(q + k, b) * h.A[(size_t)a * q + b];
+      for (int c = 0; c < np; ++c) v += G(q + k, q + c) * h.B[(size_t)a * np + c];
+      gC[(size_t)k * q + a] = v;
+    }
+  std::vector<double> MT((size_t)q * q);
+  for (int a = 0; a < q; ++a)
+    for (int b = 0; b < q; ++b) {
+      double v = h.R[(size_t)a * q + b] + h.F[(size_t)a * q + b];
+      for (int k = 0; k < np; ++k) v += Lt(a, k) * h.cp[k] * Lt(b, k);
+      MT[(size_t)b * q + a] = v;
+    }
+  std::vector<int> piv;
+  if (!la::lu_factor(q, MT.data(), piv)) return false;
+  la::lu_solve(q, MT.data(), piv, W.data(), nc);
+  std::vector<double> gM((size_t)q * q), gN((size_t)q * q);
+  for (int a = 0; a < q; ++a)
+    for (int b = 0; b < q; ++b) {
+      double v = 0;
+      for (int c = 0; c < q; ++c) v += W[(size_t)a * nc + c] * h.A[(size_t)b * q + c];
+      for (int c = 0; c < np; ++c) v += W[(size_t)a * nc + q + c] * h.B[(size_t)b * np + c];
+      gM[(size_t)a * q + b] = -v;
+      gN[(size_t)a * q + b] = W[(size_t)a * nc + b];
+    }
+  gR.resize((size_t)q * q);
+  gF.resize((size_t)q * q);
+  for (size_t e = 0; e < gR.size(); ++e) {
+    gR[e] = gM[e] + gN[e];
+    gF[e] = gM[e] - gN[e];
+  }
+  gL.assign((size_t)q * np, 0.0);
+  gcp.assign(np, 0.0);
+  gcm.assign(np, 0.0);
+  for (int k = 0; k < np; ++k) {
+    std::vector<double> mp(q, 0.0), mn(q, 0.0);  // (dM + dM^T) l_k, (dN + dN^T) l_k
+    for (int a = 0; a < q; ++a)
+      for (int b = 0; b < q; ++b) {
+        const double l = Lt(b, k);
+        if (l == 0.0) continue;
+        mp[a] += (gM[(size_t)a * q + b] + gM[(size_t)b * q + a]) * l;
+        mn[a] += (gN[(size_t)a * q + b] + gN[(size_t)b * q + a]) * l;
+      }
+    double sp = 0, sm = 0;
+    for (int a = 0; a < q; ++a) {
+      gL[(size_t)a * np + k] = mp[a] * h.cp[k] + mn[a] * h.cm[k] + W[(size_t)a * nc + q + k] * h.sc[k] +
+                               gC[(size_t)k * q + a];
+      sp += Lt(a, k) * mp[a];
+      sm += Lt(a, k) * mn[a];
+    }
+    gcp[k] = 0.5 * sp;  // l^T dM l = l^T (dM + dM^T) l / 2
+    gcm[k] = 0.5 * sm;
+  }
+  return true;
+}
+
 template <typename T>
 int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A, double* J,
-                 double* grad_eps, double* grad_sig, bool noalloc) {
+                 double* grad_eps, double* grad_sig, bool noalloc, const ModelOut* mo = nullptr) {
   const Layout& L = s->L;
   hipStream_t st = s->stream;
   const size_t fe = L.field_elems;
@@ -228,14 +350,30 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
     if (hipMemsetAsync(aw + A.off_ctrl, 0, kCtrlInts * sizeof(int), st) != hipSuccess ||
         hipMemsetAsync(aw + A.off_slots, 0, A.off_gt - A.off_slots, st) != hipSuccess)
       return dev_err("hipMemsetAsync");
+    if (A.models && s->nroms > 0) {
+      std::vector<int64_t> dgo(s->nroms);
+      for (int k = 0; k < s->nroms; ++k) dgo[k] = (int64_t)region_dg(s, k);
+      if (hipMemsetAsync(aw + A.off_dg, 0, A.dg_elems * sizeof(double), st) != hipSuccess ||
+          hipMemcpyAsync(aw + A.off_dgoff, dgo.data(), dgo.size() * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return dev_err("model gradient set-up");
+    }
   }
+  // the recompute's model tables: the handle's, with xstride = +img, -img
+  const RomDev* hroms = (const RomDev*)(ws + L.off_roms);
+  RomDev* rtab = (RomDev*)(aw + A.off_rtab);
+  if (launch_rom_xstride(rtab, hroms, s->nroms, (int64_t)A.img, st) != hipSuccess ||
+      launch_rom_xstride(rtab + s->nroms, hroms, s->nroms, -(int64_t)A.img, st) != hipSuccess)
+    return dev_err("recompute model tables");
 
   auto ckpt = [&](int c) { return aw + A.off_ckpt + (size_t)c * A.ck_stride; };
   auto ckpt_xs = [&](int c) { return ckpt(c) + align_up(A.set_bytes, 256); };
   // checkpoint's auxiliary fields: [psi at Hz (2), psi at Ex, psi at Ey]
   auto ckpt_psi = [&](int c) { return (T*)(ckpt(c) + A.ck_psi); };
   auto slot = [&](int k) { return aw + A.off_slots + (size_t)k * A.slot_bytes; };
-  T* xs_scr = (T*)(aw + A.off_xs);
+  // reduced states x~^{m0+k} of the segment being swept, k = 0..K
+  auto image = [&](int k) { return (T*)(aw + A.off_xrec) + (size_t)k * A.img; };
   T* psih = (T*)(aw + A.off_psih);  // recompute's psi at Hz, [parity][2]
   const size_t xs_copy = L.xs_elems * sizeof(T);
   const size_t fb = fe * sizeof(T);
@@ -276,7 +414,6 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   StepParams<T> rp = step_params<T>(s);
   rp.ctrl = (int*)(aw + A.off_ctrl);
   rp.nprobes = 0;
-  rp.xs = xs_scr;
   AdjParams<T> ap{};
   ap.al = sp.al;
   ap.be = sp.be;
@@ -307,6 +444,8 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   ap.mats = (const T*)(aw + A.off_gt);
   ap.idx = (const int*)(ws + L.off_idx);
   ap.pml = L.pml ? 1 : 0;
+  ap.dgt = A.models && s->nroms > 0 ? (double*)(aw + A.off_dg) : nullptr;
+  ap.dg_off = (const int64_t*)(aw + A.off_dgoff);
   ap.pml_xlo = sp.pml_xlo;
   ap.pml_xhi = sp.pml_xhi;
   ap.pml_ylo = sp.pml_ylo;
@@ -325,7 +464,7 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
     auto state = [&](int k) -> T* { return (T*)(k == 0 ? ckpt(c) : slot(k - 1)); };
     // psi at Ex then at Ey of state m0 + k (contiguous)
     auto psi_e = [&](int k) -> T* { return k == 0 ? ckpt_psi(c) + 2 * fe : state(k) + 3 * fe; };
-    if (xs_copy > 0 && hipMemcpyAsync(xs_scr, ckpt_xs(c), xs_copy, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    if (launch_states_to_image<T>((const T*)ckpt_xs(c), image(0), hroms, s->nroms, m0 & 1, st) != hipSuccess)
       return dev_err("state restore");
     if (L.pml && hipMemcpyAsync(psih + (size_t)(m0 & 1) * 2 * fe, ckpt_psi(c), 2 * fb, hipMemcpyDeviceToDevice,
                                 st) != hipSuccess)
@@ -352,7 +491,9 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
         rp.psi_ey = psi_e(k + 1) + fe;
       }
       rp.step_off = m;
-      if (const int rc = check_recompute<T>(rp, par, aw, A, fe); rc != FDTD_OK) return rc;
+      rp.roms = par ? rtab + s->nroms : rtab;
+      rp.xs = par ? image(k + 1) : image(k);
+      if (const int rc = check_recompute<T>(rp, par, aw, A, fe, s->nroms); rc != FDTD_OK) return rc;
       if (launch_step<T>(rp, s->seg, s->smem, st) != hipSuccess) return dev_err("recompute launch");
     }
     for (int k = len - 1; k >= 0; --k) {
@@ -367,6 +508,7 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
       ap.lx_in = lx[cur];
       ap.lx_out = lx[cur ^ 1];
       ap.hz1 = state(k + 1);
+      ap.xn = image(k);
       ap.ex0 = state(k) + fe;
       ap.ey0 = state(k) + 2 * fe;
       if (L.pml) {
@@ -410,10 +552,47 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   }
   for (size_t c = 0; c < s->pec.size(); ++c)
     if (s->pec[c]) grad_eps[c] = grad_sig[c] = 0.0;  // metal: no material gradient
+  // regions (and, with the models held, their rings) report zero
+  const int ring = A.models ? 0 : 1;
   for (const RomHost& h : s->roms)
-    for (int j = std::max(h.j0 - 1, 0); j < std::min(h.j0 + h.nj + 1, ny); ++j)
-      for (int i = std::max(h.i0 - 1, 0); i < std::min(h.i0 + h.ni + 1, nx); ++i)
+    for (int j = std::max(h.j0 - ring, 0); j < std::min(h.j0 + h.nj + ring, ny); ++j)
+      for (int i = std::max(h.i0 - ring, 0); i < std::min(h.i0 + h.ni + ring, nx); ++i)
         grad_eps[(size_t)j * nx + i] = grad_sig[(size_t)j * nx + i] = 0.0;
+  if (A.models && s->nroms > 0) {
+    // dJ/dG^T per region -> dJ/dG -> the closed form's inputs; the port half
+    // cells' share goes to the ring cells: C+- = Dl Dl' (eps0 eps_r/dt +- sigma/2)
+    std::vector<double> dgt(A.dg_elems);
+    if (hipMemcpyAsync(dgt.data(), aw + A.off_dg, A.dg_elems * sizeof(double), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return dev_err("model gradient read");
+    for (int k = 0; k < s->nroms; ++k) {
+      const RomHost& h = s->roms[k];
+      const int q = h.q, np = h.np, nc = q + np;
+      const size_t ldg = align_up((size_t)nc, kWave);
+      const double* d = dgt.data() + region_dg(s, k);
+      std::vector<double> gG((size_t)nc * nc), gR, gF, gL, gcp, gcm;
+      for (int r = 0; r < nc; ++r)
+        for (int c = 0; c < nc; ++c) gG[(size_t)r * nc + c] = d[(size_t)c * ldg + r];
+      if (!model_vjp(h, gG, gR, gF, gL, gcp, gcm))
+        return fail(FDTD_ENOTPASSIVE, "region %d: eq. (23) matrix M is singular", k);
+      for (int c = 0; c < np; ++c) {
+        int oi, oj;
+        double dl, dlh;
+        if (c < h.ni) { oi = h.i0 + c; oj = h.j0 - 1; dl = s->dx; dlh = s->dy / 2; }
+        else if (c < 2 * h.ni) { oi = h.i0 + c - h.ni; oj = h.j0 + h.nj; dl = s->dx; dlh = s->dy / 2; }
+        else if (c < 2 * h.ni + h.nj) { oi = h.i0 - 1; oj = h.j0 + c - 2 * h.ni; dl = s->dy; dlh = s->dx / 2; }
+        else { oi = h.i0 + h.ni; oj = h.j0 + c - 2 * h.ni - h.nj; dl = s->dy; dlh = s->dx / 2; }
+        const size_t ci = (size_t)oj * nx + oi;
+        if (!s->pec.empty() && s->pec[ci]) continue;
+        grad_eps[ci] += dl * dlh * kEps0 / s->dt * (gcp[c] + gcm[c]);
+        grad_sig[ci] += dl * dlh * 0.5 * (gcp[c] - gcm[c]);
+      }
+      if (mo->rt && mo->rt[k]) std::copy(gR.begin(), gR.end(), mo->rt[k]);
+      if (mo->ft && mo->ft[k]) std::copy(gF.begin(), gF.end(), mo->ft[k]);
+      if (mo->lt && mo->lt[k]) std::copy(gL.begin(), gL.end(), mo->lt[k]);
+    }
+  }
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const size_t c = (size_t)j * nx + i;
@@ -458,6 +637,45 @@ int fdtd_rom_adjoint(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int3
     char* aw = (char*)dev_adj_ws;
     return sim->dtype == FDTD_F32 ? adjoint_impl<float>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma, false)
                                   : adjoint_impl<double>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma, false);
+  } catch (const std::bad_alloc&) {
+    return fail(FDTD_ENOMEM, "host allocation failed");
+  }
+}
+
+int fdtd_rom_adjoint_models_workspace_size(const fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every,
+                                           size_t* bytes) {
+  if (!sim || !bytes) return fail(FDTD_EINVAL, "null argument");
+  try {
+    AdjLayout A;
+    const int rc = plan_adjoint(sim, nsteps, ckpt_every, A, true);
+    if (rc != FDTD_OK) return rc;
+    *bytes = A.total;
+    return FDTD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(FDTD_ENOMEM, "host allocation failed");
+  }
+}
+
+int fdtd_rom_adjoint_models(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_every, int32_t probe,
+                            void* dev_adj_ws, size_t ws_bytes, double* J, double* grad_eps_r,
+                            double* grad_sigma, double* const* grad_Rt, double* const* grad_Ft,
+                            double* const* grad_Lt) {
+  if (!sim || !J || !grad_eps_r || !grad_sigma) return fail(FDTD_EINVAL, "null argument");
+  if (sim->steps != 0) return fail(FDTD_ESTATE, "the adjoint starts from the initial state (%d steps taken)", sim->steps);
+  if (probe < 0 || probe >= sim->nprobes) return fail(FDTD_EINVAL, "probe %d out of range", probe);
+  if (sim->probes[probe].comp != FDTD_HZ) return fail(FDTD_EINVAL, "probe %d is not an Hz probe", probe);
+  try {
+    AdjLayout A;
+    int rc = plan_adjoint(sim, nsteps, ckpt_every, A, true);
+    if (rc != FDTD_OK) return rc;
+    if (!dev_adj_ws) return fail(FDTD_EINVAL, "null adjoint workspace");
+    if (((uintptr_t)dev_adj_ws) % 256) return fail(FDTD_EINVAL, "adjoint workspace must be 256-byte aligned");
+    if (ws_bytes < A.total) return fail(FDTD_ENOMEM, "adjoint workspace has %zu bytes, %zu needed", ws_bytes, A.total);
+    char* aw = (char*)dev_adj_ws;
+    const ModelOut mo{grad_Rt, grad_Ft, grad_Lt};
+    return sim->dtype == FDTD_F32
+               ? adjoint_impl<float>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma, false, &mo)
+               : adjoint_impl<double>(sim, nsteps, probe, aw, A, J, grad_eps_r, grad_sigma, false, &mo);
   } catch (const std::bad_alloc&) {
     return fail(FDTD_ENOMEM, "host allocation failed");
   }

@@ -70,6 +70,9 @@ struct FineModel {
   int nEx, nEy, nE, nH, n;
   double dx, dy, dxh, dyh, dt;
   std::vector<double> De, Ds, Sc;  // E diagonals, port scale
+  // per E coordinate the fine cells whose half cells make it up:
+  // De = sum w eps0 eps_r(cell), Ds = sum w sigma(cell)
+  std::vector<std::vector<std::pair<int, double>>> ecells;
   double Dm;
   Csr K, KT;                       // E x H and its transpose
   std::vector<int> port_row;       // E index of each port
@@ -131,22 +134,26 @@ bool assemble(FineModel& m, int ni, int nj, int r, double dx, double dy, double 
   auto S = [&](int i, int j) { return sg[(size_t)j * Nx + i]; };
   auto H = [&](int i, int j) { return hid[(size_t)j * Nx + i]; };
   std::vector<std::vector<std::pair<int, double>>> rows;
-  auto add_e = [&](double de, double ds, std::vector<std::pair<int, double>> k) {
+  m.ecells.clear();
+  auto cell = [&](int i, int j) { return j * Nx + i; };
+  auto add_e = [&](double de, double ds, std::vector<std::pair<int, double>> k,
+                   std::vector<std::pair<int, double>> cells) {
     m.De.push_back(de);
     m.Ds.push_back(ds);
     rows.push_back(std::move(k));
+    m.ecells.push_back(std::move(cells));
   };
   for (int j = 1; j < Ny; ++j)
     for (int i = 0; i < Nx; ++i)
       if (!pin_x(i, j))
         add_e(A * kEps0 * 0.5 * (E(i, j - 1) + E(i, j)), A * 0.5 * (S(i, j - 1) + S(i, j)),
-              {{H(i, j), +m.dxh}, {H(i, j - 1), -m.dxh}});
+              {{H(i, j), +m.dxh}, {H(i, j - 1), -m.dxh}}, {{cell(i, j - 1), 0.5 * A}, {cell(i, j), 0.5 * A}});
   m.nEx = (int)rows.size();
   for (int j = 0; j < Ny; ++j)
     for (int i = 1; i < Nx; ++i)
       if (!pin_y(i, j))
         add_e(A * kEps0 * 0.5 * (E(i - 1, j) + E(i, j)), A * 0.5 * (S(i - 1, j) + S(i, j)),
-              {{H(i, j), -m.dyh}, {H(i - 1, j), +m.dyh}});
+              {{H(i, j), -m.dyh}, {H(i - 1, j), +m.dyh}}, {{cell(i - 1, j), 0.5 * A}, {cell(i, j), 0.5 * A}});
   m.nEy = (int)rows.size() - m.nEx;
   m.Sc.assign(m.np, 0.0);
   m.port_row.assign(m.np, -1);
@@ -162,32 +169,36 @@ bool assemble(FineModel& m, int ni, int nj, int r, double dx, double dy, double 
     if (!live[c]) continue;
     // boundary half cells of eq. (4), summed over the r fine edges
     double de = 0, ds = 0;
-    std::vector<std::pair<int, double>> k;
+    std::vector<std::pair<int, double>> k, cells;
     for (int t = 0; t < r; ++t) {
       if (c < ni) {
         const int i = c * r + t;
         de += m.dxh * (m.dyh / 2) * kEps0 * E(i, 0);
         ds += m.dxh * (m.dyh / 2) * S(i, 0);
         k.push_back({H(i, 0), +m.dxh});
+        cells.push_back({cell(i, 0), m.dxh * (m.dyh / 2)});
       } else if (c < 2 * ni) {
         const int i = (c - ni) * r + t;
         de += m.dxh * (m.dyh / 2) * kEps0 * E(i, Ny - 1);
         ds += m.dxh * (m.dyh / 2) * S(i, Ny - 1);
         k.push_back({H(i, Ny - 1), -m.dxh});
+        cells.push_back({cell(i, Ny - 1), m.dxh * (m.dyh / 2)});
       } else if (c < 2 * ni + nj) {
         const int j = (c - 2 * ni) * r + t;
         de += m.dyh * (m.dxh / 2) * kEps0 * E(0, j);
         ds += m.dyh * (m.dxh / 2) * S(0, j);
         k.push_back({H(0, j), -m.dyh});
+        cells.push_back({cell(0, j), m.dyh * (m.dxh / 2)});
       } else {
         const int j = (c - 2 * ni - nj) * r + t;
         de += m.dyh * (m.dxh / 2) * kEps0 * E(Nx - 1, j);
         ds += m.dyh * (m.dxh / 2) * S(Nx - 1, j);
         k.push_back({H(Nx - 1, j), +m.dyh});
+        cells.push_back({cell(Nx - 1, j), m.dyh * (m.dxh / 2)});
       }
     }
     m.port_row[c] = (int)rows.size();
-    add_e(de, ds, std::move(k));
+    add_e(de, ds, std::move(k), std::move(cells));
   }
   m.nE = (int)rows.size();
   m.n = m.nE + m.nH;
@@ -456,12 +467,27 @@ Cols gs_part(const Cols& dirs, int r0, int len, int q) {
   return out;
 }
 
+// What the gradient through the builder needs of a build.
+struct BuildState {
+  FineModel fm;
+  Cols V1;                 // E basis (empty: identity)
+  std::vector<double> K0;  // K~ before the clip, q1 x q2
+  int q1 = 0, q2 = 0;
+  bool clipped = false;
+  double lim = 0;
+};
+
+int build_impl(const fdtd_rom_build_params* prm, double* Rt, double* Ft, double* Lt, fdtd_rom_build_info* info,
+               BuildState* bs);
+
 }  // namespace
 
 using fdtd::fail;
 
-extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, double* Ft, double* Lt,
-                              fdtd_rom_build_info* info) {
+namespace {
+
+int build_impl(const fdtd_rom_build_params* prm, double* Rt, double* Ft, double* Lt, fdtd_rom_build_info* info,
+               BuildState* bs) {
   if (!prm) return fail(FDTD_EINVAL, "null argument");
   const bool query = !Rt && !Ft && !Lt;
   if (query ? !info : (!Rt || !Ft || !Lt)) return fail(FDTD_EINVAL, "null argument");
@@ -564,6 +590,7 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
             R[(size_t)(q1 + a) * q + q1 + b2] = R[(size_t)(q1 + b2) * q + q1 + a] = fm.Dm / P.dt * GH[(size_t)a * q2 + b2];
       }
     }
+    if (bs) bs->K0 = Kt;
     // eq. (27): singular values s_k of R11^{-1/2} K~ R22^{-1/2} against 2/dt.
     // With Cholesky factors R11 = L1 L1^T, R22 = L2 L2^T the matrix
     // M = L1^{-1} K~ L2^{-T} is orthogonally equivalent to it (R^{1/2} =
@@ -696,6 +723,217 @@ extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, doub
       info->smax_after = smax_after;
       info->clipped = clipped;
       info->n_fine_states = fm.n;
+    }
+    if (bs) {
+      bs->q1 = q1;
+      bs->q2 = q2;
+      bs->clipped = clipped != 0;
+      bs->lim = lim;
+      bs->V1 = std::move(V1);
+      bs->fm = std::move(fm);
+    }
+    return FDTD_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(FDTD_ENOMEM, "host allocation failed");
+  }
+}
+
+}  // namespace
+
+extern "C" int fdtd_rom_build(const fdtd_rom_build_params* prm, double* Rt, double* Ft, double* Lt,
+                              fdtd_rom_build_info* info) {
+  return build_impl(prm, Rt, Ft, Lt, info, nullptr);
+}
+
+namespace {
+
+using Mat = std::vector<double>;  // dense, row-major
+
+Mat mul(const Mat& A, const Mat& B, int m, int k, int n) {  // (m x k)(k x n)
+  Mat C((size_t)m * n);
+  fdtd::la::gemm(m, n, k, A.data(), B.data(), C.data());
+  return C;
+}
+
+Mat tr(const Mat& A, int m, int n) {  // (m x n)^T
+  Mat T((size_t)n * m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) T[(size_t)j * m + i] = A[(size_t)i * n + j];
+  return T;
+}
+
+// Symmetric eigen-decomposition S = Z diag(w) Z^T (Z columns).  Diagonal
+// matrices skip the iteration.
+bool eig(int n, const Mat& S, Mat& Z, std::vector<double>& w) {
+  bool diag = true;
+  for (int i = 0; i < n && diag; ++i)
+    for (int j = 0; j < n && diag; ++j) diag = i == j || S[(size_t)i * n + j] == 0.0;
+  Z.assign((size_t)n * n, 0.0);
+  w.resize(n);
+  if (diag) {
+    for (int i = 0; i < n; ++i) {
+      Z[(size_t)i * n + i] = 1.0;
+      w[i] = S[(size_t)i * n + i];
+    }
+    return true;
+  }
+  Mat A(S);
+  return fdtd::la::sym_eig(n, A.data(), Z.data(), w.data());
+}
+
+// Z f(w) Z^T
+Mat spectral(const Mat& Z, const std::vector<double>& f, int n) {
+  Mat T((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) T[(size_t)i * n + j] = Z[(size_t)i * n + j] * f[j];
+  return mul(T, tr(Z, n, n), n, n, n);
+}
+
+// Daleckii-Krein pull-back of a symmetric matrix function:
+// S_bar = Z (D o (Z^T sym(X) Z)) Z^T
+Mat dk_pullback(const Mat& Z, const Mat& D, const Mat& X, int n) {
+  Mat Xs((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Xs[(size_t)i * n + j] = 0.5 * (X[(size_t)i * n + j] + X[(size_t)j * n + i]);
+  const Mat Zt = tr(Z, n, n);
+  Mat T = mul(mul(Zt, Xs, n, n, n), Z, n, n, n);
+  for (size_t e = 0; e < T.size(); ++e) T[e] *= D[e];
+  return mul(mul(Z, T, n, n, n), Zt, n, n, n);
+}
+
+// dJ/dR11 of the eq. (27) clip K~_c = R11^{1/2} M g(M^T M) R22^{1/2},
+// M = R11^{-1/2} K R22^{-1/2}, g(mu) = min(1, lim/sqrt(mu)), given dJ/dK~_c
+// (R22 and K held).  Difference quotients on the spectra:
+//   sqrt: 1/(a+b) (a, b the square roots of two eigenvalues),
+//   1/sqrt: -1/(ab(a+b)),
+//   g: 0 between two unclipped values, -lim/(ab(a+b)) between two clipped
+//      ones, (g_i - g_j)/(mu_i - mu_j) across the bound.
+bool clip_vjp(const Mat& R11, const Mat& R22, const Mat& K, int q1, int q2, double lim, const Mat& gK, Mat& gR11) {
+  Mat Y, Zr, U;
+  std::vector<double> nu, w, mu;
+  if (!eig(q1, R11, Y, nu) || !eig(q2, R22, Zr, w)) return false;
+  std::vector<double> rn(q1), irn(q1), rw(q2), irw(q2);
+  for (int i = 0; i < q1; ++i) {
+    if (!(nu[i] > 0)) return false;
+    rn[i] = std::sqrt(nu[i]);
+    irn[i] = 1.0 / rn[i];
+  }
+  for (int i = 0; i < q2; ++i) {
+    if (!(w[i] > 0)) return false;
+    rw[i] = std::sqrt(w[i]);
+    irw[i] = 1.0 / rw[i];
+  }
+  const Mat P = spectral(Y, rn, q1), Q = spectral(Y, irn, q1);
+  const Mat R22h = spectral(Zr, rw, q2), R22ih = spectral(Zr, irw, q2);
+  const Mat M = mul(mul(Q, K, q1, q1, q2), R22ih, q1, q2, q2);
+  const Mat Mt = tr(M, q1, q2);
+  if (!eig(q2, mul(Mt, M, q2, q1, q2), U, mu)) return false;
+  std::vector<double> sq(q2), g(q2);
+  std::vector<char> big(q2);
+  for (int i = 0; i < q2; ++i) {
+    mu[i] = std::max(mu[i], 0.0);
+    sq[i] = std::sqrt(mu[i]);
+    big[i] = sq[i] > lim;
+    g[i] = big[i] ? lim / sq[i] : 1.0;
+  }
+  Mat Dg((size_t)q2 * q2, 0.0), Dp((size_t)q1 * q1), Dq((size_t)q1 * q1);
+  for (int i = 0; i < q2; ++i)
+    for (int j = 0; j < q2; ++j) {
+      double v = 0;
+      if (big[i] && big[j]) v = -lim / (sq[i] * sq[j] * (sq[i] + sq[j]));
+      else if (big[i] != big[j] && mu[i] != mu[j]) v = (g[i] - g[j]) / (mu[i] - mu[j]);
+      Dg[(size_t)i * q2 + j] = v;
+    }
+  for (int i = 0; i < q1; ++i)
+    for (int j = 0; j < q1; ++j) {
+      Dp[(size_t)i * q1 + j] = 1.0 / (rn[i] + rn[j]);
+      Dq[(size_t)i * q1 + j] = -1.0 / (rn[i] * rn[j] * (rn[i] + rn[j]));
+    }
+  const Mat Gm = spectral(U, g, q2);
+  const Mat Phi = mul(M, Gm, q1, q2, q2);
+  const Mat gKR = mul(gK, R22h, q1, q2, q2);
+  const Mat gP = mul(gKR, tr(Phi, q1, q2), q1, q2, q1);
+  const Mat gPhi = mul(P, gKR, q1, q1, q2);
+  Mat gM = mul(gPhi, Gm, q1, q2, q2);
+  const Mat gS = dk_pullback(U, Dg, mul(Mt, gPhi, q2, q1, q2), q2);
+  Mat gS2((size_t)q2 * q2);
+  for (int i = 0; i < q2; ++i)
+    for (int j = 0; j < q2; ++j) gS2[(size_t)i * q2 + j] = gS[(size_t)i * q2 + j] + gS[(size_t)j * q2 + i];
+  const Mat MgS = mul(M, gS2, q1, q2, q2);
+  for (size_t e = 0; e < gM.size(); ++e) gM[e] += MgS[e];
+  const Mat gQ = mul(mul(gM, R22ih, q1, q2, q2), tr(K, q1, q2), q1, q2, q1);
+  const Mat a = dk_pullback(Y, Dp, gP, q1), b = dk_pullback(Y, Dq, gQ, q1);
+  gR11.resize((size_t)q1 * q1);
+  for (size_t e = 0; e < gR11.size(); ++e) gR11[e] = a[e] + b[e];
+  return true;
+}
+
+}  // namespace
+
+extern "C" int fdtd_rom_build_vjp(const fdtd_rom_build_params* prm, const double* grad_Rt, const double* grad_Ft,
+                                  double* grad_eps_r, double* grad_sigma) {
+  if (!prm || !grad_Rt || !grad_Ft || !grad_eps_r || !grad_sigma) return fail(FDTD_EINVAL, "null argument");
+  try {
+    fdtd_rom_build_info info{};
+    if (int rc = build_impl(prm, nullptr, nullptr, nullptr, &info, nullptr); rc != FDTD_OK) return rc;
+    const int q = info.q1 + info.q2;
+    const int np = 2 * (prm->ni + prm->nj);
+    Mat Rt((size_t)q * q), Ft((size_t)q * q), Lt((size_t)q * np);
+    BuildState bs;
+    if (int rc = build_impl(prm, Rt.data(), Ft.data(), Lt.data(), &info, &bs); rc != FDTD_OK) return rc;
+    const int q1 = bs.q1, q2 = bs.q2;
+    const double dt = prm->dt;
+    // the E block of dJ/dR~ (through the clip when it acted) and of dJ/dF~
+    Mat gR11((size_t)q1 * q1), gF11((size_t)q1 * q1);
+    for (int a = 0; a < q1; ++a)
+      for (int b = 0; b < q1; ++b) {
+        gR11[(size_t)a * q1 + b] = grad_Rt[(size_t)a * q + b];
+        gF11[(size_t)a * q1 + b] = grad_Ft[(size_t)a * q + b];
+      }
+    if (bs.clipped) {
+      // R~12 = -K~_c/2, R~21 = -K~_c^T/2, F~12 = -K~_c/2, F~21 = +K~_c^T/2
+      Mat gK((size_t)q1 * q2), R11((size_t)q1 * q1), R22((size_t)q2 * q2), g;
+      for (int a = 0; a < q1; ++a)
+        for (int c = 0; c < q2; ++c)
+          gK[(size_t)a * q2 + c] = -0.5 * grad_Rt[(size_t)a * q + q1 + c] - 0.5 * grad_Rt[(size_t)(q1 + c) * q + a] -
+                                   0.5 * grad_Ft[(size_t)a * q + q1 + c] + 0.5 * grad_Ft[(size_t)(q1 + c) * q + a];
+      for (int a = 0; a < q1; ++a)
+        for (int b = 0; b < q1; ++b) R11[(size_t)a * q1 + b] = dt * Rt[(size_t)a * q + b];
+      for (int a = 0; a < q2; ++a)
+        for (int b = 0; b < q2; ++b) R22[(size_t)a * q2 + b] = dt * Rt[(size_t)(q1 + a) * q + q1 + b];
+      if (!clip_vjp(R11, R22, bs.K0, q1, q2, bs.lim, gK, g))
+        return fail(FDTD_EINVAL, "eigen-decomposition for the clip's gradient did not converge");
+      for (size_t e = 0; e < gR11.size(); ++e) gR11[e] += dt * g[e];
+    }
+    // congruence: per E coordinate e, dJ/dDe = (V1 gR11 V1^T)_ee / dt,
+    // dJ/dDs = (V1 gF11 V1^T)_ee / 2 (V1 = I for the identity basis)
+    const FineModel& fm = bs.fm;
+    const size_t nf = (size_t)prm->r * prm->ni * prm->r * prm->nj;
+    std::fill(grad_eps_r, grad_eps_r + nf, 0.0);
+    std::fill(grad_sigma, grad_sigma + nf, 0.0);
+    const bool ident = bs.V1.empty();
+    std::vector<double> u(q1), tR(q1), tF(q1);
+    for (int e = 0; e < fm.nE; ++e) {
+      double dDe, dDs;
+      if (ident) {
+        dDe = gR11[(size_t)e * q1 + e] / dt;
+        dDs = 0.5 * gF11[(size_t)e * q1 + e];
+      } else {
+        for (int a = 0; a < q1; ++a) u[a] = bs.V1[a][e];
+        std::fill(tR.begin(), tR.end(), 0.0);
+        std::fill(tF.begin(), tF.end(), 0.0);
+        for (int a = 0; a < q1; ++a) {
+          if (u[a] == 0.0) continue;
+          fdtd::la::axpy(u[a], gR11.data() + (size_t)a * q1, tR.data(), q1);
+          fdtd::la::axpy(u[a], gF11.data() + (size_t)a * q1, tF.data(), q1);
+        }
+        dDe = fdtd::la::dot(tR.data(), u.data(), q1) / dt;
+        dDs = 0.5 * fdtd::la::dot(tF.data(), u.data(), q1);
+      }
+      for (const auto& cw : fm.ecells[e]) {
+        grad_eps_r[cw.first] += cw.second * kEps0 * dDe;
+        grad_sigma[cw.first] += cw.second * dDs;
+      }
     }
     return FDTD_OK;
   } catch (const std::bad_alloc&) {

@@ -686,6 +686,10 @@ int coupling_precompute(const fdtd_problem* p, std::vector<RomHost>& out) {
     for (int c = 0; c < np; ++c)
       for (int a = 0; a < q; ++a) h.C[(size_t)c * q + a] = r.Lt[(size_t)a * np + c];
     h.R.assign(r.Rt, r.Rt + (size_t)q * q);
+    h.F.assign(r.Ft, r.Ft + (size_t)q * q);
+    h.cp = std::move(cp);
+    h.cm = std::move(cm);
+    h.sc = std::move(sc);
   }
   return FDTD_OK;
 }

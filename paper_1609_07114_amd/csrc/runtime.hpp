@@ -58,6 +58,8 @@ struct RomHost {
   int i0, j0, ni, nj, q, np, slot;
   std::vector<double> A, B, C;  // closed form, row-major
   std::vector<double> R;        // R~ (energy diagnostic)
+  std::vector<double> F;        // F~ (gradients through the models)
+  std::vector<double> cp, cm, sc;  // eq. (13) half cells C+, C- and Sc per port
 };
 
 }  // namespace fdtd

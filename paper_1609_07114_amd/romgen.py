@@ -55,3 +55,13 @@ def build_roms_many(probs, theta=0.99, clip=True, workers=None):
         out.append(built[k:k + len(prob.roms)])
         k += len(prob.roms)
     return out
+
+
+def build_vjp(prob, k, grad_Rt, grad_Ft, theta=0.99, clip=True, basis="sprim"):
+    """Gradient of J with respect to region k's fine-cell eps_r and sigma
+    ([r*nj, r*ni] each) from dJ/dR~ and dJ/dF~ of the model build_roms makes
+    for it (the library's builder, its projection basis held)."""
+    spec = prob.roms[k]
+    return capi.fdtd_rom_build_vjp(spec.ni, spec.nj, spec.r, prob.dx, prob.dy, prob.dt, spec.eps_r,
+                                   spec.sigma, spec.q, spec.f_max, grad_Rt, grad_Ft, theta, clip, basis,
+                                   getattr(spec, "pec", None))

@@ -126,6 +126,21 @@ class Simulation:
             self.stream.synchronize()
             del aws
 
+    def adjoint_models(self, nsteps=None, probe=0, ckpt_every=0):
+        """The reverse sweep with the gradients through the reduced models:
+        (J, dJ/deps_r, dJ/dsigma, [dict(Rt, Ft, Lt) of dJ/d(matrix)] per
+        region); the coarse maps include the ring cells' eq. (13) share."""
+        nsteps = self.prob.nsteps if nsteps is None else nsteps
+        nb = capi.fdtd_rom_adjoint_models_workspace_size(self.h, nsteps, ckpt_every)
+        aws = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
+        shapes = [(s.q, s.n_ports) for s in self.prob.roms]
+        try:
+            return capi.fdtd_rom_adjoint_models(self.h, nsteps, ckpt_every, probe, aws.data_ptr(), nb,
+                                                self.prob.nx, self.prob.ny, shapes)
+        finally:
+            self.stream.synchronize()
+            del aws
+
     def profile(self, enable=True):
         capi.fdtd_rom_profile_enable(self.h, enable)
 

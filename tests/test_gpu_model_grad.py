@@ -1,0 +1,116 @@
+"""Gradients through the reduced models on the device
+(fdtd_rom_adjoint_models, fdtd_rom_build_vjp) against the oracle
+(oracle.model_grad, pinned by finite differences).
+
+* Same model inputs on both sides: J, the coarse maps (ring cells included)
+  and every region's dJ/dR~, dJ/dF~, dJ/dL~ - FP64 <= 1e-10 relative L2,
+  FP32 (the transpose of the FP32 run, FP64 accumulators and algebra)
+  <= 1e-4, the adjoint's FP32 bar.
+* The whole chain to the fine cells: the library-built models, the device
+  sweep and the library's builder gradient against the oracle's chain
+  (its own models and builder) - FP64 <= 1e-9 (the two builders agree to
+  about 1e-12 on a model's basis-independent content) - and against
+  central differences of the oracle's run with the basis held at sampled
+  fine cells (1e-5, the differences' own accuracy), with and without the
+  eq. (27) clip."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint as oadj
+from oracle import model_grad as mg
+from oracle import rom as orom
+from oracle import sim as osim
+from paper_1609_07114_amd import romgen
+from paper_1609_07114_amd.sim import Simulation
+from tests._util import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(r=2, q=12, seed=31, nroms=1, nsteps=250, dtype="f64"):
+    p = W.random_problem(seed, 30, 26, nsteps, nroms=nroms, block=(5, 4), r=r, q=q,
+                         dt_frac_coarse=0.9, f_bw=3e9)
+    p.dtype = dtype
+    return p
+
+
+def _gpu(p, roms, dtype, ckpt=0):
+    print(f"[gpu-mg] {p.name} {dtype} q={[s.q for s in p.roms]} ckpt={ckpt}", flush=True)
+    with Simulation(p, roms, dtype=dtype) as s:
+        return s.adjoint_models(p.nsteps, probe=0, ckpt_every=ckpt)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-4)])
+@pytest.mark.parametrize("nroms,ckpt", [(1, 0), (2, 37)])
+def test_matrix_and_ring_gradients_vs_oracle(dtype, tol, nroms, ckpt):
+    p = _problem(nroms=nroms, seed=31 + nroms)
+    roms = osim.build_roms(p)
+    J, ge, gs, models = _gpu(p, roms, dtype, ckpt)
+    o = mg.model_gradient(p, roms, fp32=(dtype == "f32"))
+    assert J == pytest.approx(o["J"], rel=tol)
+    for name, a, b in (("eps_r", ge, o["eps_r"]), ("sigma", gs, o["sigma"])):
+        e = rel_l2(a, b)
+        print(f"[gpu-mg] {dtype} coarse {name} {e:.2e}", flush=True)
+        assert e <= tol, (name, e)
+    for k, (gm, om) in enumerate(zip(models, o["models"])):
+        for key in ("Rt", "Ft", "Lt"):
+            e = rel_l2(gm[key], om[key])
+            print(f"[gpu-mg] {dtype} region {k} d{key} {e:.2e}", flush=True)
+            assert e <= tol, (k, key, e)
+    # ring cells carry their eq. (13) share, region interiors stay zero
+    for s in p.roms:
+        ring = ge[s.j0 - 1, s.i0:s.i0 + s.ni]
+        assert np.all(ring != 0.0)
+        assert np.all(ge[s.j0:s.j0 + s.nj, s.i0:s.i0 + s.ni] == 0.0)
+
+
+def test_plain_adjoint_unchanged_outside_rings():
+    """Outside the regions and rings the coarse gradient equals the plain
+    adjoint's bit for bit (the same sweep)."""
+    p = _problem()
+    roms = osim.build_roms(p)
+    with Simulation(p, roms) as s:
+        J0, ge0, gs0 = s.adjoint(p.nsteps)
+    J, ge, gs, _ = _gpu(p, roms, "f64")
+    m = oadj.gradient_mask(p)
+    assert J == J0
+    assert np.array_equal(ge[m], ge0[m]) and np.array_equal(gs[m], gs0[m])
+
+
+@pytest.mark.parametrize("r,q,clipped", [(2, 12, False), (3, 140, True)])
+def test_fine_cell_gradients_whole_chain(r, q, clipped):
+    p = _problem(r=r, q=q)
+    s = p.roms[0]
+    lib = romgen.build_roms(p)
+    assert lib[0]["clipped"] == clipped
+    J, ge, gs, models = _gpu(p, lib, "f64")
+    fe, fs = romgen.build_vjp(p, 0, models[0]["Rt"], models[0]["Ft"])
+    # the oracle's chain on its own models
+    full = orom.build_rom(s.eps_r, s.sigma, s.r, p.dx, p.dy, p.dt, s.q, s.f_max)
+    og = mg.model_gradient(p, [dict(Rt=full["Rt"], Ft=full["Ft"], Lt=full["Lt"])])
+    oe, os_ = mg.build_vjp(full, og["models"][0]["Rt"], og["models"][0]["Ft"])
+    for name, a, b in (("eps_r", fe, oe), ("sigma", fs, os_)):
+        e = rel_l2(a, b)
+        print(f"[gpu-mg] fine {name} r={r} q={q} vs oracle chain {e:.2e}", flush=True)
+        assert e <= 1e-9, (name, e)
+    # central differences of the oracle's run, basis held
+    basis = (full["V1"], full["V2"])
+
+    def J_of(er, sg):
+        m = orom.build_rom(er, sg, s.r, p.dx, p.dy, p.dt, s.q, s.f_max, basis=basis)
+        return oadj.objective(p, [dict(Rt=m["Rt"], Ft=m["Ft"], Lt=m["Lt"])])
+    Ny, Nx = s.eps_r.shape
+    for (i, j) in [(0, 0), (Nx // 2, Ny // 3), (Nx - 1, Ny - 1)]:
+        h = 1e-4 * s.eps_r[j, i]
+        ep, em = s.eps_r.copy(), s.eps_r.copy()
+        ep[j, i] += h
+        em[j, i] -= h
+        fd = (J_of(ep, s.sigma) - J_of(em, s.sigma)) / (2 * h)
+        assert fe[j, i] == pytest.approx(fd, rel=1e-5, abs=1e-6 * np.abs(fe).max()), (i, j)
+        h = 1e-4
+        sp, sm = s.sigma.copy(), s.sigma.copy()
+        sp[j, i] += h
+        sm[j, i] -= h
+        fd = (J_of(s.eps_r, sp) - J_of(s.eps_r, sm)) / (2 * h)
+        assert fs[j, i] == pytest.approx(fd, rel=1e-5, abs=1e-6 * np.abs(fs).max()), (i, j)

@@ -167,3 +167,45 @@ def test_builder_with_pec_cells_matches_oracle(basis):
     bad[0, 0] = True
     with pytest.raises(capi.FdtdError):
         capi.fdtd_rom_build(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, s.q, s.f_max, pec=bad)
+
+
+def _port_response(Rt, Ft, Lt, Wm, p=0.3):
+    """f = sum(W o H(p)), H(p) = L~^T (p R~ + F~)^{-1} L~ - a quantity of the
+    model that does not depend on its basis - and its gradients with
+    respect to R~ and F~."""
+    X = p * Rt + Ft
+    Xi = np.linalg.inv(X)
+    gX = -Xi.T @ Lt @ Wm @ Lt.T @ Xi.T
+    return float(np.sum(Wm * (Lt.T @ Xi @ Lt))), p * gX, gX
+
+
+@pytest.mark.parametrize("r,q,basis,clipped,pec", [(2, 12, "sprim", False, False), (3, 140, "sprim", True, False),
+                                                   (2, 0, "identity", True, False), (2, 16, "sprim", False, True)])
+def test_build_vjp_matches_oracle(r, q, basis, clipped, pec):
+    """The gradient through the builder (basis held; through the eq. (27)
+    clip when it acts) of a basis-independent function of the model equals
+    the oracle's (pinned by finite differences) to 1e-12: each side takes
+    the function's gradient in its own basis."""
+    p = W.random_problem(31, 30, 26, 10, nroms=1, block=(5, 4), r=r, q=q, dt_frac_coarse=0.9, f_bw=3e9)
+    s = p.roms[0]
+    fp = None
+    if pec:
+        fp = np.zeros((r * s.nj, r * s.ni), dtype=bool)
+        fp[:4, 4:6] = True
+        fp[2, 2] = True
+    o = orom.build_rom(s.eps_r, s.sigma, s.r, p.dx, p.dy, p.dt, s.q, s.f_max, basis=basis, pec=fp)
+    lib = capi.fdtd_rom_build(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, s.q, s.f_max, basis=basis,
+                              pec=fp)
+    assert o["clipped"] == clipped and lib["clipped"] == clipped
+    Wm = np.random.default_rng(0).standard_normal((s.n_ports, s.n_ports))
+    fo, gRo, gFo = _port_response(o["Rt"], o["Ft"], o["Lt"], Wm)
+    fl, gRl, gFl = _port_response(lib["Rt"], lib["Ft"], lib["Lt"], Wm)
+    assert fl == pytest.approx(fo, rel=1e-12)
+    from oracle import model_grad as mg
+    geo, gso = mg.build_vjp(o, gRo, gFo)
+    gel, gsl = capi.fdtd_rom_build_vjp(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, s.q, s.f_max, gRl, gFl,
+                                       basis=basis, pec=fp)
+    assert np.linalg.norm(gel - geo) <= 1e-12 * np.linalg.norm(geo)
+    assert np.linalg.norm(gsl - gso) <= 1e-12 * np.linalg.norm(gso)
+    if pec:
+        assert np.all(gel[fp] == 0) and np.all(gsl[fp] == 0)
