@@ -1,11 +1,14 @@
 """GPU reverse sweep (fdtd_rom_adjoint through the C ABI) against the CPU
 FP64 oracle adjoint, against central finite differences of the GPU's own
 FP64 forward, across checkpoint intervals, and through the PyTorch
-autograd wrapper.  Bars: FP64 <= 1e-10 relative L2 over the gradient maps
-(the reverse sweep sums N steps of per-edge products, the forward bar is
-1e-12); FP32 <= 1e-4 relative L2 against the oracle's transpose of the
-FP32-coefficient forward (the FP32 forward is held to 1e-5 on probes; the
-gradient is a sum of products of two FP32 trajectories)."""
+autograd wrapper.  Bars: FP64 <= 1e-12 relative L2 over the gradient maps;
+FP32 <= 1e-5 relative L2 against the oracle's transpose of the FP32
+forward (the oracle evaluates it in FP64 arithmetic on the FP32-rounded
+coefficients and update matrices, so the bar measures the sweep's own
+arithmetic).  Against the FP64 run of the full C5 workload the FP32 maps
+are held to 5e-5: that distance is set by rounding the eq. (3)
+coefficients and eq. (23) matrices to FP32 (a different discrete problem),
+not by the sweep's arithmetic."""
 import copy
 
 import numpy as np
@@ -20,8 +23,8 @@ from tests._util import rel_l2
 
 pytestmark = pytest.mark.gpu
 
-TOL64 = 1e-10
-TOL32 = 1e-4
+TOL64 = 1e-12
+TOL32 = 1e-5
 
 
 def _gpu_adj(prob, roms, nsteps=None, dtype=None, ckpt=0, probe=0):
@@ -41,6 +44,8 @@ def _gpu_J(prob, roms, nsteps, dtype="f64", probe=0):
 def _compare(g, o, tol):
     Jg, geg, gsg = g
     Jo, geo, gso = o
+    print(f"[gpu-adjoint] J {abs(Jg - Jo) / abs(Jo):.2e} eps {rel_l2(geg, geo):.2e} sigma {rel_l2(gsg, gso):.2e}",
+          flush=True)
     assert Jg == pytest.approx(Jo, rel=tol)
     assert rel_l2(geg, geo) <= tol, rel_l2(geg, geo)
     assert rel_l2(gsg, gso) <= tol, rel_l2(gsg, gso)
@@ -189,9 +194,11 @@ def test_c5_full_fp32_vs_fp64(c5_full):
     p, roms = c5_full
     J64, ge64, gs64 = _gpu_adj(p, roms, dtype="f64", ckpt=200)
     J32, ge32, gs32 = _gpu_adj(p, roms, dtype="f32", ckpt=200)
-    assert J32 == pytest.approx(J64, rel=1e-4)
-    assert rel_l2(ge32, ge64) <= 1e-3, rel_l2(ge32, ge64)
-    assert rel_l2(gs32, gs64) <= 1e-3, rel_l2(gs32, gs64)
+    print(f"[gpu-adjoint] C5 FP32 vs FP64: J {abs(J32 - J64) / abs(J64):.2e} eps {rel_l2(ge32, ge64):.2e} "
+          f"sigma {rel_l2(gs32, gs64):.2e}", flush=True)
+    assert J32 == pytest.approx(J64, rel=1e-5)
+    assert rel_l2(ge32, ge64) <= 5e-5, rel_l2(ge32, ge64)
+    assert rel_l2(gs32, gs64) <= 5e-5, rel_l2(gs32, gs64)
 
 
 def test_host_plan_equals_handle_workspace_size():

@@ -2,7 +2,7 @@
 C ABI): against the oracle's transpose of the layered run, against central
 finite differences of the GPU's own FP64 forward at cells inside the
 layers, and across checkpoint intervals.  Bars as for the PEC-walled
-sweep: FP64 <= 1e-10, FP32 <= 1e-4 relative L2 over the gradient maps.
+sweep: FP64 <= 1e-12, FP32 <= 1e-5 relative L2 over the gradient maps.
 
 The grids are wide and tall enough that waves of the reverse step fall
 both inside the layers (layer form) and wholly outside them (plain form),
@@ -23,8 +23,8 @@ from tests._util import rel_l2
 
 pytestmark = pytest.mark.gpu
 
-TOL64 = 1e-10
-TOL32 = 1e-4
+TOL64 = 1e-12
+TOL32 = 1e-5
 
 
 def _with_layers(p, want, probe, **grading):

@@ -3,13 +3,13 @@
 (oracle.model_grad, pinned by finite differences).
 
 * Same model inputs on both sides: J, the coarse maps (ring cells included)
-  and every region's dJ/dR~, dJ/dF~, dJ/dL~ - FP64 <= 1e-10 relative L2,
+  and every region's dJ/dR~, dJ/dF~, dJ/dL~ - FP64 <= 1e-12 relative L2,
   FP32 (the transpose of the FP32 run, FP64 accumulators and algebra)
-  <= 1e-4, the adjoint's FP32 bar.
+  <= 1e-5, the adjoint's bars.
 * The whole chain to the fine cells: the library-built models, the device
   sweep and the library's builder gradient against the oracle's chain
-  (its own models and builder) - FP64 <= 1e-9 (the two builders agree to
-  about 1e-12 on a model's basis-independent content) - and against
+  (its own models and builder) - FP64 <= 1e-10 (the two builders agree to
+  about 1e-13 on a model's basis-independent content) - and against
   central differences of the oracle's run with the basis held at sampled
   fine cells (1e-5, the differences' own accuracy), with and without the
   eq. (27) clip."""
@@ -41,7 +41,7 @@ def _gpu(p, roms, dtype, ckpt=0):
         return s.adjoint_models(p.nsteps, probe=0, ckpt_every=ckpt)
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-4)])
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
 @pytest.mark.parametrize("nroms,ckpt", [(1, 0), (2, 37)])
 def test_matrix_and_ring_gradients_vs_oracle(dtype, tol, nroms, ckpt):
     p = _problem(nroms=nroms, seed=31 + nroms)
@@ -93,7 +93,7 @@ def test_fine_cell_gradients_whole_chain(r, q, clipped):
     for name, a, b in (("eps_r", fe, oe), ("sigma", fs, os_)):
         e = rel_l2(a, b)
         print(f"[gpu-mg] fine {name} r={r} q={q} vs oracle chain {e:.2e}", flush=True)
-        assert e <= 1e-9, (name, e)
+        assert e <= 1e-10, (name, e)
     # central differences of the oracle's run, basis held
     basis = (full["V1"], full["V2"])
 

@@ -4,7 +4,7 @@ the wall through a region's ring into the region, a metal corner cell and
 an interior metal cell, against the oracle (FP64 <= 1e-12, FP32 <= 1e-5
 relative L2 on probes, fields and reduced states), with one launch per step
 and with two steps per pass, in a batch (bit-identical to its own handle),
-and through the adjoint (FP64 <= 1e-10, the adjoint bar)."""
+and through the adjoint (FP64 <= 1e-12, FP32 <= 1e-5, the adjoint bars)."""
 import numpy as np
 import pytest
 
@@ -68,7 +68,7 @@ def test_pec_problem_library_models_and_batch():
         assert np.array_equal(got, s.probes())
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-4)])
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_pec_adjoint_vs_oracle(dtype, tol):
     p = W.pec_problem(7, r=2, q=10, nsteps=200, dtype=dtype)
     roms = osim.build_roms(p)
