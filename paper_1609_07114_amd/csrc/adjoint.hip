@@ -520,6 +520,7 @@ hipError_t launch_adjoint_step(const AdjParams<T>& p, size_t smem, hipStream_t s
   auto go = [&](auto layers) -> hipError_t {
     constexpr bool Ly = decltype(layers)::value;
     switch (p.seg) {
+      case 2: hipLaunchKernelGGL((adj_stream<T, 2, Ly>), g, dim3(kBlock), 0, s, p); break;
       case 4: hipLaunchKernelGGL((adj_stream<T, 4, Ly>), g, dim3(kBlock), 0, s, p); break;
       case 8: hipLaunchKernelGGL((adj_stream<T, 8, Ly>), g, dim3(kBlock), 0, s, p); break;
       case 16: hipLaunchKernelGGL((adj_stream<T, 16, Ly>), g, dim3(kBlock), 0, s, p); break;

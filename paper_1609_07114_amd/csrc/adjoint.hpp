@@ -32,7 +32,7 @@ struct AdjParams {
   T* ga_e;
   T* ga_s;
   int nx, ny, pitch;
-  int seg;           // rows per wave of the streamed reverse step (4, 8, 16)
+  int seg;           // rows per wave of the streamed reverse step (2, 4, 8, 16)
   T chdy, chdx, k2dy, k2dx;
   double dx, dy;
   double fa;         // d(eps0*eps_r/dt averaged on an edge)/d eps_r(cell) = eps0/(2 dt)

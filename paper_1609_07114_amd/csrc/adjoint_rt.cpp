@@ -428,7 +428,13 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   ap.nx = s->nx;
   ap.ny = s->ny;
   ap.pitch = s->pitch;
-  ap.seg = std::min(default_tiling(s->nx, s->ny, (int)L.tsize), 16);
+  // rows per reverse wave: half the forward's 4-row default on grids that
+  // small (more waves in flight; the C5 1024^2 sweep: 182.5 ms at 2 rows,
+  // 190.7 at 4, 185.8 at 8), else the forward's, at most 16
+  {
+    const int fw = default_tiling(s->nx, s->ny, (int)L.tsize);
+    ap.seg = fw == 4 ? 2 : std::min(fw, 16);
+  }
   ap.chdy = sp.chdy;
   ap.chdx = sp.chdx;
   ap.k2dy = sp.k2dy;

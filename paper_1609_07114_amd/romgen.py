@@ -65,3 +65,16 @@ def build_vjp(prob, k, grad_Rt, grad_Ft, theta=0.99, clip=True, basis="sprim"):
     return capi.fdtd_rom_build_vjp(spec.ni, spec.nj, spec.r, prob.dx, prob.dy, prob.dt, spec.eps_r,
                                    spec.sigma, spec.q, spec.f_max, grad_Rt, grad_Ft, theta, clip, basis,
                                    getattr(spec, "pec", None))
+
+
+def build_vjps(prob, model_grads, theta=0.99, clip=True, basis="sprim", workers=None):
+    """build_vjp for every region (model_grads: per region a dict with Rt
+    and Ft gradients, as Simulation.adjoint_models returns), regions in
+    parallel threads (each call rebuilds its region's model)."""
+    n = len(prob.roms)
+    one = lambda k: build_vjp(prob, k, model_grads[k]["Rt"], model_grads[k]["Ft"], theta, clip, basis)
+    workers = workers or min(n, max(1, min(16, os.cpu_count() or 1))) or 1
+    if n <= 1:
+        return [one(k) for k in range(n)]
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(one, range(n)))

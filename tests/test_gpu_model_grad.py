@@ -114,3 +114,25 @@ def test_fine_cell_gradients_whole_chain(r, q, clipped):
         sm[j, i] -= h
         fd = (J_of(s.eps_r, sp) - J_of(s.eps_r, sm)) / (2 * h)
         assert fs[j, i] == pytest.approx(fd, rel=1e-5, abs=1e-6 * np.abs(fs).max()), (i, j)
+
+
+def test_autograd_through_models():
+    """probe_energy_models: J of the coarse maps and the region's fine maps
+    as a torch function; its gradients are the library's (sweep through the
+    models, then the builder's gradient), scaled by the incoming gradient."""
+    import torch
+    from paper_1609_07114_amd.adjoint import probe_energy_models
+    p = _problem()
+    lib = romgen.build_roms(p)
+    J, ge, gs, models = _gpu(p, lib, "f64")
+    fe, fs = romgen.build_vjp(p, 0, models[0]["Rt"], models[0]["Ft"])
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    er, sg, fer, fsg = t(p.eps_r), t(p.sigma), t(p.roms[0].eps_r), t(p.roms[0].sigma)
+    out = probe_energy_models(er, sg, [fer], [fsg], p, dtype="f64")
+    (2.0 * out).backward()
+    assert float(out.detach()) == pytest.approx(J, rel=1e-14)
+    for got, want in ((er.grad, ge), (sg.grad, gs), (fer.grad, fe), (fsg.grad, fs)):
+        assert np.allclose(got.cpu().numpy(), 2.0 * want, rtol=1e-14, atol=0)
+    with torch.no_grad():
+        J2 = probe_energy_models(er, sg, [fer], [fsg], p, dtype="f64")
+    assert float(J2) == pytest.approx(J, rel=1e-14)
