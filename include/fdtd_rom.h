@@ -542,6 +542,10 @@ int fdtd_rom_batch_read_field(const fdtd_rom_batch* batch, int32_t b, int32_t co
                               double* host_out);
 int fdtd_rom_batch_set_tiling(fdtd_rom_batch* batch, int32_t b, int32_t seg);
 int fdtd_rom_batch_set_graph(fdtd_rom_batch* batch, int32_t batch_steps);
+/* The far tiles' share in a pair's second launch (fdtd_rom_set_pair_split)
+ * for instance b, or for every instance with b = -1; the batch's pair
+ * tables are rebuilt before the next pair.  Results do not depend on it. */
+int fdtd_rom_batch_set_pair_split(fdtd_rom_batch* batch, int32_t b, int32_t percent);
 /* Two steps per pass for every instance (as fdtd_rom_set_time_blocking, all
  * instances in lockstep): on by default when no instance has absorbing
  * layers; FDTD_EINVAL for on = 1 otherwise or a value other than 0/1. */

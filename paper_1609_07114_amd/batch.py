@@ -54,6 +54,11 @@ class Batch:
     def set_graph(self, steps):
         capi.fdtd_rom_batch_set_graph(self.h, steps)
 
+    def set_pair_split(self, b, percent):
+        """Far tiles' share (percent) in a pair's second launch, instance b
+        (all instances for b = -1; -1 percent restores the default)."""
+        capi.fdtd_rom_batch_set_pair_split(self.h, b, percent)
+
     def set_time_blocking(self, on):
         capi.fdtd_rom_batch_set_time_blocking(self.h, on)
 

@@ -112,6 +112,7 @@ _SIGS = {
     "fdtd_rom_set_pair_split": (C.c_int, [C.c_void_p, C.c_int32]),
     "fdtd_rom_get_pair_split": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "fdtd_rom_batch_set_time_blocking": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fdtd_rom_batch_set_pair_split": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "fdtd_rom_batch_get_time_blocking": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fdtd_rom_get_time_blocking": (C.c_int, [C.c_void_p, C.c_void_p]),
     "fdtd_rom_adjoint_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
@@ -440,6 +441,10 @@ def fdtd_rom_get_time_blocking(h) -> bool:
     v = C.c_int32(0)
     _check(lib().fdtd_rom_get_time_blocking(h, C.byref(v)))
     return bool(v.value)
+
+
+def fdtd_rom_batch_set_pair_split(h, b: int, percent: int):
+    _check(lib().fdtd_rom_batch_set_pair_split(h, int(b), int(percent)))
 
 
 def fdtd_rom_batch_set_time_blocking(h, on: bool):

@@ -456,6 +456,19 @@ int fdtd_rom_batch_set_tiling(fdtd_rom_batch* bt, int32_t b, int32_t seg) {
   return FDTD_OK;
 }
 
+int fdtd_rom_batch_set_pair_split(fdtd_rom_batch* bt, int32_t b, int32_t percent) {
+  if (!bt) return fail(FDTD_EINVAL, "null handle");
+  if (b < -1 || b >= bt->B) return fail(FDTD_EINVAL, "instance %d out of range", b);
+  for (int k = 0; k < bt->B; ++k)
+    if (b < 0 || k == b) {
+      const int rc = fdtd_rom_set_pair_split(bt->sims[k], percent);
+      if (rc != FDTD_OK) return rc;
+    }
+  drop_batch_graph(bt);  // the pair tables change size
+  bt->dirty = true;
+  return FDTD_OK;
+}
+
 int fdtd_rom_batch_set_time_blocking(fdtd_rom_batch* bt, int32_t on) {
   if (!bt) return fail(FDTD_EINVAL, "null handle");
   if (on != 0 && on != 1) return fail(FDTD_EINVAL, "time blocking must be 0 or 1");

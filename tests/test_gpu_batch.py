@@ -117,9 +117,11 @@ def test_autotuner_caches_choice(tmp_path):
     path = str(tmp_path / "tune.json")
     seen = []
     choice = autotune.tune(probs, roms, path=path, trial_steps=8, log=seen.append)
-    assert set(choice) == {autotune.bucket_of(p) for p in probs}
-    assert all(v in autotune.CANDIDATES for v in choice.values())
-    assert len(seen) == len(autotune.CANDIDATES) * len(choice)
+    buckets = {autotune.bucket_of(p) for p in probs}
+    assert set(choice) == buckets | {autotune.SPLIT}
+    assert all(choice[b] in autotune.CANDIDATES for b in buckets)
+    assert choice[autotune.SPLIT] in autotune.SPLITS
+    assert len(seen) == len(autotune.CANDIDATES) * len(buckets) + len(autotune.SPLITS)
     d = json.load(open(path))
     assert all(k.endswith(tuple(choice)) for k in d)
     again = []

@@ -170,11 +170,13 @@ def test_layers_refuse_two_steps():
         assert not s.time_blocking()
 
 
-def _batch_run(probs, models, tb, pieces, graph=0, seg=None):
+def _batch_run(probs, models, tb, pieces, graph=0, seg=None, split=None):
     from paper_1609_07114_amd.batch import Batch
     with Batch(probs, models, dtype="f32") as bt:
         if seg:
             bt.set_tiling(-1, seg)
+        if split is not None:
+            bt.set_pair_split(-1, split)
         bt.set_graph(graph)
         bt.set_time_blocking(tb)
         assert bt.time_blocking() == tb
@@ -192,14 +194,15 @@ def mix():
     return probs, [osim.build_roms(p) for p in probs]
 
 
-@pytest.mark.parametrize("graph,seg", [(0, None), (8, None), (64, 4), (0, 32)])
-def test_batch_two_step_equals_single_step(mix, graph, seg):
+@pytest.mark.parametrize("graph,seg,split", [(0, None, None), (8, None, 50), (64, 4, 25), (0, 32, 90)])
+def test_batch_two_step_equals_single_step(mix, graph, seg, split):
     """Four uneven instances in one batch, pairs and odd pieces, graph
-    batches, every tiling: two steps per pass equals one launch per step,
-    and each instance equals its own handle."""
+    batches, every tiling, far tiles shared with the second launch: two
+    steps per pass equals one launch per step, and each instance equals its
+    own handle."""
     probs, models = mix
     pieces = (3, 64, 1, 40, 22)
-    a = _batch_run(probs, models, True, pieces, graph, seg)
+    a = _batch_run(probs, models, True, pieces, graph, seg, split)
     b = _batch_run(probs, models, False, pieces, graph, seg)
     for k in range(len(probs)):
         assert np.array_equal(a[0][k], b[0][k]), k
