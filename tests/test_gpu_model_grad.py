@@ -136,3 +136,43 @@ def test_autograd_through_models():
     with torch.no_grad():
         J2 = probe_energy_models(er, sg, [fer], [fsg], p, dtype="f64")
     assert float(J2) == pytest.approx(J, rel=1e-14)
+
+
+def _check_vs_oracle(p, roms, dtype="f64", tol=1e-12, ckpt=0):
+    J, ge, gs, models = _gpu(p, roms, dtype, ckpt)
+    o = mg.model_gradient(p, roms, fp32=(dtype == "f32"))
+    assert J == pytest.approx(o["J"], rel=tol)
+    errs = [rel_l2(ge, o["eps_r"]), rel_l2(gs, o["sigma"])]
+    for gm, om in zip(models, o["models"]):
+        errs += [rel_l2(gm[k], om[k]) for k in ("Rt", "Ft", "Lt")]
+    print(f"[gpu-mg] {p.name} {dtype} errors {['%.1e' % e for e in errs]}", flush=True)
+    assert max(errs) <= tol, errs
+    return ge, gs, models
+
+
+def test_with_absorbing_layers():
+    """Layers at every side (graded, kappa and alpha on), two models: the
+    sweep through the models transposes the auxiliary fields as the plain
+    adjoint does."""
+    import copy
+    p = W.random_problem(41, 150, 140, 300, nroms=2, block=(5, 4), r=2, q=10, dt_frac_coarse=0.9, f_bw=3e9)
+    p = copy.deepcopy(p)
+    p.probes[0] = W.Probe(W.HZ, 144, 118)
+    lim = [10, 10, 8, 8]
+    for s in p.roms:
+        lim = [min(lim[0], s.i0 - 2), min(lim[1], p.nx - s.i0 - s.ni - 2),
+               min(lim[2], s.j0 - 2), min(lim[3], p.ny - s.j0 - s.nj - 2)]
+    p.pml = W.Pml(*[max(0, v) for v in lim], kappa_max=3.0, alpha_max=0.03)
+    assert p.pml.any
+    _check_vs_oracle(p, osim.build_roms(p), ckpt=60)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_with_pec_cells(dtype, tol):
+    """A region with PEC fine cells (dead ports: zero columns of L~) next to
+    PEC coarse cells of its ring: their gradients are zero, the live ports'
+    are the oracle's."""
+    p = W.pec_problem(nsteps=200)
+    roms = osim.build_roms(p)
+    ge, gs, models = _check_vs_oracle(p, roms, dtype, tol)
+    assert np.all(ge[p.pec] == 0) and np.all(gs[p.pec] == 0)
