@@ -841,14 +841,15 @@ int fdtd::default_tiling(int nx, int ny, int ts) {
 // Default rows per wave of the two-step launches (60 owned columns per
 // wave): 16 while the launch still holds >= 4096 waves and the three field
 // sets and the material stay Infinity-Cache resident (2048^2 FP32: 14.8 us
-// per step at 16 rows, 15.0 at 8), else 8 for large grids (8192^2: 246 us
-// at 8 rows, 262 at 16) and 4 for small ones.
+// per step at 16 rows, 15.0 at 8), else 4: more waves in flight beat the
+// extra halo rows they read (8192^2: 243.8 us per step at 4 rows, 248.9 at
+// 8, 268.7 at 16; 4096^2 with 256 copies of one model: 80.8, 82.1, 93.4).
 int fdtd::default_tiling2(int nx, int ny, int ts) {
   const long tx = (nx + kOwned2 - 1) / kOwned2;
   auto waves = [&](int seg) { return tx * ((ny + seg - 1) / seg); };
   const double bytes = (9.0 * ts + 2.0) * (double)nx * (double)ny;  // three field sets + material index
   if (waves(16) >= 4096 && bytes <= 192.0 * (1 << 20)) return 16;
-  return waves(8) >= 4096 ? 8 : 4;
+  return 4;
 }
 
 // a stencil workgroup covers 64 columns x (4 waves x seg rows)
