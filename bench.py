@@ -127,10 +127,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, material_mode, tb=False, seg=None):
+def measured_traffic(workload, material_mode, tb=False, seg=None, split=None):
     """HBM bytes per unit (step launch, or two-step pair) from committed
     rocprofv3 counter runs, if they were taken on the current kernel source
-    in the same material and stepping mode and rows per wave (else None)."""
+    in the same material and stepping mode, rows per wave and pair split
+    (else None)."""
     try:
         with open(COUNTERS[workload]) as fh:
             d = json.load(fh)
@@ -138,7 +139,8 @@ def measured_traffic(workload, material_mode, tb=False, seg=None):
         return None
     if (d.get("kernel_source_hash") != kernel_source_hash() or d.get("material_mode", 0) != material_mode
             or bool(d.get("time_blocking", 0)) != bool(tb)
-            or (seg is not None and d.get("rows_per_wave") != seg)):
+            or (seg is not None and d.get("rows_per_wave") != seg)
+            or (split is not None and d.get("pair_split", 0) != split)):
         return None
     return d.get("bytes_per_unit", d.get("bytes_per_launch"))
 
@@ -359,11 +361,13 @@ def run_headline(prob, roms, steps, warmup, kind, workload, time_blocking=1, mat
     t1 = time.perf_counter()
     ev_ms = ev0.elapsed_time(ev1)
     probes = sim.probes(0, total)
+    split = sim.pair_split() if tb else 0
     sim.close()
     elapsed = t1 - t0
     cells = prob.nx * prob.ny
     roof = stencil_roofline(prob, steps, ev_ms, mmode, tb, seg, kind)
-    roof["traffic"] = measured_traffic(workload, mmode, tb, seg)
+    roof["traffic"] = measured_traffic(workload, mmode, tb, seg, split)
+    roof["pair_split"] = split
     roof["material"] = {"mode": "table" if mmode else "per-cell", "entries": nmat}
     return {"value": cells * steps / elapsed / 1e6, "ms_per_step": elapsed * 1e3 / steps,
             "event_ms": ev_ms, "roofline": roof, "finite": bool(np.all(np.isfinite(probes))),

@@ -409,7 +409,7 @@ int fdtd_rom_get_time_blocking(const fdtd_rom_sim* sim, int32_t* on);
  * first.  Far tiles read only step n and write step n+2, so either launch
  * may take them; in the second they run beside the coupling blocks of step
  * n+1, whose chain of dependent loads would otherwise run alone there.
- * -1 (default) picks 50 when the grid's tiles do not fit on the GPU at once
+ * -1 (default) picks 60 when the grid's tiles do not fit on the GPU at once
  * and a shared model runs as the MFMA GEMM (fdtd_rom_set_shared_gemm; its
  * blocks form the longest chain), else 0.  Results do not depend on it.  get: the share in
  * effect (after the next pair's set-up), else the requested value. */

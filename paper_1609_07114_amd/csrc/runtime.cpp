@@ -915,11 +915,13 @@ int fdtd::prepare_tb(fdtd_rom_sim* s) {
   const int resident = 256 * 7;  // two-step tiles the GPU holds at once (256 CUs, 7 per CU)
   // the long chain of a shared model's MFMA GEMM blocks is worth hiding
   // under far tiles (4096^2 with 256 copies of one order-128 model: 176 ->
-  // 155 us per pair at 50 %); row-parallel GEMV blocks are short (8192^2
-  // with 256 models of orders 32-96: 490 us per pair at 0 %, 555 at 50 %)
+  // 155 us per pair at 50 % with 8-row waves; with 4-row waves per step
+  // 82.5 us at 30 %, 79.4 at 40, 80.1 at 50, 77.8 at 60, 77.9 at 70);
+  // row-parallel GEMV blocks are short (8192^2 with 256 models of orders
+  // 32-96, 4-row waves: 243.3 us per step at 0 %, 252-260 at 5-30 %)
   bool gemm = false;
   for (size_t sl = 0; sl < L.slot_gemm.size(); ++sl) gemm = gemm || (L.slot_gemm[sl] && s->shared_gemm);
-  const int split_pct = s->pair_split >= 0 ? s->pair_split : (nt > resident && gemm ? 50 : 0);
+  const int split_pct = s->pair_split >= 0 ? s->pair_split : (nt > resident && gemm ? 60 : 0);
   const int near_rows = nt <= resident ? 2 : s->seg;
   auto fill = [&](auto& sp) {
     sp.tiles_x2 = tx2;
