@@ -444,14 +444,19 @@ def bench_adjoint(ckpt=200, log=None):
     prob = W.adjoint_c5()
     roms = romgen.build_roms(prob)
     n = prob.nsteps
+    # both timed runs start with their graph batches captured (prepare_run):
+    # the forward's for the whole run, the adjoint's for its checkpoint
+    # segments, which its forward replays
     with Simulation(prob, roms) as s:
         s.set_graph(100)
+        s.prepare_run(n)
         t_f, _ = _timed(s.stream, lambda: s.run(n))
-    with Simulation(prob, roms) as s:      # untimed pass: graph capture, allocator
+    with Simulation(prob, roms) as s:      # untimed pass: allocator, code paths
         s.set_graph(100)
         s.adjoint(n, ckpt_every=ckpt)
     with Simulation(prob, roms) as s:
         s.set_graph(100)
+        s.prepare_run(ckpt)
         res = {}
         t_a, _ = _timed(s.stream, lambda: res.setdefault("r", s.adjoint(n, ckpt_every=ckpt)))
         J32, ge32, gs32 = res["r"]
@@ -462,6 +467,7 @@ def bench_adjoint(ckpt=200, log=None):
     # cells of every region, basis held)
     with Simulation(prob, roms) as s:
         s.set_graph(100)
+        s.prepare_run(ckpt)
         res = {}
         t_m, _ = _timed(s.stream, lambda: res.setdefault("m", s.adjoint_models(n, ckpt_every=ckpt)))
     _, _, _, mods32 = res["m"]

@@ -151,6 +151,24 @@ template hipError_t launch_transpose_block<double>(const double*, double*, int, 
 template hipError_t launch_probe_energy<float>(const float*, int, int, int, double, double*, hipStream_t);
 template hipError_t launch_probe_energy<double>(const double*, int, int, int, double, double*, hipStream_t);
 
+// mu of a cell outside the layers: its adjoint Hz plus the coupling's
+// lambda_h (0 off the ring cells) and the objective term, then the E
+// update's transposes of its south, north, west and east edges, in this
+// order and uncontracted, so that the stream and the fused coupling blocks
+// form the same value bit for bit
+template <typename T>
+__device__ __forceinline__ T mu_plain(T lh, T pend, T obj, bool aS, T cS, T lS, bool aN, T cN, T lN, bool aW, T cW,
+                                      T lW, bool aE, T cE, T lE) {
+#pragma clang fp contract(off)
+  T mu = lh + pend;
+  mu += obj;
+  mu += aS ? cS * lS : T(0);
+  mu -= aN ? cN * lN : T(0);
+  mu -= aW ? cW * lW : T(0);
+  mu += aE ? cE * lE : T(0);
+  return mu;
+}
+
 template <typename T>
 __device__ __forceinline__ void adj_coef(T s, T t, T k2, T& ca, T& cb, T& rcp) {
 #pragma clang fp contract(off)
@@ -315,12 +333,12 @@ constexpr int kAdjOwned = kWave - 3;  // columns a reverse-sweep wave owns
 // adjoints become ldE(below) - ldE(own), and the Cb weights take the
 // stretched difference dH/kappa + psi'.
 template <typename T, int SEG, bool PML>
-__device__ __forceinline__ void adj_rows(const AdjParams<T>& p) {
+__device__ __forceinline__ void adj_rows(const AdjParams<T>& p, int bx, int by) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int iw = blockIdx.x * kAdjOwned;
+  const int iw = bx * kAdjOwned;
   const int ic = iw - 2 + lane;
-  const int j0 = (blockIdx.y * (kBlock / kWave) + wv) * SEG;
+  const int j0 = (by * (kBlock / kWave) + wv) * SEG;
   const int j1 = min(j0 + SEG, p.ny);
   const int js = j0 > 0 ? j0 - 1 : 0;
   const int nx = p.nx, ny = p.ny;
@@ -376,8 +394,15 @@ __device__ __forceinline__ void adj_rows(const AdjParams<T>& p) {
     const bool actN = up && act && nxt.a > T(0);
     const bool actW = ic >= 1 && act && aw > T(0);
     const bool actE = ic + 1 < nx && act && ae > T(0);
-    T mu = cur.lh;
-    mu += (in && ob == obj_b) ? p.obj_coef * cur.h : T(0);
+    // fused form: eq. (23)'s lambda_h of this step at a ring cell (an
+    // active cell with a side on a region cell)
+    T pend = T(0);
+    if (p.pend_in) {
+      const bool ring = act && (prv.a < T(0) || nxt.a < T(0) || aw < T(0) || ae < T(0));
+      pend = ring ? ld(p.pend_in, ob) : T(0);
+    }
+    const T obj = (in && ob == obj_b) ? p.obj_coef * cur.h : T(0);
+    T mu = cur.lh + pend;
     // y profiles of this row and of its north edge (wave-uniform)
     Prof<T> py{T(1), T(1), T(0), T(1), T(1), T(0)};
     T ikyN = T(1), ayN = T(0);
@@ -392,15 +417,13 @@ __device__ __forceinline__ void adj_rows(const AdjParams<T>& p) {
       tW = cur.lpw - cbw * cur.ly;
       const T tN = nxt.lpe + cbn * nxt.lx;
       const T tE = lpwE - cbe * lye;
+      mu += obj;
       mu += actS ? cbs * py.ik_e * cur.lx + py.a_e * tS : T(0);
       mu -= actN ? cbn * ikyN * nxt.lx + ayN * tN : T(0);
       mu += actW ? -cbw * px.ik_e * cur.ly + px.a_e * tW : T(0);
       mu -= actE ? -cbe * ikxE * lye + axE * tE : T(0);
     } else {
-      mu += actS ? cbs * cur.lx : T(0);
-      mu -= actN ? cbn * nxt.lx : T(0);
-      mu -= actW ? cbw * cur.ly : T(0);
-      mu += actE ? cbe * lye : T(0);
+      mu = mu_plain(cur.lh, pend, obj, actS, cbs, cur.lx, actN, cbn, nxt.lx, actW, cbw, cur.ly, actE, cbe, lye);
     }
     mu = act ? mu : T(0);
     // adjoints handed to the E differences of the Hz update (layers)
@@ -492,24 +515,125 @@ __device__ __forceinline__ void adj_rows(const AdjParams<T>& p) {
 // layers every a is zero, so the entries other waves own stay zero and
 // are never weighted.
 template <typename T, int SEG, bool Layers>
-__global__ void __launch_bounds__(kBlock) adj_stream(const AdjParams<T> p) {
+__device__ __forceinline__ void adj_tile(const AdjParams<T>& p, int bx, int by) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int j0 = (blockIdx.y * (kBlock / kWave) + wv) * SEG;
+  const int j0 = (by * (kBlock / kWave) + wv) * SEG;
   if (j0 >= p.ny) return;
   if constexpr (!Layers) {
-    adj_rows<T, SEG, false>(p);
+    adj_rows<T, SEG, false>(p, bx, by);
   } else {
-    const int iw = blockIdx.x * kAdjOwned;
+    const int iw = bx * kAdjOwned;
     const int js = j0 > 0 ? j0 - 1 : 0;
     const int j1 = min(j0 + SEG, p.ny);
     const bool layer = (p.pml_xlo > 0 && iw - 2 < p.pml_xlo) ||
                        (p.pml_xhi > 0 && iw + kWave - 3 >= p.nx - p.pml_xhi) ||
                        (p.pml_ylo > 0 && js < p.pml_ylo) || (p.pml_yhi > 0 && j1 >= p.ny - p.pml_yhi);
     if (layer)
-      adj_rows<T, SEG, true>(p);
+      adj_rows<T, SEG, true>(p, bx, by);
     else
-      adj_rows<T, SEG, false>(p);
+      adj_rows<T, SEG, false>(p, bx, by);
   }
+}
+
+template <typename T, int SEG, bool Layers>
+__global__ void __launch_bounds__(kBlock) adj_stream(const AdjParams<T> p) {
+  adj_tile<T, SEG, Layers>(p, blockIdx.x, blockIdx.y);
+}
+
+// mu of an active cell at offset `off` as adj_rows forms it (no absorbing
+// layer reaches a ring cell): the adjoint of its Hz^{n+1/2} after the
+// coupling's and the E update's transposes, same terms in the same order
+template <typename T>
+__device__ __forceinline__ T ring_mu(const AdjParams<T>& p, int off) {
+  const int P = p.pitch;
+  const int j = off / P, i = off - j * P;
+  const T a = p.al[off], b = p.be[off];
+  if (!(a > T(0))) return T(0);
+  T ca, cS = T(0), cN = T(0), cW = T(0), cE = T(0), rcp;
+  const bool aS = j >= 1 && p.al[off - P] > T(0);          // south Ex(i, j)
+  const bool aN = j + 1 < p.ny && p.al[off + P] > T(0);    // north Ex(i, j+1)
+  const bool aW = i >= 1 && p.al[off - 1] > T(0);          // west Ey(i, j)
+  const bool aE = i + 1 < p.nx && p.al[off + 1] > T(0);    // east Ey(i+1, j)
+  if (aS) adj_coef(a + p.al[off - P], b + p.be[off - P], p.k2dy, ca, cS, rcp);
+  if (aN) adj_coef(p.al[off + P] + a, p.be[off + P] + b, p.k2dy, ca, cN, rcp);
+  if (aW) adj_coef(a + p.al[off - 1], b + p.be[off - 1], p.k2dx, ca, cW, rcp);
+  if (aE) adj_coef(p.al[off + 1] + a, p.be[off + 1] + b, p.k2dx, ca, cE, rcp);
+  const T obj = (off == p.obj_off) ? p.obj_coef * p.hz1[off] : T(0);
+  return mu_plain(p.lhz_in[off], p.pend_in[off], obj, aS, cS, aS ? p.lex_in[off] : T(0), aN, cN,
+                  aN ? p.lex_in[off + P] : T(0), aW, cW, aW ? p.ley_in[off] : T(0), aE, cE,
+                  aE ? p.ley_in[off + 1] : T(0));
+}
+
+// Fused form, coupling block: eq. (23)'s transpose for step n-1.  Its input
+// adjoint is [lambda_x^n; lambda_y^n]; lambda_y^n, the adjoint of E^n on the
+// interface edges, is what the stream of step n writes there:
+// +-chd * mu(ring cell) (S: chdy (mu - 0), N: chdy (0 - mu), W: chdx (0 - mu),
+// E: chdx (mu - 0), the other side's cell lying in the region), formed here
+// from step n's inputs with the stream's arithmetic.  lambda_h^{n-1} of each
+// port goes to pend_out at its ring cell (each ring cell serves one port).
+template <typename T>
+__device__ __forceinline__ void coupling_fused_block(const AdjParams<T>& p, int blk, T* z) {
+  const int tid = threadIdx.x;
+  const RowBlock rb = p.blocks[blk];
+  const RomDev r = p.roms[rb.a];
+  const T* lxin = p.lx_in + r.x_off;
+  T* lxout = p.lx_out + r.x_off;
+  const int* gi = p.idx + r.i_off;
+  const int lane = tid & (kWave - 1);
+  const int row0 = rb.b + (tid / kWave) * kRowsPerWave;
+  const T* GT = p.mats + r.gt_off + (size_t)row0 * r.ldg;
+  const int ni = r.n_ex / 2;
+  T acc[kRowsPerWave];
+#pragma unroll
+  for (int k = 0; k < kRowsPerWave; ++k) acc[k] = T(0);
+  auto stage = [&]() {
+    for (int c = tid; c < r.ldg; c += kBlock) {
+      T v = T(0);
+      if (c < r.q) {
+        v = lxin[c];
+      } else if (c < r.q + r.np) {
+        const int k = c - r.q;
+        const T mu = ring_mu(p, gi[k]);
+        if (k < ni) v = p.chdy * (mu - T(0));
+        else if (k < 2 * ni) v = p.chdy * (T(0) - mu);
+        else if (k < r.n_ex + (r.np - r.n_ex) / 2) v = p.chdx * (T(0) - mu);
+        else v = p.chdx * (mu - T(0));
+      }
+      z[c] = v;
+    }
+    lds_barrier();
+  };
+  lane_row_dots<T, kRowsPerWave>(GT, r.ldg, z, lane, acc, stage);
+#pragma unroll
+  for (int k = 0; k < kRowsPerWave; ++k)
+    for (int o = kWave / 2; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, kWave);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) {
+      const int row = row0 + k;
+      if (row < r.q)
+        lxout[row] = acc[k];
+      else if (row < r.q + r.np)
+        p.pend_out[gi[row - r.q]] = acc[k];
+    }
+  }
+}
+
+// Fused reverse step: workgroups [0, ncoup) are coupling blocks of step n-1
+// (first, so their chains start early), the rest the stream of step n
+// (tile (s % gx, s / gx) for workgroup ncoup + s).  The coupling blocks read
+// only step n's inputs and write lx_out and pend_out, which no stream
+// workgroup reads, so the two parts run side by side.
+template <typename T, int SEG, bool Layers>
+__global__ void __launch_bounds__(kBlock) adj_fused(const AdjParams<T> p, int ncoup, int gx) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x;
+  if (b < ncoup) {
+    coupling_fused_block(p, b, reinterpret_cast<T*>(smem));
+    return;
+  }
+  const int s = b - ncoup;
+  adj_tile<T, SEG, Layers>(p, s % gx, s / gx);
 }
 
 template <typename T>
@@ -524,6 +648,27 @@ hipError_t launch_adjoint_step(const AdjParams<T>& p, size_t smem, hipStream_t s
       case 4: hipLaunchKernelGGL((adj_stream<T, 4, Ly>), g, dim3(kBlock), 0, s, p); break;
       case 8: hipLaunchKernelGGL((adj_stream<T, 8, Ly>), g, dim3(kBlock), 0, s, p); break;
       case 16: hipLaunchKernelGGL((adj_stream<T, 16, Ly>), g, dim3(kBlock), 0, s, p); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  };
+  return p.pml ? go(std::true_type{}) : go(std::false_type{});
+}
+
+template <typename T>
+hipError_t launch_adjoint_fused(const AdjParams<T>& p, bool coupling, size_t smem, hipStream_t s) {
+  const int rows = (kBlock / kWave) * p.seg;
+  const int gx = (p.nx + kAdjOwned - 1) / kAdjOwned, gy = (p.ny + rows - 1) / rows;
+  const int ncoup = coupling ? p.nblocks : 0;
+  const dim3 g((unsigned)(ncoup + gx * gy));
+  const size_t lds = ncoup > 0 ? smem : 0;
+  auto go = [&](auto layers) -> hipError_t {
+    constexpr bool Ly = decltype(layers)::value;
+    switch (p.seg) {
+      case 2: hipLaunchKernelGGL((adj_fused<T, 2, Ly>), g, dim3(kBlock), lds, s, p, ncoup, gx); break;
+      case 4: hipLaunchKernelGGL((adj_fused<T, 4, Ly>), g, dim3(kBlock), lds, s, p, ncoup, gx); break;
+      case 8: hipLaunchKernelGGL((adj_fused<T, 8, Ly>), g, dim3(kBlock), lds, s, p, ncoup, gx); break;
+      case 16: hipLaunchKernelGGL((adj_fused<T, 16, Ly>), g, dim3(kBlock), lds, s, p, ncoup, gx); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -546,5 +691,7 @@ hipError_t launch_adjoint_flush(float* a, double* g, size_t n, hipStream_t s) {
 
 template hipError_t launch_adjoint_step<float>(const AdjParams<float>&, size_t, hipStream_t);
 template hipError_t launch_adjoint_step<double>(const AdjParams<double>&, size_t, hipStream_t);
+template hipError_t launch_adjoint_fused<float>(const AdjParams<float>&, bool, size_t, hipStream_t);
+template hipError_t launch_adjoint_fused<double>(const AdjParams<double>&, bool, size_t, hipStream_t);
 
 }  // namespace fdtd

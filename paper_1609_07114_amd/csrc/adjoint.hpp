@@ -65,10 +65,24 @@ struct AdjParams {
   double* dgt;
   const int64_t* dg_off;
   const T* xn;
+  // fused reverse step (launch_adjoint_fused): lambda_h of eq. (23)'s
+  // transpose kept per ring cell in a field-shaped array instead of being
+  // added into lhz_in - pend_in holds this step's (added at ring cells by
+  // the stream), pend_out receives the step before's (written by the
+  // coupling blocks of the same launch); null in the two-launch form
+  const T* pend_in;
+  T* pend_out;
 };
 
 template <typename T>
 hipError_t launch_adjoint_step(const AdjParams<T>& p, size_t smem, hipStream_t s);
+// One launch per reverse step: the stream of step n (lambda_h of step n in
+// pend_in) and, when `coupling`, eq. (23)'s transpose of step n-1, whose
+// input adjoint y^n on the interface edges it forms from step n's inputs
+// exactly as the stream forms it (lx_in: lambda_x^n, lx_out: lambda_x^{n-1},
+// pend_out: lambda_h^{n-1}).  No model-gradient accumulation (dgt null).
+template <typename T>
+hipError_t launch_adjoint_fused(const AdjParams<T>& p, bool coupling, size_t smem, hipStream_t s);
 // g[k] += a[k], a[k] = 0 for k < n (both accumulator pairs: a, g hold 2n)
 hipError_t launch_adjoint_flush(float* a, double* g, size_t n, hipStream_t s);
 

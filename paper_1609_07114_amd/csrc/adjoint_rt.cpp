@@ -39,7 +39,7 @@ struct AdjLayout {
   size_t slot_bytes = 0, lam_bytes = 0, ck_psi = 0;  // per slot / adjoint set; checkpoint's psi offset
   size_t off_ctrl = 0, off_ckpt = 0, ck_stride = 0, off_slots = 0, off_xrec = 0, off_psih = 0;
   size_t off_lam = 0, off_lx = 0, off_g = 0, off_gseg = 0, off_gt = 0, off_roms = 0, off_j = 0;
-  size_t off_rtab = 0, off_dgoff = 0, off_dg = 0, total = 0;
+  size_t off_rtab = 0, off_dgoff = 0, off_dg = 0, off_pend = 0, pend_bytes = 0, total = 0;
   size_t gt_elems = 0;
   size_t img = 0;        // elements per image of reduced states (one per step of a segment)
   bool models = false;   // gradients through the models: dJ/dG accumulators
@@ -100,7 +100,12 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
   A.off_lam = o;
   o = align_up(o + 2 * A.lam_bytes, 256);
   A.off_lx = o;
-  o += 2 * A.xs_bytes;
+  o = align_up(o + 2 * A.xs_bytes, 256);
+  // fused reverse steps (all but the sweep through the models): lambda_h of
+  // eq. (23)'s transpose per ring cell, two field-shaped arrays (ping-pong)
+  A.off_pend = o;
+  A.pend_bytes = models ? 0 : 2 * fb;
+  o = align_up(o + A.pend_bytes, 256);
   A.off_g = o;
   o = align_up(o + 2 * L.field_elems * sizeof(double), 256);
   A.off_gseg = o;  // FP32 runs: per-segment accumulators in FP32
@@ -132,6 +137,7 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
       {A.off_psih, L.pml ? 4 * fb : 0},
       {A.off_lam, 2 * A.lam_bytes},
       {A.off_lx, 2 * A.xs_bytes},
+      {A.off_pend, A.pend_bytes},
       {A.off_g, 2 * L.field_elems * sizeof(double)},
       {A.off_gseg, ts == 4 ? 2 * L.field_elems * ts : 0},
       {A.off_gt, A.gt_elems * ts},
@@ -462,6 +468,7 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   ap.py = sp.py;
   T* lam[2] = {(T*)(aw + A.off_lam), (T*)(aw + A.off_lam + A.lam_bytes)};
   T* lx[2] = {(T*)(aw + A.off_lx), (T*)(aw + A.off_lx + A.xs_bytes)};
+  T* pend[2] = {(T*)(aw + A.off_pend), (T*)(aw + A.off_pend + fb)};
   int cur = 0;
   for (int c = A.nck - 1; c >= 0; --c) {
     const int m0 = c * A.K;
@@ -525,7 +532,18 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
         ap.pex1 = psi_e(k + 1);
         ap.pey1 = psi_e(k + 1) + fe;
       }
-      if (launch_adjoint_step<T>(ap, L.smem_gemv, st) != hipSuccess) return dev_err("adjoint launch");
+      if (A.models) {
+        // two launches: eq. (23)'s transpose of step m (accumulating dJ/dG
+        // with this segment's x~^m), then the stream
+        if (launch_adjoint_step<T>(ap, L.smem_gemv, st) != hipSuccess) return dev_err("adjoint launch");
+      } else {
+        // one launch: the stream of step m with lambda_h^m from the launch
+        // before, and eq. (23)'s transpose of step m-1 (none for m = 0)
+        ap.pend_in = pend[cur];
+        ap.pend_out = pend[cur ^ 1];
+        if (launch_adjoint_fused<T>(ap, m0 + k >= 1, L.smem_gemv, st) != hipSuccess)
+          return dev_err("adjoint launch");
+      }
       cur ^= 1;
     }
     if constexpr (kSeg) {
