@@ -1,13 +1,18 @@
-// Host orchestration of the reverse sweep (fdtd_rom_adjoint).
+// Host orchestration of the reverse sweep (fdtd_rom_adjoint,
+// fdtd_rom_adjoint_models, fdtd_rom_adjoint_noalloc).
 //
 // Forward: the handle runs nsteps as usual; before every segment of
 // ckpt_every steps its current field set and reduced states are copied to a
 // checkpoint.  Reverse, one segment at a time from the last: the segment's
 // forward states are recomputed from its checkpoint with the step kernel
-// writing each step's output into its own slot (nothing overwritten, no
-// probe record, a private step counter), then the adjoint steps run from the
-// segment's end back to its start, each reading E^n (slot n) and
-// Hz^{n+1/2} (slot n+1).  Peak memory: checkpoints + one segment.
+// writing each step's output into its own slot and its reduced states into
+// its own image (nothing overwritten, no probe record, a private step
+// counter), then the adjoint steps run from the segment's end back to its
+// start, each reading E^n (slot n) and Hz^{n+1/2} (slot n+1).  A reverse
+// step is one launch (the stream of step n beside eq. (23)'s transpose of
+// step n-1); the sweep through the models keeps two launches per step, the
+// transpose accumulating dJ/dG with x~^n of the segment's images.  Peak
+// memory: checkpoints + one segment.
 //
 // Absorbing layers add the auxiliary fields: a checkpoint also holds the
 // four of its step, a slot also the two at Ex and Ey (the reverse step
