@@ -439,7 +439,7 @@ def bench_hbm_resident(n=8192, steps=400, warmup=52, log=None):
 def bench_adjoint(ckpt=200, log=None):
     import numpy as np
     import workloads as W
-    from paper_1609_07114_amd import romgen
+    from paper_1609_07114_amd import capi, romgen
     from paper_1609_07114_amd.sim import Simulation
     prob = W.adjoint_c5()
     roms = romgen.build_roms(prob)
@@ -460,6 +460,17 @@ def bench_adjoint(ckpt=200, log=None):
         res = {}
         t_a, _ = _timed(s.stream, lambda: res.setdefault("r", s.adjoint(n, ckpt_every=ckpt)))
         J32, ge32, gs32 = res["r"]
+    # every forward state resident in HBM: one segment of n steps, so the
+    # recompute is the only forward (12.6 MB per FP32 step, ~50 GB at 4000
+    # steps of the 288 GB); an untimed call first leaves the workspace in
+    # torch's cache
+    for _ in range(2):
+        with Simulation(prob, roms) as s:
+            s.set_graph(100)
+            res = {}
+            t_r, _ = _timed(s.stream, lambda: res.setdefault("r", s.adjoint(n, ckpt_every=n)))
+            ws_all = capi.fdtd_rom_adjoint_workspace_size(s.h, n, n)
+    same = bool(np.array_equal(res["r"][1], ge32) and np.array_equal(res["r"][2], gs32))
     with Simulation(prob, roms, dtype="f64") as s:
         J64, ge64, gs64 = s.adjoint(n, ckpt_every=ckpt)
     # the same sweep with the gradients through the models: dJ/dG summed on
@@ -489,6 +500,9 @@ def bench_adjoint(ckpt=200, log=None):
             "value": round(cells * n / t_a / 1e6, 1), "unit": "Mcell-updates/s (forward+reverse)",
             "J_rel_err_vs_f64": abs(J32 - J64) / abs(J64),
             "grad_eps_rel_l2_vs_f64": rel(ge32, ge64), "grad_sigma_rel_l2_vs_f64": rel(gs32, gs64),
+            "all_states_resident": {"ckpt_every": n, "workspace_GB": round(ws_all / 1e9, 1),
+                                    "adjoint_s": round(t_r, 4), "ratio_vs_forward": round(t_r / t_f, 2),
+                                    "gradients_identical_to_checkpointed": same},
             "through_models": {"adjoint_models_s": round(t_m, 4),
                                "build_vjp_host_s": round(t_b, 4),
                                "build_vjp_note": "host FP64, regions in parallel threads; each rebuilds its model",
@@ -756,7 +770,8 @@ def main():
         out["hbm_resident"] = bench_hbm_resident(log=log)
         log(f"hbm-resident 8192^2: {out['hbm_resident']['roofline']['achieved']:.0f} GB/s")
         out["adjoint"] = bench_adjoint(log=log)
-        log(f"adjoint {out['adjoint']['ratio_vs_forward']}x forward")
+        log(f"adjoint {out['adjoint']['ratio_vs_forward']}x forward, every state resident "
+            f"{out['adjoint']['all_states_resident']['ratio_vs_forward']}x")
         out["waveguides"] = bench_waveguides(log=log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)

@@ -144,6 +144,69 @@ hipError_t launch_states_to_image(const T* src, T* dst, const RomDev* roms, int 
   return hipGetLastError();
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kBlock) image_to_states(const T* __restrict__ src, T* __restrict__ dst,
+                                                        const RomDev* __restrict__ roms, int par) {
+  const RomDev r = roms[blockIdx.x];
+  for (int a = threadIdx.x; a < r.q; a += kBlock) dst[r.x_off + par * r.xstride + a] = src[r.x_off + a];
+}
+
+template <typename T>
+hipError_t launch_image_to_states(const T* src, T* dst, const RomDev* roms, int nroms, int par, hipStream_t s) {
+  if (nroms <= 0) return hipSuccess;
+  hipLaunchKernelGGL((image_to_states<T>), dim3(nroms), dim3(kBlock), 0, s, src, dst, roms, par);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) slots_to_probes(const T* __restrict__ slot0, size_t stride, size_t fe,
+                                                        int len, int nprobes, const int* __restrict__ off,
+                                                        const int* __restrict__ comp, T* __restrict__ buf, int m0) {
+  const size_t n = (size_t)len * nprobes;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+    const size_t k = e / nprobes, t = e - k * nprobes;
+    buf[((size_t)m0 + k) * nprobes + t] = slot0[k * stride + (size_t)comp[t] * fe + off[t]];
+  }
+}
+
+template <typename T>
+hipError_t launch_slots_to_probes(const T* slot0, size_t stride, size_t fe, int len, int nprobes, const int* off,
+                                  const int* comp, T* buf, int m0, hipStream_t s) {
+  const size_t n = (size_t)len * nprobes;
+  if (n == 0) return hipSuccess;
+  const unsigned nb = (unsigned)std::min<size_t>((n + kBlock - 1) / kBlock, 1024);
+  hipLaunchKernelGGL((slots_to_probes<T>), dim3(nb), dim3(kBlock), 0, s, slot0, stride, fe, len, nprobes, off, comp,
+                     buf, m0);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) zero_padding(T* __restrict__ base, size_t count, int ny, int pitch, int nx) {
+  const int w = pitch - nx;
+  const size_t n = count * (size_t)ny * w;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+    const size_t row = e / w;  // row over all arrays
+    base[row * pitch + nx + (e - row * w)] = T(0);
+  }
+}
+
+template <typename T>
+hipError_t launch_zero_padding(T* base, size_t count, int ny, int pitch, int nx, hipStream_t s) {
+  const size_t n = count * (size_t)ny * (size_t)(pitch - nx);
+  if (n == 0) return hipSuccess;
+  const unsigned nb = (unsigned)std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL((zero_padding<T>), dim3(nb), dim3(kBlock), 0, s, base, count, ny, pitch, nx);
+  return hipGetLastError();
+}
+
+template hipError_t launch_zero_padding<float>(float*, size_t, int, int, int, hipStream_t);
+template hipError_t launch_zero_padding<double>(double*, size_t, int, int, int, hipStream_t);
+template hipError_t launch_image_to_states<float>(const float*, float*, const RomDev*, int, int, hipStream_t);
+template hipError_t launch_image_to_states<double>(const double*, double*, const RomDev*, int, int, hipStream_t);
+template hipError_t launch_slots_to_probes<float>(const float*, size_t, size_t, int, int, const int*, const int*,
+                                                  float*, int, hipStream_t);
+template hipError_t launch_slots_to_probes<double>(const double*, size_t, size_t, int, int, const int*, const int*,
+                                                   double*, int, hipStream_t);
 template hipError_t launch_states_to_image<float>(const float*, float*, const RomDev*, int, int, hipStream_t);
 template hipError_t launch_states_to_image<double>(const double*, double*, const RomDev*, int, int, hipStream_t);
 template hipError_t launch_transpose_block<float>(const float*, float*, int, int, hipStream_t);

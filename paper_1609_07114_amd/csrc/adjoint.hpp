@@ -106,6 +106,10 @@ hipError_t launch_probe_energy(const T* buf, int nprobes, int probe, int n, doub
                                hipStream_t s);
 // Zero `bytes` bytes at p (both multiples of 16).
 hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s);
+// Zero the padding columns [nx, pitch) of `count` consecutive field-shaped
+// arrays (ny rows of pitch elements each) starting at base.
+template <typename T>
+hipError_t launch_zero_padding(T* base, size_t count, int ny, int pitch, int nx, hipStream_t s);
 
 // Forward reduced states kept per step while a segment is recomputed: the
 // image of step k holds every region's x~ at its x_off (the parity-0 place
@@ -119,5 +123,15 @@ hipError_t launch_rom_xstride(RomDev* out, const RomDev* in, int nroms, int64_t 
 // a checkpoint's states into the parity-0 places of an image.
 template <typename T>
 hipError_t launch_states_to_image(const T* src, T* dst, const RomDev* roms, int nroms, int par, hipStream_t s);
+// The reverse: dst[x_off + par * xstride + a] = src[x_off + a].
+template <typename T>
+hipError_t launch_image_to_states(const T* src, T* dst, const RomDev* roms, int nroms, int par, hipStream_t s);
+// Probe record rows [m0, m0 + len) from recomputed slots (slot k holds the
+// state after step m0 + k, fields Hz, Ex, Ey of fe elements each, slots
+// `stride` elements apart): buf[(m0 + k) * nprobes + t] = field
+// comp[t] of slot k at off[t].
+template <typename T>
+hipError_t launch_slots_to_probes(const T* slot0, size_t stride, size_t fe, int len, int nprobes, const int* off,
+                                  const int* comp, T* buf, int m0, hipStream_t s);
 
 }  // namespace fdtd

@@ -298,10 +298,12 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
     return fail(FDTD_EDEVICE, "%s failed: %s", what, hipGetErrorString(hipGetLastError()));
   };
   if (noalloc) {
-    // clear the control block and everything from the slots to G^T, as the
-    // host path below does with hipMemsetAsync
+    // clear the control block, everything from the recompute's psi at Hz to
+    // G^T and the slots' padding columns, as the host path below does
     if (launch_zero_fill(aw + A.off_ctrl, align_up(kCtrlInts * sizeof(int), 16), st) != hipSuccess ||
-        launch_zero_fill(aw + A.off_slots, A.off_gt - A.off_slots, st) != hipSuccess)
+        launch_zero_fill(aw + A.off_psih, A.off_gt - A.off_psih, st) != hipSuccess ||
+        launch_zero_padding<T>((T*)(aw + A.off_slots), (size_t)A.K * (A.slot_bytes / (fe * sizeof(T))), s->ny,
+                               s->pitch, s->nx, st) != hipSuccess)
       return dev_err("scratch clear");
     const T* mats = (const T*)(ws + L.off_mats);
     T* gt = (T*)(aw + A.off_gt);
@@ -357,10 +359,16 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
                                         hipMemcpyHostToDevice, st) != hipSuccess) ||
         hipStreamSynchronize(st) != hipSuccess)
       return dev_err("model upload");
-    // zero the private step counter, slots, adjoint fields, states, gradients
+    // zero the private step counter; the recompute's psi at Hz (only waves
+    // that reach a layer write it, the rest of it must read zero), the
+    // adjoint fields, states and gradients; and the slots' padding columns
+    // (the stencil reads them unguarded and never writes them - every other
+    // sample of a slot is written by its recompute step before it is read)
     if (hipMemsetAsync(aw + A.off_ctrl, 0, kCtrlInts * sizeof(int), st) != hipSuccess ||
-        hipMemsetAsync(aw + A.off_slots, 0, A.off_gt - A.off_slots, st) != hipSuccess)
-      return dev_err("hipMemsetAsync");
+        hipMemsetAsync(aw + A.off_psih, 0, A.off_gt - A.off_psih, st) != hipSuccess ||
+        launch_zero_padding<T>((T*)(aw + A.off_slots), (size_t)A.K * (A.slot_bytes / (fe * sizeof(T))), s->ny,
+                               s->pitch, s->nx, st) != hipSuccess)
+      return dev_err("workspace clear");
     if (A.models && s->nroms > 0) {
       std::vector<int64_t> dgo(s->nroms);
       for (int k = 0; k < s->nroms; ++k) dgo[k] = (int64_t)region_dg(s, k);
@@ -390,7 +398,8 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   const size_t fb = fe * sizeof(T);
   const StepParams<T>& sp = step_params<T>(s);
 
-  // forward with checkpoints
+  // forward with checkpoints; the last segment's steps are not taken here:
+  // its recompute takes them and hands the handle the result
   for (int c = 0; c < A.nck; ++c) {
     const int m0 = c * A.K;
     const int len = std::min(A.K, N - m0);
@@ -404,22 +413,24 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
         if (hipMemcpyAsync(ckpt_psi(c) + k * fe, src[k], fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
           return dev_err("checkpoint copy");
     }
+    if (c == A.nck - 1) break;
     const int rc = noalloc ? run_direct_any(s, len) : run_steps_any(s, len);
     if (rc != FDTD_OK) return rc;
   }
 
-  // objective from the probe record
-  if (noalloc) {
-    double* jd = (double*)(aw + A.off_j);
-    if (launch_probe_energy<T>((const T*)(ws + L.off_pbuf), s->nprobes, probe, N, s->dt, jd, st) != hipSuccess ||
-        hipMemcpyAsync(J, jd, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-      return dev_err("objective");
-    if (!std::isfinite(*J)) return fail(FDTD_EUNSTABLE, "non-finite objective");
-  } else {
-    const int rc = fdtd_rom_probe_objective(s, probe, 0, N, J);
-    if (rc != FDTD_OK) return rc;
-  }
+  // objective from the probe record (once the last segment has filled it)
+  auto objective = [&]() -> int {
+    if (noalloc) {
+      double* jd = (double*)(aw + A.off_j);
+      if (launch_probe_energy<T>((const T*)(ws + L.off_pbuf), s->nprobes, probe, N, s->dt, jd, st) != hipSuccess ||
+          hipMemcpyAsync(J, jd, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return dev_err("objective");
+      if (!std::isfinite(*J)) return fail(FDTD_EUNSTABLE, "non-finite objective");
+      return FDTD_OK;
+    }
+    return fdtd_rom_probe_objective(s, probe, 0, N, J);
+  };
 
   // reverse sweep
   StepParams<T> rp = step_params<T>(s);
@@ -513,6 +524,31 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
       rp.xs = par ? image(k + 1) : image(k);
       if (const int rc = check_recompute<T>(rp, par, aw, A, fe, s->nroms); rc != FDTD_OK) return rc;
       if (launch_step<T>(rp, s->seg, s->smem, st) != hipSuccess) return dev_err("recompute launch");
+    }
+    if (c == A.nck - 1) {
+      // the forward stopped at m0: the handle takes the recomputed state
+      // after step N (fields into its set for N, reduced states into their
+      // parity-N places, with layers the auxiliary fields), the segment's
+      // probe rows and the step count, as if it had run the steps
+      const int dst = (N & 1) ^ s->flip;
+      if (hipMemcpyAsync(ws + L.off_fields + (size_t)dst * A.set_bytes, state(len), A.set_bytes,
+                         hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          launch_image_to_states<T>(image(len), (T*)(ws + L.off_xs), hroms, s->nroms, N & 1, st) != hipSuccess)
+        return dev_err("handing over the last segment");
+      if (L.pml) {
+        const T* ph = psih + (size_t)(N & 1) * 2 * fe;
+        if (hipMemcpyAsync(sp.psi_h[N & 1][0], ph, fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(sp.psi_h[N & 1][1], ph + fe, fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(sp.psi_ex, psi_e(len), fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(sp.psi_ey, psi_e(len) + fe, fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+          return dev_err("handing over the last segment");
+      }
+      if (launch_slots_to_probes<T>(state(1), A.slot_bytes / sizeof(T), fe, len, s->nprobes, sp.probe_off,
+                                    sp.probe_comp, sp.probe_buf, m0, st) != hipSuccess ||
+          launch_tick(sp.ctrl, len, st) != hipSuccess)
+        return dev_err("handing over the last segment");
+      s->steps = N;
+      if (const int rc = objective(); rc != FDTD_OK) return rc;
     }
     for (int k = len - 1; k >= 0; --k) {
       T* li = lam[cur];

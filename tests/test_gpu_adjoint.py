@@ -216,3 +216,31 @@ def test_host_plan_equals_handle_workspace_size():
             plan = capi.fdtd_rom_adjoint_plan(capi.ProblemStruct.from_workload(p, roms), p.nsteps, K)
             with Simulation(p, roms) as s:
                 assert capi.fdtd_rom_adjoint_workspace_size(s.h, p.nsteps, K) == plan
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ckpt", [0, 7, 250])
+def test_handle_after_adjoint_stands_at_nsteps(dtype, ckpt):
+    """The forward stops at the last checkpoint and the last segment's
+    recompute hands the handle its state: afterwards the probe record, the
+    fields and the reduced states equal those of a plain run, bit for bit,
+    and the handle runs on exactly as that run does."""
+    n, more = 250, 40
+    p = W.random_problem(31, 30, 26, n + more, nroms=1, block=(5, 4), r=2, q=12,
+                         dt_frac_coarse=0.9, f_bw=3e9)
+    roms = osim.build_roms(p)
+    with Simulation(p, roms, max_steps=n + more, dtype=dtype) as s:
+        s.adjoint(n, ckpt_every=ckpt)
+        a = (s.probes(0, n), [s.field(c) for c in range(3)], s.rom_state(0))
+        s.run(more)
+        a2 = (s.probes(n, more), [s.field(c) for c in range(3)])
+    with Simulation(p, roms, max_steps=n + more, dtype=dtype) as s:
+        s.run(n)
+        b = (s.probes(0, n), [s.field(c) for c in range(3)], s.rom_state(0))
+        s.run(more)
+        b2 = (s.probes(n, more), [s.field(c) for c in range(3)])
+    assert np.array_equal(a[0], b[0])
+    for c in range(3):
+        assert np.array_equal(a[1][c], b[1][c]) and np.array_equal(a2[1][c], b2[1][c]), c
+    assert np.array_equal(a[2], b[2])
+    assert np.array_equal(a2[0], b2[0])

@@ -138,3 +138,25 @@ def test_layered_adjoint_vs_gpu_finite_differences():
             getattr(pm, name)[j, i] -= h
             fd = (_gpu_J(pp, roms) - _gpu_J(pm, roms)) / (2 * h)
             assert g[j, i] == pytest.approx(fd, rel=2e-6, abs=1e-6 * np.abs(g).max()), (name, i, j)
+
+
+@pytest.mark.parametrize("ckpt", [0, 7])
+def test_layered_handle_after_adjoint_runs_on_like_a_plain_run(ckpt):
+    """With layers the last segment's recompute also hands the handle the
+    auxiliary fields: afterwards the handle's probes and fields, and the
+    steps it then takes, equal a plain run's bit for bit."""
+    n, more = 300, 30
+    p = W.random_problem(41, 150, 140, n + more, nroms=2, block=(5, 4), r=2, q=10,
+                         dt_frac_coarse=0.9, f_bw=3e9)
+    p = _with_layers(p, (10, 10, 8, 8), (144, 118), kappa_max=3.0, alpha_max=0.03)
+    roms = osim.build_roms(p)
+    with Simulation(p, roms, max_steps=n + more, dtype="f64") as s:
+        s.adjoint(n, ckpt_every=ckpt)
+        s.run(more)
+        a = (s.probes(0, n + more), [s.field(c) for c in range(3)])
+    with Simulation(p, roms, max_steps=n + more, dtype="f64") as s:
+        s.run(n + more)
+        b = (s.probes(0, n + more), [s.field(c) for c in range(3)])
+    assert np.array_equal(a[0], b[0])
+    for c in range(3):
+        assert np.array_equal(a[1][c], b[1][c]), c
