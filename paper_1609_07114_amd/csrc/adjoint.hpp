@@ -27,8 +27,8 @@ struct AdjParams {
   const T* be;       // per-cell sigma/2
   // dJ/deps_r and dJ/dsigma accumulators per cell (pitch layout) in the
   // run's precision: the FP64 totals themselves in FP64 runs; in FP32 runs
-  // per-segment sums, folded into the FP64 totals after every checkpoint
-  // segment (adj_flush)
+  // sums over at most 128 steps, folded into the FP64 totals at every
+  // multiple of 128 steps and at every checkpoint (adj_flush)
   T* ga_e;
   T* ga_s;
   int nx, ny, pitch;

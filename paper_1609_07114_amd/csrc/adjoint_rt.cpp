@@ -440,7 +440,11 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   ap.al = sp.al;
   ap.be = sp.be;
   double* g64 = (double*)(aw + A.off_g);
-  constexpr bool kSeg = sizeof(T) == 4;  // FP32: segment sums, folded into g64 per segment
+  // FP32: the gradients are summed in FP32 over at most kFoldSteps steps
+  // (folded into g64 at every multiple of kFoldSteps and at every
+  // checkpoint), so their rounding does not grow with the checkpoint interval
+  constexpr bool kSeg = sizeof(T) == 4;
+  constexpr int kFoldSteps = 128;
   if constexpr (kSeg) {
     ap.ga_e = (T*)(aw + A.off_gseg);
   } else {
@@ -586,9 +590,11 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
           return dev_err("adjoint launch");
       }
       cur ^= 1;
-    }
-    if constexpr (kSeg) {
-      if (launch_adjoint_flush((float*)ap.ga_e, g64, 2 * fe, st) != hipSuccess) return dev_err("gradient flush");
+      if constexpr (kSeg) {
+        if ((k == 0 || (m0 + k) % kFoldSteps == 0) &&
+            launch_adjoint_flush((float*)ap.ga_e, g64, 2 * fe, st) != hipSuccess)
+          return dev_err("gradient flush");
+      }
     }
   }
   // gradients: pitch layout -> natural, zero on regions and their rings and

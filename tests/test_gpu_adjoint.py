@@ -159,6 +159,22 @@ def test_c5_scaled_vs_oracle(c5_small, dtype, tol):
     _compare(_gpu_adj(p, roms, dtype=dtype, ckpt=50), o, tol)
 
 
+@pytest.mark.parametrize("ckpt", [256, 600])
+def test_fp32_gradients_fold_every_128_steps(c5_small, ckpt):
+    """FP32 runs sum the gradients in FP32 over at most 128 steps, folding
+    them into FP64 at multiples of 128 steps and at every checkpoint:
+    intervals that are multiples of 128, or one segment over the whole run
+    (every state resident), fold at the same steps and agree bit for bit;
+    the one-segment sweep also holds the oracle bar."""
+    p, roms = c5_small
+    ref = _gpu_adj(p, roms, dtype="f32", ckpt=128)
+    got = _gpu_adj(p, roms, dtype="f32", ckpt=ckpt)
+    assert got[0] == ref[0]
+    assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
+    if ckpt == p.nsteps:
+        _compare(got, oadj.adjoint_gradient(p, roms, fp32=True), TOL32)
+
+
 @pytest.fixture(scope="module")
 def c5_full():
     """The full adjoint workload: 1024^2, four q=64 models (product
