@@ -334,8 +334,14 @@ template <typename T, bool PML>
 __device__ __forceinline__ AdjRow<T> adj_load(const AdjParams<T>& p, uint32_t ob, bool ok) {
   const uint32_t o = ok ? ob : 0u;
   AdjRow<T> r{};
-  r.a = ld(p.al, o);
-  r.b = ld(p.be, o);
+  if (p.midx) {
+    const MatPair<T> m = p.mt[ld(p.mi, o / (uint32_t)(sizeof(T) / sizeof(uint16_t)))];
+    r.a = m.a;
+    r.b = m.b;
+  } else {
+    r.a = ld(p.al, o);
+    r.b = ld(p.be, o);
+  }
   r.h = ld(p.hz1, o);
   r.lx = ld(p.lex_in, o);
   r.e = ld(p.ex0, o);

@@ -25,6 +25,12 @@ struct AdjParams {
   const T* ey0;
   const T* al;       // per-cell eps0*eps_r/dt (negative inside regions)
   const T* be;       // per-cell sigma/2
+  // the same pairs as a 16-bit index per cell into a table of (a, b), when
+  // the handle has one (midx = 1): the streamed reverse step then reads 2 B
+  // of material per cell instead of 2 x sizeof(T)
+  const uint16_t* mi;
+  const MatPair<T>* mt;
+  int midx;
   // dJ/deps_r and dJ/dsigma accumulators per cell (pitch layout) in the
   // run's precision: the FP64 totals themselves in FP64 runs; in FP32 runs
   // sums over at most 128 steps, folded into the FP64 totals at every

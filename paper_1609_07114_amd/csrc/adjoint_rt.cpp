@@ -439,6 +439,9 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   AdjParams<T> ap{};
   ap.al = sp.al;
   ap.be = sp.be;
+  ap.mi = sp.mi;
+  ap.mt = sp.mt;
+  ap.midx = sp.midx;
   double* g64 = (double*)(aw + A.off_g);
   // FP32: the gradients are summed in FP32 over at most kFoldSteps steps
   // (folded into g64 at every multiple of kFoldSteps and at every

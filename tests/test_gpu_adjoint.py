@@ -92,6 +92,22 @@ def test_checkpoint_interval_does_not_change_result(small, ckpt):
     assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_material_table_and_per_cell_arrays_agree(small, dtype):
+    """The reverse step reads the material through the handle's 16-bit
+    table when it has one, else the per-cell arrays: the same values, so
+    the same gradient bit for bit."""
+    p, roms = small
+    out = []
+    for mode in (1, 0):
+        with Simulation(p, roms, max_steps=p.nsteps, dtype=dtype) as s:
+            assert s.material_mode()[1] > 0
+            s.set_material_mode(mode)
+            out.append(s.adjoint(p.nsteps, ckpt_every=60))
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+
+
 def test_adjoint_shared_model_gemm_fp32():
     """FP32 run whose regions share one model (MFMA GEMM forward): the
     recomputed forward takes the same path, gradient against the oracle."""
