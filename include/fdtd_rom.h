@@ -429,16 +429,22 @@ int fdtd_rom_get_pair_split(const fdtd_rom_sim* sim, int32_t* percent);
  * fdtd_rom_adjoint_workspace_size: device bytes the sweep needs for nsteps
  * with a checkpoint every ckpt_every steps (0 selects ceil(sqrt(nsteps))):
  * ceil(nsteps/ckpt_every) checkpoints of the fields and reduced states,
- * ckpt_every recomputed field sets, two adjoint field sets, the adjoint
- * reduced states, two FP64 per-cell accumulators and G^T of every model.
+ * ckpt_every recomputed field sets (twice that with two or more segments:
+ * the next segment's recompute fills the second set beside the reverse
+ * steps of the current one), two adjoint field sets, the adjoint reduced
+ * states, two FP64 per-cell accumulators and G^T of every model.
  * With absorbing layers a checkpoint also holds the four auxiliary fields,
  * a recomputed set the two at Ex and Ey, an adjoint set the adjoints of
  * all four (plus one private pair of the two at Hz).
  *
  * fdtd_rom_adjoint: runs the forward from the handle's initial state (the
  * handle must have taken no step; FDTD_ESTATE otherwise), keeping
- * checkpoints, then sweeps back one segment at a time, recomputing each
- * segment's forward states from its checkpoint.  Inside absorbing layers
+ * checkpoints up to the last one, then sweeps back one segment at a time,
+ * recomputing each segment's forward states from its checkpoint; the
+ * recompute of the segment below runs on a second stream of the device
+ * (default priority, created and destroyed by the call) while the reverse
+ * steps of the current one run on the handle's stream, ordered by events.
+ * Inside absorbing layers
  * the sweep transposes the auxiliary-field recursions as well, so the
  * gradient is that of the layered run (no material gradient of the layer
  * profiles themselves, which are fixed by fdtd_pml).  Afterwards the handle
@@ -504,8 +510,10 @@ int fdtd_rom_adjoint_models(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_ever
  * runs as plain launches without graph capture or finiteness checks, the
  * objective is summed on the device).  Arguments, the handle's state
  * afterwards and the results are those of fdtd_rom_adjoint (J summed in a
- * different order: equal to rounding).  FDTD_ENOMEM if the sweep needs more
- * than the 64 MiB (fdtd_rom_adjoint_workspace_size gives the need).  Call
+ * different order: equal to rounding).  The recompute runs on the handle's
+ * stream between the reverse segments (no second stream, one set of
+ * recomputed fields), so the need is at most
+ * fdtd_rom_adjoint_workspace_size's; FDTD_ENOMEM if it exceeds the 64 MiB.  Call
  * with the handle's device current.  Every call on a GPU shares that GPU's
  * array and leaves its contents behind (each call clears what must start at
  * zero): calls that overlap on one GPU, from several threads or streams,

@@ -40,6 +40,11 @@ namespace {
 // no-allocation entry point plans it too).
 struct AdjLayout {
   int K = 0, nck = 0;
+  // buffer sets of recomputed slots and images: 2 when the recompute of
+  // the segment below runs on a second stream beside the reverse steps of
+  // this one (at least two segments, not the no-allocation entry), else 1
+  int nbuf = 1;
+  size_t slots_stride = 0, xrec_stride = 0;  // bytes per buffer set
   size_t set_bytes = 0, xs_bytes = 0;
   size_t slot_bytes = 0, lam_bytes = 0, ck_psi = 0;  // per slot / adjoint set; checkpoint's psi offset
   size_t off_ctrl = 0, off_ckpt = 0, ck_stride = 0, off_slots = 0, off_xrec = 0, off_psih = 0;
@@ -72,7 +77,8 @@ size_t slot_gt(const fdtd_rom_sim* s, size_t sl) {
   return ge;
 }
 
-int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A, bool models = false) {
+int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A, bool models = false,
+                 bool pipelined = true) {
   if (nsteps < 1 || nsteps > s->max_steps)
     return fail(FDTD_EINVAL, "nsteps=%d outside [1, max_steps=%d]", nsteps, s->max_steps);
   if (ckpt_every < 0 || ckpt_every > nsteps)
@@ -80,6 +86,7 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
   const Layout& L = s->L;
   A.K = ckpt_every > 0 ? ckpt_every : (int)std::ceil(std::sqrt((double)nsteps));
   A.nck = (nsteps + A.K - 1) / A.K;
+  A.nbuf = pipelined && A.nck >= 2 ? 2 : 1;
   const size_t ts = L.tsize;
   const size_t fb = L.field_elems * ts;
   A.set_bytes = 3 * fb;
@@ -95,11 +102,13 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
   A.ck_stride = A.ck_psi + (L.pml ? align_up(4 * fb, 256) : 0);
   o += (size_t)A.nck * A.ck_stride;
   A.off_slots = o;
-  o = align_up(o + (size_t)A.K * A.slot_bytes, 256);
+  A.slots_stride = align_up((size_t)A.K * A.slot_bytes, 256);
+  o += A.nbuf * A.slots_stride;
   // reduced states of every step of a segment: K + 1 images (256-B aligned)
   A.img = align_up(std::max<size_t>(L.xs_elems, 1), 64);
   A.off_xrec = o;
-  o = align_up(o + (size_t)(A.K + 1) * A.img * ts, 256);
+  A.xrec_stride = align_up((size_t)(A.K + 1) * A.img * ts, 256);
+  o += A.nbuf * A.xrec_stride;
   A.off_psih = o;
   o = align_up(o + (L.pml ? 4 * fb : 0), 256);
   A.off_lam = o;
@@ -137,8 +146,8 @@ int plan_adjoint(const fdtd_rom_sim* s, int nsteps, int ckpt_every, AdjLayout& A
   const size_t parts[][2] = {
       {A.off_ctrl, kCtrlInts * sizeof(int)},
       {A.off_ckpt, (size_t)A.nck * A.ck_stride},
-      {A.off_slots, (size_t)A.K * A.slot_bytes},
-      {A.off_xrec, (size_t)(A.K + 1) * A.img * ts},
+      {A.off_slots, A.nbuf * A.slots_stride},
+      {A.off_xrec, A.nbuf * A.xrec_stride},
       {A.off_psih, L.pml ? 4 * fb : 0},
       {A.off_lam, 2 * A.lam_bytes},
       {A.off_lx, 2 * A.xs_bytes},
@@ -182,8 +191,11 @@ int check_recompute(const StepParams<T>& rp, int par, const char* aw, const AdjL
       return fail(FDTD_EINVAL, "internal: recompute field %d outside the adjoint workspace", f);
   const char* xlo = (const char*)rp.xs - (par ? A.img * sizeof(T) : 0);
   const char* rec = aw + A.off_xrec;
-  if (!inside_span(rp.ctrl, kCtrlInts * sizeof(int), aw, A.total) ||
-      !inside_span(xlo, 2 * A.img * sizeof(T), rec, (size_t)(A.K + 1) * A.img * sizeof(T)))
+  bool in_set = false;  // both images inside one buffer set's images
+  for (int b = 0; b < A.nbuf; ++b)
+    in_set = in_set || inside_span(xlo, 2 * A.img * sizeof(T), rec + b * A.xrec_stride,
+                                   (size_t)(A.K + 1) * A.img * sizeof(T));
+  if (!inside_span(rp.ctrl, kCtrlInts * sizeof(int), aw, A.total) || !in_set)
     return fail(FDTD_EINVAL, "internal: recompute control or reduced-state images outside the adjoint workspace");
   if (nroms > 0 && !inside_span(rp.roms, (size_t)nroms * sizeof(RomDev), aw + A.off_rtab,
                                 2 * (size_t)nroms * sizeof(RomDev)))
@@ -297,13 +309,20 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   auto dev_err = [&](const char* what) {
     return fail(FDTD_EDEVICE, "%s failed: %s", what, hipGetErrorString(hipGetLastError()));
   };
+  // the slots' padding columns of every buffer set
+  auto clear_padding = [&]() {
+    for (int b = 0; b < A.nbuf; ++b)
+      if (launch_zero_padding<T>((T*)(aw + A.off_slots + b * A.slots_stride),
+                                 (size_t)A.K * (A.slot_bytes / (fe * sizeof(T))), s->ny, s->pitch, s->nx,
+                                 st) != hipSuccess)
+        return false;
+    return true;
+  };
   if (noalloc) {
     // clear the control block, everything from the recompute's psi at Hz to
     // G^T and the slots' padding columns, as the host path below does
     if (launch_zero_fill(aw + A.off_ctrl, align_up(kCtrlInts * sizeof(int), 16), st) != hipSuccess ||
-        launch_zero_fill(aw + A.off_psih, A.off_gt - A.off_psih, st) != hipSuccess ||
-        launch_zero_padding<T>((T*)(aw + A.off_slots), (size_t)A.K * (A.slot_bytes / (fe * sizeof(T))), s->ny,
-                               s->pitch, s->nx, st) != hipSuccess)
+        launch_zero_fill(aw + A.off_psih, A.off_gt - A.off_psih, st) != hipSuccess || !clear_padding())
       return dev_err("scratch clear");
     const T* mats = (const T*)(ws + L.off_mats);
     T* gt = (T*)(aw + A.off_gt);
@@ -365,9 +384,7 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
     // (the stencil reads them unguarded and never writes them - every other
     // sample of a slot is written by its recompute step before it is read)
     if (hipMemsetAsync(aw + A.off_ctrl, 0, kCtrlInts * sizeof(int), st) != hipSuccess ||
-        hipMemsetAsync(aw + A.off_psih, 0, A.off_gt - A.off_psih, st) != hipSuccess ||
-        launch_zero_padding<T>((T*)(aw + A.off_slots), (size_t)A.K * (A.slot_bytes / (fe * sizeof(T))), s->ny,
-                               s->pitch, s->nx, st) != hipSuccess)
+        hipMemsetAsync(aw + A.off_psih, 0, A.off_gt - A.off_psih, st) != hipSuccess || !clear_padding())
       return dev_err("workspace clear");
     if (A.models && s->nroms > 0) {
       std::vector<int64_t> dgo(s->nroms);
@@ -390,9 +407,16 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   auto ckpt_xs = [&](int c) { return ckpt(c) + align_up(A.set_bytes, 256); };
   // checkpoint's auxiliary fields: [psi at Hz (2), psi at Ex, psi at Ey]
   auto ckpt_psi = [&](int c) { return (T*)(ckpt(c) + A.ck_psi); };
-  auto slot = [&](int k) { return aw + A.off_slots + (size_t)k * A.slot_bytes; };
-  // reduced states x~^{m0+k} of the segment being swept, k = 0..K
-  auto image = [&](int k) { return (T*)(aw + A.off_xrec) + (size_t)k * A.img; };
+  // segment c's buffer set of slots and images (segments alternate when the
+  // recompute of the segment below runs beside the reverse steps)
+  auto bset = [&](int c) -> size_t { return A.nbuf == 2 ? (size_t)(c & 1) : 0; };
+  auto slot = [&](int c, int k) { return aw + A.off_slots + bset(c) * A.slots_stride + (size_t)k * A.slot_bytes; };
+  // reduced states x~^{m0+k} of segment c, k = 0..K
+  auto image = [&](int c, int k) { return (T*)(aw + A.off_xrec + bset(c) * A.xrec_stride) + (size_t)k * A.img; };
+  // state m0 + k of segment c: k = 0 is the checkpoint, k >= 1 is slot k - 1
+  auto state = [&](int c, int k) -> T* { return (T*)(k == 0 ? ckpt(c) : slot(c, k - 1)); };
+  // psi at Ex then at Ey of state m0 + k (contiguous)
+  auto psi_e = [&](int c, int k) -> T* { return k == 0 ? ckpt_psi(c) + 2 * fe : state(c, k) + 3 * fe; };
   T* psih = (T*)(aw + A.off_psih);  // recompute's psi at Hz, [parity][2]
   const size_t xs_copy = L.xs_elems * sizeof(T);
   const size_t fb = fe * sizeof(T);
@@ -492,24 +516,21 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   T* lam[2] = {(T*)(aw + A.off_lam), (T*)(aw + A.off_lam + A.lam_bytes)};
   T* lx[2] = {(T*)(aw + A.off_lx), (T*)(aw + A.off_lx + A.xs_bytes)};
   T* pend[2] = {(T*)(aw + A.off_pend), (T*)(aw + A.off_pend + fb)};
-  int cur = 0;
-  for (int c = A.nck - 1; c >= 0; --c) {
+  // recompute of segment c on stream qs: states m0+1 .. m0+len into its
+  // slots 0 .. len-1, reduced states into its images
+  auto recompute = [&](int c, hipStream_t qs) -> int {
     const int m0 = c * A.K;
     const int len = std::min(A.K, N - m0);
-    // state m0 + k: k = 0 is the checkpoint, k >= 1 is slot k - 1
-    auto state = [&](int k) -> T* { return (T*)(k == 0 ? ckpt(c) : slot(k - 1)); };
-    // psi at Ex then at Ey of state m0 + k (contiguous)
-    auto psi_e = [&](int k) -> T* { return k == 0 ? ckpt_psi(c) + 2 * fe : state(k) + 3 * fe; };
-    if (launch_states_to_image<T>((const T*)ckpt_xs(c), image(0), hroms, s->nroms, m0 & 1, st) != hipSuccess)
+    if (launch_states_to_image<T>((const T*)ckpt_xs(c), image(c, 0), hroms, s->nroms, m0 & 1, qs) != hipSuccess)
       return dev_err("state restore");
     if (L.pml && hipMemcpyAsync(psih + (size_t)(m0 & 1) * 2 * fe, ckpt_psi(c), 2 * fb, hipMemcpyDeviceToDevice,
-                                st) != hipSuccess)
+                                qs) != hipSuccess)
       return dev_err("state restore");
     for (int k = 0; k < len; ++k) {  // states m0+1 .. m0+len into slots 0 .. len-1
       const int m = m0 + k;
       const int par = m & 1;
-      T* in = state(k);
-      T* out = state(k + 1);
+      T* in = state(c, k);
+      T* out = state(c, k + 1);
       for (int f = 0; f < 3; ++f) {
         rp.f[par][f] = in + (size_t)f * fe;
         rp.f[par ^ 1][f] = out + (size_t)f * fe;
@@ -517,20 +538,53 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
       if (L.pml) {
         // the step updates psi at Ex and Ey in place: start the new slot's
         // pair from this state's
-        if (hipMemcpyAsync(psi_e(k + 1), psi_e(k), 2 * fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        if (hipMemcpyAsync(psi_e(c, k + 1), psi_e(c, k), 2 * fb, hipMemcpyDeviceToDevice, qs) != hipSuccess)
           return dev_err("recompute copy");
         for (int q = 0; q < 2; ++q) {
           rp.psi_h[q][0] = psih + (size_t)q * 2 * fe;
           rp.psi_h[q][1] = psih + (size_t)q * 2 * fe + fe;
         }
-        rp.psi_ex = psi_e(k + 1);
-        rp.psi_ey = psi_e(k + 1) + fe;
+        rp.psi_ex = psi_e(c, k + 1);
+        rp.psi_ey = psi_e(c, k + 1) + fe;
       }
       rp.step_off = m;
       rp.roms = par ? rtab + s->nroms : rtab;
-      rp.xs = par ? image(k + 1) : image(k);
+      rp.xs = par ? image(c, k + 1) : image(c, k);
       if (const int rc = check_recompute<T>(rp, par, aw, A, fe, s->nroms); rc != FDTD_OK) return rc;
-      if (launch_step<T>(rp, s->seg, s->smem, st) != hipSuccess) return dev_err("recompute launch");
+      if (launch_step<T>(rp, s->seg, s->smem, qs) != hipSuccess) return dev_err("recompute launch");
+    }
+    return FDTD_OK;
+  };
+  // the recompute of segment c-1 runs on a second stream (default priority)
+  // beside the reverse steps of segment c; events order it after the
+  // reverse steps of segment c+1, whose buffer set it takes over
+  struct Pipe {
+    hipStream_t sb = nullptr;
+    hipEvent_t ev[5] = {};  // start, recomputed[2], reversed[2]
+    ~Pipe() {
+      if (sb) hipStreamSynchronize(sb);
+      for (hipEvent_t e : ev)
+        if (e) hipEventDestroy(e);
+      if (sb) hipStreamDestroy(sb);
+    }
+  } pipe;
+  const bool piped = A.nbuf == 2 && !noalloc;
+  if (piped) {
+    if (hipStreamCreateWithFlags(&pipe.sb, hipStreamNonBlocking) != hipSuccess) return dev_err("recompute stream");
+    for (hipEvent_t& e : pipe.ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return dev_err("recompute events");
+  }
+  hipEvent_t& ev_start = pipe.ev[0];
+  hipEvent_t* ev_rec = pipe.ev + 1;
+  hipEvent_t* ev_rev = pipe.ev + 3;
+  int cur = 0;
+  for (int c = A.nck - 1; c >= 0; --c) {
+    const int m0 = c * A.K;
+    const int len = std::min(A.K, N - m0);
+    if (!piped || c == A.nck - 1) {
+      if (const int rc = recompute(c, st); rc != FDTD_OK) return rc;
+    } else if (hipStreamWaitEvent(st, ev_rec[c & 1], 0) != hipSuccess) {
+      return dev_err("recompute wait");
     }
     if (c == A.nck - 1) {
       // the forward stopped at m0: the handle takes the recomputed state
@@ -538,24 +592,33 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
       // parity-N places, with layers the auxiliary fields), the segment's
       // probe rows and the step count, as if it had run the steps
       const int dst = (N & 1) ^ s->flip;
-      if (hipMemcpyAsync(ws + L.off_fields + (size_t)dst * A.set_bytes, state(len), A.set_bytes,
+      if (hipMemcpyAsync(ws + L.off_fields + (size_t)dst * A.set_bytes, state(c, len), A.set_bytes,
                          hipMemcpyDeviceToDevice, st) != hipSuccess ||
-          launch_image_to_states<T>(image(len), (T*)(ws + L.off_xs), hroms, s->nroms, N & 1, st) != hipSuccess)
+          launch_image_to_states<T>(image(c, len), (T*)(ws + L.off_xs), hroms, s->nroms, N & 1, st) != hipSuccess)
         return dev_err("handing over the last segment");
       if (L.pml) {
         const T* ph = psih + (size_t)(N & 1) * 2 * fe;
         if (hipMemcpyAsync(sp.psi_h[N & 1][0], ph, fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
             hipMemcpyAsync(sp.psi_h[N & 1][1], ph + fe, fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(sp.psi_ex, psi_e(len), fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(sp.psi_ey, psi_e(len) + fe, fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            hipMemcpyAsync(sp.psi_ex, psi_e(c, len), fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(sp.psi_ey, psi_e(c, len) + fe, fb, hipMemcpyDeviceToDevice, st) != hipSuccess)
           return dev_err("handing over the last segment");
       }
-      if (launch_slots_to_probes<T>(state(1), A.slot_bytes / sizeof(T), fe, len, s->nprobes, sp.probe_off,
+      if (launch_slots_to_probes<T>(state(c, 1), A.slot_bytes / sizeof(T), fe, len, s->nprobes, sp.probe_off,
                                     sp.probe_comp, sp.probe_buf, m0, st) != hipSuccess ||
           launch_tick(sp.ctrl, len, st) != hipSuccess)
         return dev_err("handing over the last segment");
       s->steps = N;
       if (const int rc = objective(); rc != FDTD_OK) return rc;
+    }
+    if (piped && c >= 1) {
+      // after the hand-over (the recompute's private psi at Hz is free), or
+      // once segment c+1's reverse steps have left its buffer set
+      if (c == A.nck - 1 && hipEventRecord(ev_start, st) != hipSuccess) return dev_err("recompute event");
+      if (hipStreamWaitEvent(pipe.sb, c == A.nck - 1 ? ev_start : ev_rev[(c + 1) & 1], 0) != hipSuccess)
+        return dev_err("recompute wait");
+      if (const int rc = recompute(c - 1, pipe.sb); rc != FDTD_OK) return rc;
+      if (hipEventRecord(ev_rec[(c - 1) & 1], pipe.sb) != hipSuccess) return dev_err("recompute event");
     }
     for (int k = len - 1; k >= 0; --k) {
       T* li = lam[cur];
@@ -568,17 +631,17 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
       ap.ley_out = lo + 2 * fe;
       ap.lx_in = lx[cur];
       ap.lx_out = lx[cur ^ 1];
-      ap.hz1 = state(k + 1);
-      ap.xn = image(k);
-      ap.ex0 = state(k) + fe;
-      ap.ey0 = state(k) + 2 * fe;
+      ap.hz1 = state(c, k + 1);
+      ap.xn = image(c, k);
+      ap.ex0 = state(c, k) + fe;
+      ap.ey0 = state(c, k) + 2 * fe;
       if (L.pml) {
         for (int q = 0; q < 4; ++q) {
           ap.lps_in[q] = li + (size_t)(3 + q) * fe;
           ap.lps_out[q] = lo + (size_t)(3 + q) * fe;
         }
-        ap.pex1 = psi_e(k + 1);
-        ap.pey1 = psi_e(k + 1) + fe;
+        ap.pex1 = psi_e(c, k + 1);
+        ap.pey1 = psi_e(c, k + 1) + fe;
       }
       if (A.models) {
         // two launches: eq. (23)'s transpose of step m (accumulating dJ/dG
@@ -599,6 +662,7 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
           return dev_err("gradient flush");
       }
     }
+    if (piped && hipEventRecord(ev_rev[c & 1], st) != hipSuccess) return dev_err("reverse event");
   }
   // gradients: pitch layout -> natural, zero on regions and their rings and
   // on PEC cells
@@ -789,7 +853,7 @@ int fdtd_rom_adjoint_noalloc(fdtd_rom_sim* sim, int32_t nsteps, int32_t ckpt_eve
   if (probe < 0 || probe >= sim->nprobes) return fail(FDTD_EINVAL, "probe %d out of range", probe);
   if (sim->probes[probe].comp != FDTD_HZ) return fail(FDTD_EINVAL, "probe %d is not an Hz probe", probe);
   AdjLayout A;
-  int rc = plan_adjoint(sim, nsteps, ckpt_every, A);
+  int rc = plan_adjoint(sim, nsteps, ckpt_every, A, false, false);  // one stream, one buffer set
   if (rc != FDTD_OK) return rc;
   if (A.total > kNoAllocScratchBytes)
     return fail(FDTD_ENOMEM, "the sweep needs %zu bytes of scratch, the static scratch array holds %zu "
