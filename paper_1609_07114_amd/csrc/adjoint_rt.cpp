@@ -481,12 +481,15 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   ap.nx = s->nx;
   ap.ny = s->ny;
   ap.pitch = s->pitch;
-  // rows per reverse wave: half the forward's 4-row default on grids that
-  // small (more waves in flight; the C5 1024^2 sweep: 182.5 ms at 2 rows,
-  // 190.7 at 4, 185.8 at 8), else the forward's, at most 16
+  // rows per reverse wave: the forward's default, at most 16; where that is
+  // 4 rows (grids this small) and the reverse steps run alone, half of it
+  // for more waves in flight (the C5 1024^2 sweep in one launch per reverse
+  // step without a recompute beside it: 182.5 ms at 2 rows, 190.7 at 4,
+  // 185.8 at 8), but 4 while the next segment's recompute runs beside them
+  // (133.6 ms at 4 rows, 140.6 at 2, 148.7 at 8; checkpoints every 200)
   {
     const int fw = default_tiling(s->nx, s->ny, (int)L.tsize);
-    ap.seg = fw == 4 ? 2 : std::min(fw, 16);
+    ap.seg = fw == 4 && !(A.nbuf == 2 && !noalloc) ? 2 : std::min(fw, 16);
   }
   ap.chdy = sp.chdy;
   ap.chdx = sp.chdx;
@@ -562,10 +565,10 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
     hipStream_t sb = nullptr;
     hipEvent_t ev[5] = {};  // start, recomputed[2], reversed[2]
     ~Pipe() {
-      if (sb) hipStreamSynchronize(sb);
+      if (sb) (void)hipStreamSynchronize(sb);
       for (hipEvent_t e : ev)
-        if (e) hipEventDestroy(e);
-      if (sb) hipStreamDestroy(sb);
+        if (e) (void)hipEventDestroy(e);
+      if (sb) (void)hipStreamDestroy(sb);
     }
   } pipe;
   const bool piped = A.nbuf == 2 && !noalloc;
