@@ -29,7 +29,7 @@ _u8p = C.POINTER(C.c_uint8)
 class fdtd_grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
                 ("dt", C.c_double), ("dtype", C.c_int32), ("eps_r", _dp), ("sigma", _dp),
-                ("pec", _u8p)]
+                ("pec", _u8p), ("pitch_pad", C.c_int32)]
 
 
 class fdtd_rom(C.Structure):
@@ -204,7 +204,7 @@ class ProblemStruct:
     """Owns the C structs and the contiguous float64 arrays they point to."""
 
     def __init__(self, nx, ny, dx, dy, dt, dtype, eps_r, sigma, roms, sources, probes,
-                 max_steps, pml=None, pec=None):
+                 max_steps, pml=None, pec=None, pitch_pad=0):
         self._keep = []
 
         def arr(x):
@@ -214,7 +214,7 @@ class ProblemStruct:
             self._keep.append(a)
             return a
         g = fdtd_grid(nx, ny, dx, dy, dt, FDTD_F64 if dtype in ("f64", FDTD_F64) else FDTD_F32,
-                      _ptr(arr(eps_r)), _ptr(arr(sigma)), _mask(pec, self._keep, (ny, nx)))
+                      _ptr(arr(eps_r)), _ptr(arr(sigma)), _mask(pec, self._keep, (ny, nx)), int(pitch_pad))
         rarr = (fdtd_rom * max(1, len(roms)))()
         for k, r in enumerate(roms):
             Rt, Ft, Lt = arr(r["Rt"]), arr(r["Ft"]), arr(r["Lt"])
@@ -249,7 +249,7 @@ class ProblemStruct:
         ms = prob.nsteps if max_steps is None else max_steps
         return cls(prob.nx, prob.ny, prob.dx, prob.dy, prob.dt, dtype or prob.dtype, prob.eps_r,
                    prob.sigma, roms, srcs, prbs, ms, getattr(prob, "pml", None),
-                   getattr(prob, "pec", None))
+                   getattr(prob, "pec", None), getattr(prob, "pitch_pad", 0))
 
 
 # ---------------------------------------------------------------------------

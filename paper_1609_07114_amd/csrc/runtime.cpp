@@ -53,7 +53,9 @@ int fdtd::plan_problem(const fdtd_problem* p, Layout& L) {
   if (p->nprobes < 0 || (p->nprobes > 0 && !p->probes)) return fail(FDTD_EINVAL, "bad probe list");
   const size_t ts = g.dtype == FDTD_F32 ? 4 : 8;
   L.tsize = ts;
-  L.pitch = (int)align_up((size_t)g.nx, kWave);
+  if (g.pitch_pad < 0 || g.pitch_pad > 1024 || g.pitch_pad % kWave != 0)
+    return fail(FDTD_EINVAL, "pitch_pad=%d must be a multiple of %d in [0, 1024]", g.pitch_pad, kWave);
+  L.pitch = (int)align_up((size_t)g.nx, kWave) + g.pitch_pad;
   L.field_elems = (size_t)g.ny * L.pitch;
   // the stencil addresses every field with 32-bit byte offsets
   if ((double)L.field_elems * (double)ts >= 2147483648.0)

@@ -279,3 +279,18 @@ def test_adjoint_plan_host_only(dtype):
         capi.fdtd_rom_adjoint_plan(_struct(p, roms), 301, 7)      # beyond max_steps
     with pytest.raises(capi.FdtdError):
         capi.fdtd_rom_adjoint_plan(_struct(p, roms), 300, 301)
+
+
+def test_pitch_pad_checked_and_sized(small):
+    """fdtd_grid.pitch_pad: multiples of 64 in [0, 1024] widen every field
+    row; anything else is refused."""
+    p, roms = small
+    base = capi.fdtd_rom_workspace_size(_struct(p, roms))
+    q = copy.copy(p)
+    q.pitch_pad = 64
+    assert capi.fdtd_rom_workspace_size(_struct(q, roms)) > base
+    for bad in (-64, 32, 1088):
+        q.pitch_pad = bad
+        with pytest.raises(capi.FdtdError) as e:
+            capi.fdtd_rom_workspace_size(_struct(q, roms))
+        assert e.value.status == capi.FDTD_EINVAL

@@ -117,6 +117,7 @@ class Problem:
     dtype: str          # "f64" or "f32"
     pml: Optional[Pml] = None
     pec: Optional[np.ndarray] = None   # coarse cells that are perfect conductors [ny, nx]
+    pitch_pad: int = 0                  # device layout: unused columns appended to each row
 
     @property
     def ncells(self) -> int:
