@@ -164,6 +164,9 @@ int fdtd_rom_workspace_size(const fdtd_problem* prob, size_t* bytes);
  *     aligned; owned by the caller and must outlive the handle.
  *   hip_stream: hipStream_t every launch and copy of this handle goes to
  *     (NULL = the default stream).
+ * Every call on a handle runs on the device current on the calling thread,
+ * which must be the device of its workspace and stream (the library never
+ * switches devices).
  * Checks: dimensions > 0; dt <= the coarse CFL limit of eq. (1) with
  * c = c0/sqrt(min eps_r) (FDTD_EINVAL); every region at least one cell from
  * the walls and its one-cell ring disjoint from other regions (FDTD_EINVAL);
