@@ -352,6 +352,23 @@ int fdtd_rom_build(const fdtd_rom_build_params* params, double* Rt, double* Ft, 
 int fdtd_rom_build_vjp(const fdtd_rom_build_params* params, const double* grad_Rt, const double* grad_Ft,
                        double* grad_eps_r, double* grad_sigma);
 
+/* The builder's state kept for its gradient (same steps as
+ * fdtd_rom_build_vjp without rebuilding the model: the fine model, the E
+ * basis V1, K~ before the clip and the clip's limit stay on the host).
+ * fdtd_rom_build_keep: fdtd_rom_build (same arguments, outputs and errors;
+ * Rt, Ft, Lt required) that also returns *state, owned by the caller until
+ * fdtd_rom_model_state_free (tens of MB for a 128x128-cell region: the basis
+ * over every fine edge).  fdtd_rom_model_state_vjp: fdtd_rom_build_vjp's
+ * result for the model the state was built with (bit for bit), sizes as
+ * there; the state is read only, so calls on one state may run in parallel
+ * threads. */
+typedef struct fdtd_rom_model_state fdtd_rom_model_state;
+int fdtd_rom_build_keep(const fdtd_rom_build_params* params, double* Rt, double* Ft, double* Lt,
+                        fdtd_rom_build_info* info, fdtd_rom_model_state** state);
+int fdtd_rom_model_state_vjp(const fdtd_rom_model_state* state, const double* grad_Rt, const double* grad_Ft,
+                             double* grad_eps_r, double* grad_sigma);
+void fdtd_rom_model_state_free(fdtd_rom_model_state* state);
+
 /* Per-kernel timing with HIP events on the handle's stream.  One step is
  * one launch of the step kernel (coarse stencil, every model's eq. (23)
  * update and the probe record run as concurrent workgroups of that launch);

@@ -73,12 +73,13 @@ def _model_function():
                      for k, s in enumerate(prob.roms)]
             p = dataclasses.replace(_problem_with(prob, cpu(eps_r), cpu(sigma)), roms=specs)
             nsteps = p.nsteps if nsteps is None else nsteps
-            mats = romgen.build_roms(p)
+            grad = any(ctx.needs_input_grad)
+            mats = romgen.build_roms(p, keep=grad)   # builder states for the gradient, no rebuild
             with Simulation(p, mats, dtype=dtype, device=device) as sim:
-                if any(ctx.needs_input_grad):
+                if grad:
                     J, ge, gs, models = sim.adjoint_models(nsteps, probe=probe, ckpt_every=ckpt_every)
                     fe, fs = [], []
-                    for k, (a, b) in enumerate(romgen.build_vjps(p, models)):
+                    for k, (a, b) in enumerate(romgen.build_vjps(p, models, roms=mats)):
                         fe.append(torch.from_numpy(a).to(fine[k].device, fine[k].dtype))
                         fs.append(torch.from_numpy(b).to(fine[nr + k].device, fine[nr + k].dtype))
                     ctx.save_for_backward(torch.from_numpy(ge).to(eps_r.device, eps_r.dtype),

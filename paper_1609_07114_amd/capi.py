@@ -128,6 +128,10 @@ _SIGS = {
                                           C.c_size_t, _dp, _dp, _dp, C.POINTER(_dp), C.POINTER(_dp),
                                           C.POINTER(_dp)]),
     "fdtd_rom_build_vjp": (C.c_int, [C.POINTER(fdtd_rom_build_params), _dp, _dp, _dp, _dp]),
+    "fdtd_rom_build_keep": (C.c_int, [C.POINTER(fdtd_rom_build_params), _dp, _dp, _dp,
+                                      C.POINTER(fdtd_rom_build_info), C.POINTER(C.c_void_p)]),
+    "fdtd_rom_model_state_vjp": (C.c_int, [C.c_void_p, _dp, _dp, _dp, _dp]),
+    "fdtd_rom_model_state_free": (None, [C.c_void_p]),
     "fdtd_rom_energy": (C.c_int, [C.c_void_p, _dp]),
     "fdtd_rom_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "fdtd_rom_get_state": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -381,6 +385,52 @@ def fdtd_rom_build_vjp(ni, nj, r, dx, dy, dt, eps_r, sigma, q, f_max, grad_Rt, g
     ge = np.zeros(er.shape)
     gs = np.zeros(er.shape)
     _check(lib().fdtd_rom_build_vjp(C.byref(prm), _ptr(gR), _ptr(gF), _ptr(ge), _ptr(gs)))
+    return ge, gs
+
+
+class ModelState:
+    """The builder's state of one model (fdtd_rom_build_keep), freed with
+    the object."""
+
+    def __init__(self, ptr, q, fine_shape):
+        self.ptr, self.q, self.fine_shape = ptr, q, fine_shape
+
+    def __del__(self):
+        if self.ptr is not None and _LIB is not None:
+            _LIB.fdtd_rom_model_state_free(C.c_void_p(self.ptr))
+            self.ptr = None
+
+
+def fdtd_rom_build_keep(ni, nj, r, dx, dy, dt, eps_r, sigma, q, f_max, theta=0.99, clip=True, pec=None):
+    """fdtd_rom_build (SPRIM basis) that also keeps the builder's state for
+    fdtd_rom_model_state_vjp: the model dict gains 'state'."""
+    er = np.ascontiguousarray(eps_r, dtype=np.float64)
+    sg = np.ascontiguousarray(sigma, dtype=np.float64)
+    assert er.shape == (r * nj, r * ni) and sg.shape == er.shape
+    np_ = 2 * (ni + nj)
+    keep = []
+    prm = fdtd_rom_build_params(ni, nj, r, dx, dy, dt, _ptr(er), _ptr(sg), q, f_max, theta,
+                                1 if clip else 0, 0, _mask(pec, keep, er.shape))
+    info = fdtd_rom_build_info()
+    Rt = np.zeros((q, q))
+    Ft = np.zeros((q, q))
+    Lt = np.zeros((q, np_))
+    st = C.c_void_p(None)
+    _check(lib().fdtd_rom_build_keep(C.byref(prm), _ptr(Rt), _ptr(Ft), _ptr(Lt), C.byref(info), C.byref(st)))
+    return dict(Rt=Rt, Ft=Ft, Lt=Lt, q1=info.q1, q2=info.q2, p0=info.p0,
+                smax_before=info.smax_before, smax_after=info.smax_after,
+                clipped=bool(info.clipped), n_fine_states=info.n_fine_states,
+                state=ModelState(st.value, q, er.shape))
+
+
+def fdtd_rom_model_state_vjp(state: ModelState, grad_Rt, grad_Ft):
+    """fdtd_rom_build_vjp's fine-cell gradients from a kept builder state."""
+    gR = np.ascontiguousarray(grad_Rt, dtype=np.float64)
+    gF = np.ascontiguousarray(grad_Ft, dtype=np.float64)
+    assert gR.shape == (state.q, state.q) and gF.shape == gR.shape, (gR.shape, state.q)
+    ge = np.zeros(state.fine_shape)
+    gs = np.zeros(state.fine_shape)
+    _check(lib().fdtd_rom_model_state_vjp(C.c_void_p(state.ptr), _ptr(gR), _ptr(gF), _ptr(ge), _ptr(gs)))
     return ge, gs
 
 

@@ -870,73 +870,136 @@ bool clip_vjp(const Mat& R11, const Mat& R22, const Mat& K, int q1, int q2, doub
 
 }  // namespace
 
+// What the builder's gradient needs of one build: the build state (fine
+// model, E basis, K~ before the clip, the clip's limit), R~ and the sizes.
+struct fdtd_rom_model_state {
+  BuildState bs;
+  Mat Rt;
+  double dt = 0;
+  size_t nfine = 0;
+};
+
+namespace {
+
+// Build with the state kept (as fdtd_rom_build; Rt/Ft/Lt may be null to
+// only keep the state).
+int build_keep(const fdtd_rom_build_params* prm, fdtd_rom_model_state& st, double* Rt, double* Ft, double* Lt,
+               fdtd_rom_build_info* info_out) {
+  fdtd_rom_build_info info{};
+  if (int rc = build_impl(prm, nullptr, nullptr, nullptr, &info, nullptr); rc != FDTD_OK) return rc;
+  const int q = info.q1 + info.q2;
+  const int np = 2 * (prm->ni + prm->nj);
+  st.Rt.assign((size_t)q * q, 0.0);
+  Mat f((size_t)q * q), l((size_t)q * np);
+  if (int rc = build_impl(prm, st.Rt.data(), f.data(), l.data(), &info, &st.bs); rc != FDTD_OK) return rc;
+  st.dt = prm->dt;
+  st.nfine = (size_t)prm->r * prm->ni * prm->r * prm->nj;
+  if (Rt) std::copy(st.Rt.begin(), st.Rt.end(), Rt);
+  if (Ft) std::copy(f.begin(), f.end(), Ft);
+  if (Lt) std::copy(l.begin(), l.end(), Lt);
+  if (info_out) *info_out = info;
+  return FDTD_OK;
+}
+
+// dJ/dR~, dJ/dF~ -> fine-cell dJ/deps_r, dJ/dsigma with the state's basis
+int vjp_from_state(const fdtd_rom_model_state& st, const double* grad_Rt, const double* grad_Ft, double* grad_eps_r,
+                   double* grad_sigma) {
+  const int q1 = st.bs.q1, q2 = st.bs.q2, q = q1 + q2;
+  const double dt = st.dt;
+  // the E block of dJ/dR~ (through the clip when it acted) and of dJ/dF~
+  Mat gR11((size_t)q1 * q1), gF11((size_t)q1 * q1);
+  for (int a = 0; a < q1; ++a)
+    for (int b = 0; b < q1; ++b) {
+      gR11[(size_t)a * q1 + b] = grad_Rt[(size_t)a * q + b];
+      gF11[(size_t)a * q1 + b] = grad_Ft[(size_t)a * q + b];
+    }
+  if (st.bs.clipped) {
+    // R~12 = -K~_c/2, R~21 = -K~_c^T/2, F~12 = -K~_c/2, F~21 = +K~_c^T/2
+    Mat gK((size_t)q1 * q2), R11((size_t)q1 * q1), R22((size_t)q2 * q2), g;
+    for (int a = 0; a < q1; ++a)
+      for (int c = 0; c < q2; ++c)
+        gK[(size_t)a * q2 + c] = -0.5 * grad_Rt[(size_t)a * q + q1 + c] - 0.5 * grad_Rt[(size_t)(q1 + c) * q + a] -
+                                 0.5 * grad_Ft[(size_t)a * q + q1 + c] + 0.5 * grad_Ft[(size_t)(q1 + c) * q + a];
+    for (int a = 0; a < q1; ++a)
+      for (int b = 0; b < q1; ++b) R11[(size_t)a * q1 + b] = dt * st.Rt[(size_t)a * q + b];
+    for (int a = 0; a < q2; ++a)
+      for (int b = 0; b < q2; ++b) R22[(size_t)a * q2 + b] = dt * st.Rt[(size_t)(q1 + a) * q + q1 + b];
+    if (!clip_vjp(R11, R22, st.bs.K0, q1, q2, st.bs.lim, gK, g))
+      return fail(FDTD_EINVAL, "eigen-decomposition for the clip's gradient did not converge");
+    for (size_t e = 0; e < gR11.size(); ++e) gR11[e] += dt * g[e];
+  }
+  // congruence: per E coordinate e, dJ/dDe = (V1 gR11 V1^T)_ee / dt,
+  // dJ/dDs = (V1 gF11 V1^T)_ee / 2 (V1 = I for the identity basis)
+  const FineModel& fm = st.bs.fm;
+  const size_t nf = st.nfine;
+  std::fill(grad_eps_r, grad_eps_r + nf, 0.0);
+  std::fill(grad_sigma, grad_sigma + nf, 0.0);
+  const bool ident = st.bs.V1.empty();
+  std::vector<double> u(q1), tR(q1), tF(q1);
+  for (int e = 0; e < fm.nE; ++e) {
+    double dDe, dDs;
+    if (ident) {
+      dDe = gR11[(size_t)e * q1 + e] / dt;
+      dDs = 0.5 * gF11[(size_t)e * q1 + e];
+    } else {
+      for (int a = 0; a < q1; ++a) u[a] = st.bs.V1[a][e];
+      std::fill(tR.begin(), tR.end(), 0.0);
+      std::fill(tF.begin(), tF.end(), 0.0);
+      for (int a = 0; a < q1; ++a) {
+        if (u[a] == 0.0) continue;
+        fdtd::la::axpy(u[a], gR11.data() + (size_t)a * q1, tR.data(), q1);
+        fdtd::la::axpy(u[a], gF11.data() + (size_t)a * q1, tF.data(), q1);
+      }
+      dDe = fdtd::la::dot(tR.data(), u.data(), q1) / dt;
+      dDs = 0.5 * fdtd::la::dot(tF.data(), u.data(), q1);
+    }
+    for (const auto& cw : fm.ecells[e]) {
+      grad_eps_r[cw.first] += cw.second * kEps0 * dDe;
+      grad_sigma[cw.first] += cw.second * dDs;
+    }
+  }
+  return FDTD_OK;
+}
+
+}  // namespace
+
 extern "C" int fdtd_rom_build_vjp(const fdtd_rom_build_params* prm, const double* grad_Rt, const double* grad_Ft,
                                   double* grad_eps_r, double* grad_sigma) {
   if (!prm || !grad_Rt || !grad_Ft || !grad_eps_r || !grad_sigma) return fail(FDTD_EINVAL, "null argument");
   try {
-    fdtd_rom_build_info info{};
-    if (int rc = build_impl(prm, nullptr, nullptr, nullptr, &info, nullptr); rc != FDTD_OK) return rc;
-    const int q = info.q1 + info.q2;
-    const int np = 2 * (prm->ni + prm->nj);
-    Mat Rt((size_t)q * q), Ft((size_t)q * q), Lt((size_t)q * np);
-    BuildState bs;
-    if (int rc = build_impl(prm, Rt.data(), Ft.data(), Lt.data(), &info, &bs); rc != FDTD_OK) return rc;
-    const int q1 = bs.q1, q2 = bs.q2;
-    const double dt = prm->dt;
-    // the E block of dJ/dR~ (through the clip when it acted) and of dJ/dF~
-    Mat gR11((size_t)q1 * q1), gF11((size_t)q1 * q1);
-    for (int a = 0; a < q1; ++a)
-      for (int b = 0; b < q1; ++b) {
-        gR11[(size_t)a * q1 + b] = grad_Rt[(size_t)a * q + b];
-        gF11[(size_t)a * q1 + b] = grad_Ft[(size_t)a * q + b];
-      }
-    if (bs.clipped) {
-      // R~12 = -K~_c/2, R~21 = -K~_c^T/2, F~12 = -K~_c/2, F~21 = +K~_c^T/2
-      Mat gK((size_t)q1 * q2), R11((size_t)q1 * q1), R22((size_t)q2 * q2), g;
-      for (int a = 0; a < q1; ++a)
-        for (int c = 0; c < q2; ++c)
-          gK[(size_t)a * q2 + c] = -0.5 * grad_Rt[(size_t)a * q + q1 + c] - 0.5 * grad_Rt[(size_t)(q1 + c) * q + a] -
-                                   0.5 * grad_Ft[(size_t)a * q + q1 + c] + 0.5 * grad_Ft[(size_t)(q1 + c) * q + a];
-      for (int a = 0; a < q1; ++a)
-        for (int b = 0; b < q1; ++b) R11[(size_t)a * q1 + b] = dt * Rt[(size_t)a * q + b];
-      for (int a = 0; a < q2; ++a)
-        for (int b = 0; b < q2; ++b) R22[(size_t)a * q2 + b] = dt * Rt[(size_t)(q1 + a) * q + q1 + b];
-      if (!clip_vjp(R11, R22, bs.K0, q1, q2, bs.lim, gK, g))
-        return fail(FDTD_EINVAL, "eigen-decomposition for the clip's gradient did not converge");
-      for (size_t e = 0; e < gR11.size(); ++e) gR11[e] += dt * g[e];
+    fdtd_rom_model_state st;
+    if (int rc = build_keep(prm, st, nullptr, nullptr, nullptr, nullptr); rc != FDTD_OK) return rc;
+    return vjp_from_state(st, grad_Rt, grad_Ft, grad_eps_r, grad_sigma);
+  } catch (const std::bad_alloc&) {
+    return fail(FDTD_ENOMEM, "host allocation failed");
+  }
+}
+
+extern "C" int fdtd_rom_build_keep(const fdtd_rom_build_params* prm, double* Rt, double* Ft, double* Lt,
+                                   fdtd_rom_build_info* info, fdtd_rom_model_state** state) {
+  if (!prm || !Rt || !Ft || !Lt || !state) return fail(FDTD_EINVAL, "null argument");
+  *state = nullptr;
+  try {
+    auto* st = new fdtd_rom_model_state();
+    if (int rc = build_keep(prm, *st, Rt, Ft, Lt, info); rc != FDTD_OK) {
+      delete st;
+      return rc;
     }
-    // congruence: per E coordinate e, dJ/dDe = (V1 gR11 V1^T)_ee / dt,
-    // dJ/dDs = (V1 gF11 V1^T)_ee / 2 (V1 = I for the identity basis)
-    const FineModel& fm = bs.fm;
-    const size_t nf = (size_t)prm->r * prm->ni * prm->r * prm->nj;
-    std::fill(grad_eps_r, grad_eps_r + nf, 0.0);
-    std::fill(grad_sigma, grad_sigma + nf, 0.0);
-    const bool ident = bs.V1.empty();
-    std::vector<double> u(q1), tR(q1), tF(q1);
-    for (int e = 0; e < fm.nE; ++e) {
-      double dDe, dDs;
-      if (ident) {
-        dDe = gR11[(size_t)e * q1 + e] / dt;
-        dDs = 0.5 * gF11[(size_t)e * q1 + e];
-      } else {
-        for (int a = 0; a < q1; ++a) u[a] = bs.V1[a][e];
-        std::fill(tR.begin(), tR.end(), 0.0);
-        std::fill(tF.begin(), tF.end(), 0.0);
-        for (int a = 0; a < q1; ++a) {
-          if (u[a] == 0.0) continue;
-          fdtd::la::axpy(u[a], gR11.data() + (size_t)a * q1, tR.data(), q1);
-          fdtd::la::axpy(u[a], gF11.data() + (size_t)a * q1, tF.data(), q1);
-        }
-        dDe = fdtd::la::dot(tR.data(), u.data(), q1) / dt;
-        dDs = 0.5 * fdtd::la::dot(tF.data(), u.data(), q1);
-      }
-      for (const auto& cw : fm.ecells[e]) {
-        grad_eps_r[cw.first] += cw.second * kEps0 * dDe;
-        grad_sigma[cw.first] += cw.second * dDs;
-      }
-    }
+    *state = st;
     return FDTD_OK;
   } catch (const std::bad_alloc&) {
     return fail(FDTD_ENOMEM, "host allocation failed");
   }
 }
+
+extern "C" int fdtd_rom_model_state_vjp(const fdtd_rom_model_state* state, const double* grad_Rt,
+                                        const double* grad_Ft, double* grad_eps_r, double* grad_sigma) {
+  if (!state || !grad_Rt || !grad_Ft || !grad_eps_r || !grad_sigma) return fail(FDTD_EINVAL, "null argument");
+  try {
+    return vjp_from_state(*state, grad_Rt, grad_Ft, grad_eps_r, grad_sigma);
+  } catch (const std::bad_alloc&) {
+    return fail(FDTD_ENOMEM, "host allocation failed");
+  }
+}
+
+extern "C" void fdtd_rom_model_state_free(fdtd_rom_model_state* state) { delete state; }

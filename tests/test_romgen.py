@@ -209,3 +209,36 @@ def test_build_vjp_matches_oracle(r, q, basis, clipped, pec):
     assert np.linalg.norm(gsl - gso) <= 1e-12 * np.linalg.norm(gso)
     if pec:
         assert np.all(gel[fp] == 0) and np.all(gsl[fp] == 0)
+
+
+@pytest.mark.parametrize("r,q,clipped,pec", [(2, 12, False, False), (3, 140, True, False), (2, 16, False, True)])
+def test_kept_builder_state_gives_the_rebuilt_gradient(r, q, clipped, pec):
+    """fdtd_rom_build_keep returns fdtd_rom_build's model bit for bit and a
+    state whose gradient (fdtd_rom_model_state_vjp, no rebuild) is
+    fdtd_rom_build_vjp's bit for bit, on every call; build_roms(keep=True)
+    hands the states to build_vjps; gradients of the wrong shape are
+    refused."""
+    p = W.random_problem(31, 30, 26, 10, nroms=1, block=(5, 4), r=r, q=q, dt_frac_coarse=0.9, f_bw=3e9)
+    s = p.roms[0]
+    fp = None
+    if pec:
+        fp = np.zeros((r * s.nj, r * s.ni), dtype=bool)
+        fp[:4, 4:6] = True
+    a = capi.fdtd_rom_build(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, s.q, s.f_max, pec=fp)
+    b = capi.fdtd_rom_build_keep(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, s.q, s.f_max, pec=fp)
+    assert b["clipped"] == clipped
+    for k in ("Rt", "Ft", "Lt"):
+        assert np.array_equal(a[k], b[k]), k
+    rng = np.random.default_rng(3)
+    gR, gF = rng.standard_normal((s.q, s.q)), rng.standard_normal((s.q, s.q))
+    want = capi.fdtd_rom_build_vjp(s.ni, s.nj, s.r, p.dx, p.dy, p.dt, s.eps_r, s.sigma, s.q, s.f_max, gR, gF,
+                                   pec=fp)
+    for _ in range(2):   # the state is read only: the same answer twice
+        got = capi.fdtd_rom_model_state_vjp(b["state"], gR, gF)
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    if fp is None:
+        roms = romgen.build_roms(p, keep=True)
+        got = romgen.build_vjps(p, [dict(Rt=gR, Ft=gF)], roms=roms)[0]
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    with pytest.raises(AssertionError):
+        capi.fdtd_rom_model_state_vjp(b["state"], gR[:-1, :-1], gF[:-1, :-1])
