@@ -138,7 +138,8 @@ int fdtd::plan_problem(const fdtd_problem* p, Layout& L) {
     if (L.slot_gemm[sl]) {
       const fdtd_rom& r = p->roms[L.slot_rep[sl]];
       const size_t ldg = align_up((size_t)r.q + ports_of(r), kWave);
-      L.nblocks_mixed += (int)(((L.slot_members[sl] + kGemmCopies - 1) / kGemmCopies) * (ldg / kGemmRowsPerBlock));
+      L.nblocks_mixed += (int)(align_up((L.slot_members[sl] + kGemmCopies - 1) / kGemmCopies, 8) *
+                               (ldg / kGemmRowsPerBlock));
     }
   L.xs_elems = xe;
   L.idx_elems = ie;
@@ -411,12 +412,24 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
       if (L.slot_of_rom[k] == (int)sl) members.push_back(k);
     const fdtd_rom& rr = p->roms[L.slot_rep[sl]];
     const int ldg = (int)align_up((size_t)rr.q + ports_of(rr), kWave);
-    for (size_t c0 = 0; c0 < members.size(); c0 += kGemmCopies) {
-      const int cnt = (int)std::min<size_t>(kGemmCopies, members.size() - c0);
-      for (int row0 = 0; row0 < ldg; row0 += kGemmRowsPerBlock)
-        mixed.push_back(RowBlock{1, row0 / 16, (int)copies.size(), cnt});
-      for (int c = 0; c < cnt; ++c) copies.push_back(members[c0 + c]);
-    }
+    // Every row block of a group of copies gathers that group's inputs (its
+    // reduced states and the ring Hz, scattered loads from the step-n
+    // fields).  Blocks are listed row block by row block over the groups,
+    // the groups padded to a multiple of 8 with empty blocks, so that a
+    // group's row blocks sit at workgroup indices equal modulo 8: the same
+    // XCD, whose L2 then serves the repeated gathers (they were spread over
+    // four XCDs).
+    const size_t first = copies.size();
+    const size_t ngroups = (members.size() + kGemmCopies - 1) / kGemmCopies;
+    for (size_t c = 0; c < members.size(); ++c) copies.push_back(members[c]);
+    for (int row0 = 0; row0 < ldg; row0 += kGemmRowsPerBlock)
+      for (size_t g = 0; g < align_up(ngroups, 8); ++g) {
+        const size_t c0 = g * kGemmCopies;
+        const int cnt = g < ngroups ? (int)std::min<size_t>(kGemmCopies, members.size() - c0) : 0;
+        // an empty block points at the group's first copy (a valid
+        // descriptor) and writes nothing
+        mixed.push_back(RowBlock{1, row0 / 16, (int)(first + (g < ngroups ? c0 : 0)), cnt});
+      }
   }
   for (int k = 0; k < p->nroms; ++k) {
     const fdtd_rom& r = p->roms[k];
