@@ -1161,10 +1161,13 @@ step2_kernel(const StepParams<T> p) {
     }
   } else {
     // near pieces padded to a multiple of 8 workgroups, so that the far
-    // tiles' XCD remap still sees workgroup t on XCD t % 8
+    // tiles' XCD remap still sees workgroup t on XCD t % 8; the pieces are
+    // remapped the same way (each XCD a contiguous run of the near list, so
+    // a region's near tiles, which share halo rows and lines, share an L2)
     const int nn = p.n_near * (SEG / min(p.near_rows, SEG)), nn8 = (nn + 7) & ~7;
     if (t < nn8) {
-      if (t < nn) stencil2_near<T, SEG, MIdx>(p, t, n);
+      const int u = xcd_tile(t, nn8);
+      if (u < nn) stencil2_near<T, SEG, MIdx>(p, u, n);
     } else if (t < nn8 + p.far_split) {
       stencil2_tile<T, SEG, MIdx, false>(p, t - nn8, n);
     } else {
