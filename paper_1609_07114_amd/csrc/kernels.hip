@@ -1155,7 +1155,9 @@ step2_kernel(const StepParams<T> p) {
     // far tiles that follow)
     const int nb = p.n_band * kBandSplit, nb8 = (nb + 7) & ~7;
     if (t < nb8) {
-      if (t < nb) band_block(p, t / kBandSplit, t % kBandSplit, n);
+      // remapped like the near pieces: a region's parts on one XCD
+      const int u = xcd_tile(t, nb8);
+      if (u < nb) band_block(p, u / kBandSplit, u % kBandSplit, n);
     } else {
       stencil2_tile<T, SEG, MIdx, true>(p, t - nb8, n);
     }
