@@ -141,14 +141,23 @@ void build_table(fdtd_rom_batch* bt) {
         const int near_rows = bt->dtype == FDTD_F32 ? sb->sp_f.near_rows : sb->sp_d.near_rows;
         const int nt = bt->dtype == FDTD_F32 ? sb->sp_f.nst2_blocks : sb->sp_d.nst2_blocks;
         const int split = bt->dtype == FDTD_F32 ? sb->sp_f.far_split : sb->sp_d.far_split;
+        // near pieces and band blocks are listed in the order the single
+        // handle's launch remaps them to (each XCD a contiguous run, so a
+        // region's pieces share an L2); entries start at a multiple of 8,
+        // so entry k runs on XCD k % 8
+        auto xcd_order = [&](int cnt, int kind) {
+          const int cnt8 = (cnt + 7) & ~7, per = cnt8 / 8;
+          for (int k = 0; k < cnt8; ++k) {
+            const int v = (k & 7) * per + (k >> 3);
+            u.push_back(v < cnt ? BatchRef{b, kind, v, 0} : BatchRef{0, 3, 0, 0});
+          }
+        };
         if (second) {
-          for (int k = 0; k < sb->nroms * kBandSplit; ++k) u.push_back(BatchRef{b, 1, k, 0});
-          while (u.size() % 8) u.push_back(BatchRef{0, 3, 0, 0});
+          xcd_order(sb->nroms * kBandSplit, 1);
           for (int k = 0; k < nt - split; ++k) u.push_back(BatchRef{b, 5, k, 0});
         } else {
           const int nn = n_near * (sb->seg / std::min(near_rows, sb->seg));
-          for (int k = 0; k < nn; ++k) u.push_back(BatchRef{b, 4, k, 0});
-          while (u.size() % 8) u.push_back(BatchRef{0, 3, 0, 0});
+          xcd_order(nn, 4);
           for (int k = 0; k < split; ++k) u.push_back(BatchRef{b, 1, k, 0});
         }
       }
