@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -980,12 +981,9 @@ extern "C" int fdtd_rom_build_keep(const fdtd_rom_build_params* prm, double* Rt,
   if (!prm || !Rt || !Ft || !Lt || !state) return fail(FDTD_EINVAL, "null argument");
   *state = nullptr;
   try {
-    auto* st = new fdtd_rom_model_state();
-    if (int rc = build_keep(prm, *st, Rt, Ft, Lt, info); rc != FDTD_OK) {
-      delete st;
-      return rc;
-    }
-    *state = st;
+    std::unique_ptr<fdtd_rom_model_state> st(new fdtd_rom_model_state());
+    if (int rc = build_keep(prm, *st, Rt, Ft, Lt, info); rc != FDTD_OK) return rc;
+    *state = st.release();
     return FDTD_OK;
   } catch (const std::bad_alloc&) {
     return fail(FDTD_ENOMEM, "host allocation failed");
