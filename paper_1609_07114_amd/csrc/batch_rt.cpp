@@ -79,12 +79,12 @@ int plan_batch(const fdtd_problem* probs, int B, BatchPlan& P) {
     const int rc = plan_problem(&probs[b], L);
     if (rc != FDTD_OK) return fail(rc, "instance %d: %s", b, fdtd_rom_last_error());
     sizes[b] = L.total;
-    cap += (size_t)std::max(L.nrowblocks, L.nblocks_mixed) + (size_t)tiles_for(probs[b], 4) + 7 + 1;
+    cap += (size_t)std::max(L.nrowblocks, L.nblocks_mixed) + (size_t)tiles_for(probs[b], 4) + 14 + 1;
     // first table: coupling blocks, near-tile pieces (at most twice the
     // tile count of 4-row waves: a near tile of SEG-row waves is SEG/2
     // pieces), tiles, two paddings, probe block; second: coupling and band
     cap2 += (size_t)std::max(L.nrowblocks, L.nblocks_mixed) +
-            std::max((size_t)L.max_tiles2 * 3 + 16, (size_t)L.max_tiles2 + (size_t)probs[b].nroms * kBandSplit) + 14 + 1;
+            std::max((size_t)L.max_tiles2 * 3 + 16, (size_t)L.max_tiles2 + (size_t)probs[b].nroms * kBandSplit) + 21 + 1;
   }
   const size_t desc_bytes = (size_t)B * (dt == FDTD_F32 ? sizeof(StepParams<float>) : sizeof(StepParams<double>));
   P.desc_stride = align_up(desc_bytes, 256);
@@ -119,8 +119,12 @@ void build_table(fdtd_rom_batch* bt) {
   // the parameter block of the handle's own dtype (the other stays unset)
   auto nrow = [&](int b) { return bt->dtype == FDTD_F32 ? bt->sims[b]->sp_f.nrowblocks : bt->sims[b]->sp_d.nrowblocks; };
   auto ntile = [&](int b) { return bt->dtype == FDTD_F32 ? bt->sims[b]->sp_f.nst_blocks : bt->sims[b]->sp_d.nst_blocks; };
-  for (int b = 0; b < bt->B; ++b)
+  // each instance's coupling blocks from an index that is a multiple of 8,
+  // so that the handle's XCD grouping of a model's blocks holds
+  for (int b = 0; b < bt->B; ++b) {
+    pad8();
     for (int k = 0; k < nrow(b); ++k) t.push_back(BatchRef{b, 0, k, 0});
+  }
   for (int b = 0; b < bt->B; ++b) {
     pad8();
     for (int k = 0; k < ntile(b); ++k) t.push_back(BatchRef{b, 1, k, 0});
@@ -129,8 +133,10 @@ void build_table(fdtd_rom_batch* bt) {
   if (bt->tb) {
     auto two = [&](std::vector<BatchRef>& u, bool second) {
       u.clear();
-      for (int b = 0; b < bt->B; ++b)
+      for (int b = 0; b < bt->B; ++b) {
+        while (u.size() % 8) u.push_back(BatchRef{0, 3, 0, 0});
         for (int k = 0; k < nrow(b); ++k) u.push_back(BatchRef{b, 0, k, 0});
+      }
       for (int b = 0; b < bt->B; ++b) {
         while (u.size() % 8) u.push_back(BatchRef{0, 3, 0, 0});
         const fdtd_rom_sim* sb = bt->sims[b];

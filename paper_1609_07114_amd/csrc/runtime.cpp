@@ -244,6 +244,54 @@ void pml_axis(int n, double d, double dt, int nlo, int nhi, const fdtd_pml& pm, 
   for (int i = 0; i < n; ++i) put(3, i, (i + 0.5) * d);
 }
 
+
+// Every GEMV row block of a model stages the same inputs (its reduced state
+// and the ring Hz, scattered loads from the step-n fields).  Reorder
+// v[start, end) so that a model's blocks sit at indices equal modulo 8 -
+// workgroup i runs on XCD i % 8, so they share one L2 - as far as the
+// counts allow: models go to residues largest first, each to the residue
+// with the most free slots; a slot whose residue has run out takes a block
+// of another.  Only the order changes (each block is independent).
+void xcd_group(std::vector<RowBlock>& v, size_t start) {
+  if (v.size() <= start + 8) return;
+  std::vector<std::vector<RowBlock>> by_model;
+  std::vector<int> slot_of;  // model -> index in by_model
+  for (size_t i = start; i < v.size(); ++i) {
+    const int k = v[i].a;
+    if (k >= (int)slot_of.size()) slot_of.resize(k + 1, -1);
+    if (slot_of[k] < 0) {
+      slot_of[k] = (int)by_model.size();
+      by_model.emplace_back();
+    }
+    by_model[slot_of[k]].push_back(v[i]);
+  }
+  std::vector<size_t> order(by_model.size());
+  for (size_t m = 0; m < order.size(); ++m) order[m] = m;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t a, size_t b) { return by_model[a].size() > by_model[b].size(); });
+  long cap[8] = {0};
+  for (size_t i = start; i < v.size(); ++i) cap[i % 8]++;
+  std::vector<RowBlock> q[8];
+  for (size_t m : order) {
+    int best = 0;
+    for (int r = 1; r < 8; ++r)
+      if (cap[r] > cap[best]) best = r;
+    cap[best] -= (long)by_model[m].size();
+    q[best].insert(q[best].end(), by_model[m].begin(), by_model[m].end());
+  }
+  size_t head[8] = {0};
+  for (size_t i = start; i < v.size(); ++i) {
+    int r = (int)(i % 8);
+    if (head[r] == q[r].size()) {  // this residue ran out: the fullest other
+      int best = -1;
+      for (int s = 0; s < 8; ++s)
+        if (head[s] < q[s].size() && (best < 0 || q[s].size() - head[s] > q[best].size() - head[best])) best = s;
+      r = best;
+    }
+    v[i] = q[r][head[r]++];
+  }
+}
+
 template <typename T>
 int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsigned char>& inside) {
   const Layout& L = s->L;
@@ -463,6 +511,14 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
   }
   if ((int)blocks.size() != L.nrowblocks || (int)mixed.size() != L.nblocks_mixed || copies.size() != L.ncopies)
     return fail(FDTD_EINVAL, "internal: coupling block count mismatch");
+  // GEMV blocks (after the GEMM blocks, whose count is a multiple of 8) in
+  // XCD groups per model
+  {
+    size_t ngemm = 0;
+    while (ngemm < mixed.size() && mixed[ngemm].kind == 1) ++ngemm;
+    xcd_group(blocks, 0);
+    xcd_group(mixed, ngemm);
+  }
   if ((rc = up(L.off_blocks, blocks.data(), blocks.size() * sizeof(RowBlock))) != FDTD_OK) return rc;
   if ((rc = up(L.off_blocks_mixed, mixed.data(), mixed.size() * sizeof(RowBlock))) != FDTD_OK) return rc;
   if ((rc = up(L.off_copies, copies.data(), copies.size() * sizeof(int))) != FDTD_OK) return rc;
