@@ -377,7 +377,7 @@ constexpr int kAdjOwned = kWave - 3;  // columns a reverse-sweep wave owns
 
 // Transposed eq. (3) + eq. (5) and the coefficient gradients, streamed up
 // the rows like the forward stencil.  A wave covers 64 lanes = columns
-// iw-2 .. iw+61 (iw = 61 * blockIdx.x).  Lanes 2..62 own their column; lane 1
+// iw-2 .. iw+61 (iw = 61 * bx, tile column bx).  Lanes 2..62 own their column; lane 1
 // only supplies mu of column iw-1 (its own west neighbour comes from lane
 // 0), lanes 0 and 63 only supply data, so no lane loads anything outside
 // its own column.  A segment of SEG rows recomputes mu of the row below it;
@@ -604,9 +604,18 @@ __device__ __forceinline__ void adj_tile(const AdjParams<T>& p, int bx, int by) 
   }
 }
 
+// Stream workgroup s of n8 (a multiple of 8) -> tile index: each of the 8
+// XCDs (workgroup s runs on XCD s % 8 when the stream part starts at a
+// multiple of 8) takes a contiguous run of tiles, so vertically and
+// laterally neighbouring tiles, which read each other's halo rows and
+// lines, mostly share an L2.
+__device__ __forceinline__ int adj_xcd_tile(int s, int n8) { return (s & 7) * (n8 >> 3) + (s >> 3); }
+
 template <typename T, int SEG, bool Layers>
-__global__ void __launch_bounds__(kBlock) adj_stream(const AdjParams<T> p) {
-  adj_tile<T, SEG, Layers>(p, blockIdx.x, blockIdx.y);
+__global__ void __launch_bounds__(kBlock) adj_stream(const AdjParams<T> p, int gx, int ntiles) {
+  const int t = adj_xcd_tile(blockIdx.x, (int)gridDim.x);
+  if (t >= ntiles) return;
+  adj_tile<T, SEG, Layers>(p, t % gx, t / gx);
 }
 
 // mu of an active cell at offset `off` as adj_rows forms it (no absorbing
@@ -689,34 +698,38 @@ __device__ __forceinline__ void coupling_fused_block(const AdjParams<T>& p, int 
 }
 
 // Fused reverse step: workgroups [0, ncoup) are coupling blocks of step n-1
-// (first, so their chains start early), the rest the stream of step n
-// (tile (s % gx, s / gx) for workgroup ncoup + s).  The coupling blocks read
+// (first, so their chains start early), the rest, from the next multiple
+// of 8, the stream of step n (workgroup ncoup8 + s takes tile
+// adj_xcd_tile(s, n8), (t % gx, t / gx)).  The coupling blocks read
 // only step n's inputs and write lx_out and pend_out, which no stream
 // workgroup reads, so the two parts run side by side.
 template <typename T, int SEG, bool Layers>
-__global__ void __launch_bounds__(kBlock) adj_fused(const AdjParams<T> p, int ncoup, int gx) {
+__global__ void __launch_bounds__(kBlock) adj_fused(const AdjParams<T> p, int ncoup, int gx, int ntiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x;
-  if (b < ncoup) {
-    coupling_fused_block(p, b, reinterpret_cast<T*>(smem));
+  const int ncoup8 = (ncoup + 7) & ~7;
+  if (b < ncoup8) {
+    if (b < ncoup) coupling_fused_block(p, b, reinterpret_cast<T*>(smem));
     return;
   }
-  const int s = b - ncoup;
-  adj_tile<T, SEG, Layers>(p, s % gx, s / gx);
+  const int t = adj_xcd_tile(b - ncoup8, (int)gridDim.x - ncoup8);
+  if (t >= ntiles) return;
+  adj_tile<T, SEG, Layers>(p, t % gx, t / gx);
 }
 
 template <typename T>
 hipError_t launch_adjoint_step(const AdjParams<T>& p, size_t smem, hipStream_t s) {
   if (p.nblocks > 0) hipLaunchKernelGGL((adj_coupling<T>), dim3(p.nblocks), dim3(kBlock), smem, s, p);
   const int rows = (kBlock / kWave) * p.seg;
-  const dim3 g((p.nx + kAdjOwned - 1) / kAdjOwned, (p.ny + rows - 1) / rows);
+  const int gx = (p.nx + kAdjOwned - 1) / kAdjOwned, gy = (p.ny + rows - 1) / rows, nt = gx * gy;
+  const dim3 g((unsigned)((nt + 7) & ~7));
   auto go = [&](auto layers) -> hipError_t {
     constexpr bool Ly = decltype(layers)::value;
     switch (p.seg) {
-      case 2: hipLaunchKernelGGL((adj_stream<T, 2, Ly>), g, dim3(kBlock), 0, s, p); break;
-      case 4: hipLaunchKernelGGL((adj_stream<T, 4, Ly>), g, dim3(kBlock), 0, s, p); break;
-      case 8: hipLaunchKernelGGL((adj_stream<T, 8, Ly>), g, dim3(kBlock), 0, s, p); break;
-      case 16: hipLaunchKernelGGL((adj_stream<T, 16, Ly>), g, dim3(kBlock), 0, s, p); break;
+      case 2: hipLaunchKernelGGL((adj_stream<T, 2, Ly>), g, dim3(kBlock), 0, s, p, gx, nt); break;
+      case 4: hipLaunchKernelGGL((adj_stream<T, 4, Ly>), g, dim3(kBlock), 0, s, p, gx, nt); break;
+      case 8: hipLaunchKernelGGL((adj_stream<T, 8, Ly>), g, dim3(kBlock), 0, s, p, gx, nt); break;
+      case 16: hipLaunchKernelGGL((adj_stream<T, 16, Ly>), g, dim3(kBlock), 0, s, p, gx, nt); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -728,16 +741,16 @@ template <typename T>
 hipError_t launch_adjoint_fused(const AdjParams<T>& p, bool coupling, size_t smem, hipStream_t s) {
   const int rows = (kBlock / kWave) * p.seg;
   const int gx = (p.nx + kAdjOwned - 1) / kAdjOwned, gy = (p.ny + rows - 1) / rows;
-  const int ncoup = coupling ? p.nblocks : 0;
-  const dim3 g((unsigned)(ncoup + gx * gy));
+  const int ncoup = coupling ? p.nblocks : 0, nt = gx * gy;
+  const dim3 g((unsigned)(((ncoup + 7) & ~7) + ((nt + 7) & ~7)));
   const size_t lds = ncoup > 0 ? smem : 0;
   auto go = [&](auto layers) -> hipError_t {
     constexpr bool Ly = decltype(layers)::value;
     switch (p.seg) {
-      case 2: hipLaunchKernelGGL((adj_fused<T, 2, Ly>), g, dim3(kBlock), lds, s, p, ncoup, gx); break;
-      case 4: hipLaunchKernelGGL((adj_fused<T, 4, Ly>), g, dim3(kBlock), lds, s, p, ncoup, gx); break;
-      case 8: hipLaunchKernelGGL((adj_fused<T, 8, Ly>), g, dim3(kBlock), lds, s, p, ncoup, gx); break;
-      case 16: hipLaunchKernelGGL((adj_fused<T, 16, Ly>), g, dim3(kBlock), lds, s, p, ncoup, gx); break;
+      case 2: hipLaunchKernelGGL((adj_fused<T, 2, Ly>), g, dim3(kBlock), lds, s, p, ncoup, gx, nt); break;
+      case 4: hipLaunchKernelGGL((adj_fused<T, 4, Ly>), g, dim3(kBlock), lds, s, p, ncoup, gx, nt); break;
+      case 8: hipLaunchKernelGGL((adj_fused<T, 8, Ly>), g, dim3(kBlock), lds, s, p, ncoup, gx, nt); break;
+      case 16: hipLaunchKernelGGL((adj_fused<T, 16, Ly>), g, dim3(kBlock), lds, s, p, ncoup, gx, nt); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
