@@ -481,16 +481,11 @@ int adjoint_impl(fdtd_rom_sim* s, int N, int probe, char* aw, const AdjLayout& A
   ap.nx = s->nx;
   ap.ny = s->ny;
   ap.pitch = s->pitch;
-  // rows per reverse wave: the forward's default, at most 16; where that is
-  // 4 rows (grids this small) and the reverse steps run alone, half of it
-  // for more waves in flight (the C5 1024^2 sweep in one launch per reverse
-  // step without a recompute beside it: 182.5 ms at 2 rows, 190.7 at 4,
-  // 185.8 at 8), but 4 while the next segment's recompute runs beside them
-  // (133.6 ms at 4 rows, 140.6 at 2, 148.7 at 8; checkpoints every 200)
-  {
-    const int fw = default_tiling(s->nx, s->ny, (int)L.tsize);
-    ap.seg = fw == 4 && !(A.nbuf == 2 && !noalloc) ? 2 : std::min(fw, 16);
-  }
+  // rows per reverse wave: the forward's default, at most 16 (the C5 1024^2
+  // sweep with the stream tiles in XCD runs: 117.5 ms at 4 rows, 131.0 at
+  // 2, 137.0 at 8 with the recompute beside the reverse steps; 111.0, 117.3
+  // and 126.4 ms with every state resident)
+  ap.seg = std::min(default_tiling(s->nx, s->ny, (int)L.tsize), 16);
   ap.chdy = sp.chdy;
   ap.chdx = sp.chdx;
   ap.k2dy = sp.k2dy;
