@@ -131,6 +131,11 @@ struct StepParams {
   int tiles_x2, nst2_blocks, n_near, n_band, near_rows, far_split;
   const uint8_t* role2;
   const int* near_list;
+  // per cell (pitch layout): non-zero where a near tile stores step n+1 -
+  // the cells the second launch reads from the step-(n+1) set (the band
+  // blocks and the coupling's ring gathers: x in [i-1, i+2], y in [j-1, j+2]
+  // around each ring cell (i, j)); nothing else reads that set
+  const uint8_t* st1m;
 };
 
 constexpr int kOwned2 = kWave - 4;  // columns a two-step wave owns (lanes 2..61)

@@ -472,8 +472,9 @@ __device__ __forceinline__ void stencil_tile(const StepParams<T>& p, int t, int 
 //   ring or a source: two steps into f2, every owned sample stored.
 // Near = true: a tile near a region or a source (first launch of the pair):
 //   the same two steps with source terms, storing
-//   * stage 1 (step n+1) of every owned sample into the step-(n+1) set,
-//     except interface edges (the step-n coupling writes them);
+//   * stage 1 (step n+1) into the step-(n+1) set where the second launch
+//     reads it (StepParams::st1m: a box around each ring cell), except
+//     interface edges (the step-n coupling writes them);
 //   * stage 2 (step n+2) into f2, except the band around each region - the
 //     Hz of ring cells (active cells with a side on a region cell) and E on
 //     every edge of a ring cell - and the interface edges.  The band's step
@@ -678,7 +679,8 @@ __device__ __forceinline__ void stencil2_rows(const StepParams<T>& p, const Sets
       // coupling blocks
       o.ix = (cur.al < T(0)) != (a_prev < T(0));
       o.iy = (cur.al < T(0)) != (all < T(0));
-      if (own && r >= j0 && r < j1) {
+      // only where the second launch reads the step-(n+1) set
+      if (own && r >= j0 && r < j1 && p.st1m[ob / ts] != 0) {
         st(hz1, ob, hn);
         if (!o.ix) st(ex1o, ob, exn);
         if (!o.iy) st(ey1o, ob, eyn);

@@ -203,6 +203,8 @@ int fdtd::plan_problem(const fdtd_problem* p, Layout& L) {
     o = align_up(o + (size_t)L.max_tiles2, 256);
     L.off_near = o;
     o = align_up(o + (size_t)L.max_tiles2 * sizeof(int), 256);
+    L.off_st1m = o;
+    o = align_up(o + L.field_elems, 256);
   }
   L.total = o;
   return FDTD_OK;
@@ -356,6 +358,30 @@ int setup_device(fdtd_rom_sim* s, const fdtd_problem* p, const std::vector<unsig
     }
   if ((rc = up(L.off_al, al.data(), fb)) != FDTD_OK) return rc;
   if ((rc = up(L.off_be, be.data(), fb)) != FDTD_OK) return rc;
+  if (L.tb_ok) {
+    // where the second launch of a pair reads the step-(n+1) set: the box
+    // x in [i-1, i+2], y in [j-1, j+2] around each ring cell (i, j) (the
+    // band's Hz and edges and the ring gathers, each Hz formed from its
+    // cell, the Ex above and the Ey east of it)
+    std::vector<uint8_t> m(fe, 0);
+    for (int k = 0; k < p->nroms; ++k) {
+      const fdtd_rom& r = p->roms[k];
+      const int np = ports_of(r);
+      for (int c = 0; c < np; ++c) {
+        int oi, oj;
+        if (c < r.ni) { oi = r.i0 + c; oj = r.j0 - 1; }
+        else if (c < 2 * r.ni) { oi = r.i0 + c - r.ni; oj = r.j0 + r.nj; }
+        else if (c < 2 * r.ni + r.nj) { oi = r.i0 - 1; oj = r.j0 + c - 2 * r.ni; }
+        else { oi = r.i0 + r.ni; oj = r.j0 + c - 2 * r.ni - r.nj; }
+        for (int dy = -1; dy <= 2; ++dy)
+          for (int dx = -1; dx <= 2; ++dx) {
+            const int i = oi + dx, j = oj + dy;
+            if (i >= 0 && i < nx && j >= 0 && j < ny) m[(size_t)j * P + i] = 1;
+          }
+      }
+    }
+    if ((rc = up(L.off_st1m, m.data(), fe)) != FDTD_OK) return rc;
+  }
   // the same material as a 16-bit index into a table of the distinct (a, b)
   // pairs (exact bit patterns), when there are at most kMaxMaterials of them
   {
@@ -1003,6 +1029,7 @@ int fdtd::prepare_tb(fdtd_rom_sim* s) {
     sp.far_split = nt - (int)((int64_t)nt * split_pct / 100);
     sp.role2 = (const uint8_t*)(s->ws + L.off_role2);
     sp.near_list = (const int*)(s->ws + L.off_near);
+    sp.st1m = (const uint8_t*)(s->ws + L.off_st1m);
   };
   fill(s->sp_f);
   fill(s->sp_d);

@@ -35,7 +35,7 @@ struct Layout {
   // pair writes near regions, tile roles, near-tile list, near-probe flags
   bool tb_ok = false;
   int max_tiles2 = 0;
-  size_t off_fc = 0, off_role2 = 0, off_near = 0;
+  size_t off_fc = 0, off_role2 = 0, off_near = 0, off_st1m = 0;
   size_t mats_elems = 0, xs_elems = 0, idx_elems = 0;
   int nrowblocks = 0;        // all-GEMV coupling list
   int nblocks_mixed = 0;     // GEMM for eligible shared groups + GEMV for the rest
