@@ -741,7 +741,8 @@ def main():
         kind = "vacuum"
         desc = (f"C3 many copies {prob.nx}x{prob.ny} vacuum, {len(prob.roms)} embedded 32x32-cell regions "
                 f"(r=4, eps_r=4, sigma=0.01) sharing one q={prob.roms[0].q} model (FP32 MFMA GEMM over the "
-                f"copies), dt=0.95 coarse CFL, Ey plane-wave line source, {len(prob.probes)} probes")
+                f"copies), dt=0.95 coarse CFL, Ey plane-wave line source, {len(prob.probes)} probes, device rows "
+                f"padded by {prob.pitch_pad} columns")
     else:
         prob = W.random_media(n=2048, nsteps=total)
         kind = "material"
